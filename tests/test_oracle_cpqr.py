@@ -1,0 +1,57 @@
+"""Pins of the oracle's pivoted QR / interpolative decomposition (Section 2.2).
+
+* On matrices whose column norms are distinct at every step, the pivot
+  order and |R| equal LAPACK dgeqp3's (scipy.linalg.qr(pivoting=True)).
+* ID accuracy: ||M_R - M_S T||_2 <= sqrt(k (n - k) + 1) |R_{k+1,k+1}| ... up
+  to the factor of the strong rank-revealing bound, checked with margin.
+* Exact rank: a product of rank-k factors gives rank k at tolerance 1e-10.
+"""
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from oracle.cpqr import PivotedQR
+
+
+@pytest.mark.parametrize("shape", [(40, 12), (200, 64), (30, 50)])
+def test_matches_lapack_geqp3(shape):
+    rng = np.random.Generator(np.random.PCG64(7))
+    m, n = shape
+    M = rng.standard_normal((m, n)) * np.logspace(0, -3, n)[None, :]
+    q = PivotedQR(M)
+    q.advance_to(min(m, n))
+    _, R, P = sla.qr(M, pivoting=True, mode="economic")
+    assert np.array_equal(q.perm, P)
+    Ro = q.r_factor()
+    kk = min(m, n)
+    assert np.allclose(np.abs(Ro[:kk]), np.abs(R[:kk]), rtol=1e-10, atol=1e-13)
+
+
+def test_rank_and_id_bound():
+    rng = np.random.Generator(np.random.PCG64(3))
+    m, n, k = 300, 80, 23
+    M = rng.standard_normal((m, k)) @ rng.standard_normal((k, n))
+    M += 1e-13 * rng.standard_normal((m, n))
+    q = PivotedQR(M)
+    kk = q.rank(1e-10)
+    assert kk == k
+    T = q.interpolation(kk)
+    S, Rr = q.perm[:kk], q.perm[kk:]
+    err = np.linalg.norm(M[:, Rr] - M[:, S] @ T, 2)
+    q.advance_to(kk + 1)
+    rkk = abs(q.A[kk, kk])
+    assert err <= np.sqrt(kk * (n - kk) + 1) * rkk * 10 + 1e-14
+    assert err < 1e-10 * np.linalg.norm(M, 2)
+
+
+def test_tie_break_prefers_first_column():
+    M = np.array([[1.0, 0.0, 1.0], [0.0, 1.0, 0.0]])
+    q = PivotedQR(M)
+    q.step()
+    assert q.perm[0] == 0
+
+
+def test_zero_matrix_rank_zero():
+    q = PivotedQR(np.zeros((5, 3)))
+    assert q.rank(1e-10) == 0
