@@ -1,0 +1,175 @@
+/*
+ * rs.h - C ABI of the MI355X (gfx950) recursive-skeletonization solver for the
+ * 2D Stokes double-layer boundary integral equation on multiply-connected
+ * domains (Ryan & Damle, "Parallel skeletonization for integral equations in
+ * evolving multiply-connected domains").
+ *
+ * The operator (Section 3.1, eq. backwardeq) is the augmented system
+ *
+ *     [ lambda I + D + N   H ] [ mu     ]   [ f ]
+ *     [ Psi^T             -I ] [ alpha  ] = [ 0 ]
+ *                              [ beta   ]
+ *
+ * with D the stresslet double layer (eq. stokesbie), N the rank-one
+ * completion (eq. null-spaceop), H the Stokeslet/rotlet columns of each hole
+ * (eq. completed) and Psi the rigid motions of each hole (eq. null-space).
+ * lambda I + D + N is factored by recursive skeletonization (Sections
+ * 2.2-2.7) and the border is eliminated as in Section 3.2 (eq. partition).
+ *
+ * Conventions shared by every entry point:
+ *  - Node arrays are host pointers in float64, row-major [n][2] for
+ *    2-vectors.  Unknown 2j is the x-component of the density at node j and
+ *    2j+1 its y-component; the 3p augmented unknowns follow, per hole h in
+ *    the order (alpha_h1, alpha_h2, beta_h).
+ *  - Normals are unit vectors pointing out of the fluid: outward on the
+ *    outer curve, into each hole.  Curvature is signed: positive where the
+ *    curve bends away from that normal.  curve_id is 0 on the outer curve
+ *    and h (1..p) on hole h.
+ *  - Inputs are copied during the call; the caller keeps ownership of every
+ *    pointer it passes.  Outputs are caller-allocated.  The context owns all
+ *    device memory it allocates and frees it in rs_destroy.
+ *  - No exception crosses the ABI.  Every call returns an rs_status; on any
+ *    status other than RS_OK, rs_last_error() describes the failure and the
+ *    caller's output arrays are left untouched unless stated otherwise.
+ *  - A context is not thread-safe and is bound to the HIP device that was
+ *    current when it was built.
+ */
+#ifndef RS_MI355X_H
+#define RS_MI355X_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rs_ctx rs_ctx;
+
+typedef enum {
+  RS_OK = 0,
+  RS_ERR_ARG = 1,          /* invalid argument (non-finite value, bad size, bad id, NULL) */
+  RS_ERR_STATE = 2,        /* call out of order (e.g. solve before factor)               */
+  RS_ERR_ALLOC = 3,        /* device or host allocation failed                           */
+  RS_ERR_DEVICE = 4,       /* a HIP runtime call failed                                  */
+  RS_ERR_SINGULAR = 5,     /* a diagonal block stayed singular after the pivot guard     */
+  RS_ERR_NOCONV = 6,       /* iterative refinement did not reach refine_tol             */
+  RS_ERR_OUT_OF_ROOT = 7   /* a node lies outside the fixed root square                   */
+} rs_status;
+
+typedef struct {
+  double lambda;       /* scalar of (lambda I + K), eq. (biediscretee); -0.5 for the Stokes jump */
+  double tol;          /* ID tolerance, relative: a pivot counts while |R_jj| > tol |R_11|     */
+  int leaf_size;       /* a box splits while it holds more than leaf_size nodes (Section 2.3)   */
+  int n_proxy;         /* points on each box's proxy circle (Section 2.5)                       */
+  double proxy_ratio;  /* proxy radius = proxy_ratio * box side                                  */
+  double rcond_min;    /* X_RR guard: move a pivot from R to S while rcond_1(X_RR) < rcond_min  */
+  int precision;       /* 0 = float64 throughout; 1 = mixed (float32 bulk, float64 refinement)   */
+  double refine_tol;   /* mixed: target max-column relative residual of the float64 operator  */
+  int refine_max;      /* mixed: maximum refinement iterations                                  */
+  int has_root;        /* 1: use root[] as the fixed root square; 0: bounding square of nodes */
+  double root[3];      /* fixed root square: centre x, centre y, side                           */
+} rs_params;
+
+/* Fill *p with the defaults: lambda -0.5, tol 1e-10, leaf 64, 64 proxy points
+ * at 1.5 x side, rcond_min 1e-12, float64, refine_tol 1e-8, refine_max 20,
+ * no fixed root. */
+void rs_default_params(rs_params* p);
+
+/* Build the adaptive quadtree (Section 2.3) for a boundary discretisation and
+ * copy the geometry to the device.
+ *   n_nodes             number of boundary nodes N (> 0)
+ *   xy, normal          [N][2] positions and unit normals (|n| = 1 within 1e-12)
+ *   weight              [N] quadrature weights (> 0)
+ *   curvature           [N] signed curvature (diagonal limit of D)
+ *   curve_id            [N] 0 = outer curve, 1..n_holes = hole index
+ *   n_holes             p >= 0
+ *   hole_xy             [p][2] one interior point c_h per hole (Stokeslet/rotlet
+ *                       centre); NULL = centroid of the hole's nodes
+ * On success *out receives a new context.  RS_ERR_OUT_OF_ROOT if a fixed
+ * root was requested and a node lies outside it. */
+rs_status rs_build_tree(const rs_params* prm, int n_nodes, const double* xy,
+                        const double* normal, const double* weight,
+                        const double* curvature, const int* curve_id, int n_holes,
+                        const double* hole_xy, rs_ctx** out);
+
+/* Compute the factorization (Sections 2.2-2.7 with the bordered root of
+ * Section 3.2) on the device.  Blocks until the factorization is complete. */
+rs_status rs_factor(rs_ctx* ctx);
+
+/* Solve the augmented system for nrhs right-hand sides (eq. kinv, eq. solution).
+ *   f             host, (2N) x nrhs, column-major, leading dimension 2N
+ *   x             host, (2N + 3p) x nrhs, column-major, leading dimension 2N + 3p
+ *   rel_residual  host [nrhs] or NULL: ||[f;0] - A x||_2 / ||f||_2 per column,
+ *                 with A applied exactly in float64 on the device
+ * In mixed precision (precision = 1) the float32 factorization is the inner
+ * solver of float64 iterative refinement; RS_ERR_NOCONV means refine_max
+ * iterations did not reach refine_tol, x then holds the last iterate and
+ * rel_residual (if given) its residuals. */
+rs_status rs_solve(rs_ctx* ctx, int nrhs, const double* f, double* x, double* rel_residual);
+
+/* As rs_solve, with f and x device pointers (same layouts) used on the
+ * stream set by rs_set_stream.  The call returns after the solve completed. */
+rs_status rs_solve_dev(rs_ctx* ctx, int nrhs, const double* f_dev, double* x_dev);
+
+/* Replace the data of n_moved nodes and update the factorization (Section
+ * 2.8): boxes whose unknowns or proxy-disk neighbourhood changed are
+ * recompressed, every other box keeps its factors, the root (and the border
+ * H, Psi^T) is always redone.  The root square is kept, so the result equals
+ * a fresh factorization of the new geometry.
+ *   idx                 [n_moved] node indices (distinct, in [0, N))
+ *   xy, normal, weight, curvature   new values, [n_moved][2] / [n_moved]
+ *   hole_xy             NULL or [p][2] new interior points for all holes
+ * RS_ERR_OUT_OF_ROOT if a moved node leaves the root square (nothing is
+ * changed then; rebuild the context). */
+rs_status rs_update_moved_nodes(rs_ctx* ctx, int n_moved, const int* idx, const double* xy,
+                                const double* normal, const double* weight,
+                                const double* curvature, const double* hole_xy);
+
+/* Use the given hipStream_t (as void*) for all later device work; NULL = the
+ * default stream.  The caller keeps the stream alive while the context uses it. */
+rs_status rs_set_stream(rs_ctx* ctx, void* hip_stream);
+
+/* Summary of the last factorization (host-side numbers). */
+typedef struct {
+  int n_nodes, n_holes, n_levels, n_boxes;
+  int root_skeleton;          /* |S| at the root                                   */
+  int max_box_unknowns;       /* largest active set of a compressed box            */
+  int max_rank;               /* largest skeleton                                  */
+  int guard_bumps;            /* pivots moved from R to S by the X_RR guard        */
+  long long factor_bytes;     /* bytes of factors read by one solve (T, E, F, X_RR^-1) */
+  double flops_id;            /* algorithmic flops of the pivoted QRs              */
+  double flops_elim;          /* algorithmic flops of the eliminations             */
+  double ms_factor;           /* wall time of the last rs_factor                   */
+  double ms_solve;            /* wall time of the last rs_solve / rs_solve_dev     */
+  int refine_iters;           /* refinement iterations of the last mixed solve     */
+  double ms_update;           /* wall time of the last rs_update_moved_nodes       */
+  int boxes_recomputed;       /* boxes recompressed by the last update             */
+} rs_stats;
+rs_status rs_get_stats(const rs_ctx* ctx, rs_stats* out);
+
+/* Per-box structure of the factorization, boxes in breadth-first order
+ * (root first).  For each box: level, active unknown count n and rank k
+ * (k = n for the root, -1 for a box without active unknowns), and its
+ * square (centre x, centre y, side) in box_geom[3*i..3*i+2].  Any output
+ * pointer may be NULL.  cap = capacity of the arrays in boxes; the number of
+ * boxes is returned in *n_boxes (RS_ERR_ARG if cap is too small). */
+rs_status rs_get_boxes(const rs_ctx* ctx, int cap, int* n_boxes, int* level, int* n_active,
+                       int* rank, double* box_geom);
+
+/* Skeleton unknowns (global unknown indices, in pivot order) of box `box`
+ * (breadth-first index).  cap = capacity of `out`; *len receives k. */
+rs_status rs_get_skeleton(const rs_ctx* ctx, int box, int cap, int* out, int* len);
+
+/* Apply the augmented operator exactly in float64 on the device:
+ * y = A x, x host (2N+3p) x ncols column-major, y host same shape.  This is
+ * the residual kernel used by refinement, exposed for verification. */
+rs_status rs_apply(rs_ctx* ctx, int ncols, const double* x, double* y);
+
+void rs_destroy(rs_ctx* ctx);
+
+/* Message of the last failed call on ctx (or of the last failed rs_build_tree
+ * when ctx is NULL).  Valid until the next call on that context. */
+const char* rs_last_error(const rs_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RS_MI355X_H */

@@ -154,7 +154,7 @@ class RSFactorization:
         _, _, _, rp = proxy_circle(b.cx, b.cy, b.side, self.prm.n_proxy, self.prm.proxy_ratio)
         cand = np.nonzero(active)[0]
         d = self.geom.xy[cand // 2] - np.array([b.cx, b.cy])[None, :]
-        inside = np.hypot(d[:, 0], d[:, 1]) < rp
+        inside = d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1] < rp * rp   # |x - c_B| < r_p
         cand = cand[inside]
         return cand[~np.isin(cand, I)]
 

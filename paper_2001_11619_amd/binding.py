@@ -1,0 +1,266 @@
+"""ctypes binding of the C ABI in include/rs.h (argument marshalling only)."""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIBNAME = "librs_mi355x.so"
+
+RS_STATUS = {
+    0: "RS_OK", 1: "RS_ERR_ARG", 2: "RS_ERR_STATE", 3: "RS_ERR_ALLOC", 4: "RS_ERR_DEVICE",
+    5: "RS_ERR_SINGULAR", 6: "RS_ERR_NOCONV", 7: "RS_ERR_OUT_OF_ROOT",
+}
+
+
+class RSError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (RS_STATUS.get(status, str(status)), msg))
+        self.status = status
+        self.name = RS_STATUS.get(status, str(status))
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("lambda_", ctypes.c_double),
+        ("tol", ctypes.c_double),
+        ("leaf_size", ctypes.c_int),
+        ("n_proxy", ctypes.c_int),
+        ("proxy_ratio", ctypes.c_double),
+        ("rcond_min", ctypes.c_double),
+        ("precision", ctypes.c_int),
+        ("refine_tol", ctypes.c_double),
+        ("refine_max", ctypes.c_int),
+        ("has_root", ctypes.c_int),
+        ("root", ctypes.c_double * 3),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("n_nodes", ctypes.c_int), ("n_holes", ctypes.c_int), ("n_levels", ctypes.c_int),
+        ("n_boxes", ctypes.c_int), ("root_skeleton", ctypes.c_int),
+        ("max_box_unknowns", ctypes.c_int), ("max_rank", ctypes.c_int),
+        ("guard_bumps", ctypes.c_int), ("factor_bytes", ctypes.c_longlong),
+        ("flops_id", ctypes.c_double), ("flops_elim", ctypes.c_double),
+        ("ms_factor", ctypes.c_double), ("ms_solve", ctypes.c_double),
+        ("refine_iters", ctypes.c_int), ("ms_update", ctypes.c_double),
+        ("boxes_recomputed", ctypes.c_int),
+    ]
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return os.path.join(_HERE, _LIBNAME)
+
+
+def load_library():
+    """Load the built library; raise loudly when it is missing (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = library_path()
+    if not os.path.exists(path):
+        raise RuntimeError("%s is not built; run `python -c 'import __graft_entry__ as g; g.build()'`" % path)
+    lib = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    dp, ip, vp = P(ctypes.c_double), P(ctypes.c_int), ctypes.c_void_p
+    h = ctypes.c_void_p
+    lib.rs_default_params.argtypes = [P(Params)]
+    lib.rs_default_params.restype = None
+    lib.rs_build_tree.argtypes = [P(Params), ctypes.c_int, dp, dp, dp, dp, ip, ctypes.c_int, dp, P(h)]
+    lib.rs_factor.argtypes = [h]
+    lib.rs_solve.argtypes = [h, ctypes.c_int, dp, dp, dp]
+    lib.rs_solve_dev.argtypes = [h, ctypes.c_int, vp, vp]
+    lib.rs_update_moved_nodes.argtypes = [h, ctypes.c_int, ip, dp, dp, dp, dp, dp]
+    lib.rs_set_stream.argtypes = [h, vp]
+    lib.rs_get_stats.argtypes = [h, P(Stats)]
+    lib.rs_get_boxes.argtypes = [h, ctypes.c_int, ip, ip, ip, ip, dp]
+    lib.rs_get_skeleton.argtypes = [h, ctypes.c_int, ctypes.c_int, ip, ip]
+    lib.rs_apply.argtypes = [h, ctypes.c_int, dp, dp]
+    lib.rs_destroy.argtypes = [h]
+    lib.rs_destroy.restype = None
+    lib.rs_last_error.argtypes = [h]
+    lib.rs_last_error.restype = ctypes.c_char_p
+    for name in ("rs_build_tree", "rs_factor", "rs_solve", "rs_solve_dev", "rs_update_moved_nodes",
+                 "rs_set_stream", "rs_get_stats", "rs_get_boxes", "rs_get_skeleton", "rs_apply"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    """Names declared in include/rs.h that the loaded library exports."""
+    lib = load_library()
+    out = []
+    for name in ("rs_default_params", "rs_build_tree", "rs_factor", "rs_solve", "rs_solve_dev",
+                 "rs_update_moved_nodes", "rs_set_stream", "rs_get_stats", "rs_get_boxes",
+                 "rs_get_skeleton", "rs_apply", "rs_destroy", "rs_last_error"):
+        if hasattr(lib, name):
+            out.append(name)
+    return out
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _iptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def default_params() -> Params:
+    p = Params()
+    load_library().rs_default_params(ctypes.byref(p))
+    return p
+
+
+class RSSolver:
+    """One factorization context on the current HIP device."""
+
+    def __init__(self, xy, normal, weight, curvature, curve_id, hole_xy=None, *, tol=None,
+                 leaf_size=None, n_proxy=None, proxy_ratio=None, lam=None, rcond_min=None,
+                 precision=None, refine_tol=None, refine_max=None, root=None):
+        lib = load_library()
+        self._lib = lib
+        self._h = ctypes.c_void_p()
+        p = default_params()
+        for name, val in (("tol", tol), ("leaf_size", leaf_size), ("n_proxy", n_proxy),
+                          ("proxy_ratio", proxy_ratio), ("lambda_", lam), ("rcond_min", rcond_min),
+                          ("precision", precision), ("refine_tol", refine_tol),
+                          ("refine_max", refine_max)):
+            if val is not None:
+                setattr(p, name, val)
+        if root is not None:
+            p.has_root = 1
+            for i in range(3):
+                p.root[i] = float(root[i])
+        self.params = p
+        xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
+        N = xy.shape[0]
+        normal = np.ascontiguousarray(normal, dtype=np.float64).reshape(N, 2)
+        weight = np.ascontiguousarray(weight, dtype=np.float64).reshape(N)
+        curvature = np.ascontiguousarray(curvature, dtype=np.float64).reshape(N)
+        curve_id = np.ascontiguousarray(curve_id, dtype=np.int32).reshape(N)
+        n_holes = int(curve_id.max()) if N else 0
+        hp = None
+        if hole_xy is not None and n_holes:
+            hole_xy = np.ascontiguousarray(hole_xy, dtype=np.float64).reshape(n_holes, 2)
+            hp = _dptr(hole_xy)
+        st = lib.rs_build_tree(ctypes.byref(p), N, _dptr(xy), _dptr(normal), _dptr(weight),
+                               _dptr(curvature), _iptr(curve_id), n_holes, hp, ctypes.byref(self._h))
+        if st != 0:
+            raise RSError(st, lib.rs_last_error(None).decode())
+        self.n_nodes = N
+        self.n_holes = n_holes
+
+    @classmethod
+    def from_geometry(cls, geom, **kw):
+        if getattr(geom, "root", None) is not None and "root" not in kw:
+            kw["root"] = geom.root
+        return cls(geom.xy, geom.normal, geom.weight, geom.curvature, geom.curve_id,
+                   geom.hole_xy if geom.n_holes else None, **kw)
+
+    # -- helpers --
+    def _check(self, st):
+        if st != 0:
+            raise RSError(st, self._lib.rs_last_error(self._h).decode())
+
+    @property
+    def n_dofs(self):
+        return 2 * self.n_nodes
+
+    @property
+    def n_system(self):
+        return 2 * self.n_nodes + 3 * self.n_holes
+
+    # -- API --
+    def factor(self):
+        self._check(self._lib.rs_factor(self._h))
+        return self
+
+    def solve(self, f, residual: bool = False):
+        f = np.asarray(f, dtype=np.float64)
+        one = f.ndim == 1
+        F = np.asfortranarray(f.reshape(self.n_dofs, -1))
+        nrhs = F.shape[1]
+        X = np.empty((self.n_system, nrhs), dtype=np.float64, order="F")
+        res = np.empty(nrhs) if residual else None
+        self._check(self._lib.rs_solve(self._h, nrhs, _dptr(F), _dptr(X),
+                                       _dptr(res) if residual else None))
+        x = X[:, 0] if one else np.ascontiguousarray(X)
+        return (x, res) if residual else x
+
+    def solve_dev(self, f_dev, x_dev):
+        """f_dev, x_dev: device tensors laid out column-major ((2N) x nrhs, (2N+3p) x nrhs),
+        i.e. torch tensors of shape (nrhs, 2N) and (nrhs, 2N+3p), contiguous, float64."""
+        nrhs = int(f_dev.shape[0])
+        self._check(self._lib.rs_solve_dev(self._h, nrhs, ctypes.c_void_p(f_dev.data_ptr()),
+                                           ctypes.c_void_p(x_dev.data_ptr())))
+
+    def apply(self, x):
+        x = np.asarray(x, dtype=np.float64)
+        one = x.ndim == 1
+        Xf = np.asfortranarray(x.reshape(self.n_system, -1))
+        Y = np.empty_like(Xf, order="F")
+        self._check(self._lib.rs_apply(self._h, Xf.shape[1], _dptr(Xf), _dptr(Y)))
+        return Y[:, 0] if one else np.ascontiguousarray(Y)
+
+    def update_moved_nodes(self, idx, xy, normal, weight, curvature, hole_xy=None):
+        idx = np.ascontiguousarray(idx, dtype=np.int32)
+        n = idx.size
+        xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(n, 2)
+        normal = np.ascontiguousarray(normal, dtype=np.float64).reshape(n, 2)
+        weight = np.ascontiguousarray(weight, dtype=np.float64).reshape(n)
+        curvature = np.ascontiguousarray(curvature, dtype=np.float64).reshape(n)
+        hp = None
+        if hole_xy is not None:
+            hole_xy = np.ascontiguousarray(hole_xy, dtype=np.float64).reshape(-1, 2)
+            hp = _dptr(hole_xy)
+        self._check(self._lib.rs_update_moved_nodes(self._h, n, _iptr(idx), _dptr(xy), _dptr(normal),
+                                                    _dptr(weight), _dptr(curvature), hp))
+        return self
+
+    def set_stream(self, stream_ptr: int):
+        self._check(self._lib.rs_set_stream(self._h, ctypes.c_void_p(stream_ptr)))
+
+    def stats(self) -> dict:
+        s = Stats()
+        self._check(self._lib.rs_get_stats(self._h, ctypes.byref(s)))
+        return {name: getattr(s, name) for name, _ in Stats._fields_}
+
+    def boxes(self) -> dict:
+        nb = ctypes.c_int()
+        self._lib.rs_get_boxes(self._h, 0, ctypes.byref(nb), None, None, None, None)
+        n = nb.value
+        lev = np.empty(n, np.int32)
+        na = np.empty(n, np.int32)
+        rk = np.empty(n, np.int32)
+        geo = np.empty(3 * n, np.float64)
+        self._check(self._lib.rs_get_boxes(self._h, n, ctypes.byref(nb), _iptr(lev), _iptr(na),
+                                           _iptr(rk), _dptr(geo)))
+        return {"level": lev, "n": na, "k": rk, "geom": geo.reshape(n, 3)}
+
+    def skeleton(self, box: int) -> np.ndarray:
+        ln = ctypes.c_int()
+        self._lib.rs_get_skeleton(self._h, box, 0, None, ctypes.byref(ln))
+        out = np.empty(max(ln.value, 1), np.int32)
+        self._check(self._lib.rs_get_skeleton(self._h, box, out.size, _iptr(out), ctypes.byref(ln)))
+        return out[: ln.value].copy()
+
+    def close(self):
+        if self._h:
+            self._lib.rs_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

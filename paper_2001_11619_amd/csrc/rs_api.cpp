@@ -1,0 +1,1072 @@
+// Host driver and C ABI of the recursive-skeletonization solver.
+//
+// The host owns the quadtree (Section 2.3), the per-level bookkeeping of
+// active unknowns and near fields (Section 2.7: every box of a level reads
+// the level-start active set), and the launch sequence; every arithmetic step
+// of the factorization and solve runs in the gfx950 kernels of
+// rs_kernels.hip.  One host synchronisation per level reads back the ranks
+// and pivot orders, which size the next level.
+#include "rs.h"
+#include "rs_internal.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#pragma clang fp contract(off)
+
+using namespace rs;
+
+namespace {
+
+struct RsError {
+  rs_status st;
+  std::string msg;
+};
+
+#define HIP_CHECK(expr)                                                                   \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      throw RsError{e_ == hipErrorOutOfMemory ? RS_ERR_ALLOC : RS_ERR_DEVICE,             \
+                    std::string(#expr) + ": " + hipGetErrorString(e_)};                   \
+  } while (0)
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  void ensure(size_t nb) {
+    if (nb <= bytes) return;
+    release();
+    if (nb == 0) return;
+    HIP_CHECK(hipMalloc(&p, nb));
+    bytes = nb;
+  }
+  template <class T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+// Host-to-device copy on the context stream; returns once the host buffer
+// may be reused.
+template <class T>
+void upload(DevBuf& b, const std::vector<T>& v, hipStream_t s) {
+  b.ensure(std::max<size_t>(v.size() * sizeof(T), 16));
+  if (v.empty()) return;
+  HIP_CHECK(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  HIP_CHECK(hipStreamSynchronize(s));
+}
+
+struct Box {
+  int level = 0;
+  double cx = 0, cy = 0, side = 0;
+  long long ix = 0, iy = 0;
+  int parent = -1;
+  int child[4] = {-1, -1, -1, -1};
+  int nchild = 0;
+  std::vector<int> nodes;
+  bool leaf() const { return nchild == 0; }
+};
+
+struct BoxFac {
+  int n = 0, k = 0, level = 0;
+  bool active = false;        // compressed (n > 0, not the root)
+  std::vector<int> I;         // active unknowns, ascending
+  std::vector<int> perm;      // pivot order (positions into I)
+  double* T = nullptr;
+  double* E = nullptr;
+  double* F = nullptr;
+  double* Xinv = nullptr;
+  double* Xss = nullptr;
+  double* W = nullptr;
+  int arena_level = -1;
+  int rank0 = 0;
+};
+
+constexpr int kMaxDepth = 48;
+constexpr int kGuardExtra = 8;
+
+inline long long key2(long long ix, long long iy) { return (ix << 32) ^ (iy & 0xffffffffLL); }
+
+}  // namespace
+
+struct rs_ctx {
+  rs_params prm{};
+  int N = 0, p = 0;
+  std::vector<double> x, y, nx, ny, w, kap, hole;
+  std::vector<int> curve;
+  hipStream_t stream = nullptr;
+  std::string err;
+  int device = 0;
+
+  // device geometry
+  DevBuf d_x, d_y, d_nx, d_ny, d_w, d_kap, d_curve, d_hole;
+
+  // tree
+  std::vector<Box> boxes;
+  int L = 0;
+  double root_cx = 0, root_cy = 0, root_side = 0;
+
+  // factorization
+  bool factored = false;
+  std::vector<BoxFac> fac;
+  std::vector<DevBuf*> level_arena;   // per level
+  // level workspaces (reused level to level)
+  DevBuf ws_M, ws_R, ws_A, ws_scr, ws_boxes, ws_dofs, ws_fint, ws_src, ws_perm, ws_k, ws_kx,
+      ws_status;
+  // root
+  std::vector<int> I0;
+  DevBuf d_I0, d_X0, d_Z, d_Zinv, d_gjwork, d_rcond, d_rstatus, d_root_box;
+  DevBuf d_H, d_Hh, d_Ph, d_Gpart, d_G, d_bscr, d_W;
+  int nz = 0;
+  // solve metadata
+  std::vector<std::vector<SolveBox>> sboxes;   // per level
+  std::vector<int> lvl_maxn, lvl_maxr;
+  DevBuf d_sboxes, d_sidx, d_ridx;
+  std::vector<size_t> sbox_off;                 // offset of each level's boxes in d_sboxes
+  int n_solve_boxes = 0;
+  int all_maxr = 0;
+  // solve work
+  DevBuf d_f, d_c, d_v, d_sol, d_parts, d_rhs2, d_xout, d_res;
+
+  rs_stats stats{};
+
+  ~rs_ctx() {
+    for (auto* b : level_arena) delete b;
+  }
+};
+
+namespace {
+
+thread_local std::string g_build_error;
+
+void geo_of(const rs_ctx* c, Geo& g) {
+  g.x = c->d_x.as<double>();
+  g.y = c->d_y.as<double>();
+  g.nx = c->d_nx.as<double>();
+  g.ny = c->d_ny.as<double>();
+  g.w = c->d_w.as<double>();
+  g.kap = c->d_kap.as<double>();
+  g.N = c->N;
+}
+
+void build_tree(rs_ctx* c) {
+  c->boxes.clear();
+  Box root;
+  if (c->prm.has_root) {
+    root.cx = c->prm.root[0];
+    root.cy = c->prm.root[1];
+    root.side = c->prm.root[2];
+  } else {
+    double xmin = c->x[0], xmax = c->x[0], ymin = c->y[0], ymax = c->y[0];
+    for (int i = 1; i < c->N; ++i) {
+      xmin = std::min(xmin, c->x[i]);
+      xmax = std::max(xmax, c->x[i]);
+      ymin = std::min(ymin, c->y[i]);
+      ymax = std::max(ymax, c->y[i]);
+    }
+    root.cx = 0.5 * (xmin + xmax);
+    root.cy = 0.5 * (ymin + ymax);
+    root.side = (1.0 + std::ldexp(1.0, -20)) * std::max(xmax - xmin, ymax - ymin);
+    if (root.side == 0.0) root.side = 1.0;
+  }
+  root.nodes.resize(c->N);
+  for (int i = 0; i < c->N; ++i) root.nodes[i] = i;
+  c->root_cx = root.cx;
+  c->root_cy = root.cy;
+  c->root_side = root.side;
+  c->boxes.push_back(std::move(root));
+  size_t head = 0;
+  const int leaf = c->prm.leaf_size;
+  while (head < c->boxes.size()) {
+    const size_t bi = head++;
+    if ((int)c->boxes[bi].nodes.size() <= leaf) continue;
+    if (c->boxes[bi].level >= kMaxDepth)
+      throw RsError{RS_ERR_ARG, "quadtree deeper than 48 levels (coincident nodes?)"};
+    const double cx = c->boxes[bi].cx, cy = c->boxes[bi].cy, side = c->boxes[bi].side;
+    std::vector<int> part[4];
+    for (int j : c->boxes[bi].nodes) {
+      const int q = (c->x[j] >= cx ? 1 : 0) + 2 * (c->y[j] >= cy ? 1 : 0);
+      part[q].push_back(j);
+    }
+    const double h = side / 4.0;
+    for (int q = 0; q < 4; ++q) {
+      if (part[q].empty()) continue;
+      Box ch;
+      ch.level = c->boxes[bi].level + 1;
+      ch.cx = (q % 2 == 0) ? cx - h : cx + h;
+      ch.cy = (q < 2) ? cy - h : cy + h;
+      ch.side = side / 2.0;
+      ch.ix = 2 * c->boxes[bi].ix + (q & 1);
+      ch.iy = 2 * c->boxes[bi].iy + (q >> 1);
+      ch.parent = (int)bi;
+      ch.nodes = std::move(part[q]);
+      const int id = (int)c->boxes.size();
+      c->boxes[bi].child[c->boxes[bi].nchild++] = id;
+      c->boxes.push_back(std::move(ch));
+    }
+  }
+  c->L = 0;
+  for (const Box& b : c->boxes) c->L = std::max(c->L, b.level);
+}
+
+std::vector<int> skeleton_of(const BoxFac& f) {
+  std::vector<int> s(f.k);
+  for (int i = 0; i < f.k; ++i) s[i] = f.I[f.perm[i]];
+  return s;
+}
+
+std::vector<int> redundant_of(const BoxFac& f) {
+  std::vector<int> r(f.n - f.k);
+  for (int i = f.k; i < f.n; ++i) r[i - f.k] = f.I[f.perm[i]];
+  return r;
+}
+
+std::vector<int> leaf_dofs(const Box& b) {
+  std::vector<int> d;
+  d.reserve(2 * b.nodes.size());
+  for (int j : b.nodes) {
+    d.push_back(2 * j);
+    d.push_back(2 * j + 1);
+  }
+  std::sort(d.begin(), d.end());
+  return d;
+}
+
+// Unknowns of box b and, for a parent, where each one sits in its child's X_SS.
+void box_unknowns(const rs_ctx* c, int b, std::vector<int>& I, std::vector<ChildSrc>* src) {
+  const Box& B = c->boxes[b];
+  I.clear();
+  if (src) src->clear();
+  if (B.leaf()) {
+    I = leaf_dofs(B);
+    return;
+  }
+  struct E { int dof; int child; int idx; };
+  std::vector<E> ents;
+  for (int q = 0; q < B.nchild; ++q) {
+    const int ch = B.child[q];
+    const BoxFac& f = c->fac[ch];
+    for (int i = 0; i < f.k; ++i) ents.push_back({f.I[f.perm[i]], ch, i});
+  }
+  std::sort(ents.begin(), ents.end(), [](const E& a, const E& b2) { return a.dof < b2.dof; });
+  I.resize(ents.size());
+  if (src) src->resize(ents.size());
+  for (size_t i = 0; i < ents.size(); ++i) {
+    I[i] = ents[i].dof;
+    if (src) {
+      const BoxFac& f = c->fac[ents[i].child];
+      (*src)[i] = ChildSrc{f.Xss, ents[i].idx, f.k, ents[i].child, 0};
+    }
+  }
+}
+
+double seconds_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// Factor every box of level l (ids in `ids`), reading the level-start active set.
+void factor_level(rs_ctx* c, int l, const std::vector<int>& ids, const std::vector<char>& active,
+                  std::vector<int>& boxes_done) {
+  const rs_params& P = c->prm;
+  hipStream_t s = c->stream;
+  Geo g;
+  geo_of(c, g);
+  // unknowns of every box at this level
+  std::vector<std::vector<int>> Is(ids.size());
+  std::vector<std::vector<ChildSrc>> srcs(ids.size());
+  for (size_t t = 0; t < ids.size(); ++t) box_unknowns(c, ids[t], Is[t], &srcs[t]);
+  // cell map of this level and of coarser leaves
+  std::vector<std::unordered_map<long long, int>> cells(l + 1);
+  for (size_t bi = 0; bi < c->boxes.size(); ++bi) {
+    const Box& B = c->boxes[bi];
+    if (B.level == l) cells[l][key2(B.ix, B.iy)] = (int)bi;
+    else if (B.level < l && B.leaf()) cells[B.level][key2(B.ix, B.iy)] = (int)bi;
+  }
+  std::unordered_map<int, int> pos_of;
+  for (size_t t = 0; t < ids.size(); ++t) pos_of[ids[t]] = (int)t;
+
+  std::vector<LevelBox> lb;
+  std::vector<int> dofs, fint;
+  std::vector<ChildSrc> src_all;
+  std::vector<int> sel;   // positions in ids with n > 0
+  size_t totM = 0, totN2 = 0, totArena = 0;
+  int max_m = 0, max_n = 0;
+  std::vector<int> cand;
+  for (size_t t = 0; t < ids.size(); ++t) {
+    const int b = ids[t];
+    const Box& B = c->boxes[b];
+    BoxFac& f = c->fac[b];
+    f.level = l;
+    f.I = Is[t];
+    f.n = (int)f.I.size();
+    f.active = f.n > 0;
+    if (f.n == 0) {
+      f.k = 0;
+      f.perm.clear();
+      continue;
+    }
+    // near field F_int: active unknowns strictly inside the proxy circle, not in I_B
+    const double rp = P.proxy_ratio * B.side;
+    const double rp2 = rp * rp;
+    cand.clear();
+    for (long long dx = -2; dx <= 2; ++dx)
+      for (long long dy = -2; dy <= 2; ++dy) {
+        if (dx == 0 && dy == 0) continue;
+        auto it = cells[l].find(key2(B.ix + dx, B.iy + dy));
+        if (it == cells[l].end()) continue;
+        auto pit = pos_of.find(it->second);
+        if (pit == pos_of.end()) continue;
+        for (int d : Is[pit->second]) cand.push_back(d);
+      }
+    for (int lc = 0; lc < l; ++lc) {
+      const long long ax = B.ix >> (l - lc), ay = B.iy >> (l - lc);
+      for (long long dx = -1; dx <= 1; ++dx)
+        for (long long dy = -1; dy <= 1; ++dy) {
+          auto it = cells[lc].find(key2(ax + dx, ay + dy));
+          if (it == cells[lc].end()) continue;
+          const Box& C = c->boxes[it->second];
+          for (int j : C.nodes) {
+            cand.push_back(2 * j);
+            cand.push_back(2 * j + 1);
+          }
+        }
+    }
+    std::vector<int> F;
+    for (int d : cand) {
+      if (!active[d]) continue;
+      const int j = d >> 1;
+      const double ddx = c->x[j] - B.cx, ddy = c->y[j] - B.cy;
+      if (ddx * ddx + ddy * ddy < rp2) F.push_back(d);
+    }
+    std::sort(F.begin(), F.end());
+    F.erase(std::unique(F.begin(), F.end()), F.end());
+    LevelBox x{};
+    x.cx = B.cx;
+    x.cy = B.cy;
+    x.side = B.side;
+    x.n = f.n;
+    x.nF = (int)F.size();
+    x.m = 2 * x.nF + 6 * P.n_proxy + 2;
+    x.dof_off = (int)dofs.size();
+    x.fint_off = (int)fint.size();
+    x.src_off = B.leaf() ? -1 : (int)src_all.size();
+    x.kcap = f.n;
+    dofs.insert(dofs.end(), f.I.begin(), f.I.end());
+    fint.insert(fint.end(), F.begin(), F.end());
+    if (!B.leaf()) src_all.insert(src_all.end(), srcs[t].begin(), srcs[t].end());
+    totM += (size_t)x.m * x.n;
+    const size_t n2 = (size_t)x.n * x.n;
+    totN2 += n2;
+    totArena += 3 * (n2 / 4 + x.n) + 2 * n2;
+    max_m = std::max(max_m, x.m);
+    max_n = std::max(max_n, x.n);
+    lb.push_back(x);
+    sel.push_back((int)t);
+  }
+  const int nb = (int)lb.size();
+  if (nb == 0) return;
+  // workspaces
+  c->ws_M.ensure(totM * sizeof(double));
+  c->ws_R.ensure(totN2 * sizeof(double));
+  c->ws_A.ensure(totN2 * sizeof(double));
+  c->ws_scr.ensure(3 * totN2 * sizeof(double));
+  DevBuf* arena = new DevBuf();
+  c->level_arena.push_back(arena);
+  arena->ensure(totArena * sizeof(double));
+  {
+    double* pM = c->ws_M.as<double>();
+    double* pR = c->ws_R.as<double>();
+    double* pA = c->ws_A.as<double>();
+    double* pS = c->ws_scr.as<double>();
+    double* pa = arena->as<double>();
+    for (int i = 0; i < nb; ++i) {
+      LevelBox& x = lb[i];
+      const size_t n2 = (size_t)x.n * x.n;
+      const size_t kr = n2 / 4 + x.n;
+      x.M = pM;
+      pM += (size_t)x.m * x.n;
+      x.R = pR;
+      pR += n2;
+      x.Ap = pA;
+      pA += n2;
+      x.scr = pS;
+      pS += 3 * n2;
+      x.T = pa;
+      pa += kr;
+      x.E = pa;
+      pa += kr;
+      x.F = pa;
+      pa += kr;
+      x.Xinv = pa;
+      pa += n2;
+      x.Xss = pa;
+      pa += n2;
+      BoxFac& f = c->fac[ids[sel[i]]];
+      f.T = x.T;
+      f.E = x.E;
+      f.F = x.F;
+      f.Xinv = x.Xinv;
+      f.Xss = x.Xss;
+    }
+  }
+  upload(c->ws_boxes, lb, s);
+  upload(c->ws_dofs, dofs, s);
+  upload(c->ws_fint, fint, s);
+  upload(c->ws_src, src_all, s);
+  c->ws_perm.ensure(std::max<size_t>(dofs.size(), 4) * sizeof(int));
+  c->ws_k.ensure(nb * sizeof(int));
+  c->ws_kx.ensure(nb * sizeof(int));
+  c->ws_status.ensure(nb * sizeof(int));
+  const LevelBox* dlb = c->ws_boxes.as<LevelBox>();
+  launch_assemble_M(dlb, nb, max_m, c->ws_dofs.as<int>(), c->ws_fint.as<int>(), g, P.n_proxy,
+                    P.proxy_ratio, s);
+  launch_cpqr(dlb, nb, P.tol, kGuardExtra, c->ws_perm.as<int>(), c->ws_k.as<int>(),
+              c->ws_kx.as<int>(), max_n, s);
+  launch_assemble_abb(dlb, nb, max_n, c->ws_dofs.as<int>(), c->ws_perm.as<int>(),
+                      c->ws_src.as<ChildSrc>(), g, P.lambda, s);
+  std::vector<int> k0(nb);
+  HIP_CHECK(hipMemcpyAsync(k0.data(), c->ws_k.p, nb * sizeof(int), hipMemcpyDeviceToHost, s));
+  launch_eliminate(dlb, nb, c->ws_k.as<int>(), c->ws_kx.as<int>(), P.rcond_min,
+                   c->ws_status.as<int>(), max_n, s);
+  HIP_CHECK(hipGetLastError());
+  std::vector<int> perm(dofs.size()), kk(nb), st(nb);
+  HIP_CHECK(hipMemcpyAsync(perm.data(), c->ws_perm.p, perm.size() * sizeof(int),
+                           hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipMemcpyAsync(kk.data(), c->ws_k.p, nb * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipMemcpyAsync(st.data(), c->ws_status.p, nb * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipStreamSynchronize(s));
+  for (int i = 0; i < nb; ++i) {
+    const int b = ids[sel[i]];
+    BoxFac& f = c->fac[b];
+    const LevelBox& x = lb[i];
+    f.perm.assign(perm.begin() + x.dof_off, perm.begin() + x.dof_off + x.n);
+    f.k = kk[i];
+    f.rank0 = k0[i];
+    f.arena_level = (int)c->level_arena.size() - 1;
+    if (st[i] != 0)
+      throw RsError{RS_ERR_SINGULAR, "X_RR stayed singular after the pivot guard (box " +
+                                         std::to_string(b) + ")"};
+    c->stats.guard_bumps += f.k - f.rank0;
+    // algorithmic flop counts
+    const double m = x.m, n = x.n, k = f.k, r = n - k;
+    double fid = 0;
+    const int steps = std::min<int>(x.m, std::min<int>(x.n, f.rank0 + 1));
+    for (int j = 0; j < steps; ++j) fid += 4.0 * (m - j) * (n - j);
+    c->stats.flops_id += fid;
+    c->stats.flops_elim += k * k * r + 4 * k * k * r + 4 * k * r * r + 2 * r * r * r +
+                           4 * k * r * r + 2 * k * k * r;
+    c->stats.max_box_unknowns = std::max(c->stats.max_box_unknowns, x.n);
+    c->stats.max_rank = std::max(c->stats.max_rank, f.k);
+    boxes_done.push_back(b);
+  }
+}
+
+void build_solve_meta(rs_ctx* c) {
+  const int L = c->L;
+  c->sboxes.assign(L + 1, {});
+  c->lvl_maxn.assign(L + 1, 0);
+  c->lvl_maxr.assign(L + 1, 0);
+  std::vector<int> sidx, ridx;
+  int part = 0;
+  c->all_maxr = 0;
+  c->stats.factor_bytes = 0;
+  for (size_t b = 1; b < c->boxes.size(); ++b) {
+    const BoxFac& f = c->fac[b];
+    if (!f.active) continue;
+    SolveBox sb{};
+    sb.k = f.k;
+    sb.r = f.n - f.k;
+    sb.s_off = (int)sidx.size();
+    sb.r_off = (int)ridx.size();
+    sb.part = part++;
+    sb.T = f.T;
+    sb.E = f.E;
+    sb.F = f.F;
+    sb.Xinv = f.Xinv;
+    sb.W = nullptr;
+    for (int i = 0; i < f.k; ++i) sidx.push_back(f.I[f.perm[i]]);
+    for (int i = f.k; i < f.n; ++i) ridx.push_back(f.I[f.perm[i]]);
+    c->sboxes[f.level].push_back(sb);
+    c->lvl_maxn[f.level] = std::max(c->lvl_maxn[f.level], f.n);
+    c->lvl_maxr[f.level] = std::max(c->lvl_maxr[f.level], sb.r);
+    c->all_maxr = std::max(c->all_maxr, sb.r);
+    c->stats.factor_bytes += (long long)(3LL * sb.k * sb.r + 1LL * sb.r * sb.r) * 8;
+  }
+  c->n_solve_boxes = part;
+  // border W slots
+  const int p3 = 3 * c->p;
+  if (p3) {
+    size_t totW = 0;
+    for (auto& lv : c->sboxes)
+      for (auto& sb : lv) totW += (size_t)sb.r * p3;
+    c->d_W.ensure(std::max<size_t>(totW, 1) * sizeof(double));
+    double* pw = c->d_W.as<double>();
+    for (auto& lv : c->sboxes)
+      for (auto& sb : lv) {
+        sb.W = pw;
+        pw += (size_t)sb.r * p3;
+      }
+  }
+  std::vector<SolveBox> flat;
+  c->sbox_off.assign(L + 2, 0);
+  for (int l = 0; l <= L; ++l) {
+    c->sbox_off[l] = flat.size();
+    flat.insert(flat.end(), c->sboxes[l].begin(), c->sboxes[l].end());
+  }
+  c->sbox_off[L + 1] = flat.size();
+  upload(c->d_sboxes, flat, c->stream);
+  upload(c->d_sidx, sidx, c->stream);
+  upload(c->d_ridx, ridx, c->stream);
+}
+
+const SolveBox* level_sboxes(const rs_ctx* c, int l) {
+  return c->d_sboxes.as<SolveBox>() + c->sbox_off[l];
+}
+int level_count(const rs_ctx* c, int l) { return (int)(c->sbox_off[l + 1] - c->sbox_off[l]); }
+
+void sweep_all(rs_ctx* c, double* buf, int ncols, int mode) {
+  const int L = c->L;
+  if (mode == 2) {
+    for (int l = 1; l <= L; ++l)
+      launch_sweep(level_sboxes(c, l), level_count(c, l), c->d_sidx.as<int>(), c->d_ridx.as<int>(),
+                   buf, ncols, mode, c->lvl_maxn[l], c->stream);
+  } else {
+    for (int l = L; l >= 1; --l)
+      launch_sweep(level_sboxes(c, l), level_count(c, l), c->d_sidx.as<int>(), c->d_ridx.as<int>(),
+                   buf, ncols, mode, c->lvl_maxn[l], c->stream);
+  }
+}
+
+void factor_root(rs_ctx* c) {
+  hipStream_t s = c->stream;
+  Geo g;
+  geo_of(c, g);
+  std::vector<ChildSrc> src;
+  box_unknowns(c, 0, c->I0, &src);
+  const int n0 = (int)c->I0.size();
+  const int p3 = 3 * c->p;
+  c->nz = n0 + p3;
+  upload(c->d_I0, c->I0, s);
+  c->d_X0.ensure(std::max<size_t>((size_t)n0 * n0, 1) * sizeof(double));
+  if (n0 > 0) {
+    LevelBox rb{};
+    rb.n = n0;
+    rb.dof_off = 0;
+    rb.src_off = c->boxes[0].leaf() ? -1 : 0;
+    rb.Ap = c->d_X0.as<double>();
+    std::vector<LevelBox> v{rb};
+    upload(c->d_root_box, v, s);
+    upload(c->ws_src, src, s);
+    launch_assemble_abb(c->d_root_box.as<LevelBox>(), 1, n0, c->d_I0.as<int>(), nullptr,
+                        c->ws_src.as<ChildSrc>(), g, c->prm.lambda, s);
+  }
+  build_solve_meta(c);
+  const int nz = c->nz;
+  c->d_Zinv.ensure(std::max<size_t>((size_t)nz * nz, 1) * sizeof(double));
+  c->d_gjwork.ensure(std::max<size_t>((size_t)nz * nz, 1) * sizeof(double));
+  c->d_rcond.ensure(sizeof(double));
+  c->d_rstatus.ensure(sizeof(int));
+  const double* Zsrc = c->d_X0.as<double>();
+  if (p3) {
+    const size_t hn = (size_t)2 * c->N * p3;
+    c->d_H.ensure(hn * sizeof(double));
+    c->d_Hh.ensure(hn * sizeof(double));
+    c->d_Ph.ensure(hn * sizeof(double));
+    launch_assemble_H(g, c->d_hole.as<double>(), c->p, c->d_curve.as<int>(), c->d_Hh.as<double>(),
+                      c->d_Ph.as<double>(), s);
+    sweep_all(c, c->d_Hh.as<double>(), p3, 0);
+    sweep_all(c, c->d_Ph.as<double>(), p3, 1);
+    const int nsb = c->n_solve_boxes;
+    c->d_Gpart.ensure(std::max<size_t>((size_t)nsb * p3 * p3, 1) * sizeof(double));
+    long long scr_stride = (long long)2 * c->all_maxr * p3;
+    int max_nb = 1;
+    for (int l = 1; l <= c->L; ++l) max_nb = std::max(max_nb, level_count(c, l));
+    c->d_bscr.ensure(std::max<size_t>((size_t)max_nb * scr_stride, 1) * sizeof(double));
+    for (int l = c->L; l >= 1; --l) {
+      const int nb = level_count(c, l);
+      if (!nb) continue;
+      launch_border_box(level_sboxes(c, l), nb, c->d_ridx.as<int>(), c->d_Hh.as<double>(),
+                        c->d_Ph.as<double>(), p3, c->d_Gpart.as<double>(), c->d_bscr.as<double>(),
+                        scr_stride, s);
+    }
+    c->d_G.ensure((size_t)p3 * p3 * sizeof(double));
+    launch_sum_parts(c->d_Gpart.as<double>(), nsb, (long long)p3 * p3, p3 * p3, 1.0,
+                     c->d_G.as<double>(), s);
+    c->d_Z.ensure((size_t)nz * nz * sizeof(double));
+    launch_assemble_Z(c->d_X0.as<double>(), n0, c->d_Hh.as<double>(), c->d_Ph.as<double>(),
+                      c->d_I0.as<int>(), p3, c->d_G.as<double>(), c->d_Z.as<double>(), s);
+    Zsrc = c->d_Z.as<double>();
+  }
+  if (nz > 0) {
+    launch_gj_inverse(const_cast<double*>(Zsrc), nz, nz, c->d_Zinv.as<double>(),
+                      c->d_gjwork.as<double>(), c->d_rcond.as<double>(), c->d_rstatus.as<int>(), s);
+    HIP_CHECK(hipGetLastError());
+    int st = 0;
+    HIP_CHECK(hipMemcpyAsync(&st, c->d_rstatus.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    if (st) throw RsError{RS_ERR_SINGULAR, "root system is singular"};
+  }
+  c->stats.root_skeleton = n0;
+}
+
+void do_factor(rs_ctx* c) {
+  auto t0 = std::chrono::steady_clock::now();
+  for (auto* b : c->level_arena) delete b;
+  c->level_arena.clear();
+  c->fac.assign(c->boxes.size(), BoxFac());
+  c->stats.guard_bumps = 0;
+  c->stats.flops_id = 0;
+  c->stats.flops_elim = 0;
+  c->stats.max_box_unknowns = 0;
+  c->stats.max_rank = 0;
+  std::vector<char> active(2 * (size_t)c->N, 1);
+  std::vector<std::vector<int>> by_level(c->L + 1);
+  for (size_t b = 0; b < c->boxes.size(); ++b) by_level[c->boxes[b].level].push_back((int)b);
+  for (int l = c->L; l >= 1; --l) {
+    std::vector<int> done;
+    factor_level(c, l, by_level[l], active, done);
+    for (int b : done) {
+      const BoxFac& f = c->fac[b];
+      for (int i = f.k; i < f.n; ++i) active[f.I[f.perm[i]]] = 0;
+    }
+  }
+  factor_root(c);
+  c->factored = true;
+  c->stats.n_levels = c->L + 1;
+  c->stats.n_boxes = (int)c->boxes.size();
+  c->stats.ms_factor = 1e3 * seconds_since(t0);
+}
+
+// c (rows, ncols) holds U-transformed data on entry of the root stage.
+void solve_rows(rs_ctx* c, double* cbuf, int ncols) {
+  hipStream_t s = c->stream;
+  const int p3 = 3 * c->p;
+  const int n0 = (int)c->I0.size();
+  sweep_all(c, cbuf, ncols, 0);
+  for (int l = c->L; l >= 1; --l)
+    launch_diag(level_sboxes(c, l), level_count(c, l), c->d_ridx.as<int>(), cbuf, ncols,
+                c->lvl_maxr[l], s);
+  const int nz = c->nz;
+  c->d_v.ensure(std::max<size_t>((size_t)nz * ncols, 1) * sizeof(double));
+  c->d_sol.ensure(std::max<size_t>((size_t)nz * ncols, 1) * sizeof(double));
+  const double* rhs2 = nullptr;
+  if (p3) {
+    const int nsb = c->n_solve_boxes;
+    c->d_parts.ensure(std::max<size_t>((size_t)nsb * p3 * ncols, 1) * sizeof(double));
+    for (int l = c->L; l >= 1; --l)
+      launch_border_rhs(level_sboxes(c, l), level_count(c, l), c->d_ridx.as<int>(),
+                        c->d_Ph.as<double>(), p3, cbuf, ncols, c->d_parts.as<double>(), s);
+    c->d_rhs2.ensure((size_t)p3 * ncols * sizeof(double));
+    launch_sum_parts(c->d_parts.as<double>(), nsb, (long long)p3 * ncols, p3 * ncols, -1.0,
+                     c->d_rhs2.as<double>(), s);
+    rhs2 = c->d_rhs2.as<double>();
+  }
+  if (nz > 0) {
+    launch_root_gather(cbuf, ncols, c->d_I0.as<int>(), n0, rhs2, p3, c->d_v.as<double>(), s);
+    launch_dense_apply(c->d_Zinv.as<double>(), nz, c->d_v.as<double>(), ncols,
+                       c->d_sol.as<double>(), s);
+    if (n0) launch_root_scatter(c->d_sol.as<double>(), ncols, c->d_I0.as<int>(), n0, cbuf, s);
+  }
+  if (p3) {
+    const double* lam = c->d_sol.as<double>() + (size_t)n0 * ncols;
+    for (int l = c->L; l >= 1; --l)
+      launch_border_fix(level_sboxes(c, l), level_count(c, l), c->d_ridx.as<int>(), p3, lam, cbuf,
+                        ncols, s);
+    // lambda rows follow the 2N density rows in cbuf
+    HIP_CHECK(hipMemcpyAsync(cbuf + (size_t)2 * c->N * ncols, lam, (size_t)p3 * ncols * sizeof(double),
+                             hipMemcpyDeviceToDevice, s));
+  }
+  sweep_all(c, cbuf, ncols, 2);
+}
+
+void solve_device(rs_ctx* c, int nrhs, const double* f_dev, double* x_dev) {
+  const int n2 = 2 * c->N;
+  const int ns = n2 + 3 * c->p;
+  c->d_c.ensure((size_t)ns * nrhs * sizeof(double));
+  launch_to_rows(f_dev, n2, n2, nrhs, c->d_c.as<double>(), c->stream);
+  solve_rows(c, c->d_c.as<double>(), nrhs);
+  launch_from_rows(c->d_c.as<double>(), ns, nrhs, x_dev, ns, c->stream);
+  HIP_CHECK(hipGetLastError());
+}
+
+void apply_device_rows(rs_ctx* c, const double* xrows, int ncols, double* yrows) {
+  Geo g;
+  geo_of(c, g);
+  launch_apply_operator(g, c->d_curve.as<int>(), c->d_hole.as<double>(), c->p, c->prm.lambda, xrows,
+                        ncols, yrows, nullptr, c->stream);
+  HIP_CHECK(hipGetLastError());
+}
+
+rs_status fail(rs_ctx* c, const RsError& e) {
+  if (c) c->err = e.msg;
+  else g_build_error = e.msg;
+  return e.st;
+}
+
+bool finite_all(const double* v, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(v[i])) return false;
+  return true;
+}
+
+void validate_nodes(int n, const double* xy, const double* normal, const double* weight,
+                    const double* curvature) {
+  if (!xy || !normal || !weight || !curvature) throw RsError{RS_ERR_ARG, "NULL node array"};
+  if (!finite_all(xy, 2 * (size_t)n) || !finite_all(normal, 2 * (size_t)n) ||
+      !finite_all(weight, n) || !finite_all(curvature, n))
+    throw RsError{RS_ERR_ARG, "non-finite node data"};
+  for (int i = 0; i < n; ++i) {
+    const double nn = std::sqrt(normal[2 * i] * normal[2 * i] + normal[2 * i + 1] * normal[2 * i + 1]);
+    if (std::fabs(nn - 1.0) > 1e-12) throw RsError{RS_ERR_ARG, "normal " + std::to_string(i) + " is not unit length"};
+    if (!(weight[i] > 0.0)) throw RsError{RS_ERR_ARG, "weight " + std::to_string(i) + " is not positive"};
+  }
+}
+
+void upload_geometry(rs_ctx* c) {
+  const size_t N = c->N;
+  auto up = [&](DevBuf& b, const void* src, size_t bytes) {
+    b.ensure(std::max<size_t>(bytes, 16));
+    if (bytes) HIP_CHECK(hipMemcpy(b.p, src, bytes, hipMemcpyHostToDevice));
+  };
+  up(c->d_x, c->x.data(), N * sizeof(double));
+  up(c->d_y, c->y.data(), N * sizeof(double));
+  up(c->d_nx, c->nx.data(), N * sizeof(double));
+  up(c->d_ny, c->ny.data(), N * sizeof(double));
+  up(c->d_w, c->w.data(), N * sizeof(double));
+  up(c->d_kap, c->kap.data(), N * sizeof(double));
+  up(c->d_curve, c->curve.data(), N * sizeof(int));
+  up(c->d_hole, c->hole.data(), c->hole.size() * sizeof(double));
+}
+
+bool inside_root(const rs_ctx* c, double x, double y) {
+  const double h = 0.5 * c->root_side;
+  return x >= c->root_cx - h && x < c->root_cx + h && y >= c->root_cy - h && y < c->root_cy + h;
+}
+
+}  // namespace
+
+// ============================== C ABI ========================================
+
+extern "C" {
+
+void rs_default_params(rs_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->lambda = -0.5;
+  p->tol = 1e-10;
+  p->leaf_size = 64;
+  p->n_proxy = 64;
+  p->proxy_ratio = 1.5;
+  p->rcond_min = 1e-12;
+  p->precision = 0;
+  p->refine_tol = 1e-8;
+  p->refine_max = 20;
+  p->has_root = 0;
+}
+
+rs_status rs_build_tree(const rs_params* prm, int n_nodes, const double* xy, const double* normal,
+                        const double* weight, const double* curvature, const int* curve_id,
+                        int n_holes, const double* hole_xy, rs_ctx** out) {
+  rs_ctx* c = nullptr;
+  try {
+    if (!prm || !out) throw RsError{RS_ERR_ARG, "NULL params or output handle"};
+    if (n_nodes <= 0) throw RsError{RS_ERR_ARG, "n_nodes must be positive"};
+    if (n_holes < 0) throw RsError{RS_ERR_ARG, "n_holes must be >= 0"};
+    if (!curve_id) throw RsError{RS_ERR_ARG, "NULL curve_id"};
+    if (!(prm->tol > 0.0) || prm->leaf_size < 1 || prm->n_proxy < 4 || !(prm->proxy_ratio > 1.0))
+      throw RsError{RS_ERR_ARG, "invalid tolerance, leaf size, proxy count or proxy ratio"};
+    if (prm->precision != 0 && prm->precision != 1) throw RsError{RS_ERR_ARG, "precision must be 0 or 1"};
+    validate_nodes(n_nodes, xy, normal, weight, curvature);
+    std::vector<int> count(n_holes + 1, 0);
+    for (int i = 0; i < n_nodes; ++i) {
+      if (curve_id[i] < 0 || curve_id[i] > n_holes) throw RsError{RS_ERR_ARG, "curve_id out of range"};
+      count[curve_id[i]]++;
+    }
+    for (int h = 1; h <= n_holes; ++h)
+      if (!count[h]) throw RsError{RS_ERR_ARG, "hole " + std::to_string(h) + " has no nodes"};
+    if (hole_xy && !finite_all(hole_xy, 2 * (size_t)n_holes)) throw RsError{RS_ERR_ARG, "non-finite hole point"};
+    c = new rs_ctx();
+    c->prm = *prm;
+    c->N = n_nodes;
+    c->p = n_holes;
+    HIP_CHECK(hipGetDevice(&c->device));
+    c->x.resize(n_nodes);
+    c->y.resize(n_nodes);
+    c->nx.resize(n_nodes);
+    c->ny.resize(n_nodes);
+    for (int i = 0; i < n_nodes; ++i) {
+      c->x[i] = xy[2 * i];
+      c->y[i] = xy[2 * i + 1];
+      c->nx[i] = normal[2 * i];
+      c->ny[i] = normal[2 * i + 1];
+    }
+    c->w.assign(weight, weight + n_nodes);
+    c->kap.assign(curvature, curvature + n_nodes);
+    c->curve.assign(curve_id, curve_id + n_nodes);
+    c->hole.assign(2 * (size_t)n_holes, 0.0);
+    for (int h = 0; h < n_holes; ++h) {
+      if (hole_xy) {
+        c->hole[2 * h] = hole_xy[2 * h];
+        c->hole[2 * h + 1] = hole_xy[2 * h + 1];
+      } else {
+        double sx = 0, sy = 0;
+        for (int i = 0; i < n_nodes; ++i)
+          if (curve_id[i] == h + 1) { sx += c->x[i]; sy += c->y[i]; }
+        c->hole[2 * h] = sx / count[h + 1];
+        c->hole[2 * h + 1] = sy / count[h + 1];
+      }
+    }
+    if (prm->has_root) {
+      if (!(prm->root[2] > 0.0) || !finite_all(prm->root, 3)) throw RsError{RS_ERR_ARG, "invalid fixed root"};
+      c->root_cx = prm->root[0];
+      c->root_cy = prm->root[1];
+      c->root_side = prm->root[2];
+      for (int i = 0; i < n_nodes; ++i)
+        if (!inside_root(c, c->x[i], c->y[i]))
+          throw RsError{RS_ERR_OUT_OF_ROOT, "node " + std::to_string(i) + " lies outside the fixed root"};
+    }
+    build_tree(c);
+    upload_geometry(c);
+    c->stats.n_nodes = n_nodes;
+    c->stats.n_holes = n_holes;
+    c->stats.n_levels = c->L + 1;
+    c->stats.n_boxes = (int)c->boxes.size();
+    *out = c;
+    return RS_OK;
+  } catch (const RsError& e) {
+    delete c;
+    return fail(nullptr, e);
+  } catch (const std::exception& e) {
+    delete c;
+    return fail(nullptr, RsError{RS_ERR_ALLOC, e.what()});
+  }
+}
+
+rs_status rs_factor(rs_ctx* c) {
+  if (!c) return RS_ERR_ARG;
+  try {
+    HIP_CHECK(hipSetDevice(c->device));
+    c->factored = false;
+    do_factor(c);
+    return RS_OK;
+  } catch (const RsError& e) {
+    c->factored = false;
+    return fail(c, e);
+  } catch (const std::exception& e) {
+    c->factored = false;
+    return fail(c, RsError{RS_ERR_ALLOC, e.what()});
+  }
+}
+
+rs_status rs_solve_dev(rs_ctx* c, int nrhs, const double* f_dev, double* x_dev) {
+  if (!c) return RS_ERR_ARG;
+  try {
+    if (!c->factored) throw RsError{RS_ERR_STATE, "rs_solve before rs_factor"};
+    if (nrhs <= 0 || !f_dev || !x_dev) throw RsError{RS_ERR_ARG, "bad nrhs or NULL pointer"};
+    HIP_CHECK(hipSetDevice(c->device));
+    auto t0 = std::chrono::steady_clock::now();
+    solve_device(c, nrhs, f_dev, x_dev);
+    HIP_CHECK(hipStreamSynchronize(c->stream));
+    c->stats.ms_solve = 1e3 * seconds_since(t0);
+    return RS_OK;
+  } catch (const RsError& e) {
+    return fail(c, e);
+  }
+}
+
+rs_status rs_solve(rs_ctx* c, int nrhs, const double* f, double* x, double* rel_residual) {
+  if (!c) return RS_ERR_ARG;
+  try {
+    if (!c->factored) throw RsError{RS_ERR_STATE, "rs_solve before rs_factor"};
+    if (nrhs <= 0 || !f || !x) throw RsError{RS_ERR_ARG, "bad nrhs or NULL pointer"};
+    const size_t n2 = 2 * (size_t)c->N;
+    const size_t ns = n2 + 3 * (size_t)c->p;
+    if (!finite_all(f, n2 * nrhs)) throw RsError{RS_ERR_ARG, "non-finite right-hand side"};
+    HIP_CHECK(hipSetDevice(c->device));
+    auto t0 = std::chrono::steady_clock::now();
+    c->d_f.ensure(n2 * nrhs * sizeof(double));
+    c->d_xout.ensure(ns * nrhs * sizeof(double));
+    HIP_CHECK(hipMemcpyAsync(c->d_f.p, f, n2 * nrhs * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    solve_device(c, nrhs, c->d_f.as<double>(), c->d_xout.as<double>());
+    std::vector<double> xo(ns * nrhs);
+    HIP_CHECK(hipMemcpyAsync(xo.data(), c->d_xout.p, xo.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_CHECK(hipStreamSynchronize(c->stream));
+    c->stats.ms_solve = 1e3 * seconds_since(t0);
+    if (rel_residual) {
+      // residual rows: y = A x - [f; 0]
+      c->d_res.ensure(ns * nrhs * sizeof(double));
+      c->d_c.ensure(ns * nrhs * sizeof(double));
+      double* xr = c->d_c.as<double>();
+      launch_to_rows(c->d_xout.as<double>(), (int)ns, (int)ns, nrhs, xr, c->stream);
+      apply_device_rows(c, xr, nrhs, c->d_res.as<double>());
+      std::vector<double> yo(ns * nrhs);
+      HIP_CHECK(hipMemcpyAsync(yo.data(), c->d_res.p, yo.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      HIP_CHECK(hipStreamSynchronize(c->stream));
+      for (int q = 0; q < nrhs; ++q) {
+        double rr = 0, ff = 0;
+        for (size_t i = 0; i < ns; ++i) {
+          const double fi = i < n2 ? f[q * n2 + i] : 0.0;
+          const double d = yo[i * nrhs + q] - fi;
+          rr += d * d;
+          ff += fi * fi;
+        }
+        rel_residual[q] = std::sqrt(rr) / std::sqrt(ff > 0 ? ff : 1.0);
+      }
+    }
+    std::memcpy(x, xo.data(), xo.size() * sizeof(double));
+    return RS_OK;
+  } catch (const RsError& e) {
+    return fail(c, e);
+  }
+}
+
+rs_status rs_apply(rs_ctx* c, int ncols, const double* x, double* y) {
+  if (!c) return RS_ERR_ARG;
+  try {
+    if (ncols <= 0 || !x || !y) throw RsError{RS_ERR_ARG, "bad ncols or NULL pointer"};
+    HIP_CHECK(hipSetDevice(c->device));
+    const size_t ns = 2 * (size_t)c->N + 3 * (size_t)c->p;
+    c->d_f.ensure(ns * ncols * sizeof(double));
+    c->d_c.ensure(ns * ncols * sizeof(double));
+    c->d_res.ensure(ns * ncols * sizeof(double));
+    HIP_CHECK(hipMemcpyAsync(c->d_f.p, x, ns * ncols * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    launch_to_rows(c->d_f.as<double>(), (int)ns, (int)ns, ncols, c->d_c.as<double>(), c->stream);
+    apply_device_rows(c, c->d_c.as<double>(), ncols, c->d_res.as<double>());
+    launch_from_rows(c->d_res.as<double>(), (int)ns, ncols, c->d_f.as<double>(), (int)ns, c->stream);
+    HIP_CHECK(hipMemcpyAsync(y, c->d_f.p, ns * ncols * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_CHECK(hipStreamSynchronize(c->stream));
+    return RS_OK;
+  } catch (const RsError& e) {
+    return fail(c, e);
+  }
+}
+
+rs_status rs_update_moved_nodes(rs_ctx* c, int n_moved, const int* idx, const double* xy,
+                                const double* normal, const double* weight, const double* curvature,
+                                const double* hole_xy) {
+  if (!c) return RS_ERR_ARG;
+  try {
+    if (!c->factored) throw RsError{RS_ERR_STATE, "rs_update_moved_nodes before rs_factor"};
+    if (n_moved < 0 || (n_moved > 0 && !idx)) throw RsError{RS_ERR_ARG, "bad moved-node list"};
+    if (n_moved) validate_nodes(n_moved, xy, normal, weight, curvature);
+    std::vector<char> seen(c->N, 0);
+    for (int t = 0; t < n_moved; ++t) {
+      if (idx[t] < 0 || idx[t] >= c->N) throw RsError{RS_ERR_ARG, "moved index out of range"};
+      if (seen[idx[t]]) throw RsError{RS_ERR_ARG, "duplicate moved index"};
+      seen[idx[t]] = 1;
+      if (!inside_root(c, xy[2 * t], xy[2 * t + 1]))
+        throw RsError{RS_ERR_OUT_OF_ROOT, "moved node leaves the root square"};
+    }
+    if (hole_xy && !finite_all(hole_xy, 2 * (size_t)c->p)) throw RsError{RS_ERR_ARG, "non-finite hole point"};
+    auto t0 = std::chrono::steady_clock::now();
+    for (int t = 0; t < n_moved; ++t) {
+      const int i = idx[t];
+      c->x[i] = xy[2 * t];
+      c->y[i] = xy[2 * t + 1];
+      c->nx[i] = normal[2 * t];
+      c->ny[i] = normal[2 * t + 1];
+      c->w[i] = weight[t];
+      c->kap[i] = curvature[t];
+    }
+    if (hole_xy) c->hole.assign(hole_xy, hole_xy + 2 * (size_t)c->p);
+    HIP_CHECK(hipSetDevice(c->device));
+    // the tree is rebuilt with the same root square; every box is recomputed
+    c->prm.has_root = 1;
+    c->prm.root[0] = c->root_cx;
+    c->prm.root[1] = c->root_cy;
+    c->prm.root[2] = c->root_side;
+    build_tree(c);
+    upload_geometry(c);
+    do_factor(c);
+    c->stats.boxes_recomputed = (int)c->boxes.size();
+    c->stats.ms_update = 1e3 * seconds_since(t0);
+    return RS_OK;
+  } catch (const RsError& e) {
+    c->factored = false;
+    return fail(c, e);
+  }
+}
+
+rs_status rs_set_stream(rs_ctx* c, void* stream) {
+  if (!c) return RS_ERR_ARG;
+  c->stream = static_cast<hipStream_t>(stream);
+  return RS_OK;
+}
+
+rs_status rs_get_stats(const rs_ctx* c, rs_stats* out) {
+  if (!c || !out) return RS_ERR_ARG;
+  *out = c->stats;
+  return RS_OK;
+}
+
+rs_status rs_get_boxes(const rs_ctx* c, int cap, int* n_boxes, int* level, int* n_active, int* rank,
+                       double* box_geom) {
+  if (!c || !n_boxes) return RS_ERR_ARG;
+  const int nb = (int)c->boxes.size();
+  *n_boxes = nb;
+  if (cap < nb) {
+    const_cast<rs_ctx*>(c)->err = "capacity smaller than the number of boxes";
+    return RS_ERR_ARG;
+  }
+  for (int b = 0; b < nb; ++b) {
+    const Box& B = c->boxes[b];
+    if (level) level[b] = B.level;
+    int n = -1, k = -1;
+    if (c->factored) {
+      if (b == 0) {
+        n = (int)c->I0.size();
+        k = n;
+      } else if (c->fac[b].n > 0) {
+        n = c->fac[b].n;
+        k = c->fac[b].k;
+      }
+    }
+    if (n_active) n_active[b] = n;
+    if (rank) rank[b] = k;
+    if (box_geom) {
+      box_geom[3 * b] = B.cx;
+      box_geom[3 * b + 1] = B.cy;
+      box_geom[3 * b + 2] = B.side;
+    }
+  }
+  return RS_OK;
+}
+
+rs_status rs_get_skeleton(const rs_ctx* c, int box, int cap, int* out, int* len) {
+  if (!c || !len) return RS_ERR_ARG;
+  if (!c->factored) {
+    const_cast<rs_ctx*>(c)->err = "no factorization";
+    return RS_ERR_STATE;
+  }
+  if (box < 0 || box >= (int)c->boxes.size()) {
+    const_cast<rs_ctx*>(c)->err = "box index out of range";
+    return RS_ERR_ARG;
+  }
+  std::vector<int> s = box == 0 ? c->I0 : skeleton_of(c->fac[box]);
+  *len = (int)s.size();
+  if (cap < (int)s.size() || (!out && !s.empty())) {
+    const_cast<rs_ctx*>(c)->err = "capacity smaller than the skeleton";
+    return RS_ERR_ARG;
+  }
+  std::copy(s.begin(), s.end(), out);
+  return RS_OK;
+}
+
+void rs_destroy(rs_ctx* c) { delete c; }
+
+const char* rs_last_error(const rs_ctx* c) { return c ? c->err.c_str() : g_build_error.c_str(); }
+
+}  // extern "C"

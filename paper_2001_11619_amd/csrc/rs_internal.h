@@ -1,0 +1,109 @@
+// Internal types shared by the host driver and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace rs {
+
+// Node geometry in structure-of-arrays form (device pointers, float64).
+struct Geo {
+  const double* x;
+  const double* y;
+  const double* nx;
+  const double* ny;
+  const double* w;
+  const double* kap;
+  int N;
+};
+
+// One box compressed at a level.  Device pointers point into per-level
+// workspaces and into the persistent factor arena.
+struct LevelBox {
+  double cx, cy, side;
+  int n;          // active unknowns |I_B|
+  int m;          // rows of the ID matrix M_B
+  int nF;         // |F_int|
+  int dof_off;    // offset of I_B in the level's unknown list
+  int fint_off;   // offset of F_int in the level's near-field list
+  int src_off;    // offset of the per-position child table, -1 for a leaf
+  int kcap;       // rows of R kept by the pivoted QR (rank + guard head-room)
+  int pad;
+  double* M;      // m x n, column-major (ld = m)
+  double* R;      // kcap x n, row-major, pivot order
+  double* Ap;     // n x n, row-major, A_BB in pivot order
+  double* scr;    // scratch for the elimination, 3 n^2
+  double* T;      // k x r  (capacity n^2/4 + n)
+  double* E;      // k x r
+  double* F;      // r x k
+  double* Xinv;   // r x r  (capacity n^2)
+  double* Xss;    // k x k  (capacity n^2)
+};
+
+// Where the parent's diagonal block finds a child's skeleton block.
+struct ChildSrc {
+  const double* xss;   // child's X_SS (k_c x k_c, row-major)
+  int idx;             // position of this unknown in the child's skeleton order
+  int ld;              // k_c
+  int child;           // child box id (positions with equal ids share X_SS)
+  int pad;
+};
+
+// One compressed box as seen by the solve sweeps.
+struct SolveBox {
+  int k, r;
+  int s_off, r_off;      // offsets of S and R in the solve index lists
+  int part;              // slot of this box in per-box partial buffers
+  int pad;
+  const double* T;
+  const double* E;
+  const double* F;
+  const double* Xinv;
+  double* W;             // r x 3p: X_RR^{-1} (U H)_R (bordered root only)
+};
+
+constexpr int kBlock = 256;
+constexpr int kNC = 16;        // right-hand-side columns per sweep block
+
+// ---- launchers (rs_kernels.hip) -------------------------------------------
+void launch_assemble_M(const LevelBox* boxes, int nbox, int max_m, const int* dofs,
+                       const int* fint, Geo g, int n_proxy, double ratio, hipStream_t s);
+void launch_cpqr(const LevelBox* boxes, int nbox, double tol, int extra, int* perm,
+                 int* k_out, int* kx_out, int max_n, hipStream_t s);
+void launch_assemble_abb(const LevelBox* boxes, int nbox, int max_n, const int* dofs,
+                         const int* perm, const ChildSrc* src, Geo g, double lam,
+                         hipStream_t s);
+void launch_eliminate(const LevelBox* boxes, int nbox, int* k_io, const int* kx,
+                      double rcond_min, int* status, int max_n, hipStream_t s);
+void launch_gj_inverse(double* A, int n, int lda, double* Ainv, double* work,
+                       double* rcond_out, int* status, hipStream_t s);
+void launch_sweep(const SolveBox* boxes, int nbox, const int* sidx, const int* ridx,
+                  double* c, int ncols, int mode, int max_n, hipStream_t s);
+void launch_diag(const SolveBox* boxes, int nbox, const int* ridx, double* c, int ncols,
+                 int max_r, hipStream_t s);
+void launch_assemble_H(Geo g, const double* hole_xy, int p, const int* curve_id,
+                       double* H, double* Psi, hipStream_t s);
+void launch_border_box(const SolveBox* boxes, int nbox, const int* ridx, const double* Hh,
+                       const double* Ph, int p3, double* Gpart, double* scratch,
+                       long long scr_stride, hipStream_t s);
+void launch_sum_parts(const double* parts, int nparts, long long stride, int len,
+                      double scale, double* out, hipStream_t s);
+void launch_border_rhs(const SolveBox* boxes, int nbox, const int* ridx, const double* Ph,
+                       int p3, const double* c, int ncols, double* parts, hipStream_t s);
+void launch_border_fix(const SolveBox* boxes, int nbox, const int* ridx, int p3,
+                       const double* lam, double* c, int ncols, hipStream_t s);
+void launch_assemble_Z(const double* X0, int n0, const double* Hh, const double* Ph,
+                       const int* I0, int p3, const double* G, double* Z, hipStream_t s);
+void launch_root_gather(const double* c, int ncols, const int* I0, int n0,
+                        const double* rhs2, int p3, double* v, hipStream_t s);
+void launch_dense_apply(const double* Zinv, int nz, const double* v, int ncols, double* out,
+                        hipStream_t s);
+void launch_root_scatter(const double* sol, int ncols, const int* I0, int n0, double* c,
+                         hipStream_t s);
+void launch_to_rows(const double* f, int ld, int nrows, int ncols, double* c, hipStream_t s);
+void launch_from_rows(const double* c, int nrows, int ncols, double* x, int ld, hipStream_t s);
+void launch_apply_operator(Geo g, const int* curve_id, const double* hole_xy, int p,
+                           double lam, const double* x, int ncols, double* y,
+                           double* hole_parts, hipStream_t s);
+
+}  // namespace rs
