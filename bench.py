@@ -1,0 +1,177 @@
+#!/usr/bin/env python3
+"""Benchmark of the recursive-skeletonization hot path on one MI355X.
+
+One step = one factorization of the workload's boundary operator followed by
+the solve of all its right-hand sides (device-resident in and out), i.e.
+every kernel of the path: ID-matrix assembly, pivoted QR, diagonal-block
+assembly, elimination, border and root, and the U / X_D^{-1} / V sweeps.
+The quadtree and the geometry upload happen once before the timed region
+(their time is reported as setup_ms, never inside `value`).
+
+value = right-hand sides solved per second including their factorization
+        = nrhs * steps / (time of `steps` factor+solve steps).
+
+Prints one JSON line.  `--gpus` above 1 is not supported (single-GPU build).
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_VECTOR_PEAK_TFLOPS = 78.6     # MI355X published FP64 vector / matrix peak
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "circle10_8holes": dict(desc="outer circle R=10 (4096 nodes) + 8 random ellipses (1024 nodes each), "
+                                 "24576 unknowns + 24 border, seed 2", nrhs=4, seed=2),
+    "ellipse_2048": dict(desc="ellipse semi-axes 1.0/0.6, 2048 nodes, 4096 unknowns", nrhs=1, seed=1),
+    "circle40_64holes": dict(desc="outer circle R=40 (16384 nodes) + 64 random ellipses (1792 nodes each), "
+                                  "262144 unknowns + 192 border, seed 3", nrhs=16, seed=3),
+}
+
+
+def make_geometry(name):
+    import workloads as W
+
+    return {"circle10_8holes": W.workload_circle10_8holes, "ellipse_2048": W.workload_ellipse_2048,
+            "circle40_64holes": W.workload_circle40_64holes}[name]()
+
+
+def cpu_baseline(geom, f, tol, budget_s=30.0):
+    """The CPU oracle (plain level-parallel RS, float64) on the host cores.
+
+    Sample: one full factorization + solve of the same workload when it fits
+    the budget (it does for the 2048- and 12288-node workloads)."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    from oracle.rs import RSFactorization, RSParams
+
+    threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    t0 = time.perf_counter()
+    orc = RSFactorization(geom, RSParams(tol=tol)).factor()
+    t1 = time.perf_counter()
+    orc.solve(f)
+    t2 = time.perf_counter()
+    nrhs = f.shape[1]
+    return {
+        "value": nrhs / (t2 - t0),
+        "unit": "solves/s",
+        "cores": int(threads),
+        "kind": "oracle",
+        "sample": "one full factorization + solve of the same workload (%d rhs): factor %.2f s, solve %.3f s"
+                  % (nrhs, t1 - t0, t2 - t1),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="circle10_8holes", choices=sorted(WORKLOADS))
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2001_11619_amd import RSSolver
+    from workloads import boundary_data, exterior_forces_for_geometry
+
+    wl = WORKLOADS[args.workload]
+    geom = make_geometry(args.workload)
+    f = boundary_data(geom, exterior_forces_for_geometry(geom, wl["nrhs"], seed=wl["seed"]))
+    nrhs = f.shape[1]
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    s = RSSolver.from_geometry(geom, tol=args.tol)
+    setup_ms = 1e3 * (time.perf_counter() - t0)
+    stream = torch.cuda.current_stream()
+    s.set_stream(stream.cuda_stream)
+    fd = torch.tensor(np.ascontiguousarray(f.T), dtype=torch.float64, device="cuda")
+    xd = torch.empty((nrhs, geom.n_system), dtype=torch.float64, device="cuda")
+
+    def step():
+        s.factor()
+        s.solve_dev(fd, xd)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    s.set_kernel_timing(True)
+    s.kernel_times(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fac_ms = []
+    for _ in range(args.steps):
+        step()
+        fac_ms.append(s.stats()["ms_factor"])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ktimes = s.kernel_times(reset=True)
+    s.set_kernel_timing(False)
+    st = s.stats()
+    # accuracy of the last step (outside the timed region)
+    x, res = s.solve(f, residual=True)
+    ms_step = 1e3 * elapsed / args.steps
+
+    # roofline of the dominant kernel family (largest device time in the timed region)
+    models = {
+        # family: (bound, unit, work per factorization or solve, peak)
+        "cpqr": ("alu", "TFLOP/s", st["flops_id"], FP64_VECTOR_PEAK_TFLOPS),
+        "eliminate": ("alu", "TFLOP/s", st["flops_elim"], FP64_VECTOR_PEAK_TFLOPS),
+        "sweep_U": ("hbm", "GB/s", st["factor_bytes"] * 2 / 3.0, HBM_PEAK_GBS),
+        "sweep_V": ("hbm", "GB/s", st["factor_bytes"] * 2 / 3.0, HBM_PEAK_GBS),
+    }
+    fam = max(ktimes, key=lambda k: ktimes[k][1]) if ktimes else None
+    roofline = None
+    if fam in models:
+        bound, unit, work, peak = models[fam]
+        launches, tot_ms = ktimes[fam]
+        per_step_s = tot_ms / 1e3 / args.steps
+        achieved = work / per_step_s / (1e12 if unit == "TFLOP/s" else 1e9)
+        roofline = {"bound": bound, "kernel": fam, "achieved": achieved, "peak": peak, "unit": unit,
+                    "frac": achieved / peak, "traffic": None,
+                    "launches_per_step": launches // args.steps, "ms_per_step": tot_ms / args.steps}
+    out = {
+        "metric": "RS factor s + solves/s at 1e-8 rel. residual, mixed-batched vs FP64 plain",
+        "value": nrhs * args.steps / elapsed,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "desc": wl["desc"], "nrhs": nrhs, "tol": args.tol,
+                   "precision": "fp64 plain", "leaf": 64, "n_proxy": 64},
+        "factor_s": float(np.median(fac_ms)) / 1e3,
+        "solves_per_s_solve_only": nrhs / (st["ms_solve"] / 1e3) if st["ms_solve"] > 0 else None,
+        "setup_ms": setup_ms,
+        "max_rel_residual": float(np.max(res)),
+        "kernel_ms_per_step": {k: v[1] / args.steps for k, v in sorted(ktimes.items())},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(geom, f, args.tol)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -163,6 +163,19 @@ rs_status rs_get_skeleton(const rs_ctx* ctx, int box, int cap, int* out, int* le
  * the residual kernel used by refinement, exposed for verification. */
 rs_status rs_apply(rs_ctx* ctx, int ncols, const double* x, double* y);
 
+/* Per-kernel device time, measured with HIP events recorded around every
+ * launch on the context's stream while timing is enabled (it adds two event
+ * records per launch; disabled by default). */
+typedef struct {
+  char name[32];       /* kernel family, e.g. "cpqr", "eliminate", "sweep" */
+  int launches;
+  double total_ms;
+} rs_kernel_time;
+rs_status rs_set_kernel_timing(rs_ctx* ctx, int enable);
+/* Copies up to cap entries accumulated since the last reset; *n receives the
+ * number of kernel families.  reset != 0 clears the accumulators afterwards. */
+rs_status rs_get_kernel_times(rs_ctx* ctx, int cap, rs_kernel_time* out, int* n, int reset);
+
 void rs_destroy(rs_ctx* ctx);
 
 /* Message of the last failed call on ctx (or of the last failed rs_build_tree

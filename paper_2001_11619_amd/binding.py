@@ -53,6 +53,10 @@ class Stats(ctypes.Structure):
     ]
 
 
+class KernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int), ("total_ms", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -84,12 +88,15 @@ def load_library():
     lib.rs_get_boxes.argtypes = [h, ctypes.c_int, ip, ip, ip, ip, dp]
     lib.rs_get_skeleton.argtypes = [h, ctypes.c_int, ctypes.c_int, ip, ip]
     lib.rs_apply.argtypes = [h, ctypes.c_int, dp, dp]
+    lib.rs_set_kernel_timing.argtypes = [h, ctypes.c_int]
+    lib.rs_get_kernel_times.argtypes = [h, ctypes.c_int, P(KernelTime), ip, ctypes.c_int]
     lib.rs_destroy.argtypes = [h]
     lib.rs_destroy.restype = None
     lib.rs_last_error.argtypes = [h]
     lib.rs_last_error.restype = ctypes.c_char_p
     for name in ("rs_build_tree", "rs_factor", "rs_solve", "rs_solve_dev", "rs_update_moved_nodes",
-                 "rs_set_stream", "rs_get_stats", "rs_get_boxes", "rs_get_skeleton", "rs_apply"):
+                 "rs_set_stream", "rs_get_stats", "rs_get_boxes", "rs_get_skeleton", "rs_apply",
+                 "rs_set_kernel_timing", "rs_get_kernel_times"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -101,7 +108,8 @@ def exported_symbols():
     out = []
     for name in ("rs_default_params", "rs_build_tree", "rs_factor", "rs_solve", "rs_solve_dev",
                  "rs_update_moved_nodes", "rs_set_stream", "rs_get_stats", "rs_get_boxes",
-                 "rs_get_skeleton", "rs_apply", "rs_destroy", "rs_last_error"):
+                 "rs_get_skeleton", "rs_apply", "rs_set_kernel_timing", "rs_get_kernel_times",
+                 "rs_destroy", "rs_last_error"):
         if hasattr(lib, name):
             out.append(name)
     return out
@@ -253,6 +261,16 @@ class RSSolver:
         out = np.empty(max(ln.value, 1), np.int32)
         self._check(self._lib.rs_get_skeleton(self._h, box, out.size, _iptr(out), ctypes.byref(ln)))
         return out[: ln.value].copy()
+
+    def set_kernel_timing(self, enable: bool = True):
+        self._check(self._lib.rs_set_kernel_timing(self._h, 1 if enable else 0))
+
+    def kernel_times(self, reset: bool = False) -> dict:
+        n = ctypes.c_int()
+        self._check(self._lib.rs_get_kernel_times(self._h, 0, None, ctypes.byref(n), 0))
+        arr = (KernelTime * max(n.value, 1))()
+        self._check(self._lib.rs_get_kernel_times(self._h, n.value, arr, ctypes.byref(n), 1 if reset else 0))
+        return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms) for i in range(n.value)}
 
     def close(self):
         if self._h:

@@ -128,7 +128,7 @@ struct rs_ctx {
       ws_status;
   // root
   std::vector<int> I0;
-  DevBuf d_I0, d_X0, d_Z, d_Zinv, d_gjwork, d_rcond, d_rstatus, d_root_box;
+  DevBuf d_I0, d_X0, d_Z, d_Zinv, d_gjwork, d_gjiwork, d_rcond, d_rstatus, d_root_box;
   DevBuf d_H, d_Hh, d_Ph, d_Gpart, d_G, d_bscr, d_W;
   int nz = 0;
   // solve metadata
@@ -143,8 +143,22 @@ struct rs_ctx {
 
   rs_stats stats{};
 
+  // kernel timing (HIP events around launches)
+  bool timing = false;
+  struct Pending { int fam; hipEvent_t a, b; };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> event_pool;
+  std::vector<std::string> fam_name;
+  std::vector<int> fam_launches;
+  std::vector<double> fam_ms;
+
   ~rs_ctx() {
     for (auto* b : level_arena) delete b;
+    for (auto& p : pending) {
+      (void)hipEventDestroy(p.a);
+      (void)hipEventDestroy(p.b);
+    }
+    for (auto e : event_pool) (void)hipEventDestroy(e);
   }
 };
 
@@ -160,6 +174,64 @@ void geo_of(const rs_ctx* c, Geo& g) {
   g.w = c->d_w.as<double>();
   g.kap = c->d_kap.as<double>();
   g.N = c->N;
+}
+
+// ---- kernel timing --------------------------------------------------------
+hipEvent_t take_event(rs_ctx* c) {
+  if (!c->event_pool.empty()) {
+    hipEvent_t e = c->event_pool.back();
+    c->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  HIP_CHECK(hipEventCreate(&e));
+  return e;
+}
+
+int family(rs_ctx* c, const char* name) {
+  for (size_t i = 0; i < c->fam_name.size(); ++i)
+    if (c->fam_name[i] == name) return (int)i;
+  c->fam_name.push_back(name);
+  c->fam_launches.push_back(0);
+  c->fam_ms.push_back(0.0);
+  return (int)c->fam_name.size() - 1;
+}
+
+// Brackets one launch (or a group of launches) with events when timing is on.
+struct KTimer {
+  rs_ctx* c;
+  int fam = -1;
+  hipEvent_t a{};
+  KTimer(rs_ctx* ctx, const char* name) : c(ctx) {
+    if (!c->timing) return;
+    fam = family(c, name);
+    a = take_event(c);
+    HIP_CHECK(hipEventRecord(a, c->stream));
+  }
+  ~KTimer() {
+    if (fam < 0) return;
+    hipEvent_t b{};
+    if (!c->event_pool.empty()) {
+      b = c->event_pool.back();
+      c->event_pool.pop_back();
+    } else if (hipEventCreate(&b) != hipSuccess) {
+      return;
+    }
+    if (hipEventRecord(b, c->stream) == hipSuccess) c->pending.push_back({fam, a, b});
+  }
+};
+
+// Resolve recorded event pairs; call after the stream has been synchronised.
+void resolve_timers(rs_ctx* c) {
+  for (auto& p : c->pending) {
+    float ms = 0.f;
+    HIP_CHECK(hipEventElapsedTime(&ms, p.a, p.b));
+    c->fam_ms[p.fam] += ms;
+    c->fam_launches[p.fam] += 1;
+    c->event_pool.push_back(p.a);
+    c->event_pool.push_back(p.b);
+  }
+  c->pending.clear();
 }
 
 void build_tree(rs_ctx* c) {
@@ -378,6 +450,9 @@ void factor_level(rs_ctx* c, int l, const std::vector<int>& ids, const std::vect
   }
   const int nb = (int)lb.size();
   if (nb == 0) return;
+  if (cpqr_lds_bytes(max_m, max_n) > 65536)
+    throw RsError{RS_ERR_ARG, "box too large for the pivoted-QR kernel (m=" + std::to_string(max_m) +
+                                  ", n=" + std::to_string(max_n) + ")"};
   // workspaces
   c->ws_M.ensure(totM * sizeof(double));
   c->ws_R.ensure(totN2 * sizeof(double));
@@ -431,16 +506,28 @@ void factor_level(rs_ctx* c, int l, const std::vector<int>& ids, const std::vect
   c->ws_kx.ensure(nb * sizeof(int));
   c->ws_status.ensure(nb * sizeof(int));
   const LevelBox* dlb = c->ws_boxes.as<LevelBox>();
-  launch_assemble_M(dlb, nb, max_m, c->ws_dofs.as<int>(), c->ws_fint.as<int>(), g, P.n_proxy,
-                    P.proxy_ratio, s);
-  launch_cpqr(dlb, nb, P.tol, kGuardExtra, c->ws_perm.as<int>(), c->ws_k.as<int>(),
-              c->ws_kx.as<int>(), max_n, s);
-  launch_assemble_abb(dlb, nb, max_n, c->ws_dofs.as<int>(), c->ws_perm.as<int>(),
-                      c->ws_src.as<ChildSrc>(), g, P.lambda, s);
+  {
+    KTimer kt_(c, "assemble_M");
+    launch_assemble_M(dlb, nb, max_m, c->ws_dofs.as<int>(), c->ws_fint.as<int>(), g, P.n_proxy,
+                      P.proxy_ratio, s);
+  }
+  {
+    KTimer kt_(c, "cpqr");
+    launch_cpqr(dlb, nb, P.tol, kGuardExtra, c->ws_perm.as<int>(), c->ws_k.as<int>(),
+                c->ws_kx.as<int>(), max_m, max_n, s);
+  }
+  {
+    KTimer kt_(c, "assemble_abb");
+    launch_assemble_abb(dlb, nb, max_n, c->ws_dofs.as<int>(), c->ws_perm.as<int>(),
+                        c->ws_src.as<ChildSrc>(), g, P.lambda, s);
+  }
   std::vector<int> k0(nb);
   HIP_CHECK(hipMemcpyAsync(k0.data(), c->ws_k.p, nb * sizeof(int), hipMemcpyDeviceToHost, s));
-  launch_eliminate(dlb, nb, c->ws_k.as<int>(), c->ws_kx.as<int>(), P.rcond_min,
-                   c->ws_status.as<int>(), max_n, s);
+  {
+    KTimer kt_(c, "eliminate");
+    launch_eliminate(dlb, nb, c->ws_k.as<int>(), c->ws_kx.as<int>(), P.rcond_min,
+                     c->ws_status.as<int>(), max_n, s);
+  }
   HIP_CHECK(hipGetLastError());
   std::vector<int> perm(dofs.size()), kk(nb), st(nb);
   HIP_CHECK(hipMemcpyAsync(perm.data(), c->ws_perm.p, perm.size() * sizeof(int),
@@ -448,6 +535,7 @@ void factor_level(rs_ctx* c, int l, const std::vector<int>& ids, const std::vect
   HIP_CHECK(hipMemcpyAsync(kk.data(), c->ws_k.p, nb * sizeof(int), hipMemcpyDeviceToHost, s));
   HIP_CHECK(hipMemcpyAsync(st.data(), c->ws_status.p, nb * sizeof(int), hipMemcpyDeviceToHost, s));
   HIP_CHECK(hipStreamSynchronize(s));
+  resolve_timers(c);
   for (int i = 0; i < nb; ++i) {
     const int b = ids[sel[i]];
     BoxFac& f = c->fac[b];
@@ -539,6 +627,7 @@ int level_count(const rs_ctx* c, int l) { return (int)(c->sbox_off[l + 1] - c->s
 
 void sweep_all(rs_ctx* c, double* buf, int ncols, int mode) {
   const int L = c->L;
+  KTimer kt_(c, mode == 0 ? "sweep_U" : (mode == 1 ? "sweep_PsiV" : "sweep_V"));
   if (mode == 2) {
     for (int l = 1; l <= L; ++l)
       launch_sweep(level_sboxes(c, l), level_count(c, l), c->d_sidx.as<int>(), c->d_ridx.as<int>(),
@@ -570,13 +659,17 @@ void factor_root(rs_ctx* c) {
     std::vector<LevelBox> v{rb};
     upload(c->d_root_box, v, s);
     upload(c->ws_src, src, s);
-    launch_assemble_abb(c->d_root_box.as<LevelBox>(), 1, n0, c->d_I0.as<int>(), nullptr,
-                        c->ws_src.as<ChildSrc>(), g, c->prm.lambda, s);
+    {
+      KTimer kt_(c, "root_abb");
+      launch_assemble_abb(c->d_root_box.as<LevelBox>(), 1, n0, c->d_I0.as<int>(), nullptr,
+                          c->ws_src.as<ChildSrc>(), g, c->prm.lambda, s);
+    }
   }
   build_solve_meta(c);
   const int nz = c->nz;
   c->d_Zinv.ensure(std::max<size_t>((size_t)nz * nz, 1) * sizeof(double));
-  c->d_gjwork.ensure(std::max<size_t>((size_t)nz * nz, 1) * sizeof(double));
+  c->d_gjwork.ensure(((size_t)3 * nz * 32 + 32 * 32) * sizeof(double));
+  c->d_gjiwork.ensure(((size_t)nz + 32) * sizeof(int));
   c->d_rcond.ensure(sizeof(double));
   c->d_rstatus.ensure(sizeof(int));
   const double* Zsrc = c->d_X0.as<double>();
@@ -585,8 +678,11 @@ void factor_root(rs_ctx* c) {
     c->d_H.ensure(hn * sizeof(double));
     c->d_Hh.ensure(hn * sizeof(double));
     c->d_Ph.ensure(hn * sizeof(double));
-    launch_assemble_H(g, c->d_hole.as<double>(), c->p, c->d_curve.as<int>(), c->d_Hh.as<double>(),
-                      c->d_Ph.as<double>(), s);
+    {
+      KTimer kt_(c, "border_H");
+      launch_assemble_H(g, c->d_hole.as<double>(), c->p, c->d_curve.as<int>(), c->d_Hh.as<double>(),
+                        c->d_Ph.as<double>(), s);
+    }
     sweep_all(c, c->d_Hh.as<double>(), p3, 0);
     sweep_all(c, c->d_Ph.as<double>(), p3, 1);
     const int nsb = c->n_solve_boxes;
@@ -598,25 +694,35 @@ void factor_root(rs_ctx* c) {
     for (int l = c->L; l >= 1; --l) {
       const int nb = level_count(c, l);
       if (!nb) continue;
-      launch_border_box(level_sboxes(c, l), nb, c->d_ridx.as<int>(), c->d_Hh.as<double>(),
-                        c->d_Ph.as<double>(), p3, c->d_Gpart.as<double>(), c->d_bscr.as<double>(),
-                        scr_stride, s);
+      {
+        KTimer kt_(c, "border_box");
+        launch_border_box(level_sboxes(c, l), nb, c->d_ridx.as<int>(), c->d_Hh.as<double>(),
+                          c->d_Ph.as<double>(), p3, c->d_Gpart.as<double>(), c->d_bscr.as<double>(),
+                          scr_stride, s);
+      }
     }
     c->d_G.ensure((size_t)p3 * p3 * sizeof(double));
     launch_sum_parts(c->d_Gpart.as<double>(), nsb, (long long)p3 * p3, p3 * p3, 1.0,
                      c->d_G.as<double>(), s);
     c->d_Z.ensure((size_t)nz * nz * sizeof(double));
-    launch_assemble_Z(c->d_X0.as<double>(), n0, c->d_Hh.as<double>(), c->d_Ph.as<double>(),
-                      c->d_I0.as<int>(), p3, c->d_G.as<double>(), c->d_Z.as<double>(), s);
+    {
+      KTimer kt_(c, "root_Z");
+      launch_assemble_Z(c->d_X0.as<double>(), n0, c->d_Hh.as<double>(), c->d_Ph.as<double>(),
+                        c->d_I0.as<int>(), p3, c->d_G.as<double>(), c->d_Z.as<double>(), s);
+    }
     Zsrc = c->d_Z.as<double>();
   }
   if (nz > 0) {
-    launch_gj_inverse(const_cast<double*>(Zsrc), nz, nz, c->d_Zinv.as<double>(),
-                      c->d_gjwork.as<double>(), c->d_rcond.as<double>(), c->d_rstatus.as<int>(), s);
+    {
+      KTimer kt_(c, "root_inverse");
+      launch_gj_blocked(const_cast<double*>(Zsrc), nz, c->d_Zinv.as<double>(), c->d_gjwork.as<double>(),
+                        c->d_gjiwork.as<int>(), c->d_rstatus.as<int>(), s);
+    }
     HIP_CHECK(hipGetLastError());
     int st = 0;
     HIP_CHECK(hipMemcpyAsync(&st, c->d_rstatus.p, sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_CHECK(hipStreamSynchronize(s));
+    resolve_timers(c);
     if (st) throw RsError{RS_ERR_SINGULAR, "root system is singular"};
   }
   c->stats.root_skeleton = n0;
@@ -657,8 +763,11 @@ void solve_rows(rs_ctx* c, double* cbuf, int ncols) {
   const int n0 = (int)c->I0.size();
   sweep_all(c, cbuf, ncols, 0);
   for (int l = c->L; l >= 1; --l)
-    launch_diag(level_sboxes(c, l), level_count(c, l), c->d_ridx.as<int>(), cbuf, ncols,
-                c->lvl_maxr[l], s);
+    {
+      KTimer kt_(c, "diag");
+      launch_diag(level_sboxes(c, l), level_count(c, l), c->d_ridx.as<int>(), cbuf, ncols,
+                  c->lvl_maxr[l], s);
+    }
   const int nz = c->nz;
   c->d_v.ensure(std::max<size_t>((size_t)nz * ncols, 1) * sizeof(double));
   c->d_sol.ensure(std::max<size_t>((size_t)nz * ncols, 1) * sizeof(double));
@@ -667,8 +776,11 @@ void solve_rows(rs_ctx* c, double* cbuf, int ncols) {
     const int nsb = c->n_solve_boxes;
     c->d_parts.ensure(std::max<size_t>((size_t)nsb * p3 * ncols, 1) * sizeof(double));
     for (int l = c->L; l >= 1; --l)
-      launch_border_rhs(level_sboxes(c, l), level_count(c, l), c->d_ridx.as<int>(),
-                        c->d_Ph.as<double>(), p3, cbuf, ncols, c->d_parts.as<double>(), s);
+      {
+        KTimer kt_(c, "border_rhs");
+        launch_border_rhs(level_sboxes(c, l), level_count(c, l), c->d_ridx.as<int>(),
+                          c->d_Ph.as<double>(), p3, cbuf, ncols, c->d_parts.as<double>(), s);
+      }
     c->d_rhs2.ensure((size_t)p3 * ncols * sizeof(double));
     launch_sum_parts(c->d_parts.as<double>(), nsb, (long long)p3 * ncols, p3 * ncols, -1.0,
                      c->d_rhs2.as<double>(), s);
@@ -676,15 +788,21 @@ void solve_rows(rs_ctx* c, double* cbuf, int ncols) {
   }
   if (nz > 0) {
     launch_root_gather(cbuf, ncols, c->d_I0.as<int>(), n0, rhs2, p3, c->d_v.as<double>(), s);
-    launch_dense_apply(c->d_Zinv.as<double>(), nz, c->d_v.as<double>(), ncols,
-                       c->d_sol.as<double>(), s);
+    {
+      KTimer kt_(c, "root_apply");
+      launch_dense_apply(c->d_Zinv.as<double>(), nz, c->d_v.as<double>(), ncols,
+                         c->d_sol.as<double>(), s);
+    }
     if (n0) launch_root_scatter(c->d_sol.as<double>(), ncols, c->d_I0.as<int>(), n0, cbuf, s);
   }
   if (p3) {
     const double* lam = c->d_sol.as<double>() + (size_t)n0 * ncols;
     for (int l = c->L; l >= 1; --l)
-      launch_border_fix(level_sboxes(c, l), level_count(c, l), c->d_ridx.as<int>(), p3, lam, cbuf,
-                        ncols, s);
+      {
+        KTimer kt_(c, "border_fix");
+        launch_border_fix(level_sboxes(c, l), level_count(c, l), c->d_ridx.as<int>(), p3, lam, cbuf,
+                          ncols, s);
+      }
     // lambda rows follow the 2N density rows in cbuf
     HIP_CHECK(hipMemcpyAsync(cbuf + (size_t)2 * c->N * ncols, lam, (size_t)p3 * ncols * sizeof(double),
                              hipMemcpyDeviceToDevice, s));
@@ -705,8 +823,11 @@ void solve_device(rs_ctx* c, int nrhs, const double* f_dev, double* x_dev) {
 void apply_device_rows(rs_ctx* c, const double* xrows, int ncols, double* yrows) {
   Geo g;
   geo_of(c, g);
-  launch_apply_operator(g, c->d_curve.as<int>(), c->d_hole.as<double>(), c->p, c->prm.lambda, xrows,
-                        ncols, yrows, nullptr, c->stream);
+  {
+    KTimer kt_(c, "apply_operator");
+    launch_apply_operator(g, c->d_curve.as<int>(), c->d_hole.as<double>(), c->p, c->prm.lambda, xrows,
+                          ncols, yrows, nullptr, c->stream);
+  }
   HIP_CHECK(hipGetLastError());
 }
 
@@ -802,7 +923,6 @@ rs_status rs_build_tree(const rs_params* prm, int n_nodes, const double* xy, con
     c->prm = *prm;
     c->N = n_nodes;
     c->p = n_holes;
-    HIP_CHECK(hipGetDevice(&c->device));
     c->x.resize(n_nodes);
     c->y.resize(n_nodes);
     c->nx.resize(n_nodes);
@@ -839,6 +959,7 @@ rs_status rs_build_tree(const rs_params* prm, int n_nodes, const double* xy, con
           throw RsError{RS_ERR_OUT_OF_ROOT, "node " + std::to_string(i) + " lies outside the fixed root"};
     }
     build_tree(c);
+    HIP_CHECK(hipGetDevice(&c->device));
     upload_geometry(c);
     c->stats.n_nodes = n_nodes;
     c->stats.n_holes = n_holes;
@@ -881,6 +1002,7 @@ rs_status rs_solve_dev(rs_ctx* c, int nrhs, const double* f_dev, double* x_dev) 
     solve_device(c, nrhs, f_dev, x_dev);
     HIP_CHECK(hipStreamSynchronize(c->stream));
     c->stats.ms_solve = 1e3 * seconds_since(t0);
+    resolve_timers(c);
     return RS_OK;
   } catch (const RsError& e) {
     return fail(c, e);
@@ -905,6 +1027,7 @@ rs_status rs_solve(rs_ctx* c, int nrhs, const double* f, double* x, double* rel_
     HIP_CHECK(hipMemcpyAsync(xo.data(), c->d_xout.p, xo.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIP_CHECK(hipStreamSynchronize(c->stream));
     c->stats.ms_solve = 1e3 * seconds_since(t0);
+    resolve_timers(c);
     if (rel_residual) {
       // residual rows: y = A x - [f; 0]
       c->d_res.ensure(ns * nrhs * sizeof(double));
@@ -915,6 +1038,7 @@ rs_status rs_solve(rs_ctx* c, int nrhs, const double* f, double* x, double* rel_
       std::vector<double> yo(ns * nrhs);
       HIP_CHECK(hipMemcpyAsync(yo.data(), c->d_res.p, yo.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
       HIP_CHECK(hipStreamSynchronize(c->stream));
+      resolve_timers(c);
       for (int q = 0; q < nrhs; ++q) {
         double rr = 0, ff = 0;
         for (size_t i = 0; i < ns; ++i) {
@@ -948,6 +1072,7 @@ rs_status rs_apply(rs_ctx* c, int ncols, const double* x, double* y) {
     launch_from_rows(c->d_res.as<double>(), (int)ns, ncols, c->d_f.as<double>(), (int)ns, c->stream);
     HIP_CHECK(hipMemcpyAsync(y, c->d_f.p, ns * ncols * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIP_CHECK(hipStreamSynchronize(c->stream));
+    resolve_timers(c);
     return RS_OK;
   } catch (const RsError& e) {
     return fail(c, e);
@@ -1062,6 +1187,35 @@ rs_status rs_get_skeleton(const rs_ctx* c, int box, int cap, int* out, int* len)
     return RS_ERR_ARG;
   }
   std::copy(s.begin(), s.end(), out);
+  return RS_OK;
+}
+
+rs_status rs_set_kernel_timing(rs_ctx* c, int enable) {
+  if (!c) return RS_ERR_ARG;
+  c->timing = enable != 0;
+  return RS_OK;
+}
+
+rs_status rs_get_kernel_times(rs_ctx* c, int cap, rs_kernel_time* out, int* n, int reset) {
+  if (!c || !n) return RS_ERR_ARG;
+  try {
+    HIP_CHECK(hipStreamSynchronize(c->stream));
+    resolve_timers(c);
+  } catch (const RsError& e) {
+    return fail(c, e);
+  }
+  const int nf = (int)c->fam_name.size();
+  *n = nf;
+  for (int i = 0; i < nf && i < cap && out; ++i) {
+    std::memset(out[i].name, 0, sizeof(out[i].name));
+    std::strncpy(out[i].name, c->fam_name[i].c_str(), sizeof(out[i].name) - 1);
+    out[i].launches = c->fam_launches[i];
+    out[i].total_ms = c->fam_ms[i];
+  }
+  if (reset) {
+    std::fill(c->fam_launches.begin(), c->fam_launches.end(), 0);
+    std::fill(c->fam_ms.begin(), c->fam_ms.end(), 0.0);
+  }
   return RS_OK;
 }
 

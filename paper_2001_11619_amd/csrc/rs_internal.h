@@ -68,8 +68,9 @@ constexpr int kNC = 16;        // right-hand-side columns per sweep block
 // ---- launchers (rs_kernels.hip) -------------------------------------------
 void launch_assemble_M(const LevelBox* boxes, int nbox, int max_m, const int* dofs,
                        const int* fint, Geo g, int n_proxy, double ratio, hipStream_t s);
+size_t cpqr_lds_bytes(int max_m, int max_n);
 void launch_cpqr(const LevelBox* boxes, int nbox, double tol, int extra, int* perm,
-                 int* k_out, int* kx_out, int max_n, hipStream_t s);
+                 int* k_out, int* kx_out, int max_m, int max_n, hipStream_t s);
 void launch_assemble_abb(const LevelBox* boxes, int nbox, int max_n, const int* dofs,
                          const int* perm, const ChildSrc* src, Geo g, double lam,
                          hipStream_t s);
@@ -77,6 +78,8 @@ void launch_eliminate(const LevelBox* boxes, int nbox, int* k_io, const int* kx,
                       double rcond_min, int* status, int max_n, hipStream_t s);
 void launch_gj_inverse(double* A, int n, int lda, double* Ainv, double* work,
                        double* rcond_out, int* status, hipStream_t s);
+void launch_gj_blocked(double* A, int n, double* Ainv, double* work, int* iwork, int* status,
+                       hipStream_t s);
 void launch_sweep(const SolveBox* boxes, int nbox, const int* sidx, const int* ridx,
                   double* c, int ncols, int mode, int max_n, hipStream_t s);
 void launch_diag(const SolveBox* boxes, int nbox, const int* ridx, double* c, int ncols,

@@ -21,6 +21,7 @@
 //   k_apply_D / k_apply_psi   the exact float64 operator applied on the fly
 #include "rs_internal.h"
 
+#include <algorithm>
 #include <cmath>
 
 namespace rs {
@@ -314,13 +315,19 @@ __global__ __launch_bounds__(kBlock) void k_assemble_M(const LevelBox* boxes, co
 // step with |R_jj| <= tol |R_11| plus `extra` further steps (head-room for
 // the X_RR guard).  Writes perm (pivot order of positions in I_B), the
 // tolerance rank k and the number of R rows kept, R in pivot order.
-__global__ __launch_bounds__(kBlock) void k_cpqr(const LevelBox* boxes, double tol, int extra,
-                                                 int* perm_out, int* k_out, int* kx_out) {
+// The Householder vector lives in LDS; each trailing column is read once
+// into registers (rows lane + 64 u), updated and written back, and its new
+// norm is formed in the same pass.
+constexpr int kQRThreads = 512;
+constexpr int kQRRows = 32;             // rows per lane held in registers (m <= 2048)
+
+__global__ __launch_bounds__(kQRThreads) void k_cpqr(const LevelBox* boxes, double tol, int extra,
+                                                     int* perm_out, int* k_out, int* kx_out) {
   extern __shared__ double smem[];
   const LevelBox& B = boxes[blockIdx.x];
   const int m = B.m, n = B.n;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  constexpr int NW = kBlock / 64;
+  constexpr int NW = kQRThreads / 64;
   __shared__ double red[NW];
   __shared__ double bval[NW];
   __shared__ int bperm[NW];
@@ -329,19 +336,21 @@ __global__ __launch_bounds__(kBlock) void k_cpqr(const LevelBox* boxes, double t
     if (tid == 0) { k_out[blockIdx.x] = 0; kx_out[blockIdx.x] = 0; }
     return;
   }
-  double* nrm = smem;            // n
-  double* rdiag = smem + n;      // n
-  int* pv = (int*)(smem + 2 * n);  // n
+  double* nrm = smem;              // n
+  double* rdiag = smem + n;        // n
+  double* vsh = smem + 2 * n;      // m
+  int* pv = (int*)(smem + 2 * n + m);  // n
   double* A = B.M;
+  const bool regs = m <= 64 * kQRRows;
   for (int c = wid; c < n; c += NW) {
     const double* col = A + (size_t)c * m;
-    double s = 0.0;
+    double sum = 0.0;
     for (int i = lane; i < m; i += 64) {
       const double a = col[i];
-      s += a * a;
+      sum += a * a;
     }
-    s = wave_sum(s);
-    if (lane == 0) { nrm[c] = s; pv[c] = c; }
+    sum = wave_sum(sum);
+    if (lane == 0) { nrm[c] = sum; pv[c] = c; }
   }
   __syncthreads();
   const int steps = min(m, n);
@@ -352,7 +361,7 @@ __global__ __launch_bounds__(kBlock) void k_cpqr(const LevelBox* boxes, double t
   for (; j < limit; ++j) {
     double best = -1.0;
     int bp = 1 << 30, bq = -1;
-    for (int c = j + tid; c < n; c += kBlock) {
+    for (int c = j + tid; c < n; c += kQRThreads) {
       const double v = nrm[c];
       const int p = pv[c];
       if (v > best || (v == best && p < bp)) { best = v; bp = p; bq = c; }
@@ -377,23 +386,24 @@ __global__ __launch_bounds__(kBlock) void k_cpqr(const LevelBox* boxes, double t
       }
     }
     __syncthreads();
-    double* x = A + (size_t)pv[j] * m;
-    double s = 0.0;
-    for (int i = j + 1 + tid; i < m; i += kBlock) {
+    const double* x = A + (size_t)pv[j] * m;
+    double sum = 0.0;
+    for (int i = j + 1 + tid; i < m; i += kQRThreads) {
       const double a = x[i];
-      s += a * a;
+      vsh[i] = a;
+      sum += a * a;
     }
-    s = block_sum(s, red);
+    sum = block_sum(sum, red);
     const double alpha = x[j];
     double beta, tau;
-    if (s == 0.0) {
+    if (sum == 0.0) {
       beta = alpha;
       tau = 0.0;
     } else {
-      beta = -copysign(sqrt(alpha * alpha + s), alpha);
+      beta = -copysign(sqrt(alpha * alpha + sum), alpha);
       tau = (beta - alpha) / beta;
       const double scal = 1.0 / (alpha - beta);
-      for (int i = j + 1 + tid; i < m; i += kBlock) x[i] *= scal;
+      for (int i = j + 1 + tid; i < m; i += kQRThreads) vsh[i] *= scal;
     }
     if (tid == 0) rdiag[j] = beta;
     __syncthreads();
@@ -403,30 +413,62 @@ __global__ __launch_bounds__(kBlock) void k_cpqr(const LevelBox* boxes, double t
       kk = j;
       limit = min(steps, j + 1 + extra);
     }
-    for (int c = j + 1 + wid; c < n; c += NW) {
-      double* y = A + (size_t)pv[c] * m;
-      const double yj = y[j];
-      double ws = 0.0;
-      for (int i = j + 1 + lane; i < m; i += 64) ws += x[i] * y[i];
-      ws = wave_sum(ws) + yj;
-      const double tw = tau * ws;
-      double ns = 0.0;
-      for (int i = j + 1 + lane; i < m; i += 64) {
-        const double v = y[i] - tw * x[i];
-        y[i] = v;
-        ns += v * v;
+    if (regs) {
+      for (int c = j + 1 + wid; c < n; c += NW) {
+        double* y = A + (size_t)pv[c] * m;
+        const double yj = y[j];
+        double yr[kQRRows];
+        double ws = 0.0;
+#pragma unroll
+        for (int u = 0; u < kQRRows; ++u) {
+          const int i = lane + 64 * u;
+          yr[u] = (i > j && i < m) ? y[i] : 0.0;
+          ws += (i > j && i < m) ? vsh[i] * yr[u] : 0.0;
+        }
+        ws = wave_sum(ws) + yj;
+        const double tw = tau * ws;
+        double ns = 0.0;
+#pragma unroll
+        for (int u = 0; u < kQRRows; ++u) {
+          const int i = lane + 64 * u;
+          if (i > j && i < m) {
+            const double v = yr[u] - tw * vsh[i];
+            y[i] = v;
+            ns += v * v;
+          }
+        }
+        ns = wave_sum(ns);
+        if (lane == 0) {
+          y[j] = yj - tw;
+          nrm[c] = ns;
+        }
       }
-      ns = wave_sum(ns);
-      if (lane == 0) {
-        y[j] = yj - tw;
-        nrm[c] = ns;
+    } else {
+      for (int c = j + 1 + wid; c < n; c += NW) {
+        double* y = A + (size_t)pv[c] * m;
+        const double yj = y[j];
+        double ws = 0.0;
+        for (int i = j + 1 + lane; i < m; i += 64) ws += vsh[i] * y[i];
+        ws = wave_sum(ws) + yj;
+        const double tw = tau * ws;
+        double ns = 0.0;
+        for (int i = j + 1 + lane; i < m; i += 64) {
+          const double v = y[i] - tw * vsh[i];
+          y[i] = v;
+          ns += v * v;
+        }
+        ns = wave_sum(ns);
+        if (lane == 0) {
+          y[j] = yj - tw;
+          nrm[c] = ns;
+        }
       }
     }
     __syncthreads();
   }
   const int kx = j;
   if (kk < 0) kk = kx;
-  for (int t = tid; t < kx * n; t += kBlock) {
+  for (int t = tid; t < kx * n; t += kQRThreads) {
     const int r = t / n, c = t % n;
     double v;
     if (c < r) v = 0.0;
@@ -434,7 +476,7 @@ __global__ __launch_bounds__(kBlock) void k_cpqr(const LevelBox* boxes, double t
     else v = A[(size_t)pv[c] * m + r];
     B.R[t] = v;
   }
-  for (int c = tid; c < n; c += kBlock) perm_out[B.dof_off + c] = pv[c];
+  for (int c = tid; c < n; c += kQRThreads) perm_out[B.dof_off + c] = pv[c];
   if (tid == 0) { k_out[blockIdx.x] = kk; kx_out[blockIdx.x] = kx; }
 }
 
@@ -525,6 +567,178 @@ __global__ __launch_bounds__(kBlock) void k_gj_inverse(double* A, int n, int lda
     *rcond_out = rc;
     *status = rc > 0.0 ? 0 : 1;
   }
+}
+
+// ---- blocked in-place Gauss-Jordan inverse (root system) ----------------------
+// A (n x n, row-major) is overwritten by the inverse of P A, where P is the
+// row permutation chosen by partial pivoting (recorded in rowperm); a final
+// column scatter yields A^{-1}.  Per block of b pivot columns K:
+//   panel:  LU with partial pivoting of A[k0:n, K] picks the pivot rows and
+//           gives D^{-1} for the pivot block D (after the row swaps);
+//   swap:   the b row interchanges over all columns, copy of the column block;
+//   rows:   R = D^{-1} A[K, :];
+//   update: A[K,K] = D^{-1}, A[K,~K] = R, A[~K,K] = -A[~K,K] D^{-1},
+//           A[~K,~K] -= A[~K,K] R.
+constexpr int kGJB = 32;
+
+__global__ __launch_bounds__(kBlock) void k_gjb_panel(const double* A, int n, int k0, int bb,
+                                                      double* W, int* piv, double* Dinv,
+                                                      int* status) {
+  constexpr int NW = kBlock / 64;
+  __shared__ double red[NW];
+  __shared__ int ired[NW];
+  __shared__ double lu[kGJB][kGJB + 1];
+  __shared__ double inv[kGJB][kGJB + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int h = n - k0;
+  for (int t = tid; t < h * bb; t += kBlock) {
+    const int i = t / bb, c = t % bb;
+    W[t] = A[(size_t)(k0 + i) * n + k0 + c];
+  }
+  __syncthreads();
+  bool singular = false;
+  for (int j = 0; j < bb; ++j) {
+    double best = -1.0;
+    int bi = h;
+    for (int i = j + tid; i < h; i += kBlock) {
+      const double v = fabs(W[(size_t)i * bb + j]);
+      if (v > best) { best = v; bi = i; }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_xor(best, o, 64);
+      const int oi = __shfl_xor(bi, o, 64);
+      if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+    }
+    if (lane == 0) { red[wid] = best; ired[wid] = bi; }
+    __syncthreads();
+    best = red[0];
+    bi = ired[0];
+    for (int w = 1; w < NW; ++w)
+      if (red[w] > best || (red[w] == best && ired[w] < bi)) { best = red[w]; bi = ired[w]; }
+    __syncthreads();
+    if (!(best > 0.0)) { singular = true; break; }
+    if (tid == 0) piv[j] = bi;
+    if (bi != j)
+      for (int c = tid; c < bb; c += kBlock) {
+        const double a = W[(size_t)j * bb + c];
+        W[(size_t)j * bb + c] = W[(size_t)bi * bb + c];
+        W[(size_t)bi * bb + c] = a;
+      }
+    __syncthreads();
+    const double d = W[(size_t)j * bb + j];
+    for (int i = j + 1 + tid; i < h; i += kBlock) W[(size_t)i * bb + j] /= d;
+    __syncthreads();
+    const int rest = bb - j - 1;
+    if (rest > 0)
+      for (int t = tid; t < (h - j - 1) * rest; t += kBlock) {
+        const int i = j + 1 + t / rest, c = j + 1 + t % rest;
+        W[(size_t)i * bb + c] -= W[(size_t)i * bb + j] * W[(size_t)j * bb + c];
+      }
+    __syncthreads();
+  }
+  if (singular) {
+    if (tid == 0) *status = 1;
+    return;
+  }
+  // D = L U (first bb rows of W); D^{-1} = U^{-1} L^{-1}
+  for (int t = tid; t < bb * bb; t += kBlock) lu[t / bb][t % bb] = W[t];
+  __syncthreads();
+  // columns of L^{-1} (unit lower) then U^{-1} applied: one thread per column
+  if (tid < bb) {
+    const int c = tid;
+    double y[kGJB];
+    for (int i = 0; i < bb; ++i) {
+      double s = (i == c) ? 1.0 : 0.0;
+      for (int l = 0; l < i; ++l) s -= lu[i][l] * y[l];
+      y[i] = s;
+    }
+    for (int i = bb - 1; i >= 0; --i) {
+      double s = y[i];
+      for (int l = i + 1; l < bb; ++l) s -= lu[i][l] * y[l];
+      y[i] = s / lu[i][i];
+    }
+    for (int i = 0; i < bb; ++i) inv[i][c] = y[i];
+  }
+  __syncthreads();
+  for (int t = tid; t < bb * bb; t += kBlock) Dinv[t] = inv[t / bb][t % bb];
+}
+
+// Row interchanges of this block over all columns; copy of the column block.
+__global__ void k_gjb_swap(double* A, int n, int k0, int bb, const int* piv, int* rowperm,
+                           double* Cpanel) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < n) {
+    for (int j = 0; j < bb; ++j) {
+      const int r = k0 + piv[j];
+      if (r != k0 + j) {
+        const double a = A[(size_t)(k0 + j) * n + c];
+        A[(size_t)(k0 + j) * n + c] = A[(size_t)r * n + c];
+        A[(size_t)r * n + c] = a;
+      }
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    for (int j = 0; j < bb; ++j) {
+      const int r = k0 + piv[j];
+      const int t = rowperm[k0 + j];
+      rowperm[k0 + j] = rowperm[r];
+      rowperm[r] = t;
+    }
+  }
+}
+
+__global__ void k_gjb_copycol(const double* A, int n, int k0, int bb, double* Cpanel) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * bb) return;
+  const int i = t / bb, c = t % bb;
+  Cpanel[t] = A[(size_t)i * n + k0 + c];
+}
+
+// R = D^{-1} A[K, :]
+__global__ void k_gjb_rows(const double* A, int n, int k0, int bb, const double* Dinv, double* R) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= bb * n) return;
+  const int i = t / n, c = t % n;
+  double s = 0.0;
+  for (int l = 0; l < bb; ++l) s += Dinv[i * bb + l] * A[(size_t)(k0 + l) * n + c];
+  R[t] = s;
+}
+
+__global__ void k_gjb_update(double* A, int n, int k0, int bb, const double* Dinv,
+                             const double* R, const double* Cpanel) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)n * n) return;
+  const int i = (int)(t / n), c = (int)(t % n);
+  const bool ik = i >= k0 && i < k0 + bb;
+  const bool ck = c >= k0 && c < k0 + bb;
+  double v;
+  if (ik) {
+    v = ck ? Dinv[(i - k0) * bb + (c - k0)] : R[(size_t)(i - k0) * n + c];
+  } else if (ck) {
+    double s = 0.0;
+    for (int l = 0; l < bb; ++l) s += Cpanel[(size_t)i * bb + l] * Dinv[l * bb + (c - k0)];
+    v = -s;
+  } else {
+    double s = 0.0;
+    for (int l = 0; l < bb; ++l) s += Cpanel[(size_t)i * bb + l] * R[(size_t)l * n + c];
+    v = A[t] - s;
+  }
+  A[t] = v;
+}
+
+// out[:, rowperm[i]] = A[:, i]  (undo the row permutation of the input)
+__global__ void k_gjb_unpermute(const double* A, int n, const int* rowperm, double* out) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)n * n) return;
+  const int i = (int)(t / n), c = (int)(t % n);
+  out[(size_t)i * n + rowperm[c]] = A[t];
+}
+
+__global__ void k_iota(int* v, int n, int* zero) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) v[t] = t;
+  if (t == 0) *zero = 0;
 }
 
 // ---- solve kernels -----------------------------------------------------------
@@ -919,12 +1133,15 @@ void launch_assemble_M(const LevelBox* boxes, int nbox, int max_m, const int* do
   hipLaunchKernelGGL(k_assemble_M, grid, dim3(kBlock), 0, s, boxes, dofs, fint, g, n_proxy, ratio);
 }
 
+size_t cpqr_lds_bytes(int max_m, int max_n) {
+  return (size_t)max_n * (2 * sizeof(double) + sizeof(int)) + (size_t)max_m * sizeof(double) + 16;
+}
+
 void launch_cpqr(const LevelBox* boxes, int nbox, double tol, int extra, int* perm,
-                 int* k_out, int* kx_out, int max_n, hipStream_t s) {
+                 int* k_out, int* kx_out, int max_m, int max_n, hipStream_t s) {
   if (nbox == 0) return;
-  const size_t shm = (size_t)max_n * (2 * sizeof(double) + sizeof(int)) + 16;
-  hipLaunchKernelGGL(k_cpqr, dim3(nbox), dim3(kBlock), shm, s, boxes, tol, extra, perm, k_out,
-                     kx_out);
+  hipLaunchKernelGGL(k_cpqr, dim3(nbox), dim3(kQRThreads), cpqr_lds_bytes(max_m, max_n), s, boxes,
+                     tol, extra, perm, k_out, kx_out);
 }
 
 void launch_assemble_abb(const LevelBox* boxes, int nbox, int max_n, const int* dofs,
@@ -955,6 +1172,34 @@ inline int chunk_cols(int rows) {
   int nc = kNC;
   while (nc > 1 && (size_t)rows * nc * sizeof(double) > 65536) nc >>= 1;
   return nc;
+}
+
+// Inverse of A (n x n) into Ainv; A is destroyed.  work: >= n*kGJB + kGJB*n +
+// n*kGJB + kGJB*kGJB doubles; iwork: >= n + kGJB ints.
+void launch_gj_blocked(double* A, int n, double* Ainv, double* work, int* iwork, int* status,
+                       hipStream_t s) {
+  double* W = work;                        // (n x kGJB)
+  double* R = W + (size_t)n * kGJB;        // (kGJB x n)
+  double* Cp = R + (size_t)kGJB * n;       // (n x kGJB)
+  double* Dinv = Cp + (size_t)n * kGJB;    // kGJB x kGJB
+  int* rowperm = iwork;
+  int* piv = iwork + n;
+  hipLaunchKernelGGL(k_iota, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, rowperm, n, status);
+  const long long nn = (long long)n * n;
+  for (int k0 = 0; k0 < n; k0 += kGJB) {
+    const int bb = std::min(kGJB, n - k0);
+    hipLaunchKernelGGL(k_gjb_panel, dim3(1), dim3(kBlock), 0, s, A, n, k0, bb, W, piv, Dinv, status);
+    hipLaunchKernelGGL(k_gjb_swap, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, A, n, k0, bb,
+                       piv, rowperm, Cp);
+    hipLaunchKernelGGL(k_gjb_copycol, dim3(blocks_for((long long)n * bb, kBlock)), dim3(kBlock), 0,
+                       s, A, n, k0, bb, Cp);
+    hipLaunchKernelGGL(k_gjb_rows, dim3(blocks_for((long long)bb * n, kBlock)), dim3(kBlock), 0, s,
+                       A, n, k0, bb, Dinv, R);
+    hipLaunchKernelGGL(k_gjb_update, dim3(blocks_for(nn, kBlock)), dim3(kBlock), 0, s, A, n, k0, bb,
+                       Dinv, R, Cp);
+  }
+  hipLaunchKernelGGL(k_gjb_unpermute, dim3(blocks_for(nn, kBlock)), dim3(kBlock), 0, s, A, n,
+                     rowperm, Ainv);
 }
 
 void launch_sweep(const SolveBox* boxes, int nbox, const int* sidx, const int* ridx, double* c,
