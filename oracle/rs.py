@@ -33,6 +33,19 @@ Z = [[X_SS, Hh_S], [Ph_S, -I - G]].
 Solve x = V X_D^{-1} U f (eq. kinv) with U applied leaf level first and V
 level 1 first.
 
+Updating (Section 2.8): after nodes move, the tree is rebuilt on the same
+root square and, level by level, a box is recompressed exactly when an input
+of its compression changed; every other box keeps its stored factors:
+  * leaf: it is new, its node set changed, or one of its nodes moved;
+  * parent: it is new, its set of children changed, or a child was
+    recompressed (its skeleton or X_SS may differ);
+  * any box: its near field F_int (ids, in order) changed, or a node of
+    F_int moved.
+Moved nodes outside the proxy circle act only through the proxy rows, which
+is the locality the paper's updating relies on.  The root (and H, Psi^T)
+is always redone.  With the same root the result equals a fresh
+factorization of the new geometry.
+
 Pins: dense LU agreement to O(eps) (P5), explicit U A V block-diagonal on
 tiny inputs (P6), exact point-force solutions, update == refactor (P8).
 """
@@ -338,6 +351,50 @@ class RSFactorization:
         out = np.vstack([x, lam]) if p else x
         assert out.shape[0] == N2 + 3 * p
         return out[:, 0] if one else out
+
+    # ---- updating (Section 2.8) -------------------------------------------------
+    def update(self, new_geom, moved_nodes):
+        """Refactor for new_geom (same root square) recompressing only the boxes
+        whose compression inputs changed.  Returns the set of recompressed box ids."""
+        old_boxes, old_fac = self.boxes, self.fac
+        old_by_key = {b.key: b for b in old_boxes}
+        moved = np.zeros(new_geom.n_nodes, dtype=bool)
+        moved[np.asarray(moved_nodes, dtype=np.int64)] = True
+        self.geom = new_geom
+        self.boxes = build_tree(new_geom.xy, self.prm.leaf_size, self.root)
+        self.L = depth(self.boxes)
+        self.fac = {}
+        recomputed = set()
+        active = np.ones(new_geom.n_dofs, dtype=bool)
+        for l in range(self.L, 0, -1):
+            bl = self.levels(l)
+            snap = active.copy()
+            for b in bl:
+                ob = old_by_key.get(b.key)
+                ofb = old_fac.get(ob.id) if ob is not None else None
+                changed = ob is None or ofb is None or ob.is_leaf != b.is_leaf
+                if not changed:
+                    if b.is_leaf:
+                        changed = not np.array_equal(ob.nodes, b.nodes) or bool(moved[b.nodes].any())
+                    else:
+                        okeys = sorted(old_boxes[c].key for c in ob.children)
+                        nkeys = sorted(self.boxes[c].key for c in b.children)
+                        changed = okeys != nkeys or any(c in recomputed for c in b.children)
+                if not changed:
+                    I = self.box_dofs(b)
+                    Fint = self.far_near(b, I, snap)
+                    changed = (not np.array_equal(Fint, ofb.Fint)) or bool(moved[Fint // 2].any())
+                if changed:
+                    self.fac[b.id] = self.compress(b, snap)
+                    recomputed.add(b.id)
+                else:
+                    ofb.box = b.id
+                    self.fac[b.id] = ofb
+            for b in bl:
+                active[self.fac[b.id].R] = False
+        self._factor_root()
+        self.factored = True
+        return recomputed
 
     # ---- statistics -----------------------------------------------------------
     def ranks(self):

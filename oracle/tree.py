@@ -33,6 +33,12 @@ class Box:
     parent: int
     nodes: np.ndarray                    # sorted node indices inside the box
     children: List[int] = field(default_factory=list)
+    ix: int = 0                          # integer position of the box on its level's grid
+    iy: int = 0
+
+    @property
+    def key(self):
+        return (self.level, self.ix, self.iy)
 
     @property
     def is_leaf(self) -> bool:
@@ -71,7 +77,8 @@ def build_tree(xy: np.ndarray, leaf_size: int, root: Optional[tuple] = None) -> 
                 continue
             ccx = b.cx - h if quad % 2 == 0 else b.cx + h
             ccy = b.cy - h if quad < 2 else b.cy + h
-            child = Box(len(boxes), b.level + 1, ccx, ccy, b.side / 2.0, b.id, sel)
+            child = Box(len(boxes), b.level + 1, ccx, ccy, b.side / 2.0, b.id, sel,
+                        ix=2 * b.ix + (quad & 1), iy=2 * b.iy + (quad >> 1))
             b.children.append(child.id)
             boxes.append(child)
     return boxes

@@ -13,7 +13,10 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <memory>
 #include <string>
+#include <tuple>
 #include <unordered_map>
 #include <vector>
 
@@ -91,8 +94,19 @@ struct BoxFac {
   double* Xinv = nullptr;
   double* Xss = nullptr;
   double* W = nullptr;
-  int arena_level = -1;
+  int arena = -1;             // id of the device arena holding T, E, F, Xinv, Xss
   int rank0 = 0;
+  std::vector<int> fint;      // near field F_int used by the compression
+};
+
+using BoxKey = std::tuple<int, long long, long long>;   // (level, ix, iy)
+
+// Factorization state before an update: boxes are matched by BoxKey.
+struct OldState {
+  std::vector<Box> boxes;
+  std::vector<BoxFac> fac;
+  std::map<BoxKey, int> by_key;
+  std::vector<char> moved;    // per node of the new geometry
 };
 
 constexpr int kMaxDepth = 48;
@@ -122,7 +136,10 @@ struct rs_ctx {
   // factorization
   bool factored = false;
   std::vector<BoxFac> fac;
-  std::vector<DevBuf*> level_arena;   // per level
+  std::map<int, std::unique_ptr<DevBuf>> arenas;   // factor storage, one per level launch
+  int next_arena = 0;
+  std::vector<char> recomputed;   // per box of the current tree
+  const OldState* old = nullptr;  // set while an update runs
   // level workspaces (reused level to level)
   DevBuf ws_M, ws_R, ws_A, ws_scr, ws_boxes, ws_dofs, ws_fint, ws_src, ws_perm, ws_k, ws_kx,
       ws_status;
@@ -153,7 +170,6 @@ struct rs_ctx {
   std::vector<double> fam_ms;
 
   ~rs_ctx() {
-    for (auto* b : level_arena) delete b;
     for (auto& p : pending) {
       (void)hipEventDestroy(p.a);
       (void)hipEventDestroy(p.b);
@@ -349,6 +365,44 @@ double seconds_since(std::chrono::steady_clock::time_point t0) {
   return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 
+// Updating rule (Section 2.8): a box is recompressed when an input of its
+// compression changed.  Leaf: new box, different node set, or a moved node.
+// Parent: new box, different children, or a recompressed child.  Any box: a
+// different near field F_int or a moved node in it.  Otherwise the stored
+// factors are exactly those a fresh factorization would compute.
+bool compress_needed(const rs_ctx* c, int b, const std::vector<int>& F) {
+  const OldState& O = *c->old;
+  const Box& B = c->boxes[b];
+  auto it = O.by_key.find(BoxKey{B.level, B.ix, B.iy});
+  if (it == O.by_key.end()) return true;
+  const Box& OB = O.boxes[it->second];
+  const BoxFac& OF = O.fac[it->second];
+  if (!OF.active || OB.leaf() != B.leaf()) return true;
+  if (B.leaf()) {
+    if (OB.nodes != B.nodes) return true;
+    for (int j : B.nodes)
+      if (O.moved[j]) return true;
+  } else {
+    std::vector<BoxKey> ok, nk;
+    for (int q = 0; q < OB.nchild; ++q) {
+      const Box& C = O.boxes[OB.child[q]];
+      ok.emplace_back(C.level, C.ix, C.iy);
+    }
+    for (int q = 0; q < B.nchild; ++q) {
+      const Box& C = c->boxes[B.child[q]];
+      nk.emplace_back(C.level, C.ix, C.iy);
+      if (c->recomputed[B.child[q]]) return true;
+    }
+    std::sort(ok.begin(), ok.end());
+    std::sort(nk.begin(), nk.end());
+    if (ok != nk) return true;
+  }
+  if (F != OF.fint) return true;
+  for (int d : F)
+    if (O.moved[d >> 1]) return true;
+  return false;
+}
+
 // Factor every box of level l (ids in `ids`), reading the level-start active set.
 void factor_level(rs_ctx* c, int l, const std::vector<int>& ids, const std::vector<char>& active,
                   std::vector<int>& boxes_done) {
@@ -425,6 +479,16 @@ void factor_level(rs_ctx* c, int l, const std::vector<int>& ids, const std::vect
     }
     std::sort(F.begin(), F.end());
     F.erase(std::unique(F.begin(), F.end()), F.end());
+    if (c->old && !compress_needed(c, b, F)) {
+      // every input of this box's compression is unchanged: keep its factors
+      const OldState& O = *c->old;
+      const BoxFac& of = O.fac[O.by_key.at(BoxKey{B.level, B.ix, B.iy})];
+      f = of;
+      c->recomputed[b] = 0;
+      continue;
+    }
+    c->recomputed[b] = 1;
+    f.fint = F;
     LevelBox x{};
     x.cx = B.cx;
     x.cy = B.cy;
@@ -458,8 +522,9 @@ void factor_level(rs_ctx* c, int l, const std::vector<int>& ids, const std::vect
   c->ws_R.ensure(totN2 * sizeof(double));
   c->ws_A.ensure(totN2 * sizeof(double));
   c->ws_scr.ensure(3 * totN2 * sizeof(double));
-  DevBuf* arena = new DevBuf();
-  c->level_arena.push_back(arena);
+  const int aid = c->next_arena++;
+  c->arenas[aid] = std::make_unique<DevBuf>();
+  DevBuf* arena = c->arenas[aid].get();
   arena->ensure(totArena * sizeof(double));
   {
     double* pM = c->ws_M.as<double>();
@@ -543,7 +608,7 @@ void factor_level(rs_ctx* c, int l, const std::vector<int>& ids, const std::vect
     f.perm.assign(perm.begin() + x.dof_off, perm.begin() + x.dof_off + x.n);
     f.k = kk[i];
     f.rank0 = k0[i];
-    f.arena_level = (int)c->level_arena.size() - 1;
+    f.arena = aid;
     if (st[i] != 0)
       throw RsError{RS_ERR_SINGULAR, "X_RR stayed singular after the pivot guard (box " +
                                          std::to_string(b) + ")"};
@@ -728,11 +793,22 @@ void factor_root(rs_ctx* c) {
   c->stats.root_skeleton = n0;
 }
 
+// Free factor arenas no box refers to any more.
+void collect_arenas(rs_ctx* c) {
+  std::vector<char> used(c->next_arena, 0);
+  for (const BoxFac& f : c->fac)
+    if (f.active && f.arena >= 0) used[f.arena] = 1;
+  for (auto it = c->arenas.begin(); it != c->arenas.end();) {
+    if (!used[it->first]) it = c->arenas.erase(it);
+    else ++it;
+  }
+}
+
 void do_factor(rs_ctx* c) {
   auto t0 = std::chrono::steady_clock::now();
-  for (auto* b : c->level_arena) delete b;
-  c->level_arena.clear();
+  if (!c->old) c->arenas.clear();
   c->fac.assign(c->boxes.size(), BoxFac());
+  c->recomputed.assign(c->boxes.size(), 1);
   c->stats.guard_bumps = 0;
   c->stats.flops_id = 0;
   c->stats.flops_elim = 0;
@@ -750,7 +826,11 @@ void do_factor(rs_ctx* c) {
     }
   }
   factor_root(c);
+  collect_arenas(c);
   c->factored = true;
+  c->stats.boxes_recomputed = 0;
+  for (size_t b = 1; b < c->boxes.size(); ++b)
+    if (c->fac[b].active && c->recomputed[b]) c->stats.boxes_recomputed++;
   c->stats.n_levels = c->L + 1;
   c->stats.n_boxes = (int)c->boxes.size();
   c->stats.ms_factor = 1e3 * seconds_since(t0);
@@ -1108,15 +1188,28 @@ rs_status rs_update_moved_nodes(rs_ctx* c, int n_moved, const int* idx, const do
     }
     if (hole_xy) c->hole.assign(hole_xy, hole_xy + 2 * (size_t)c->p);
     HIP_CHECK(hipSetDevice(c->device));
-    // the tree is rebuilt with the same root square; every box is recomputed
+    // the tree is rebuilt on the same root square; boxes are matched by position
+    OldState O;
+    O.boxes = std::move(c->boxes);
+    O.fac = std::move(c->fac);
+    for (size_t b = 0; b < O.boxes.size(); ++b)
+      O.by_key[BoxKey{O.boxes[b].level, O.boxes[b].ix, O.boxes[b].iy}] = (int)b;
+    O.moved.assign(c->N, 0);
+    for (int t = 0; t < n_moved; ++t) O.moved[idx[t]] = 1;
     c->prm.has_root = 1;
     c->prm.root[0] = c->root_cx;
     c->prm.root[1] = c->root_cy;
     c->prm.root[2] = c->root_side;
     build_tree(c);
     upload_geometry(c);
-    do_factor(c);
-    c->stats.boxes_recomputed = (int)c->boxes.size();
+    c->old = &O;
+    try {
+      do_factor(c);
+    } catch (...) {
+      c->old = nullptr;
+      throw;
+    }
+    c->old = nullptr;
     c->stats.ms_update = 1e3 * seconds_since(t0);
     return RS_OK;
   } catch (const RsError& e) {
