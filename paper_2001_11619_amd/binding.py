@@ -262,8 +262,9 @@ class RSSolver:
         self._check(self._lib.rs_get_skeleton(self._h, box, out.size, _iptr(out), ctypes.byref(ln)))
         return out[: ln.value].copy()
 
-    def set_kernel_timing(self, enable: bool = True):
-        self._check(self._lib.rs_set_kernel_timing(self._h, 1 if enable else 0))
+    def set_kernel_timing(self, enable=True):
+        """enable: False/0 off, True/1 per kernel family, 2 per family and tree level."""
+        self._check(self._lib.rs_set_kernel_timing(self._h, int(enable)))
 
     def kernel_times(self, reset: bool = False) -> dict:
         n = ctypes.c_int()

@@ -142,7 +142,8 @@ struct rs_ctx {
   const OldState* old = nullptr;  // set while an update runs
   // level workspaces (reused level to level)
   DevBuf ws_M, ws_R, ws_A, ws_scr, ws_boxes, ws_dofs, ws_fint, ws_src, ws_perm, ws_k, ws_kx,
-      ws_status;
+      ws_status, ws_coop, ws_err;
+  int n_cu = 0;                   // compute units of the device
   // root
   std::vector<int> I0;
   DevBuf d_I0, d_X0, d_Z, d_Zinv, d_gjwork, d_gjiwork, d_rcond, d_rstatus, d_root_box;
@@ -161,7 +162,8 @@ struct rs_ctx {
   rs_stats stats{};
 
   // kernel timing (HIP events around launches)
-  bool timing = false;
+  int timing = 0;                 // 0 off, 1 per kernel family, 2 per family and level
+  int cur_level = -1;
   struct Pending { int fam; hipEvent_t a, b; };
   std::vector<Pending> pending;
   std::vector<hipEvent_t> event_pool;
@@ -220,7 +222,12 @@ struct KTimer {
   hipEvent_t a{};
   KTimer(rs_ctx* ctx, const char* name) : c(ctx) {
     if (!c->timing) return;
-    fam = family(c, name);
+    if (c->timing == 2 && c->cur_level >= 0) {
+      const std::string full = std::string(name) + "@L" + std::to_string(c->cur_level);
+      fam = family(c, full.c_str());
+    } else {
+      fam = family(c, name);
+    }
     a = take_event(c);
     HIP_CHECK(hipEventRecord(a, c->stream));
   }
@@ -514,14 +521,32 @@ void factor_level(rs_ctx* c, int l, const std::vector<int>& ids, const std::vect
   }
   const int nb = (int)lb.size();
   if (nb == 0) return;
-  if (cpqr_lds_bytes(max_m, max_n) > 65536)
+  const size_t qr_lds = cpqr_lds_bytes(max_m, max_n);
+  if (qr_lds > 160 * 1024)
     throw RsError{RS_ERR_ARG, "box too large for the pivoted-QR kernel (m=" + std::to_string(max_m) +
                                   ", n=" + std::to_string(max_n) + ")"};
+  // workgroups per box for the pivoted QR: spread the few large boxes near the
+  // root over the whole device (all must be co-resident: cooperative launch)
+  int G = 1;
+  {
+    const int per_cu = cpqr_blocks_per_cu(qr_lds);
+    const int cap = per_cu * c->n_cu;
+    if (cap > 0) G = std::min({cap / nb, std::max(1, max_n / 16), 64});
+    if (G < 2 || nb > c->n_cu / 4) G = 1;
+  }
+  int Ge = 1;
+  {
+    const int cap = eliminate_blocks_per_cu() * c->n_cu;
+    if (cap > 0) Ge = std::min({cap / nb, std::max(1, max_n / 8), 64});
+    if (Ge < 2 || nb > c->n_cu / 4) Ge = 1;
+  }
   // workspaces
   c->ws_M.ensure(totM * sizeof(double));
   c->ws_R.ensure(totN2 * sizeof(double));
   c->ws_A.ensure(totN2 * sizeof(double));
-  c->ws_scr.ensure(3 * totN2 * sizeof(double));
+  size_t totScr = 0;
+  for (const LevelBox& x : lb) totScr += 3 * (size_t)x.n * x.n + 128 * (size_t)x.n + 2048;
+  c->ws_scr.ensure(totScr * sizeof(double));
   const int aid = c->next_arena++;
   c->arenas[aid] = std::make_unique<DevBuf>();
   DevBuf* arena = c->arenas[aid].get();
@@ -543,7 +568,7 @@ void factor_level(rs_ctx* c, int l, const std::vector<int>& ids, const std::vect
       x.Ap = pA;
       pA += n2;
       x.scr = pS;
-      pS += 3 * n2;
+      pS += 3 * n2 + 128 * (size_t)x.n + 2048;
       x.T = pa;
       pa += kr;
       x.E = pa;
@@ -562,6 +587,26 @@ void factor_level(rs_ctx* c, int l, const std::vector<int>& ids, const std::vect
       f.Xss = x.Xss;
     }
   }
+  {
+    // cooperation scratch per box: barrier, (beta, tau), 2G candidates, Householder vector
+    size_t tot = 0;
+    for (const LevelBox& x : lb) tot += 8 + 2 + 2 * (size_t)G + (size_t)G + (size_t)x.m;
+    c->ws_coop.ensure(tot * sizeof(double));
+    double* pc = c->ws_coop.as<double>();
+    for (LevelBox& x : lb) {
+      x.bar = reinterpret_cast<unsigned*>(pc);
+      pc += 8;
+      x.hh = pc;
+      pc += 2;
+      x.cval = pc;
+      pc += 2 * (size_t)G;
+      x.cphys = reinterpret_cast<int*>(pc);
+      pc += G;
+      x.vbuf = pc;
+      pc += x.m;
+    }
+    c->ws_err.ensure(sizeof(int) * 4);
+  }
   upload(c->ws_boxes, lb, s);
   upload(c->ws_dofs, dofs, s);
   upload(c->ws_fint, fint, s);
@@ -578,8 +623,8 @@ void factor_level(rs_ctx* c, int l, const std::vector<int>& ids, const std::vect
   }
   {
     KTimer kt_(c, "cpqr");
-    launch_cpqr(dlb, nb, P.tol, kGuardExtra, c->ws_perm.as<int>(), c->ws_k.as<int>(),
-                c->ws_kx.as<int>(), max_m, max_n, s);
+    HIP_CHECK(launch_cpqr(dlb, nb, G, P.tol, kGuardExtra, c->ws_perm.as<int>(), c->ws_k.as<int>(),
+                          c->ws_kx.as<int>(), c->ws_err.as<int>(), max_m, max_n, s));
   }
   {
     KTimer kt_(c, "assemble_abb");
@@ -590,17 +635,20 @@ void factor_level(rs_ctx* c, int l, const std::vector<int>& ids, const std::vect
   HIP_CHECK(hipMemcpyAsync(k0.data(), c->ws_k.p, nb * sizeof(int), hipMemcpyDeviceToHost, s));
   {
     KTimer kt_(c, "eliminate");
-    launch_eliminate(dlb, nb, c->ws_k.as<int>(), c->ws_kx.as<int>(), P.rcond_min,
-                     c->ws_status.as<int>(), max_n, s);
+    HIP_CHECK(launch_eliminate(dlb, nb, Ge, c->ws_k.as<int>(), c->ws_kx.as<int>(), P.rcond_min,
+                               c->ws_status.as<int>(), c->ws_err.as<int>() + 1, s));
   }
   HIP_CHECK(hipGetLastError());
   std::vector<int> perm(dofs.size()), kk(nb), st(nb);
+  int qr_err[2] = {0, 0};
+  HIP_CHECK(hipMemcpyAsync(qr_err, c->ws_err.p, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
   HIP_CHECK(hipMemcpyAsync(perm.data(), c->ws_perm.p, perm.size() * sizeof(int),
                            hipMemcpyDeviceToHost, s));
   HIP_CHECK(hipMemcpyAsync(kk.data(), c->ws_k.p, nb * sizeof(int), hipMemcpyDeviceToHost, s));
   HIP_CHECK(hipMemcpyAsync(st.data(), c->ws_status.p, nb * sizeof(int), hipMemcpyDeviceToHost, s));
   HIP_CHECK(hipStreamSynchronize(s));
   resolve_timers(c);
+  if (qr_err[0] || qr_err[1]) throw RsError{RS_ERR_DEVICE, "box barrier timed out"};
   for (int i = 0; i < nb; ++i) {
     const int b = ids[sel[i]];
     BoxFac& f = c->fac[b];
@@ -819,12 +867,14 @@ void do_factor(rs_ctx* c) {
   for (size_t b = 0; b < c->boxes.size(); ++b) by_level[c->boxes[b].level].push_back((int)b);
   for (int l = c->L; l >= 1; --l) {
     std::vector<int> done;
+    c->cur_level = l;
     factor_level(c, l, by_level[l], active, done);
     for (int b : done) {
       const BoxFac& f = c->fac[b];
       for (int i = f.k; i < f.n; ++i) active[f.I[f.perm[i]]] = 0;
     }
   }
+  c->cur_level = -1;
   factor_root(c);
   collect_arenas(c);
   c->factored = true;
@@ -1040,6 +1090,7 @@ rs_status rs_build_tree(const rs_params* prm, int n_nodes, const double* xy, con
     }
     build_tree(c);
     HIP_CHECK(hipGetDevice(&c->device));
+    HIP_CHECK(hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, c->device));
     upload_geometry(c);
     c->stats.n_nodes = n_nodes;
     c->stats.n_holes = n_holes;
@@ -1285,7 +1336,7 @@ rs_status rs_get_skeleton(const rs_ctx* c, int box, int cap, int* out, int* len)
 
 rs_status rs_set_kernel_timing(rs_ctx* c, int enable) {
   if (!c) return RS_ERR_ARG;
-  c->timing = enable != 0;
+  c->timing = enable < 0 ? 0 : (enable > 2 ? 2 : enable);
   return RS_OK;
 }
 

@@ -32,12 +32,18 @@ struct LevelBox {
   double* M;      // m x n, column-major (ld = m)
   double* R;      // kcap x n, row-major, pivot order
   double* Ap;     // n x n, row-major, A_BB in pivot order
-  double* scr;    // scratch for the elimination, 3 n^2
+  double* scr;    // scratch for the elimination: 3 n^2 + 128 n + 2048
   double* T;      // k x r  (capacity n^2/4 + n)
   double* E;      // k x r
   double* F;      // r x k
   double* Xinv;   // r x r  (capacity n^2)
   double* Xss;    // k x k  (capacity n^2)
+  // cooperation of several workgroups on one box (pivoted QR)
+  unsigned* bar;  // box barrier counter
+  double* hh;     // beta, tau of the current step
+  double* cval;   // 2 x G pivot candidates (value)
+  int* cphys;     // 2 x G pivot candidates (column)
+  double* vbuf;   // m: current Householder vector
 };
 
 // Where the parent's diagonal block finds a child's skeleton block.
@@ -69,13 +75,15 @@ constexpr int kNC = 16;        // right-hand-side columns per sweep block
 void launch_assemble_M(const LevelBox* boxes, int nbox, int max_m, const int* dofs,
                        const int* fint, Geo g, int n_proxy, double ratio, hipStream_t s);
 size_t cpqr_lds_bytes(int max_m, int max_n);
-void launch_cpqr(const LevelBox* boxes, int nbox, double tol, int extra, int* perm,
-                 int* k_out, int* kx_out, int max_m, int max_n, hipStream_t s);
+int cpqr_blocks_per_cu(size_t lds);
+hipError_t launch_cpqr(const LevelBox* boxes, int nbox, int G, double tol, int extra, int* perm,
+                       int* k_out, int* kx_out, int* err, int max_m, int max_n, hipStream_t s);
 void launch_assemble_abb(const LevelBox* boxes, int nbox, int max_n, const int* dofs,
                          const int* perm, const ChildSrc* src, Geo g, double lam,
                          hipStream_t s);
-void launch_eliminate(const LevelBox* boxes, int nbox, int* k_io, const int* kx,
-                      double rcond_min, int* status, int max_n, hipStream_t s);
+int eliminate_blocks_per_cu();
+hipError_t launch_eliminate(const LevelBox* boxes, int nbox, int G, int* k_io, const int* kx,
+                            double rcond_min, int* status, int* err, hipStream_t s);
 void launch_gj_inverse(double* A, int n, int lda, double* Ainv, double* work,
                        double* rcond_out, int* status, hipStream_t s);
 void launch_gj_blocked(double* A, int n, double* Ainv, double* work, int* iwork, int* status,

@@ -309,40 +309,120 @@ __global__ __launch_bounds__(kBlock) void k_assemble_M(const LevelBox* boxes, co
   }
 }
 
-// Pivoted Householder QR of M_B (m x n, column-major), one block per box.
+// Pivoted Householder QR of M_B (m x n, column-major).
 // Pivot: largest remaining column norm (recomputed exactly after every
 // step), ties to the column that came first in I_B.  Runs until the first
 // step with |R_jj| <= tol |R_11| plus `extra` further steps (head-room for
 // the X_RR guard).  Writes perm (pivot order of positions in I_B), the
 // tolerance rank k and the number of R rows kept, R in pivot order.
-// The Householder vector lives in LDS; each trailing column is read once
-// into registers (rows lane + 64 u), updated and written back, and its new
-// norm is formed in the same pass.
+//
+// A box is worked on by G workgroups (G = 1 for the many small boxes of the
+// lower levels; the few large boxes near the root get many).  Workgroup g
+// owns the physical columns q with q % G == g for the whole factorization.
+// Each step: local pivot candidates -> box barrier -> the owner of the pivot
+// column forms the Householder vector and publishes it -> box barrier -> every
+// workgroup reflects its own columns and recomputes their norms.  Cross-
+// workgroup data goes through agent-scope atomics; barrier waits are bounded
+// (a timed-out wait flags an error and the kernel drains).
 constexpr int kQRThreads = 512;
 constexpr int kQRRows = 32;             // rows per lane held in registers (m <= 2048)
+constexpr unsigned kSpinLimit = 1u << 22;
 
-__global__ __launch_bounds__(kQRThreads) void k_cpqr(const LevelBox* boxes, double tol, int extra,
-                                                     int* perm_out, int* k_out, int* kx_out) {
+__device__ __forceinline__ void st_relaxed(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_relaxed(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_relaxed(int* p, int v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int ld_relaxed(const int* p) {
+  return __hip_atomic_load(const_cast<int*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Barriers over the G workgroups of one box.  `count` is this workgroup's
+// number of completed box barriers; `dead` turns every later wait into a no-op
+// once a wait has timed out (the kernel then drains and the host reports it).
+//
+// box_barrier_x: for exchanges whose data is written and read only with
+// agent-scope atomics (coherent across the device): every wave waits for its
+// own memory operations to complete, then one thread per workgroup counts in.
+// box_barrier_full: additionally an agent-scope release / acquire fence, for
+// phases that share ordinary global-memory matrices.
+__device__ __forceinline__ void box_wait(unsigned* bar, int G, unsigned& count, int* dead,
+                                         int* err) {
+  if (threadIdx.x == 0 && !*dead) {
+    ++count;
+    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned target = count * (unsigned)G;
+    unsigned spins = 0;
+    while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > kSpinLimit) {
+        *dead = 1;
+        __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+    }
+  }
+}
+
+__device__ void box_barrier_x(unsigned* bar, int G, unsigned& count, int* dead, int* err) {
+  if (G > 1) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    box_wait(bar, G, count, dead, err);
+  }
+  __syncthreads();
+}
+
+__device__ void box_barrier_full(unsigned* bar, int G, unsigned& count, int* dead, int* err) {
+  if (G > 1) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    box_wait(bar, G, count, dead, err);
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kQRThreads) void k_cpqr(const LevelBox* boxes, int G, double tol,
+                                                     int extra, int* perm_out, int* k_out,
+                                                     int* kx_out, int* err) {
   extern __shared__ double smem[];
-  const LevelBox& B = boxes[blockIdx.x];
+  const int bidx = blockIdx.x / G, g = blockIdx.x % G;
+  const LevelBox& B = boxes[bidx];
   const int m = B.m, n = B.n;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   constexpr int NW = kQRThreads / 64;
   __shared__ double red[NW];
   __shared__ double bval[NW];
-  __shared__ int bperm[NW];
-  __shared__ int bpos[NW];
+  __shared__ int bphys[NW];
+  __shared__ int s_q;
+  __shared__ double s_hh[2];
+  __shared__ int s_dead;
   if (n == 0) {
-    if (tid == 0) { k_out[blockIdx.x] = 0; kx_out[blockIdx.x] = 0; }
+    if (tid == 0 && g == 0) { k_out[bidx] = 0; kx_out[bidx] = 0; }
     return;
   }
-  double* nrm = smem;              // n
-  double* rdiag = smem + n;        // n
-  double* vsh = smem + 2 * n;      // m
-  int* pv = (int*)(smem + 2 * n + m);  // n
+  double* nrm = smem;                        // n, by physical column
+  double* rdiag = smem + n;                  // n
+  double* vsh = smem + 2 * n;                // m
+  int* pv = (int*)(smem + 2 * n + m);        // n: physical column at each position
+  int* ipv = pv + n;                         // n: position of each physical column
+  int* own = ipv + n;                        // columns owned by this workgroup
+  unsigned char* done = (unsigned char*)(own + n);   // n
+  const int nown = (n - g + G - 1) / G;
   double* A = B.M;
   const bool regs = m <= 64 * kQRRows;
-  for (int c = wid; c < n; c += NW) {
+  unsigned nbar = 0;
+  if (tid == 0) s_dead = 0;
+  for (int c = tid; c < n; c += kQRThreads) { pv[c] = c; ipv[c] = c; done[c] = 0; }
+  for (int t = tid; t < nown; t += kQRThreads) own[t] = g + t * G;
+  for (int t = wid; t < nown; t += NW) {
+    const int c = g + t * G;
     const double* col = A + (size_t)c * m;
     double sum = 0.0;
     for (int i = lane; i < m; i += 64) {
@@ -350,7 +430,7 @@ __global__ __launch_bounds__(kQRThreads) void k_cpqr(const LevelBox* boxes, doub
       sum += a * a;
     }
     sum = wave_sum(sum);
-    if (lane == 0) { nrm[c] = sum; pv[c] = c; }
+    if (lane == 0) nrm[c] = sum;
   }
   __syncthreads();
   const int steps = min(m, n);
@@ -359,71 +439,119 @@ __global__ __launch_bounds__(kQRThreads) void k_cpqr(const LevelBox* boxes, doub
   double r00 = 0.0;
   int j = 0;
   for (; j < limit; ++j) {
+    // local pivot candidate among owned, not yet pivoted columns
     double best = -1.0;
-    int bp = 1 << 30, bq = -1;
-    for (int c = j + tid; c < n; c += kQRThreads) {
-      const double v = nrm[c];
-      const int p = pv[c];
-      if (v > best || (v == best && p < bp)) { best = v; bp = p; bq = c; }
+    int bq = 1 << 30;
+    for (int t = tid; t < nown; t += kQRThreads) {
+      const int q = own[t];
+      if (done[q]) continue;
+      const double v = nrm[q];
+      if (v > best || (v == best && q < bq)) { best = v; bq = q; }
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
       const double ov = __shfl_xor(best, o, 64);
-      const int op = __shfl_xor(bp, o, 64);
       const int oq = __shfl_xor(bq, o, 64);
-      if (ov > best || (ov == best && op < bp)) { best = ov; bp = op; bq = oq; }
+      if (ov > best || (ov == best && oq < bq)) { best = ov; bq = oq; }
     }
-    if (lane == 0) { bval[wid] = best; bperm[wid] = bp; bpos[wid] = bq; }
+    if (lane == 0) { bval[wid] = best; bphys[wid] = bq; }
     __syncthreads();
     if (tid == 0) {
-      double bv = bval[0];
-      int bpp = bperm[0], bqq = bpos[0];
       for (int w = 1; w < NW; ++w)
-        if (bval[w] > bv || (bval[w] == bv && bperm[w] < bpp)) { bv = bval[w]; bpp = bperm[w]; bqq = bpos[w]; }
-      if (bqq != j) {
-        const double t = nrm[j]; nrm[j] = nrm[bqq]; nrm[bqq] = t;
-        const int u = pv[j]; pv[j] = pv[bqq]; pv[bqq] = u;
+        if (bval[w] > best || (bval[w] == best && bphys[w] < bq)) { best = bval[w]; bq = bphys[w]; }
+      if (G > 1) {
+        const int par = j & 1;
+        st_relaxed(B.cval + par * G + g, best);
+        st_relaxed(B.cphys + par * G + g, bq);
+      } else {
+        s_q = bq;
+      }
+    }
+    if (G > 1) {
+      box_barrier_x(B.bar, G, nbar, &s_dead, err);
+      if (tid == 0) {
+        const int par = j & 1;
+        double bb = -1.0;
+        int qq = 1 << 30;
+        for (int h = 0; h < G; ++h) {
+          const double v = ld_relaxed(B.cval + par * G + h);
+          const int q = ld_relaxed(B.cphys + par * G + h);
+          if (v > bb || (v == bb && q < qq)) { bb = v; qq = q; }
+        }
+        s_q = qq;
       }
     }
     __syncthreads();
-    const double* x = A + (size_t)pv[j] * m;
-    double sum = 0.0;
-    for (int i = j + 1 + tid; i < m; i += kQRThreads) {
-      const double a = x[i];
-      vsh[i] = a;
-      sum += a * a;
+    const int q = s_q;
+    if (tid == 0) {
+      const int p = ipv[q];
+      const int u = pv[j];
+      pv[j] = q; pv[p] = u;
+      ipv[q] = j; ipv[u] = p;
+      done[q] = 1;
     }
-    sum = block_sum(sum, red);
-    const double alpha = x[j];
-    double beta, tau;
-    if (sum == 0.0) {
-      beta = alpha;
-      tau = 0.0;
-    } else {
-      beta = -copysign(sqrt(alpha * alpha + sum), alpha);
-      tau = (beta - alpha) / beta;
-      const double scal = 1.0 / (alpha - beta);
-      for (int i = j + 1 + tid; i < m; i += kQRThreads) vsh[i] *= scal;
+    // Householder vector of the pivot column, formed by its owner
+    if (q % G == g) {
+      const double* x = A + (size_t)q * m;
+      double sum = 0.0;
+      for (int i = j + 1 + tid; i < m; i += kQRThreads) {
+        const double a = x[i];
+        vsh[i] = a;
+        sum += a * a;
+      }
+      sum = block_sum(sum, red);
+      const double alpha = x[j];
+      double beta, tau;
+      if (sum == 0.0) {
+        beta = alpha;
+        tau = 0.0;
+      } else {
+        beta = -copysign(sqrt(alpha * alpha + sum), alpha);
+        tau = (beta - alpha) / beta;
+        const double scal = 1.0 / (alpha - beta);
+        for (int i = j + 1 + tid; i < m; i += kQRThreads) {
+          const double v = vsh[i] * scal;
+          vsh[i] = v;
+          if (G > 1) st_relaxed(B.vbuf + i, v);
+        }
+      }
+      if (tid == 0) {
+        s_hh[0] = beta;
+        s_hh[1] = tau;
+        if (G > 1) { st_relaxed(B.hh, beta); st_relaxed(B.hh + 1, tau); }
+      }
     }
-    if (tid == 0) rdiag[j] = beta;
+    if (G > 1) {
+      box_barrier_x(B.bar, G, nbar, &s_dead, err);
+      if (q % G != g) {
+        for (int i = j + 1 + tid; i < m; i += kQRThreads) vsh[i] = ld_relaxed(B.vbuf + i);
+        if (tid == 0) { s_hh[0] = ld_relaxed(B.hh); s_hh[1] = ld_relaxed(B.hh + 1); }
+      }
+    }
     __syncthreads();
+    const double beta = s_hh[0], tau = s_hh[1];
+    if (tid == 0) rdiag[j] = beta;
     const double rjj = fabs(beta);
     if (j == 0) r00 = rjj;
     if (kk < 0 && !(rjj > tol * r00)) {
       kk = j;
       limit = min(steps, j + 1 + extra);
     }
-    if (regs) {
-      for (int c = j + 1 + wid; c < n; c += NW) {
-        double* y = A + (size_t)pv[c] * m;
-        const double yj = y[j];
+    // reflect the owned columns that are still to be pivoted
+    for (int t = wid; t < nown; t += NW) {
+      const int c = own[t];
+      if (done[c]) continue;
+      double* y = A + (size_t)c * m;
+      const double yj = y[j];
+      if (regs) {
         double yr[kQRRows];
         double ws = 0.0;
 #pragma unroll
         for (int u = 0; u < kQRRows; ++u) {
           const int i = lane + 64 * u;
-          yr[u] = (i > j && i < m) ? y[i] : 0.0;
-          ws += (i > j && i < m) ? vsh[i] * yr[u] : 0.0;
+          const bool in = i > j && i < m;
+          yr[u] = in ? y[i] : 0.0;
+          ws += in ? vsh[i] * yr[u] : 0.0;
         }
         ws = wave_sum(ws) + yj;
         const double tw = tau * ws;
@@ -438,15 +566,8 @@ __global__ __launch_bounds__(kQRThreads) void k_cpqr(const LevelBox* boxes, doub
           }
         }
         ns = wave_sum(ns);
-        if (lane == 0) {
-          y[j] = yj - tw;
-          nrm[c] = ns;
-        }
-      }
-    } else {
-      for (int c = j + 1 + wid; c < n; c += NW) {
-        double* y = A + (size_t)pv[c] * m;
-        const double yj = y[j];
+        if (lane == 0) { y[j] = yj - tw; nrm[c] = ns; }
+      } else {
         double ws = 0.0;
         for (int i = j + 1 + lane; i < m; i += 64) ws += vsh[i] * y[i];
         ws = wave_sum(ws) + yj;
@@ -458,26 +579,32 @@ __global__ __launch_bounds__(kQRThreads) void k_cpqr(const LevelBox* boxes, doub
           ns += v * v;
         }
         ns = wave_sum(ns);
-        if (lane == 0) {
-          y[j] = yj - tw;
-          nrm[c] = ns;
-        }
+        if (lane == 0) { y[j] = yj - tw; nrm[c] = ns; }
       }
     }
     __syncthreads();
   }
   const int kx = j;
   if (kk < 0) kk = kx;
+  // R rows in pivot order: each workgroup writes the entries of its columns
   for (int t = tid; t < kx * n; t += kQRThreads) {
     const int r = t / n, c = t % n;
-    double v;
-    if (c < r) v = 0.0;
-    else if (c == r) v = rdiag[r];
-    else v = A[(size_t)pv[c] * m + r];
-    B.R[t] = v;
+    if (c <= r) {
+      if (g == 0) B.R[t] = (c == r) ? rdiag[r] : 0.0;
+    } else if (pv[c] % G == g) {
+      B.R[t] = A[(size_t)pv[c] * m + r];
+    }
   }
-  for (int c = tid; c < n; c += kQRThreads) perm_out[B.dof_off + c] = pv[c];
-  if (tid == 0) { k_out[blockIdx.x] = kk; kx_out[blockIdx.x] = kx; }
+  if (g == 0) {
+    for (int c = tid; c < n; c += kQRThreads) perm_out[B.dof_off + c] = pv[c];
+    if (tid == 0) { k_out[bidx] = kk; kx_out[bidx] = kx; }
+  }
+}
+
+__global__ void k_zero_bars(const LevelBox* boxes, int nbox, int* err) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < nbox && boxes[t].bar) *boxes[t].bar = 0u;
+  if (t == 0) *err = 0;
 }
 
 __global__ __launch_bounds__(kBlock) void k_assemble_abb(const LevelBox* boxes, const int* dofs,
@@ -502,26 +629,258 @@ __global__ __launch_bounds__(kBlock) void k_assemble_abb(const LevelBox* boxes, 
   B.Ap[t] = op_entry(g, di >> 1, di & 1, dj >> 1, dj & 1, lam);
 }
 
-__global__ __launch_bounds__(kBlock) void k_eliminate(const LevelBox* boxes, int* k_io,
+// ---- elimination of the redundant unknowns (G workgroups per box) -----------
+
+// C = beta*C0 + alpha*op(A) op(B), 4x4 tiles dealt cyclically over the
+// G*blockDim threads of a box; no barrier inside.
+__device__ void coop_gemm(int g, int G, int M, int N, int K, double alpha, const double* A,
+                          int lda, bool tA, const double* B, int ldb, bool tB, double beta,
+                          const double* C0, int ldc0, double* C, int ldc) {
+  const int tm = (M + 3) >> 2, tn = (N + 3) >> 2;
+  const int stride = G * blockDim.x;
+  for (int t = g * blockDim.x + threadIdx.x; t < tm * tn; t += stride) {
+    const int i0 = (t / tn) << 2, j0 = (t % tn) << 2;
+    double acc[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+    for (int kk = 0; kk < K; ++kk) {
+      double a[4], b[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = i0 + u;
+        a[u] = (i < M) ? (tA ? A[(size_t)kk * lda + i] : A[(size_t)i * lda + kk]) : 0.0;
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int j = j0 + v;
+        b[v] = (j < N) ? (tB ? B[(size_t)j * ldb + kk] : B[(size_t)kk * ldb + j]) : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = i0 + u;
+      if (i >= M) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int j = j0 + v;
+        if (j >= N) continue;
+        double val = alpha * acc[u][v];
+        if (C0) val += beta * C0[(size_t)i * ldc0 + j];
+        C[(size_t)i * ldc + j] = val;
+      }
+    }
+  }
+}
+
+// Largest column 1-norm of X (n x n, ld ldx) over the box, identical in all workgroups.
+__device__ double coop_norm1(int g, int G, const double* X, int n, int ldx, double* red,
+                             const LevelBox& B, unsigned& nbar, int* dead, int* err) {
+  double v = 0.0;
+  for (int c = g * blockDim.x + threadIdx.x; c < n; c += G * blockDim.x) {
+    double sum = 0.0;
+    for (int i = 0; i < n; ++i) sum += fabs(X[(size_t)i * ldx + c]);
+    v = fmax(v, sum);
+  }
+  v = block_max(v, red);
+  if (G == 1) return v;
+  if (threadIdx.x == 0) st_relaxed(B.cval + g, v);
+  box_barrier_x(B.bar, G, nbar, dead, err);
+  double m = 0.0;
+  for (int h = 0; h < G; ++h) m = fmax(m, ld_relaxed(B.cval + h));
+  box_barrier_x(B.bar, G, nbar, dead, err);   // slots are reused afterwards
+  return m;
+}
+
+constexpr int kGJP = 32;   // pivot block of the in-place Gauss-Jordan
+
+// X_RR^{-1} of the box (blocked in-place Gauss-Jordan with partial pivoting,
+// panels of kGJP columns): W holds X_RR on entry and is destroyed; Xi receives
+// the inverse.  Returns false (uniformly) if a pivot vanished.
+__device__ bool coop_gj(int g, int G, double* W, int r, double* Xi, double* Pn, double* Rb,
+                        double* Cp, double* Dinv, int* piv, int* rowperm, int* flag, double* red,
+                        int* ired, const LevelBox& B, unsigned& nbar, int* dead, int* err) {
+  const int NT = blockDim.x, tid = threadIdx.x;
+  const int gt = g * NT + tid, GT = G * NT;
+  for (int c = gt; c < r; c += GT) rowperm[c] = c;
+  __shared__ double lu[kGJP][kGJP + 1];
+  __shared__ double inv[kGJP][kGJP + 1];
+  for (int k0 = 0; k0 < r; k0 += kGJP) {
+    const int bb = min(kGJP, r - k0);
+    const int h = r - k0;
+    if (g == 0) {
+      // panel: LU with partial pivoting of W[k0:r, k0:k0+bb] (private copy Pn)
+      for (int t = tid; t < h * bb; t += NT) {
+        const int i = t / bb, c = t % bb;
+        Pn[t] = W[(size_t)(k0 + i) * r + k0 + c];
+      }
+      __syncthreads();
+      bool singular = false;
+      for (int j = 0; j < bb; ++j) {
+        double best = -1.0;
+        int bi = h;
+        for (int i = j + tid; i < h; i += NT) {
+          const double v = fabs(Pn[(size_t)i * bb + j]);
+          if (v > best) { best = v; bi = i; }
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+          const double ov = __shfl_xor(best, o, 64);
+          const int oi = __shfl_xor(bi, o, 64);
+          if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+        }
+        const int lane = tid & 63, wid = tid >> 6;
+        if (lane == 0) { red[wid] = best; ired[wid] = bi; }
+        __syncthreads();
+        best = red[0];
+        bi = ired[0];
+        for (int w = 1; w < (NT >> 6); ++w)
+          if (red[w] > best || (red[w] == best && ired[w] < bi)) { best = red[w]; bi = ired[w]; }
+        __syncthreads();
+        if (!(best > 0.0)) { singular = true; break; }
+        if (tid == 0) piv[j] = bi;
+        if (bi != j)
+          for (int c = tid; c < bb; c += NT) {
+            const double a = Pn[(size_t)j * bb + c];
+            Pn[(size_t)j * bb + c] = Pn[(size_t)bi * bb + c];
+            Pn[(size_t)bi * bb + c] = a;
+          }
+        __syncthreads();
+        const double d = Pn[(size_t)j * bb + j];
+        for (int i = j + 1 + tid; i < h; i += NT) Pn[(size_t)i * bb + j] /= d;
+        __syncthreads();
+        const int rest = bb - j - 1;
+        if (rest > 0)
+          for (int t = tid; t < (h - j - 1) * rest; t += NT) {
+            const int i = j + 1 + t / rest, c = j + 1 + t % rest;
+            Pn[(size_t)i * bb + c] -= Pn[(size_t)i * bb + j] * Pn[(size_t)j * bb + c];
+          }
+        __syncthreads();
+      }
+      if (singular) {
+        if (tid == 0) *flag = 1;
+      } else {
+        for (int t = tid; t < bb * bb; t += NT) lu[t / bb][t % bb] = Pn[t];
+        __syncthreads();
+        if (tid < bb) {
+          const int c = tid;
+          double y[kGJP];
+          for (int i = 0; i < bb; ++i) {
+            double sum = (i == c) ? 1.0 : 0.0;
+            for (int l = 0; l < i; ++l) sum -= lu[i][l] * y[l];
+            y[i] = sum;
+          }
+          for (int i = bb - 1; i >= 0; --i) {
+            double sum = y[i];
+            for (int l = i + 1; l < bb; ++l) sum -= lu[i][l] * y[l];
+            y[i] = sum / lu[i][i];
+          }
+          for (int i = 0; i < bb; ++i) inv[i][c] = y[i];
+        }
+        __syncthreads();
+        for (int t = tid; t < bb * bb; t += NT) Dinv[t] = inv[t / bb][t % bb];
+      }
+    }
+    box_barrier_full(B.bar, G, nbar, dead, err);
+    if (*(volatile int*)flag) return false;
+    // row interchanges over all columns; the owner of a panel column copies it
+    for (int c = gt; c < r; c += GT) {
+      for (int j = 0; j < bb; ++j) {
+        const int rr = k0 + piv[j];
+        if (rr != k0 + j) {
+          const double a = W[(size_t)(k0 + j) * r + c];
+          W[(size_t)(k0 + j) * r + c] = W[(size_t)rr * r + c];
+          W[(size_t)rr * r + c] = a;
+        }
+      }
+    }
+    if (g == 0 && tid == 0)
+      for (int j = 0; j < bb; ++j) {
+        const int rr = k0 + piv[j];
+        const int t = rowperm[k0 + j];
+        rowperm[k0 + j] = rowperm[rr];
+        rowperm[rr] = t;
+      }
+    box_barrier_full(B.bar, G, nbar, dead, err);
+    for (int t = gt; t < r * bb; t += GT) {
+      const int i = t / bb, l = t % bb;
+      Cp[t] = W[(size_t)i * r + k0 + l];
+    }
+    for (int t = gt; t < bb * r; t += GT) {
+      const int i = t / r, c = t % r;
+      double sum = 0.0;
+      for (int l = 0; l < bb; ++l) sum += Dinv[i * bb + l] * W[(size_t)(k0 + l) * r + c];
+      Rb[t] = sum;
+    }
+    box_barrier_full(B.bar, G, nbar, dead, err);
+    for (int t = gt; t < r * r; t += GT) {
+      const int i = t / r, c = t % r;
+      const bool ik = i >= k0 && i < k0 + bb;
+      const bool ck = c >= k0 && c < k0 + bb;
+      double v;
+      if (ik) {
+        v = ck ? Dinv[(i - k0) * bb + (c - k0)] : Rb[(size_t)(i - k0) * r + c];
+      } else if (ck) {
+        double sum = 0.0;
+        for (int l = 0; l < bb; ++l) sum += Cp[(size_t)i * bb + l] * Dinv[l * bb + (c - k0)];
+        v = -sum;
+      } else {
+        double sum = 0.0;
+        for (int l = 0; l < bb; ++l) sum += Cp[(size_t)i * bb + l] * Rb[(size_t)l * r + c];
+        v = W[t] - sum;
+      }
+      W[t] = v;
+    }
+    box_barrier_full(B.bar, G, nbar, dead, err);
+  }
+  for (int t = gt; t < r * r; t += GT) {
+    const int i = t / r, c = t % r;
+    Xi[(size_t)i * r + rowperm[c]] = W[t];
+  }
+  box_barrier_full(B.bar, G, nbar, dead, err);
+  return true;
+}
+
+// Per box (G workgroups): T = R11^{-1} R12; X_SR, X_RS, X_RR (eq. tmat);
+// X_RR^{-1} with the rcond guard (move the next pivot to S while
+// rcond_1(X_RR) < rcond_min); E, F and the Schur complement X_SS (eq. schurmat).
+__global__ __launch_bounds__(kBlock) void k_eliminate(const LevelBox* boxes, int G, int* k_io,
                                                       const int* kx_in, double rcond_min,
-                                                      int* status) {
-  extern __shared__ double smem[];
+                                                      int* status, int* err) {
   constexpr int NW = kBlock / 64;
   __shared__ double red[NW];
   __shared__ int ired[NW];
-  const LevelBox& B = boxes[blockIdx.x];
+  __shared__ int s_dead;
+  const int bidx = blockIdx.x / G, g = blockIdx.x % G;
+  const LevelBox& B = boxes[bidx];
   const int n = B.n;
   if (n == 0) return;
-  int k = k_io[blockIdx.x];
-  const int kx = kx_in[blockIdx.x];
+  if (threadIdx.x == 0) s_dead = 0;
+  __syncthreads();
+  unsigned nbar = 0;
+  int k = k_io[bidx];
+  const int kx = kx_in[bidx];
   int st = 0;
   const double* Ap = B.Ap;
+  const int gt = g * kBlock + threadIdx.x, GT = G * kBlock;
   while (true) {
     const int r = n - k;
     double* T = B.T;
-    wg_trsm_upper(B.R, n, k, r, T);
+    for (int c = gt; c < r; c += GT) {
+      for (int i = k - 1; i >= 0; --i) {
+        double sum = B.R[(size_t)i * n + k + c];
+        for (int l = i + 1; l < k; ++l) sum -= B.R[(size_t)i * n + l] * T[(size_t)l * r + c];
+        T[(size_t)i * r + c] = sum / B.R[(size_t)i * n + i];
+      }
+    }
+    box_barrier_full(B.bar, G, nbar, &s_dead, err);
     if (r == 0) {
-      for (int t = threadIdx.x; t < k * k; t += kBlock) {
+      for (int t = gt; t < k * k; t += GT) {
         const int i = t / k, c = t % k;
         B.Xss[t] = Ap[(size_t)i * n + c];
       }
@@ -530,28 +889,50 @@ __global__ __launch_bounds__(kBlock) void k_eliminate(const LevelBox* boxes, int
     double* Xsr = B.scr;
     double* Xrs = Xsr + (size_t)k * r;
     double* Xrr = Xrs + (size_t)r * k;
-    double* Wk = Xrr + (size_t)r * r;
-    wg_gemm(k, r, k, -1.0, Ap, n, false, T, r, false, 1.0, Ap + k, n, Xsr, r);
-    wg_gemm(r, k, k, -1.0, T, r, true, Ap, n, false, 1.0, Ap + (size_t)k * n, n, Xrs, k);
-    wg_gemm(r, r, k, -1.0, Ap + (size_t)k * n, n, false, T, r, false, 1.0,
-            Ap + (size_t)k * n + k, n, Xrr, r);
-    wg_gemm(r, r, k, -1.0, T, r, true, Xsr, r, false, 1.0, Xrr, r, Xrr, r);
-    const double rc = wg_gj_inverse(Xrr, r, r, B.Xinv, r, Wk, smem, red, ired);
+    double* W = Xrr + (size_t)r * r;
+    double* Pn = W + (size_t)r * r;
+    double* Rb = Pn + (size_t)r * kGJP;
+    double* Cp = Rb + (size_t)kGJP * r;
+    double* Dinv = Cp + (size_t)r * kGJP;
+    int* piv = reinterpret_cast<int*>(Dinv + kGJP * kGJP);
+    int* rowperm = piv + kGJP;
+    int* flag = rowperm + r + 1;
+    coop_gemm(g, G, k, r, k, -1.0, Ap, n, false, T, r, false, 1.0, Ap + k, n, Xsr, r);
+    coop_gemm(g, G, r, k, k, -1.0, T, r, true, Ap, n, false, 1.0, Ap + (size_t)k * n, n, Xrs, k);
+    coop_gemm(g, G, r, r, k, -1.0, Ap + (size_t)k * n, n, false, T, r, false, 1.0,
+              Ap + (size_t)k * n + k, n, Xrr, r);
+    if (g == 0 && threadIdx.x == 0) *flag = 0;
+    box_barrier_full(B.bar, G, nbar, &s_dead, err);
+    // X_RR -= T^T X_SR, written into W as the working copy for the inverse
+    coop_gemm(g, G, r, r, k, -1.0, T, r, true, Xsr, r, false, 1.0, Xrr, r, W, r);
+    box_barrier_full(B.bar, G, nbar, &s_dead, err);
+    const double n1 = coop_norm1(g, G, W, r, r, red, B, nbar, &s_dead, err);
+    const bool ok = coop_gj(g, G, W, r, B.Xinv, Pn, Rb, Cp, Dinv, piv, rowperm, flag, red, ired, B,
+                            nbar, &s_dead, err);
+    double rc = 0.0;
+    if (ok) {
+      const double n2 = coop_norm1(g, G, B.Xinv, r, r, red, B, nbar, &s_dead, err);
+      rc = 1.0 / (n1 * n2);
+      if (!isfinite(rc)) rc = 0.0;
+    }
     if (!(rc >= rcond_min)) {
       if (k < kx) {
         ++k;
+        box_barrier_full(B.bar, G, nbar, &s_dead, err);
         continue;
       }
       st = 1;
     }
-    wg_gemm(k, r, r, 1.0, Xsr, r, false, B.Xinv, r, false, 0.0, nullptr, 0, B.E, r);
-    wg_gemm(r, k, r, 1.0, B.Xinv, r, false, Xrs, k, false, 0.0, nullptr, 0, B.F, k);
-    wg_gemm(k, k, r, -1.0, Xsr, r, false, B.F, k, false, 1.0, Ap, n, B.Xss, k);
+    // X_RR itself (the pre-inverse block) is not needed any more
+    coop_gemm(g, G, k, r, r, 1.0, Xsr, r, false, B.Xinv, r, false, 0.0, nullptr, 0, B.E, r);
+    coop_gemm(g, G, r, k, r, 1.0, B.Xinv, r, false, Xrs, k, false, 0.0, nullptr, 0, B.F, k);
+    box_barrier_full(B.bar, G, nbar, &s_dead, err);
+    coop_gemm(g, G, k, k, r, -1.0, Xsr, r, false, B.F, k, false, 1.0, Ap, n, B.Xss, k);
     break;
   }
-  if (threadIdx.x == 0) {
-    k_io[blockIdx.x] = k;
-    status[blockIdx.x] = st;
+  if (g == 0 && threadIdx.x == 0) {
+    k_io[bidx] = k;
+    status[bidx] = st;
   }
 }
 
@@ -1134,14 +1515,30 @@ void launch_assemble_M(const LevelBox* boxes, int nbox, int max_m, const int* do
 }
 
 size_t cpqr_lds_bytes(int max_m, int max_n) {
-  return (size_t)max_n * (2 * sizeof(double) + sizeof(int)) + (size_t)max_m * sizeof(double) + 16;
+  return (size_t)max_n * (2 * sizeof(double) + 4 * sizeof(int) + 1) + (size_t)max_m * sizeof(double) + 64;
 }
 
-void launch_cpqr(const LevelBox* boxes, int nbox, double tol, int extra, int* perm,
-                 int* k_out, int* kx_out, int max_m, int max_n, hipStream_t s) {
-  if (nbox == 0) return;
-  hipLaunchKernelGGL(k_cpqr, dim3(nbox), dim3(kQRThreads), cpqr_lds_bytes(max_m, max_n), s, boxes,
-                     tol, extra, perm, k_out, kx_out);
+// Workgroups per resident CU for the pivoted-QR kernel with `lds` bytes of LDS.
+int cpqr_blocks_per_cu(size_t lds) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_cpqr, kQRThreads, lds) != hipSuccess) return 0;
+  return nb;
+}
+
+hipError_t launch_cpqr(const LevelBox* boxes, int nbox, int G, double tol, int extra, int* perm,
+                       int* k_out, int* kx_out, int* err, int max_m, int max_n, hipStream_t s) {
+  if (nbox == 0) return hipSuccess;
+  const size_t lds = cpqr_lds_bytes(max_m, max_n);
+  hipLaunchKernelGGL(k_zero_bars, dim3(blocks_for(nbox, kBlock)), dim3(kBlock), 0, s, boxes, nbox, err);
+  if (G <= 1) {
+    hipLaunchKernelGGL(k_cpqr, dim3(nbox), dim3(kQRThreads), lds, s, boxes, 1, tol, extra, perm,
+                       k_out, kx_out, err);
+    return hipGetLastError();
+  }
+  void* args[] = {(void*)&boxes, (void*)&G, (void*)&tol, (void*)&extra, (void*)&perm,
+                  (void*)&k_out, (void*)&kx_out, (void*)&err};
+  return hipLaunchCooperativeKernel((const void*)k_cpqr, dim3(nbox * G), dim3(kQRThreads), args,
+                                    (unsigned)lds, s);
 }
 
 void launch_assemble_abb(const LevelBox* boxes, int nbox, int max_n, const int* dofs,
@@ -1152,12 +1549,24 @@ void launch_assemble_abb(const LevelBox* boxes, int nbox, int max_n, const int* 
   hipLaunchKernelGGL(k_assemble_abb, grid, dim3(kBlock), 0, s, boxes, dofs, perm, src, g, lam);
 }
 
-void launch_eliminate(const LevelBox* boxes, int nbox, int* k_io, const int* kx,
-                      double rcond_min, int* status, int max_n, hipStream_t s) {
-  if (nbox == 0) return;
-  const size_t shm = (size_t)(max_n + 1) * sizeof(double);
-  hipLaunchKernelGGL(k_eliminate, dim3(nbox), dim3(kBlock), shm, s, boxes, k_io, kx, rcond_min,
-                     status);
+int eliminate_blocks_per_cu() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eliminate, kBlock, 0) != hipSuccess) return 0;
+  return nb;
+}
+
+hipError_t launch_eliminate(const LevelBox* boxes, int nbox, int G, int* k_io, const int* kx,
+                            double rcond_min, int* status, int* err, hipStream_t s) {
+  if (nbox == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_bars, dim3(blocks_for(nbox, kBlock)), dim3(kBlock), 0, s, boxes, nbox, err);
+  if (G <= 1) {
+    hipLaunchKernelGGL(k_eliminate, dim3(nbox), dim3(kBlock), 0, s, boxes, 1, k_io, kx, rcond_min,
+                       status, err);
+    return hipGetLastError();
+  }
+  void* args[] = {(void*)&boxes, (void*)&G, (void*)&k_io, (void*)&kx, (void*)&rcond_min,
+                  (void*)&status, (void*)&err};
+  return hipLaunchCooperativeKernel((const void*)k_eliminate, dim3(nbox * G), dim3(kBlock), args, 0, s);
 }
 
 void launch_gj_inverse(double* A, int n, int lda, double* Ainv, double* work,
