@@ -62,15 +62,15 @@ typedef struct {
   double proxy_ratio;  /* proxy radius = proxy_ratio * box side                                  */
   double rcond_min;    /* X_RR guard: move a pivot from R to S while rcond_1(X_RR) < rcond_min  */
   int precision;       /* 0 = float64 throughout; 1 = mixed (float32 bulk, float64 refinement)   */
-  double refine_tol;   /* mixed: target max-column relative residual of the float64 operator  */
-  int refine_max;      /* mixed: maximum refinement iterations                                  */
+  double refine_tol;   /* refinement target: max-column ||[f;0] - A x||_2 / ||f||_2             */
+  int refine_max;      /* 0: direct solve; > 0: at most this many refinement iterations        */
   int has_root;        /* 1: use root[] as the fixed root square; 0: bounding square of nodes */
   double root[3];      /* fixed root square: centre x, centre y, side                           */
 } rs_params;
 
 /* Fill *p with the defaults: lambda -0.5, tol 1e-10, leaf 64, 64 proxy points
- * at 1.5 x side, rcond_min 1e-12, float64, refine_tol 1e-8, refine_max 20,
- * no fixed root. */
+ * at 1.5 x side, rcond_min 1e-12, float64, refine_tol 1e-8, refine_max 0
+ * (direct solve), no fixed root. */
 void rs_default_params(rs_params* p);
 
 /* Build the adaptive quadtree (Section 2.3) for a boundary discretisation and
@@ -99,10 +99,14 @@ rs_status rs_factor(rs_ctx* ctx);
  *   x             host, (2N + 3p) x nrhs, column-major, leading dimension 2N + 3p
  *   rel_residual  host [nrhs] or NULL: ||[f;0] - A x||_2 / ||f||_2 per column,
  *                 with A applied exactly in float64 on the device
- * In mixed precision (precision = 1) the float32 factorization is the inner
- * solver of float64 iterative refinement; RS_ERR_NOCONV means refine_max
- * iterations did not reach refine_tol, x then holds the last iterate and
- * rel_residual (if given) its residuals. */
+ * With refine_max > 0 the solve is iterative refinement: the residual
+ * [f;0] - A x is evaluated exactly in float64 on the device (O(N^2) pairs)
+ * and the factorization (float64, or float32 when precision = 1) is the inner
+ * solver, until every column reaches refine_tol; RS_ERR_NOCONV means
+ * refine_max iterations did not reach it, x then holds the last iterate and
+ * rel_residual (if given) its residuals.  precision = 1 keeps the pivoted QR,
+ * X_RR^{-1} and the root system in float64 and applies T, E, F, X_RR^{-1}
+ * in float32. */
 rs_status rs_solve(rs_ctx* ctx, int nrhs, const double* f, double* x, double* rel_residual);
 
 /* As rs_solve, with f and x device pointers (same layouts) used on the

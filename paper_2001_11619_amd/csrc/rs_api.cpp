@@ -94,6 +94,10 @@ struct BoxFac {
   double* Xinv = nullptr;
   double* Xss = nullptr;
   double* W = nullptr;
+  float* Tf = nullptr;        // float copies (mixed precision)
+  float* Ef = nullptr;
+  float* Ff = nullptr;
+  float* Xinvf = nullptr;
   int arena = -1;             // id of the device arena holding T, E, F, Xinv, Xss
   int rank0 = 0;
   std::vector<int> fint;      // near field F_int used by the compression
@@ -147,7 +151,7 @@ struct rs_ctx {
   // root
   std::vector<int> I0;
   DevBuf d_I0, d_X0, d_Z, d_Zinv, d_gjwork, d_gjiwork, d_rcond, d_rstatus, d_root_box;
-  DevBuf d_H, d_Hh, d_Ph, d_Gpart, d_G, d_bscr, d_W;
+  DevBuf d_H, d_Hh, d_Ph, d_Phf, d_Gpart, d_G, d_bscr, d_W, d_Wf;
   int nz = 0;
   // solve metadata
   std::vector<std::vector<SolveBox>> sboxes;   // per level
@@ -157,7 +161,9 @@ struct rs_ctx {
   int n_solve_boxes = 0;
   int all_maxr = 0;
   // solve work
-  DevBuf d_f, d_c, d_v, d_sol, d_parts, d_rhs2, d_xout, d_res;
+  DevBuf d_f, d_c, d_cf, d_v, d_sol, d_parts, d_rhs2, d_xout, d_res, d_frows, d_xs, d_r, d_dx,
+      d_ys, d_norms;
+  std::vector<double> last_res;   // relative residual per column of the last refined solve
 
   rs_stats stats{};
 
@@ -514,6 +520,7 @@ void factor_level(rs_ctx* c, int l, const std::vector<int>& ids, const std::vect
     const size_t n2 = (size_t)x.n * x.n;
     totN2 += n2;
     totArena += 3 * (n2 / 4 + x.n) + 2 * n2;
+    if (P.precision == 1) totArena += (3 * (n2 / 4 + x.n) + n2 + 1) / 2 + 4;
     max_m = std::max(max_m, x.m);
     max_n = std::max(max_n, x.n);
     lb.push_back(x);
@@ -579,12 +586,27 @@ void factor_level(rs_ctx* c, int l, const std::vector<int>& ids, const std::vect
       pa += n2;
       x.Xss = pa;
       pa += n2;
+      if (P.precision == 1) {
+        float* pf = reinterpret_cast<float*>(pa);
+        x.Tf = pf;
+        pf += kr;
+        x.Ef = pf;
+        pf += kr;
+        x.Ff = pf;
+        pf += kr;
+        x.Xinvf = pf;
+        pa += (3 * kr + n2 + 1) / 2 + 4;
+      }
       BoxFac& f = c->fac[ids[sel[i]]];
       f.T = x.T;
       f.E = x.E;
       f.F = x.F;
       f.Xinv = x.Xinv;
       f.Xss = x.Xss;
+      f.Tf = x.Tf;
+      f.Ef = x.Ef;
+      f.Ff = x.Ff;
+      f.Xinvf = x.Xinvf;
     }
   }
   {
@@ -637,6 +659,7 @@ void factor_level(rs_ctx* c, int l, const std::vector<int>& ids, const std::vect
     KTimer kt_(c, "eliminate");
     HIP_CHECK(launch_eliminate(dlb, nb, Ge, c->ws_k.as<int>(), c->ws_kx.as<int>(), P.rcond_min,
                                c->ws_status.as<int>(), c->ws_err.as<int>() + 1, s));
+    if (P.precision == 1) launch_factor_to_float(dlb, nb, c->ws_k.as<int>(), s);
   }
   HIP_CHECK(hipGetLastError());
   std::vector<int> perm(dofs.size()), kk(nb), st(nb);
@@ -698,6 +721,11 @@ void build_solve_meta(rs_ctx* c) {
     sb.F = f.F;
     sb.Xinv = f.Xinv;
     sb.W = nullptr;
+    sb.Tf = f.Tf;
+    sb.Ef = f.Ef;
+    sb.Ff = f.Ff;
+    sb.Xinvf = f.Xinvf;
+    sb.Wf = nullptr;
     for (int i = 0; i < f.k; ++i) sidx.push_back(f.I[f.perm[i]]);
     for (int i = f.k; i < f.n; ++i) ridx.push_back(f.I[f.perm[i]]);
     c->sboxes[f.level].push_back(sb);
@@ -715,10 +743,19 @@ void build_solve_meta(rs_ctx* c) {
       for (auto& sb : lv) totW += (size_t)sb.r * p3;
     c->d_W.ensure(std::max<size_t>(totW, 1) * sizeof(double));
     double* pw = c->d_W.as<double>();
+    float* pwf = nullptr;
+    if (c->prm.precision == 1) {
+      c->d_Wf.ensure(std::max<size_t>(totW, 1) * sizeof(float));
+      pwf = c->d_Wf.as<float>();
+    }
     for (auto& lv : c->sboxes)
       for (auto& sb : lv) {
         sb.W = pw;
         pw += (size_t)sb.r * p3;
+        if (pwf) {
+          sb.Wf = pwf;
+          pwf += (size_t)sb.r * p3;
+        }
       }
   }
   std::vector<SolveBox> flat;
@@ -738,7 +775,8 @@ const SolveBox* level_sboxes(const rs_ctx* c, int l) {
 }
 int level_count(const rs_ctx* c, int l) { return (int)(c->sbox_off[l + 1] - c->sbox_off[l]); }
 
-void sweep_all(rs_ctx* c, double* buf, int ncols, int mode) {
+template <typename T>
+void sweep_all(rs_ctx* c, T* buf, int ncols, int mode) {
   const int L = c->L;
   KTimer kt_(c, mode == 0 ? "sweep_U" : (mode == 1 ? "sweep_PsiV" : "sweep_V"));
   if (mode == 2) {
@@ -814,6 +852,11 @@ void factor_root(rs_ctx* c) {
                           scr_stride, s);
       }
     }
+    if (c->prm.precision == 1) {
+      for (int l = c->L; l >= 1; --l) launch_w_to_float(level_sboxes(c, l), level_count(c, l), p3, s);
+      c->d_Phf.ensure(hn * sizeof(float));
+      launch_to_float(c->d_Ph.as<double>(), (long long)hn, c->d_Phf.as<float>(), s);
+    }
     c->d_G.ensure((size_t)p3 * p3 * sizeof(double));
     launch_sum_parts(c->d_Gpart.as<double>(), nsb, (long long)p3 * p3, p3 * p3, 1.0,
                      c->d_G.as<double>(), s);
@@ -886,18 +929,28 @@ void do_factor(rs_ctx* c) {
   c->stats.ms_factor = 1e3 * seconds_since(t0);
 }
 
-// c (rows, ncols) holds U-transformed data on entry of the root stage.
-void solve_rows(rs_ctx* c, double* cbuf, int ncols) {
+template <typename T>
+const T* ph_of(const rs_ctx* c);
+template <>
+const double* ph_of<double>(const rs_ctx* c) { return c->d_Ph.as<double>(); }
+template <>
+const float* ph_of<float>(const rs_ctx* c) { return c->d_Phf.as<float>(); }
+
+// Apply the factored inverse in place: cbuf (rows layout, ncols columns) holds
+// the first 2N rows of the right-hand side on entry and [mu; lambda] (2N + 3p
+// rows) on exit.  rbot (nullable, float64, 3p x ncols) is the right-hand side
+// of the border rows (zero when null).
+template <typename T>
+void solve_rows(rs_ctx* c, T* cbuf, int ncols, const double* rbot) {
   hipStream_t s = c->stream;
   const int p3 = 3 * c->p;
   const int n0 = (int)c->I0.size();
-  sweep_all(c, cbuf, ncols, 0);
-  for (int l = c->L; l >= 1; --l)
-    {
-      KTimer kt_(c, "diag");
-      launch_diag(level_sboxes(c, l), level_count(c, l), c->d_ridx.as<int>(), cbuf, ncols,
-                  c->lvl_maxr[l], s);
-    }
+  sweep_all<T>(c, cbuf, ncols, 0);
+  for (int l = c->L; l >= 1; --l) {
+    KTimer kt_(c, "diag");
+    launch_diag<T>(level_sboxes(c, l), level_count(c, l), c->d_ridx.as<int>(), cbuf, ncols,
+                   c->lvl_maxr[l], s);
+  }
   const int nz = c->nz;
   c->d_v.ensure(std::max<size_t>((size_t)nz * ncols, 1) * sizeof(double));
   c->d_sol.ensure(std::max<size_t>((size_t)nz * ncols, 1) * sizeof(double));
@@ -905,49 +958,126 @@ void solve_rows(rs_ctx* c, double* cbuf, int ncols) {
   if (p3) {
     const int nsb = c->n_solve_boxes;
     c->d_parts.ensure(std::max<size_t>((size_t)nsb * p3 * ncols, 1) * sizeof(double));
-    for (int l = c->L; l >= 1; --l)
-      {
-        KTimer kt_(c, "border_rhs");
-        launch_border_rhs(level_sboxes(c, l), level_count(c, l), c->d_ridx.as<int>(),
-                          c->d_Ph.as<double>(), p3, cbuf, ncols, c->d_parts.as<double>(), s);
-      }
+    for (int l = c->L; l >= 1; --l) {
+      KTimer kt_(c, "border_rhs");
+      launch_border_rhs<T>(level_sboxes(c, l), level_count(c, l), c->d_ridx.as<int>(), ph_of<T>(c),
+                           p3, cbuf, ncols, c->d_parts.as<double>(), s);
+    }
     c->d_rhs2.ensure((size_t)p3 * ncols * sizeof(double));
     launch_sum_parts(c->d_parts.as<double>(), nsb, (long long)p3 * ncols, p3 * ncols, -1.0,
                      c->d_rhs2.as<double>(), s);
+    if (rbot) launch_accumulate(rbot, (long long)p3 * ncols, c->d_rhs2.as<double>(), s);
     rhs2 = c->d_rhs2.as<double>();
   }
   if (nz > 0) {
-    launch_root_gather(cbuf, ncols, c->d_I0.as<int>(), n0, rhs2, p3, c->d_v.as<double>(), s);
+    launch_root_gather<T>(cbuf, ncols, c->d_I0.as<int>(), n0, rhs2, p3, c->d_v.as<double>(), s);
     {
       KTimer kt_(c, "root_apply");
       launch_dense_apply(c->d_Zinv.as<double>(), nz, c->d_v.as<double>(), ncols,
                          c->d_sol.as<double>(), s);
     }
-    if (n0) launch_root_scatter(c->d_sol.as<double>(), ncols, c->d_I0.as<int>(), n0, cbuf, s);
+    if (n0) launch_root_scatter<T>(c->d_sol.as<double>(), ncols, c->d_I0.as<int>(), n0, cbuf, s);
   }
   if (p3) {
     const double* lam = c->d_sol.as<double>() + (size_t)n0 * ncols;
-    for (int l = c->L; l >= 1; --l)
-      {
-        KTimer kt_(c, "border_fix");
-        launch_border_fix(level_sboxes(c, l), level_count(c, l), c->d_ridx.as<int>(), p3, lam, cbuf,
-                          ncols, s);
-      }
-    // lambda rows follow the 2N density rows in cbuf
-    HIP_CHECK(hipMemcpyAsync(cbuf + (size_t)2 * c->N * ncols, lam, (size_t)p3 * ncols * sizeof(double),
-                             hipMemcpyDeviceToDevice, s));
+    for (int l = c->L; l >= 1; --l) {
+      KTimer kt_(c, "border_fix");
+      launch_border_fix<T>(level_sboxes(c, l), level_count(c, l), c->d_ridx.as<int>(), p3, lam,
+                           cbuf, ncols, s);
+    }
+    // lambda rows follow the 2N density rows
+    T* dst = cbuf + (size_t)2 * c->N * ncols;
+    if (sizeof(T) == sizeof(double))
+      HIP_CHECK(hipMemcpyAsync(dst, lam, (size_t)p3 * ncols * sizeof(double), hipMemcpyDeviceToDevice, s));
+    else
+      launch_to_float(lam, (long long)p3 * ncols, reinterpret_cast<float*>(dst), s);
   }
-  sweep_all(c, cbuf, ncols, 2);
+  sweep_all<T>(c, cbuf, ncols, 2);
 }
 
-void solve_device(rs_ctx* c, int nrhs, const double* f_dev, double* x_dev) {
+// out (float64 rows, 2N+3p) = factored inverse applied to rhs (float64 rows,
+// 2N + 3p; the border rows are used as their right-hand side).
+void apply_inverse(rs_ctx* c, const double* rhs, int ncols, double* out) {
+  const size_t n2 = 2 * (size_t)c->N;
+  const size_t ns = n2 + 3 * (size_t)c->p;
+  const double* rbot = c->p ? rhs + n2 * ncols : nullptr;
+  if (c->prm.precision == 0) {
+    HIP_CHECK(hipMemcpyAsync(out, rhs, n2 * ncols * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    solve_rows<double>(c, out, ncols, rbot);
+  } else {
+    c->d_cf.ensure(ns * ncols * sizeof(float));
+    float* cf = c->d_cf.as<float>();
+    launch_to_float(rhs, (long long)(n2 * ncols), cf, c->stream);
+    solve_rows<float>(c, cf, ncols, rbot);
+    launch_to_double(cf, (long long)(ns * ncols), out, c->stream);
+  }
+}
+
+void apply_device_rows(rs_ctx* c, const double* xrows, int ncols, double* yrows);
+
+// Solve with f_dev (2N x nrhs, column-major) into x_dev ((2N+3p) x nrhs,
+// column-major).  With refine_max > 0: iterative refinement, the residual
+// [f; 0] - A x evaluated exactly in float64 and the factored inverse (float64
+// or float32) as the inner solver, until max_q ||r_q|| / ||f_q|| <= refine_tol.
+// Returns false if refinement did not reach the tolerance.
+bool solve_device(rs_ctx* c, int nrhs, const double* f_dev, double* x_dev) {
   const int n2 = 2 * c->N;
   const int ns = n2 + 3 * c->p;
-  c->d_c.ensure((size_t)ns * nrhs * sizeof(double));
-  launch_to_rows(f_dev, n2, n2, nrhs, c->d_c.as<double>(), c->stream);
-  solve_rows(c, c->d_c.as<double>(), nrhs);
-  launch_from_rows(c->d_c.as<double>(), ns, nrhs, x_dev, ns, c->stream);
+  hipStream_t s = c->stream;
+  const size_t rows = (size_t)ns * nrhs;
+  c->d_frows.ensure((size_t)n2 * nrhs * sizeof(double));
+  c->d_xs.ensure(rows * sizeof(double));
+  launch_to_rows(f_dev, n2, n2, nrhs, c->d_frows.as<double>(), s);
+  c->last_res.clear();
+  c->stats.refine_iters = 0;
+  if (c->prm.refine_max <= 0) {
+    c->d_r.ensure(rows * sizeof(double));
+    // right-hand side rows [f; 0]
+    launch_fill(c->d_r.as<double>(), (long long)rows, 0.0, s);
+    HIP_CHECK(hipMemcpyAsync(c->d_r.p, c->d_frows.p, (size_t)n2 * nrhs * sizeof(double),
+                             hipMemcpyDeviceToDevice, s));
+    apply_inverse(c, c->d_r.as<double>(), nrhs, c->d_xs.as<double>());
+    launch_from_rows(c->d_xs.as<double>(), ns, nrhs, x_dev, ns, s);
+    HIP_CHECK(hipGetLastError());
+    return true;
+  }
+  c->d_r.ensure(rows * sizeof(double));
+  c->d_dx.ensure(rows * sizeof(double));
+  c->d_ys.ensure(rows * sizeof(double));
+  c->d_norms.ensure(2 * (size_t)nrhs * sizeof(double));
+  double* x = c->d_xs.as<double>();
+  double* r = c->d_r.as<double>();
+  double* dx = c->d_dx.as<double>();
+  double* y = c->d_ys.as<double>();
+  double* colsq = c->d_norms.as<double>();
+  double* fsq = colsq + nrhs;
+  launch_fill(x, (long long)rows, 0.0, s);
+  launch_residual(c->d_frows.as<double>(), n2, x, ns, nrhs, r, colsq, fsq, s);   // r = [f; 0]
+  std::vector<double> nrm(2 * nrhs);
+  bool conv = false;
+  for (int it = 0; it < c->prm.refine_max; ++it) {
+    apply_inverse(c, r, nrhs, dx);
+    launch_accumulate(dx, (long long)rows, x, s);
+    apply_device_rows(c, x, nrhs, y);
+    launch_residual(c->d_frows.as<double>(), n2, y, ns, nrhs, r, colsq, fsq, s);
+    HIP_CHECK(hipMemcpyAsync(nrm.data(), colsq, 2 * nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    c->stats.refine_iters = it + 1;
+    double worst = 0.0;
+    c->last_res.assign(nrhs, 0.0);
+    for (int q = 0; q < nrhs; ++q) {
+      const double fq = nrm[nrhs + q] > 0 ? nrm[nrhs + q] : 1.0;
+      c->last_res[q] = std::sqrt(nrm[q] / fq);
+      worst = std::max(worst, c->last_res[q]);
+    }
+    if (worst <= c->prm.refine_tol) {
+      conv = true;
+      break;
+    }
+  }
+  launch_from_rows(x, ns, nrhs, x_dev, ns, s);
   HIP_CHECK(hipGetLastError());
+  return conv;
 }
 
 void apply_device_rows(rs_ctx* c, const double* xrows, int ncols, double* yrows) {
@@ -1024,7 +1154,7 @@ void rs_default_params(rs_params* p) {
   p->rcond_min = 1e-12;
   p->precision = 0;
   p->refine_tol = 1e-8;
-  p->refine_max = 20;
+  p->refine_max = 0;
   p->has_root = 0;
 }
 
@@ -1130,10 +1260,11 @@ rs_status rs_solve_dev(rs_ctx* c, int nrhs, const double* f_dev, double* x_dev) 
     if (nrhs <= 0 || !f_dev || !x_dev) throw RsError{RS_ERR_ARG, "bad nrhs or NULL pointer"};
     HIP_CHECK(hipSetDevice(c->device));
     auto t0 = std::chrono::steady_clock::now();
-    solve_device(c, nrhs, f_dev, x_dev);
+    const bool conv = solve_device(c, nrhs, f_dev, x_dev);
     HIP_CHECK(hipStreamSynchronize(c->stream));
     c->stats.ms_solve = 1e3 * seconds_since(t0);
     resolve_timers(c);
+    if (!conv) throw RsError{RS_ERR_NOCONV, "refinement did not reach refine_tol"};
     return RS_OK;
   } catch (const RsError& e) {
     return fail(c, e);
@@ -1149,39 +1280,39 @@ rs_status rs_solve(rs_ctx* c, int nrhs, const double* f, double* x, double* rel_
     const size_t ns = n2 + 3 * (size_t)c->p;
     if (!finite_all(f, n2 * nrhs)) throw RsError{RS_ERR_ARG, "non-finite right-hand side"};
     HIP_CHECK(hipSetDevice(c->device));
+    hipStream_t s = c->stream;
     auto t0 = std::chrono::steady_clock::now();
     c->d_f.ensure(n2 * nrhs * sizeof(double));
     c->d_xout.ensure(ns * nrhs * sizeof(double));
-    HIP_CHECK(hipMemcpyAsync(c->d_f.p, f, n2 * nrhs * sizeof(double), hipMemcpyHostToDevice, c->stream));
-    solve_device(c, nrhs, c->d_f.as<double>(), c->d_xout.as<double>());
+    HIP_CHECK(hipMemcpyAsync(c->d_f.p, f, n2 * nrhs * sizeof(double), hipMemcpyHostToDevice, s));
+    const bool conv = solve_device(c, nrhs, c->d_f.as<double>(), c->d_xout.as<double>());
     std::vector<double> xo(ns * nrhs);
-    HIP_CHECK(hipMemcpyAsync(xo.data(), c->d_xout.p, xo.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    HIP_CHECK(hipStreamSynchronize(c->stream));
+    HIP_CHECK(hipMemcpyAsync(xo.data(), c->d_xout.p, xo.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
     c->stats.ms_solve = 1e3 * seconds_since(t0);
     resolve_timers(c);
     if (rel_residual) {
-      // residual rows: y = A x - [f; 0]
-      c->d_res.ensure(ns * nrhs * sizeof(double));
-      c->d_c.ensure(ns * nrhs * sizeof(double));
-      double* xr = c->d_c.as<double>();
-      launch_to_rows(c->d_xout.as<double>(), (int)ns, (int)ns, nrhs, xr, c->stream);
-      apply_device_rows(c, xr, nrhs, c->d_res.as<double>());
-      std::vector<double> yo(ns * nrhs);
-      HIP_CHECK(hipMemcpyAsync(yo.data(), c->d_res.p, yo.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-      HIP_CHECK(hipStreamSynchronize(c->stream));
-      resolve_timers(c);
-      for (int q = 0; q < nrhs; ++q) {
-        double rr = 0, ff = 0;
-        for (size_t i = 0; i < ns; ++i) {
-          const double fi = i < n2 ? f[q * n2 + i] : 0.0;
-          const double d = yo[i * nrhs + q] - fi;
-          rr += d * d;
-          ff += fi * fi;
-        }
-        rel_residual[q] = std::sqrt(rr) / std::sqrt(ff > 0 ? ff : 1.0);
+      if ((int)c->last_res.size() == nrhs) {
+        std::copy(c->last_res.begin(), c->last_res.end(), rel_residual);
+      } else {
+        // residual of the direct solve: x rows are in d_xs
+        c->d_ys.ensure(ns * nrhs * sizeof(double));
+        c->d_r.ensure(ns * nrhs * sizeof(double));
+        c->d_norms.ensure(2 * (size_t)nrhs * sizeof(double));
+        apply_device_rows(c, c->d_xs.as<double>(), nrhs, c->d_ys.as<double>());
+        double* colsq = c->d_norms.as<double>();
+        launch_residual(c->d_frows.as<double>(), (int)n2, c->d_ys.as<double>(), (int)ns, nrhs,
+                        c->d_r.as<double>(), colsq, colsq + nrhs, s);
+        std::vector<double> nrm(2 * nrhs);
+        HIP_CHECK(hipMemcpyAsync(nrm.data(), colsq, nrm.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        resolve_timers(c);
+        for (int q = 0; q < nrhs; ++q)
+          rel_residual[q] = std::sqrt(nrm[q] / (nrm[nrhs + q] > 0 ? nrm[nrhs + q] : 1.0));
       }
     }
     std::memcpy(x, xo.data(), xo.size() * sizeof(double));
+    if (!conv) throw RsError{RS_ERR_NOCONV, "refinement did not reach refine_tol"};
     return RS_OK;
   } catch (const RsError& e) {
     return fail(c, e);

@@ -38,6 +38,10 @@ struct LevelBox {
   double* F;      // r x k
   double* Xinv;   // r x r  (capacity n^2)
   double* Xss;    // k x k  (capacity n^2)
+  float* Tf;      // float copies for the mixed-precision solve (or null)
+  float* Ef;
+  float* Ff;
+  float* Xinvf;
   // cooperation of several workgroups on one box (pivoted QR)
   unsigned* bar;  // box barrier counter
   double* hh;     // beta, tau of the current step
@@ -66,6 +70,11 @@ struct SolveBox {
   const double* F;
   const double* Xinv;
   double* W;             // r x 3p: X_RR^{-1} (U H)_R (bordered root only)
+  const float* Tf;       // float copies (mixed precision)
+  const float* Ef;
+  const float* Ff;
+  const float* Xinvf;
+  float* Wf;
 };
 
 constexpr int kBlock = 256;
@@ -88,10 +97,12 @@ void launch_gj_inverse(double* A, int n, int lda, double* Ainv, double* work,
                        double* rcond_out, int* status, hipStream_t s);
 void launch_gj_blocked(double* A, int n, double* Ainv, double* work, int* iwork, int* status,
                        hipStream_t s);
-void launch_sweep(const SolveBox* boxes, int nbox, const int* sidx, const int* ridx,
-                  double* c, int ncols, int mode, int max_n, hipStream_t s);
-void launch_diag(const SolveBox* boxes, int nbox, const int* ridx, double* c, int ncols,
-                 int max_r, hipStream_t s);
+template <typename T>
+void launch_sweep(const SolveBox* boxes, int nbox, const int* sidx, const int* ridx, T* c,
+                  int ncols, int mode, int max_n, hipStream_t s);
+template <typename T>
+void launch_diag(const SolveBox* boxes, int nbox, const int* ridx, T* c, int ncols, int max_r,
+                 hipStream_t s);
 void launch_assemble_H(Geo g, const double* hole_xy, int p, const int* curve_id,
                        double* H, double* Psi, hipStream_t s);
 void launch_border_box(const SolveBox* boxes, int nbox, const int* ridx, const double* Hh,
@@ -99,18 +110,30 @@ void launch_border_box(const SolveBox* boxes, int nbox, const int* ridx, const d
                        long long scr_stride, hipStream_t s);
 void launch_sum_parts(const double* parts, int nparts, long long stride, int len,
                       double scale, double* out, hipStream_t s);
-void launch_border_rhs(const SolveBox* boxes, int nbox, const int* ridx, const double* Ph,
-                       int p3, const double* c, int ncols, double* parts, hipStream_t s);
-void launch_border_fix(const SolveBox* boxes, int nbox, const int* ridx, int p3,
-                       const double* lam, double* c, int ncols, hipStream_t s);
+template <typename T>
+void launch_border_rhs(const SolveBox* boxes, int nbox, const int* ridx, const T* Ph, int p3,
+                       const T* c, int ncols, double* parts, hipStream_t s);
+template <typename T>
+void launch_border_fix(const SolveBox* boxes, int nbox, const int* ridx, int p3, const double* lam,
+                       T* c, int ncols, hipStream_t s);
 void launch_assemble_Z(const double* X0, int n0, const double* Hh, const double* Ph,
                        const int* I0, int p3, const double* G, double* Z, hipStream_t s);
-void launch_root_gather(const double* c, int ncols, const int* I0, int n0,
-                        const double* rhs2, int p3, double* v, hipStream_t s);
+template <typename T>
+void launch_root_gather(const T* c, int ncols, const int* I0, int n0, const double* rhs2, int p3,
+                        double* v, hipStream_t s);
 void launch_dense_apply(const double* Zinv, int nz, const double* v, int ncols, double* out,
                         hipStream_t s);
-void launch_root_scatter(const double* sol, int ncols, const int* I0, int n0, double* c,
-                         hipStream_t s);
+template <typename T>
+void launch_root_scatter(const double* sol, int ncols, const int* I0, int n0, T* c, hipStream_t s);
+void launch_to_float(const double* x, long long n, float* y, hipStream_t s);
+void launch_to_double(const float* x, long long n, double* y, hipStream_t s);
+void launch_fill(double* x, long long n, double v, hipStream_t s);
+void launch_accumulate(const double* d, long long n, double* x, hipStream_t s);
+void launch_accumulate(const float* d, long long n, double* x, hipStream_t s);
+void launch_residual(const double* f, int nf, const double* y, int nrows, int ncols, double* r,
+                     double* colsq, double* fsq, hipStream_t s);
+void launch_factor_to_float(const LevelBox* boxes, int nbox, const int* k_final, hipStream_t s);
+void launch_w_to_float(const SolveBox* boxes, int nbox, int p3, hipStream_t s);
 void launch_to_rows(const double* f, int ld, int nrows, int ncols, double* c, hipStream_t s);
 void launch_from_rows(const double* c, int nrows, int ncols, double* x, int ld, hipStream_t s);
 void launch_apply_operator(Geo g, const int* curve_id, const double* hole_xy, int p,

@@ -1124,61 +1124,83 @@ __global__ void k_iota(int* v, int n, int* zero) {
 
 // ---- solve kernels -----------------------------------------------------------
 
+// Factor blocks of a box in the solve's working precision.
+template <typename T> struct Fac;
+template <> struct Fac<double> {
+  static __device__ const double* t(const SolveBox& b) { return b.T; }
+  static __device__ const double* e(const SolveBox& b) { return b.E; }
+  static __device__ const double* f(const SolveBox& b) { return b.F; }
+  static __device__ const double* xi(const SolveBox& b) { return b.Xinv; }
+  static __device__ const double* w(const SolveBox& b) { return b.W; }
+};
+template <> struct Fac<float> {
+  static __device__ const float* t(const SolveBox& b) { return b.Tf; }
+  static __device__ const float* e(const SolveBox& b) { return b.Ef; }
+  static __device__ const float* f(const SolveBox& b) { return b.Ff; }
+  static __device__ const float* xi(const SolveBox& b) { return b.Xinvf; }
+  static __device__ const float* w(const SolveBox& b) { return b.Wf; }
+};
+
 // mode 0: U   c_R -= T^T c_S ; c_S -= E c_R
 // mode 1: Psi^T V rows (columns of Psi)   c_R -= T^T c_S ; c_S -= F^T c_R
 // mode 2: V   c_R -= F c_S ; c_S -= T c_R
+template <typename T>
 __global__ __launch_bounds__(kBlock) void k_sweep(const SolveBox* boxes, const int* sidx,
-                                                  const int* ridx, double* c, int ncols,
-                                                  int mode, int kNC) {
-  extern __shared__ double smem[];
+                                                  const int* ridx, T* c, int ncols, int mode,
+                                                  int kNC) {
+  extern __shared__ double smem_d[];
+  T* smem = reinterpret_cast<T*>(smem_d);
   const SolveBox& B = boxes[blockIdx.x];
   const int k = B.k, r = B.r;
   if (k == 0 || r == 0) return;
+  const T* Tm = Fac<T>::t(B);
+  const T* Em = Fac<T>::e(B);
+  const T* Fm = Fac<T>::f(B);
   const int q0 = blockIdx.y * kNC;
   const int nq = min(kNC, ncols - q0);
-  double* cs = smem;
-  double* cr = smem + (size_t)k * kNC;
+  T* cs = smem;
+  T* cr = smem + (size_t)k * kNC;
   const int* S = sidx + B.s_off;
   const int* R = ridx + B.r_off;
   const int tid = threadIdx.x;
   for (int t = tid; t < k * kNC; t += kBlock) {
     const int s = t / kNC, q = t % kNC;
-    cs[t] = q < nq ? c[(size_t)S[s] * ncols + q0 + q] : 0.0;
+    cs[t] = q < nq ? c[(size_t)S[s] * ncols + q0 + q] : T(0);
   }
   for (int t = tid; t < r * kNC; t += kBlock) {
     const int i = t / kNC, q = t % kNC;
-    cr[t] = q < nq ? c[(size_t)R[i] * ncols + q0 + q] : 0.0;
+    cr[t] = q < nq ? c[(size_t)R[i] * ncols + q0 + q] : T(0);
   }
   __syncthreads();
   if (mode != 2) {
     for (int t = tid; t < r * kNC; t += kBlock) {
       const int i = t / kNC, q = t % kNC;
-      double acc = 0.0;
-      for (int s = 0; s < k; ++s) acc += B.T[(size_t)s * r + i] * cs[s * kNC + q];
+      T acc = 0;
+      for (int s = 0; s < k; ++s) acc += Tm[(size_t)s * r + i] * cs[s * kNC + q];
       cr[t] -= acc;
     }
     __syncthreads();
     for (int t = tid; t < k * kNC; t += kBlock) {
       const int s = t / kNC, q = t % kNC;
-      double acc = 0.0;
+      T acc = 0;
       if (mode == 0)
-        for (int i = 0; i < r; ++i) acc += B.E[(size_t)s * r + i] * cr[i * kNC + q];
+        for (int i = 0; i < r; ++i) acc += Em[(size_t)s * r + i] * cr[i * kNC + q];
       else
-        for (int i = 0; i < r; ++i) acc += B.F[(size_t)i * k + s] * cr[i * kNC + q];
+        for (int i = 0; i < r; ++i) acc += Fm[(size_t)i * k + s] * cr[i * kNC + q];
       cs[t] -= acc;
     }
   } else {
     for (int t = tid; t < r * kNC; t += kBlock) {
       const int i = t / kNC, q = t % kNC;
-      double acc = 0.0;
-      for (int s = 0; s < k; ++s) acc += B.F[(size_t)i * k + s] * cs[s * kNC + q];
+      T acc = 0;
+      for (int s = 0; s < k; ++s) acc += Fm[(size_t)i * k + s] * cs[s * kNC + q];
       cr[t] -= acc;
     }
     __syncthreads();
     for (int t = tid; t < k * kNC; t += kBlock) {
       const int s = t / kNC, q = t % kNC;
-      double acc = 0.0;
-      for (int i = 0; i < r; ++i) acc += B.T[(size_t)s * r + i] * cr[i * kNC + q];
+      T acc = 0;
+      for (int i = 0; i < r; ++i) acc += Tm[(size_t)s * r + i] * cr[i * kNC + q];
       cs[t] -= acc;
     }
   }
@@ -1194,26 +1216,29 @@ __global__ __launch_bounds__(kBlock) void k_sweep(const SolveBox* boxes, const i
 }
 
 // c_R <- X_RR^{-1} c_R
-__global__ __launch_bounds__(kBlock) void k_diag(const SolveBox* boxes, const int* ridx,
-                                                 double* c, int ncols, int kNC) {
-  extern __shared__ double smem[];
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_diag(const SolveBox* boxes, const int* ridx, T* c,
+                                                 int ncols, int kNC) {
+  extern __shared__ double smem_d[];
+  T* smem = reinterpret_cast<T*>(smem_d);
   const SolveBox& B = boxes[blockIdx.x];
   const int r = B.r;
   if (r == 0) return;
+  const T* Xi = Fac<T>::xi(B);
   const int q0 = blockIdx.y * kNC;
   const int nq = min(kNC, ncols - q0);
-  double* in = smem;
-  double* out = smem + (size_t)r * kNC;
+  T* in = smem;
+  T* out = smem + (size_t)r * kNC;
   const int* R = ridx + B.r_off;
   for (int t = threadIdx.x; t < r * kNC; t += kBlock) {
     const int i = t / kNC, q = t % kNC;
-    in[t] = q < nq ? c[(size_t)R[i] * ncols + q0 + q] : 0.0;
+    in[t] = q < nq ? c[(size_t)R[i] * ncols + q0 + q] : T(0);
   }
   __syncthreads();
   for (int t = threadIdx.x; t < r * kNC; t += kBlock) {
     const int i = t / kNC, q = t % kNC;
-    double acc = 0.0;
-    for (int j = 0; j < r; ++j) acc += B.Xinv[(size_t)i * r + j] * in[j * kNC + q];
+    T acc = 0;
+    for (int j = 0; j < r; ++j) acc += Xi[(size_t)i * r + j] * in[j * kNC + q];
     out[t] = acc;
   }
   __syncthreads();
@@ -1292,10 +1317,10 @@ __global__ void k_sum_parts(const double* parts, int nparts, long long stride, i
   out[t] = scale * s;
 }
 
-// parts[box] (3p x ncols) = Ph_R^T c_R
+// parts[box] (3p x ncols) = Ph_R^T c_R (accumulated in float64)
+template <typename T>
 __global__ __launch_bounds__(kBlock) void k_border_rhs(const SolveBox* boxes, const int* ridx,
-                                                       const double* Ph, int p3,
-                                                       const double* c, int ncols,
+                                                       const T* Ph, int p3, const T* c, int ncols,
                                                        double* parts) {
   const SolveBox& B = boxes[blockIdx.x];
   double* out = parts + (size_t)B.part * p3 * ncols;
@@ -1303,22 +1328,25 @@ __global__ __launch_bounds__(kBlock) void k_border_rhs(const SolveBox* boxes, co
   for (int t = threadIdx.x; t < p3 * ncols; t += kBlock) {
     const int h = t / ncols, q = t % ncols;
     double acc = 0.0;
-    for (int i = 0; i < B.r; ++i) acc += Ph[(size_t)R[i] * p3 + h] * c[(size_t)R[i] * ncols + q];
+    for (int i = 0; i < B.r; ++i)
+      acc += (double)Ph[(size_t)R[i] * p3 + h] * (double)c[(size_t)R[i] * ncols + q];
     out[t] = acc;
   }
 }
 
 // c_R -= W lam
+template <typename T>
 __global__ __launch_bounds__(kBlock) void k_border_fix(const SolveBox* boxes, const int* ridx,
-                                                       int p3, const double* lam, double* c,
+                                                       int p3, const double* lam, T* c,
                                                        int ncols) {
   const SolveBox& B = boxes[blockIdx.x];
   const int* R = ridx + B.r_off;
+  const T* W = Fac<T>::w(B);
   for (int t = threadIdx.x; t < B.r * ncols; t += kBlock) {
     const int i = t / ncols, q = t % ncols;
     double acc = 0.0;
-    for (int h = 0; h < p3; ++h) acc += B.W[(size_t)i * p3 + h] * lam[(size_t)h * ncols + q];
-    c[(size_t)R[i] * ncols + q] -= acc;
+    for (int h = 0; h < p3; ++h) acc += (double)W[(size_t)i * p3 + h] * lam[(size_t)h * ncols + q];
+    c[(size_t)R[i] * ncols + q] -= (T)acc;
   }
 }
 
@@ -1337,12 +1365,13 @@ __global__ void k_assemble_Z(const double* X0, int n0, const double* Hh, const d
   Z[t] = v;
 }
 
-__global__ void k_root_gather(const double* c, int ncols, const int* I0, int n0,
+template <typename T>
+__global__ void k_root_gather(const T* c, int ncols, const int* I0, int n0,
                               const double* rhs2, int p3, double* v) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (n0 + p3) * ncols) return;
   const int i = t / ncols, q = t % ncols;
-  v[t] = i < n0 ? c[(size_t)I0[i] * ncols + q] : rhs2[(size_t)(i - n0) * ncols + q];
+  v[t] = i < n0 ? (double)c[(size_t)I0[i] * ncols + q] : rhs2[(size_t)(i - n0) * ncols + q];
 }
 
 __global__ void k_dense_apply(const double* Zinv, int nz, const double* v, int ncols,
@@ -1355,11 +1384,74 @@ __global__ void k_dense_apply(const double* Zinv, int nz, const double* v, int n
   out[t] = acc;
 }
 
-__global__ void k_root_scatter(const double* sol, int ncols, const int* I0, int n0, double* c) {
+template <typename T>
+__global__ void k_root_scatter(const double* sol, int ncols, const int* I0, int n0, T* c) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n0 * ncols) return;
   const int i = t / ncols, q = t % ncols;
-  c[(size_t)I0[i] * ncols + q] = sol[t];
+  c[(size_t)I0[i] * ncols + q] = (T)sol[t];
+}
+
+// y = (T) x  (element count n)
+template <typename TO, typename TI>
+__global__ void k_convert(const TI* x, long long n, TO* y) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) y[t] = (TO)x[t];
+}
+
+__global__ void k_fill(double* x, long long n, double v) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) x[t] = v;
+}
+
+// x += (double) d
+template <typename TI>
+__global__ void k_accumulate(const TI* d, long long n, double* x) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) x[t] += (double)d[t];
+}
+
+// r = [f; 0] - y  (rows layout, f has nf rows); colsq[q] = ||r_q||^2 and fsq[q] = ||f_q||^2,
+// one block per column, fixed-order sums.
+__global__ __launch_bounds__(kBlock) void k_residual(const double* f, int nf, const double* y,
+                                                    int nrows, int ncols, double* r,
+                                                    double* colsq, double* fsq) {
+  constexpr int NW = kBlock / 64;
+  __shared__ double red[NW];
+  const int q = blockIdx.x;
+  double sr = 0.0, sf = 0.0;
+  for (int i = threadIdx.x; i < nrows; i += kBlock) {
+    const double fi = i < nf ? f[(size_t)i * ncols + q] : 0.0;
+    const double v = fi - y[(size_t)i * ncols + q];
+    r[(size_t)i * ncols + q] = v;
+    sr += v * v;
+    sf += fi * fi;
+  }
+  sr = block_sum(sr, red);
+  sf = block_sum(sf, red);
+  if (threadIdx.x == 0) { colsq[q] = sr; fsq[q] = sf; }
+}
+
+// float copies of the factor blocks of every box of a level (sizes from the final ranks)
+__global__ void k_factor_to_float(const LevelBox* boxes, const int* k_final) {
+  const LevelBox& B = boxes[blockIdx.x];
+  const int n = B.n;
+  if (n == 0) return;
+  const int k = k_final[blockIdx.x], r = n - k;
+  const int kr = k * r, rr = r * r;
+  for (int t = threadIdx.x; t < kr; t += blockDim.x) {
+    B.Tf[t] = (float)B.T[t];
+    B.Ef[t] = (float)B.E[t];
+    B.Ff[t] = (float)B.F[t];
+  }
+  for (int t = threadIdx.x; t < rr; t += blockDim.x) B.Xinvf[t] = (float)B.Xinv[t];
+}
+
+// float copy of W of every box (after the border stage)
+__global__ void k_w_to_float(const SolveBox* boxes, int p3) {
+  const SolveBox& B = boxes[blockIdx.x];
+  const int len = B.r * p3;
+  for (int t = threadIdx.x; t < len; t += blockDim.x) B.Wf[t] = (float)B.W[t];
 }
 
 __global__ void k_to_rows(const double* f, int ld, int nrows, int ncols, double* c) {
@@ -1611,23 +1703,31 @@ void launch_gj_blocked(double* A, int n, double* Ainv, double* work, int* iwork,
                      rowperm, Ainv);
 }
 
-void launch_sweep(const SolveBox* boxes, int nbox, const int* sidx, const int* ridx, double* c,
+template <typename T>
+void launch_sweep(const SolveBox* boxes, int nbox, const int* sidx, const int* ridx, T* c,
                   int ncols, int mode, int max_n, hipStream_t s) {
   if (nbox == 0 || ncols == 0) return;
   const int nc = chunk_cols(max_n);
   dim3 grid(nbox, blocks_for(ncols, nc));
-  const size_t shm = (size_t)max_n * nc * sizeof(double);
-  hipLaunchKernelGGL(k_sweep, grid, dim3(kBlock), shm, s, boxes, sidx, ridx, c, ncols, mode, nc);
+  const size_t shm = (size_t)max_n * nc * sizeof(T);
+  hipLaunchKernelGGL(k_sweep<T>, grid, dim3(kBlock), shm, s, boxes, sidx, ridx, c, ncols, mode, nc);
 }
+template void launch_sweep<double>(const SolveBox*, int, const int*, const int*, double*, int, int,
+                                   int, hipStream_t);
+template void launch_sweep<float>(const SolveBox*, int, const int*, const int*, float*, int, int,
+                                  int, hipStream_t);
 
-void launch_diag(const SolveBox* boxes, int nbox, const int* ridx, double* c, int ncols,
-                 int max_r, hipStream_t s) {
+template <typename T>
+void launch_diag(const SolveBox* boxes, int nbox, const int* ridx, T* c, int ncols, int max_r,
+                 hipStream_t s) {
   if (nbox == 0 || ncols == 0) return;
   const int nc = chunk_cols(2 * max_r);
   dim3 grid(nbox, blocks_for(ncols, nc));
-  const size_t shm = (size_t)2 * max_r * nc * sizeof(double);
-  hipLaunchKernelGGL(k_diag, grid, dim3(kBlock), shm, s, boxes, ridx, c, ncols, nc);
+  const size_t shm = (size_t)2 * max_r * nc * sizeof(T);
+  hipLaunchKernelGGL(k_diag<T>, grid, dim3(kBlock), shm, s, boxes, ridx, c, ncols, nc);
 }
+template void launch_diag<double>(const SolveBox*, int, const int*, double*, int, int, hipStream_t);
+template void launch_diag<float>(const SolveBox*, int, const int*, float*, int, int, hipStream_t);
 
 void launch_assemble_H(Geo g, const double* hole_xy, int p, const int* curve_id, double* H,
                        double* Psi, hipStream_t s) {
@@ -1650,19 +1750,28 @@ void launch_sum_parts(const double* parts, int nparts, long long stride, int len
                      nparts, stride, len, scale, out);
 }
 
-void launch_border_rhs(const SolveBox* boxes, int nbox, const int* ridx, const double* Ph,
-                       int p3, const double* c, int ncols, double* parts, hipStream_t s) {
+template <typename T>
+void launch_border_rhs(const SolveBox* boxes, int nbox, const int* ridx, const T* Ph, int p3,
+                       const T* c, int ncols, double* parts, hipStream_t s) {
   if (nbox == 0) return;
-  hipLaunchKernelGGL(k_border_rhs, dim3(nbox), dim3(kBlock), 0, s, boxes, ridx, Ph, p3, c,
-                     ncols, parts);
+  hipLaunchKernelGGL(k_border_rhs<T>, dim3(nbox), dim3(kBlock), 0, s, boxes, ridx, Ph, p3, c, ncols,
+                     parts);
 }
+template void launch_border_rhs<double>(const SolveBox*, int, const int*, const double*, int,
+                                        const double*, int, double*, hipStream_t);
+template void launch_border_rhs<float>(const SolveBox*, int, const int*, const float*, int,
+                                       const float*, int, double*, hipStream_t);
 
-void launch_border_fix(const SolveBox* boxes, int nbox, const int* ridx, int p3,
-                       const double* lam, double* c, int ncols, hipStream_t s) {
+template <typename T>
+void launch_border_fix(const SolveBox* boxes, int nbox, const int* ridx, int p3, const double* lam,
+                       T* c, int ncols, hipStream_t s) {
   if (nbox == 0) return;
-  hipLaunchKernelGGL(k_border_fix, dim3(nbox), dim3(kBlock), 0, s, boxes, ridx, p3, lam, c,
-                     ncols);
+  hipLaunchKernelGGL(k_border_fix<T>, dim3(nbox), dim3(kBlock), 0, s, boxes, ridx, p3, lam, c, ncols);
 }
+template void launch_border_fix<double>(const SolveBox*, int, const int*, int, const double*,
+                                        double*, int, hipStream_t);
+template void launch_border_fix<float>(const SolveBox*, int, const int*, int, const double*, float*,
+                                       int, hipStream_t);
 
 void launch_assemble_Z(const double* X0, int n0, const double* Hh, const double* Ph,
                        const int* I0, int p3, const double* G, double* Z, hipStream_t s) {
@@ -1671,11 +1780,16 @@ void launch_assemble_Z(const double* X0, int n0, const double* Hh, const double*
                      n0, Hh, Ph, I0, p3, G, Z);
 }
 
-void launch_root_gather(const double* c, int ncols, const int* I0, int n0, const double* rhs2,
-                        int p3, double* v, hipStream_t s) {
-  hipLaunchKernelGGL(k_root_gather, dim3(blocks_for((long long)(n0 + p3) * ncols, kBlock)),
+template <typename T>
+void launch_root_gather(const T* c, int ncols, const int* I0, int n0, const double* rhs2, int p3,
+                        double* v, hipStream_t s) {
+  hipLaunchKernelGGL(k_root_gather<T>, dim3(blocks_for((long long)(n0 + p3) * ncols, kBlock)),
                      dim3(kBlock), 0, s, c, ncols, I0, n0, rhs2, p3, v);
 }
+template void launch_root_gather<double>(const double*, int, const int*, int, const double*, int,
+                                         double*, hipStream_t);
+template void launch_root_gather<float>(const float*, int, const int*, int, const double*, int,
+                                        double*, hipStream_t);
 
 void launch_dense_apply(const double* Zinv, int nz, const double* v, int ncols, double* out,
                         hipStream_t s) {
@@ -1683,10 +1797,38 @@ void launch_dense_apply(const double* Zinv, int nz, const double* v, int ncols, 
                      Zinv, nz, v, ncols, out);
 }
 
-void launch_root_scatter(const double* sol, int ncols, const int* I0, int n0, double* c,
-                         hipStream_t s) {
-  hipLaunchKernelGGL(k_root_scatter, dim3(blocks_for((long long)n0 * ncols, kBlock)),
+template <typename T>
+void launch_root_scatter(const double* sol, int ncols, const int* I0, int n0, T* c, hipStream_t s) {
+  hipLaunchKernelGGL(k_root_scatter<T>, dim3(blocks_for((long long)n0 * ncols, kBlock)),
                      dim3(kBlock), 0, s, sol, ncols, I0, n0, c);
+}
+template void launch_root_scatter<double>(const double*, int, const int*, int, double*, hipStream_t);
+template void launch_root_scatter<float>(const double*, int, const int*, int, float*, hipStream_t);
+
+void launch_to_float(const double* x, long long n, float* y, hipStream_t s) {
+  if (n) hipLaunchKernelGGL((k_convert<float, double>), dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, x, n, y);
+}
+void launch_to_double(const float* x, long long n, double* y, hipStream_t s) {
+  if (n) hipLaunchKernelGGL((k_convert<double, float>), dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, x, n, y);
+}
+void launch_fill(double* x, long long n, double v, hipStream_t s) {
+  if (n) hipLaunchKernelGGL(k_fill, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, x, n, v);
+}
+void launch_accumulate(const double* d, long long n, double* x, hipStream_t s) {
+  if (n) hipLaunchKernelGGL(k_accumulate<double>, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, d, n, x);
+}
+void launch_accumulate(const float* d, long long n, double* x, hipStream_t s) {
+  if (n) hipLaunchKernelGGL(k_accumulate<float>, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, d, n, x);
+}
+void launch_residual(const double* f, int nf, const double* y, int nrows, int ncols, double* r,
+                     double* colsq, double* fsq, hipStream_t s) {
+  hipLaunchKernelGGL(k_residual, dim3(ncols), dim3(kBlock), 0, s, f, nf, y, nrows, ncols, r, colsq, fsq);
+}
+void launch_factor_to_float(const LevelBox* boxes, int nbox, const int* k_final, hipStream_t s) {
+  if (nbox) hipLaunchKernelGGL(k_factor_to_float, dim3(nbox), dim3(kBlock), 0, s, boxes, k_final);
+}
+void launch_w_to_float(const SolveBox* boxes, int nbox, int p3, hipStream_t s) {
+  if (nbox) hipLaunchKernelGGL(k_w_to_float, dim3(nbox), dim3(kBlock), 0, s, boxes, p3);
 }
 
 void launch_to_rows(const double* f, int ld, int nrows, int ncols, double* c, hipStream_t s) {

@@ -1,0 +1,70 @@
+"""Iterative refinement and mixed precision (the float64 residual of the exact
+operator with the factorization as inner solver).
+
+Bar after refinement (north-star): max-column relative residual <= 1e-8 and
+||x - x_ref|| / ||x_ref|| <= 1e-8, with x_ref from the oracle: the dense LU on
+the small case, and the oracle's RS at tolerance 1e-13 (residual ~1e-11) on
+the 12288-node workload.  The mixed path's parity with the oracle is only
+through these solutions and residuals (its float32 factors have no oracle
+counterpart)."""
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from oracle import stokes
+from oracle.rs import RSFactorization, RSParams
+from workloads import boundary_data, exterior_forces_for_geometry, workload_circle10_8holes, workload_small
+
+
+def _solver(g, **kw):
+    import torch
+
+    assert torch.cuda.is_available()
+    from paper_2001_11619_amd import RSSolver
+
+    return RSSolver.from_geometry(g, **kw)
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b, axis=0) / np.linalg.norm(b, axis=0)
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 1e-7), (1, 1e-5)])
+def test_refined_matches_dense_small(precision, tol):
+    g = workload_small(seed=11, n_outer=256, n_holes=2, nodes_per_hole=128, radius=3.0)
+    f = boundary_data(g, exterior_forces_for_geometry(g, 3, seed=5))
+    xd = stokes.dense_solve(g, f)
+    s = _solver(g, leaf_size=32, tol=tol, precision=precision, refine_max=30, refine_tol=1e-12).factor()
+    x, res = s.solve(f, residual=True)
+    assert np.all(res <= 1e-12)
+    assert np.all(_rel(x, xd) < 1e-10)
+    assert 1 <= s.stats()["refine_iters"] <= 30
+
+
+def test_mixed_circle10_8holes():
+    g = workload_circle10_8holes()
+    f = boundary_data(g, exterior_forces_for_geometry(g, 4, seed=2))
+    ref = RSFactorization(g, RSParams(tol=1e-13)).factor().solve(f)
+    s = _solver(g, tol=1e-7, precision=1, refine_max=20, refine_tol=1e-8).factor()
+    x, res = s.solve(f, residual=True)
+    assert np.all(res <= 1e-8)
+    assert np.all(_rel(x, ref) <= 1e-8)
+    it_mixed = s.stats()["refine_iters"]
+    p = _solver(g, tol=1e-10, precision=0, refine_max=20, refine_tol=1e-8).factor()
+    xp, resp = p.solve(f, residual=True)
+    assert np.all(resp <= 1e-8)
+    assert np.all(_rel(xp, ref) <= 1e-8)
+    assert p.stats()["refine_iters"] <= it_mixed
+
+
+def test_noconv_reported():
+    from paper_2001_11619_amd import RSError
+
+    g = workload_small(seed=11, n_outer=256, n_holes=2, nodes_per_hole=128, radius=3.0)
+    f = boundary_data(g, exterior_forces_for_geometry(g, 1, seed=5))
+    s = _solver(g, leaf_size=32, tol=1e-4, precision=1, refine_max=1, refine_tol=1e-14).factor()
+    with pytest.raises(RSError) as e:
+        s.solve(f)
+    assert e.value.name == "RS_ERR_NOCONV"
