@@ -2,14 +2,19 @@
 """Benchmark of the recursive-skeletonization hot path on one MI355X.
 
 One step = one factorization of the workload's boundary operator followed by
-the solve of all its right-hand sides (device-resident in and out), i.e.
-every kernel of the path: ID-matrix assembly, pivoted QR, diagonal-block
-assembly, elimination, border and root, and the U / X_D^{-1} / V sweeps.
-The quadtree and the geometry upload happen once before the timed region
-(their time is reported as setup_ms, never inside `value`).
+the solve of all its right-hand sides to a relative residual of 1e-8
+(device-resident in and out): ID-matrix assembly, pivoted QR, diagonal-block
+assembly, elimination, border and root, the U / X_D^{-1} / V sweeps and the
+iterative refinement with the exact float64 residual.  The quadtree and the
+geometry upload happen once before the timed region (their time is reported
+as setup_ms, never inside `value`).
+
+Forms: "mixed" (ID tolerance 1e-7, float32 factor application, float64
+pivoted QR / inverses / root / residual) and "plain" (float64 throughout, ID
+tolerance 1e-10); both refine to 1e-8.  The first form listed is `value`.
 
 value = right-hand sides solved per second including their factorization
-        = nrhs * steps / (time of `steps` factor+solve steps).
+      = nrhs * steps / (time of `steps` factor+solve steps).
 
 Prints one JSON line.  `--gpus` above 1 is not supported (single-GPU build).
 """
@@ -71,36 +76,19 @@ def cpu_baseline(geom, f, tol, budget_s=30.0):
     }
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="circle10_8holes", choices=sorted(WORKLOADS))
-    ap.add_argument("--tol", type=float, default=1e-10)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % args.gpus,
-              file=sys.stderr)
-        sys.exit(2)
-
+def run_form(geom, f, form, steps, warmup, tol_plain, tol_mixed):
+    """Time `steps` factor + refined solve steps of one form ("plain" or "mixed")."""
     import numpy as np
     import torch
 
     from paper_2001_11619_amd import RSSolver
-    from workloads import boundary_data, exterior_forces_for_geometry
 
-    wl = WORKLOADS[args.workload]
-    geom = make_geometry(args.workload)
-    f = boundary_data(geom, exterior_forces_for_geometry(geom, wl["nrhs"], seed=wl["seed"]))
     nrhs = f.shape[1]
-    torch.cuda.set_device(0)
+    kw = dict(tol=tol_plain, precision=0) if form == "plain" else dict(tol=tol_mixed, precision=1)
     t0 = time.perf_counter()
-    s = RSSolver.from_geometry(geom, tol=args.tol)
+    s = RSSolver.from_geometry(geom, refine_max=20, refine_tol=1e-8, **kw)
     setup_ms = 1e3 * (time.perf_counter() - t0)
-    stream = torch.cuda.current_stream()
-    s.set_stream(stream.cuda_stream)
+    s.set_stream(torch.cuda.current_stream().cuda_stream)
     fd = torch.tensor(np.ascontiguousarray(f.T), dtype=torch.float64, device="cuda")
     xd = torch.empty((nrhs, geom.n_system), dtype=torch.float64, device="cuda")
 
@@ -108,68 +96,120 @@ def main():
         s.factor()
         s.solve_dev(fd, xd)
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
     s.set_kernel_timing(True)
     s.kernel_times(reset=True)
     torch.cuda.synchronize()
+    fac_ms, sol_ms, iters = [], [], []
     t0 = time.perf_counter()
-    fac_ms = []
-    for _ in range(args.steps):
+    for _ in range(steps):
         step()
-        fac_ms.append(s.stats()["ms_factor"])
+        st = s.stats()
+        fac_ms.append(st["ms_factor"])
+        sol_ms.append(st["ms_solve"])
+        iters.append(st["refine_iters"])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ktimes = s.kernel_times(reset=True)
     s.set_kernel_timing(False)
     st = s.stats()
-    # accuracy of the last step (outside the timed region)
-    x, res = s.solve(f, residual=True)
-    ms_step = 1e3 * elapsed / args.steps
+    x, res = s.solve(f, residual=True)     # accuracy check outside the timed region
+    return {
+        "solver": s, "elapsed": elapsed, "setup_ms": setup_ms, "ktimes": ktimes, "stats": st,
+        "factor_s": float(np.median(fac_ms)) / 1e3, "solve_s": float(np.median(sol_ms)) / 1e3,
+        "refine_iters": int(max(iters)), "max_rel_residual": float(np.max(res)),
+        "value": nrhs * steps / elapsed, "ms_per_step": 1e3 * elapsed / steps,
+    }
 
-    # roofline of the dominant kernel family (largest device time in the timed region)
+
+def roofline_of(run, steps, nrhs, n_nodes, n_holes):
+    st, ktimes = run["stats"], run["ktimes"]
+    # algorithmic work per step of each modelled kernel family
+    pairs = float(n_nodes) ** 2
     models = {
-        # family: (bound, unit, work per factorization or solve, peak)
         "cpqr": ("alu", "TFLOP/s", st["flops_id"], FP64_VECTOR_PEAK_TFLOPS),
         "eliminate": ("alu", "TFLOP/s", st["flops_elim"], FP64_VECTOR_PEAK_TFLOPS),
-        "sweep_U": ("hbm", "GB/s", st["factor_bytes"] * 2 / 3.0, HBM_PEAK_GBS),
-        "sweep_V": ("hbm", "GB/s", st["factor_bytes"] * 2 / 3.0, HBM_PEAK_GBS),
+        # refinement residual: ~25 flops per node pair for the 2x2 block plus 8 per column
+        "apply_operator": ("alu", "TFLOP/s", pairs * (25.0 + 8.0 * nrhs) * run["refine_iters"],
+                           FP64_VECTOR_PEAK_TFLOPS),
     }
     fam = max(ktimes, key=lambda k: ktimes[k][1]) if ktimes else None
-    roofline = None
-    if fam in models:
-        bound, unit, work, peak = models[fam]
-        launches, tot_ms = ktimes[fam]
-        per_step_s = tot_ms / 1e3 / args.steps
-        achieved = work / per_step_s / (1e12 if unit == "TFLOP/s" else 1e9)
-        roofline = {"bound": bound, "kernel": fam, "achieved": achieved, "peak": peak, "unit": unit,
-                    "frac": achieved / peak, "traffic": None,
-                    "launches_per_step": launches // args.steps, "ms_per_step": tot_ms / args.steps}
+    if fam not in models:
+        return None
+    bound, unit, work, peak = models[fam]
+    launches, tot_ms = ktimes[fam]
+    per_step_s = tot_ms / 1e3 / steps
+    achieved = work / per_step_s / 1e12
+    return {"bound": bound, "kernel": fam, "achieved": achieved, "peak": peak, "unit": unit,
+            "frac": achieved / peak, "traffic": None, "launches_per_step": launches // steps,
+            "ms_per_step": tot_ms / steps}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="circle10_8holes", choices=sorted(WORKLOADS))
+    ap.add_argument("--tol-plain", type=float, default=1e-10)
+    ap.add_argument("--tol-mixed", type=float, default=1e-7)
+    ap.add_argument("--forms", default="mixed,plain")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from workloads import boundary_data, exterior_forces_for_geometry
+
+    wl = WORKLOADS[args.workload]
+    geom = make_geometry(args.workload)
+    f = boundary_data(geom, exterior_forces_for_geometry(geom, wl["nrhs"], seed=wl["seed"]))
+    nrhs = f.shape[1]
+    torch.cuda.set_device(0)
+    forms = [x for x in args.forms.split(",") if x]
+    runs = {fm: run_form(geom, f, fm, args.steps, args.warmup, args.tol_plain, args.tol_mixed)
+            for fm in forms}
+    head = runs[forms[0]]
     out = {
         "metric": "RS factor s + solves/s at 1e-8 rel. residual, mixed-batched vs FP64 plain",
-        "value": nrhs * args.steps / elapsed,
+        "value": head["value"],
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32+f64" if forms[0] == "mixed" else "f64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "desc": wl["desc"], "nrhs": nrhs, "tol": args.tol,
-                   "precision": "fp64 plain", "leaf": 64, "n_proxy": 64},
-        "factor_s": float(np.median(fac_ms)) / 1e3,
-        "solves_per_s_solve_only": nrhs / (st["ms_solve"] / 1e3) if st["ms_solve"] > 0 else None,
-        "setup_ms": setup_ms,
-        "max_rel_residual": float(np.max(res)),
-        "kernel_ms_per_step": {k: v[1] / args.steps for k, v in sorted(ktimes.items())},
-        "roofline": roofline,
+        "config": {"workload": args.workload, "desc": wl["desc"], "nrhs": nrhs, "form": forms[0],
+                   "tol": args.tol_mixed if forms[0] == "mixed" else args.tol_plain,
+                   "refine_tol": 1e-8, "leaf": 64, "n_proxy": 64},
+        "factor_s": head["factor_s"],
+        "solve_s": head["solve_s"],
+        "refine_iters": head["refine_iters"],
+        "max_rel_residual": head["max_rel_residual"],
+        "setup_ms": head["setup_ms"],
+        "kernel_ms_per_step": {k: v[1] / args.steps for k, v in sorted(head["ktimes"].items())},
+        "roofline": roofline_of(head, args.steps, nrhs, geom.n_nodes, geom.n_holes),
     }
+    for fm in forms[1:]:
+        r = runs[fm]
+        out["form_" + fm] = {"value": r["value"], "ms_per_step": r["ms_per_step"],
+                             "factor_s": r["factor_s"], "solve_s": r["solve_s"],
+                             "refine_iters": r["refine_iters"],
+                             "max_rel_residual": r["max_rel_residual"],
+                             "kernel_ms_per_step": {k: v[1] / args.steps for k, v in sorted(r["ktimes"].items())}}
+        out["speedup_vs_" + fm] = head["value"] / r["value"]
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(geom, f, args.tol)
+        out["cpu_baseline"] = cpu_baseline(geom, f, args.tol_plain)
     print(json.dumps(out), flush=True)
 
 

@@ -127,6 +127,21 @@ rs_status rs_update_moved_nodes(rs_ctx* ctx, int n_moved, const int* idx, const 
                                 const double* normal, const double* weight,
                                 const double* curvature, const double* hole_xy);
 
+/* Factor n contexts together (the many-geometry batch): level by level, the
+ * boxes of all contexts are compressed by one launch per kernel (Section 2.7's
+ * level parallelism extended across geometries; the paper's Scheme A runs
+ * independent factorizations side by side).  The contexts must live on one
+ * device and share lambda, tol, n_proxy, proxy_ratio, rcond_min and
+ * precision; the first context's stream is used.  Each context ends up exactly
+ * as after its own rs_factor.  On failure every context is left unfactored
+ * and carries the message. */
+rs_status rs_factor_batch(rs_ctx** ctxs, int n);
+
+/* rs_solve_dev for each of n factored contexts (f_dev[i], x_dev[i] laid out
+ * as for rs_solve_dev of context i).  Returns the first non-RS_OK status. */
+rs_status rs_solve_batch(rs_ctx** ctxs, int n, int nrhs, const double* const* f_dev,
+                         double* const* x_dev);
+
 /* Use the given hipStream_t (as void*) for all later device work; NULL = the
  * default stream.  The caller keeps the stream alive while the context uses it. */
 rs_status rs_set_stream(rs_ctx* ctx, void* hip_stream);

@@ -5,4 +5,5 @@ this package only marshals arguments to it.  Importing the package does not
 load the library; the first `RSSolver` does, and raises if it was not built.
 """
 
-from .binding import RSSolver, RSError, library_path, load_library, exported_symbols  # noqa: F401
+from .binding import (RSSolver, RSError, library_path, load_library, exported_symbols,  # noqa: F401
+                      factor_batch, solve_batch)

@@ -88,6 +88,8 @@ def load_library():
     lib.rs_get_boxes.argtypes = [h, ctypes.c_int, ip, ip, ip, ip, dp]
     lib.rs_get_skeleton.argtypes = [h, ctypes.c_int, ctypes.c_int, ip, ip]
     lib.rs_apply.argtypes = [h, ctypes.c_int, dp, dp]
+    lib.rs_factor_batch.argtypes = [P(h), ctypes.c_int]
+    lib.rs_solve_batch.argtypes = [P(h), ctypes.c_int, ctypes.c_int, P(vp), P(vp)]
     lib.rs_set_kernel_timing.argtypes = [h, ctypes.c_int]
     lib.rs_get_kernel_times.argtypes = [h, ctypes.c_int, P(KernelTime), ip, ctypes.c_int]
     lib.rs_destroy.argtypes = [h]
@@ -96,7 +98,7 @@ def load_library():
     lib.rs_last_error.restype = ctypes.c_char_p
     for name in ("rs_build_tree", "rs_factor", "rs_solve", "rs_solve_dev", "rs_update_moved_nodes",
                  "rs_set_stream", "rs_get_stats", "rs_get_boxes", "rs_get_skeleton", "rs_apply",
-                 "rs_set_kernel_timing", "rs_get_kernel_times"):
+                 "rs_set_kernel_timing", "rs_get_kernel_times", "rs_factor_batch", "rs_solve_batch"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -109,7 +111,7 @@ def exported_symbols():
     for name in ("rs_default_params", "rs_build_tree", "rs_factor", "rs_solve", "rs_solve_dev",
                  "rs_update_moved_nodes", "rs_set_stream", "rs_get_stats", "rs_get_boxes",
                  "rs_get_skeleton", "rs_apply", "rs_set_kernel_timing", "rs_get_kernel_times",
-                 "rs_destroy", "rs_last_error"):
+                 "rs_factor_batch", "rs_solve_batch", "rs_destroy", "rs_last_error"):
         if hasattr(lib, name):
             out.append(name)
     return out
@@ -127,6 +129,29 @@ def default_params() -> Params:
     p = Params()
     load_library().rs_default_params(ctypes.byref(p))
     return p
+
+
+def factor_batch(solvers):
+    """Factor several RSSolver contexts together (one launch per kernel per level)."""
+    lib = load_library()
+    n = len(solvers)
+    arr = (ctypes.c_void_p * n)(*[sv._h.value for sv in solvers])
+    st = lib.rs_factor_batch(arr, n)
+    if st != 0:
+        raise RSError(st, lib.rs_last_error(solvers[0]._h).decode())
+
+
+def solve_batch(solvers, f_devs, x_devs):
+    """rs_solve_dev on each context; f_devs / x_devs are device tensors as for solve_dev."""
+    lib = load_library()
+    n = len(solvers)
+    arr = (ctypes.c_void_p * n)(*[sv._h.value for sv in solvers])
+    fp = (ctypes.c_void_p * n)(*[t.data_ptr() for t in f_devs])
+    xp = (ctypes.c_void_p * n)(*[t.data_ptr() for t in x_devs])
+    nrhs = int(f_devs[0].shape[0])
+    st = lib.rs_solve_batch(arr, n, nrhs, fp, xp)
+    if st != 0:
+        raise RSError(st, "batch solve failed")
 
 
 class RSSolver:

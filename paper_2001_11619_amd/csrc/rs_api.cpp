@@ -162,7 +162,7 @@ struct rs_ctx {
   int all_maxr = 0;
   // solve work
   DevBuf d_f, d_c, d_cf, d_v, d_sol, d_parts, d_rhs2, d_xout, d_res, d_frows, d_xs, d_r, d_dx,
-      d_ys, d_norms;
+      d_ys, d_norms, d_apply;
   std::vector<double> last_res;   // relative residual per column of the last refined solve
 
   rs_stats stats{};
@@ -416,14 +416,30 @@ bool compress_needed(const rs_ctx* c, int b, const std::vector<int>& F) {
   return false;
 }
 
-// Factor every box of level l (ids in `ids`), reading the level-start active set.
-void factor_level(rs_ctx* c, int l, const std::vector<int>& ids, const std::vector<char>& active,
-                  std::vector<int>& boxes_done) {
-  const rs_params& P = c->prm;
+// Work of one context at one level: the boxes it compresses, prepared on the host.
+struct LevelPrep {
+  std::vector<int> ids;          // all boxes of the level
+  std::vector<int> sel;          // positions in ids that are compressed now
+  std::vector<LevelBox> lb;      // their descriptors (device pointers filled)
+  std::vector<int> doff;         // offset of each compressed box's I_B in the context's list
+  std::vector<int> perm;         // pivot orders read back
+  int max_m = 0, max_n = 0;
+  int aid = -1;
+  size_t first = 0;              // index of the first box in the batched launch
+};
+
+constexpr int kMaxCoop = 64;     // most workgroups per box in the cooperative kernels
+
+// Host part of one level for one context: unknowns, near fields, reuse
+// decisions, workspace and arena allocation, uploads of the index lists.
+void prepare_level(rs_ctx* c, int l, const std::vector<int>& ids, const std::vector<char>& active,
+                   LevelPrep& P) {
+  const rs_params& prm = c->prm;
   hipStream_t s = c->stream;
   Geo g;
   geo_of(c, g);
-  // unknowns of every box at this level
+  P = LevelPrep();
+  P.ids = ids;
   std::vector<std::vector<int>> Is(ids.size());
   std::vector<std::vector<ChildSrc>> srcs(ids.size());
   for (size_t t = 0; t < ids.size(); ++t) box_unknowns(c, ids[t], Is[t], &srcs[t]);
@@ -436,13 +452,10 @@ void factor_level(rs_ctx* c, int l, const std::vector<int>& ids, const std::vect
   }
   std::unordered_map<int, int> pos_of;
   for (size_t t = 0; t < ids.size(); ++t) pos_of[ids[t]] = (int)t;
-
-  std::vector<LevelBox> lb;
   std::vector<int> dofs, fint;
   std::vector<ChildSrc> src_all;
-  std::vector<int> sel;   // positions in ids with n > 0
-  size_t totM = 0, totN2 = 0, totArena = 0;
-  int max_m = 0, max_n = 0;
+  std::vector<int> soff;
+  size_t totM = 0, totN2 = 0, totArena = 0, totScr = 0;
   std::vector<int> cand;
   for (size_t t = 0; t < ids.size(); ++t) {
     const int b = ids[t];
@@ -458,7 +471,7 @@ void factor_level(rs_ctx* c, int l, const std::vector<int>& ids, const std::vect
       continue;
     }
     // near field F_int: active unknowns strictly inside the proxy circle, not in I_B
-    const double rp = P.proxy_ratio * B.side;
+    const double rp = prm.proxy_ratio * B.side;
     const double rp2 = rp * rp;
     cand.clear();
     for (long long dx = -2; dx <= 2; ++dx)
@@ -508,178 +521,120 @@ void factor_level(rs_ctx* c, int l, const std::vector<int>& ids, const std::vect
     x.side = B.side;
     x.n = f.n;
     x.nF = (int)F.size();
-    x.m = 2 * x.nF + 6 * P.n_proxy + 2;
-    x.dof_off = (int)dofs.size();
-    x.fint_off = (int)fint.size();
-    x.src_off = B.leaf() ? -1 : (int)src_all.size();
-    x.kcap = f.n;
+    x.m = 2 * x.nF + 6 * prm.n_proxy + 2;
+    x.geo = g;
+    P.doff.push_back((int)dofs.size());
+    soff.push_back(B.leaf() ? -1 : (int)src_all.size());
+    x.fint = reinterpret_cast<const int*>((uintptr_t)fint.size());   // offsets for now
     dofs.insert(dofs.end(), f.I.begin(), f.I.end());
     fint.insert(fint.end(), F.begin(), F.end());
     if (!B.leaf()) src_all.insert(src_all.end(), srcs[t].begin(), srcs[t].end());
     totM += (size_t)x.m * x.n;
     const size_t n2 = (size_t)x.n * x.n;
     totN2 += n2;
+    totScr += 3 * n2 + 128 * (size_t)x.n + 2048;
     totArena += 3 * (n2 / 4 + x.n) + 2 * n2;
-    if (P.precision == 1) totArena += (3 * (n2 / 4 + x.n) + n2 + 1) / 2 + 4;
-    max_m = std::max(max_m, x.m);
-    max_n = std::max(max_n, x.n);
-    lb.push_back(x);
-    sel.push_back((int)t);
+    if (prm.precision == 1) totArena += (3 * (n2 / 4 + x.n) + n2 + 1) / 2 + 4;
+    P.max_m = std::max(P.max_m, x.m);
+    P.max_n = std::max(P.max_n, x.n);
+    P.lb.push_back(x);
+    P.sel.push_back((int)t);
   }
-  const int nb = (int)lb.size();
+  const int nb = (int)P.lb.size();
   if (nb == 0) return;
-  const size_t qr_lds = cpqr_lds_bytes(max_m, max_n);
-  if (qr_lds > 160 * 1024)
-    throw RsError{RS_ERR_ARG, "box too large for the pivoted-QR kernel (m=" + std::to_string(max_m) +
-                                  ", n=" + std::to_string(max_n) + ")"};
-  // workgroups per box for the pivoted QR: spread the few large boxes near the
-  // root over the whole device (all must be co-resident: cooperative launch)
-  int G = 1;
-  {
-    const int per_cu = cpqr_blocks_per_cu(qr_lds);
-    const int cap = per_cu * c->n_cu;
-    if (cap > 0) G = std::min({cap / nb, std::max(1, max_n / 16), 64});
-    if (G < 2 || nb > c->n_cu / 4) G = 1;
-  }
-  int Ge = 1;
-  {
-    const int cap = eliminate_blocks_per_cu() * c->n_cu;
-    if (cap > 0) Ge = std::min({cap / nb, std::max(1, max_n / 8), 64});
-    if (Ge < 2 || nb > c->n_cu / 4) Ge = 1;
-  }
-  // workspaces
+  // workspaces and the factor arena of this level
   c->ws_M.ensure(totM * sizeof(double));
   c->ws_R.ensure(totN2 * sizeof(double));
   c->ws_A.ensure(totN2 * sizeof(double));
-  size_t totScr = 0;
-  for (const LevelBox& x : lb) totScr += 3 * (size_t)x.n * x.n + 128 * (size_t)x.n + 2048;
   c->ws_scr.ensure(totScr * sizeof(double));
-  const int aid = c->next_arena++;
-  c->arenas[aid] = std::make_unique<DevBuf>();
-  DevBuf* arena = c->arenas[aid].get();
+  size_t totCoop = 0;
+  for (const LevelBox& x : P.lb) totCoop += 8 + 2 + 3 * (size_t)kMaxCoop + (size_t)x.m;
+  c->ws_coop.ensure(totCoop * sizeof(double));
+  P.aid = c->next_arena++;
+  c->arenas[P.aid] = std::make_unique<DevBuf>();
+  DevBuf* arena = c->arenas[P.aid].get();
   arena->ensure(totArena * sizeof(double));
-  {
-    double* pM = c->ws_M.as<double>();
-    double* pR = c->ws_R.as<double>();
-    double* pA = c->ws_A.as<double>();
-    double* pS = c->ws_scr.as<double>();
-    double* pa = arena->as<double>();
-    for (int i = 0; i < nb; ++i) {
-      LevelBox& x = lb[i];
-      const size_t n2 = (size_t)x.n * x.n;
-      const size_t kr = n2 / 4 + x.n;
-      x.M = pM;
-      pM += (size_t)x.m * x.n;
-      x.R = pR;
-      pR += n2;
-      x.Ap = pA;
-      pA += n2;
-      x.scr = pS;
-      pS += 3 * n2 + 128 * (size_t)x.n + 2048;
-      x.T = pa;
-      pa += kr;
-      x.E = pa;
-      pa += kr;
-      x.F = pa;
-      pa += kr;
-      x.Xinv = pa;
-      pa += n2;
-      x.Xss = pa;
-      pa += n2;
-      if (P.precision == 1) {
-        float* pf = reinterpret_cast<float*>(pa);
-        x.Tf = pf;
-        pf += kr;
-        x.Ef = pf;
-        pf += kr;
-        x.Ff = pf;
-        pf += kr;
-        x.Xinvf = pf;
-        pa += (3 * kr + n2 + 1) / 2 + 4;
-      }
-      BoxFac& f = c->fac[ids[sel[i]]];
-      f.T = x.T;
-      f.E = x.E;
-      f.F = x.F;
-      f.Xinv = x.Xinv;
-      f.Xss = x.Xss;
-      f.Tf = x.Tf;
-      f.Ef = x.Ef;
-      f.Ff = x.Ff;
-      f.Xinvf = x.Xinvf;
-    }
-  }
-  {
-    // cooperation scratch per box: barrier, (beta, tau), 2G candidates, Householder vector
-    size_t tot = 0;
-    for (const LevelBox& x : lb) tot += 8 + 2 + 2 * (size_t)G + (size_t)G + (size_t)x.m;
-    c->ws_coop.ensure(tot * sizeof(double));
-    double* pc = c->ws_coop.as<double>();
-    for (LevelBox& x : lb) {
-      x.bar = reinterpret_cast<unsigned*>(pc);
-      pc += 8;
-      x.hh = pc;
-      pc += 2;
-      x.cval = pc;
-      pc += 2 * (size_t)G;
-      x.cphys = reinterpret_cast<int*>(pc);
-      pc += G;
-      x.vbuf = pc;
-      pc += x.m;
-    }
-    c->ws_err.ensure(sizeof(int) * 4);
-  }
-  upload(c->ws_boxes, lb, s);
   upload(c->ws_dofs, dofs, s);
   upload(c->ws_fint, fint, s);
   upload(c->ws_src, src_all, s);
   c->ws_perm.ensure(std::max<size_t>(dofs.size(), 4) * sizeof(int));
-  c->ws_k.ensure(nb * sizeof(int));
-  c->ws_kx.ensure(nb * sizeof(int));
-  c->ws_status.ensure(nb * sizeof(int));
-  const LevelBox* dlb = c->ws_boxes.as<LevelBox>();
-  {
-    KTimer kt_(c, "assemble_M");
-    launch_assemble_M(dlb, nb, max_m, c->ws_dofs.as<int>(), c->ws_fint.as<int>(), g, P.n_proxy,
-                      P.proxy_ratio, s);
-  }
-  {
-    KTimer kt_(c, "cpqr");
-    HIP_CHECK(launch_cpqr(dlb, nb, G, P.tol, kGuardExtra, c->ws_perm.as<int>(), c->ws_k.as<int>(),
-                          c->ws_kx.as<int>(), c->ws_err.as<int>(), max_m, max_n, s));
-  }
-  {
-    KTimer kt_(c, "assemble_abb");
-    launch_assemble_abb(dlb, nb, max_n, c->ws_dofs.as<int>(), c->ws_perm.as<int>(),
-                        c->ws_src.as<ChildSrc>(), g, P.lambda, s);
-  }
-  std::vector<int> k0(nb);
-  HIP_CHECK(hipMemcpyAsync(k0.data(), c->ws_k.p, nb * sizeof(int), hipMemcpyDeviceToHost, s));
-  {
-    KTimer kt_(c, "eliminate");
-    HIP_CHECK(launch_eliminate(dlb, nb, Ge, c->ws_k.as<int>(), c->ws_kx.as<int>(), P.rcond_min,
-                               c->ws_status.as<int>(), c->ws_err.as<int>() + 1, s));
-    if (P.precision == 1) launch_factor_to_float(dlb, nb, c->ws_k.as<int>(), s);
-  }
-  HIP_CHECK(hipGetLastError());
-  std::vector<int> perm(dofs.size()), kk(nb), st(nb);
-  int qr_err[2] = {0, 0};
-  HIP_CHECK(hipMemcpyAsync(qr_err, c->ws_err.p, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
-  HIP_CHECK(hipMemcpyAsync(perm.data(), c->ws_perm.p, perm.size() * sizeof(int),
-                           hipMemcpyDeviceToHost, s));
-  HIP_CHECK(hipMemcpyAsync(kk.data(), c->ws_k.p, nb * sizeof(int), hipMemcpyDeviceToHost, s));
-  HIP_CHECK(hipMemcpyAsync(st.data(), c->ws_status.p, nb * sizeof(int), hipMemcpyDeviceToHost, s));
-  HIP_CHECK(hipStreamSynchronize(s));
-  resolve_timers(c);
-  if (qr_err[0] || qr_err[1]) throw RsError{RS_ERR_DEVICE, "box barrier timed out"};
+  double* pM = c->ws_M.as<double>();
+  double* pR = c->ws_R.as<double>();
+  double* pA = c->ws_A.as<double>();
+  double* pS = c->ws_scr.as<double>();
+  double* pa = arena->as<double>();
+  double* pc = c->ws_coop.as<double>();
   for (int i = 0; i < nb; ++i) {
-    const int b = ids[sel[i]];
+    LevelBox& x = P.lb[i];
+    const size_t n2 = (size_t)x.n * x.n;
+    const size_t kr = n2 / 4 + x.n;
+    x.dofs = c->ws_dofs.as<int>() + P.doff[i];
+    x.fint = c->ws_fint.as<int>() + (size_t)reinterpret_cast<uintptr_t>(x.fint);
+    x.src = soff[i] < 0 ? nullptr : c->ws_src.as<ChildSrc>() + soff[i];
+    x.perm = c->ws_perm.as<int>() + P.doff[i];
+    x.M = pM;
+    pM += (size_t)x.m * x.n;
+    x.R = pR;
+    pR += n2;
+    x.Ap = pA;
+    pA += n2;
+    x.scr = pS;
+    pS += 3 * n2 + 128 * (size_t)x.n + 2048;
+    x.T = pa;
+    pa += kr;
+    x.E = pa;
+    pa += kr;
+    x.F = pa;
+    pa += kr;
+    x.Xinv = pa;
+    pa += n2;
+    x.Xss = pa;
+    pa += n2;
+    if (prm.precision == 1) {
+      float* pf = reinterpret_cast<float*>(pa);
+      x.Tf = pf;
+      pf += kr;
+      x.Ef = pf;
+      pf += kr;
+      x.Ff = pf;
+      pf += kr;
+      x.Xinvf = pf;
+      pa += (3 * kr + n2 + 1) / 2 + 4;
+    }
+    x.bar = reinterpret_cast<unsigned*>(pc);
+    pc += 8;
+    x.hh = pc;
+    pc += 2;
+    x.cval = pc;
+    pc += 2 * (size_t)kMaxCoop;
+    x.cphys = reinterpret_cast<int*>(pc);
+    pc += kMaxCoop;
+    x.vbuf = pc;
+    pc += x.m;
+    BoxFac& f = c->fac[ids[P.sel[i]]];
+    f.T = x.T;
+    f.E = x.E;
+    f.F = x.F;
+    f.Xinv = x.Xinv;
+    f.Xss = x.Xss;
+    f.Tf = x.Tf;
+    f.Ef = x.Ef;
+    f.Ff = x.Ff;
+    f.Xinvf = x.Xinvf;
+  }
+}
+
+// Ranks and pivot orders read back for one context: fill its box records.
+void finish_level(rs_ctx* c, LevelPrep& P, const int* k0, const int* kk, const int* st,
+                  std::vector<int>& boxes_done) {
+  for (size_t i = 0; i < P.lb.size(); ++i) {
+    const int b = P.ids[P.sel[i]];
     BoxFac& f = c->fac[b];
-    const LevelBox& x = lb[i];
-    f.perm.assign(perm.begin() + x.dof_off, perm.begin() + x.dof_off + x.n);
+    const LevelBox& x = P.lb[i];
+    f.perm.assign(P.perm.begin() + P.doff[i], P.perm.begin() + P.doff[i] + x.n);
     f.k = kk[i];
     f.rank0 = k0[i];
-    f.arena = aid;
+    f.arena = P.aid;
     if (st[i] != 0)
       throw RsError{RS_ERR_SINGULAR, "X_RR stayed singular after the pivot guard (box " +
                                          std::to_string(b) + ")"};
@@ -695,6 +650,90 @@ void factor_level(rs_ctx* c, int l, const std::vector<int>& ids, const std::vect
     c->stats.max_box_unknowns = std::max(c->stats.max_box_unknowns, x.n);
     c->stats.max_rank = std::max(c->stats.max_rank, f.k);
     boxes_done.push_back(b);
+  }
+}
+
+// One launch per kernel over the boxes of all contexts at this level (the
+// lead context provides the stream, the descriptor array and the rank arrays).
+void launch_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps) {
+  rs_ctx* c = cs[0];
+  const rs_params& prm = c->prm;
+  hipStream_t s = c->stream;
+  std::vector<LevelBox> all;
+  int max_m = 0, max_n = 0;
+  for (size_t i = 0; i < cs.size(); ++i) {
+    preps[i].first = all.size();
+    all.insert(all.end(), preps[i].lb.begin(), preps[i].lb.end());
+    max_m = std::max(max_m, preps[i].max_m);
+    max_n = std::max(max_n, preps[i].max_n);
+  }
+  const int nb = (int)all.size();
+  if (nb == 0) return;
+  const size_t qr_lds = cpqr_lds_bytes(max_m, max_n);
+  if (qr_lds > 160 * 1024)
+    throw RsError{RS_ERR_ARG, "box too large for the pivoted-QR kernel (m=" + std::to_string(max_m) +
+                                  ", n=" + std::to_string(max_n) + ")"};
+  // workgroups per box: spread the few large boxes near the root over the
+  // device (cooperative launch: all of them co-resident)
+  int G = 1, Ge = 1;
+  if (nb <= c->n_cu / 4) {
+    const int capq = cpqr_blocks_per_cu(qr_lds) * c->n_cu;
+    const int cape = eliminate_blocks_per_cu() * c->n_cu;
+    if (capq > 0) G = std::min({capq / nb, std::max(1, max_n / 16), kMaxCoop});
+    if (cape > 0) Ge = std::min({cape / nb, std::max(1, max_n / 8), kMaxCoop});
+    if (G < 2) G = 1;
+    if (Ge < 2) Ge = 1;
+  }
+  upload(c->ws_boxes, all, s);
+  c->ws_k.ensure(nb * sizeof(int));
+  c->ws_kx.ensure(nb * sizeof(int));
+  c->ws_status.ensure(nb * sizeof(int));
+  c->ws_err.ensure(sizeof(int) * 4);
+  const LevelBox* dlb = c->ws_boxes.as<LevelBox>();
+  {
+    KTimer kt_(c, "assemble_M");
+    launch_assemble_M(dlb, nb, max_m, prm.n_proxy, prm.proxy_ratio, s);
+  }
+  {
+    KTimer kt_(c, "cpqr");
+    HIP_CHECK(launch_cpqr(dlb, nb, G, prm.tol, kGuardExtra, c->ws_k.as<int>(), c->ws_kx.as<int>(),
+                          c->ws_err.as<int>(), max_m, max_n, s));
+  }
+  {
+    KTimer kt_(c, "assemble_abb");
+    launch_assemble_abb(dlb, nb, max_n, prm.lambda, true, s);
+  }
+  std::vector<int> k0(nb), kk(nb), st(nb);
+  HIP_CHECK(hipMemcpyAsync(k0.data(), c->ws_k.p, nb * sizeof(int), hipMemcpyDeviceToHost, s));
+  {
+    KTimer kt_(c, "eliminate");
+    HIP_CHECK(launch_eliminate(dlb, nb, Ge, c->ws_k.as<int>(), c->ws_kx.as<int>(), prm.rcond_min,
+                               c->ws_status.as<int>(), c->ws_err.as<int>() + 1, s));
+    if (prm.precision == 1) launch_factor_to_float(dlb, nb, c->ws_k.as<int>(), s);
+  }
+  HIP_CHECK(hipGetLastError());
+  int qr_err[2] = {0, 0};
+  HIP_CHECK(hipMemcpyAsync(qr_err, c->ws_err.p, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipMemcpyAsync(kk.data(), c->ws_k.p, nb * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipMemcpyAsync(st.data(), c->ws_status.p, nb * sizeof(int), hipMemcpyDeviceToHost, s));
+  for (size_t i = 0; i < cs.size(); ++i) {
+    LevelPrep& P = preps[i];
+    if (P.lb.empty()) continue;
+    size_t tot = 0;
+    for (const LevelBox& x : P.lb) tot += x.n;
+    P.perm.resize(P.doff.back() + P.lb.back().n);
+    HIP_CHECK(hipMemcpyAsync(P.perm.data(), cs[i]->ws_perm.p, P.perm.size() * sizeof(int),
+                             hipMemcpyDeviceToHost, s));
+    (void)tot;
+  }
+  HIP_CHECK(hipStreamSynchronize(s));
+  resolve_timers(c);
+  if (qr_err[0] || qr_err[1]) throw RsError{RS_ERR_DEVICE, "box barrier timed out"};
+  for (size_t i = 0; i < cs.size(); ++i) {
+    LevelPrep& P = preps[i];
+    if (P.lb.empty()) continue;
+    std::vector<int> done;
+    finish_level(cs[i], P, k0.data() + P.first, kk.data() + P.first, st.data() + P.first, done);
   }
 }
 
@@ -804,16 +843,16 @@ void factor_root(rs_ctx* c) {
   if (n0 > 0) {
     LevelBox rb{};
     rb.n = n0;
-    rb.dof_off = 0;
-    rb.src_off = c->boxes[0].leaf() ? -1 : 0;
+    rb.geo = g;
+    rb.dofs = c->d_I0.as<int>();
     rb.Ap = c->d_X0.as<double>();
+    upload(c->ws_src, src, s);
+    rb.src = c->boxes[0].leaf() ? nullptr : c->ws_src.as<ChildSrc>();
     std::vector<LevelBox> v{rb};
     upload(c->d_root_box, v, s);
-    upload(c->ws_src, src, s);
     {
       KTimer kt_(c, "root_abb");
-      launch_assemble_abb(c->d_root_box.as<LevelBox>(), 1, n0, c->d_I0.as<int>(), nullptr,
-                          c->ws_src.as<ChildSrc>(), g, c->prm.lambda, s);
+      launch_assemble_abb(c->d_root_box.as<LevelBox>(), 1, n0, c->prm.lambda, false, s);
     }
   }
   build_solve_meta(c);
@@ -895,38 +934,64 @@ void collect_arenas(rs_ctx* c) {
   }
 }
 
-void do_factor(rs_ctx* c) {
+// Factor several contexts level-synchronously: every level is one launch per
+// kernel over the boxes of all contexts (a single context is the plain case).
+void do_factor_multi(std::vector<rs_ctx*>& cs) {
   auto t0 = std::chrono::steady_clock::now();
-  if (!c->old) c->arenas.clear();
-  c->fac.assign(c->boxes.size(), BoxFac());
-  c->recomputed.assign(c->boxes.size(), 1);
-  c->stats.guard_bumps = 0;
-  c->stats.flops_id = 0;
-  c->stats.flops_elim = 0;
-  c->stats.max_box_unknowns = 0;
-  c->stats.max_rank = 0;
-  std::vector<char> active(2 * (size_t)c->N, 1);
-  std::vector<std::vector<int>> by_level(c->L + 1);
-  for (size_t b = 0; b < c->boxes.size(); ++b) by_level[c->boxes[b].level].push_back((int)b);
-  for (int l = c->L; l >= 1; --l) {
-    std::vector<int> done;
-    c->cur_level = l;
-    factor_level(c, l, by_level[l], active, done);
-    for (int b : done) {
-      const BoxFac& f = c->fac[b];
-      for (int i = f.k; i < f.n; ++i) active[f.I[f.perm[i]]] = 0;
+  const size_t nc = cs.size();
+  int L = 0;
+  std::vector<std::vector<char>> active(nc);
+  std::vector<std::vector<std::vector<int>>> by_level(nc);
+  for (size_t i = 0; i < nc; ++i) {
+    rs_ctx* c = cs[i];
+    if (!c->old) c->arenas.clear();
+    c->fac.assign(c->boxes.size(), BoxFac());
+    c->recomputed.assign(c->boxes.size(), 1);
+    c->stats.guard_bumps = 0;
+    c->stats.flops_id = 0;
+    c->stats.flops_elim = 0;
+    c->stats.max_box_unknowns = 0;
+    c->stats.max_rank = 0;
+    active[i].assign(2 * (size_t)c->N, 1);
+    by_level[i].assign(c->L + 1, {});
+    for (size_t b = 0; b < c->boxes.size(); ++b) by_level[i][c->boxes[b].level].push_back((int)b);
+    L = std::max(L, c->L);
+  }
+  for (int l = L; l >= 1; --l) {
+    std::vector<LevelPrep> preps(nc);
+    cs[0]->cur_level = l;
+    for (size_t i = 0; i < nc; ++i)
+      if (cs[i]->L >= l) prepare_level(cs[i], l, by_level[i][l], active[i], preps[i]);
+    launch_level(cs, preps);
+    // the redundant unknowns of every box of the level (recompressed or kept) leave the active set
+    for (size_t i = 0; i < nc; ++i) {
+      if (cs[i]->L < l) continue;
+      for (int b : by_level[i][l]) {
+        const BoxFac& f = cs[i]->fac[b];
+        if (!f.active) continue;
+        for (int t = f.k; t < f.n; ++t) active[i][f.I[f.perm[t]]] = 0;
+      }
     }
   }
-  c->cur_level = -1;
-  factor_root(c);
-  collect_arenas(c);
-  c->factored = true;
-  c->stats.boxes_recomputed = 0;
-  for (size_t b = 1; b < c->boxes.size(); ++b)
-    if (c->fac[b].active && c->recomputed[b]) c->stats.boxes_recomputed++;
-  c->stats.n_levels = c->L + 1;
-  c->stats.n_boxes = (int)c->boxes.size();
-  c->stats.ms_factor = 1e3 * seconds_since(t0);
+  cs[0]->cur_level = -1;
+  for (size_t i = 0; i < nc; ++i) {
+    rs_ctx* c = cs[i];
+    factor_root(c);
+    collect_arenas(c);
+    c->factored = true;
+    c->stats.boxes_recomputed = 0;
+    for (size_t b = 1; b < c->boxes.size(); ++b)
+      if (c->fac[b].active && c->recomputed[b]) c->stats.boxes_recomputed++;
+    c->stats.n_levels = c->L + 1;
+    c->stats.n_boxes = (int)c->boxes.size();
+  }
+  const double ms = 1e3 * seconds_since(t0);
+  for (rs_ctx* c : cs) c->stats.ms_factor = ms;
+}
+
+void do_factor(rs_ctx* c) {
+  std::vector<rs_ctx*> cs{c};
+  do_factor_multi(cs);
 }
 
 template <typename T>
@@ -1085,8 +1150,9 @@ void apply_device_rows(rs_ctx* c, const double* xrows, int ncols, double* yrows)
   geo_of(c, g);
   {
     KTimer kt_(c, "apply_operator");
+    c->d_apply.ensure(apply_scratch_doubles(c->N, ncols) * sizeof(double));
     launch_apply_operator(g, c->d_curve.as<int>(), c->d_hole.as<double>(), c->p, c->prm.lambda, xrows,
-                          ncols, yrows, nullptr, c->stream);
+                          ncols, yrows, c->d_apply.as<double>(), c->stream);
   }
   HIP_CHECK(hipGetLastError());
 }
@@ -1251,6 +1317,50 @@ rs_status rs_factor(rs_ctx* c) {
     c->factored = false;
     return fail(c, RsError{RS_ERR_ALLOC, e.what()});
   }
+}
+
+rs_status rs_factor_batch(rs_ctx** ctxs, int n) {
+  if (!ctxs || n <= 0) return RS_ERR_ARG;
+  for (int i = 0; i < n; ++i)
+    if (!ctxs[i]) return RS_ERR_ARG;
+  rs_ctx* lead = ctxs[0];
+  try {
+    std::vector<rs_ctx*> cs(ctxs, ctxs + n);
+    for (rs_ctx* c : cs) {
+      const rs_params& a = lead->prm;
+      const rs_params& b = c->prm;
+      if (c->device != lead->device) throw RsError{RS_ERR_ARG, "contexts of a batch must share the device"};
+      if (a.tol != b.tol || a.n_proxy != b.n_proxy || a.proxy_ratio != b.proxy_ratio ||
+          a.lambda != b.lambda || a.rcond_min != b.rcond_min || a.precision != b.precision)
+        throw RsError{RS_ERR_ARG, "contexts of a batch must share lambda, tol, proxy, rcond and precision"};
+    }
+    std::vector<rs_ctx*> sorted(cs);
+    std::sort(sorted.begin(), sorted.end());
+    if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+      throw RsError{RS_ERR_ARG, "a context appears twice in the batch"};
+    HIP_CHECK(hipSetDevice(lead->device));
+    for (rs_ctx* c : cs) c->factored = false;
+    do_factor_multi(cs);
+    return RS_OK;
+  } catch (const RsError& e) {
+    for (int i = 0; i < n; ++i) ctxs[i]->factored = false;
+    for (int i = 0; i < n; ++i) ctxs[i]->err = e.msg;
+    return e.st;
+  } catch (const std::exception& e) {
+    for (int i = 0; i < n; ++i) ctxs[i]->factored = false;
+    return fail(lead, RsError{RS_ERR_ALLOC, e.what()});
+  }
+}
+
+rs_status rs_solve_batch(rs_ctx** ctxs, int n, int nrhs, const double* const* f_dev,
+                         double* const* x_dev) {
+  if (!ctxs || n <= 0 || !f_dev || !x_dev) return RS_ERR_ARG;
+  rs_status worst = RS_OK;
+  for (int i = 0; i < n; ++i) {
+    const rs_status st = rs_solve_dev(ctxs[i], nrhs, f_dev[i], x_dev[i]);
+    if (st != RS_OK && worst == RS_OK) worst = st;
+  }
+  return worst;
 }
 
 rs_status rs_solve_dev(rs_ctx* c, int nrhs, const double* f_dev, double* x_dev) {

@@ -19,16 +19,19 @@ struct Geo {
 
 // One box compressed at a level.  Device pointers point into per-level
 // workspaces and into the persistent factor arena.
+struct ChildSrc;
+
 struct LevelBox {
   double cx, cy, side;
   int n;          // active unknowns |I_B|
   int m;          // rows of the ID matrix M_B
   int nF;         // |F_int|
-  int dof_off;    // offset of I_B in the level's unknown list
-  int fint_off;   // offset of F_int in the level's near-field list
-  int src_off;    // offset of the per-position child table, -1 for a leaf
-  int kcap;       // rows of R kept by the pivoted QR (rank + guard head-room)
   int pad;
+  Geo geo;                 // geometry of the box's boundary (per context)
+  const int* dofs;         // I_B (n), ascending
+  const int* fint;         // F_int (nF)
+  const ChildSrc* src;     // per position of I_B: where its child's X_SS is (null for a leaf)
+  int* perm;               // pivot order output (n)
   double* M;      // m x n, column-major (ld = m)
   double* R;      // kcap x n, row-major, pivot order
   double* Ap;     // n x n, row-major, A_BB in pivot order
@@ -42,7 +45,7 @@ struct LevelBox {
   float* Ef;
   float* Ff;
   float* Xinvf;
-  // cooperation of several workgroups on one box (pivoted QR)
+  // cooperation of several workgroups on one box (pivoted QR, elimination)
   unsigned* bar;  // box barrier counter
   double* hh;     // beta, tau of the current step
   double* cval;   // 2 x G pivot candidates (value)
@@ -81,14 +84,13 @@ constexpr int kBlock = 256;
 constexpr int kNC = 16;        // right-hand-side columns per sweep block
 
 // ---- launchers (rs_kernels.hip) -------------------------------------------
-void launch_assemble_M(const LevelBox* boxes, int nbox, int max_m, const int* dofs,
-                       const int* fint, Geo g, int n_proxy, double ratio, hipStream_t s);
+void launch_assemble_M(const LevelBox* boxes, int nbox, int max_m, int n_proxy, double ratio,
+                       hipStream_t s);
 size_t cpqr_lds_bytes(int max_m, int max_n);
 int cpqr_blocks_per_cu(size_t lds);
-hipError_t launch_cpqr(const LevelBox* boxes, int nbox, int G, double tol, int extra, int* perm,
+hipError_t launch_cpqr(const LevelBox* boxes, int nbox, int G, double tol, int extra,
                        int* k_out, int* kx_out, int* err, int max_m, int max_n, hipStream_t s);
-void launch_assemble_abb(const LevelBox* boxes, int nbox, int max_n, const int* dofs,
-                         const int* perm, const ChildSrc* src, Geo g, double lam,
+void launch_assemble_abb(const LevelBox* boxes, int nbox, int max_n, double lam, bool use_perm,
                          hipStream_t s);
 int eliminate_blocks_per_cu();
 hipError_t launch_eliminate(const LevelBox* boxes, int nbox, int G, int* k_io, const int* kx,
@@ -136,8 +138,9 @@ void launch_factor_to_float(const LevelBox* boxes, int nbox, const int* k_final,
 void launch_w_to_float(const SolveBox* boxes, int nbox, int p3, hipStream_t s);
 void launch_to_rows(const double* f, int ld, int nrows, int ncols, double* c, hipStream_t s);
 void launch_from_rows(const double* c, int nrows, int ncols, double* x, int ld, hipStream_t s);
+size_t apply_scratch_doubles(int N, int ncols);
 void launch_apply_operator(Geo g, const int* curve_id, const double* hole_xy, int p,
                            double lam, const double* x, int ncols, double* y,
-                           double* hole_parts, hipStream_t s);
+                           double* part, hipStream_t s);
 
 }  // namespace rs

@@ -258,14 +258,14 @@ __device__ double wg_gj_inverse(const double* X, int n, int ldx, double* Xi, int
 
 // ---- factorization kernels -------------------------------------------------
 
-__global__ __launch_bounds__(kBlock) void k_assemble_M(const LevelBox* boxes, const int* dofs,
-                                                       const int* fint, Geo g, int n_proxy,
+__global__ __launch_bounds__(kBlock) void k_assemble_M(const LevelBox* boxes, int n_proxy,
                                                        double ratio) {
   const LevelBox& B = boxes[blockIdx.x];
   const int i = blockIdx.y * blockDim.x + threadIdx.x;
   const int m = B.m, n = B.n, nF = B.nF;
   if (i >= m || n == 0) return;
-  const int* I = dofs + B.dof_off;
+  const int* I = B.dofs;
+  const Geo& g = B.geo;
   const int np2 = 2 * n_proxy;
   const double rp = ratio * B.side;
   const double wp = 2.0 * kPi * rp / n_proxy;
@@ -273,10 +273,10 @@ __global__ __launch_bounds__(kBlock) void k_assemble_M(const LevelBox* boxes, co
   double px = 0, py = 0, pnx = 0, pny = 0;
   if (i < nF) {
     type = 0;
-    f = fint[B.fint_off + i];
+    f = B.fint[i];
   } else if (i < 2 * nF) {
     type = 1;
-    f = fint[B.fint_off + i - nF];
+    f = B.fint[i - nF];
   } else if (i < 2 * nF + 3 * np2) {
     const int t = i - 2 * nF;
     type = 2 + t / np2;
@@ -389,8 +389,8 @@ __device__ void box_barrier_full(unsigned* bar, int G, unsigned& count, int* dea
 }
 
 __global__ __launch_bounds__(kQRThreads) void k_cpqr(const LevelBox* boxes, int G, double tol,
-                                                     int extra, int* perm_out, int* k_out,
-                                                     int* kx_out, int* err) {
+                                                     int extra, int* k_out, int* kx_out,
+                                                     int* err) {
   extern __shared__ double smem[];
   const int bidx = blockIdx.x / G, g = blockIdx.x % G;
   const LevelBox& B = boxes[bidx];
@@ -596,7 +596,7 @@ __global__ __launch_bounds__(kQRThreads) void k_cpqr(const LevelBox* boxes, int 
     }
   }
   if (g == 0) {
-    for (int c = tid; c < n; c += kQRThreads) perm_out[B.dof_off + c] = pv[c];
+    for (int c = tid; c < n; c += kQRThreads) B.perm[c] = pv[c];
     if (tid == 0) { k_out[bidx] = kk; kx_out[bidx] = kx; }
   }
 }
@@ -607,26 +607,25 @@ __global__ void k_zero_bars(const LevelBox* boxes, int nbox, int* err) {
   if (t == 0) *err = 0;
 }
 
-__global__ __launch_bounds__(kBlock) void k_assemble_abb(const LevelBox* boxes, const int* dofs,
-                                                         const int* perm, const ChildSrc* src,
-                                                         Geo g, double lam) {
+__global__ __launch_bounds__(kBlock) void k_assemble_abb(const LevelBox* boxes, double lam,
+                                                         int use_perm) {
   const LevelBox& B = boxes[blockIdx.x];
   const int n = B.n;
   const int t = blockIdx.y * blockDim.x + threadIdx.x;
   if (t >= n * n) return;
   const int i = t / n, j = t % n;
-  const int pi = perm ? perm[B.dof_off + i] : i;
-  const int pj = perm ? perm[B.dof_off + j] : j;
-  if (B.src_off >= 0) {
-    const ChildSrc& si = src[B.src_off + pi];
-    const ChildSrc& sj = src[B.src_off + pj];
+  const int pi = use_perm ? B.perm[i] : i;
+  const int pj = use_perm ? B.perm[j] : j;
+  if (B.src) {
+    const ChildSrc& si = B.src[pi];
+    const ChildSrc& sj = B.src[pj];
     if (si.child == sj.child) {
       B.Ap[t] = si.xss[(size_t)si.idx * si.ld + sj.idx];
       return;
     }
   }
-  const int di = dofs[B.dof_off + pi], dj = dofs[B.dof_off + pj];
-  B.Ap[t] = op_entry(g, di >> 1, di & 1, dj >> 1, dj & 1, lam);
+  const int di = B.dofs[pi], dj = B.dofs[pj];
+  B.Ap[t] = op_entry(B.geo, di >> 1, di & 1, dj >> 1, dj & 1, lam);
 }
 
 // ---- elimination of the redundant unknowns (G workgroups per box) -----------
@@ -1470,32 +1469,32 @@ __global__ void k_from_rows(const double* c, int nrows, int ncols, double* x, in
 
 // ---- exact float64 operator (refinement residual) ---------------------------
 // y = A x with A = [[lam I + D + N, H], [Psi^T, -I]]; x, y row layout
-// [(2N + 3p)][ncols].  One thread per target node, sources staged through LDS,
-// kApplyCols columns per block.
+// [(2N + 3p)][ncols].  Blocks tile (targets) x (source chunks) x (column
+// chunks); each block writes the partial sums of its source chunk, and a
+// second kernel adds the chunks in a fixed order (deterministic).
 constexpr int kApplyCols = 8;
 constexpr int kApplyTile = 256;
 
-__global__ __launch_bounds__(kApplyTile) void k_apply_D(Geo g, const double* hole_xy, int p,
-                                                        double lam, const double* x,
-                                                        int ncols, double* y) {
+__global__ __launch_bounds__(kApplyTile) void k_apply_D(Geo g, double lam, const double* x,
+                                                        int ncols, int chunk, double* part) {
   __shared__ double sx[kApplyTile], sy[kApplyTile], snx[kApplyTile], sny[kApplyTile],
       sw[kApplyTile];
   __shared__ double sm[kApplyTile][2 * kApplyCols];
   const int N = g.N;
   const int i = blockIdx.x * kApplyTile + threadIdx.x;
-  const int q0 = blockIdx.y * kApplyCols;
+  const int js0 = blockIdx.y * chunk, js1 = min(N, js0 + chunk);
+  const int q0 = blockIdx.z * kApplyCols;
   const int nq = min(kApplyCols, ncols - q0);
-  const int ldx = ncols;
   const bool live = i < N;
   const double xi = live ? g.x[i] : 0.0, yi = live ? g.y[i] : 0.0;
   const double nxi = live ? g.nx[i] : 0.0, nyi = live ? g.ny[i] : 0.0;
   double ax[kApplyCols], ay[kApplyCols];
 #pragma unroll
   for (int q = 0; q < kApplyCols; ++q) { ax[q] = 0.0; ay[q] = 0.0; }
-  for (int j0 = 0; j0 < N; j0 += kApplyTile) {
+  for (int j0 = js0; j0 < js1; j0 += kApplyTile) {
     const int j = j0 + threadIdx.x;
     __syncthreads();
-    if (j < N) {
+    if (j < js1) {
       sx[threadIdx.x] = g.x[j];
       sy[threadIdx.x] = g.y[j];
       snx[threadIdx.x] = g.nx[j];
@@ -1503,23 +1502,22 @@ __global__ __launch_bounds__(kApplyTile) void k_apply_D(Geo g, const double* hol
       sw[threadIdx.x] = g.w[j];
 #pragma unroll
       for (int q = 0; q < kApplyCols; ++q) {
-        sm[threadIdx.x][2 * q] = q < nq ? x[(size_t)(2 * j) * ldx + q0 + q] : 0.0;
-        sm[threadIdx.x][2 * q + 1] = q < nq ? x[(size_t)(2 * j + 1) * ldx + q0 + q] : 0.0;
+        sm[threadIdx.x][2 * q] = q < nq ? x[(size_t)(2 * j) * ncols + q0 + q] : 0.0;
+        sm[threadIdx.x][2 * q + 1] = q < nq ? x[(size_t)(2 * j + 1) * ncols + q0 + q] : 0.0;
       }
     }
     __syncthreads();
-    const int cnt = min(kApplyTile, N - j0);
+    const int cnt = min(kApplyTile, js1 - j0);
     if (!live) continue;
     for (int jj = 0; jj < cnt; ++jj) {
       const int js = j0 + jj;
-      double bxx, bxy, byx, byy;
+      double bxx, bxy, byy;
       const double wn_x = sw[jj] * snx[jj], wn_y = sw[jj] * sny[jj];
       if (js == i) {
         const double tx = -nyi, ty = nxi;
         const double c = -(g.w[i] * g.kap[i]) / (2.0 * kPi);
         bxx = c * tx * tx + lam;
         bxy = c * tx * ty;
-        byx = bxy;
         byy = c * ty * ty + lam;
       } else {
         const double rx = xi - sx[jj], ry = yi - sy[jj];
@@ -1528,12 +1526,11 @@ __global__ __launch_bounds__(kApplyTile) void k_apply_D(Geo g, const double* hol
         const double coef = kInvPi * sw[jj] * rn / (r2 * r2);
         bxx = coef * rx * rx;
         bxy = coef * rx * ry;
-        byx = bxy;
         byy = coef * ry * ry;
       }
+      const double byx = bxy + nyi * wn_x;
       bxx += nxi * wn_x;
       bxy += nxi * wn_y;
-      byx += nyi * wn_x;
       byy += nyi * wn_y;
 #pragma unroll
       for (int q = 0; q < kApplyCols; ++q) {
@@ -1544,7 +1541,27 @@ __global__ __launch_bounds__(kApplyTile) void k_apply_D(Geo g, const double* hol
     }
   }
   if (!live) return;
-  const int p3 = 3 * p;
+  double* out = part + (size_t)blockIdx.y * 2 * N * ncols;
+  for (int q = 0; q < nq; ++q) {
+    out[(size_t)(2 * i) * ncols + q0 + q] = ax[q];
+    out[(size_t)(2 * i + 1) * ncols + q0 + q] = ay[q];
+  }
+}
+
+// y[2N rows] = sum over source chunks (fixed order) + H lambda
+__global__ void k_apply_sum(Geo g, const double* hole_xy, int p, const double* x, int ncols,
+                            const double* part, int nchunk, double* y) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int N = g.N;
+  if (t >= (long long)N * ncols) return;
+  const int i = (int)(t / ncols), q = (int)(t % ncols);
+  const size_t stride = (size_t)2 * N * ncols;
+  double ax = 0.0, ay = 0.0;
+  for (int c = 0; c < nchunk; ++c) {
+    ax += part[c * stride + (size_t)(2 * i) * ncols + q];
+    ay += part[c * stride + (size_t)(2 * i + 1) * ncols + q];
+  }
+  const double xi = g.x[i], yi = g.y[i];
   const size_t base = (size_t)2 * N;
   for (int h = 0; h < p; ++h) {
     const double rx = xi - hole_xy[2 * h], ry = yi - hole_xy[2 * h + 1];
@@ -1553,19 +1570,14 @@ __global__ __launch_bounds__(kApplyTile) void k_apply_D(Geo g, const double* hol
     const double sxx = kInv4Pi * (lg + rx * rx / r2), sxy = kInv4Pi * (rx * ry / r2);
     const double syy = kInv4Pi * (lg + ry * ry / r2);
     const double rotx = kInv4Pi * (-ry) / r2, roty = kInv4Pi * rx / r2;
-    for (int q = 0; q < nq; ++q) {
-      const double a1 = x[(base + 3 * h) * ldx + q0 + q];
-      const double a2 = x[(base + 3 * h + 1) * ldx + q0 + q];
-      const double b = x[(base + 3 * h + 2) * ldx + q0 + q];
-      ax[q] += sxx * a1 + sxy * a2 + rotx * b;
-      ay[q] += sxy * a1 + syy * a2 + roty * b;
-    }
+    const double a1 = x[(base + 3 * h) * ncols + q];
+    const double a2 = x[(base + 3 * h + 1) * ncols + q];
+    const double b = x[(base + 3 * h + 2) * ncols + q];
+    ax += sxx * a1 + sxy * a2 + rotx * b;
+    ay += sxy * a1 + syy * a2 + roty * b;
   }
-  (void)p3;
-  for (int q = 0; q < nq; ++q) {
-    y[(size_t)(2 * i) * ldx + q0 + q] = ax[q];
-    y[(size_t)(2 * i + 1) * ldx + q0 + q] = ay[q];
-  }
+  y[(size_t)(2 * i) * ncols + q] = ax;
+  y[(size_t)(2 * i + 1) * ncols + q] = ay;
 }
 
 // Rows of Psi^T x - lambda: one block per (hole, mode), fixed-order sums.
@@ -1599,11 +1611,11 @@ inline unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1)
 
 // ---- launchers ---------------------------------------------------------------
 
-void launch_assemble_M(const LevelBox* boxes, int nbox, int max_m, const int* dofs,
-                       const int* fint, Geo g, int n_proxy, double ratio, hipStream_t s) {
+void launch_assemble_M(const LevelBox* boxes, int nbox, int max_m, int n_proxy, double ratio,
+                       hipStream_t s) {
   if (nbox == 0 || max_m == 0) return;
   dim3 grid(nbox, blocks_for(max_m, kBlock));
-  hipLaunchKernelGGL(k_assemble_M, grid, dim3(kBlock), 0, s, boxes, dofs, fint, g, n_proxy, ratio);
+  hipLaunchKernelGGL(k_assemble_M, grid, dim3(kBlock), 0, s, boxes, n_proxy, ratio);
 }
 
 size_t cpqr_lds_bytes(int max_m, int max_n) {
@@ -1617,28 +1629,27 @@ int cpqr_blocks_per_cu(size_t lds) {
   return nb;
 }
 
-hipError_t launch_cpqr(const LevelBox* boxes, int nbox, int G, double tol, int extra, int* perm,
+hipError_t launch_cpqr(const LevelBox* boxes, int nbox, int G, double tol, int extra,
                        int* k_out, int* kx_out, int* err, int max_m, int max_n, hipStream_t s) {
   if (nbox == 0) return hipSuccess;
   const size_t lds = cpqr_lds_bytes(max_m, max_n);
   hipLaunchKernelGGL(k_zero_bars, dim3(blocks_for(nbox, kBlock)), dim3(kBlock), 0, s, boxes, nbox, err);
   if (G <= 1) {
-    hipLaunchKernelGGL(k_cpqr, dim3(nbox), dim3(kQRThreads), lds, s, boxes, 1, tol, extra, perm,
+    hipLaunchKernelGGL(k_cpqr, dim3(nbox), dim3(kQRThreads), lds, s, boxes, 1, tol, extra,
                        k_out, kx_out, err);
     return hipGetLastError();
   }
-  void* args[] = {(void*)&boxes, (void*)&G, (void*)&tol, (void*)&extra, (void*)&perm,
+  void* args[] = {(void*)&boxes, (void*)&G, (void*)&tol, (void*)&extra,
                   (void*)&k_out, (void*)&kx_out, (void*)&err};
   return hipLaunchCooperativeKernel((const void*)k_cpqr, dim3(nbox * G), dim3(kQRThreads), args,
                                     (unsigned)lds, s);
 }
 
-void launch_assemble_abb(const LevelBox* boxes, int nbox, int max_n, const int* dofs,
-                         const int* perm, const ChildSrc* src, Geo g, double lam,
+void launch_assemble_abb(const LevelBox* boxes, int nbox, int max_n, double lam, bool use_perm,
                          hipStream_t s) {
   if (nbox == 0 || max_n == 0) return;
   dim3 grid(nbox, blocks_for((long long)max_n * max_n, kBlock));
-  hipLaunchKernelGGL(k_assemble_abb, grid, dim3(kBlock), 0, s, boxes, dofs, perm, src, g, lam);
+  hipLaunchKernelGGL(k_assemble_abb, grid, dim3(kBlock), 0, s, boxes, lam, use_perm ? 1 : 0);
 }
 
 int eliminate_blocks_per_cu() {
@@ -1841,12 +1852,29 @@ void launch_from_rows(const double* c, int nrows, int ncols, double* x, int ld, 
                      dim3(kBlock), 0, s, c, nrows, ncols, x, ld);
 }
 
+// Source chunk length so that targets x chunks gives about 2048 blocks.
+int apply_chunk(int N) {
+  const int tiles = (N + kApplyTile - 1) / kApplyTile;
+  const int want = std::max(1, 2048 / std::max(1, tiles));
+  int chunk = (N + want - 1) / want;
+  chunk = ((chunk + kApplyTile - 1) / kApplyTile) * kApplyTile;
+  return std::max(chunk, kApplyTile);
+}
+
+size_t apply_scratch_doubles(int N, int ncols) {
+  const int chunk = apply_chunk(N);
+  const int nchunk = (N + chunk - 1) / chunk;
+  return (size_t)nchunk * 2 * N * ncols;
+}
+
 void launch_apply_operator(Geo g, const int* curve_id, const double* hole_xy, int p, double lam,
-                           const double* x, int ncols, double* y, double* hole_parts,
-                           hipStream_t s) {
-  (void)hole_parts;
-  dim3 grid(blocks_for(g.N, kApplyTile), blocks_for(ncols, kApplyCols));
-  hipLaunchKernelGGL(k_apply_D, grid, dim3(kApplyTile), 0, s, g, hole_xy, p, lam, x, ncols, y);
+                           const double* x, int ncols, double* y, double* part, hipStream_t s) {
+  const int chunk = apply_chunk(g.N);
+  const int nchunk = (g.N + chunk - 1) / chunk;
+  dim3 grid(blocks_for(g.N, kApplyTile), nchunk, blocks_for(ncols, kApplyCols));
+  hipLaunchKernelGGL(k_apply_D, grid, dim3(kApplyTile), 0, s, g, lam, x, ncols, chunk, part);
+  hipLaunchKernelGGL(k_apply_sum, dim3(blocks_for((long long)g.N * ncols, kBlock)), dim3(kBlock), 0, s,
+                     g, hole_xy, p, x, ncols, part, nchunk, y);
   if (p > 0)
     hipLaunchKernelGGL(k_apply_psi, dim3(3 * p), dim3(kBlock), 0, s, g, curve_id, p, x, ncols, y);
 }

@@ -74,3 +74,20 @@ def test_update_out_of_root_rejected():
         s.update_moved_nodes(np.array([3], np.int32), np.array([[100.0, 0.0]]), g.normal[3:4],
                              g.weight[3:4], g.curvature[3:4])
     assert e.value.name == "RS_ERR_OUT_OF_ROOT"
+
+
+def test_batch_factor_equals_single():
+    """Level-synchronous factorization of several geometries in shared launches
+    gives each geometry exactly its own factorization."""
+    from paper_2001_11619_amd import factor_batch
+    from workloads import single_ellipse, workload_small
+
+    geoms = [random_holes_geometry(31 + i, 5.0, 512 + 128 * i, [128 + 64 * i] * (i + 1)) for i in range(3)]
+    geoms.append(single_ellipse(700, 1.0, 0.5))
+    geoms.append(workload_small(seed=11, n_outer=256, n_holes=2, nodes_per_hole=128, radius=3.0))
+    batch = [_solver(g, leaf_size=32) for g in geoms]
+    factor_batch(batch)
+    for g, s in zip(geoms, batch):
+        f = boundary_data(g, exterior_forces_for_geometry(g, 2, seed=7))
+        alone = _solver(g, leaf_size=32).factor()
+        assert np.array_equal(s.solve(f), alone.solve(f))
