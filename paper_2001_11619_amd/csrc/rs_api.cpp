@@ -669,16 +669,18 @@ void launch_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps) {
   }
   const int nb = (int)all.size();
   if (nb == 0) return;
+  for (int i = 0; i < nb; ++i) all[i].slot = i;
   const size_t qr_lds = cpqr_lds_bytes(max_m, max_n);
   if (qr_lds > 160 * 1024)
     throw RsError{RS_ERR_ARG, "box too large for the pivoted-QR kernel (m=" + std::to_string(max_m) +
                                   ", n=" + std::to_string(max_n) + ")"};
   // workgroups per box: spread the few large boxes near the root over the
-  // device (cooperative launch: all of them co-resident)
+  // device (cooperative launch: all of them co-resident).  Results do not
+  // depend on G: every reduction is done by one fixed workgroup.
   int G = 1, Ge = 1;
   if (nb <= c->n_cu / 4) {
     const int capq = cpqr_blocks_per_cu(qr_lds) * c->n_cu;
-    const int cape = eliminate_blocks_per_cu() * c->n_cu;
+    const int cape = eliminate_blocks_per_cu(max_n) * c->n_cu;
     if (capq > 0) G = std::min({capq / nb, std::max(1, max_n / 16), kMaxCoop});
     if (cape > 0) Ge = std::min({cape / nb, std::max(1, max_n / 8), kMaxCoop});
     if (G < 2) G = 1;
@@ -696,8 +698,11 @@ void launch_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps) {
   }
   {
     KTimer kt_(c, "cpqr");
-    HIP_CHECK(launch_cpqr(dlb, nb, G, prm.tol, kGuardExtra, c->ws_k.as<int>(), c->ws_kx.as<int>(),
-                          c->ws_err.as<int>(), max_m, max_n, s));
+    const hipError_t e = launch_cpqr(dlb, nb, G, prm.tol, kGuardExtra, c->ws_k.as<int>(),
+                                     c->ws_kx.as<int>(), c->ws_err.as<int>(), max_m, max_n, s);
+    if (e != hipSuccess)
+      throw RsError{RS_ERR_DEVICE, std::string("pivoted-QR launch failed (") + hipGetErrorString(e) +
+                                       ", boxes " + std::to_string(nb) + ", G " + std::to_string(G) + ")"};
   }
   {
     KTimer kt_(c, "assemble_abb");
@@ -708,7 +713,7 @@ void launch_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps) {
   {
     KTimer kt_(c, "eliminate");
     HIP_CHECK(launch_eliminate(dlb, nb, Ge, c->ws_k.as<int>(), c->ws_kx.as<int>(), prm.rcond_min,
-                               c->ws_status.as<int>(), c->ws_err.as<int>() + 1, s));
+                               c->ws_status.as<int>(), c->ws_err.as<int>() + 1, max_n, s));
     if (prm.precision == 1) launch_factor_to_float(dlb, nb, c->ws_k.as<int>(), s);
   }
   HIP_CHECK(hipGetLastError());

@@ -26,7 +26,7 @@ struct LevelBox {
   int n;          // active unknowns |I_B|
   int m;          // rows of the ID matrix M_B
   int nF;         // |F_int|
-  int pad;
+  int slot;       // index of the box in the level's full descriptor list (rank outputs)
   Geo geo;                 // geometry of the box's boundary (per context)
   const int* dofs;         // I_B (n), ascending
   const int* fint;         // F_int (nF)
@@ -92,9 +92,9 @@ hipError_t launch_cpqr(const LevelBox* boxes, int nbox, int G, double tol, int e
                        int* k_out, int* kx_out, int* err, int max_m, int max_n, hipStream_t s);
 void launch_assemble_abb(const LevelBox* boxes, int nbox, int max_n, double lam, bool use_perm,
                          hipStream_t s);
-int eliminate_blocks_per_cu();
+int eliminate_blocks_per_cu(int max_n);
 hipError_t launch_eliminate(const LevelBox* boxes, int nbox, int G, int* k_io, const int* kx,
-                            double rcond_min, int* status, int* err, hipStream_t s);
+                            double rcond_min, int* status, int* err, int max_n, hipStream_t s);
 void launch_gj_inverse(double* A, int n, int lda, double* Ainv, double* work,
                        double* rcond_out, int* status, hipStream_t s);
 void launch_gj_blocked(double* A, int n, double* Ainv, double* work, int* iwork, int* status,

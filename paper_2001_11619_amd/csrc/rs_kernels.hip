@@ -325,7 +325,7 @@ __global__ __launch_bounds__(kBlock) void k_assemble_M(const LevelBox* boxes, in
 // workgroup data goes through agent-scope atomics; barrier waits are bounded
 // (a timed-out wait flags an error and the kernel drains).
 constexpr int kQRThreads = 512;
-constexpr int kQRRows = 32;             // rows per lane held in registers (m <= 2048)
+constexpr int kQRRows = 24;             // rows per lane held in registers (m <= 1536)
 constexpr unsigned kSpinLimit = 1u << 22;
 
 __device__ __forceinline__ void st_relaxed(double* p, double v) {
@@ -404,7 +404,7 @@ __global__ __launch_bounds__(kQRThreads) void k_cpqr(const LevelBox* boxes, int 
   __shared__ double s_hh[2];
   __shared__ int s_dead;
   if (n == 0) {
-    if (tid == 0 && g == 0) { k_out[bidx] = 0; kx_out[bidx] = 0; }
+    if (tid == 0 && g == 0) { k_out[B.slot] = 0; kx_out[B.slot] = 0; }
     return;
   }
   double* nrm = smem;                        // n, by physical column
@@ -537,37 +537,71 @@ __global__ __launch_bounds__(kQRThreads) void k_cpqr(const LevelBox* boxes, int 
       kk = j;
       limit = min(steps, j + 1 + extra);
     }
-    // reflect the owned columns that are still to be pivoted
-    for (int t = wid; t < nown; t += NW) {
-      const int c = own[t];
-      if (done[c]) continue;
-      double* y = A + (size_t)c * m;
-      const double yj = y[j];
-      if (regs) {
-        double yr[kQRRows];
-        double ws = 0.0;
+    // reflect the owned columns that are still to be pivoted; in the register
+    // path each wave carries two columns at once so their loads overlap
+    if (regs) {
+      // compact list of this step's live owned columns, dealt two per wave
+      for (int t = wid; 2 * t < nown; t += NW) {
+        const int c0 = own[2 * t];
+        const int c1 = 2 * t + 1 < nown ? own[2 * t + 1] : -1;
+        const bool a0 = !done[c0];
+        const bool a1 = c1 >= 0 && !done[c1];
+        if (!a0 && !a1) continue;
+        double* y0 = A + (size_t)c0 * m;
+        double* y1 = A + (size_t)(a1 ? c1 : c0) * m;
+        const double yj0 = y0[j], yj1 = y1[j];
+        double r0[kQRRows], r1[kQRRows];
+        double w0 = 0.0, w1 = 0.0;
 #pragma unroll
         for (int u = 0; u < kQRRows; ++u) {
           const int i = lane + 64 * u;
           const bool in = i > j && i < m;
-          yr[u] = in ? y[i] : 0.0;
-          ws += in ? vsh[i] * yr[u] : 0.0;
+          r0[u] = (in && a0) ? y0[i] : 0.0;
+          r1[u] = (in && a1) ? y1[i] : 0.0;
         }
-        ws = wave_sum(ws) + yj;
-        const double tw = tau * ws;
-        double ns = 0.0;
+#pragma unroll
+        for (int u = 0; u < kQRRows; ++u) {
+          const int i = lane + 64 * u;
+          const double v = (i > j && i < m) ? vsh[i] : 0.0;
+          w0 += v * r0[u];
+          w1 += v * r1[u];
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+          w0 += __shfl_xor(w0, o, 64);
+          w1 += __shfl_xor(w1, o, 64);
+        }
+        const double tw0 = tau * (w0 + yj0), tw1 = tau * (w1 + yj1);
+        double n0 = 0.0, n1 = 0.0;
 #pragma unroll
         for (int u = 0; u < kQRRows; ++u) {
           const int i = lane + 64 * u;
           if (i > j && i < m) {
-            const double v = yr[u] - tw * vsh[i];
-            y[i] = v;
-            ns += v * v;
+            const double v = vsh[i];
+            const double z0 = r0[u] - tw0 * v;
+            const double z1 = r1[u] - tw1 * v;
+            if (a0) y0[i] = z0;
+            if (a1) y1[i] = z1;
+            n0 += z0 * z0;
+            n1 += z1 * z1;
           }
         }
-        ns = wave_sum(ns);
-        if (lane == 0) { y[j] = yj - tw; nrm[c] = ns; }
-      } else {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+          n0 += __shfl_xor(n0, o, 64);
+          n1 += __shfl_xor(n1, o, 64);
+        }
+        if (lane == 0) {
+          if (a0) { y0[j] = yj0 - tw0; nrm[c0] = n0; }
+          if (a1) { y1[j] = yj1 - tw1; nrm[c1] = n1; }
+        }
+      }
+    } else {
+      for (int t = wid; t < nown; t += NW) {
+        const int c = own[t];
+        if (done[c]) continue;
+        double* y = A + (size_t)c * m;
+        const double yj = y[j];
         double ws = 0.0;
         for (int i = j + 1 + lane; i < m; i += 64) ws += vsh[i] * y[i];
         ws = wave_sum(ws) + yj;
@@ -597,7 +631,7 @@ __global__ __launch_bounds__(kQRThreads) void k_cpqr(const LevelBox* boxes, int 
   }
   if (g == 0) {
     for (int c = tid; c < n; c += kQRThreads) B.perm[c] = pv[c];
-    if (tid == 0) { k_out[bidx] = kk; kx_out[bidx] = kx; }
+    if (tid == 0) { k_out[B.slot] = kk; kx_out[B.slot] = kx; }
   }
 }
 
@@ -677,6 +711,144 @@ __device__ void coop_gemm(int g, int G, int M, int N, int K, double alpha, const
   }
 }
 
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// C = beta*C0 + alpha*op(A) op(B) on FP64 matrix cores.  32 x 32 blocks of C
+// are dealt to the G workgroups of the box; in a block each of the 4 waves
+// owns a 16 x 16 tile and accumulates v_mfma_f64_16x16x4 products over K
+// chunks of 16 staged through LDS (zero padded at the edges).  Operand lanes:
+// A[l % 16][l / 16], B[l / 16][l % 16]; result lane l, register q holds
+// row 4 q + l / 16, column l % 16 of the tile.  C0 may alias C.
+constexpr int kTB = 32;   // block edge
+constexpr int kTK = 16;   // K chunk
+
+__device__ void mfma_gemm(int g, int G, int M, int N, int K, double alpha, const double* A,
+                          int lda, bool tA, const double* B, int ldb, bool tB, double beta,
+                          const double* C0, int ldc0, double* C, int ldc, double* sA, double* sB) {
+  const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
+  const int bm = (M + kTB - 1) / kTB, bn = (N + kTB - 1) / kTB;
+  const int wr = (wid >> 1) * 16, wc = (wid & 1) * 16;
+  for (int blk = g; blk < bm * bn; blk += G) {
+    const int i0 = (blk / bn) * kTB, j0 = (blk % bn) * kTB;
+    dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < K; k0 += kTK) {
+      for (int t = tid; t < kTB * kTK; t += blockDim.x) {
+        const int ii = t / kTK, kk = t % kTK;
+        const int gi = i0 + ii, gk = k0 + kk;
+        sA[ii * (kTK + 1) + kk] =
+            (gi < M && gk < K) ? (tA ? A[(size_t)gk * lda + gi] : A[(size_t)gi * lda + gk]) : 0.0;
+        const int kb = t / kTB, jj = t % kTB;
+        const int gk2 = k0 + kb, gj = j0 + jj;
+        sB[kb * (kTB + 1) + jj] =
+            (gk2 < K && gj < N) ? (tB ? B[(size_t)gj * ldb + gk2] : B[(size_t)gk2 * ldb + gj]) : 0.0;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < kTK; kk += 4) {
+        const double a = sA[(wr + (lane & 15)) * (kTK + 1) + kk + (lane >> 4)];
+        const double b = sB[(kk + (lane >> 4)) * (kTB + 1) + wc + (lane & 15)];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int gi = i0 + wr + 4 * q + (lane >> 4), gj = j0 + wc + (lane & 15);
+      if (gi < M && gj < N) {
+        double v = alpha * acc[q];
+        if (C0) v += beta * C0[(size_t)gi * ldc0 + gj];
+        C[(size_t)gi * ldc + gj] = v;
+      }
+    }
+  }
+}
+
+// In-place Gauss-Jordan sweep with partial pivoting of X (r x r) held in
+// LDS (W, row-major); the inverse of X goes to Xi (global, ld r).  One
+// workgroup.  Returns the reciprocal 1-norm condition number (0 if a pivot
+// vanished), identical in all threads.
+__device__ double lds_gj(const double* X, int r, double* W, double* Xi, double* rowj, double* colj,
+                         int* rowperm, double* red, int* ired) {
+  const int tid = threadIdx.x, NT = blockDim.x, lane = tid & 63, wid = tid >> 6;
+  for (int t = tid; t < r * r; t += NT) W[t] = X[t];
+  for (int c = tid; c < r; c += NT) rowperm[c] = c;
+  __syncthreads();
+  double n1 = 0.0;
+  for (int c = tid; c < r; c += NT) {
+    double sum = 0.0;
+    for (int i = 0; i < r; ++i) sum += fabs(W[i * r + c]);
+    n1 = fmax(n1, sum);
+  }
+  n1 = block_max(n1, red);
+  bool singular = false;
+  for (int j = 0; j < r; ++j) {
+    double best = -1.0;
+    int bi = r;
+    for (int i = j + tid; i < r; i += NT) {
+      const double v = fabs(W[i * r + j]);
+      if (v > best) { best = v; bi = i; }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_xor(best, o, 64);
+      const int oi = __shfl_xor(bi, o, 64);
+      if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+    }
+    __syncthreads();
+    if (lane == 0) { red[wid] = best; ired[wid] = bi; }
+    __syncthreads();
+    best = red[0];
+    bi = ired[0];
+    for (int w = 1; w < (NT >> 6); ++w)
+      if (red[w] > best || (red[w] == best && ired[w] < bi)) { best = red[w]; bi = ired[w]; }
+    if (!(best > 0.0)) { singular = true; break; }
+    // row interchange, then copies of the pivot row and column
+    for (int c = tid; c < r; c += NT) {
+      double a = W[j * r + c];
+      double b = W[bi * r + c];
+      if (bi != j) {
+        W[j * r + c] = b;
+        W[bi * r + c] = a;
+        a = b;
+      }
+      rowj[c] = a;
+    }
+    if (tid == 0 && bi != j) {
+      const int t = rowperm[j];
+      rowperm[j] = rowperm[bi];
+      rowperm[bi] = t;
+    }
+    __syncthreads();
+    for (int i = tid; i < r; i += NT) colj[i] = W[i * r + j];
+    __syncthreads();
+    const double inv = 1.0 / rowj[j];
+    for (int t = tid; t < r * r; t += NT) {
+      const int i = t / r, c = t % r;
+      double v;
+      if (i == j) v = (c == j) ? inv : rowj[c] * inv;
+      else if (c == j) v = -colj[i] * inv;
+      else v = W[t] - colj[i] * (rowj[c] * inv);
+      W[t] = v;
+    }
+    __syncthreads();
+  }
+  if (singular) return 0.0;
+  for (int t = tid; t < r * r; t += NT) {
+    const int i = t / r, c = t % r;
+    Xi[(size_t)i * r + rowperm[c]] = W[t];
+  }
+  __syncthreads();
+  double n2 = 0.0;
+  for (int c = tid; c < r; c += NT) {
+    double sum = 0.0;
+    for (int i = 0; i < r; ++i) sum += fabs(Xi[(size_t)i * r + c]);
+    n2 = fmax(n2, sum);
+  }
+  n2 = block_max(n2, red);
+  const double rc = 1.0 / (n1 * n2);
+  return isfinite(rc) ? rc : 0.0;
+}
+
 // Largest column 1-norm of X (n x n, ld ldx) over the box, identical in all workgroups.
 __device__ double coop_norm1(int g, int G, const double* X, int n, int ldx, double* red,
                              const LevelBox& B, unsigned& nbar, int* dead, int* err) {
@@ -697,6 +869,7 @@ __device__ double coop_norm1(int g, int G, const double* X, int n, int ldx, doub
 }
 
 constexpr int kGJP = 32;   // pivot block of the in-place Gauss-Jordan
+constexpr int kLdsGJMax = 120;   // X_RR up to this edge is inverted in LDS by one workgroup
 
 // X_RR^{-1} of the box (blocked in-place Gauss-Jordan with partial pivoting,
 // panels of kGJP columns): W holds X_RR on entry and is destroyed; Xi receives
@@ -851,10 +1024,13 @@ __device__ bool coop_gj(int g, int G, double* W, int r, double* Xi, double* Pn, 
 __global__ __launch_bounds__(kBlock) void k_eliminate(const LevelBox* boxes, int G, int* k_io,
                                                       const int* kx_in, double rcond_min,
                                                       int* status, int* err) {
+  extern __shared__ double smem_e[];
   constexpr int NW = kBlock / 64;
   __shared__ double red[NW];
   __shared__ int ired[NW];
   __shared__ int s_dead;
+  __shared__ double sA[kTB * (kTK + 1)];
+  __shared__ double sB[kTK * (kTB + 1)];
   const int bidx = blockIdx.x / G, g = blockIdx.x % G;
   const LevelBox& B = boxes[bidx];
   const int n = B.n;
@@ -862,8 +1038,8 @@ __global__ __launch_bounds__(kBlock) void k_eliminate(const LevelBox* boxes, int
   if (threadIdx.x == 0) s_dead = 0;
   __syncthreads();
   unsigned nbar = 0;
-  int k = k_io[bidx];
-  const int kx = kx_in[bidx];
+  int k = k_io[B.slot];
+  const int kx = kx_in[B.slot];
   int st = 0;
   const double* Ap = B.Ap;
   const int gt = g * kBlock + threadIdx.x, GT = G * kBlock;
@@ -896,23 +1072,40 @@ __global__ __launch_bounds__(kBlock) void k_eliminate(const LevelBox* boxes, int
     int* piv = reinterpret_cast<int*>(Dinv + kGJP * kGJP);
     int* rowperm = piv + kGJP;
     int* flag = rowperm + r + 1;
-    coop_gemm(g, G, k, r, k, -1.0, Ap, n, false, T, r, false, 1.0, Ap + k, n, Xsr, r);
-    coop_gemm(g, G, r, k, k, -1.0, T, r, true, Ap, n, false, 1.0, Ap + (size_t)k * n, n, Xrs, k);
-    coop_gemm(g, G, r, r, k, -1.0, Ap + (size_t)k * n, n, false, T, r, false, 1.0,
-              Ap + (size_t)k * n + k, n, Xrr, r);
+    mfma_gemm(g, G, k, r, k, -1.0, Ap, n, false, T, r, false, 1.0, Ap + k, n, Xsr, r, sA, sB);
+    mfma_gemm(g, G, r, k, k, -1.0, T, r, true, Ap, n, false, 1.0, Ap + (size_t)k * n, n, Xrs, k, sA, sB);
+    mfma_gemm(g, G, r, r, k, -1.0, Ap + (size_t)k * n, n, false, T, r, false, 1.0,
+              Ap + (size_t)k * n + k, n, Xrr, r, sA, sB);
     if (g == 0 && threadIdx.x == 0) *flag = 0;
     box_barrier_full(B.bar, G, nbar, &s_dead, err);
-    // X_RR -= T^T X_SR, written into W as the working copy for the inverse
-    coop_gemm(g, G, r, r, k, -1.0, T, r, true, Xsr, r, false, 1.0, Xrr, r, W, r);
+    // X_RR -= T^T X_SR
+    mfma_gemm(g, G, r, r, k, -1.0, T, r, true, Xsr, r, false, 1.0, Xrr, r, W, r, sA, sB);
     box_barrier_full(B.bar, G, nbar, &s_dead, err);
-    const double n1 = coop_norm1(g, G, W, r, r, red, B, nbar, &s_dead, err);
-    const bool ok = coop_gj(g, G, W, r, B.Xinv, Pn, Rb, Cp, Dinv, piv, rowperm, flag, red, ired, B,
-                            nbar, &s_dead, err);
     double rc = 0.0;
-    if (ok) {
-      const double n2 = coop_norm1(g, G, B.Xinv, r, r, red, B, nbar, &s_dead, err);
-      rc = 1.0 / (n1 * n2);
-      if (!isfinite(rc)) rc = 0.0;
+    // the inversion algorithm depends on r only (not on G), so a box factors
+    // identically whatever launch it is part of
+    if (r <= kLdsGJMax) {
+      if (g == 0) {
+        double* Wl = smem_e;
+        double* rowj = Wl + (size_t)r * r;
+        double* colj = rowj + r;
+        int* rp = reinterpret_cast<int*>(colj + r);
+        rc = lds_gj(W, r, Wl, B.Xinv, rowj, colj, rp, red, ired);
+        if (G > 1 && threadIdx.x == 0) st_relaxed(B.cval, rc);
+      }
+      if (G > 1) {
+        box_barrier_full(B.bar, G, nbar, &s_dead, err);
+        rc = ld_relaxed(B.cval);
+      }
+    } else {
+      const double n1 = coop_norm1(g, G, W, r, r, red, B, nbar, &s_dead, err);
+      const bool ok = coop_gj(g, G, W, r, B.Xinv, Pn, Rb, Cp, Dinv, piv, rowperm, flag, red, ired,
+                              B, nbar, &s_dead, err);
+      if (ok) {
+        const double n2 = coop_norm1(g, G, B.Xinv, r, r, red, B, nbar, &s_dead, err);
+        rc = 1.0 / (n1 * n2);
+        if (!isfinite(rc)) rc = 0.0;
+      }
     }
     if (!(rc >= rcond_min)) {
       if (k < kx) {
@@ -922,16 +1115,16 @@ __global__ __launch_bounds__(kBlock) void k_eliminate(const LevelBox* boxes, int
       }
       st = 1;
     }
-    // X_RR itself (the pre-inverse block) is not needed any more
-    coop_gemm(g, G, k, r, r, 1.0, Xsr, r, false, B.Xinv, r, false, 0.0, nullptr, 0, B.E, r);
-    coop_gemm(g, G, r, k, r, 1.0, B.Xinv, r, false, Xrs, k, false, 0.0, nullptr, 0, B.F, k);
     box_barrier_full(B.bar, G, nbar, &s_dead, err);
-    coop_gemm(g, G, k, k, r, -1.0, Xsr, r, false, B.F, k, false, 1.0, Ap, n, B.Xss, k);
+    mfma_gemm(g, G, k, r, r, 1.0, Xsr, r, false, B.Xinv, r, false, 0.0, nullptr, 0, B.E, r, sA, sB);
+    mfma_gemm(g, G, r, k, r, 1.0, B.Xinv, r, false, Xrs, k, false, 0.0, nullptr, 0, B.F, k, sA, sB);
+    box_barrier_full(B.bar, G, nbar, &s_dead, err);
+    mfma_gemm(g, G, k, k, r, -1.0, Xsr, r, false, B.F, k, false, 1.0, Ap, n, B.Xss, k, sA, sB);
     break;
   }
   if (g == 0 && threadIdx.x == 0) {
-    k_io[bidx] = k;
-    status[bidx] = st;
+    k_io[B.slot] = k;
+    status[B.slot] = st;
   }
 }
 
@@ -1436,7 +1629,7 @@ __global__ void k_factor_to_float(const LevelBox* boxes, const int* k_final) {
   const LevelBox& B = boxes[blockIdx.x];
   const int n = B.n;
   if (n == 0) return;
-  const int k = k_final[blockIdx.x], r = n - k;
+  const int k = k_final[B.slot], r = n - k;
   const int kr = k * r, rr = r * r;
   for (int t = threadIdx.x; t < kr; t += blockDim.x) {
     B.Tf[t] = (float)B.T[t];
@@ -1632,8 +1825,8 @@ int cpqr_blocks_per_cu(size_t lds) {
 hipError_t launch_cpqr(const LevelBox* boxes, int nbox, int G, double tol, int extra,
                        int* k_out, int* kx_out, int* err, int max_m, int max_n, hipStream_t s) {
   if (nbox == 0) return hipSuccess;
-  const size_t lds = cpqr_lds_bytes(max_m, max_n);
   hipLaunchKernelGGL(k_zero_bars, dim3(blocks_for(nbox, kBlock)), dim3(kBlock), 0, s, boxes, nbox, err);
+  const size_t lds = cpqr_lds_bytes(max_m, max_n);
   if (G <= 1) {
     hipLaunchKernelGGL(k_cpqr, dim3(nbox), dim3(kQRThreads), lds, s, boxes, 1, tol, extra,
                        k_out, kx_out, err);
@@ -1652,24 +1845,43 @@ void launch_assemble_abb(const LevelBox* boxes, int nbox, int max_n, double lam,
   hipLaunchKernelGGL(k_assemble_abb, grid, dim3(kBlock), 0, s, boxes, lam, use_perm ? 1 : 0);
 }
 
-int eliminate_blocks_per_cu() {
+size_t eliminate_lds_bytes(int max_n) {
+  const int r = std::min(max_n, kLdsGJMax);
+  return ((size_t)r * r + 2 * (size_t)r) * sizeof(double) + r * sizeof(int) + 64;
+}
+
+int eliminate_blocks_per_cu(int max_n) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eliminate, kBlock, 0) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eliminate, kBlock,
+                                                   eliminate_lds_bytes(max_n)) != hipSuccess)
+    return 0;
   return nb;
 }
 
 hipError_t launch_eliminate(const LevelBox* boxes, int nbox, int G, int* k_io, const int* kx,
-                            double rcond_min, int* status, int* err, hipStream_t s) {
+                            double rcond_min, int* status, int* err, int max_n, hipStream_t s) {
   if (nbox == 0) return hipSuccess;
   hipLaunchKernelGGL(k_zero_bars, dim3(blocks_for(nbox, kBlock)), dim3(kBlock), 0, s, boxes, nbox, err);
+  const size_t lds = eliminate_lds_bytes(max_n);
+  if (lds > 65536) {
+    hipFuncAttributes fa;
+    hipError_t e = hipFuncGetAttributes(&fa, (const void*)k_eliminate);
+    if (e != hipSuccess) return e;
+    if (fa.maxDynamicSharedSizeBytes < (int)lds) {
+      e = hipFuncSetAttribute((const void*)k_eliminate, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+      if (e != hipSuccess) return e;
+    }
+  }
   if (G <= 1) {
-    hipLaunchKernelGGL(k_eliminate, dim3(nbox), dim3(kBlock), 0, s, boxes, 1, k_io, kx, rcond_min,
+    hipLaunchKernelGGL(k_eliminate, dim3(nbox), dim3(kBlock), lds, s, boxes, 1, k_io, kx, rcond_min,
                        status, err);
     return hipGetLastError();
   }
   void* args[] = {(void*)&boxes, (void*)&G, (void*)&k_io, (void*)&kx, (void*)&rcond_min,
                   (void*)&status, (void*)&err};
-  return hipLaunchCooperativeKernel((const void*)k_eliminate, dim3(nbox * G), dim3(kBlock), args, 0, s);
+  return hipLaunchCooperativeKernel((const void*)k_eliminate, dim3(nbox * G), dim3(kBlock), args,
+                                    (unsigned)lds, s);
 }
 
 void launch_gj_inverse(double* A, int n, int lda, double* Ainv, double* work,
