@@ -135,7 +135,8 @@ def roofline_of(run, steps, nrhs, n_nodes, n_holes):
         "apply_operator": ("alu", "TFLOP/s", pairs * (25.0 + 8.0 * nrhs) * run["refine_iters"],
                            FP64_VECTOR_PEAK_TFLOPS),
     }
-    fam = max(ktimes, key=lambda k: ktimes[k][1]) if ktimes else None
+    dev = {k: v for k, v in ktimes.items() if not k.startswith("host:")}
+    fam = max(dev, key=lambda k: dev[k][1]) if dev else None
     if fam not in models:
         return None
     bound, unit, work, peak = models[fam]

@@ -6,19 +6,33 @@ Section 2.2 (eq. lowrank): a column-pivoted QR of a block splits its columns
 into skeleton S and redundant R with M_R ~= M_S T, T = R11^{-1} R12, to a
 tolerance eps.  Readings taken where the paper is silent:
   * pivot = remaining column of largest 2-norm, norms recomputed from the
-    trailing block at every step; exact ties go to the column that came
-    first in the block's original order;
+    trailing block at every step.  The paper says nothing about ties, and
+    mirror-symmetric node pairs make columns whose norms agree up to
+    rounding; so squared norms are compared on their leading 20 mantissa
+    bits (the low 32 bits of the float64 pattern cleared, a relative
+    quantum of 2^-20), and among the columns that tie at that precision the
+    one that came first in the block's original order is taken.  Any choice
+    within a factor 1 + 2^-20 of the largest norm keeps the rank-revealing
+    property of the pivoting;
   * the tolerance is relative: step j counts toward the rank k while
     |R_jj| > eps |R_11|.
 
 Pinned by tests/test_oracle_cpqr.py: same permutation and |R| as LAPACK
-dgeqp3 on matrices with distinct column norms, and the ID residual bound.
+dgeqp3 on matrices whose column norms are distinct at that precision, the
+tie rule, and the ID residual bound.
 """
 
 from __future__ import annotations
 
 import numpy as np
 import scipy.linalg as sla
+
+
+def pivot_key(sq_norms: np.ndarray) -> np.ndarray:
+    """Squared norms truncated to their leading 20 mantissa bits (the value
+    the pivot rule compares; non-negative inputs, so truncation is monotone)."""
+    bits = np.ascontiguousarray(sq_norms, dtype=np.float64).view(np.uint64)
+    return (bits & np.uint64(0xFFFFFFFF00000000)).view(np.float64)
 
 
 class PivotedQR:
@@ -39,7 +53,7 @@ class PivotedQR:
         j = self.steps
         A = self.A
         sub = A[j:, j:]
-        norms = np.einsum("ij,ij->j", sub, sub)
+        norms = pivot_key(np.einsum("ij,ij->j", sub, sub))
         mx = norms.max()
         cand = np.nonzero(norms == mx)[0]
         p = j + cand[np.argmin(self.perm[j + cand])]

@@ -42,10 +42,22 @@ struct RsError {
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  // pinned host mirror used by upload(): the copy out of it is asynchronous,
+  // `ev` marks its completion before the mirror is written again
+  void* host = nullptr;
+  size_t host_bytes = 0;
+  hipEvent_t ev = nullptr;
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  ~DevBuf() { release(); }
+  ~DevBuf() {
+    release();
+    if (ev) {
+      (void)hipEventSynchronize(ev);
+      (void)hipEventDestroy(ev);
+    }
+    if (host) (void)hipHostFree(host);
+  }
   void release() {
     if (p) (void)hipFree(p);
     p = nullptr;
@@ -58,19 +70,60 @@ struct DevBuf {
     HIP_CHECK(hipMalloc(&p, nb));
     bytes = nb;
   }
+  // Copy nb bytes into the mirror once the previous copy out of it is done.
+  void stage(const void* src, size_t nb) {
+    if (ev) HIP_CHECK(hipEventSynchronize(ev));
+    else HIP_CHECK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    if (nb > host_bytes) {
+      if (host) HIP_CHECK(hipHostFree(host));
+      host = nullptr;
+      host_bytes = 0;
+      const size_t cap = std::max<size_t>(nb + nb / 2, 4096);
+      HIP_CHECK(hipHostMalloc(&host, cap, hipHostMallocDefault));
+      host_bytes = cap;
+    }
+    std::memcpy(host, src, nb);
+  }
   template <class T>
   T* as() const { return static_cast<T*>(p); }
 };
 
-// Host-to-device copy on the context stream; returns once the host buffer
-// may be reused.
+// Host-to-device copy on the context stream through the buffer's pinned
+// mirror; returns at once (the host vector may be reused immediately).
 template <class T>
 void upload(DevBuf& b, const std::vector<T>& v, hipStream_t s) {
-  b.ensure(std::max<size_t>(v.size() * sizeof(T), 16));
-  if (v.empty()) return;
-  HIP_CHECK(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
-  HIP_CHECK(hipStreamSynchronize(s));
+  const size_t nb = v.size() * sizeof(T);
+  b.ensure(std::max<size_t>(nb, 16));
+  if (nb == 0) return;
+  b.stage(v.data(), nb);
+  HIP_CHECK(hipMemcpyAsync(b.p, b.host, nb, hipMemcpyHostToDevice, s));
+  HIP_CHECK(hipEventRecord(b.ev, s));
 }
+
+// Pinned host buffer for device-to-host copies that stay asynchronous.
+struct PinHost {
+  void* p = nullptr;
+  size_t bytes = 0;
+  PinHost() = default;
+  PinHost(const PinHost&) = delete;
+  PinHost& operator=(const PinHost&) = delete;
+  ~PinHost() {
+    if (p) (void)hipHostFree(p);
+  }
+  template <class T>
+  T* get(size_t n) {   // contents are not kept when the buffer grows
+    const size_t nb = n * sizeof(T);
+    if (nb > bytes) {
+      if (p) HIP_CHECK(hipHostFree(p));
+      p = nullptr;
+      bytes = 0;
+      const size_t cap = std::max<size_t>(nb + nb / 2, 4096);
+      HIP_CHECK(hipHostMalloc(&p, cap, hipHostMallocDefault));
+      bytes = cap;
+    }
+    return static_cast<T*>(p);
+  }
+};
 
 struct Box {
   int level = 0;
@@ -80,6 +133,11 @@ struct Box {
   int child[4] = {-1, -1, -1, -1};
   int nchild = 0;
   std::vector<int> nodes;
+  std::vector<int> dofs;        // leaf: its unknowns, ascending
+  // boxes whose square comes within the proxy radius of this box's centre:
+  // same-level boxes and coarser leaves (the only holders of active unknowns
+  // that can lie inside the proxy circle when this box is compressed)
+  std::vector<int> near_same, near_leaf;
   bool leaf() const { return nchild == 0; }
 };
 
@@ -141,12 +199,15 @@ struct rs_ctx {
   bool factored = false;
   std::vector<BoxFac> fac;
   std::map<int, std::unique_ptr<DevBuf>> arenas;   // factor storage, one per level launch
+  std::vector<std::unique_ptr<DevBuf>> arena_pool;  // released arenas kept for reuse
   int next_arena = 0;
   std::vector<char> recomputed;   // per box of the current tree
+  std::vector<int> lvl_pos;       // host scratch of prepare_level
+  PinHost h_rank, h_perm, h_small;  // pinned read-back buffers
   const OldState* old = nullptr;  // set while an update runs
   // level workspaces (reused level to level)
   DevBuf ws_M, ws_R, ws_A, ws_scr, ws_boxes, ws_dofs, ws_fint, ws_src, ws_perm, ws_k, ws_kx,
-      ws_status, ws_coop, ws_err;
+      ws_status, ws_coop, ws_err, ws_work, ws_fblist, ws_tasks, ws_tq, ws_work16;
   int n_cu = 0;                   // compute units of the device
   // root
   std::vector<int> I0;
@@ -226,8 +287,9 @@ struct KTimer {
   rs_ctx* c;
   int fam = -1;
   hipEvent_t a{};
-  KTimer(rs_ctx* ctx, const char* name) : c(ctx) {
-    if (!c->timing) return;
+  // detail: a sub-phase, timed only in per-level mode
+  KTimer(rs_ctx* ctx, const char* name, bool detail = false) : c(ctx) {
+    if (!c->timing || (detail && c->timing != 2)) return;
     if (c->timing == 2 && c->cur_level >= 0) {
       const std::string full = std::string(name) + "@L" + std::to_string(c->cur_level);
       fam = family(c, full.c_str());
@@ -250,6 +312,23 @@ struct KTimer {
   }
 };
 
+// Wall time of a host phase (name "host:..."), accumulated when timing is on.
+struct HTimer {
+  rs_ctx* c;
+  int fam = -1;
+  std::chrono::steady_clock::time_point t0;
+  HTimer(rs_ctx* ctx, const char* name) : c(ctx) {
+    if (!c->timing) return;
+    fam = family(c, name);
+    t0 = std::chrono::steady_clock::now();
+  }
+  ~HTimer() {
+    if (fam < 0) return;
+    c->fam_ms[fam] += 1e3 * std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    c->fam_launches[fam] += 1;
+  }
+};
+
 // Resolve recorded event pairs; call after the stream has been synchronised.
 void resolve_timers(rs_ctx* c) {
   for (auto& p : c->pending) {
@@ -261,6 +340,62 @@ void resolve_timers(rs_ctx* c) {
     c->event_pool.push_back(p.b);
   }
   c->pending.clear();
+}
+
+// Leaf unknowns and the near-box lists of every box (static for a tree).  A
+// box is listed when the distance from the compressed box's centre to its
+// square is at most the proxy radius (with a relative margin of 1e-9, so that
+// rounding in box centres never drops a box whose points may pass the strict
+// inside test).
+void build_neighbors(rs_ctx* c) {
+  std::vector<std::unordered_map<long long, int>> cells(c->L + 1);
+  for (size_t bi = 0; bi < c->boxes.size(); ++bi) {
+    const Box& B = c->boxes[bi];
+    cells[B.level][key2(B.ix, B.iy)] = (int)bi;
+  }
+  const double ratio = c->prm.proxy_ratio;
+  auto near = [](const Box& B, const Box& Q, double rp) {
+    const double h = 0.5 * Q.side;
+    const double ex = std::max(0.0, std::fabs(B.cx - Q.cx) - h);
+    const double ey = std::max(0.0, std::fabs(B.cy - Q.cy) - h);
+    return ex * ex + ey * ey <= rp * rp * (1.0 + 1e-9);
+  };
+  for (size_t bi = 0; bi < c->boxes.size(); ++bi) {
+    Box& B = c->boxes[bi];
+    B.dofs.clear();
+    B.near_same.clear();
+    B.near_leaf.clear();
+    if (B.leaf()) {
+      B.dofs.reserve(2 * B.nodes.size());
+      for (int j : B.nodes) {
+        B.dofs.push_back(2 * j);
+        B.dofs.push_back(2 * j + 1);
+      }
+      std::sort(B.dofs.begin(), B.dofs.end());
+    }
+    if (B.level == 0) continue;
+    const int l = B.level;
+    const double rp = ratio * B.side;
+    const long long D = (long long)std::floor(ratio + 0.5) + 1;
+    for (long long dx = -D; dx <= D; ++dx)
+      for (long long dy = -D; dy <= D; ++dy) {
+        if (dx == 0 && dy == 0) continue;
+        auto it = cells[l].find(key2(B.ix + dx, B.iy + dy));
+        if (it != cells[l].end() && near(B, c->boxes[it->second], rp)) B.near_same.push_back(it->second);
+      }
+    for (int lc = 0; lc < l; ++lc) {
+      const long long ax = B.ix >> (l - lc), ay = B.iy >> (l - lc);
+      const double sc = std::ldexp(B.side, l - lc);
+      const long long Dc = (long long)std::ceil(rp / sc) + 1;
+      for (long long dx = -Dc; dx <= Dc; ++dx)
+        for (long long dy = -Dc; dy <= Dc; ++dy) {
+          auto it = cells[lc].find(key2(ax + dx, ay + dy));
+          if (it == cells[lc].end()) continue;
+          const Box& Q = c->boxes[it->second];
+          if (Q.leaf() && near(B, Q, rp)) B.near_leaf.push_back(it->second);
+        }
+    }
+  }
 }
 
 void build_tree(rs_ctx* c) {
@@ -321,6 +456,7 @@ void build_tree(rs_ctx* c) {
   }
   c->L = 0;
   for (const Box& b : c->boxes) c->L = std::max(c->L, b.level);
+  build_neighbors(c);
 }
 
 std::vector<int> skeleton_of(const BoxFac& f) {
@@ -335,24 +471,13 @@ std::vector<int> redundant_of(const BoxFac& f) {
   return r;
 }
 
-std::vector<int> leaf_dofs(const Box& b) {
-  std::vector<int> d;
-  d.reserve(2 * b.nodes.size());
-  for (int j : b.nodes) {
-    d.push_back(2 * j);
-    d.push_back(2 * j + 1);
-  }
-  std::sort(d.begin(), d.end());
-  return d;
-}
-
 // Unknowns of box b and, for a parent, where each one sits in its child's X_SS.
 void box_unknowns(const rs_ctx* c, int b, std::vector<int>& I, std::vector<ChildSrc>* src) {
   const Box& B = c->boxes[b];
   I.clear();
   if (src) src->clear();
   if (B.leaf()) {
-    I = leaf_dofs(B);
+    I = B.dofs;
     return;
   }
   struct E { int dof; int child; int idx; };
@@ -430,10 +555,33 @@ struct LevelPrep {
 
 constexpr int kMaxCoop = 64;     // most workgroups per box in the cooperative kernels
 
+// A factor arena of at least `bytes`: the smallest pooled one that fits, else
+// the largest pooled one grown, else a new one.  Work that read a pooled arena
+// has completed (every entry point returns after its device work).
+std::unique_ptr<DevBuf> take_arena(rs_ctx* c, size_t bytes) {
+  auto& pool = c->arena_pool;
+  int best = -1, largest = -1;
+  for (int i = 0; i < (int)pool.size(); ++i) {
+    if (pool[i]->bytes >= bytes && (best < 0 || pool[i]->bytes < pool[best]->bytes)) best = i;
+    if (largest < 0 || pool[i]->bytes > pool[largest]->bytes) largest = i;
+  }
+  const int pick = best >= 0 ? best : largest;
+  std::unique_ptr<DevBuf> a;
+  if (pick >= 0) {
+    a = std::move(pool[pick]);
+    pool.erase(pool.begin() + pick);
+  } else {
+    a = std::make_unique<DevBuf>();
+  }
+  a->ensure(bytes);
+  return a;
+}
+
 // Host part of one level for one context: unknowns, near fields, reuse
 // decisions, workspace and arena allocation, uploads of the index lists.
 void prepare_level(rs_ctx* c, int l, const std::vector<int>& ids, const std::vector<char>& active,
                    LevelPrep& P) {
+  HTimer ht_(c, "host:prepare");
   const rs_params& prm = c->prm;
   hipStream_t s = c->stream;
   Geo g;
@@ -443,20 +591,15 @@ void prepare_level(rs_ctx* c, int l, const std::vector<int>& ids, const std::vec
   std::vector<std::vector<int>> Is(ids.size());
   std::vector<std::vector<ChildSrc>> srcs(ids.size());
   for (size_t t = 0; t < ids.size(); ++t) box_unknowns(c, ids[t], Is[t], &srcs[t]);
-  // cell map of this level and of coarser leaves
-  std::vector<std::unordered_map<long long, int>> cells(l + 1);
-  for (size_t bi = 0; bi < c->boxes.size(); ++bi) {
-    const Box& B = c->boxes[bi];
-    if (B.level == l) cells[l][key2(B.ix, B.iy)] = (int)bi;
-    else if (B.level < l && B.leaf()) cells[B.level][key2(B.ix, B.iy)] = (int)bi;
-  }
-  std::unordered_map<int, int> pos_of;
+  // position of each box of this level in ids (-1: other levels)
+  std::vector<int>& pos_of = c->lvl_pos;
+  pos_of.assign(c->boxes.size(), -1);
   for (size_t t = 0; t < ids.size(); ++t) pos_of[ids[t]] = (int)t;
   std::vector<int> dofs, fint;
   std::vector<ChildSrc> src_all;
   std::vector<int> soff;
   size_t totM = 0, totN2 = 0, totArena = 0, totScr = 0;
-  std::vector<int> cand;
+  std::vector<int> F;
   for (size_t t = 0; t < ids.size(); ++t) {
     const int b = ids[t];
     const Box& B = c->boxes[b];
@@ -473,38 +616,19 @@ void prepare_level(rs_ctx* c, int l, const std::vector<int>& ids, const std::vec
     // near field F_int: active unknowns strictly inside the proxy circle, not in I_B
     const double rp = prm.proxy_ratio * B.side;
     const double rp2 = rp * rp;
-    cand.clear();
-    for (long long dx = -2; dx <= 2; ++dx)
-      for (long long dy = -2; dy <= 2; ++dy) {
-        if (dx == 0 && dy == 0) continue;
-        auto it = cells[l].find(key2(B.ix + dx, B.iy + dy));
-        if (it == cells[l].end()) continue;
-        auto pit = pos_of.find(it->second);
-        if (pit == pos_of.end()) continue;
-        for (int d : Is[pit->second]) cand.push_back(d);
+    F.clear();
+    auto take = [&](const std::vector<int>& cand) {
+      for (int d : cand) {
+        if (!active[d]) continue;
+        const int j = d >> 1;
+        const double ddx = c->x[j] - B.cx, ddy = c->y[j] - B.cy;
+        if (ddx * ddx + ddy * ddy < rp2) F.push_back(d);
       }
-    for (int lc = 0; lc < l; ++lc) {
-      const long long ax = B.ix >> (l - lc), ay = B.iy >> (l - lc);
-      for (long long dx = -1; dx <= 1; ++dx)
-        for (long long dy = -1; dy <= 1; ++dy) {
-          auto it = cells[lc].find(key2(ax + dx, ay + dy));
-          if (it == cells[lc].end()) continue;
-          const Box& C = c->boxes[it->second];
-          for (int j : C.nodes) {
-            cand.push_back(2 * j);
-            cand.push_back(2 * j + 1);
-          }
-        }
-    }
-    std::vector<int> F;
-    for (int d : cand) {
-      if (!active[d]) continue;
-      const int j = d >> 1;
-      const double ddx = c->x[j] - B.cx, ddy = c->y[j] - B.cy;
-      if (ddx * ddx + ddy * ddy < rp2) F.push_back(d);
-    }
+    };
+    for (int q : B.near_same)
+      if (pos_of[q] >= 0) take(Is[pos_of[q]]);
+    for (int q : B.near_leaf) take(c->boxes[q].dofs);
     std::sort(F.begin(), F.end());
-    F.erase(std::unique(F.begin(), F.end()), F.end());
     if (c->old && !compress_needed(c, b, F)) {
       // every input of this box's compression is unchanged: keep its factors
       const OldState& O = *c->old;
@@ -551,9 +675,8 @@ void prepare_level(rs_ctx* c, int l, const std::vector<int>& ids, const std::vec
   for (const LevelBox& x : P.lb) totCoop += 8 + 2 + 3 * (size_t)kMaxCoop + (size_t)x.m;
   c->ws_coop.ensure(totCoop * sizeof(double));
   P.aid = c->next_arena++;
-  c->arenas[P.aid] = std::make_unique<DevBuf>();
+  c->arenas[P.aid] = take_arena(c, totArena * sizeof(double));
   DevBuf* arena = c->arenas[P.aid].get();
-  arena->ensure(totArena * sizeof(double));
   upload(c->ws_dofs, dofs, s);
   upload(c->ws_fint, fint, s);
   upload(c->ws_src, src_all, s);
@@ -653,6 +776,24 @@ void finish_level(rs_ctx* c, LevelPrep& P, const int* k0, const int* kk, const i
   }
 }
 
+// Pivoted-QR route of an m x n ID matrix (depends on m and n only):
+//   1  the 16-lane kernel on M_B itself (m <= 256, n <= 128);
+//   2  row reduction by 256-row blocks, then the 16-lane kernel on the stack
+//      of factors (n <= 128): h = rows per first-round block, P[r] = factors
+//      left after round r;
+//   0  otherwise (the 64-lane register kernel or the memory-resident one).
+int qr_route(int m, int n, int& h, std::vector<int>& P) {
+  auto fits16 = [](int rows, int cols) { return rows <= 16 * kR16MaxRU && cols <= kR16MaxN; };
+  P.clear();
+  if (n == 0 || n > kR16MaxN) return 0;
+  if (fits16(m, n)) return 1;
+  h = 16 * kR16MaxRU;
+  const int s = h / n;
+  P.push_back((m + h - 1) / h);
+  while (!fits16(P.back() * n, n)) P.push_back((P.back() + s - 1) / s);
+  return 2;
+}
+
 // One launch per kernel over the boxes of all contexts at this level (the
 // lead context provides the stream, the descriptor array and the rank arrays).
 void launch_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps) {
@@ -670,23 +811,141 @@ void launch_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps) {
   const int nb = (int)all.size();
   if (nb == 0) return;
   for (int i = 0; i < nb; ++i) all[i].slot = i;
-  const size_t qr_lds = cpqr_lds_bytes(max_m, max_n);
-  if (qr_lds > 160 * 1024)
-    throw RsError{RS_ERR_ARG, "box too large for the pivoted-QR kernel (m=" + std::to_string(max_m) +
-                                  ", n=" + std::to_string(max_n) + ")"};
-  // workgroups per box: spread the few large boxes near the root over the
-  // device (cooperative launch: all of them co-resident).  Results do not
-  // depend on G: every reduction is done by one fixed workgroup.
+  // Pivoted-QR routes (depend on m and n only): most boxes are reduced by
+  // blocks of rows to a stack of triangular factors (which has the same
+  // pivots, ranks and R up to row signs) and factored by one workgroup.
+  std::vector<QRTask> tasks;
+  std::vector<int> round_first{0};
+  std::vector<int4> work16;
+  std::vector<int> route(nb, 0);
+  {
+    std::vector<std::vector<int>> plans(nb);
+    std::vector<int> hrows(nb, 0);
+    size_t tq = 0;
+    int rounds = 0;
+    for (int i = 0; i < nb; ++i) {
+      all[i].Mq = all[i].M;
+      all[i].mq = all[i].m;
+      route[i] = qr_route(all[i].m, all[i].n, hrows[i], plans[i]);
+      if (route[i] == 2) {
+        const size_t n2 = (size_t)all[i].n * all[i].n;
+        tq += n2 * (plans[i][0] + (plans[i].size() > 1 ? plans[i][1] : 0));
+        rounds = std::max(rounds, (int)plans[i].size());
+      }
+    }
+    c->ws_tq.ensure(std::max<size_t>(tq, 1) * sizeof(double));
+    std::vector<std::vector<QRTask>> by_round(rounds);
+    double* base = c->ws_tq.as<double>();
+    for (int i = 0; i < nb; ++i) {
+      LevelBox& x = all[i];
+      if (route[i] == 2) {
+        const std::vector<int>& P = plans[i];
+        const int n = x.n, h = hrows[i], s_per = h / n;
+        double* buf[2] = {base, base + (size_t)n * n * P[0]};
+        base += (size_t)n * n * (P[0] + (P.size() > 1 ? P[1] : 0));
+        for (int b = 0; b < P[0]; ++b) {
+          const int rows = std::min(h, x.m - b * h);
+          // the row class covers the n output rows too (a short last block)
+          by_round[0].push_back(QRTask{x.M + (size_t)b * h, buf[0] + (size_t)b * n, x.m, P[0] * n, rows, n,
+                                       r16_row_class(std::max(rows, n)), 0});
+        }
+        for (size_t r = 1; r < P.size(); ++r) {
+          const double* in = buf[(r - 1) & 1];
+          double* out = buf[r & 1];
+          for (int t = 0; t < P[r]; ++t) {
+            const int cnt = std::min(s_per, P[r - 1] - t * s_per);
+            by_round[r].push_back(QRTask{in + (size_t)t * s_per * n, out + (size_t)t * n, P[r - 1] * n,
+                                         P[r] * n, cnt * n, n, r16_row_class(std::max(cnt * n, n)), 0});
+          }
+        }
+        x.Mq = buf[(P.size() - 1) & 1];
+        x.mq = P.back() * n;
+      }
+      if (route[i]) work16.push_back(make_int4(i, 0, 1, r16_row_class(x.mq)));
+    }
+    for (auto& r : by_round) {
+      tasks.insert(tasks.end(), r.begin(), r.end());
+      round_first.push_back((int)tasks.size());
+    }
+  }
+  // Pivoted-QR plan.  Boxes whose (reduced) matrix has at most 1536 rows
+  // take the register-resident kernel with the fewest workgroups that hold
+  // their columns (G = 1: an ordinary launch; G > 1: cooperative launches of
+  // at most the resident capacity); taller ones take the memory-resident
+  // kernel.  Neither result depends on G; which kernel a box takes depends on
+  // its m and n only.
+  std::vector<int4> work;
+  std::vector<int> fb;
+  std::vector<std::pair<int, int>> coop;      // (first work item, count)
+  int fb_m = 0, fb_n = 0, rq_ru = 2, rq_n = 1;
+  {
+    std::vector<int4> wide;
+    for (int i = 0; i < nb; ++i) {
+      const LevelBox& x = all[i];
+      if (route[i]) continue;
+      if (x.mq > 64 * kRQMaxRU) {
+        fb.push_back(i);
+        fb_m = std::max(fb_m, x.m);
+        fb_n = std::max(fb_n, x.n);
+        continue;
+      }
+      const int ru = rq_row_class(x.mq);
+      const int per = kRQWaves * rq_cols_per_wave(ru);
+      const int G = std::max(1, (x.n + per - 1) / per);
+      if (G > kMaxCoop) {
+        fb.push_back(i);
+        fb_m = std::max(fb_m, x.m);
+        fb_n = std::max(fb_n, x.n);
+        continue;
+      }
+      rq_ru = std::max(rq_ru, ru);
+      rq_n = std::max(rq_n, x.n);
+      if (G == 1) work.push_back(make_int4(i, 0, 1, ru));
+      else wide.push_back(make_int4(i, 0, G, ru));
+    }
+    const size_t lds = cpqr_reg_lds_bytes(rq_ru, rq_n);
+    const int cap = cpqr_reg_blocks_per_cu(lds) * c->n_cu;
+    int first = (int)work.size(), used = 0;
+    for (const int4& w : wide) {
+      if (w.z > cap)
+        throw RsError{RS_ERR_ARG, "box too large for the pivoted-QR kernel (m=" + std::to_string(all[w.x].m) +
+                                      ", n=" + std::to_string(all[w.x].n) + ")"};
+      if (used + w.z > cap) {
+        coop.push_back({first, used});
+        first = (int)work.size();
+        used = 0;
+      }
+      for (int g = 0; g < w.z; ++g) work.push_back(make_int4(w.x, g, w.z, w.w));
+      used += w.z;
+    }
+    if (used) coop.push_back({first, used});
+  }
+  const size_t rq_lds = cpqr_reg_lds_bytes(rq_ru, rq_n);
+  const size_t qr_lds = cpqr_lds_bytes(fb_m, fb_n);
+  if (!fb.empty() && qr_lds > 160 * 1024)
+    throw RsError{RS_ERR_ARG, "box too large for the pivoted-QR kernel (m=" + std::to_string(fb_m) +
+                                  ", n=" + std::to_string(fb_n) + ")"};
+  // workgroups per box for the memory-resident QR and the elimination: spread
+  // the few large boxes near the root over the device (cooperative launch: all
+  // of them co-resident).  Results do not depend on G: every reduction is done
+  // by one fixed workgroup.
   int G = 1, Ge = 1;
-  if (nb <= c->n_cu / 4) {
+  const int nfb = (int)fb.size();
+  if (nfb && nfb <= c->n_cu / 4) {
     const int capq = cpqr_blocks_per_cu(qr_lds) * c->n_cu;
-    const int cape = eliminate_blocks_per_cu(max_n) * c->n_cu;
-    if (capq > 0) G = std::min({capq / nb, std::max(1, max_n / 16), kMaxCoop});
-    if (cape > 0) Ge = std::min({cape / nb, std::max(1, max_n / 8), kMaxCoop});
+    if (capq > 0) G = std::min({capq / nfb, std::max(1, fb_n / 16), kMaxCoop});
     if (G < 2) G = 1;
+  }
+  if (nb <= c->n_cu / 4) {
+    const int cape = eliminate_blocks_per_cu(max_n) * c->n_cu;
+    if (cape > 0) Ge = std::min({cape / nb, std::max(1, max_n / 8), kMaxCoop});
     if (Ge < 2) Ge = 1;
   }
   upload(c->ws_boxes, all, s);
+  upload(c->ws_work, work, s);
+  upload(c->ws_work16, work16, s);
+  upload(c->ws_tasks, tasks, s);
+  upload(c->ws_fblist, fb, s);
   c->ws_k.ensure(nb * sizeof(int));
   c->ws_kx.ensure(nb * sizeof(int));
   c->ws_status.ensure(nb * sizeof(int));
@@ -698,18 +957,52 @@ void launch_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps) {
   }
   {
     KTimer kt_(c, "cpqr");
-    const hipError_t e = launch_cpqr(dlb, nb, G, prm.tol, kGuardExtra, c->ws_k.as<int>(),
-                                     c->ws_kx.as<int>(), c->ws_err.as<int>(), max_m, max_n, s);
-    if (e != hipSuccess)
-      throw RsError{RS_ERR_DEVICE, std::string("pivoted-QR launch failed (") + hipGetErrorString(e) +
-                                       ", boxes " + std::to_string(nb) + ", G " + std::to_string(G) + ")"};
+    launch_zero_bars(dlb, nb, c->ws_err.as<int>(), s);
+    for (size_t r = 0; r + 1 < round_first.size(); ++r) {
+      KTimer kt2_(c, "cpqr.rows", true);
+      launch_tsqr(c->ws_tasks.as<QRTask>() + round_first[r], round_first[r + 1] - round_first[r], s);
+    }
+    const int4* dw = c->ws_work.as<int4>();
+    const int nA = coop.empty() ? (int)work.size() : coop.front().first;
+    auto check = [&](hipError_t e, const char* what, int blocks) {
+      if (e != hipSuccess)
+        throw RsError{RS_ERR_DEVICE, std::string("pivoted-QR launch failed (") + what + ", " +
+                                         hipGetErrorString(e) + ", blocks " + std::to_string(blocks) + ")"};
+    };
+    {
+      KTimer kt2_(c, "cpqr.r16", true);
+      check(launch_cpqr16(dlb, c->ws_work16.as<int4>(), (int)work16.size(), prm.tol, kGuardExtra,
+                          c->ws_k.as<int>(), c->ws_kx.as<int>(), c->ws_err.as<int>(), s),
+            "16-lane", (int)work16.size());
+    }
+    {
+      KTimer kt2_(c, "cpqr.reg", true);
+      check(launch_cpqr_reg(dlb, dw, nA, false, prm.tol, kGuardExtra, c->ws_k.as<int>(), c->ws_kx.as<int>(),
+                            c->ws_err.as<int>(), rq_lds, s), "register", nA);
+    }
+    for (const auto& ch : coop) {
+      KTimer kt2_(c, "cpqr.coop", true);
+      check(launch_cpqr_reg(dlb, dw + ch.first, ch.second, true, prm.tol, kGuardExtra, c->ws_k.as<int>(),
+                            c->ws_kx.as<int>(), c->ws_err.as<int>(), rq_lds, s), "register, cooperative",
+            ch.second);
+    }
+    {
+      KTimer kt2_(c, "cpqr.mem", true);
+      check(launch_cpqr(dlb, c->ws_fblist.as<int>(), nfb, G, prm.tol, kGuardExtra, c->ws_k.as<int>(),
+                        c->ws_kx.as<int>(), c->ws_err.as<int>(), fb_m, fb_n, s), "memory", nfb * G);
+    }
   }
   {
     KTimer kt_(c, "assemble_abb");
     launch_assemble_abb(dlb, nb, max_n, prm.lambda, true, s);
   }
-  std::vector<int> k0(nb), kk(nb), st(nb);
-  HIP_CHECK(hipMemcpyAsync(k0.data(), c->ws_k.p, nb * sizeof(int), hipMemcpyDeviceToHost, s));
+  // read-backs into pinned memory stay asynchronous: one wait per level
+  int* hk = c->h_rank.get<int>(3 * (size_t)nb + 3);
+  int* k0 = hk;
+  int* kk = hk + nb;
+  int* st = hk + 2 * (size_t)nb;
+  int* qr_err = hk + 3 * (size_t)nb;
+  HIP_CHECK(hipMemcpyAsync(k0, c->ws_k.p, nb * sizeof(int), hipMemcpyDeviceToHost, s));
   {
     KTimer kt_(c, "eliminate");
     HIP_CHECK(launch_eliminate(dlb, nb, Ge, c->ws_k.as<int>(), c->ws_kx.as<int>(), prm.rcond_min,
@@ -717,28 +1010,31 @@ void launch_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps) {
     if (prm.precision == 1) launch_factor_to_float(dlb, nb, c->ws_k.as<int>(), s);
   }
   HIP_CHECK(hipGetLastError());
-  int qr_err[2] = {0, 0};
-  HIP_CHECK(hipMemcpyAsync(qr_err, c->ws_err.p, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
-  HIP_CHECK(hipMemcpyAsync(kk.data(), c->ws_k.p, nb * sizeof(int), hipMemcpyDeviceToHost, s));
-  HIP_CHECK(hipMemcpyAsync(st.data(), c->ws_status.p, nb * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipMemcpyAsync(qr_err, c->ws_err.p, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipMemcpyAsync(kk, c->ws_k.p, nb * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipMemcpyAsync(st, c->ws_status.p, nb * sizeof(int), hipMemcpyDeviceToHost, s));
+  std::vector<int*> hperm(cs.size(), nullptr);
   for (size_t i = 0; i < cs.size(); ++i) {
     LevelPrep& P = preps[i];
     if (P.lb.empty()) continue;
-    size_t tot = 0;
-    for (const LevelBox& x : P.lb) tot += x.n;
-    P.perm.resize(P.doff.back() + P.lb.back().n);
-    HIP_CHECK(hipMemcpyAsync(P.perm.data(), cs[i]->ws_perm.p, P.perm.size() * sizeof(int),
-                             hipMemcpyDeviceToHost, s));
-    (void)tot;
+    const size_t np = P.doff.back() + P.lb.back().n;
+    hperm[i] = cs[i]->h_perm.get<int>(np);
+    HIP_CHECK(hipMemcpyAsync(hperm[i], cs[i]->ws_perm.p, np * sizeof(int), hipMemcpyDeviceToHost, s));
   }
-  HIP_CHECK(hipStreamSynchronize(s));
+  {
+    HTimer ht_(c, "host:level_wait");
+    HIP_CHECK(hipStreamSynchronize(s));
+  }
+  for (size_t i = 0; i < cs.size(); ++i)
+    if (hperm[i]) preps[i].perm.assign(hperm[i], hperm[i] + preps[i].doff.back() + preps[i].lb.back().n);
   resolve_timers(c);
+  if (qr_err[2]) throw RsError{RS_ERR_ARG, "non-finite entries in an ID matrix (coincident nodes?)"};
   if (qr_err[0] || qr_err[1]) throw RsError{RS_ERR_DEVICE, "box barrier timed out"};
   for (size_t i = 0; i < cs.size(); ++i) {
     LevelPrep& P = preps[i];
     if (P.lb.empty()) continue;
     std::vector<int> done;
-    finish_level(cs[i], P, k0.data() + P.first, kk.data() + P.first, st.data() + P.first, done);
+    finish_level(cs[i], P, k0 + P.first, kk + P.first, st + P.first, done);
   }
 }
 
@@ -835,6 +1131,7 @@ void sweep_all(rs_ctx* c, T* buf, int ncols, int mode) {
 }
 
 void factor_root(rs_ctx* c) {
+  HTimer ht_(c, "host:root");
   hipStream_t s = c->stream;
   Geo g;
   geo_of(c, g);
@@ -928,15 +1225,24 @@ void factor_root(rs_ctx* c) {
   c->stats.root_skeleton = n0;
 }
 
-// Free factor arenas no box refers to any more.
+// Return factor arenas no box refers to any more to the pool.
 void collect_arenas(rs_ctx* c) {
   std::vector<char> used(c->next_arena, 0);
   for (const BoxFac& f : c->fac)
     if (f.active && f.arena >= 0) used[f.arena] = 1;
   for (auto it = c->arenas.begin(); it != c->arenas.end();) {
-    if (!used[it->first]) it = c->arenas.erase(it);
-    else ++it;
+    if (!used[it->first]) {
+      c->arena_pool.push_back(std::move(it->second));
+      it = c->arenas.erase(it);
+    } else {
+      ++it;
+    }
   }
+}
+
+void release_all_arenas(rs_ctx* c) {
+  for (auto& a : c->arenas) c->arena_pool.push_back(std::move(a.second));
+  c->arenas.clear();
 }
 
 // Factor several contexts level-synchronously: every level is one launch per
@@ -949,7 +1255,7 @@ void do_factor_multi(std::vector<rs_ctx*>& cs) {
   std::vector<std::vector<std::vector<int>>> by_level(nc);
   for (size_t i = 0; i < nc; ++i) {
     rs_ctx* c = cs[i];
-    if (!c->old) c->arenas.clear();
+    if (!c->old) release_all_arenas(c);
     c->fac.assign(c->boxes.size(), BoxFac());
     c->recomputed.assign(c->boxes.size(), 1);
     c->stats.guard_bumps = 0;
@@ -1517,6 +1823,10 @@ rs_status rs_update_moved_nodes(rs_ctx* c, int n_moved, const int* idx, const do
 
 rs_status rs_set_stream(rs_ctx* c, void* stream) {
   if (!c) return RS_ERR_ARG;
+  if (c->stream != static_cast<hipStream_t>(stream) && hipStreamSynchronize(c->stream) != hipSuccess) {
+    c->err = "rs_set_stream: synchronising the previous stream failed";
+    return RS_ERR_DEVICE;
+  }
   c->stream = static_cast<hipStream_t>(stream);
   return RS_OK;
 }

@@ -33,6 +33,9 @@ struct LevelBox {
   const ChildSrc* src;     // per position of I_B: where its child's X_SS is (null for a leaf)
   int* perm;               // pivot order output (n)
   double* M;      // m x n, column-major (ld = m)
+  const double* Mq;  // matrix the pivoted QR factors: M, or its row-reduced factor
+  int mq;            // its rows (leading dimension)
+  int mq_pad;
   double* R;      // kcap x n, row-major, pivot order
   double* Ap;     // n x n, row-major, A_BB in pivot order
   double* scr;    // scratch for the elimination: 3 n^2 + 128 n + 2048
@@ -86,9 +89,49 @@ constexpr int kNC = 16;        // right-hand-side columns per sweep block
 // ---- launchers (rs_kernels.hip) -------------------------------------------
 void launch_assemble_M(const LevelBox* boxes, int nbox, int max_m, int n_proxy, double ratio,
                        hipStream_t s);
+// Register-resident pivoted QR: a 1024-thread workgroup holds RU rows per
+// lane (RU even, 64 RU >= m) of CPW columns per wave.
+constexpr int kRQThreads = 512;
+constexpr int kRQWaves = kRQThreads / 64;
+constexpr int kRQBudget = 88;         // doubles per lane: CPW columns of RU rows plus v
+constexpr int kRQMaxRU = 24;           // m <= 1536
+__host__ __device__ constexpr int rq_cols_per_wave(int ru) {
+  return kRQBudget / ru - 1 < 20 ? kRQBudget / ru - 1 : 20;
+}
+__host__ __device__ constexpr int rq_row_class(int m) {
+  const int ru = (m + 63) / 64;
+  return ru < 2 ? 2 : ru + (ru & 1);
+}
+size_t cpqr_reg_lds_bytes(int max_ru, int max_n);
+// One block of the row reduction (unpivoted QR of rows x n, n-row factor out).
+struct QRTask {
+  const double* src;   // first row of the block, column-major, leading dimension ld
+  double* dst;         // triangular factor, n rows, column-major, leading dimension ldd
+  int ld, ldd;
+  int rows, n;
+  int ru, pad;         // rows per lane of the 16-lane layout: 16 ru >= max(rows, n)
+};
+void launch_tsqr(const QRTask* tasks, int ntask, hipStream_t s);
+// 16-lane layout (row reduction, pivoted QR of at most 256 rows): 32 columns
+// per register slot and workgroup, rows per lane RU = r16_row_class(rows).
+constexpr int kR16MaxRU = 16;
+constexpr int kR16MaxCols = 128;       // LDS room for the column bookkeeping (2 ints each)
+__host__ __device__ constexpr int r16_row_class(int rows) {
+  const int ru = (rows + 15) / 16;
+  return ru < 2 ? 2 : ru + (ru & 1);
+}
+// columns one workgroup holds in the 16-lane kernels (at most 4 slots of 32)
+constexpr int kR16MaxN = 128;
+hipError_t launch_cpqr16(const LevelBox* boxes, const int4* work, int nbox, double tol, int extra,
+                         int* k_out, int* kx_out, int* err, hipStream_t s);
+int cpqr_reg_blocks_per_cu(size_t lds);
+// work[b] = (box, g, G, RU) for block b; coop: cooperative launch (G > 1 boxes)
+hipError_t launch_cpqr_reg(const LevelBox* boxes, const int4* work, int nblocks, bool coop, double tol,
+                           int extra, int* k_out, int* kx_out, int* err, size_t lds, hipStream_t s);
+void launch_zero_bars(const LevelBox* boxes, int nbox, int* err, hipStream_t s);
 size_t cpqr_lds_bytes(int max_m, int max_n);
 int cpqr_blocks_per_cu(size_t lds);
-hipError_t launch_cpqr(const LevelBox* boxes, int nbox, int G, double tol, int extra,
+hipError_t launch_cpqr(const LevelBox* boxes, const int* list, int nbox, int G, double tol, int extra,
                        int* k_out, int* kx_out, int* err, int max_m, int max_n, hipStream_t s);
 void launch_assemble_abb(const LevelBox* boxes, int nbox, int max_n, double lam, bool use_perm,
                          hipStream_t s);

@@ -43,6 +43,67 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
+// Wave reductions through DPP row permutations and lane reads (no permute
+// traffic through LDS).  Every lane receives the same value; the order is
+// fixed: a butterfly inside each 16-lane row, then (row0 + row1) + (row2 + row3).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ int dpp_i32(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+__device__ __forceinline__ double lane_f64(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+constexpr int kDppXor1 = 0xB1;      // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;      // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141;
+constexpr int kDppMirror = 0x140;
+
+__device__ __forceinline__ double wave_sum_fast(double v) {
+  v += dpp_f64<kDppXor1>(v);
+  v += dpp_f64<kDppXor2>(v);
+  v += dpp_f64<kDppHalfMirror>(v);
+  v += dpp_f64<kDppMirror>(v);
+  return (lane_f64(v, 0) + lane_f64(v, 16)) + (lane_f64(v, 32) + lane_f64(v, 48));
+}
+
+// Pivot comparison key of a squared column norm: its leading 20 mantissa
+// bits (the low 32 bits of the pattern cleared).  Columns whose norms agree
+// to that precision are tied and the first column of I_B wins, so the choice
+// does not depend on rounding in the norms (mirror-symmetric node pairs give
+// such ties).
+__device__ __forceinline__ double pivot_key(double sq) { return __hiloint2double(__double2hiint(sq), 0); }
+
+// (value, index) maximum with ties to the smaller index.
+__device__ __forceinline__ void arg_better(double& bv, int& bi, double v, int i) {
+  if (v > bv || (v == bv && i < bi)) { bv = v; bi = i; }
+}
+template <int CTRL>
+__device__ __forceinline__ void argmax_step(double& bv, int& bi) {
+  const double ov = dpp_f64<CTRL>(bv);
+  const int oi = dpp_i32<CTRL>(bi);
+  arg_better(bv, bi, ov, oi);
+}
+// Wave-wide argmax; the result is uniform (read from lanes 0, 16, 32, 48).
+__device__ __forceinline__ void wave_argmax(double& bv, int& bi) {
+  argmax_step<kDppXor1>(bv, bi);
+  argmax_step<kDppXor2>(bv, bi);
+  argmax_step<kDppHalfMirror>(bv, bi);
+  argmax_step<kDppMirror>(bv, bi);
+  double rv = lane_f64(bv, 0);
+  int ri = __builtin_amdgcn_readlane(bi, 0);
+#pragma unroll
+  for (int r = 16; r < 64; r += 16) arg_better(rv, ri, lane_f64(bv, r), __builtin_amdgcn_readlane(bi, r));
+  bv = rv;
+  bi = ri;
+}
+
 // Sum over the block in a fixed order (deterministic); every thread gets it.
 __device__ double block_sum(double v, double* red) {
   v = wave_sum(v);
@@ -311,7 +372,8 @@ __global__ __launch_bounds__(kBlock) void k_assemble_M(const LevelBox* boxes, in
 
 // Pivoted Householder QR of M_B (m x n, column-major).
 // Pivot: largest remaining column norm (recomputed exactly after every
-// step), ties to the column that came first in I_B.  Runs until the first
+// step, compared through pivot_key), ties to the column that came first in
+// I_B.  Runs until the first
 // step with |R_jj| <= tol |R_11| plus `extra` further steps (head-room for
 // the X_RR guard).  Writes perm (pivot order of positions in I_B), the
 // tolerance rank k and the number of R rows kept, R in pivot order.
@@ -388,11 +450,11 @@ __device__ void box_barrier_full(unsigned* bar, int G, unsigned& count, int* dea
   __syncthreads();
 }
 
-__global__ __launch_bounds__(kQRThreads) void k_cpqr(const LevelBox* boxes, int G, double tol,
-                                                     int extra, int* k_out, int* kx_out,
+__global__ __launch_bounds__(kQRThreads) void k_cpqr(const LevelBox* boxes, const int* list, int G,
+                                                     double tol, int extra, int* k_out, int* kx_out,
                                                      int* err) {
   extern __shared__ double smem[];
-  const int bidx = blockIdx.x / G, g = blockIdx.x % G;
+  const int bidx = list[blockIdx.x / G], g = blockIdx.x % G;
   const LevelBox& B = boxes[bidx];
   const int m = B.m, n = B.n;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -445,7 +507,7 @@ __global__ __launch_bounds__(kQRThreads) void k_cpqr(const LevelBox* boxes, int 
     for (int t = tid; t < nown; t += kQRThreads) {
       const int q = own[t];
       if (done[q]) continue;
-      const double v = nrm[q];
+      const double v = pivot_key(nrm[q]);
       if (v > best || (v == best && q < bq)) { best = v; bq = q; }
     }
 #pragma unroll
@@ -483,6 +545,10 @@ __global__ __launch_bounds__(kQRThreads) void k_cpqr(const LevelBox* boxes, int 
     }
     __syncthreads();
     const int q = s_q;
+    if (q >= n) {   // no finite candidate (non-finite entries in M_B): flag and stop
+      if (tid == 0) __hip_atomic_store(err + 2, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      break;
+    }
     if (tid == 0) {
       const int p = ipv[q];
       const int u = pv[j];
@@ -635,10 +701,620 @@ __global__ __launch_bounds__(kQRThreads) void k_cpqr(const LevelBox* boxes, int 
   }
 }
 
-__global__ void k_zero_bars(const LevelBox* boxes, int nbox, int* err) {
+__global__ void k_zero_bars(const LevelBox* boxes, int nbox, int* err, int nerr) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < nbox && boxes[t].bar) *boxes[t].bar = 0u;
-  if (t == 0) *err = 0;
+  if (t < nerr) err[t] = 0;
+}
+
+// ---- register-resident pivoted QR ------------------------------------------
+// The same factorization as k_cpqr (largest remaining column norm, ties to
+// the first column of I_B, stop at |R_jj| <= tol |R_11| plus `extra` steps),
+// with M_B held in registers for all steps instead of being re-read from
+// memory at every step.  Layout: the box's columns are dealt to G workgroups
+// (column c to workgroup c % G), inside a workgroup to its 16 waves and then
+// to CPW register slots per wave; lane l of a wave holds rows l + 64 u,
+// u < RU, of each of its columns (rows >= m are zero).  Every dot product and
+// norm of a column is summed by its wave in a fixed order, so the result does
+// not depend on G, on CPW or on RU.  Work item = (box, g, G, RU).
+// Householder vector of column x at step j (rows j..m-1), formed by the one
+// wave holding the column: v (v_i = 0 above j, v_j = 1) into vsh, (beta, tau)
+// into hh; with vbuf/hhg non-null also into those (agent-scope stores, for
+// the other workgroups of the box).  x_j becomes R_jj = beta.
+template <int RU>
+__device__ __forceinline__ void reg_householder(double (&x)[RU], const int j, const int m,
+                                                const int lane, double* vsh, double* hh,
+                                                double* vbuf, double* hhg) {
+  const int uj = j >> 6, lj = j & 63;
+  double xj = 0.0, sum = 0.0;
+#pragma unroll
+  for (int u = 0; u < RU; ++u) {
+    if (u == uj) {
+      xj = x[u];
+      if (lane > lj) sum += x[u] * x[u];
+    } else if (u > uj) {
+      sum += x[u] * x[u];
+    }
+  }
+  const double alpha = lane_f64(xj, lj);
+  sum = wave_sum_fast(sum);
+  double beta, tau, scal = 0.0;
+  if (sum == 0.0) {
+    beta = alpha;
+    tau = 0.0;
+  } else {
+    beta = -copysign(sqrt(alpha * alpha + sum), alpha);
+    tau = (beta - alpha) / beta;
+    scal = 1.0 / (alpha - beta);
+  }
+#pragma unroll
+  for (int u = 0; u < RU; ++u) {
+    const int i = lane + 64 * u;
+    double v;
+    if (u < uj) v = 0.0;
+    else if (u > uj) v = x[u] * scal;
+    else v = lane < lj ? 0.0 : (lane == lj ? 1.0 : x[u] * scal);
+    vsh[i] = v;
+    if (vbuf && i < m) st_relaxed(vbuf + i, v);
+    if (u == uj && lane == lj) x[u] = beta;
+  }
+  if (lane == 0) {
+    hh[0] = beta;
+    hh[1] = tau;
+    if (hhg) { st_relaxed(hhg, beta); st_relaxed(hhg + 1, tau); }
+  }
+}
+
+// ---- register-resident pivoted QR ------------------------------------------
+// The same factorization as k_cpqr (largest remaining column norm, ties to
+// the first column of I_B, stop at |R_jj| <= tol |R_11| plus `extra` steps),
+// of the matrix B.Mq (mq rows: M_B itself, or the triangular factor of its
+// row reduction, which has the same pivots, ranks and R up to row signs),
+// held in registers for all steps.  Layout: the box's columns are dealt to G
+// workgroups (column c to workgroup c % G), inside a workgroup to its waves
+// and then to CPW register slots per wave; lane l of a wave holds rows
+// l + 64 u, u < RU, of each of its columns (rows >= mq are zero).  Every dot
+// product and norm of a column is summed by its wave in a fixed order, so the
+// result does not depend on G, on CPW or on RU.  Work item = (box, g, G, RU).
+template <int RU>
+__device__ __forceinline__ void cpqr_reg_box(const LevelBox& B, const int G, const int g,
+                                             const double tol, const int extra, int* k_out,
+                                             int* kx_out, int* err, double* dyn, double* s_hh,
+                                             int* s_dead, double* wv, int* wi) {
+  constexpr int CPW = rq_cols_per_wave(RU);
+  const int m = B.mq, n = B.n;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
+  double* vsh = dyn;                                    // 64 RU: Householder vector
+  int* pv = reinterpret_cast<int*>(vsh + 64 * RU);      // n: physical column at each position
+  int* ipv = pv + n;                                    // n: position of each physical column
+  const double* Mc = B.Mq;
+  double a[CPW][RU];
+#pragma unroll
+  for (int sl = 0; sl < CPW; ++sl) {
+    const int c = g + G * (wid + kRQWaves * sl);
+    if (c < n) {
+      const double* src = Mc + (size_t)c * m;
+#pragma unroll
+      for (int u = 0; u < RU; ++u) {
+        const int i = lane + 64 * u;
+        a[sl][u] = i < m ? src[i] : 0.0;
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < RU; ++u) a[sl][u] = 0.0;
+    }
+  }
+  // column norms (uniform across the wave) and this wave's pivot candidate
+  unsigned long long dm = 0;           // slots whose column has been pivoted
+  {
+    double bv = -1.0;
+    int bi = 1 << 30;
+#pragma unroll
+    for (int sl = 0; sl < CPW; ++sl) {
+      const int c = g + G * (wid + kRQWaves * sl);
+      if (c < n) {
+        double t = 0.0;
+#pragma unroll
+        for (int u = 0; u < RU; ++u) t += a[sl][u] * a[sl][u];
+        arg_better(bv, bi, pivot_key(wave_sum_fast(t)), c);
+      }
+    }
+    if (lane == 0) { wv[wid] = bv; wi[wid] = bi; }
+  }
+  for (int c = tid; c < n; c += kRQThreads) { pv[c] = c; ipv[c] = c; }
+  if (tid == 0) *s_dead = 0;
+  __syncthreads();
+  const int steps = min(m, n);
+  int limit = steps;
+  int kk = -1;
+  double r00 = 0.0;
+  unsigned nbar = 0;
+  int j = 0;
+  for (; j < limit; ++j) {
+    // pivot: the workgroup's best candidate, then (G > 1) the box's
+    double best = -1.0;
+    int bq = 1 << 30;
+    if (lane < kRQWaves) { best = wv[lane]; bq = wi[lane]; }
+    wave_argmax(best, bq);
+    if (G > 1) {
+      const int par = j & 1;
+      if (tid == 0) {
+        st_relaxed(B.cval + par * G + g, best);
+        st_relaxed(B.cphys + par * G + g, bq);
+      }
+      box_barrier_x(B.bar, G, nbar, s_dead, err);
+      best = -1.0;
+      bq = 1 << 30;
+      if (lane < G) {
+        best = ld_relaxed(B.cval + par * G + lane);
+        bq = ld_relaxed(B.cphys + par * G + lane);
+      }
+      wave_argmax(best, bq);
+    }
+    const int q = __builtin_amdgcn_readfirstlane(bq);
+    if (q >= n) {   // no finite candidate (non-finite entries in M_B): flag and stop
+      if (tid == 0) __hip_atomic_store(err + 2, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      break;
+    }
+    const bool mine = (q % G) == g;
+    const int qo = q / G;
+    if (mine && wid == qo % kRQWaves) {
+      const int os = qo / kRQWaves;
+#pragma unroll
+      for (int sl = 0; sl < CPW; ++sl)
+        if (sl == os)
+          reg_householder<RU>(a[sl], j, m, lane, vsh, s_hh, G > 1 ? B.vbuf : nullptr,
+                              G > 1 ? B.hh : nullptr);
+    }
+    if (G > 1) {
+      box_barrier_x(B.bar, G, nbar, s_dead, err);
+      if (!mine) {
+        for (int i = tid; i < 64 * RU; i += kRQThreads) vsh[i] = i < m ? ld_relaxed(B.vbuf + i) : 0.0;
+        if (tid == 0) { s_hh[0] = ld_relaxed(B.hh); s_hh[1] = ld_relaxed(B.hh + 1); }
+      }
+    }
+    __syncthreads();
+    const double beta = s_hh[0], tau = s_hh[1];
+    const double rjj = fabs(beta);
+    if (j == 0) r00 = rjj;
+    if (kk < 0 && !(rjj > tol * r00)) {
+      kk = j;
+      limit = min(steps, j + 1 + extra);
+    }
+    if (tid == 0) {
+      const int p = ipv[q];
+      const int u = pv[j];
+      pv[j] = q; pv[p] = u;
+      ipv[q] = j; ipv[u] = p;
+    }
+    // reflect the live columns of this wave; recompute their norms below row j
+#pragma unroll
+    for (int sl = 0; sl < CPW; ++sl)
+      if (g + G * (wid + kRQWaves * sl) == q) dm |= 1ull << sl;
+    const int uj = j >> 6, lj = j & 63;
+    double v[RU];
+#pragma unroll
+    for (int u = 0; u < RU; ++u) v[u] = u < uj ? 0.0 : vsh[lane + 64 * u];
+    double bv = -1.0;
+    int bi = 1 << 30;
+#pragma unroll
+    for (int sl = 0; sl < CPW; ++sl) {
+      const int c = g + G * (wid + kRQWaves * sl);
+      if (c < n && !((dm >> sl) & 1)) {
+        double t = 0.0;
+#pragma unroll
+        for (int u = 0; u < RU; ++u) t += v[u] * a[sl][u];
+        const double tw = tau * wave_sum_fast(t);
+        t = 0.0;
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+          a[sl][u] -= tw * v[u];   // v is zero above row j: those rows stay
+          if (u > uj || (u == uj && lane > lj)) t += a[sl][u] * a[sl][u];
+        }
+        arg_better(bv, bi, pivot_key(wave_sum_fast(t)), c);
+      }
+    }
+    if (lane == 0) { wv[wid] = bv; wi[wid] = bi; }
+    __syncthreads();
+  }
+  const int kx = j;
+  if (kk < 0) kk = kx;
+  // rows 0..kx-1 of R in pivot order: each wave writes its columns
+#pragma unroll
+  for (int sl = 0; sl < CPW; ++sl) {
+    const int c = g + G * (wid + kRQWaves * sl);
+    if (c >= n) continue;
+    const int p = ipv[c];
+    double* dst = B.R + p;
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+      const int r = lane + 64 * u;
+      if (r < kx) dst[(size_t)r * n] = r <= p ? a[sl][u] : 0.0;
+    }
+  }
+  if (g == 0) {
+    for (int c = tid; c < n; c += kRQThreads) B.perm[c] = pv[c];
+    if (tid == 0) { k_out[B.slot] = kk; kx_out[B.slot] = kx; }
+  }
+}
+
+// ---- 16-lane column layout --------------------------------------------------
+// Used by the row reduction and by the pivoted QR of matrices of at most 256
+// rows: a column lives in one 16-lane row of a wave (4 columns per wave and
+// register slot); lane p of that row holds rows p + 16 u, u < RU.  A column's
+// dot product is then a 16-lane reduction (4 DPP steps, done for the 4
+// columns of a wave at once).  Column of (wave w, slot s, lane group r):
+// 4 (w + 8 s) + r.
+__device__ __forceinline__ double row16_sum(double v) {
+  v += dpp_f64<kDppXor1>(v);
+  v += dpp_f64<kDppXor2>(v);
+  v += dpp_f64<kDppHalfMirror>(v);
+  v += dpp_f64<kDppMirror>(v);
+  return v;
+}
+
+// Householder vector at step j of the column x held by lane group og of the
+// calling wave: v into vsh (rows 0..16 RU-1, zero above j, one at j), (beta,
+// tau) into hh; x_j becomes R_jj = beta.
+template <int RU>
+__device__ __forceinline__ void r16_householder(double (&x)[RU], const int j, const int og,
+                                                const int p, const int rg, double* vsh, double* hh) {
+  const int uj = j >> 4, pj = j & 15;
+  double xj = 0.0, s0 = 0.0, s1 = 0.0;
+#pragma unroll
+  for (int u = 0; u < RU; ++u) {
+    double& acc = (u & 1) ? s1 : s0;
+    if (u == uj) {
+      xj = x[u];
+      if (p > pj) acc += x[u] * x[u];
+    } else if (u > uj) {
+      acc += x[u] * x[u];
+    }
+  }
+  const double sum = row16_sum(s0 + s1);
+  const double alpha = lane_f64(xj, 16 * og + pj);
+  const double s2 = lane_f64(sum, 16 * og);
+  double beta, tau, scal = 0.0;
+  if (s2 == 0.0) {
+    beta = alpha;
+    tau = 0.0;
+  } else {
+    beta = -copysign(sqrt(alpha * alpha + s2), alpha);
+    const double d = alpha - beta;
+    const double rcp = 1.0 / (beta * d);
+    tau = -d * d * rcp;          // (beta - alpha) / beta
+    scal = beta * rcp;           // 1 / (alpha - beta)
+  }
+  if (rg == og) {
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+      double v;
+      if (u < uj) v = 0.0;
+      else if (u > uj) v = x[u] * scal;
+      else v = p < pj ? 0.0 : (p == pj ? 1.0 : x[u] * scal);
+      vsh[p + 16 * u] = v;
+      if (u == uj && p == pj) x[u] = beta;
+    }
+  }
+  if ((threadIdx.x & 63) == 0) { hh[0] = beta; hh[1] = tau; }
+}
+
+// ---- row reduction of tall ID matrices (unpivoted block Householder QR) ----
+// One task = one block of rows (at most 16 RU) of an n-column matrix: its
+// triangular factor (n rows, zeros below the diagonal) is written to dst.
+// Blocks of M_B first, then blocks of stacked factors, until the stack has at
+// most 256 rows.  One barrier per step: the Householder vector of step j + 1
+// goes to the other of two buffers.
+template <int RU, int NS>
+__device__ __forceinline__ void tsqr16_block(const QRTask& T, double* vsh2, double* hh2) {
+  const int rows = T.rows, n = T.n;
+  const int lane = threadIdx.x & 63, p = lane & 15, rg = lane >> 4;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  double a[NS][RU];
+#pragma unroll
+  for (int sl = 0; sl < NS; ++sl) {
+    const int c = 4 * (wid + kRQWaves * sl) + rg;
+    const double* src = T.src + (size_t)(c < n ? c : 0) * T.ld;
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+      const int i = p + 16 * u;
+      a[sl][u] = (c < n && i < rows) ? src[i] : 0.0;
+    }
+  }
+  const int steps = min(rows, n);
+  for (int j = 0; j < steps; ++j) {
+    double* vsh = vsh2 + (j & 1) * 16 * RU;
+    double* hh = hh2 + 2 * (j & 1);
+    const int sj = j >> 2;
+    if (wid == sj % kRQWaves) {
+      const int os = sj / kRQWaves;
+#pragma unroll
+      for (int sl = 0; sl < NS; ++sl)
+        if (sl == os) r16_householder<RU>(a[sl], j, j & 3, p, rg, vsh, hh);
+    }
+    __syncthreads();
+    const double tau = hh[1];
+    // the slots' dependent chains are interleaved; a column that is done or
+    // absent gets tw = 0 and is left as it is
+    double v[RU], t[NS];
+#pragma unroll
+    for (int sl = 0; sl < NS; ++sl) t[sl] = 0.0;
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+      v[u] = vsh[p + 16 * u];
+#pragma unroll
+      for (int sl = 0; sl < NS; ++sl) t[sl] += v[u] * a[sl][u];
+    }
+#pragma unroll
+    for (int sl = 0; sl < NS; ++sl) {
+      const int c = 4 * (wid + kRQWaves * sl) + rg;
+      const double dot = row16_sum(t[sl]);
+      t[sl] = (c > j && c < n) ? tau * dot : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < RU; ++u)
+#pragma unroll
+      for (int sl = 0; sl < NS; ++sl) a[sl][u] -= t[sl] * v[u];
+  }
+#pragma unroll
+  for (int sl = 0; sl < NS; ++sl) {
+    const int c = 4 * (wid + kRQWaves * sl) + rg;
+    if (c >= n) continue;
+    double* dst = T.dst + (size_t)c * T.ldd;
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+      const int r = p + 16 * u;
+      if (r < n) dst[r] = r <= c ? a[sl][u] : 0.0;
+    }
+  }
+}
+
+// ---- pivoted QR in the 16-lane layout (one workgroup per box) ---------------
+// The factorization of cpqr_reg_box (same pivot rule, stopping rule and
+// outputs) of B.Mq (at most 256 rows), for boxes whose columns fit one
+// workgroup.
+template <int RU, int NS>
+__device__ __forceinline__ void cpqr16_box(const LevelBox& B, const double tol, const int extra,
+                                           int* k_out, int* kx_out, int* err, double* dyn,
+                                           double* s_hh, double* wv, int* wi) {
+  const int m = B.mq, n = B.n;
+  const int tid = threadIdx.x, lane = tid & 63, p = lane & 15, rg = lane >> 4;
+  const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
+  double* vsh = dyn;                                    // 16 RU
+  int* pv = reinterpret_cast<int*>(vsh + 16 * RU);      // n: physical column at each position
+  int* ipv = pv + n;                                    // n: position of each physical column
+  double a[NS][RU];
+#pragma unroll
+  for (int sl = 0; sl < NS; ++sl) {
+    const int c = 4 * (wid + kRQWaves * sl) + rg;
+    const double* src = B.Mq + (size_t)(c < n ? c : 0) * m;
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+      const int i = p + 16 * u;
+      a[sl][u] = (c < n && i < m) ? src[i] : 0.0;
+    }
+  }
+  // the wave's pivot candidate: best of its lane groups (uniform within a group)
+  auto publish = [&](double bv, int bi) {
+    double rv = lane_f64(bv, 0);
+    int ri = __builtin_amdgcn_readlane(bi, 0);
+#pragma unroll
+    for (int r = 16; r < 64; r += 16) arg_better(rv, ri, lane_f64(bv, r), __builtin_amdgcn_readlane(bi, r));
+    if (lane == 0) { wv[wid] = rv; wi[wid] = ri; }
+  };
+  double t[NS];
+  {
+#pragma unroll
+    for (int sl = 0; sl < NS; ++sl) t[sl] = 0.0;
+#pragma unroll
+    for (int u = 0; u < RU; ++u)
+#pragma unroll
+      for (int sl = 0; sl < NS; ++sl) t[sl] += a[sl][u] * a[sl][u];
+    double bv = -1.0;
+    int bi = 1 << 30;
+#pragma unroll
+    for (int sl = 0; sl < NS; ++sl) {
+      const int c = 4 * (wid + kRQWaves * sl) + rg;
+      const double nn = row16_sum(t[sl]);
+      if (c < n) arg_better(bv, bi, pivot_key(nn), c);
+    }
+    publish(bv, bi);
+  }
+  for (int c = tid; c < n; c += kRQThreads) { pv[c] = c; ipv[c] = c; }
+  __syncthreads();
+  unsigned dm = 0;                     // this lane group's slots whose column is pivoted
+  const int steps = min(m, n);
+  int limit = steps;
+  int kk = -1;
+  double r00 = 0.0;
+  int j = 0;
+  for (; j < limit; ++j) {
+    double best = -1.0;
+    int bq = 1 << 30;
+    if (lane < kRQWaves) { best = wv[lane]; bq = wi[lane]; }
+    wave_argmax(best, bq);
+    const int q = __builtin_amdgcn_readfirstlane(bq);
+    if (q >= n) {   // no finite candidate (non-finite entries in M_B): flag and stop
+      if (tid == 0) __hip_atomic_store(err + 2, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      break;
+    }
+    const int sq = q >> 2;
+    if (wid == sq % kRQWaves) {
+      const int os = sq / kRQWaves;
+#pragma unroll
+      for (int sl = 0; sl < NS; ++sl)
+        if (sl == os) r16_householder<RU>(a[sl], j, q & 3, p, rg, vsh, s_hh);
+    }
+    __syncthreads();
+    const double beta = s_hh[0], tau = s_hh[1];
+    const double rjj = fabs(beta);
+    if (j == 0) r00 = rjj;
+    if (kk < 0 && !(rjj > tol * r00)) {
+      kk = j;
+      limit = min(steps, j + 1 + extra);
+    }
+    if (tid == 0) {
+      const int pp = ipv[q];
+      const int u = pv[j];
+      pv[j] = q; pv[pp] = u;
+      ipv[q] = j; ipv[u] = pp;
+    }
+    const int uj = j >> 4, pj = j & 15;
+    double v[RU];
+#pragma unroll
+    for (int sl = 0; sl < NS; ++sl) {
+      if (4 * (wid + kRQWaves * sl) + rg == q) dm |= 1u << sl;
+      t[sl] = 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+      v[u] = vsh[p + 16 * u];
+#pragma unroll
+      for (int sl = 0; sl < NS; ++sl) t[sl] += v[u] * a[sl][u];
+    }
+#pragma unroll
+    for (int sl = 0; sl < NS; ++sl) {
+      const int c = 4 * (wid + kRQWaves * sl) + rg;
+      const double dot = row16_sum(t[sl]);
+      t[sl] = (c < n && !((dm >> sl) & 1)) ? tau * dot : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < RU; ++u)
+#pragma unroll
+      for (int sl = 0; sl < NS; ++sl) a[sl][u] -= t[sl] * v[u];   // v is zero above row j
+    // norms below row j, and this wave's next candidate
+#pragma unroll
+    for (int sl = 0; sl < NS; ++sl) t[sl] = 0.0;
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+      if (u > uj) {
+#pragma unroll
+        for (int sl = 0; sl < NS; ++sl) t[sl] += a[sl][u] * a[sl][u];
+      } else if (u == uj) {
+#pragma unroll
+        for (int sl = 0; sl < NS; ++sl) t[sl] += p > pj ? a[sl][u] * a[sl][u] : 0.0;
+      }
+    }
+    double bv = -1.0;
+    int bi = 1 << 30;
+#pragma unroll
+    for (int sl = 0; sl < NS; ++sl) {
+      const int c = 4 * (wid + kRQWaves * sl) + rg;
+      const double nn = row16_sum(t[sl]);
+      if (c < n && !((dm >> sl) & 1)) arg_better(bv, bi, pivot_key(nn), c);
+    }
+    publish(bv, bi);
+    __syncthreads();
+  }
+  const int kx = j;
+  if (kk < 0) kk = kx;
+#pragma unroll
+  for (int sl = 0; sl < NS; ++sl) {
+    const int c = 4 * (wid + kRQWaves * sl) + rg;
+    if (c >= n) continue;
+    const int pp = ipv[c];
+    double* dst = B.R + pp;
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+      const int r = p + 16 * u;
+      if (r < kx) dst[(size_t)r * n] = r <= pp ? a[sl][u] : 0.0;
+    }
+  }
+  for (int c = tid; c < n; c += kRQThreads) B.perm[c] = pv[c];
+  if (tid == 0) { k_out[B.slot] = kk; kx_out[B.slot] = kx; }
+}
+
+#define RS_R16_CASES(CALL) \
+  case 17: CALL(2, 1); break; \
+  case 18: CALL(2, 2); break; \
+  case 19: CALL(2, 3); break; \
+  case 20: CALL(2, 4); break; \
+  case 33: CALL(4, 1); break; \
+  case 34: CALL(4, 2); break; \
+  case 35: CALL(4, 3); break; \
+  case 36: CALL(4, 4); break; \
+  case 49: CALL(6, 1); break; \
+  case 50: CALL(6, 2); break; \
+  case 51: CALL(6, 3); break; \
+  case 52: CALL(6, 4); break; \
+  case 65: CALL(8, 1); break; \
+  case 66: CALL(8, 2); break; \
+  case 67: CALL(8, 3); break; \
+  case 68: CALL(8, 4); break; \
+  case 81: CALL(10, 1); break; \
+  case 82: CALL(10, 2); break; \
+  case 83: CALL(10, 3); break; \
+  case 84: CALL(10, 4); break; \
+  case 97: CALL(12, 1); break; \
+  case 98: CALL(12, 2); break; \
+  case 99: CALL(12, 3); break; \
+  case 100: CALL(12, 4); break; \
+  case 113: CALL(14, 1); break; \
+  case 114: CALL(14, 2); break; \
+  case 115: CALL(14, 3); break; \
+  case 116: CALL(14, 4); break; \
+  case 129: CALL(16, 1); break; \
+  case 130: CALL(16, 2); break; \
+  case 131: CALL(16, 3); break; \
+  case 132: CALL(16, 4); break; \
+  default: break;
+
+__global__ __launch_bounds__(kRQThreads) void k_tsqr(const QRTask* tasks) {
+  __shared__ double vsh2[2 * 16 * kR16MaxRU];
+  __shared__ double hh2[4];
+  const QRTask& T = tasks[blockIdx.x];
+#define RS_TSQR(R, S) tsqr16_block<R, S>(T, vsh2, hh2)
+  switch (T.ru * 8 + (T.n + 31) / 32) { RS_R16_CASES(RS_TSQR) }
+#undef RS_TSQR
+}
+
+__global__ __launch_bounds__(kRQThreads) void k_cpqr16(const LevelBox* boxes, const int4* work,
+                                                       double tol, int extra, int* k_out, int* kx_out,
+                                                       int* err) {
+  __shared__ double dyn[16 * kR16MaxRU + kR16MaxCols];   // v, then pv / ipv as ints
+  __shared__ double s_hh[2];
+  __shared__ double wv[kRQWaves];
+  __shared__ int wi[kRQWaves];
+  const int4 w = work[blockIdx.x];
+  const LevelBox& B = boxes[w.x];
+#define RS_CPQR16(R, S) cpqr16_box<R, S>(B, tol, extra, k_out, kx_out, err, dyn, s_hh, wv, wi)
+  switch (w.w * 8 + (B.n + 31) / 32) { RS_R16_CASES(RS_CPQR16) }
+#undef RS_CPQR16
+}
+
+#define RS_RU_CASES(CALL)   \
+  case 2: CALL(2); break;   \
+  case 4: CALL(4); break;   \
+  case 6: CALL(6); break;   \
+  case 8: CALL(8); break;   \
+  case 10: CALL(10); break; \
+  case 12: CALL(12); break; \
+  case 14: CALL(14); break; \
+  case 16: CALL(16); break; \
+  case 18: CALL(18); break; \
+  case 20: CALL(20); break; \
+  case 22: CALL(22); break; \
+  default: CALL(24); break;
+
+
+__global__ __launch_bounds__(kRQThreads) void k_cpqr_reg(const LevelBox* boxes, const int4* work,
+                                                         double tol, int extra, int* k_out,
+                                                         int* kx_out, int* err) {
+  extern __shared__ double dyn[];
+  __shared__ double s_hh[2];
+  __shared__ double wv[kRQWaves];
+  __shared__ int wi[kRQWaves];
+  __shared__ int s_dead;
+  const int4 w = work[blockIdx.x];
+  const LevelBox& B = boxes[w.x];
+  if (B.n == 0) {
+    if (threadIdx.x == 0 && w.y == 0) { k_out[B.slot] = 0; kx_out[B.slot] = 0; }
+    return;
+  }
+#define RS_CPQR(R) cpqr_reg_box<R>(B, w.z, w.y, tol, extra, k_out, kx_out, err, dyn, s_hh, &s_dead, wv, wi)
+  switch (w.w) { RS_RU_CASES(RS_CPQR) }
+#undef RS_CPQR
 }
 
 __global__ __launch_bounds__(kBlock) void k_assemble_abb(const LevelBox* boxes, double lam,
@@ -1822,19 +2498,61 @@ int cpqr_blocks_per_cu(size_t lds) {
   return nb;
 }
 
-hipError_t launch_cpqr(const LevelBox* boxes, int nbox, int G, double tol, int extra,
+void launch_zero_bars(const LevelBox* boxes, int nbox, int* err, hipStream_t s) {
+  if (nbox == 0) return;
+  hipLaunchKernelGGL(k_zero_bars, dim3(blocks_for(std::max(nbox, 3), kBlock)), dim3(kBlock), 0, s, boxes,
+                     nbox, err, 3);
+}
+
+hipError_t launch_cpqr(const LevelBox* boxes, const int* list, int nbox, int G, double tol, int extra,
                        int* k_out, int* kx_out, int* err, int max_m, int max_n, hipStream_t s) {
   if (nbox == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_zero_bars, dim3(blocks_for(nbox, kBlock)), dim3(kBlock), 0, s, boxes, nbox, err);
   const size_t lds = cpqr_lds_bytes(max_m, max_n);
   if (G <= 1) {
-    hipLaunchKernelGGL(k_cpqr, dim3(nbox), dim3(kQRThreads), lds, s, boxes, 1, tol, extra,
+    hipLaunchKernelGGL(k_cpqr, dim3(nbox), dim3(kQRThreads), lds, s, boxes, list, 1, tol, extra,
                        k_out, kx_out, err);
     return hipGetLastError();
   }
-  void* args[] = {(void*)&boxes, (void*)&G, (void*)&tol, (void*)&extra,
+  void* args[] = {(void*)&boxes, (void*)&list, (void*)&G, (void*)&tol, (void*)&extra,
                   (void*)&k_out, (void*)&kx_out, (void*)&err};
   return hipLaunchCooperativeKernel((const void*)k_cpqr, dim3(nbox * G), dim3(kQRThreads), args,
+                                    (unsigned)lds, s);
+}
+
+size_t cpqr_reg_lds_bytes(int max_ru, int max_n) {
+  return (size_t)(64 * max_ru) * sizeof(double) + 2 * (size_t)max_n * sizeof(int) + 64;
+}
+
+void launch_tsqr(const QRTask* tasks, int ntask, hipStream_t s) {
+  if (ntask == 0) return;
+  hipLaunchKernelGGL(k_tsqr, dim3(ntask), dim3(kRQThreads), 0, s, tasks);
+}
+
+hipError_t launch_cpqr16(const LevelBox* boxes, const int4* work, int nbox, double tol, int extra,
+                         int* k_out, int* kx_out, int* err, hipStream_t s) {
+  if (nbox == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cpqr16, dim3(nbox), dim3(kRQThreads), 0, s, boxes, work, tol, extra, k_out,
+                     kx_out, err);
+  return hipGetLastError();
+}
+
+int cpqr_reg_blocks_per_cu(size_t lds) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_cpqr_reg, kRQThreads, lds) != hipSuccess) return 0;
+  return nb;
+}
+
+hipError_t launch_cpqr_reg(const LevelBox* boxes, const int4* work, int nblocks, bool coop, double tol,
+                           int extra, int* k_out, int* kx_out, int* err, size_t lds, hipStream_t s) {
+  if (nblocks == 0) return hipSuccess;
+  if (!coop) {
+    hipLaunchKernelGGL(k_cpqr_reg, dim3(nblocks), dim3(kRQThreads), lds, s, boxes, work, tol, extra,
+                       k_out, kx_out, err);
+    return hipGetLastError();
+  }
+  void* args[] = {(void*)&boxes, (void*)&work, (void*)&tol, (void*)&extra,
+                  (void*)&k_out, (void*)&kx_out, (void*)&err};
+  return hipLaunchCooperativeKernel((const void*)k_cpqr_reg, dim3(nblocks), dim3(kRQThreads), args,
                                     (unsigned)lds, s);
 }
 
@@ -1861,7 +2579,7 @@ int eliminate_blocks_per_cu(int max_n) {
 hipError_t launch_eliminate(const LevelBox* boxes, int nbox, int G, int* k_io, const int* kx,
                             double rcond_min, int* status, int* err, int max_n, hipStream_t s) {
   if (nbox == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_zero_bars, dim3(blocks_for(nbox, kBlock)), dim3(kBlock), 0, s, boxes, nbox, err);
+  hipLaunchKernelGGL(k_zero_bars, dim3(blocks_for(nbox, kBlock)), dim3(kBlock), 0, s, boxes, nbox, err, 1);
   const size_t lds = eliminate_lds_bytes(max_n);
   if (lds > 65536) {
     hipFuncAttributes fa;

@@ -171,3 +171,18 @@ def test_state_errors():
     with pytest.raises(RSError) as e:
         s.solve(np.zeros(g.n_dofs))
     assert e.value.name == "RS_ERR_STATE"
+
+
+@pytest.mark.parametrize("ratio", [1.75, 2.75])
+def test_wider_proxy_circle(ratio):
+    """Near fields reach further than the adjacent boxes (Section 2.5's proxy
+    radius is a parameter): same solution as the oracle, same ranks."""
+    g = workload_small(seed=11, n_outer=256, n_holes=2, nodes_per_hole=128, radius=3.0)
+    f = boundary_data(g, exterior_forces_for_geometry(g, 2, seed=5))
+    orc = RSFactorization(g, RSParams(leaf_size=24, proxy_ratio=ratio)).factor()
+    xo = orc.solve(f)
+    s = _solver(g, leaf_size=24, proxy_ratio=ratio).factor()
+    x = s.solve(f)
+    assert np.all(_rel(x, xo) < 1e-10)
+    same, total = _rank_agreement(orc, s)
+    assert same >= total - 1

@@ -52,6 +52,31 @@ def test_tie_break_prefers_first_column():
     assert q.perm[0] == 0
 
 
+def test_near_tie_goes_to_first_column():
+    """Norms that agree to rounding count as tied: the earlier column wins
+    even when the later one is larger by a few ulps."""
+    M = np.array([[1.0, 0.0, 1.0 + 4e-16], [0.0, 1.0, 0.0], [0.0, 0.0, 0.0]])
+    q = PivotedQR(M)
+    q.step()
+    assert q.perm[0] == 0
+    # a genuine difference (1e-5 relative) is not a tie
+    M2 = np.array([[1.0, 0.0, 1.0 + 1e-5], [0.0, 1.0, 0.0]])
+    q2 = PivotedQR(M2)
+    q2.step()
+    assert q2.perm[0] == 2
+
+
+def test_pivot_key_is_truncation():
+    from oracle.cpqr import pivot_key
+
+    x = np.array([1.0, 1.0 + 2.0 ** -21, 1.0 + 2.0 ** -19, 3.5, 0.0])
+    k = pivot_key(x)
+    assert k[0] == k[1] == 1.0           # below the 2^-20 quantum: tied
+    assert k[2] == 1.0 + 2.0 ** -19      # representable in 20 bits: kept
+    assert k[3] == 3.5 and k[4] == 0.0
+    assert np.all(k <= x)
+
+
 def test_zero_matrix_rank_zero():
     q = PivotedQR(np.zeros((5, 3)))
     assert q.rank(1e-10) == 0
