@@ -1443,6 +1443,193 @@ __device__ void mfma_gemm(int g, int G, int M, int N, int K, double alpha, const
 // LDS (W, row-major); the inverse of X goes to Xi (global, ld r).  One
 // workgroup.  Returns the reciprocal 1-norm condition number (0 if a pivot
 // vanished), identical in all threads.
+constexpr int kLdsGJMax = 128;   // X_RR up to this edge is inverted by one workgroup (registers)
+constexpr size_t kTSolveMax = 12288;   // T (k x r) up to this size is solved in LDS
+
+// Gauss-Jordan inverse of X (r x r, row-major, r <= kLdsGJMax) by one
+// workgroup with partial pivoting by exchange steps: step j pivots on the
+// largest |W[i][j]| over the rows not used yet, and row i and column j trade
+// places; the finished tableau W holds X^{-1} with X^{-1}[j][p_c] = W[p_j][c].
+// A 16 x 16 thread grid keeps rows ty + 16 a, columns tx + 16 b of W in
+// registers for the whole sweep; per step the pivot row and column go
+// through LDS.  The pivot is compared on a 64-bit key (|W| with its low 8
+// mantissa bits replaced by 255 - i, ties within 2^-44 to the smaller row)
+// that the holders of column j + 1 fold into LDS with an atomic max during
+// step j.  The update is one FMA per element (the multipliers absorb the
+// pivot row and column).  Column 1-norms for rcond_1 are summed in a fixed
+// order.  Two barriers per step.  Returns rcond_1 (0 if singular).
+// LDS: gj_lds_doubles(r) doubles at `sh`.
+__device__ __forceinline__ unsigned long long gj_key(double v, int i) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(fabs(v));
+  return (b & ~0xFFull) | (unsigned long long)(255 - i);
+}
+
+__host__ __device__ constexpr size_t gj_lds_doubles(int r) { return 18 * (size_t)r + 4 + (size_t)r; }
+
+__device__ double reg_gj(const double* X, int r, double* Xi, double* sh, double* red) {
+  const int tid = threadIdx.x;
+  const int ty = tid >> 4, tx = tid & 15;
+  constexpr int MB = (kLdsGJMax + 15) / 16;
+  const int mb = (r + 15) >> 4;
+  double* rowbuf = sh;                       // r: pivot row
+  double* colbuf = rowbuf + r;               // r: pivot column
+  double* part = colbuf + r;                 // 16 r: column-sum partials
+  unsigned long long* keys = reinterpret_cast<unsigned long long*>(part + 16 * (size_t)r);   // 2
+  int* pv = reinterpret_cast<int*>(keys + 2);        // r
+  int* ipv = pv + r;                                  // r
+  double w[MB][MB];
+#pragma unroll
+  for (int a = 0; a < MB; ++a) {
+    if (a >= mb) break;
+#pragma unroll
+    for (int b = 0; b < MB; ++b) {
+      if (b >= mb) break;
+      const int i = ty + 16 * a, c = tx + 16 * b;
+      w[a][b] = (i < r && c < r) ? X[(size_t)i * r + c] : 0.0;
+    }
+  }
+  if (tid < 2) keys[tid] = 0ull;
+  // largest column 1-norm: per-thread partial sums, then 16 partials per column in order
+  auto colnorm = [&]() {
+#pragma unroll
+    for (int b = 0; b < MB; ++b) {
+      if (b >= mb) break;
+      double s = 0.0;
+#pragma unroll
+      for (int a = 0; a < MB; ++a) {
+        if (a >= mb) break;
+        s += fabs(w[a][b]);
+      }
+      const int c = tx + 16 * b;
+      if (c < r) part[ty * r + c] = s;
+    }
+    __syncthreads();
+    double nm = 0.0;
+    for (int c = tid; c < r; c += kBlock) {
+      double s = 0.0;
+      for (int t = 0; t < 16; ++t) s += part[t * r + c];
+      nm = fmax(nm, s);
+    }
+    return block_max(nm, red);
+  };
+  const double n1 = colnorm();
+  if (tx == 0)
+#pragma unroll
+    for (int a = 0; a < MB; ++a) {
+      if (a >= mb) break;
+      const int i = ty + 16 * a;
+      if (i < r) atomicMax(&keys[0], gj_key(w[a][0], i));
+    }
+  __syncthreads();
+  unsigned used = 0;             // bit a: row ty + 16 a is a pivot row already
+  for (int j = 0; j < r; ++j) {
+    const unsigned long long key = keys[j & 1];
+    const int bi = 255 - (int)(key & 0xFF);
+    const int ab = bi >> 4, bj = j >> 4;
+    if (ty == (bi & 15))
+#pragma unroll
+      for (int a = 0; a < MB; ++a)
+        if (a == ab)
+#pragma unroll
+          for (int b = 0; b < MB; ++b) {
+            if (b >= mb) break;
+            const int c = tx + 16 * b;
+            if (c < r) rowbuf[c] = w[a][b];
+          }
+    if (tx == (j & 15))
+#pragma unroll
+      for (int b = 0; b < MB; ++b)
+        if (b == bj)
+#pragma unroll
+          for (int a = 0; a < MB; ++a) {
+            if (a >= mb) break;
+            const int i = ty + 16 * a;
+            if (i < r) colbuf[i] = w[a][b];
+          }
+    if (tid == 0) { keys[(j + 1) & 1] = 0ull; pv[j] = bi; }
+    __syncthreads();
+    const double pvt = colbuf[bi];
+    if (!(pvt != 0.0)) return 0.0;          // uniform: every thread read the same key
+    if ((bi & 15) == ty) used |= 1u << ab;
+    const double inv = 1.0 / pvt;
+    double pr[MB], pc[MB];
+#pragma unroll
+    for (int b = 0; b < MB; ++b) {
+      if (b >= mb) break;
+      const int c = tx + 16 * b;
+      pr[b] = c < r ? (c == j ? inv : rowbuf[c] * inv) : 0.0;
+      const int i = ty + 16 * b;
+      pc[b] = i < r ? (i == bi ? -1.0 : colbuf[i]) : 0.0;
+    }
+    const int bn = (j + 1) >> 4;
+    double cand[MB];
+#pragma unroll
+    for (int a = 0; a < MB; ++a) {
+      if (a >= mb) break;
+      const bool prow = ty + 16 * a == bi;
+      cand[a] = 0.0;
+#pragma unroll
+      for (int b = 0; b < MB; ++b) {
+        if (b >= mb) break;
+        const double w0 = (prow || tx + 16 * b == j) ? 0.0 : w[a][b];
+        w[a][b] = w0 - pc[a] * pr[b];
+        if (b == bn) cand[a] = w[a][b];
+      }
+    }
+    if (tx == ((j + 1) & 15) && j + 1 < r)
+#pragma unroll
+      for (int a = 0; a < MB; ++a) {
+        if (a >= mb) break;
+        const int i = ty + 16 * a;
+        if (i < r && !((used >> a) & 1)) atomicMax(&keys[(j + 1) & 1], gj_key(cand[a], i));
+      }
+    __syncthreads();
+  }
+  // X^{-1}[j][p_c] = W[p_j][c]
+  for (int j = tid; j < r; j += kBlock) ipv[pv[j]] = j;
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < MB; ++a) {
+    if (a >= mb) break;
+    const int i = ty + 16 * a;
+    if (i >= r) continue;
+    const int row = ipv[i];
+#pragma unroll
+    for (int b = 0; b < MB; ++b) {
+      if (b >= mb) break;
+      const int c = tx + 16 * b;
+      if (c < r) Xi[(size_t)row * r + pv[c]] = w[a][b];
+    }
+  }
+  // column c of W is column p_c of X^{-1} with its rows permuted
+  const double n2 = colnorm();
+  const double rc = 1.0 / (n1 * n2);
+  return isfinite(rc) ? rc : 0.0;
+}
+
+// T = R11^{-1} R12 (k x r, row-major) by back substitution on all columns at
+// once, T staged in LDS (k r doubles): step i removes row i's contribution
+// from the rows above it; one barrier per step.  R: k x n rows of R, pivot order.
+__device__ void lds_tsolve(const double* R, int n, int k, int r, double* Tl, double* T) {
+  const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
+  for (int l = ty; l < k; l += 16)
+    for (int c = tx; c < r; c += 16) Tl[l * r + c] = R[(size_t)l * n + k + c];
+  __syncthreads();
+  for (int i = k - 1; i > 0; --i) {
+    const double d = R[(size_t)i * n + i];
+    for (int c = tx; c < r; c += 16) {
+      const double x = Tl[i * r + c] / d;
+      for (int l = ty; l < i; l += 16) Tl[l * r + c] -= R[(size_t)l * n + i] * x;
+    }
+    __syncthreads();
+  }
+  for (int l = ty; l < k; l += 16) {
+    const double d = R[(size_t)l * n + l];
+    for (int c = tx; c < r; c += 16) T[(size_t)l * r + c] = Tl[l * r + c] / d;
+  }
+  __syncthreads();
+}
+
 __device__ double lds_gj(const double* X, int r, double* W, double* Xi, double* rowj, double* colj,
                          int* rowperm, double* red, int* ired) {
   const int tid = threadIdx.x, NT = blockDim.x, lane = tid & 63, wid = tid >> 6;
@@ -1545,7 +1732,6 @@ __device__ double coop_norm1(int g, int G, const double* X, int n, int ldx, doub
 }
 
 constexpr int kGJP = 32;   // pivot block of the in-place Gauss-Jordan
-constexpr int kLdsGJMax = 120;   // X_RR up to this edge is inverted in LDS by one workgroup
 
 // X_RR^{-1} of the box (blocked in-place Gauss-Jordan with partial pivoting,
 // panels of kGJP columns): W holds X_RR on entry and is destroyed; Xi receives
@@ -1722,11 +1908,16 @@ __global__ __launch_bounds__(kBlock) void k_eliminate(const LevelBox* boxes, int
   while (true) {
     const int r = n - k;
     double* T = B.T;
-    for (int c = gt; c < r; c += GT) {
-      for (int i = k - 1; i >= 0; --i) {
-        double sum = B.R[(size_t)i * n + k + c];
-        for (int l = i + 1; l < k; ++l) sum -= B.R[(size_t)i * n + l] * T[(size_t)l * r + c];
-        T[(size_t)i * r + c] = sum / B.R[(size_t)i * n + i];
+    // the route depends on k and r only (not on the launch)
+    if ((size_t)k * r <= kTSolveMax) {
+      if (g == 0) lds_tsolve(B.R, n, k, r, smem_e, T);
+    } else {
+      for (int c = gt; c < r; c += GT) {
+        for (int i = k - 1; i >= 0; --i) {
+          double sum = B.R[(size_t)i * n + k + c];
+          for (int l = i + 1; l < k; ++l) sum -= B.R[(size_t)i * n + l] * T[(size_t)l * r + c];
+          T[(size_t)i * r + c] = sum / B.R[(size_t)i * n + i];
+        }
       }
     }
     box_barrier_full(B.bar, G, nbar, &s_dead, err);
@@ -1762,11 +1953,7 @@ __global__ __launch_bounds__(kBlock) void k_eliminate(const LevelBox* boxes, int
     // identically whatever launch it is part of
     if (r <= kLdsGJMax) {
       if (g == 0) {
-        double* Wl = smem_e;
-        double* rowj = Wl + (size_t)r * r;
-        double* colj = rowj + r;
-        int* rp = reinterpret_cast<int*>(colj + r);
-        rc = lds_gj(W, r, Wl, B.Xinv, rowj, colj, rp, red, ired);
+        rc = reg_gj(W, r, B.Xinv, smem_e, red);
         if (G > 1 && threadIdx.x == 0) st_relaxed(B.cval, rc);
       }
       if (G > 1) {
@@ -2565,7 +2752,9 @@ void launch_assemble_abb(const LevelBox* boxes, int nbox, int max_n, double lam,
 
 size_t eliminate_lds_bytes(int max_n) {
   const int r = std::min(max_n, kLdsGJMax);
-  return ((size_t)r * r + 2 * (size_t)r) * sizeof(double) + r * sizeof(int) + 64;
+  const size_t gj = gj_lds_doubles(r) * sizeof(double);
+  const size_t ts = std::min<size_t>((size_t)max_n * max_n / 4, kTSolveMax) * sizeof(double);
+  return std::max(gj, ts) + 64;
 }
 
 int eliminate_blocks_per_cu(int max_n) {
