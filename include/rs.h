@@ -66,11 +66,14 @@ typedef struct {
   int refine_max;      /* 0: direct solve; > 0: at most this many refinement iterations        */
   int has_root;        /* 1: use root[] as the fixed root square; 0: bounding square of nodes */
   double root[3];      /* fixed root square: centre x, centre y, side                           */
+  int solve_graph;     /* 1: refinement iterations replayed as a captured HIP graph, two per
+                          launch, with the convergence test on the device (a converged or
+                          exhausted iteration leaves x unchanged); 0: launched one by one      */
 } rs_params;
 
 /* Fill *p with the defaults: lambda -0.5, tol 1e-10, leaf 64, 64 proxy points
  * at 1.5 x side, rcond_min 1e-12, float64, refine_tol 1e-8, refine_max 0
- * (direct solve), no fixed root. */
+ * (direct solve), no fixed root, solve_graph 1. */
 void rs_default_params(rs_params* p);
 
 /* Build the adaptive quadtree (Section 2.3) for a boundary discretisation and

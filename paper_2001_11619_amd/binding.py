@@ -37,6 +37,7 @@ class Params(ctypes.Structure):
         ("refine_max", ctypes.c_int),
         ("has_root", ctypes.c_int),
         ("root", ctypes.c_double * 3),
+        ("solve_graph", ctypes.c_int),
     ]
 
 
@@ -159,7 +160,7 @@ class RSSolver:
 
     def __init__(self, xy, normal, weight, curvature, curve_id, hole_xy=None, *, tol=None,
                  leaf_size=None, n_proxy=None, proxy_ratio=None, lam=None, rcond_min=None,
-                 precision=None, refine_tol=None, refine_max=None, root=None):
+                 precision=None, refine_tol=None, refine_max=None, root=None, solve_graph=None):
         lib = load_library()
         self._lib = lib
         self._h = ctypes.c_void_p()
@@ -167,7 +168,7 @@ class RSSolver:
         for name, val in (("tol", tol), ("leaf_size", leaf_size), ("n_proxy", n_proxy),
                           ("proxy_ratio", proxy_ratio), ("lambda_", lam), ("rcond_min", rcond_min),
                           ("precision", precision), ("refine_tol", refine_tol),
-                          ("refine_max", refine_max)):
+                          ("refine_max", refine_max), ("solve_graph", solve_graph)):
             if val is not None:
                 setattr(p, name, val)
         if root is not None:

@@ -228,6 +228,16 @@ struct rs_ctx {
 
   rs_stats stats{};
 
+  // refinement iterations captured as a HIP graph (rebuilt after each factorization)
+  long long factor_epoch = 0;
+  bool capturing = false;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t refine_exec = nullptr;
+  int refine_nrhs = 0;
+  long long refine_epoch = -1;
+  DevBuf d_flag;                  // [converged, corrections applied]
+  PinHost h_flag;
+
   // kernel timing (HIP events around launches)
   int timing = 0;                 // 0 off, 1 per kernel family, 2 per family and level
   int cur_level = -1;
@@ -239,6 +249,8 @@ struct rs_ctx {
   std::vector<double> fam_ms;
 
   ~rs_ctx() {
+    if (refine_exec) (void)hipGraphExecDestroy(refine_exec);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     for (auto& p : pending) {
       (void)hipEventDestroy(p.a);
       (void)hipEventDestroy(p.b);
@@ -289,7 +301,7 @@ struct KTimer {
   hipEvent_t a{};
   // detail: a sub-phase, timed only in per-level mode
   KTimer(rs_ctx* ctx, const char* name, bool detail = false) : c(ctx) {
-    if (!c->timing || (detail && c->timing != 2)) return;
+    if (!c->timing || c->capturing || (detail && c->timing != 2)) return;
     if (c->timing == 2 && c->cur_level >= 0) {
       const std::string full = std::string(name) + "@L" + std::to_string(c->cur_level);
       fam = family(c, full.c_str());
@@ -1287,6 +1299,7 @@ void do_factor_multi(std::vector<rs_ctx*>& cs) {
   cs[0]->cur_level = -1;
   for (size_t i = 0; i < nc; ++i) {
     rs_ctx* c = cs[i];
+    c->factor_epoch++;
     factor_root(c);
     collect_arenas(c);
     c->factored = true;
@@ -1391,6 +1404,130 @@ void apply_inverse(rs_ctx* c, const double* rhs, int ncols, double* out) {
 
 void apply_device_rows(rs_ctx* c, const double* xrows, int ncols, double* yrows);
 
+// Every buffer one refinement iteration touches, allocated up front (a
+// captured graph must not allocate).
+void ensure_solve_buffers(rs_ctx* c, int ncols) {
+  const size_t n2 = 2 * (size_t)c->N;
+  const size_t ns = n2 + 3 * (size_t)c->p;
+  const size_t rows = ns * ncols;
+  const int p3 = 3 * c->p;
+  c->d_r.ensure(rows * sizeof(double));
+  c->d_dx.ensure(rows * sizeof(double));
+  c->d_ys.ensure(rows * sizeof(double));
+  c->d_norms.ensure(2 * (size_t)ncols * sizeof(double));
+  c->d_v.ensure(std::max<size_t>((size_t)c->nz * ncols, 1) * sizeof(double));
+  c->d_sol.ensure(std::max<size_t>((size_t)c->nz * ncols, 1) * sizeof(double));
+  if (p3) {
+    c->d_parts.ensure(std::max<size_t>((size_t)c->n_solve_boxes * p3 * ncols, 1) * sizeof(double));
+    c->d_rhs2.ensure((size_t)p3 * ncols * sizeof(double));
+  }
+  if (c->prm.precision == 1) c->d_cf.ensure(rows * sizeof(float));
+  c->d_apply.ensure(apply_scratch_doubles(c->N, ncols) * sizeof(double));
+  c->d_flag.ensure(4 * sizeof(int));
+}
+
+// One refinement iteration on the context's buffers: dx = inverse(r),
+// x += dx (unless converged), y = A x, r = [f; 0] - y, flags.
+void refine_iteration(rs_ctx* c, int nrhs) {
+  const int n2 = 2 * c->N;
+  const int ns = n2 + 3 * c->p;
+  const size_t rows = (size_t)ns * nrhs;
+  double* colsq = c->d_norms.as<double>();
+  apply_inverse(c, c->d_r.as<double>(), nrhs, c->d_dx.as<double>());
+  launch_accumulate_unless(c->d_dx.as<double>(), (long long)rows, c->d_xs.as<double>(), c->d_flag.as<int>(),
+                           c->prm.refine_max, c->stream);
+  apply_device_rows(c, c->d_xs.as<double>(), nrhs, c->d_ys.as<double>());
+  launch_residual(c->d_frows.as<double>(), n2, c->d_ys.as<double>(), ns, nrhs, c->d_r.as<double>(), colsq,
+                  colsq + nrhs, c->stream);
+  launch_refine_flag(colsq, colsq + nrhs, nrhs, c->prm.refine_tol, c->prm.refine_max, c->d_flag.as<int>(),
+                     c->stream);
+}
+
+constexpr int kRefinePerGraph = 2;   // refinement iterations per graph launch
+
+// x = 0, r = [f; 0], flags cleared (f already in d_frows).
+void refine_begin(rs_ctx* c, int nrhs) {
+  const int n2 = 2 * c->N;
+  const int ns = n2 + 3 * c->p;
+  ensure_solve_buffers(c, nrhs);
+  double* colsq = c->d_norms.as<double>();
+  launch_fill(c->d_xs.as<double>(), (long long)ns * nrhs, 0.0, c->stream);
+  launch_residual(c->d_frows.as<double>(), n2, c->d_xs.as<double>(), ns, nrhs, c->d_r.as<double>(), colsq,
+                  colsq + nrhs, c->stream);
+  launch_set_ints(c->d_flag.as<int>(), 2, 0, c->stream);
+}
+
+// Capture kRefinePerGraph refinement iterations (once per factorization and nrhs).
+void refine_graph_capture(rs_ctx* c, int nrhs) {
+  if (c->refine_exec && c->refine_nrhs == nrhs && c->refine_epoch == c->factor_epoch) return;
+  if (c->refine_exec) {
+    HIP_CHECK(hipGraphExecDestroy(c->refine_exec));
+    c->refine_exec = nullptr;
+  }
+  if (!c->cap_stream) HIP_CHECK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  hipStream_t saved = c->stream;
+  c->stream = c->cap_stream;
+  c->capturing = true;
+  hipGraph_t g = nullptr;
+  HIP_CHECK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+  try {
+    for (int it = 0; it < kRefinePerGraph; ++it) refine_iteration(c, nrhs);
+  } catch (...) {
+    (void)hipStreamEndCapture(c->cap_stream, &g);
+    if (g) (void)hipGraphDestroy(g);
+    c->stream = saved;
+    c->capturing = false;
+    throw;
+  }
+  const hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+  c->stream = saved;
+  c->capturing = false;
+  if (e != hipSuccess) throw RsError{RS_ERR_DEVICE, std::string("graph capture failed: ") + hipGetErrorString(e)};
+  const hipError_t e2 = hipGraphInstantiate(&c->refine_exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e2 != hipSuccess) {
+    c->refine_exec = nullptr;
+    throw RsError{RS_ERR_DEVICE, std::string("graph instantiation failed: ") + hipGetErrorString(e2)};
+  }
+  c->refine_nrhs = nrhs;
+  c->refine_epoch = c->factor_epoch;
+}
+
+void refine_graph_launch(rs_ctx* c, int nrhs) {
+  refine_graph_capture(c, nrhs);
+  KTimer kt_(c, "refine_graph");
+  HIP_CHECK(hipGraphLaunch(c->refine_exec, c->stream));
+}
+
+// Read the flags and norms after a graph launch; true when refinement is over
+// (conv receives whether it converged).  Fills last_res and refine_iters.
+bool refine_poll(rs_ctx* c, int nrhs, bool& conv) {
+  int* hf = c->h_flag.get<int>(4 + 4 * (size_t)nrhs);
+  double* hn = reinterpret_cast<double*>(hf + 4);
+  HIP_CHECK(hipMemcpyAsync(hf, c->d_flag.p, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIP_CHECK(hipMemcpyAsync(hn, c->d_norms.p, 2 * (size_t)nrhs * sizeof(double), hipMemcpyDeviceToHost,
+                           c->stream));
+  HIP_CHECK(hipStreamSynchronize(c->stream));
+  resolve_timers(c);
+  c->stats.refine_iters = hf[1];
+  c->last_res.assign(nrhs, 0.0);
+  for (int q = 0; q < nrhs; ++q) {
+    const double fq = hn[nrhs + q] > 0 ? hn[nrhs + q] : 1.0;
+    c->last_res[q] = std::sqrt(hn[q] / fq);
+  }
+  conv = hf[0] != 0;
+  return conv || hf[1] >= c->prm.refine_max;
+}
+
+// The same iterations launched one by one, the host testing after each.
+bool refine_eager(rs_ctx* c, int nrhs) {
+  for (;;) {
+    refine_iteration(c, nrhs);
+    bool conv;
+    if (refine_poll(c, nrhs, conv)) return conv;
+  }
+}
+
 // Solve with f_dev (2N x nrhs, column-major) into x_dev ((2N+3p) x nrhs,
 // column-major).  With refine_max > 0: iterative refinement, the residual
 // [f; 0] - A x evaluated exactly in float64 and the factored inverse (float64
@@ -1417,41 +1554,15 @@ bool solve_device(rs_ctx* c, int nrhs, const double* f_dev, double* x_dev) {
     HIP_CHECK(hipGetLastError());
     return true;
   }
-  c->d_r.ensure(rows * sizeof(double));
-  c->d_dx.ensure(rows * sizeof(double));
-  c->d_ys.ensure(rows * sizeof(double));
-  c->d_norms.ensure(2 * (size_t)nrhs * sizeof(double));
-  double* x = c->d_xs.as<double>();
-  double* r = c->d_r.as<double>();
-  double* dx = c->d_dx.as<double>();
-  double* y = c->d_ys.as<double>();
-  double* colsq = c->d_norms.as<double>();
-  double* fsq = colsq + nrhs;
-  launch_fill(x, (long long)rows, 0.0, s);
-  launch_residual(c->d_frows.as<double>(), n2, x, ns, nrhs, r, colsq, fsq, s);   // r = [f; 0]
-  std::vector<double> nrm(2 * nrhs);
-  bool conv = false;
-  for (int it = 0; it < c->prm.refine_max; ++it) {
-    apply_inverse(c, r, nrhs, dx);
-    launch_accumulate(dx, (long long)rows, x, s);
-    apply_device_rows(c, x, nrhs, y);
-    launch_residual(c->d_frows.as<double>(), n2, y, ns, nrhs, r, colsq, fsq, s);
-    HIP_CHECK(hipMemcpyAsync(nrm.data(), colsq, 2 * nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIP_CHECK(hipStreamSynchronize(s));
-    c->stats.refine_iters = it + 1;
-    double worst = 0.0;
-    c->last_res.assign(nrhs, 0.0);
-    for (int q = 0; q < nrhs; ++q) {
-      const double fq = nrm[nrhs + q] > 0 ? nrm[nrhs + q] : 1.0;
-      c->last_res[q] = std::sqrt(nrm[q] / fq);
-      worst = std::max(worst, c->last_res[q]);
-    }
-    if (worst <= c->prm.refine_tol) {
-      conv = true;
-      break;
-    }
+  refine_begin(c, nrhs);
+  bool conv;
+  if (c->prm.solve_graph) {
+    refine_graph_launch(c, nrhs);
+    while (!refine_poll(c, nrhs, conv)) refine_graph_launch(c, nrhs);
+  } else {
+    conv = refine_eager(c, nrhs);
   }
-  launch_from_rows(x, ns, nrhs, x_dev, ns, s);
+  launch_from_rows(c->d_xs.as<double>(), ns, nrhs, x_dev, ns, s);
   HIP_CHECK(hipGetLastError());
   return conv;
 }
@@ -1533,6 +1644,7 @@ void rs_default_params(rs_params* p) {
   p->refine_tol = 1e-8;
   p->refine_max = 0;
   p->has_root = 0;
+  p->solve_graph = 1;
 }
 
 rs_status rs_build_tree(const rs_params* prm, int n_nodes, const double* xy, const double* normal,
@@ -1663,13 +1775,73 @@ rs_status rs_factor_batch(rs_ctx** ctxs, int n) {
   }
 }
 
+// Refined solves of n contexts interleaved: every context's first graph
+// launch is queued before the first wait, and each later round relaunches
+// only the contexts still iterating.  Contexts with refine_max = 0 or without
+// the graph path are solved one after another.
 rs_status rs_solve_batch(rs_ctx** ctxs, int n, int nrhs, const double* const* f_dev,
                          double* const* x_dev) {
   if (!ctxs || n <= 0 || !f_dev || !x_dev) return RS_ERR_ARG;
+  for (int i = 0; i < n; ++i)
+    if (!ctxs[i] || !f_dev[i] || !x_dev[i]) return RS_ERR_ARG;
   rs_status worst = RS_OK;
+  std::vector<int> active;
   for (int i = 0; i < n; ++i) {
-    const rs_status st = rs_solve_dev(ctxs[i], nrhs, f_dev[i], x_dev[i]);
-    if (st != RS_OK && worst == RS_OK) worst = st;
+    rs_ctx* c = ctxs[i];
+    if (!c->factored || nrhs <= 0 || c->prm.refine_max <= 0 || !c->prm.solve_graph) {
+      const rs_status st = rs_solve_dev(c, nrhs, f_dev[i], x_dev[i]);
+      if (st != RS_OK && worst == RS_OK) worst = st;
+    } else {
+      active.push_back(i);
+    }
+  }
+  std::vector<std::chrono::steady_clock::time_point> t0(n);
+  std::vector<char> conv(n, 0);
+  std::vector<int> live;
+  for (int i : active) {
+    rs_ctx* c = ctxs[i];
+    try {
+      HIP_CHECK(hipSetDevice(c->device));
+      t0[i] = std::chrono::steady_clock::now();
+      const int n2 = 2 * c->N;
+      const size_t rows = (size_t)(n2 + 3 * c->p) * nrhs;
+      c->d_frows.ensure((size_t)n2 * nrhs * sizeof(double));
+      c->d_xs.ensure(rows * sizeof(double));
+      launch_to_rows(f_dev[i], n2, n2, nrhs, c->d_frows.as<double>(), c->stream);
+      c->last_res.clear();
+      c->stats.refine_iters = 0;
+      refine_begin(c, nrhs);
+      refine_graph_launch(c, nrhs);
+      live.push_back(i);
+    } catch (const RsError& e) {
+      const rs_status st = fail(c, e);
+      if (worst == RS_OK) worst = st;
+    }
+  }
+  while (!live.empty()) {
+    std::vector<int> next;
+    for (int i : live) {
+      rs_ctx* c = ctxs[i];
+      try {
+        HIP_CHECK(hipSetDevice(c->device));
+        bool cv = false;
+        if (refine_poll(c, nrhs, cv)) {
+          conv[i] = cv;
+          const int ns = 2 * c->N + 3 * c->p;
+          launch_from_rows(c->d_xs.as<double>(), ns, nrhs, x_dev[i], ns, c->stream);
+          HIP_CHECK(hipStreamSynchronize(c->stream));
+          c->stats.ms_solve = 1e3 * seconds_since(t0[i]);
+          if (!cv) throw RsError{RS_ERR_NOCONV, "refinement did not reach refine_tol"};
+        } else {
+          refine_graph_launch(c, nrhs);
+          next.push_back(i);
+        }
+      } catch (const RsError& e) {
+        const rs_status st = fail(c, e);
+        if (worst == RS_OK) worst = st;
+      }
+    }
+    live.swap(next);
   }
   return worst;
 }

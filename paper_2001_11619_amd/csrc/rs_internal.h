@@ -173,6 +173,11 @@ void launch_root_scatter(const double* sol, int ncols, const int* I0, int n0, T*
 void launch_to_float(const double* x, long long n, float* y, hipStream_t s);
 void launch_to_double(const float* x, long long n, double* y, hipStream_t s);
 void launch_fill(double* x, long long n, double v, hipStream_t s);
+void launch_refine_flag(const double* colsq, const double* fsq, int ncols, double tol, int max_iters,
+                        int* flag, hipStream_t s);
+void launch_accumulate_unless(const double* d, long long n, double* x, const int* flag, int max_iters,
+                              hipStream_t s);
+void launch_set_ints(int* p, int n, int v, hipStream_t s);
 void launch_accumulate(const double* d, long long n, double* x, hipStream_t s);
 void launch_accumulate(const float* d, long long n, double* x, hipStream_t s);
 void launch_residual(const double* f, int nf, const double* y, int nrows, int ncols, double* r,

@@ -2466,6 +2466,37 @@ __global__ void k_accumulate(const TI* d, long long n, double* x) {
   if (t < n) x[t] += (double)d[t];
 }
 
+// Refinement control on the device (lets the refinement iterations run as a
+// captured graph).  flag[0] = 1 once max_q sqrt(colsq[q] / fsq[q]) <= tol
+// (fsq = 0 counts as 1); flag[1] counts the corrections applied.  Per
+// iteration: k_accumulate_unless (reads the flags), operator apply, residual,
+// then k_refine_flag (the only writer: counts the correction the iteration
+// applied, then tests the new residual).
+__global__ void k_refine_flag(const double* colsq, const double* fsq, int ncols, double tol,
+                              int max_iters, int* flag) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  if (flag[0] == 0 && flag[1] < max_iters) flag[1] += 1;
+  double worst = 0.0;
+  for (int q = 0; q < ncols; ++q) {
+    const double fq = fsq[q] > 0.0 ? fsq[q] : 1.0;
+    worst = fmax(worst, sqrt(colsq[q] / fq));
+  }
+  flag[0] = worst <= tol ? 1 : 0;
+}
+
+// x += d unless refinement has converged or used up its iterations.
+__global__ void k_accumulate_unless(const double* d, long long n, double* x, const int* flag,
+                                    int max_iters) {
+  if (flag[0] || flag[1] >= max_iters) return;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) x[t] += d[t];
+}
+
+__global__ void k_set_ints(int* p, int n, int v) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) p[t] = v;
+}
+
 // r = [f; 0] - y  (rows layout, f has nf rows); colsq[q] = ||r_q||^2 and fsq[q] = ||f_q||^2,
 // one block per column, fixed-order sums.
 __global__ __launch_bounds__(kBlock) void k_residual(const double* f, int nf, const double* y,
@@ -2941,6 +2972,21 @@ void launch_to_float(const double* x, long long n, float* y, hipStream_t s) {
 void launch_to_double(const float* x, long long n, double* y, hipStream_t s) {
   if (n) hipLaunchKernelGGL((k_convert<double, float>), dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, x, n, y);
 }
+void launch_refine_flag(const double* colsq, const double* fsq, int ncols, double tol, int max_iters,
+                        int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_refine_flag, dim3(1), dim3(64), 0, s, colsq, fsq, ncols, tol, max_iters, flag);
+}
+
+void launch_accumulate_unless(const double* d, long long n, double* x, const int* flag, int max_iters,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_accumulate_unless, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, d, n, x,
+                     flag, max_iters);
+}
+
+void launch_set_ints(int* p, int n, int v, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_ints, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, p, n, v);
+}
+
 void launch_fill(double* x, long long n, double v, hipStream_t s) {
   if (n) hipLaunchKernelGGL(k_fill, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, x, n, v);
 }

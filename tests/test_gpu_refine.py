@@ -68,3 +68,52 @@ def test_noconv_reported():
     with pytest.raises(RSError) as e:
         s.solve(f)
     assert e.value.name == "RS_ERR_NOCONV"
+
+
+def test_graph_refinement_matches_eager():
+    """Refinement replayed as a captured HIP graph (device-side convergence
+    test) gives bitwise the iterates of the iterations launched one by one:
+    over several replays with other device work and waits between them, after
+    a new factorization (recapture) and for another number of columns."""
+    from workloads import workload_small
+
+    g = workload_small(seed=11, n_outer=256, n_holes=2, nodes_per_hole=128, radius=3.0)
+    kw = dict(leaf_size=32, tol=1e-5, precision=1, refine_max=20, refine_tol=1e-10)
+    se = _solver(g, solve_graph=0, **kw).factor()
+    sg = _solver(g, solve_graph=1, **kw).factor()
+    f = boundary_data(g, exterior_forces_for_geometry(g, 3, seed=2))
+    xe, re = se.solve(f, residual=True)
+    ie = se.stats()["refine_iters"]
+    assert ie >= 3                      # several graph launches (two iterations each)
+    rng = np.random.Generator(np.random.PCG64(1))
+    for rep in range(4):
+        xg, rg = sg.solve(f, residual=True)
+        assert np.array_equal(xg, xe) and np.array_equal(rg, re)
+        assert sg.stats()["refine_iters"] == ie
+        sg.apply(rng.standard_normal((g.n_system, 2)))     # eager work between replays
+    sg.factor()
+    assert np.array_equal(sg.solve(f), xe)
+    f1 = f[:, :1]
+    assert np.array_equal(sg.solve(f1), se.solve(f1))
+
+
+def test_solve_batch_matches_single():
+    """The interleaved batched solve returns each context's own solution."""
+    import torch
+
+    from paper_2001_11619_amd import factor_batch, solve_batch
+    from workloads import random_holes_geometry, single_ellipse
+
+    geoms = [random_holes_geometry(41 + i, 5.0, 512, [128] * (i + 1)) for i in range(3)]
+    geoms.append(single_ellipse(600, 1.0, 0.5))
+    kw = dict(leaf_size=32, tol=1e-7, precision=1, refine_max=20, refine_tol=1e-9)
+    batch = [_solver(gg, **kw) for gg in geoms]
+    factor_batch(batch)
+    fs = [boundary_data(gg, exterior_forces_for_geometry(gg, 3, seed=3)) for gg in geoms]
+    f_dev = [torch.tensor(np.ascontiguousarray(ff.T), dtype=torch.float64, device="cuda") for ff in fs]
+    x_dev = [torch.empty((3, gg.n_system), dtype=torch.float64, device="cuda") for gg in geoms]
+    torch.cuda.synchronize()
+    solve_batch(batch, f_dev, x_dev)
+    for gg, s, ff, xd in zip(geoms, batch, fs, x_dev):
+        alone = _solver(gg, **kw).factor()
+        assert np.array_equal(xd.cpu().numpy().T, alone.solve(ff))
