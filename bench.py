@@ -42,6 +42,133 @@ WORKLOADS = {
 }
 
 
+def batch_geometries(n):
+    """Members 0, k, 2k, ... of the 512-geometry batch (k = 512 // n): n geometries."""
+    import workloads as W
+
+    stride = max(1, 512 // n)
+    return [W.workload_batch_member(i * stride) for i in range(n)]
+
+
+def run_batch(args, forms):
+    """Many geometries: mixed precision, factored level-synchronously
+    (rs_factor_batch) and solved interleaved (rs_solve_batch), 16 right-hand
+    sides each, against the plain float64 path on the same geometries one
+    after another."""
+    import numpy as np
+    import torch
+
+    from paper_2001_11619_amd import RSSolver, factor_batch, solve_batch
+    from workloads import boundary_data, exterior_forces_for_geometry
+
+    nb, nrhs = args.batch_size, 16
+    geoms = batch_geometries(nb)
+    fs = [boundary_data(g, exterior_forces_for_geometry(g, nrhs, seed=100 + i)) for i, g in enumerate(geoms)]
+    out = {}
+    for form in forms:
+        kw = dict(tol=args.tol_plain, precision=0) if form == "plain" else dict(tol=args.tol_mixed, precision=1)
+        t0 = time.perf_counter()
+        sv = [RSSolver.from_geometry(g, refine_max=20, refine_tol=1e-8, **kw) for g in geoms]
+        setup_ms = 1e3 * (time.perf_counter() - t0)
+        stream = torch.cuda.current_stream().cuda_stream
+        for s in sv:
+            s.set_stream(stream)
+        fd = [torch.tensor(np.ascontiguousarray(f.T), dtype=torch.float64, device="cuda") for f in fs]
+        xd = [torch.empty((nrhs, g.n_system), dtype=torch.float64, device="cuda") for g in geoms]
+
+        def step():
+            if form == "plain":
+                for s, f_, x_ in zip(sv, fd, xd):
+                    s.factor()
+                    s.solve_dev(f_, x_)
+            else:
+                factor_batch(sv)
+                solve_batch(sv, fd, xd)
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        res = max(float(np.max(s.solve(f, residual=True)[1])) for s, f in zip(sv, fs))
+        out[form] = {"value": nb * nrhs * args.steps / el, "ms_per_step": 1e3 * el / args.steps,
+                     "setup_ms": setup_ms, "max_rel_residual": res}
+        del sv
+    unknowns = [g.n_system for g in geoms]
+    head = out[forms[0]]
+    js = {
+        "metric": "RS factor s + solves/s at 1e-8 rel. residual, mixed-batched vs FP64 plain",
+        "value": head["value"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if forms[0] == "mixed" else "f64", "data": "synthetic",
+        "config": {"workload": "batch%d_of_512" % nb, "geometries": nb, "nrhs_each": nrhs,
+                   "unknowns_min": min(unknowns), "unknowns_max": max(unknowns),
+                   "unknowns_total": int(sum(unknowns)), "form": forms[0]},
+        "max_rel_residual": head["max_rel_residual"], "setup_ms": head["setup_ms"],
+    }
+    for fm in forms[1:]:
+        js["form_" + fm] = out[fm]
+        js["speedup_vs_" + fm] = head["value"] / out[fm]["value"]
+    return js
+
+
+def run_evolve(args):
+    """Evolving domain: the 64-hole geometry, one ellipse moved per step
+    (translation 0.05 N(0, I), rotation U[-0.1, 0.1]), the factorization
+    updated (only boxes whose inputs changed are recompressed) and 16
+    right-hand sides solved to 1e-8; one full refactorization timed beside."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2001_11619_amd import RSSolver
+    from workloads import boundary_data, exterior_forces_for_geometry
+
+    g = W.workload_circle40_64holes()
+    nrhs = 16
+    kw = dict(tol=args.tol_mixed, precision=1, refine_max=20, refine_tol=1e-8)
+    s = RSSolver.from_geometry(g, **kw)
+    s.set_stream(torch.cuda.current_stream().cuda_stream)
+    root = tuple(s.boxes()["geom"][0])
+    s.factor()
+    rng = np.random.Generator(np.random.PCG64(5))
+    upd, sol, res, recomp = [], [], [], []
+    t_all = time.perf_counter()
+    for t in range(args.evolve_steps):
+        g, moved = W.move_hole(g, 1 + t % g.n_holes if args.evolve_all else 1, rng)
+        s.update_moved_nodes(moved, g.xy[moved], g.normal[moved], g.weight[moved], g.curvature[moved],
+                             hole_xy=g.hole_xy)
+        st = s.stats()
+        upd.append(st["ms_update"])
+        recomp.append(st["boxes_recomputed"])
+        f = boundary_data(g, exterior_forces_for_geometry(g, nrhs, seed=t))
+        x, r = s.solve(f, residual=True)
+        sol.append(s.stats()["ms_solve"])
+        res.append(float(np.max(r)))
+    el = time.perf_counter() - t_all
+    g.root = np.array(root)
+    fresh = RSSolver.from_geometry(g, root=root, **kw)
+    fresh.factor()
+    fresh.factor()
+    refactor_ms = fresh.stats()["ms_factor"]
+    nbox = int(np.sum(fresh.boxes()["n"][1:] > 0))
+    return {
+        "metric": "RS factorization update (Section 2.8) vs full refactor, mixed precision, 16 rhs to 1e-8",
+        "value": float(np.median(upd)), "unit": "ms/update", "higher_is_better": False, "n_gpus": 1,
+        "steps": args.evolve_steps, "data": "synthetic", "dtype": "f32+f64",
+        "config": {"workload": "circle40_64holes_evolving", "nrhs": nrhs, "moved_nodes_per_step": int(len(moved)),
+                   "tol": args.tol_mixed},
+        "update_ms_median": float(np.median(upd)), "update_ms_max": float(np.max(upd)),
+        "refactor_ms": refactor_ms, "speedup_update_vs_refactor": refactor_ms / float(np.median(upd)),
+        "boxes_recomputed_median": float(np.median(recomp)), "boxes_total": nbox,
+        "solve_ms_median": float(np.median(sol)), "max_rel_residual": float(np.max(res)),
+        "residual_per_step": res, "wall_s": el,
+    }
+
+
 def make_geometry(name):
     import workloads as W
 
@@ -153,11 +280,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="circle10_8holes", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="circle10_8holes", choices=sorted(WORKLOADS) + ["batch", "evolve"])
     ap.add_argument("--tol-plain", type=float, default=1e-10)
     ap.add_argument("--tol-mixed", type=float, default=1e-7)
     ap.add_argument("--forms", default="mixed,plain")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-size", type=int, default=32)
+    ap.add_argument("--evolve-steps", type=int, default=10)
+    ap.add_argument("--evolve-all", action="store_true", help="move hole 1, 2, 3, ... in turn")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % args.gpus,
@@ -168,6 +298,19 @@ def main():
 
     from workloads import boundary_data, exterior_forces_for_geometry
 
+    if args.workload in ("circle40_64holes", "evolve"):
+        # A factorization of this 131072-node geometry ended in a device memory
+        # fault whose cause is not yet found; these modes stay disabled until it is.
+        print("bench.py: workload %s is disabled (open device-fault investigation)" % args.workload,
+              file=sys.stderr)
+        sys.exit(3)
+    torch.cuda.set_device(0)
+    if args.workload == "batch":
+        print(json.dumps(run_batch(args, [x for x in args.forms.split(",") if x])), flush=True)
+        return
+    if args.workload == "evolve":
+        print(json.dumps(run_evolve(args)), flush=True)
+        return
     wl = WORKLOADS[args.workload]
     geom = make_geometry(args.workload)
     f = boundary_data(geom, exterior_forces_for_geometry(geom, wl["nrhs"], seed=wl["seed"]))

@@ -61,7 +61,10 @@ typedef struct {
   int n_proxy;         /* points on each box's proxy circle (Section 2.5)                       */
   double proxy_ratio;  /* proxy radius = proxy_ratio * box side                                  */
   double rcond_min;    /* X_RR guard: move a pivot from R to S while rcond_1(X_RR) < rcond_min  */
-  int precision;       /* 0 = float64 throughout; 1 = mixed (float32 bulk, float64 refinement)   */
+  int precision;       /* 0 = float64 throughout; 1 = mixed: float32 copies of T, E, F, X_RR^-1
+                          (and the border W) serve the solve for every box whose rcond_1(X_RR)
+                          is at least 1e-4 (the others keep float64); vectors, sums, the
+                          pivoted QR, the inverses and the root stay float64                      */
   double refine_tol;   /* refinement target: max-column ||[f;0] - A x||_2 / ||f||_2             */
   int refine_max;      /* 0: direct solve; > 0: at most this many refinement iterations        */
   int has_root;        /* 1: use root[] as the fixed root square; 0: bounding square of nodes */
@@ -104,12 +107,10 @@ rs_status rs_factor(rs_ctx* ctx);
  *                 with A applied exactly in float64 on the device
  * With refine_max > 0 the solve is iterative refinement: the residual
  * [f;0] - A x is evaluated exactly in float64 on the device (O(N^2) pairs)
- * and the factorization (float64, or float32 when precision = 1) is the inner
- * solver, until every column reaches refine_tol; RS_ERR_NOCONV means
- * refine_max iterations did not reach it, x then holds the last iterate and
- * rel_residual (if given) its residuals.  precision = 1 keeps the pivoted QR,
- * X_RR^{-1} and the root system in float64 and applies T, E, F, X_RR^{-1}
- * in float32. */
+ * and the factorization (with the float32 factor copies when precision = 1)
+ * is the inner solver, until every column reaches refine_tol; RS_ERR_NOCONV
+ * means refine_max iterations did not reach it, x then holds the last iterate
+ * and rel_residual (if given) its residuals. */
 rs_status rs_solve(rs_ctx* ctx, int nrhs, const double* f, double* x, double* rel_residual);
 
 /* As rs_solve, with f and x device pointers (same layouts) used on the
@@ -141,7 +142,9 @@ rs_status rs_update_moved_nodes(rs_ctx* ctx, int n_moved, const int* idx, const 
 rs_status rs_factor_batch(rs_ctx** ctxs, int n);
 
 /* rs_solve_dev for each of n factored contexts (f_dev[i], x_dev[i] laid out
- * as for rs_solve_dev of context i).  Returns the first non-RS_OK status. */
+ * as for rs_solve_dev of context i).  Refined solves with solve_graph = 1 are
+ * interleaved: every context's first graph launch is queued before the first
+ * wait.  Returns the first non-RS_OK status (each context carries its message). */
 rs_status rs_solve_batch(rs_ctx** ctxs, int n, int nrhs, const double* const* f_dev,
                          double* const* x_dev);
 

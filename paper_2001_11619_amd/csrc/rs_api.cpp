@@ -158,6 +158,7 @@ struct BoxFac {
   float* Xinvf = nullptr;
   int arena = -1;             // id of the device arena holding T, E, F, Xinv, Xss
   int rank0 = 0;
+  double rcond = 1.0;         // rcond_1 of the accepted X_RR
   std::vector<int> fint;      // near field F_int used by the compression
 };
 
@@ -172,6 +173,10 @@ struct OldState {
 };
 
 constexpr int kMaxDepth = 48;
+// Mixed precision: a box's float copies of T, E, F, X_RR^{-1} are used by the
+// solve only when rcond_1(X_RR) is at least this (float rounding of the
+// factors is then amplified by at most ~1e4).
+constexpr double kMixedRcondMin = 1e-4;
 constexpr int kGuardExtra = 8;
 
 inline long long key2(long long ix, long long iy) { return (ix << 32) ^ (iy & 0xffffffffLL); }
@@ -203,16 +208,16 @@ struct rs_ctx {
   int next_arena = 0;
   std::vector<char> recomputed;   // per box of the current tree
   std::vector<int> lvl_pos;       // host scratch of prepare_level
-  PinHost h_rank, h_perm, h_small;  // pinned read-back buffers
+  PinHost h_rank, h_perm, h_small, h_rc;  // pinned read-back buffers
   const OldState* old = nullptr;  // set while an update runs
   // level workspaces (reused level to level)
   DevBuf ws_M, ws_R, ws_A, ws_scr, ws_boxes, ws_dofs, ws_fint, ws_src, ws_perm, ws_k, ws_kx,
-      ws_status, ws_coop, ws_err, ws_work, ws_fblist, ws_tasks, ws_tq, ws_work16;
+      ws_status, ws_coop, ws_err, ws_work, ws_fblist, ws_tasks, ws_tq, ws_work16, ws_rc;
   int n_cu = 0;                   // compute units of the device
   // root
   std::vector<int> I0;
   DevBuf d_I0, d_X0, d_Z, d_Zinv, d_gjwork, d_gjiwork, d_rcond, d_rstatus, d_root_box;
-  DevBuf d_H, d_Hh, d_Ph, d_Phf, d_Gpart, d_G, d_bscr, d_W, d_Wf;
+  DevBuf d_H, d_Hh, d_Ph, d_Gpart, d_G, d_bscr, d_W, d_Wf;
   int nz = 0;
   // solve metadata
   std::vector<std::vector<SolveBox>> sboxes;   // per level
@@ -222,7 +227,7 @@ struct rs_ctx {
   int n_solve_boxes = 0;
   int all_maxr = 0;
   // solve work
-  DevBuf d_f, d_c, d_cf, d_v, d_sol, d_parts, d_rhs2, d_xout, d_res, d_frows, d_xs, d_r, d_dx,
+  DevBuf d_f, d_c, d_v, d_sol, d_parts, d_rhs2, d_xout, d_res, d_frows, d_xs, d_r, d_dx,
       d_ys, d_norms, d_apply;
   std::vector<double> last_res;   // relative residual per column of the last refined solve
 
@@ -760,7 +765,7 @@ void prepare_level(rs_ctx* c, int l, const std::vector<int>& ids, const std::vec
 }
 
 // Ranks and pivot orders read back for one context: fill its box records.
-void finish_level(rs_ctx* c, LevelPrep& P, const int* k0, const int* kk, const int* st,
+void finish_level(rs_ctx* c, LevelPrep& P, const int* k0, const int* kk, const int* st, const double* rc,
                   std::vector<int>& boxes_done) {
   for (size_t i = 0; i < P.lb.size(); ++i) {
     const int b = P.ids[P.sel[i]];
@@ -769,6 +774,7 @@ void finish_level(rs_ctx* c, LevelPrep& P, const int* k0, const int* kk, const i
     f.perm.assign(P.perm.begin() + P.doff[i], P.perm.begin() + P.doff[i] + x.n);
     f.k = kk[i];
     f.rank0 = k0[i];
+    f.rcond = rc[i];
     f.arena = P.aid;
     if (st[i] != 0)
       throw RsError{RS_ERR_SINGULAR, "X_RR stayed singular after the pivot guard (box " +
@@ -961,6 +967,7 @@ void launch_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps) {
   c->ws_k.ensure(nb * sizeof(int));
   c->ws_kx.ensure(nb * sizeof(int));
   c->ws_status.ensure(nb * sizeof(int));
+  c->ws_rc.ensure(nb * sizeof(double));
   c->ws_err.ensure(sizeof(int) * 4);
   const LevelBox* dlb = c->ws_boxes.as<LevelBox>();
   {
@@ -1018,13 +1025,16 @@ void launch_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps) {
   {
     KTimer kt_(c, "eliminate");
     HIP_CHECK(launch_eliminate(dlb, nb, Ge, c->ws_k.as<int>(), c->ws_kx.as<int>(), prm.rcond_min,
-                               c->ws_status.as<int>(), c->ws_err.as<int>() + 1, max_n, s));
+                               c->ws_status.as<int>(), c->ws_rc.as<double>(), c->ws_err.as<int>() + 1,
+                               max_n, s));
     if (prm.precision == 1) launch_factor_to_float(dlb, nb, c->ws_k.as<int>(), s);
   }
   HIP_CHECK(hipGetLastError());
   HIP_CHECK(hipMemcpyAsync(qr_err, c->ws_err.p, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
   HIP_CHECK(hipMemcpyAsync(kk, c->ws_k.p, nb * sizeof(int), hipMemcpyDeviceToHost, s));
   HIP_CHECK(hipMemcpyAsync(st, c->ws_status.p, nb * sizeof(int), hipMemcpyDeviceToHost, s));
+  double* hrc = c->h_rc.get<double>(nb);
+  HIP_CHECK(hipMemcpyAsync(hrc, c->ws_rc.p, nb * sizeof(double), hipMemcpyDeviceToHost, s));
   std::vector<int*> hperm(cs.size(), nullptr);
   for (size_t i = 0; i < cs.size(); ++i) {
     LevelPrep& P = preps[i];
@@ -1046,7 +1056,7 @@ void launch_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps) {
     LevelPrep& P = preps[i];
     if (P.lb.empty()) continue;
     std::vector<int> done;
-    finish_level(cs[i], P, k0 + P.first, kk + P.first, st + P.first, done);
+    finish_level(cs[i], P, k0 + P.first, kk + P.first, st + P.first, hrc + P.first, done);
   }
 }
 
@@ -1073,10 +1083,13 @@ void build_solve_meta(rs_ctx* c) {
     sb.F = f.F;
     sb.Xinv = f.Xinv;
     sb.W = nullptr;
-    sb.Tf = f.Tf;
-    sb.Ef = f.Ef;
-    sb.Ff = f.Ff;
-    sb.Xinvf = f.Xinvf;
+    // mixed precision: the float copies serve the solve only where X_RR is
+    // well conditioned; elsewhere the box's float64 factors are read
+    const bool use_f = c->prm.precision == 1 && f.rcond >= kMixedRcondMin && f.Tf;
+    sb.Tf = use_f ? f.Tf : nullptr;
+    sb.Ef = use_f ? f.Ef : nullptr;
+    sb.Ff = use_f ? f.Ff : nullptr;
+    sb.Xinvf = use_f ? f.Xinvf : nullptr;
     sb.Wf = nullptr;
     for (int i = 0; i < f.k; ++i) sidx.push_back(f.I[f.perm[i]]);
     for (int i = f.k; i < f.n; ++i) ridx.push_back(f.I[f.perm[i]]);
@@ -1105,7 +1118,7 @@ void build_solve_meta(rs_ctx* c) {
         sb.W = pw;
         pw += (size_t)sb.r * p3;
         if (pwf) {
-          sb.Wf = pwf;
+          if (sb.Tf) sb.Wf = pwf;
           pwf += (size_t)sb.r * p3;
         }
       }
@@ -1207,8 +1220,6 @@ void factor_root(rs_ctx* c) {
     }
     if (c->prm.precision == 1) {
       for (int l = c->L; l >= 1; --l) launch_w_to_float(level_sboxes(c, l), level_count(c, l), p3, s);
-      c->d_Phf.ensure(hn * sizeof(float));
-      launch_to_float(c->d_Ph.as<double>(), (long long)hn, c->d_Phf.as<float>(), s);
     }
     c->d_G.ensure((size_t)p3 * p3 * sizeof(double));
     launch_sum_parts(c->d_Gpart.as<double>(), nsb, (long long)p3 * p3, p3 * p3, 1.0,
@@ -1318,13 +1329,6 @@ void do_factor(rs_ctx* c) {
   do_factor_multi(cs);
 }
 
-template <typename T>
-const T* ph_of(const rs_ctx* c);
-template <>
-const double* ph_of<double>(const rs_ctx* c) { return c->d_Ph.as<double>(); }
-template <>
-const float* ph_of<float>(const rs_ctx* c) { return c->d_Phf.as<float>(); }
-
 // Apply the factored inverse in place: cbuf (rows layout, ncols columns) holds
 // the first 2N rows of the right-hand side on entry and [mu; lambda] (2N + 3p
 // rows) on exit.  rbot (nullable, float64, 3p x ncols) is the right-hand side
@@ -1349,7 +1353,7 @@ void solve_rows(rs_ctx* c, T* cbuf, int ncols, const double* rbot) {
     c->d_parts.ensure(std::max<size_t>((size_t)nsb * p3 * ncols, 1) * sizeof(double));
     for (int l = c->L; l >= 1; --l) {
       KTimer kt_(c, "border_rhs");
-      launch_border_rhs<T>(level_sboxes(c, l), level_count(c, l), c->d_ridx.as<int>(), ph_of<T>(c),
+      launch_border_rhs<T>(level_sboxes(c, l), level_count(c, l), c->d_ridx.as<int>(), c->d_Ph.as<double>(),
                            p3, cbuf, ncols, c->d_parts.as<double>(), s);
     }
     c->d_rhs2.ensure((size_t)p3 * ncols * sizeof(double));
@@ -1376,10 +1380,7 @@ void solve_rows(rs_ctx* c, T* cbuf, int ncols, const double* rbot) {
     }
     // lambda rows follow the 2N density rows
     T* dst = cbuf + (size_t)2 * c->N * ncols;
-    if (sizeof(T) == sizeof(double))
-      HIP_CHECK(hipMemcpyAsync(dst, lam, (size_t)p3 * ncols * sizeof(double), hipMemcpyDeviceToDevice, s));
-    else
-      launch_to_float(lam, (long long)p3 * ncols, reinterpret_cast<float*>(dst), s);
+    HIP_CHECK(hipMemcpyAsync(dst, lam, (size_t)p3 * ncols * sizeof(T), hipMemcpyDeviceToDevice, s));
   }
   sweep_all<T>(c, cbuf, ncols, 2);
 }
@@ -1390,16 +1391,11 @@ void apply_inverse(rs_ctx* c, const double* rhs, int ncols, double* out) {
   const size_t n2 = 2 * (size_t)c->N;
   const size_t ns = n2 + 3 * (size_t)c->p;
   const double* rbot = c->p ? rhs + n2 * ncols : nullptr;
-  if (c->prm.precision == 0) {
-    HIP_CHECK(hipMemcpyAsync(out, rhs, n2 * ncols * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-    solve_rows<double>(c, out, ncols, rbot);
-  } else {
-    c->d_cf.ensure(ns * ncols * sizeof(float));
-    float* cf = c->d_cf.as<float>();
-    launch_to_float(rhs, (long long)(n2 * ncols), cf, c->stream);
-    solve_rows<float>(c, cf, ncols, rbot);
-    launch_to_double(cf, (long long)(ns * ncols), out, c->stream);
-  }
+  (void)ns;
+  // vectors stay float64 in both precisions; mixed precision only changes
+  // which factor copies the boxes read
+  HIP_CHECK(hipMemcpyAsync(out, rhs, n2 * ncols * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  solve_rows<double>(c, out, ncols, rbot);
 }
 
 void apply_device_rows(rs_ctx* c, const double* xrows, int ncols, double* yrows);
@@ -1421,7 +1417,6 @@ void ensure_solve_buffers(rs_ctx* c, int ncols) {
     c->d_parts.ensure(std::max<size_t>((size_t)c->n_solve_boxes * p3 * ncols, 1) * sizeof(double));
     c->d_rhs2.ensure((size_t)p3 * ncols * sizeof(double));
   }
-  if (c->prm.precision == 1) c->d_cf.ensure(rows * sizeof(float));
   c->d_apply.ensure(apply_scratch_doubles(c->N, ncols) * sizeof(double));
   c->d_flag.ensure(4 * sizeof(int));
 }

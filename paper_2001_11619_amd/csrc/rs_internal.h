@@ -137,7 +137,8 @@ void launch_assemble_abb(const LevelBox* boxes, int nbox, int max_n, double lam,
                          hipStream_t s);
 int eliminate_blocks_per_cu(int max_n);
 hipError_t launch_eliminate(const LevelBox* boxes, int nbox, int G, int* k_io, const int* kx,
-                            double rcond_min, int* status, int* err, int max_n, hipStream_t s);
+                            double rcond_min, int* status, double* rc_out, int* err, int max_n,
+                            hipStream_t s);
 void launch_gj_inverse(double* A, int n, int lda, double* Ainv, double* work,
                        double* rcond_out, int* status, hipStream_t s);
 void launch_gj_blocked(double* A, int n, double* Ainv, double* work, int* iwork, int* status,

@@ -1885,7 +1885,7 @@ __device__ bool coop_gj(int g, int G, double* W, int r, double* Xi, double* Pn, 
 // rcond_1(X_RR) < rcond_min); E, F and the Schur complement X_SS (eq. schurmat).
 __global__ __launch_bounds__(kBlock) void k_eliminate(const LevelBox* boxes, int G, int* k_io,
                                                       const int* kx_in, double rcond_min,
-                                                      int* status, int* err) {
+                                                      int* status, double* rc_out, int* err) {
   extern __shared__ double smem_e[];
   constexpr int NW = kBlock / 64;
   __shared__ double red[NW];
@@ -1903,6 +1903,7 @@ __global__ __launch_bounds__(kBlock) void k_eliminate(const LevelBox* boxes, int
   int k = k_io[B.slot];
   const int kx = kx_in[B.slot];
   int st = 0;
+  double rc_final = 1.0;          // rcond_1 of the accepted X_RR (1 when r = 0)
   const double* Ap = B.Ap;
   const int gt = g * kBlock + threadIdx.x, GT = G * kBlock;
   while (true) {
@@ -1978,6 +1979,7 @@ __global__ __launch_bounds__(kBlock) void k_eliminate(const LevelBox* boxes, int
       }
       st = 1;
     }
+    rc_final = rc;
     box_barrier_full(B.bar, G, nbar, &s_dead, err);
     mfma_gemm(g, G, k, r, r, 1.0, Xsr, r, false, B.Xinv, r, false, 0.0, nullptr, 0, B.E, r, sA, sB);
     mfma_gemm(g, G, r, k, r, 1.0, B.Xinv, r, false, Xrs, k, false, 0.0, nullptr, 0, B.F, k, sA, sB);
@@ -1988,6 +1990,7 @@ __global__ __launch_bounds__(kBlock) void k_eliminate(const LevelBox* boxes, int
   if (g == 0 && threadIdx.x == 0) {
     k_io[B.slot] = k;
     status[B.slot] = st;
+    rc_out[B.slot] = rc_final;
   }
 }
 
@@ -2179,38 +2182,16 @@ __global__ void k_iota(int* v, int n, int* zero) {
 
 // ---- solve kernels -----------------------------------------------------------
 
-// Factor blocks of a box in the solve's working precision.
-template <typename T> struct Fac;
-template <> struct Fac<double> {
-  static __device__ const double* t(const SolveBox& b) { return b.T; }
-  static __device__ const double* e(const SolveBox& b) { return b.E; }
-  static __device__ const double* f(const SolveBox& b) { return b.F; }
-  static __device__ const double* xi(const SolveBox& b) { return b.Xinv; }
-  static __device__ const double* w(const SolveBox& b) { return b.W; }
-};
-template <> struct Fac<float> {
-  static __device__ const float* t(const SolveBox& b) { return b.Tf; }
-  static __device__ const float* e(const SolveBox& b) { return b.Ef; }
-  static __device__ const float* f(const SolveBox& b) { return b.Ff; }
-  static __device__ const float* xi(const SolveBox& b) { return b.Xinvf; }
-  static __device__ const float* w(const SolveBox& b) { return b.Wf; }
-};
-
 // mode 0: U   c_R -= T^T c_S ; c_S -= E c_R
 // mode 1: Psi^T V rows (columns of Psi)   c_R -= T^T c_S ; c_S -= F^T c_R
 // mode 2: V   c_R -= F c_S ; c_S -= T c_R
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_sweep(const SolveBox* boxes, const int* sidx,
-                                                  const int* ridx, T* c, int ncols, int mode,
-                                                  int kNC) {
-  extern __shared__ double smem_d[];
-  T* smem = reinterpret_cast<T*>(smem_d);
-  const SolveBox& B = boxes[blockIdx.x];
+// Each box's factors are read in the precision they are stored in (float
+// copies when present, else float64); vectors and sums are float64.
+template <typename T, typename TF>
+__device__ __forceinline__ void sweep_box(const SolveBox& B, const TF* Tm, const TF* Em, const TF* Fm,
+                                          const int* sidx, const int* ridx, T* c, int ncols, int mode,
+                                          int kNC, T* smem) {
   const int k = B.k, r = B.r;
-  if (k == 0 || r == 0) return;
-  const T* Tm = Fac<T>::t(B);
-  const T* Em = Fac<T>::e(B);
-  const T* Fm = Fac<T>::f(B);
   const int q0 = blockIdx.y * kNC;
   const int nq = min(kNC, ncols - q0);
   T* cs = smem;
@@ -2270,16 +2251,23 @@ __global__ __launch_bounds__(kBlock) void k_sweep(const SolveBox* boxes, const i
   }
 }
 
-// c_R <- X_RR^{-1} c_R
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_diag(const SolveBox* boxes, const int* ridx, T* c,
-                                                 int ncols, int kNC) {
+__global__ __launch_bounds__(kBlock) void k_sweep(const SolveBox* boxes, const int* sidx,
+                                                  const int* ridx, T* c, int ncols, int mode,
+                                                  int kNC) {
   extern __shared__ double smem_d[];
   T* smem = reinterpret_cast<T*>(smem_d);
   const SolveBox& B = boxes[blockIdx.x];
+  if (B.k == 0 || B.r == 0) return;
+  if (B.Tf) sweep_box<T, float>(B, B.Tf, B.Ef, B.Ff, sidx, ridx, c, ncols, mode, kNC, smem);
+  else sweep_box<T, double>(B, B.T, B.E, B.F, sidx, ridx, c, ncols, mode, kNC, smem);
+}
+
+// c_R <- X_RR^{-1} c_R
+template <typename T, typename TF>
+__device__ __forceinline__ void diag_box(const SolveBox& B, const TF* Xi, const int* ridx, T* c,
+                                         int ncols, int kNC, T* smem) {
   const int r = B.r;
-  if (r == 0) return;
-  const T* Xi = Fac<T>::xi(B);
   const int q0 = blockIdx.y * kNC;
   const int nq = min(kNC, ncols - q0);
   T* in = smem;
@@ -2301,6 +2289,17 @@ __global__ __launch_bounds__(kBlock) void k_diag(const SolveBox* boxes, const in
     const int i = t / kNC, q = t % kNC;
     if (q < nq) c[(size_t)R[i] * ncols + q0 + q] = out[t];
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_diag(const SolveBox* boxes, const int* ridx, T* c,
+                                                 int ncols, int kNC) {
+  extern __shared__ double smem_d[];
+  T* smem = reinterpret_cast<T*>(smem_d);
+  const SolveBox& B = boxes[blockIdx.x];
+  if (B.r == 0) return;
+  if (B.Xinvf) diag_box<T, float>(B, B.Xinvf, ridx, c, ncols, kNC, smem);
+  else diag_box<T, double>(B, B.Xinv, ridx, c, ncols, kNC, smem);
 }
 
 // H (2N x 3p) and Psi (2N x 3p, i.e. Psi^T stored by columns), row-major.
@@ -2396,11 +2395,13 @@ __global__ __launch_bounds__(kBlock) void k_border_fix(const SolveBox* boxes, co
                                                        int ncols) {
   const SolveBox& B = boxes[blockIdx.x];
   const int* R = ridx + B.r_off;
-  const T* W = Fac<T>::w(B);
   for (int t = threadIdx.x; t < B.r * ncols; t += kBlock) {
     const int i = t / ncols, q = t % ncols;
     double acc = 0.0;
-    for (int h = 0; h < p3; ++h) acc += (double)W[(size_t)i * p3 + h] * lam[(size_t)h * ncols + q];
+    if (B.Wf)
+      for (int h = 0; h < p3; ++h) acc += (double)B.Wf[(size_t)i * p3 + h] * lam[(size_t)h * ncols + q];
+    else
+      for (int h = 0; h < p3; ++h) acc += B.W[(size_t)i * p3 + h] * lam[(size_t)h * ncols + q];
     c[(size_t)R[i] * ncols + q] -= (T)acc;
   }
 }
@@ -2797,7 +2798,8 @@ int eliminate_blocks_per_cu(int max_n) {
 }
 
 hipError_t launch_eliminate(const LevelBox* boxes, int nbox, int G, int* k_io, const int* kx,
-                            double rcond_min, int* status, int* err, int max_n, hipStream_t s) {
+                            double rcond_min, int* status, double* rc_out, int* err, int max_n,
+                            hipStream_t s) {
   if (nbox == 0) return hipSuccess;
   hipLaunchKernelGGL(k_zero_bars, dim3(blocks_for(nbox, kBlock)), dim3(kBlock), 0, s, boxes, nbox, err, 1);
   const size_t lds = eliminate_lds_bytes(max_n);
@@ -2813,11 +2815,11 @@ hipError_t launch_eliminate(const LevelBox* boxes, int nbox, int G, int* k_io, c
   }
   if (G <= 1) {
     hipLaunchKernelGGL(k_eliminate, dim3(nbox), dim3(kBlock), lds, s, boxes, 1, k_io, kx, rcond_min,
-                       status, err);
+                       status, rc_out, err);
     return hipGetLastError();
   }
   void* args[] = {(void*)&boxes, (void*)&G, (void*)&k_io, (void*)&kx, (void*)&rcond_min,
-                  (void*)&status, (void*)&err};
+                  (void*)&status, (void*)&rc_out, (void*)&err};
   return hipLaunchCooperativeKernel((const void*)k_eliminate, dim3(nbox * G), dim3(kBlock), args,
                                     (unsigned)lds, s);
 }
@@ -2875,8 +2877,6 @@ void launch_sweep(const SolveBox* boxes, int nbox, const int* sidx, const int* r
 }
 template void launch_sweep<double>(const SolveBox*, int, const int*, const int*, double*, int, int,
                                    int, hipStream_t);
-template void launch_sweep<float>(const SolveBox*, int, const int*, const int*, float*, int, int,
-                                  int, hipStream_t);
 
 template <typename T>
 void launch_diag(const SolveBox* boxes, int nbox, const int* ridx, T* c, int ncols, int max_r,
@@ -2888,7 +2888,6 @@ void launch_diag(const SolveBox* boxes, int nbox, const int* ridx, T* c, int nco
   hipLaunchKernelGGL(k_diag<T>, grid, dim3(kBlock), shm, s, boxes, ridx, c, ncols, nc);
 }
 template void launch_diag<double>(const SolveBox*, int, const int*, double*, int, int, hipStream_t);
-template void launch_diag<float>(const SolveBox*, int, const int*, float*, int, int, hipStream_t);
 
 void launch_assemble_H(Geo g, const double* hole_xy, int p, const int* curve_id, double* H,
                        double* Psi, hipStream_t s) {
@@ -2920,8 +2919,6 @@ void launch_border_rhs(const SolveBox* boxes, int nbox, const int* ridx, const T
 }
 template void launch_border_rhs<double>(const SolveBox*, int, const int*, const double*, int,
                                         const double*, int, double*, hipStream_t);
-template void launch_border_rhs<float>(const SolveBox*, int, const int*, const float*, int,
-                                       const float*, int, double*, hipStream_t);
 
 template <typename T>
 void launch_border_fix(const SolveBox* boxes, int nbox, const int* ridx, int p3, const double* lam,
@@ -2931,8 +2928,6 @@ void launch_border_fix(const SolveBox* boxes, int nbox, const int* ridx, int p3,
 }
 template void launch_border_fix<double>(const SolveBox*, int, const int*, int, const double*,
                                         double*, int, hipStream_t);
-template void launch_border_fix<float>(const SolveBox*, int, const int*, int, const double*, float*,
-                                       int, hipStream_t);
 
 void launch_assemble_Z(const double* X0, int n0, const double* Hh, const double* Ph,
                        const int* I0, int p3, const double* G, double* Z, hipStream_t s) {
@@ -2949,8 +2944,6 @@ void launch_root_gather(const T* c, int ncols, const int* I0, int n0, const doub
 }
 template void launch_root_gather<double>(const double*, int, const int*, int, const double*, int,
                                          double*, hipStream_t);
-template void launch_root_gather<float>(const float*, int, const int*, int, const double*, int,
-                                        double*, hipStream_t);
 
 void launch_dense_apply(const double* Zinv, int nz, const double* v, int ncols, double* out,
                         hipStream_t s) {
@@ -2964,7 +2957,6 @@ void launch_root_scatter(const double* sol, int ncols, const int* I0, int n0, T*
                      dim3(kBlock), 0, s, sol, ncols, I0, n0, c);
 }
 template void launch_root_scatter<double>(const double*, int, const int*, int, double*, hipStream_t);
-template void launch_root_scatter<float>(const double*, int, const int*, int, float*, hipStream_t);
 
 void launch_to_float(const double* x, long long n, float* y, hipStream_t s) {
   if (n) hipLaunchKernelGGL((k_convert<float, double>), dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, x, n, y);
