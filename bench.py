@@ -176,30 +176,35 @@ def make_geometry(name):
             "circle40_64holes": W.workload_circle40_64holes}[name]()
 
 
-def cpu_baseline(geom, f, tol, budget_s=30.0):
+def cpu_baseline(geom, f, tol, repeats=3):
     """The CPU oracle (plain level-parallel RS, float64) on the host cores.
 
-    Sample: one full factorization + solve of the same workload when it fits
-    the budget (it does for the 2048- and 12288-node workloads)."""
+    Sample: `repeats` full factorizations + solves of the same workload (about
+    10 s for the 12288-node geometry); value = nrhs / median time."""
     import numpy as np
     from threadpoolctl import threadpool_info
 
     from oracle.rs import RSFactorization, RSParams
 
     threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
-    t0 = time.perf_counter()
-    orc = RSFactorization(geom, RSParams(tol=tol)).factor()
-    t1 = time.perf_counter()
-    orc.solve(f)
-    t2 = time.perf_counter()
     nrhs = f.shape[1]
+    tf, ts = [], []
+    for _ in range(repeats):
+        t0 = time.perf_counter()
+        orc = RSFactorization(geom, RSParams(tol=tol)).factor()
+        t1 = time.perf_counter()
+        orc.solve(f)
+        t2 = time.perf_counter()
+        tf.append(t1 - t0)
+        ts.append(t2 - t1)
+    tot = float(np.median(np.array(tf) + np.array(ts)))
     return {
-        "value": nrhs / (t2 - t0),
+        "value": nrhs / tot,
         "unit": "solves/s",
         "cores": int(threads),
         "kind": "oracle",
-        "sample": "one full factorization + solve of the same workload (%d rhs): factor %.2f s, solve %.3f s"
-                  % (nrhs, t1 - t0, t2 - t1),
+        "sample": "%d full factorizations + solves of the same workload (%d rhs), median: factor %.2f s, "
+                  "solve %.3f s" % (repeats, nrhs, float(np.median(tf)), float(np.median(ts))),
     }
 
 
@@ -251,18 +256,49 @@ def run_form(geom, f, form, steps, warmup, tol_plain, tol_mixed):
     }
 
 
-def roofline_of(run, steps, nrhs, n_nodes, n_holes):
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2001_11619_amd", "csrc", "rs_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_cpqr_circle10_8holes.md")
+
+
+def kernel_source_hash():
+    import hashlib
+
+    with open(KERNEL_SOURCE, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
+
+
+def measured_traffic(workload, form):
+    """HBM bytes per step of the pivoted-QR kernels from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE runs, copy-calibrated), or None when
+    the summary is for another workload or form, or the kernels changed since."""
+    if workload != "circle10_8holes" or form != "mixed" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if ":" in line and line.startswith("- "):
+                k, v = line[2:].split(":", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["fetch_bytes_per_step"]) + float(vals["write_bytes_per_step"])
+    except (KeyError, ValueError):
+        return None
+
+
+def roofline_of(run, steps, nrhs, n_nodes, workload, form):
+    """Roofline of the dominant kernel family (by device time).  Pivoted QR:
+    the ID's algorithmic flops (row reduction 2 m n^2 - 2/3 n^3 plus 4 n^2 per
+    pivoted step, or the pivoted Householder steps on M_B) over the time of
+    all its launches in the timed region; FP64 vector peak."""
     st, ktimes = run["stats"], run["ktimes"]
-    # algorithmic work per step of each modelled kernel family
     pairs = float(n_nodes) ** 2
     models = {
         "cpqr": ("alu", "TFLOP/s", st["flops_id"], FP64_VECTOR_PEAK_TFLOPS),
         "eliminate": ("alu", "TFLOP/s", st["flops_elim"], FP64_VECTOR_PEAK_TFLOPS),
-        # refinement residual: ~25 flops per node pair for the 2x2 block plus 8 per column
-        "apply_operator": ("alu", "TFLOP/s", pairs * (25.0 + 8.0 * nrhs) * run["refine_iters"],
-                           FP64_VECTOR_PEAK_TFLOPS),
     }
-    dev = {k: v for k, v in ktimes.items() if not k.startswith("host:")}
+    dev = {k: v for k, v in ktimes.items() if not k.startswith("host:") and "." not in k}
     fam = max(dev, key=lambda k: dev[k][1]) if dev else None
     if fam not in models:
         return None
@@ -270,9 +306,11 @@ def roofline_of(run, steps, nrhs, n_nodes, n_holes):
     launches, tot_ms = ktimes[fam]
     per_step_s = tot_ms / 1e3 / steps
     achieved = work / per_step_s / 1e12
+    traffic = measured_traffic(workload, form) if fam == "cpqr" else None
     return {"bound": bound, "kernel": fam, "achieved": achieved, "peak": peak, "unit": unit,
-            "frac": achieved / peak, "traffic": None, "launches_per_step": launches // steps,
-            "ms_per_step": tot_ms / steps}
+            "frac": achieved / peak, "traffic": traffic, "traffic_unit": "bytes per step",
+            "launches_per_step": launches // steps, "ms_per_step": tot_ms / steps,
+            "work_per_step": work}
 
 
 def main():
@@ -286,6 +324,9 @@ def main():
     ap.add_argument("--forms", default="mixed,plain")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-size", type=int, default=32)
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="before the timed steps, one device copy of this many MiB (the reference "
+                         "dispatch for calibrating HBM byte counters)")
     ap.add_argument("--evolve-steps", type=int, default=10)
     ap.add_argument("--evolve-all", action="store_true", help="move hole 1, 2, 3, ... in turn")
     args = ap.parse_args()
@@ -311,6 +352,13 @@ def main():
     if args.workload == "evolve":
         print(json.dumps(run_evolve(args)), flush=True)
         return
+    if args.copy_calibration_mb > 0:
+        nel = args.copy_calibration_mb * (1 << 20) // 8
+        src = torch.ones(nel, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     wl = WORKLOADS[args.workload]
     geom = make_geometry(args.workload)
     f = boundary_data(geom, exterior_forces_for_geometry(geom, wl["nrhs"], seed=wl["seed"]))
@@ -342,7 +390,7 @@ def main():
         "max_rel_residual": head["max_rel_residual"],
         "setup_ms": head["setup_ms"],
         "kernel_ms_per_step": {k: v[1] / args.steps for k, v in sorted(head["ktimes"].items())},
-        "roofline": roofline_of(head, args.steps, nrhs, geom.n_nodes, geom.n_holes),
+        "roofline": roofline_of(head, args.steps, nrhs, geom.n_nodes, args.workload, forms[0]),
     }
     for fm in forms[1:]:
         r = runs[fm]

@@ -780,11 +780,18 @@ void finish_level(rs_ctx* c, LevelPrep& P, const int* k0, const int* kk, const i
       throw RsError{RS_ERR_SINGULAR, "X_RR stayed singular after the pivot guard (box " +
                                          std::to_string(b) + ")"};
     c->stats.guard_bumps += f.k - f.rank0;
-    // algorithmic flop counts
+    // algorithmic flop counts.  ID: a row-reduced box (mq < m) costs the
+    // unpivoted QR of M_B, 2 m n^2 - (2/3) n^3, plus the pivoted steps on the
+    // n x n factor, 4 n^2 per step; otherwise the pivoted Householder steps
+    // on M_B, 4 (m - j)(n - j) each.
     const double m = x.m, n = x.n, k = f.k, r = n - k;
     double fid = 0;
-    const int steps = std::min<int>(x.m, std::min<int>(x.n, f.rank0 + 1));
-    for (int j = 0; j < steps; ++j) fid += 4.0 * (m - j) * (n - j);
+    const int steps = std::min<int>(x.m, std::min<int>(x.n, f.rank0 + 1 + kGuardExtra));
+    if (x.mq < x.m) {
+      fid = 2.0 * m * n * n - (2.0 / 3.0) * n * n * n + 4.0 * n * n * steps;
+    } else {
+      for (int j = 0; j < steps; ++j) fid += 4.0 * (m - j) * (n - j);
+    }
     c->stats.flops_id += fid;
     c->stats.flops_elim += k * k * r + 4 * k * k * r + 4 * k * r * r + 2 * r * r * r +
                            4 * k * r * r + 2 * k * k * r;
@@ -885,6 +892,9 @@ void launch_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps) {
       tasks.insert(tasks.end(), r.begin(), r.end());
       round_first.push_back((int)tasks.size());
     }
+    // the per-context records keep the reduced row count (flop accounting)
+    for (size_t ci = 0; ci < cs.size(); ++ci)
+      for (size_t t = 0; t < preps[ci].lb.size(); ++t) preps[ci].lb[t].mq = all[preps[ci].first + t].mq;
   }
   // Pivoted-QR plan.  Boxes whose (reduced) matrix has at most 1536 rows
   // take the register-resident kernel with the fewest workgroups that hold
