@@ -63,8 +63,8 @@ typedef struct {
   double rcond_min;    /* X_RR guard: move a pivot from R to S while rcond_1(X_RR) < rcond_min  */
   int precision;       /* 0 = float64 throughout; 1 = mixed: float32 copies of T, E, F, X_RR^-1
                           (and the border W) serve the solve for every box whose rcond_1(X_RR)
-                          is at least 1e-4 (the others keep float64); vectors, sums, the
-                          pivoted QR, the inverses and the root stay float64                      */
+                          is at least mixed_rcond_min (the others keep float64); vectors, sums,
+                          the pivoted QR, the inverses and the root stay float64                 */
   double refine_tol;   /* refinement target: max-column ||[f;0] - A x||_2 / ||f||_2             */
   int refine_max;      /* 0: direct solve; > 0: at most this many refinement iterations        */
   int has_root;        /* 1: use root[] as the fixed root square; 0: bounding square of nodes */
@@ -72,11 +72,14 @@ typedef struct {
   int solve_graph;     /* 1: refinement iterations replayed as a captured HIP graph, two per
                           launch, with the convergence test on the device (a converged or
                           exhausted iteration leaves x unchanged); 0: launched one by one      */
+  double mixed_rcond_min; /* precision 1: smallest rcond_1(X_RR) of a box whose solve reads
+                          float copies (float rounding of its factors is then amplified by at
+                          most about 1/mixed_rcond_min); > 1 keeps every box in float64     */
 } rs_params;
 
 /* Fill *p with the defaults: lambda -0.5, tol 1e-10, leaf 64, 64 proxy points
  * at 1.5 x side, rcond_min 1e-12, float64, refine_tol 1e-8, refine_max 0
- * (direct solve), no fixed root, solve_graph 1. */
+ * (direct solve), no fixed root, solve_graph 1, mixed_rcond_min 1e-4. */
 void rs_default_params(rs_params* p);
 
 /* Build the adaptive quadtree (Section 2.3) for a boundary discretisation and
@@ -187,6 +190,14 @@ rs_status rs_get_skeleton(const rs_ctx* ctx, int box, int cap, int* out, int* le
  * y = A x, x host (2N+3p) x ncols column-major, y host same shape.  This is
  * the residual kernel used by refinement, exposed for verification. */
 rs_status rs_apply(rs_ctx* ctx, int ncols, const double* x, double* y);
+
+/* Inverse of a dense n x n matrix by the blocked Gauss-Jordan elimination with
+ * partial pivoting that inverts the root system Z (the partitioned root solve
+ * of eq. (partition)), on the context's device and stream.  a: host, row-major,
+ * finite (RS_ERR_ARG otherwise), not modified; ainv: host, row-major, n x n,
+ * written only on success.  RS_ERR_SINGULAR when a pivot column has no nonzero
+ * candidate.  Device scratch is allocated and freed inside the call. */
+rs_status rs_dense_inverse(rs_ctx* ctx, int n, const double* a, double* ainv);
 
 /* Per-kernel device time, measured with HIP events recorded around every
  * launch on the context's stream while timing is enabled (it adds two event

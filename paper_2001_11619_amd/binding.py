@@ -38,6 +38,7 @@ class Params(ctypes.Structure):
         ("has_root", ctypes.c_int),
         ("root", ctypes.c_double * 3),
         ("solve_graph", ctypes.c_int),
+        ("mixed_rcond_min", ctypes.c_double),
     ]
 
 
@@ -89,6 +90,7 @@ def load_library():
     lib.rs_get_boxes.argtypes = [h, ctypes.c_int, ip, ip, ip, ip, dp]
     lib.rs_get_skeleton.argtypes = [h, ctypes.c_int, ctypes.c_int, ip, ip]
     lib.rs_apply.argtypes = [h, ctypes.c_int, dp, dp]
+    lib.rs_dense_inverse.argtypes = [h, ctypes.c_int, dp, dp]
     lib.rs_factor_batch.argtypes = [P(h), ctypes.c_int]
     lib.rs_solve_batch.argtypes = [P(h), ctypes.c_int, ctypes.c_int, P(vp), P(vp)]
     lib.rs_set_kernel_timing.argtypes = [h, ctypes.c_int]
@@ -99,7 +101,8 @@ def load_library():
     lib.rs_last_error.restype = ctypes.c_char_p
     for name in ("rs_build_tree", "rs_factor", "rs_solve", "rs_solve_dev", "rs_update_moved_nodes",
                  "rs_set_stream", "rs_get_stats", "rs_get_boxes", "rs_get_skeleton", "rs_apply",
-                 "rs_set_kernel_timing", "rs_get_kernel_times", "rs_factor_batch", "rs_solve_batch"):
+                 "rs_dense_inverse", "rs_set_kernel_timing", "rs_get_kernel_times",
+                 "rs_factor_batch", "rs_solve_batch"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -111,8 +114,9 @@ def exported_symbols():
     out = []
     for name in ("rs_default_params", "rs_build_tree", "rs_factor", "rs_solve", "rs_solve_dev",
                  "rs_update_moved_nodes", "rs_set_stream", "rs_get_stats", "rs_get_boxes",
-                 "rs_get_skeleton", "rs_apply", "rs_set_kernel_timing", "rs_get_kernel_times",
-                 "rs_factor_batch", "rs_solve_batch", "rs_destroy", "rs_last_error"):
+                 "rs_get_skeleton", "rs_apply", "rs_dense_inverse", "rs_set_kernel_timing",
+                 "rs_get_kernel_times", "rs_factor_batch", "rs_solve_batch", "rs_destroy",
+                 "rs_last_error"):
         if hasattr(lib, name):
             out.append(name)
     return out
@@ -160,7 +164,8 @@ class RSSolver:
 
     def __init__(self, xy, normal, weight, curvature, curve_id, hole_xy=None, *, tol=None,
                  leaf_size=None, n_proxy=None, proxy_ratio=None, lam=None, rcond_min=None,
-                 precision=None, refine_tol=None, refine_max=None, root=None, solve_graph=None):
+                 precision=None, refine_tol=None, refine_max=None, root=None, solve_graph=None,
+                 mixed_rcond_min=None):
         lib = load_library()
         self._lib = lib
         self._h = ctypes.c_void_p()
@@ -168,7 +173,8 @@ class RSSolver:
         for name, val in (("tol", tol), ("leaf_size", leaf_size), ("n_proxy", n_proxy),
                           ("proxy_ratio", proxy_ratio), ("lambda_", lam), ("rcond_min", rcond_min),
                           ("precision", precision), ("refine_tol", refine_tol),
-                          ("refine_max", refine_max), ("solve_graph", solve_graph)):
+                          ("refine_max", refine_max), ("solve_graph", solve_graph),
+                          ("mixed_rcond_min", mixed_rcond_min)):
             if val is not None:
                 setattr(p, name, val)
         if root is not None:
@@ -245,6 +251,18 @@ class RSSolver:
         Y = np.empty_like(Xf, order="F")
         self._check(self._lib.rs_apply(self._h, Xf.shape[1], _dptr(Xf), _dptr(Y)))
         return Y[:, 0] if one else np.ascontiguousarray(Y)
+
+    def dense_inverse(self, a):
+        """Inverse of a dense square matrix by the library's blocked
+        Gauss-Jordan (the root-system inverse), computed on this context's
+        device."""
+        A = np.ascontiguousarray(a, dtype=np.float64)
+        n = A.shape[0]
+        if A.shape != (n, n):
+            raise ValueError("square matrix expected")
+        out = np.empty_like(A)
+        self._check(self._lib.rs_dense_inverse(self._h, n, _dptr(A), _dptr(out)))
+        return out
 
     def update_moved_nodes(self, idx, xy, normal, weight, curvature, hole_xy=None):
         idx = np.ascontiguousarray(idx, dtype=np.int32)

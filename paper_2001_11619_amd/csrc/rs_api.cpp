@@ -173,10 +173,6 @@ struct OldState {
 };
 
 constexpr int kMaxDepth = 48;
-// Mixed precision: a box's float copies of T, E, F, X_RR^{-1} are used by the
-// solve only when rcond_1(X_RR) is at least this (float rounding of the
-// factors is then amplified by at most ~1e4).
-constexpr double kMixedRcondMin = 1e-4;
 constexpr int kGuardExtra = 8;
 
 inline long long key2(long long ix, long long iy) { return (ix << 32) ^ (iy & 0xffffffffLL); }
@@ -1095,7 +1091,7 @@ void build_solve_meta(rs_ctx* c) {
     sb.W = nullptr;
     // mixed precision: the float copies serve the solve only where X_RR is
     // well conditioned; elsewhere the box's float64 factors are read
-    const bool use_f = c->prm.precision == 1 && f.rcond >= kMixedRcondMin && f.Tf;
+    const bool use_f = c->prm.precision == 1 && f.rcond >= c->prm.mixed_rcond_min && f.Tf;
     sb.Tf = use_f ? f.Tf : nullptr;
     sb.Ef = use_f ? f.Ef : nullptr;
     sb.Ff = use_f ? f.Ff : nullptr;
@@ -1650,6 +1646,7 @@ void rs_default_params(rs_params* p) {
   p->refine_max = 0;
   p->has_root = 0;
   p->solve_graph = 1;
+  p->mixed_rcond_min = 1e-4;
 }
 
 rs_status rs_build_tree(const rs_params* prm, int n_nodes, const double* xy, const double* normal,
@@ -1664,6 +1661,8 @@ rs_status rs_build_tree(const rs_params* prm, int n_nodes, const double* xy, con
     if (!(prm->tol > 0.0) || prm->leaf_size < 1 || prm->n_proxy < 4 || !(prm->proxy_ratio > 1.0))
       throw RsError{RS_ERR_ARG, "invalid tolerance, leaf size, proxy count or proxy ratio"};
     if (prm->precision != 0 && prm->precision != 1) throw RsError{RS_ERR_ARG, "precision must be 0 or 1"};
+    if (!(prm->mixed_rcond_min >= 0.0) || !std::isfinite(prm->mixed_rcond_min))
+      throw RsError{RS_ERR_ARG, "mixed_rcond_min must be finite and >= 0"};
     validate_nodes(n_nodes, xy, normal, weight, curvature);
     std::vector<int> count(n_holes + 1, 0);
     for (int i = 0; i < n_nodes; ++i) {
@@ -1933,6 +1932,36 @@ rs_status rs_apply(rs_ctx* c, int ncols, const double* x, double* y) {
     HIP_CHECK(hipMemcpyAsync(y, c->d_f.p, ns * ncols * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIP_CHECK(hipStreamSynchronize(c->stream));
     resolve_timers(c);
+    return RS_OK;
+  } catch (const RsError& e) {
+    return fail(c, e);
+  }
+}
+
+rs_status rs_dense_inverse(rs_ctx* c, int n, const double* a, double* ainv) {
+  if (!c) return RS_ERR_ARG;
+  try {
+    if (n <= 0 || !a || !ainv) throw RsError{RS_ERR_ARG, "bad size or NULL pointer"};
+    const size_t nn = (size_t)n * n;
+    if (!finite_all(a, nn)) throw RsError{RS_ERR_ARG, "non-finite matrix entry"};
+    HIP_CHECK(hipSetDevice(c->device));
+    hipStream_t s = c->stream;
+    DevBuf dA, dAi, dW, dI, dS;
+    dA.ensure(nn * sizeof(double));
+    dAi.ensure(nn * sizeof(double));
+    dW.ensure(((size_t)3 * n * 32 + 32 * 32) * sizeof(double));
+    dI.ensure(((size_t)n + 32) * sizeof(int));
+    dS.ensure(sizeof(int));
+    HIP_CHECK(hipMemcpyAsync(dA.p, a, nn * sizeof(double), hipMemcpyHostToDevice, s));
+    launch_gj_blocked(dA.as<double>(), n, dAi.as<double>(), dW.as<double>(), dI.as<int>(),
+                      dS.as<int>(), s);
+    HIP_CHECK(hipGetLastError());
+    int st = 0;
+    HIP_CHECK(hipMemcpyAsync(&st, dS.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    if (st) throw RsError{RS_ERR_SINGULAR, "matrix is singular"};
+    HIP_CHECK(hipMemcpyAsync(ainv, dAi.p, nn * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
     return RS_OK;
   } catch (const RsError& e) {
     return fail(c, e);

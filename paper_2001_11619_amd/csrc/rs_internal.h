@@ -76,7 +76,8 @@ struct SolveBox {
   const double* F;
   const double* Xinv;
   double* W;             // r x 3p: X_RR^{-1} (U H)_R (bordered root only)
-  const float* Tf;       // float copies (mixed precision)
+  const float* Tf;       // float copies (mixed precision); null where the box's
+                         // solve reads its float64 factors (Ef, Ff, Xinvf, Wf too)
   const float* Ef;
   const float* Ff;
   const float* Xinvf;

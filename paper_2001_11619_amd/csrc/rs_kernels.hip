@@ -2018,6 +2018,9 @@ __global__ __launch_bounds__(kBlock) void k_gj_inverse(double* A, int n, int lda
 //   rows:   R = D^{-1} A[K, :];
 //   update: A[K,K] = D^{-1}, A[K,~K] = R, A[~K,K] = -A[~K,K] D^{-1},
 //           A[~K,~K] -= A[~K,K] R.
+// A panel without a nonzero pivot sets *status; every kernel of the sequence
+// returns at once when *status is set, so no pivot index of a failed panel is
+// ever used (the panel also leaves its unused entries as the identity).
 constexpr int kGJB = 32;
 
 __global__ __launch_bounds__(kBlock) void k_gjb_panel(const double* A, int n, int k0, int bb,
@@ -2029,6 +2032,7 @@ __global__ __launch_bounds__(kBlock) void k_gjb_panel(const double* A, int n, in
   __shared__ double lu[kGJB][kGJB + 1];
   __shared__ double inv[kGJB][kGJB + 1];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  if (*(volatile const int*)status) return;
   const int h = n - k0;
   for (int t = tid; t < h * bb; t += kBlock) {
     const int i = t / bb, c = t % bb;
@@ -2056,7 +2060,11 @@ __global__ __launch_bounds__(kBlock) void k_gjb_panel(const double* A, int n, in
     for (int w = 1; w < NW; ++w)
       if (red[w] > best || (red[w] == best && ired[w] < bi)) { best = red[w]; bi = ired[w]; }
     __syncthreads();
-    if (!(best > 0.0)) { singular = true; break; }
+    if (!(best > 0.0)) {
+      for (int jj = j + tid; jj < bb; jj += kBlock) piv[jj] = jj;
+      singular = true;
+      break;
+    }
     if (tid == 0) piv[j] = bi;
     if (bi != j)
       for (int c = tid; c < bb; c += kBlock) {
@@ -2105,7 +2113,8 @@ __global__ __launch_bounds__(kBlock) void k_gjb_panel(const double* A, int n, in
 
 // Row interchanges of this block over all columns; copy of the column block.
 __global__ void k_gjb_swap(double* A, int n, int k0, int bb, const int* piv, int* rowperm,
-                           double* Cpanel) {
+                           const int* status) {
+  if (*(volatile const int*)status) return;
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c < n) {
     for (int j = 0; j < bb; ++j) {
@@ -2127,7 +2136,9 @@ __global__ void k_gjb_swap(double* A, int n, int k0, int bb, const int* piv, int
   }
 }
 
-__global__ void k_gjb_copycol(const double* A, int n, int k0, int bb, double* Cpanel) {
+__global__ void k_gjb_copycol(const double* A, int n, int k0, int bb, double* Cpanel,
+                              const int* status) {
+  if (*(volatile const int*)status) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n * bb) return;
   const int i = t / bb, c = t % bb;
@@ -2135,7 +2146,9 @@ __global__ void k_gjb_copycol(const double* A, int n, int k0, int bb, double* Cp
 }
 
 // R = D^{-1} A[K, :]
-__global__ void k_gjb_rows(const double* A, int n, int k0, int bb, const double* Dinv, double* R) {
+__global__ void k_gjb_rows(const double* A, int n, int k0, int bb, const double* Dinv, double* R,
+                           const int* status) {
+  if (*(volatile const int*)status) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= bb * n) return;
   const int i = t / n, c = t % n;
@@ -2145,7 +2158,8 @@ __global__ void k_gjb_rows(const double* A, int n, int k0, int bb, const double*
 }
 
 __global__ void k_gjb_update(double* A, int n, int k0, int bb, const double* Dinv,
-                             const double* R, const double* Cpanel) {
+                             const double* R, const double* Cpanel, const int* status) {
+  if (*(volatile const int*)status) return;
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (long long)n * n) return;
   const int i = (int)(t / n), c = (int)(t % n);
@@ -2534,9 +2548,11 @@ __global__ void k_factor_to_float(const LevelBox* boxes, const int* k_final) {
   for (int t = threadIdx.x; t < rr; t += blockDim.x) B.Xinvf[t] = (float)B.Xinv[t];
 }
 
-// float copy of W of every box (after the border stage)
+// float copy of W (after the border stage) for the boxes whose solve reads
+// float factors; boxes that keep float64 factors have no float W (Wf null)
 __global__ void k_w_to_float(const SolveBox* boxes, int p3) {
   const SolveBox& B = boxes[blockIdx.x];
+  if (!B.Wf) return;
   const int len = B.r * p3;
   for (int t = threadIdx.x; t < len; t += blockDim.x) B.Wf[t] = (float)B.W[t];
 }
@@ -2854,13 +2870,13 @@ void launch_gj_blocked(double* A, int n, double* Ainv, double* work, int* iwork,
     const int bb = std::min(kGJB, n - k0);
     hipLaunchKernelGGL(k_gjb_panel, dim3(1), dim3(kBlock), 0, s, A, n, k0, bb, W, piv, Dinv, status);
     hipLaunchKernelGGL(k_gjb_swap, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, A, n, k0, bb,
-                       piv, rowperm, Cp);
+                       piv, rowperm, status);
     hipLaunchKernelGGL(k_gjb_copycol, dim3(blocks_for((long long)n * bb, kBlock)), dim3(kBlock), 0,
-                       s, A, n, k0, bb, Cp);
+                       s, A, n, k0, bb, Cp, status);
     hipLaunchKernelGGL(k_gjb_rows, dim3(blocks_for((long long)bb * n, kBlock)), dim3(kBlock), 0, s,
-                       A, n, k0, bb, Dinv, R);
+                       A, n, k0, bb, Dinv, R, status);
     hipLaunchKernelGGL(k_gjb_update, dim3(blocks_for(nn, kBlock)), dim3(kBlock), 0, s, A, n, k0, bb,
-                       Dinv, R, Cp);
+                       Dinv, R, Cp, status);
   }
   hipLaunchKernelGGL(k_gjb_unpermute, dim3(blocks_for(nn, kBlock)), dim3(kBlock), 0, s, A, n,
                      rowperm, Ainv);

@@ -186,3 +186,45 @@ def test_wider_proxy_circle(ratio):
     assert np.all(_rel(x, xo) < 1e-10)
     same, total = _rank_agreement(orc, s)
     assert same >= total - 1
+
+
+@pytest.mark.parametrize("n", [1, 31, 33, 694, 1000])
+def test_dense_inverse_matches_numpy(n):
+    """The root system's blocked Gauss-Jordan inverse (one and several pivot
+    blocks of 32, ragged last block): equal to LAPACK's inverse to rounding on a
+    well-conditioned matrix."""
+    g = workload_small(seed=11, n_outer=64, n_holes=1, nodes_per_hole=32, radius=3.0)
+    s = _solver(g, leaf_size=16)
+    rng = np.random.default_rng(n)
+    a = rng.standard_normal((n, n)) + 2.0 * np.sqrt(n) * np.eye(n)
+    ai = s.dense_inverse(a)
+    ref = np.linalg.inv(a)
+    assert np.linalg.norm(ai - ref) <= 1e-12 * np.linalg.norm(ref)
+    assert np.linalg.norm(a @ ai - np.eye(n)) <= 1e-12 * np.sqrt(n)
+
+
+def test_dense_inverse_singular_panel_stops_cleanly():
+    """A pivot column with no nonzero candidate in a middle block is reported
+    as RS_ERR_SINGULAR, and the context keeps working.  The block before it
+    takes its pivots from the last rows, so any later use of that block's
+    pivot indices would address rows past the end of the matrix."""
+    from paper_2001_11619_amd import RSError
+
+    g = workload_small(seed=11, n_outer=64, n_holes=1, nodes_per_hole=32, radius=3.0)
+    s = _solver(g, leaf_size=16)
+    n = 694
+    rng = np.random.default_rng(3)
+    a = np.eye(n) + 1e-3 * rng.standard_normal((n, n))
+    for j in range(32):
+        a[n - 32 + j, 64 + j] = 10.0
+    a[:, 100] = 0.0
+    with pytest.raises(RSError) as e:
+        s.dense_inverse(a)
+    assert e.value.name == "RS_ERR_SINGULAR"
+    b = np.eye(n) + 1e-3 * rng.standard_normal((n, n))
+    assert np.allclose(s.dense_inverse(b) @ b, np.eye(n), atol=1e-12)
+    c = b.copy()
+    c[3, 5] = np.nan
+    with pytest.raises(RSError) as e:
+        s.dense_inverse(c)
+    assert e.value.name == "RS_ERR_ARG"

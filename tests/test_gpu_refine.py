@@ -117,3 +117,23 @@ def test_solve_batch_matches_single():
     for gg, s, ff, xd in zip(geoms, batch, fs, x_dev):
         alone = _solver(gg, **kw).factor()
         assert np.array_equal(xd.cpu().numpy().T, alone.solve(ff))
+
+
+@pytest.mark.parametrize("thr", [2.0, 1e-1, 1e-2, 1e-3, 0.0])
+def test_mixed_boxes_float_and_double(thr):
+    """Mixed precision where the rcond threshold splits the boxes between float
+    copies and float64 factors (thr > 1 keeps every box in float64, 0 puts every
+    box in float): the border stage and the refined solve handle both kinds in
+    one factorization.  With every box in float64 the solve is the float64 one
+    bitwise."""
+    g = workload_small(seed=11, n_outer=256, n_holes=2, nodes_per_hole=128, radius=3.0)
+    f = boundary_data(g, exterior_forces_for_geometry(g, 3, seed=5))
+    xd = stokes.dense_solve(g, f)
+    s = _solver(g, leaf_size=32, tol=1e-7, precision=1, mixed_rcond_min=thr, refine_max=30,
+                refine_tol=1e-12).factor()
+    x, res = s.solve(f, residual=True)
+    assert np.all(res <= 1e-12)
+    assert np.all(_rel(x, xd) < 1e-10)
+    if thr > 1.0:
+        p = _solver(g, leaf_size=32, tol=1e-7, precision=0, refine_max=30, refine_tol=1e-12).factor()
+        assert np.array_equal(p.solve(f), x)

@@ -34,14 +34,15 @@ def test_default_params():
     assert p.lambda_ == -0.5 and p.tol == 1e-10 and p.leaf_size == 64
     assert p.n_proxy == 64 and p.proxy_ratio == 1.5 and p.rcond_min == 1e-12
     assert p.precision == 0 and p.refine_tol == 1e-8 and p.refine_max == 0
-    assert p.has_root == 0 and p.solve_graph == 1
+    assert p.has_root == 0 and p.solve_graph == 1 and p.mixed_rcond_min == 1e-4
 
 
 def _geom():
     return workload_small(seed=11, n_outer=64, n_holes=1, nodes_per_hole=32, radius=3.0)
 
 
-@pytest.mark.parametrize("bad", ["nan_xy", "normal_len", "weight", "curve_id", "tol", "empty_hole"])
+@pytest.mark.parametrize("bad", ["nan_xy", "normal_len", "weight", "curve_id", "tol", "empty_hole",
+                                 "mixed_rcond"])
 def test_invalid_input_rejected(bad):
     g = _geom()
     xy, nrm, w, kap, cid = g.xy.copy(), g.normal.copy(), g.weight.copy(), g.curvature.copy(), g.curve_id.copy()
@@ -56,6 +57,8 @@ def test_invalid_input_rejected(bad):
         cid[0] = 5
     elif bad == "tol":
         kw["tol"] = -1.0
+    elif bad == "mixed_rcond":
+        kw["mixed_rcond_min"] = float("nan")
     elif bad == "empty_hole":
         cid[cid == 1] = 0
         cid[0] = 2           # hole 1 has no nodes, hole 2 has one
