@@ -75,11 +75,15 @@ typedef struct {
   double mixed_rcond_min; /* precision 1: smallest rcond_1(X_RR) of a box whose solve reads
                           float copies (float rounding of its factors is then amplified by at
                           most about 1/mixed_rcond_min); > 1 keeps every box in float64     */
+  int apply_shape;     /* kernel shape of the exact operator apply (refinement residual):
+                          -1 = chosen per (N, ncols) by timing every candidate shape once per
+                          process (the autotuner); k >= 0 = candidate k (invalid ones fall
+                          back to a fixed default).  Every shape gives bitwise the same result */
 } rs_params;
 
 /* Fill *p with the defaults: lambda -0.5, tol 1e-10, leaf 64, 64 proxy points
  * at 1.5 x side, rcond_min 1e-12, float64, refine_tol 1e-8, refine_max 0
- * (direct solve), no fixed root, solve_graph 1, mixed_rcond_min 1e-4. */
+ * (direct solve), no fixed root, solve_graph 1, mixed_rcond_min 1e-4, apply_shape -1. */
 void rs_default_params(rs_params* p);
 
 /* Build the adaptive quadtree (Section 2.3) for a boundary discretisation and
@@ -170,6 +174,8 @@ typedef struct {
   int refine_iters;           /* refinement iterations of the last mixed solve     */
   double ms_update;           /* wall time of the last rs_update_moved_nodes       */
   int boxes_recomputed;       /* boxes recompressed by the last update             */
+  int apply_config;           /* operator-apply kernel shape in use (autotuner)    */
+  double apply_ms;            /* its measured time per apply (0 if not tuned)      */
 } rs_stats;
 rs_status rs_get_stats(const rs_ctx* ctx, rs_stats* out);
 

@@ -39,6 +39,7 @@ class Params(ctypes.Structure):
         ("root", ctypes.c_double * 3),
         ("solve_graph", ctypes.c_int),
         ("mixed_rcond_min", ctypes.c_double),
+        ("apply_shape", ctypes.c_int),
     ]
 
 
@@ -51,7 +52,8 @@ class Stats(ctypes.Structure):
         ("flops_id", ctypes.c_double), ("flops_elim", ctypes.c_double),
         ("ms_factor", ctypes.c_double), ("ms_solve", ctypes.c_double),
         ("refine_iters", ctypes.c_int), ("ms_update", ctypes.c_double),
-        ("boxes_recomputed", ctypes.c_int),
+        ("boxes_recomputed", ctypes.c_int), ("apply_config", ctypes.c_int),
+        ("apply_ms", ctypes.c_double),
     ]
 
 
@@ -165,7 +167,7 @@ class RSSolver:
     def __init__(self, xy, normal, weight, curvature, curve_id, hole_xy=None, *, tol=None,
                  leaf_size=None, n_proxy=None, proxy_ratio=None, lam=None, rcond_min=None,
                  precision=None, refine_tol=None, refine_max=None, root=None, solve_graph=None,
-                 mixed_rcond_min=None):
+                 mixed_rcond_min=None, apply_shape=None):
         lib = load_library()
         self._lib = lib
         self._h = ctypes.c_void_p()
@@ -174,7 +176,7 @@ class RSSolver:
                           ("proxy_ratio", proxy_ratio), ("lambda_", lam), ("rcond_min", rcond_min),
                           ("precision", precision), ("refine_tol", refine_tol),
                           ("refine_max", refine_max), ("solve_graph", solve_graph),
-                          ("mixed_rcond_min", mixed_rcond_min)):
+                          ("mixed_rcond_min", mixed_rcond_min), ("apply_shape", apply_shape)):
             if val is not None:
                 setattr(p, name, val)
         if root is not None:

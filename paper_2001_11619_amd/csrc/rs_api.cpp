@@ -3,9 +3,9 @@
 // The host owns the quadtree (Section 2.3), the per-level bookkeeping of
 // active unknowns and near fields (Section 2.7: every box of a level reads
 // the level-start active set), and the launch sequence; every arithmetic step
-// of the factorization and solve runs in the gfx950 kernels of
-// rs_kernels.hip.  One host synchronisation per level reads back the ranks
-// and pivot orders, which size the next level.
+// of the factorization and solve runs in the gfx950 kernels (rs_qr.hip,
+// rs_factor.hip, rs_solve.hip, rs_apply.hip).  One host synchronisation per
+// level reads back the ranks and pivot orders, which size the next level.
 #include "rs.h"
 #include "rs_internal.h"
 
@@ -15,6 +15,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <unordered_map>
@@ -1404,7 +1405,8 @@ void apply_inverse(rs_ctx* c, const double* rhs, int ncols, double* out) {
   solve_rows<double>(c, out, ncols, rbot);
 }
 
-void apply_device_rows(rs_ctx* c, const double* xrows, int ncols, double* yrows);
+void apply_device_rows(rs_ctx* c, const double* xrows, int ncols, double* yrows, const int* skip);
+int apply_config_for(rs_ctx* c, int ncols, const double* xrows, double* yrows);
 
 // Every buffer one refinement iteration touches, allocated up front (a
 // captured graph must not allocate).
@@ -1437,7 +1439,7 @@ void refine_iteration(rs_ctx* c, int nrhs) {
   apply_inverse(c, c->d_r.as<double>(), nrhs, c->d_dx.as<double>());
   launch_accumulate_unless(c->d_dx.as<double>(), (long long)rows, c->d_xs.as<double>(), c->d_flag.as<int>(),
                            c->prm.refine_max, c->stream);
-  apply_device_rows(c, c->d_xs.as<double>(), nrhs, c->d_ys.as<double>());
+  apply_device_rows(c, c->d_xs.as<double>(), nrhs, c->d_ys.as<double>(), c->d_flag.as<int>());
   launch_residual(c->d_frows.as<double>(), n2, c->d_ys.as<double>(), ns, nrhs, c->d_r.as<double>(), colsq,
                   colsq + nrhs, c->stream);
   launch_refine_flag(colsq, colsq + nrhs, nrhs, c->prm.refine_tol, c->prm.refine_max, c->d_flag.as<int>(),
@@ -1556,6 +1558,7 @@ bool solve_device(rs_ctx* c, int nrhs, const double* f_dev, double* x_dev) {
     return true;
   }
   refine_begin(c, nrhs);
+  apply_config_for(c, nrhs, c->d_xs.as<double>(), c->d_ys.as<double>());   // before any capture
   bool conv;
   if (c->prm.solve_graph) {
     refine_graph_launch(c, nrhs);
@@ -1568,14 +1571,89 @@ bool solve_device(rs_ctx* c, int nrhs, const double* f_dev, double* x_dev) {
   return conv;
 }
 
-void apply_device_rows(rs_ctx* c, const double* xrows, int ncols, double* yrows) {
+// Autotuner of the operator apply: the kernel shape (columns per pass,
+// targets per thread) for a problem shape (N, ncols) is chosen once per
+// process by timing every valid shape on the context's stream (all shapes
+// give bitwise the same result, so the choice only affects speed).
+struct ApplyTuneCache {
+  std::mutex mu;
+  std::map<std::pair<int, int>, std::pair<int, double>> best;   // -> (config, ms per apply)
+};
+ApplyTuneCache& apply_tune_cache() {
+  static ApplyTuneCache cache;
+  return cache;
+}
+
+int apply_config_for(rs_ctx* c, int ncols, const double* xrows, double* yrows) {
+  if (c->prm.apply_shape >= 0) {
+    const int cfg = apply_config_valid(c->prm.apply_shape, ncols) ? c->prm.apply_shape
+                                                                   : apply_default_config(ncols);
+    c->stats.apply_config = cfg;
+    return cfg;
+  }
+  const std::pair<int, int> key{c->N, ncols};
+  ApplyTuneCache& tc = apply_tune_cache();
+  {
+    std::lock_guard<std::mutex> lk(tc.mu);
+    auto it = tc.best.find(key);
+    if (it != tc.best.end()) {
+      c->stats.apply_config = it->second.first;
+      c->stats.apply_ms = it->second.second;
+      return it->second.first;
+    }
+  }
+  if (c->capturing) return apply_default_config(ncols);
+  Geo g;
+  geo_of(c, g);
+  c->d_apply.ensure(apply_scratch_doubles(c->N, ncols) * sizeof(double));
+  hipEvent_t e0, e1;
+  HIP_CHECK(hipEventCreate(&e0));
+  HIP_CHECK(hipEventCreate(&e1));
+  int best = apply_default_config(ncols);
+  float best_ms = -1.0f;
+  constexpr int kReps = 2;
+  for (int cfg = 0; cfg < apply_config_count(); ++cfg) {
+    if (!apply_config_valid(cfg, ncols)) continue;
+    auto run = [&]() {
+      launch_apply_operator(g, c->d_curve.as<int>(), c->d_hole.as<double>(), c->p, c->prm.lambda, xrows,
+                            ncols, yrows, c->d_apply.as<double>(), nullptr, 0, cfg, c->stream);
+    };
+    run();   // warm-up
+    HIP_CHECK(hipEventRecord(e0, c->stream));
+    for (int r = 0; r < kReps; ++r) run();
+    HIP_CHECK(hipEventRecord(e1, c->stream));
+    HIP_CHECK(hipEventSynchronize(e1));
+    float ms = 0.0f;
+    HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+    ms /= kReps;
+    if (best_ms < 0.0f || ms < best_ms) {
+      best_ms = ms;
+      best = cfg;
+    }
+  }
+  HIP_CHECK(hipEventDestroy(e0));
+  HIP_CHECK(hipEventDestroy(e1));
+  HIP_CHECK(hipGetLastError());
+  {
+    std::lock_guard<std::mutex> lk(tc.mu);
+    tc.best[key] = {best, (double)best_ms};
+  }
+  c->stats.apply_config = best;
+  c->stats.apply_ms = best_ms;
+  return best;
+}
+
+// y = A x on the device (rows layout).  skip (nullable): refinement flags; the
+// apply is skipped on the device once they say converged or exhausted.
+void apply_device_rows(rs_ctx* c, const double* xrows, int ncols, double* yrows, const int* skip) {
+  const int cfg = apply_config_for(c, ncols, xrows, yrows);
   Geo g;
   geo_of(c, g);
   {
     KTimer kt_(c, "apply_operator");
     c->d_apply.ensure(apply_scratch_doubles(c->N, ncols) * sizeof(double));
     launch_apply_operator(g, c->d_curve.as<int>(), c->d_hole.as<double>(), c->p, c->prm.lambda, xrows,
-                          ncols, yrows, c->d_apply.as<double>(), c->stream);
+                          ncols, yrows, c->d_apply.as<double>(), skip, c->prm.refine_max, cfg, c->stream);
   }
   HIP_CHECK(hipGetLastError());
 }
@@ -1647,6 +1725,7 @@ void rs_default_params(rs_params* p) {
   p->has_root = 0;
   p->solve_graph = 1;
   p->mixed_rcond_min = 1e-4;
+  p->apply_shape = -1;
 }
 
 rs_status rs_build_tree(const rs_params* prm, int n_nodes, const double* xy, const double* normal,
@@ -1815,6 +1894,7 @@ rs_status rs_solve_batch(rs_ctx** ctxs, int n, int nrhs, const double* const* f_
       c->last_res.clear();
       c->stats.refine_iters = 0;
       refine_begin(c, nrhs);
+      apply_config_for(c, nrhs, c->d_xs.as<double>(), c->d_ys.as<double>());
       refine_graph_launch(c, nrhs);
       live.push_back(i);
     } catch (const RsError& e) {
@@ -1896,7 +1976,7 @@ rs_status rs_solve(rs_ctx* c, int nrhs, const double* f, double* x, double* rel_
         c->d_ys.ensure(ns * nrhs * sizeof(double));
         c->d_r.ensure(ns * nrhs * sizeof(double));
         c->d_norms.ensure(2 * (size_t)nrhs * sizeof(double));
-        apply_device_rows(c, c->d_xs.as<double>(), nrhs, c->d_ys.as<double>());
+        apply_device_rows(c, c->d_xs.as<double>(), nrhs, c->d_ys.as<double>(), nullptr);
         double* colsq = c->d_norms.as<double>();
         launch_residual(c->d_frows.as<double>(), (int)n2, c->d_ys.as<double>(), (int)ns, nrhs,
                         c->d_r.as<double>(), colsq, colsq + nrhs, s);
@@ -1927,7 +2007,7 @@ rs_status rs_apply(rs_ctx* c, int ncols, const double* x, double* y) {
     c->d_res.ensure(ns * ncols * sizeof(double));
     HIP_CHECK(hipMemcpyAsync(c->d_f.p, x, ns * ncols * sizeof(double), hipMemcpyHostToDevice, c->stream));
     launch_to_rows(c->d_f.as<double>(), (int)ns, (int)ns, ncols, c->d_c.as<double>(), c->stream);
-    apply_device_rows(c, c->d_c.as<double>(), ncols, c->d_res.as<double>());
+    apply_device_rows(c, c->d_c.as<double>(), ncols, c->d_res.as<double>(), nullptr);
     launch_from_rows(c->d_res.as<double>(), (int)ns, ncols, c->d_f.as<double>(), (int)ns, c->stream);
     HIP_CHECK(hipMemcpyAsync(y, c->d_f.p, ns * ncols * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIP_CHECK(hipStreamSynchronize(c->stream));

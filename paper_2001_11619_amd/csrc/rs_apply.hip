@@ -1,0 +1,271 @@
+// gfx950 kernels applying the exact float64 operator of the augmented system
+// (eq. backwardeq), the residual of iterative refinement.
+#include "rs_device.h"
+
+#include <cstdio>
+
+namespace rs {
+namespace {
+
+// ---- exact float64 operator (refinement residual) ---------------------------
+// y = A x with A = [[lam I + D + N, H], [Psi^T, -I]]; x, y row layout
+// [(2N + 3p)][ncols].  The O(N^2) part is the double layer D between distinct
+// nodes; the diagonal (curvature limit and lam), the rank-one completion N
+// (n_i sum_j w_j n_j . x_j) and the border columns are O(N) and are added by
+// k_apply_sum.  Blocks tile (targets) x (source chunks) x (column chunks);
+// each block writes the partial sums of its source chunk and k_apply_sum adds
+// the chunks in a fixed order (deterministic).
+//
+// A thread holds T targets and NC right-hand-side columns in registers; every
+// source staged in LDS (position, w n, its NC column values) serves the T
+// targets, so LDS traffic per pair falls as 1 / T.  (NC, T) is chosen per
+// problem shape by the host's autotuner.
+constexpr int kApplyThreads = 256;   // threads per block = sources per LDS tile
+
+// 1 / d for d > 0 from the hardware reciprocal and one Newton step (relative
+// error about one ulp); 0 for d == 0 (coincident nodes).
+__device__ __forceinline__ double inv_pos(double d) {
+  const double y0 = __builtin_amdgcn_rcp(d);
+  const double e = fma(-d, y0, 1.0);
+  const double y1 = fma(y0, e, y0);
+  return d > 0.0 ? y1 : 0.0;
+}
+
+// True when refinement has converged or used up its iterations (the
+// iteration's operator apply is then not needed).
+__device__ __forceinline__ bool apply_skipped(const int* skip, int max_iters) {
+  return skip && (skip[0] != 0 || skip[1] >= max_iters);
+}
+
+template <int NC, int T>
+__global__ __launch_bounds__(kApplyThreads) void k_apply_pairs(Geo g, const double* __restrict__ x,
+                                                               int ncols, int chunk,
+                                                               double* __restrict__ part,
+                                                               const int* skip, int max_iters) {
+  if (apply_skipped(skip, max_iters)) return;
+  __shared__ double2 sxy[kApplyThreads];
+  __shared__ double2 swn[kApplyThreads];
+  __shared__ double sm[kApplyThreads * 2 * NC];
+  const int N = g.N, tid = threadIdx.x;
+  const int ib = blockIdx.x * (kApplyThreads * T) + tid;
+  const int js0 = blockIdx.y * chunk, js1 = min(N, js0 + chunk);
+  const int q0 = blockIdx.z * NC;
+  const int nq = min(NC, ncols - q0);
+  double xi[T], yi[T];
+  double ax[T][NC], ay[T][NC];
+#pragma unroll
+  for (int u = 0; u < T; ++u) {
+    const int i = ib + u * kApplyThreads;
+    xi[u] = i < N ? g.x[i] : 0.0;
+    yi[u] = i < N ? g.y[i] : 0.0;
+#pragma unroll
+    for (int q = 0; q < NC; ++q) { ax[u][q] = 0.0; ay[u][q] = 0.0; }
+  }
+  for (int j0 = js0; j0 < js1; j0 += kApplyThreads) {
+    const int j = j0 + tid;
+    __syncthreads();
+    if (j < js1) {
+      const double w = g.w[j];
+      sxy[tid] = make_double2(g.x[j], g.y[j]);
+      swn[tid] = make_double2(w * g.nx[j], w * g.ny[j]);
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        sm[tid * 2 * NC + 2 * q] = q < nq ? x[(size_t)(2 * j) * ncols + q0 + q] : 0.0;
+        sm[tid * 2 * NC + 2 * q + 1] = q < nq ? x[(size_t)(2 * j + 1) * ncols + q0 + q] : 0.0;
+      }
+    }
+    __syncthreads();
+    const int cnt = min(kApplyThreads, js1 - j0);
+    for (int jj = 0; jj < cnt; ++jj) {
+      const double2 p = sxy[jj];
+      const double2 wn = swn[jj];
+      double mv[2 * NC];
+#pragma unroll
+      for (int t = 0; t < 2 * NC; ++t) mv[t] = sm[jj * 2 * NC + t];
+#pragma unroll
+      for (int u = 0; u < T; ++u) {
+        const double rx = xi[u] - p.x, ry = yi[u] - p.y;
+        const double r2 = fma(rx, rx, ry * ry);
+        const double rn = fma(rx, wn.x, ry * wn.y);
+        const double c = kInvPi * rn * inv_pos(r2 * r2);
+        const double crx = c * rx;
+        const double bxx = crx * rx, bxy = crx * ry, byy = c * ry * ry;
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+          ax[u][q] = fma(bxx, mv[2 * q], fma(bxy, mv[2 * q + 1], ax[u][q]));
+          ay[u][q] = fma(bxy, mv[2 * q], fma(byy, mv[2 * q + 1], ay[u][q]));
+        }
+      }
+    }
+  }
+  double* out = part + (size_t)blockIdx.y * 2 * N * ncols;
+#pragma unroll
+  for (int u = 0; u < T; ++u) {
+    const int i = ib + u * kApplyThreads;
+    if (i >= N) continue;
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      if (q < nq) {
+        out[(size_t)(2 * i) * ncols + q0 + q] = ax[u][q];
+        out[(size_t)(2 * i + 1) * ncols + q0 + q] = ay[u][q];
+      }
+    }
+  }
+}
+
+// nsum[q] = sum_j w_j (n_j . x_j), column q (the rank-one term's scalar);
+// one block per column, fixed-order sums.
+__global__ __launch_bounds__(kBlock) void k_apply_nsum(Geo g, const double* x, int ncols,
+                                                       double* nsum, const int* skip, int max_iters) {
+  if (apply_skipped(skip, max_iters)) return;
+  constexpr int NW = kBlock / 64;
+  __shared__ double red[NW];
+  const int q = blockIdx.x;
+  double s = 0.0;
+  for (int j = threadIdx.x; j < g.N; j += kBlock)
+    s += g.w[j] * (g.nx[j] * x[(size_t)(2 * j) * ncols + q] + g.ny[j] * x[(size_t)(2 * j + 1) * ncols + q]);
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) nsum[q] = s;
+}
+
+// y[2N rows] = sum over source chunks (fixed order) + the diagonal (lam and
+// the curvature limit of D) + the rank-one term + H lambda
+__global__ void k_apply_sum(Geo g, double lam, const double* hole_xy, int p, const double* x,
+                            int ncols, const double* part, int nchunk, const double* nsum,
+                            double* y, const int* skip, int max_iters) {
+  if (apply_skipped(skip, max_iters)) return;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int N = g.N;
+  if (t >= (long long)N * ncols) return;
+  const int i = (int)(t / ncols), q = (int)(t % ncols);
+  const size_t stride = (size_t)2 * N * ncols;
+  double ax = 0.0, ay = 0.0;
+  for (int c = 0; c < nchunk; ++c) {
+    ax += part[c * stride + (size_t)(2 * i) * ncols + q];
+    ay += part[c * stride + (size_t)(2 * i + 1) * ncols + q];
+  }
+  const double mx = x[(size_t)(2 * i) * ncols + q], my = x[(size_t)(2 * i + 1) * ncols + q];
+  const double nxi = g.nx[i], nyi = g.ny[i];
+  {
+    const double tx = -nyi, ty = nxi;
+    const double cs = -(g.w[i] * g.kap[i]) / (2.0 * kPi);
+    ax += (cs * tx * tx + lam) * mx + cs * tx * ty * my;
+    ay += cs * tx * ty * mx + (cs * ty * ty + lam) * my;
+  }
+  ax += nxi * nsum[q];
+  ay += nyi * nsum[q];
+  const double xi = g.x[i], yi = g.y[i];
+  const size_t base = (size_t)2 * N;
+  for (int h = 0; h < p; ++h) {
+    const double rx = xi - hole_xy[2 * h], ry = yi - hole_xy[2 * h + 1];
+    const double r2 = rx * rx + ry * ry;
+    const double lg = -0.5 * log(r2);
+    const double sxx = kInv4Pi * (lg + rx * rx / r2), sxy = kInv4Pi * (rx * ry / r2);
+    const double syy = kInv4Pi * (lg + ry * ry / r2);
+    const double rotx = kInv4Pi * (-ry) / r2, roty = kInv4Pi * rx / r2;
+    const double a1 = x[(base + 3 * h) * ncols + q];
+    const double a2 = x[(base + 3 * h + 1) * ncols + q];
+    const double b = x[(base + 3 * h + 2) * ncols + q];
+    ax += sxx * a1 + sxy * a2 + rotx * b;
+    ay += sxy * a1 + syy * a2 + roty * b;
+  }
+  y[(size_t)(2 * i) * ncols + q] = ax;
+  y[(size_t)(2 * i + 1) * ncols + q] = ay;
+}
+
+// Rows of Psi^T x - lambda: one block per (hole, mode), fixed-order sums.
+__global__ __launch_bounds__(kBlock) void k_apply_psi(Geo g, const int* curve_id, int p,
+                                                      const double* x, int ncols, double* y,
+                                                      const int* skip, int max_iters) {
+  if (apply_skipped(skip, max_iters)) return;
+  constexpr int NW = kBlock / 64;
+  __shared__ double red[NW];
+  const int h = blockIdx.x / 3, mode = blockIdx.x % 3;
+  const size_t base = (size_t)2 * g.N;
+  for (int q = 0; q < ncols; ++q) {
+    double s = 0.0;
+    for (int j = threadIdx.x; j < g.N; j += kBlock) {
+      if (curve_id[j] != h + 1) continue;
+      const double w = g.w[j];
+      const double mx = x[(size_t)(2 * j) * ncols + q], my = x[(size_t)(2 * j + 1) * ncols + q];
+      if (mode == 0) s += w * mx;
+      else if (mode == 1) s += w * my;
+      else s += w * (-g.y[j] * mx + g.x[j] * my);
+    }
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) {
+      const size_t row = base + 3 * h + mode;
+      y[row * ncols + q] = s - x[row * ncols + q];
+    }
+  }
+}
+
+}  // namespace
+
+// Apply configurations (columns per pass NC, targets per thread T) the
+// autotuner chooses from.
+namespace {
+struct ApplyShape { int nc, t; };
+constexpr ApplyShape kApplyShapes[] = {{4, 2}, {4, 4}, {8, 1}, {8, 2}, {8, 4}, {16, 1}, {16, 2}};
+constexpr int kNumApplyShapes = (int)(sizeof(kApplyShapes) / sizeof(kApplyShapes[0]));
+
+// Source chunks: about 4096 blocks of one-target threads.  The partition
+// depends on N only, so every shape sums the pairs of a target in the same
+// order and all shapes give bitwise the same result.
+int apply_chunk_len(int N) {
+  const int tiles = (N + kApplyThreads - 1) / kApplyThreads;
+  const int nch = std::max(1, std::min(tiles, (4096 + tiles - 1) / std::max(1, tiles)));
+  const int chunk = (N + nch - 1) / nch;
+  return ((chunk + kApplyThreads - 1) / kApplyThreads) * kApplyThreads;
+}
+}  // namespace
+
+int apply_config_count() { return kNumApplyShapes; }
+
+bool apply_config_valid(int cfg, int ncols) {
+  if (cfg < 0 || cfg >= kNumApplyShapes) return false;
+  int want = 4;
+  while (want < ncols && want < 16) want *= 2;
+  return kApplyShapes[cfg].nc <= want;
+}
+
+int apply_default_config(int ncols) {
+  return ncols <= 4 ? 0 : (ncols <= 8 ? 3 : 6);
+}
+
+void apply_config_name(int cfg, char* buf, int len) {
+  if (cfg < 0 || cfg >= kNumApplyShapes) { std::snprintf(buf, len, "?"); return; }
+  std::snprintf(buf, len, "nc%d_t%d", kApplyShapes[cfg].nc, kApplyShapes[cfg].t);
+}
+
+size_t apply_scratch_doubles(int N, int ncols) {
+  const int len = apply_chunk_len(N);
+  const int nch = (N + len - 1) / len;
+  return (size_t)nch * 2 * N * ncols + ncols;
+}
+
+void launch_apply_operator(Geo g, const int* curve_id, const double* hole_xy, int p, double lam,
+                           const double* x, int ncols, double* y, double* part, const int* skip,
+                           int max_iters, int cfg, hipStream_t s) {
+  if (!apply_config_valid(cfg, ncols)) cfg = apply_default_config(ncols);
+  const ApplyShape sh = kApplyShapes[cfg];
+  const int chunk = apply_chunk_len(g.N);
+  const int nchunk = (g.N + chunk - 1) / chunk;
+  double* nsum = part + (size_t)nchunk * 2 * g.N * ncols;
+  dim3 grid(blocks_for(g.N, kApplyThreads * sh.t), nchunk, blocks_for(ncols, sh.nc));
+#define RS_APPLY(NC, T)                                                                         \
+  if (sh.nc == NC && sh.t == T)                                                                 \
+    hipLaunchKernelGGL((k_apply_pairs<NC, T>), grid, dim3(kApplyThreads), 0, s, g, x, ncols, chunk, \
+                       part, skip, max_iters);
+  RS_APPLY(4, 2) RS_APPLY(4, 4) RS_APPLY(8, 1) RS_APPLY(8, 2) RS_APPLY(8, 4) RS_APPLY(16, 1)
+  RS_APPLY(16, 2)
+#undef RS_APPLY
+  hipLaunchKernelGGL(k_apply_nsum, dim3(ncols), dim3(kBlock), 0, s, g, x, ncols, nsum, skip, max_iters);
+  hipLaunchKernelGGL(k_apply_sum, dim3(blocks_for((long long)g.N * ncols, kBlock)), dim3(kBlock), 0, s,
+                     g, lam, hole_xy, p, x, ncols, part, nchunk, nsum, y, skip, max_iters);
+  if (p > 0)
+    hipLaunchKernelGGL(k_apply_psi, dim3(3 * p), dim3(kBlock), 0, s, g, curve_id, p, x, ncols, y, skip,
+                       max_iters);
+}
+
+}  // namespace rs

@@ -1,0 +1,904 @@
+// gfx950 kernels of one level of the factorization around the pivoted QR
+// (Sections 2.2-2.7): the stacked ID matrix M_B (eq. greens, eq. null-spaceop),
+// the diagonal block A_BB in pivot order, the elimination of the redundant
+// unknowns (T, eq. tmat; X_RR^{-1} with the conditioning guard; E, F and the
+// Schur complement, eq. schurmat), the blocked Gauss-Jordan inverse of the root
+// system (eq. partition) and the float copies of the factors.
+#include "rs_device.h"
+
+namespace rs {
+namespace {
+
+// ---- factorization kernels -------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_assemble_M(const LevelBox* boxes, int n_proxy,
+                                                       double ratio) {
+  const LevelBox& B = boxes[blockIdx.x];
+  const int i = blockIdx.y * blockDim.x + threadIdx.x;
+  const int m = B.m, n = B.n, nF = B.nF;
+  if (i >= m || n == 0) return;
+  const int* I = B.dofs;
+  const Geo& g = B.geo;
+  const int np2 = 2 * n_proxy;
+  const double rp = ratio * B.side;
+  const double wp = 2.0 * kPi * rp / n_proxy;
+  int type, f = 0, pa = 0;
+  double px = 0, py = 0, pnx = 0, pny = 0;
+  if (i < nF) {
+    type = 0;
+    f = B.fint[i];
+  } else if (i < 2 * nF) {
+    type = 1;
+    f = B.fint[i - nF];
+  } else if (i < 2 * nF + 3 * np2) {
+    const int t = i - 2 * nF;
+    type = 2 + t / np2;
+    const int u = t % np2;
+    const int pk = u >> 1;
+    pa = u & 1;
+    const double th = 2.0 * kPi * pk / n_proxy;
+    pnx = cos(th);
+    pny = sin(th);
+    px = B.cx + rp * pnx;
+    py = B.cy + rp * pny;
+  } else {
+    type = 5 + (i - 2 * nF - 3 * np2);
+  }
+  const int fj = f >> 1, fc = f & 1;
+  for (int c = 0; c < n; ++c) {
+    const int d = I[c];
+    const int j = d >> 1, jc = d & 1;
+    double v;
+    switch (type) {
+      case 0: v = op_entry(g, fj, fc, j, jc, 0.0); break;
+      case 1: v = op_entry(g, j, jc, fj, fc, 0.0); break;
+      case 2: v = dl_entry(px - g.x[j], py - g.y[j], g.nx[j], g.ny[j], g.w[j], pa, jc); break;
+      case 3: v = dl_entry(g.x[j] - px, g.y[j] - py, pnx, pny, wp, jc, pa); break;
+      case 4: v = sl_entry(g.x[j] - px, g.y[j] - py, wp, jc, pa); break;
+      case 5: v = g.w[j] * (jc ? g.ny[j] : g.nx[j]); break;
+      default: v = jc ? g.ny[j] : g.nx[j]; break;
+    }
+    B.M[(size_t)c * m + i] = v;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_assemble_abb(const LevelBox* boxes, double lam,
+                                                         int use_perm) {
+  const LevelBox& B = boxes[blockIdx.x];
+  const int n = B.n;
+  const int t = blockIdx.y * blockDim.x + threadIdx.x;
+  if (t >= n * n) return;
+  const int i = t / n, j = t % n;
+  const int pi = use_perm ? B.perm[i] : i;
+  const int pj = use_perm ? B.perm[j] : j;
+  if (B.src) {
+    const ChildSrc& si = B.src[pi];
+    const ChildSrc& sj = B.src[pj];
+    if (si.child == sj.child) {
+      B.Ap[t] = si.xss[(size_t)si.idx * si.ld + sj.idx];
+      return;
+    }
+  }
+  const int di = B.dofs[pi], dj = B.dofs[pj];
+  B.Ap[t] = op_entry(B.geo, di >> 1, di & 1, dj >> 1, dj & 1, lam);
+}
+
+// ---- elimination of the redundant unknowns (G workgroups per box) -----------
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// C = beta*C0 + alpha*op(A) op(B) on FP64 matrix cores.  32 x 32 blocks of C
+// are dealt to the G workgroups of the box; in a block each of the 4 waves
+// owns a 16 x 16 tile and accumulates v_mfma_f64_16x16x4 products over K
+// chunks of 16 staged through LDS (zero padded at the edges).  Operand lanes:
+// A[l % 16][l / 16], B[l / 16][l % 16]; result lane l, register q holds
+// row 4 q + l / 16, column l % 16 of the tile.  C0 may alias C.
+constexpr int kTB = 32;   // block edge
+constexpr int kTK = 16;   // K chunk
+
+__device__ void mfma_gemm(int g, int G, int M, int N, int K, double alpha, const double* A,
+                          int lda, bool tA, const double* B, int ldb, bool tB, double beta,
+                          const double* C0, int ldc0, double* C, int ldc, double* sA, double* sB) {
+  const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
+  const int bm = (M + kTB - 1) / kTB, bn = (N + kTB - 1) / kTB;
+  const int wr = (wid >> 1) * 16, wc = (wid & 1) * 16;
+  for (int blk = g; blk < bm * bn; blk += G) {
+    const int i0 = (blk / bn) * kTB, j0 = (blk % bn) * kTB;
+    dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < K; k0 += kTK) {
+      for (int t = tid; t < kTB * kTK; t += blockDim.x) {
+        const int ii = t / kTK, kk = t % kTK;
+        const int gi = i0 + ii, gk = k0 + kk;
+        sA[ii * (kTK + 1) + kk] =
+            (gi < M && gk < K) ? (tA ? A[(size_t)gk * lda + gi] : A[(size_t)gi * lda + gk]) : 0.0;
+        const int kb = t / kTB, jj = t % kTB;
+        const int gk2 = k0 + kb, gj = j0 + jj;
+        sB[kb * (kTB + 1) + jj] =
+            (gk2 < K && gj < N) ? (tB ? B[(size_t)gj * ldb + gk2] : B[(size_t)gk2 * ldb + gj]) : 0.0;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < kTK; kk += 4) {
+        const double a = sA[(wr + (lane & 15)) * (kTK + 1) + kk + (lane >> 4)];
+        const double b = sB[(kk + (lane >> 4)) * (kTB + 1) + wc + (lane & 15)];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int gi = i0 + wr + 4 * q + (lane >> 4), gj = j0 + wc + (lane & 15);
+      if (gi < M && gj < N) {
+        double v = alpha * acc[q];
+        if (C0) v += beta * C0[(size_t)gi * ldc0 + gj];
+        C[(size_t)gi * ldc + gj] = v;
+      }
+    }
+  }
+}
+
+// In-place Gauss-Jordan sweep with partial pivoting of X (r x r) held in
+// LDS (W, row-major); the inverse of X goes to Xi (global, ld r).  One
+// workgroup.  Returns the reciprocal 1-norm condition number (0 if a pivot
+// vanished), identical in all threads.
+constexpr int kLdsGJMax = 128;   // X_RR up to this edge is inverted by one workgroup (registers)
+constexpr size_t kTSolveMax = 12288;   // T (k x r) up to this size is solved in LDS
+
+// Gauss-Jordan inverse of X (r x r, row-major, r <= kLdsGJMax) by one
+// workgroup with partial pivoting by exchange steps: step j pivots on the
+// largest |W[i][j]| over the rows not used yet, and row i and column j trade
+// places; the finished tableau W holds X^{-1} with X^{-1}[j][p_c] = W[p_j][c].
+// A 16 x 16 thread grid keeps rows ty + 16 a, columns tx + 16 b of W in
+// registers for the whole sweep; per step the pivot row and column go
+// through LDS.  The pivot is compared on a 64-bit key (|W| with its low 8
+// mantissa bits replaced by 255 - i, ties within 2^-44 to the smaller row)
+// that the holders of column j + 1 fold into LDS with an atomic max during
+// step j.  The update is one FMA per element (the multipliers absorb the
+// pivot row and column).  Column 1-norms for rcond_1 are summed in a fixed
+// order.  Two barriers per step.  Returns rcond_1 (0 if singular).
+// LDS: gj_lds_doubles(r) doubles at `sh`.
+__device__ __forceinline__ unsigned long long gj_key(double v, int i) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(fabs(v));
+  return (b & ~0xFFull) | (unsigned long long)(255 - i);
+}
+
+__host__ __device__ constexpr size_t gj_lds_doubles(int r) { return 18 * (size_t)r + 4 + (size_t)r; }
+
+__device__ double reg_gj(const double* X, int r, double* Xi, double* sh, double* red) {
+  const int tid = threadIdx.x;
+  const int ty = tid >> 4, tx = tid & 15;
+  constexpr int MB = (kLdsGJMax + 15) / 16;
+  const int mb = (r + 15) >> 4;
+  double* rowbuf = sh;                       // r: pivot row
+  double* colbuf = rowbuf + r;               // r: pivot column
+  double* part = colbuf + r;                 // 16 r: column-sum partials
+  unsigned long long* keys = reinterpret_cast<unsigned long long*>(part + 16 * (size_t)r);   // 2
+  int* pv = reinterpret_cast<int*>(keys + 2);        // r
+  int* ipv = pv + r;                                  // r
+  double w[MB][MB];
+#pragma unroll
+  for (int a = 0; a < MB; ++a) {
+    if (a >= mb) break;
+#pragma unroll
+    for (int b = 0; b < MB; ++b) {
+      if (b >= mb) break;
+      const int i = ty + 16 * a, c = tx + 16 * b;
+      w[a][b] = (i < r && c < r) ? X[(size_t)i * r + c] : 0.0;
+    }
+  }
+  if (tid < 2) keys[tid] = 0ull;
+  // largest column 1-norm: per-thread partial sums, then 16 partials per column in order
+  auto colnorm = [&]() {
+#pragma unroll
+    for (int b = 0; b < MB; ++b) {
+      if (b >= mb) break;
+      double s = 0.0;
+#pragma unroll
+      for (int a = 0; a < MB; ++a) {
+        if (a >= mb) break;
+        s += fabs(w[a][b]);
+      }
+      const int c = tx + 16 * b;
+      if (c < r) part[ty * r + c] = s;
+    }
+    __syncthreads();
+    double nm = 0.0;
+    for (int c = tid; c < r; c += kBlock) {
+      double s = 0.0;
+      for (int t = 0; t < 16; ++t) s += part[t * r + c];
+      nm = fmax(nm, s);
+    }
+    return block_max(nm, red);
+  };
+  const double n1 = colnorm();
+  if (tx == 0)
+#pragma unroll
+    for (int a = 0; a < MB; ++a) {
+      if (a >= mb) break;
+      const int i = ty + 16 * a;
+      if (i < r) atomicMax(&keys[0], gj_key(w[a][0], i));
+    }
+  __syncthreads();
+  unsigned used = 0;             // bit a: row ty + 16 a is a pivot row already
+  for (int j = 0; j < r; ++j) {
+    const unsigned long long key = keys[j & 1];
+    const int bi = 255 - (int)(key & 0xFF);
+    const int ab = bi >> 4, bj = j >> 4;
+    if (ty == (bi & 15))
+#pragma unroll
+      for (int a = 0; a < MB; ++a)
+        if (a == ab)
+#pragma unroll
+          for (int b = 0; b < MB; ++b) {
+            if (b >= mb) break;
+            const int c = tx + 16 * b;
+            if (c < r) rowbuf[c] = w[a][b];
+          }
+    if (tx == (j & 15))
+#pragma unroll
+      for (int b = 0; b < MB; ++b)
+        if (b == bj)
+#pragma unroll
+          for (int a = 0; a < MB; ++a) {
+            if (a >= mb) break;
+            const int i = ty + 16 * a;
+            if (i < r) colbuf[i] = w[a][b];
+          }
+    if (tid == 0) { keys[(j + 1) & 1] = 0ull; pv[j] = bi; }
+    __syncthreads();
+    const double pvt = colbuf[bi];
+    if (!(pvt != 0.0)) return 0.0;          // uniform: every thread read the same key
+    if ((bi & 15) == ty) used |= 1u << ab;
+    const double inv = 1.0 / pvt;
+    double pr[MB], pc[MB];
+#pragma unroll
+    for (int b = 0; b < MB; ++b) {
+      if (b >= mb) break;
+      const int c = tx + 16 * b;
+      pr[b] = c < r ? (c == j ? inv : rowbuf[c] * inv) : 0.0;
+      const int i = ty + 16 * b;
+      pc[b] = i < r ? (i == bi ? -1.0 : colbuf[i]) : 0.0;
+    }
+    const int bn = (j + 1) >> 4;
+    double cand[MB];
+#pragma unroll
+    for (int a = 0; a < MB; ++a) {
+      if (a >= mb) break;
+      const bool prow = ty + 16 * a == bi;
+      cand[a] = 0.0;
+#pragma unroll
+      for (int b = 0; b < MB; ++b) {
+        if (b >= mb) break;
+        const double w0 = (prow || tx + 16 * b == j) ? 0.0 : w[a][b];
+        w[a][b] = w0 - pc[a] * pr[b];
+        if (b == bn) cand[a] = w[a][b];
+      }
+    }
+    if (tx == ((j + 1) & 15) && j + 1 < r)
+#pragma unroll
+      for (int a = 0; a < MB; ++a) {
+        if (a >= mb) break;
+        const int i = ty + 16 * a;
+        if (i < r && !((used >> a) & 1)) atomicMax(&keys[(j + 1) & 1], gj_key(cand[a], i));
+      }
+    __syncthreads();
+  }
+  // X^{-1}[j][p_c] = W[p_j][c]
+  for (int j = tid; j < r; j += kBlock) ipv[pv[j]] = j;
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < MB; ++a) {
+    if (a >= mb) break;
+    const int i = ty + 16 * a;
+    if (i >= r) continue;
+    const int row = ipv[i];
+#pragma unroll
+    for (int b = 0; b < MB; ++b) {
+      if (b >= mb) break;
+      const int c = tx + 16 * b;
+      if (c < r) Xi[(size_t)row * r + pv[c]] = w[a][b];
+    }
+  }
+  // column c of W is column p_c of X^{-1} with its rows permuted
+  const double n2 = colnorm();
+  const double rc = 1.0 / (n1 * n2);
+  return isfinite(rc) ? rc : 0.0;
+}
+
+// T = R11^{-1} R12 (k x r, row-major) by back substitution on all columns at
+// once, T staged in LDS (k r doubles): step i removes row i's contribution
+// from the rows above it; one barrier per step.  R: k x n rows of R, pivot order.
+__device__ void lds_tsolve(const double* R, int n, int k, int r, double* Tl, double* T) {
+  const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
+  for (int l = ty; l < k; l += 16)
+    for (int c = tx; c < r; c += 16) Tl[l * r + c] = R[(size_t)l * n + k + c];
+  __syncthreads();
+  for (int i = k - 1; i > 0; --i) {
+    const double d = R[(size_t)i * n + i];
+    for (int c = tx; c < r; c += 16) {
+      const double x = Tl[i * r + c] / d;
+      for (int l = ty; l < i; l += 16) Tl[l * r + c] -= R[(size_t)l * n + i] * x;
+    }
+    __syncthreads();
+  }
+  for (int l = ty; l < k; l += 16) {
+    const double d = R[(size_t)l * n + l];
+    for (int c = tx; c < r; c += 16) T[(size_t)l * r + c] = Tl[l * r + c] / d;
+  }
+  __syncthreads();
+}
+
+// Largest column 1-norm of X (n x n, ld ldx) over the box, identical in all workgroups.
+__device__ double coop_norm1(int g, int G, const double* X, int n, int ldx, double* red,
+                             const LevelBox& B, unsigned& nbar, int* dead, int* err) {
+  double v = 0.0;
+  for (int c = g * blockDim.x + threadIdx.x; c < n; c += G * blockDim.x) {
+    double sum = 0.0;
+    for (int i = 0; i < n; ++i) sum += fabs(X[(size_t)i * ldx + c]);
+    v = fmax(v, sum);
+  }
+  v = block_max(v, red);
+  if (G == 1) return v;
+  if (threadIdx.x == 0) st_relaxed(B.cval + g, v);
+  box_barrier_x(B.bar, G, nbar, dead, err);
+  double m = 0.0;
+  for (int h = 0; h < G; ++h) m = fmax(m, ld_relaxed(B.cval + h));
+  box_barrier_x(B.bar, G, nbar, dead, err);   // slots are reused afterwards
+  return m;
+}
+
+constexpr int kGJP = 32;   // pivot block of the in-place Gauss-Jordan
+
+// X_RR^{-1} of the box (blocked in-place Gauss-Jordan with partial pivoting,
+// panels of kGJP columns): W holds X_RR on entry and is destroyed; Xi receives
+// the inverse.  Returns false (uniformly) if a pivot vanished.
+__device__ bool coop_gj(int g, int G, double* W, int r, double* Xi, double* Pn, double* Rb,
+                        double* Cp, double* Dinv, int* piv, int* rowperm, int* flag, double* red,
+                        int* ired, const LevelBox& B, unsigned& nbar, int* dead, int* err) {
+  const int NT = blockDim.x, tid = threadIdx.x;
+  const int gt = g * NT + tid, GT = G * NT;
+  for (int c = gt; c < r; c += GT) rowperm[c] = c;
+  __shared__ double lu[kGJP][kGJP + 1];
+  __shared__ double inv[kGJP][kGJP + 1];
+  for (int k0 = 0; k0 < r; k0 += kGJP) {
+    const int bb = min(kGJP, r - k0);
+    const int h = r - k0;
+    if (g == 0) {
+      // panel: LU with partial pivoting of W[k0:r, k0:k0+bb] (private copy Pn)
+      for (int t = tid; t < h * bb; t += NT) {
+        const int i = t / bb, c = t % bb;
+        Pn[t] = W[(size_t)(k0 + i) * r + k0 + c];
+      }
+      __syncthreads();
+      bool singular = false;
+      for (int j = 0; j < bb; ++j) {
+        double best = -1.0;
+        int bi = h;
+        for (int i = j + tid; i < h; i += NT) {
+          const double v = fabs(Pn[(size_t)i * bb + j]);
+          if (v > best) { best = v; bi = i; }
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+          const double ov = __shfl_xor(best, o, 64);
+          const int oi = __shfl_xor(bi, o, 64);
+          if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+        }
+        const int lane = tid & 63, wid = tid >> 6;
+        if (lane == 0) { red[wid] = best; ired[wid] = bi; }
+        __syncthreads();
+        best = red[0];
+        bi = ired[0];
+        for (int w = 1; w < (NT >> 6); ++w)
+          if (red[w] > best || (red[w] == best && ired[w] < bi)) { best = red[w]; bi = ired[w]; }
+        __syncthreads();
+        if (!(best > 0.0)) { singular = true; break; }
+        if (tid == 0) piv[j] = bi;
+        if (bi != j)
+          for (int c = tid; c < bb; c += NT) {
+            const double a = Pn[(size_t)j * bb + c];
+            Pn[(size_t)j * bb + c] = Pn[(size_t)bi * bb + c];
+            Pn[(size_t)bi * bb + c] = a;
+          }
+        __syncthreads();
+        const double d = Pn[(size_t)j * bb + j];
+        for (int i = j + 1 + tid; i < h; i += NT) Pn[(size_t)i * bb + j] /= d;
+        __syncthreads();
+        const int rest = bb - j - 1;
+        if (rest > 0)
+          for (int t = tid; t < (h - j - 1) * rest; t += NT) {
+            const int i = j + 1 + t / rest, c = j + 1 + t % rest;
+            Pn[(size_t)i * bb + c] -= Pn[(size_t)i * bb + j] * Pn[(size_t)j * bb + c];
+          }
+        __syncthreads();
+      }
+      if (singular) {
+        if (tid == 0) *flag = 1;
+      } else {
+        for (int t = tid; t < bb * bb; t += NT) lu[t / bb][t % bb] = Pn[t];
+        __syncthreads();
+        if (tid < bb) {
+          const int c = tid;
+          double y[kGJP];
+          for (int i = 0; i < bb; ++i) {
+            double sum = (i == c) ? 1.0 : 0.0;
+            for (int l = 0; l < i; ++l) sum -= lu[i][l] * y[l];
+            y[i] = sum;
+          }
+          for (int i = bb - 1; i >= 0; --i) {
+            double sum = y[i];
+            for (int l = i + 1; l < bb; ++l) sum -= lu[i][l] * y[l];
+            y[i] = sum / lu[i][i];
+          }
+          for (int i = 0; i < bb; ++i) inv[i][c] = y[i];
+        }
+        __syncthreads();
+        for (int t = tid; t < bb * bb; t += NT) Dinv[t] = inv[t / bb][t % bb];
+      }
+    }
+    box_barrier_full(B.bar, G, nbar, dead, err);
+    if (*(volatile int*)flag) return false;
+    // row interchanges over all columns; the owner of a panel column copies it
+    for (int c = gt; c < r; c += GT) {
+      for (int j = 0; j < bb; ++j) {
+        const int rr = k0 + piv[j];
+        if (rr != k0 + j) {
+          const double a = W[(size_t)(k0 + j) * r + c];
+          W[(size_t)(k0 + j) * r + c] = W[(size_t)rr * r + c];
+          W[(size_t)rr * r + c] = a;
+        }
+      }
+    }
+    if (g == 0 && tid == 0)
+      for (int j = 0; j < bb; ++j) {
+        const int rr = k0 + piv[j];
+        const int t = rowperm[k0 + j];
+        rowperm[k0 + j] = rowperm[rr];
+        rowperm[rr] = t;
+      }
+    box_barrier_full(B.bar, G, nbar, dead, err);
+    for (int t = gt; t < r * bb; t += GT) {
+      const int i = t / bb, l = t % bb;
+      Cp[t] = W[(size_t)i * r + k0 + l];
+    }
+    for (int t = gt; t < bb * r; t += GT) {
+      const int i = t / r, c = t % r;
+      double sum = 0.0;
+      for (int l = 0; l < bb; ++l) sum += Dinv[i * bb + l] * W[(size_t)(k0 + l) * r + c];
+      Rb[t] = sum;
+    }
+    box_barrier_full(B.bar, G, nbar, dead, err);
+    for (int t = gt; t < r * r; t += GT) {
+      const int i = t / r, c = t % r;
+      const bool ik = i >= k0 && i < k0 + bb;
+      const bool ck = c >= k0 && c < k0 + bb;
+      double v;
+      if (ik) {
+        v = ck ? Dinv[(i - k0) * bb + (c - k0)] : Rb[(size_t)(i - k0) * r + c];
+      } else if (ck) {
+        double sum = 0.0;
+        for (int l = 0; l < bb; ++l) sum += Cp[(size_t)i * bb + l] * Dinv[l * bb + (c - k0)];
+        v = -sum;
+      } else {
+        double sum = 0.0;
+        for (int l = 0; l < bb; ++l) sum += Cp[(size_t)i * bb + l] * Rb[(size_t)l * r + c];
+        v = W[t] - sum;
+      }
+      W[t] = v;
+    }
+    box_barrier_full(B.bar, G, nbar, dead, err);
+  }
+  for (int t = gt; t < r * r; t += GT) {
+    const int i = t / r, c = t % r;
+    Xi[(size_t)i * r + rowperm[c]] = W[t];
+  }
+  box_barrier_full(B.bar, G, nbar, dead, err);
+  return true;
+}
+
+// Per box (G workgroups): T = R11^{-1} R12; X_SR, X_RS, X_RR (eq. tmat);
+// X_RR^{-1} with the rcond guard (move the next pivot to S while
+// rcond_1(X_RR) < rcond_min); E, F and the Schur complement X_SS (eq. schurmat).
+__global__ __launch_bounds__(kBlock) void k_eliminate(const LevelBox* boxes, int G, int* k_io,
+                                                      const int* kx_in, double rcond_min,
+                                                      int* status, double* rc_out, int* err) {
+  extern __shared__ double smem_e[];
+  constexpr int NW = kBlock / 64;
+  __shared__ double red[NW];
+  __shared__ int ired[NW];
+  __shared__ int s_dead;
+  __shared__ double sA[kTB * (kTK + 1)];
+  __shared__ double sB[kTK * (kTB + 1)];
+  const int bidx = blockIdx.x / G, g = blockIdx.x % G;
+  const LevelBox& B = boxes[bidx];
+  const int n = B.n;
+  if (n == 0) return;
+  if (threadIdx.x == 0) s_dead = 0;
+  __syncthreads();
+  unsigned nbar = 0;
+  int k = k_io[B.slot];
+  const int kx = kx_in[B.slot];
+  int st = 0;
+  double rc_final = 1.0;          // rcond_1 of the accepted X_RR (1 when r = 0)
+  const double* Ap = B.Ap;
+  const int gt = g * kBlock + threadIdx.x, GT = G * kBlock;
+  while (true) {
+    const int r = n - k;
+    double* T = B.T;
+    // the route depends on k and r only (not on the launch)
+    if ((size_t)k * r <= kTSolveMax) {
+      if (g == 0) lds_tsolve(B.R, n, k, r, smem_e, T);
+    } else {
+      for (int c = gt; c < r; c += GT) {
+        for (int i = k - 1; i >= 0; --i) {
+          double sum = B.R[(size_t)i * n + k + c];
+          for (int l = i + 1; l < k; ++l) sum -= B.R[(size_t)i * n + l] * T[(size_t)l * r + c];
+          T[(size_t)i * r + c] = sum / B.R[(size_t)i * n + i];
+        }
+      }
+    }
+    box_barrier_full(B.bar, G, nbar, &s_dead, err);
+    if (r == 0) {
+      for (int t = gt; t < k * k; t += GT) {
+        const int i = t / k, c = t % k;
+        B.Xss[t] = Ap[(size_t)i * n + c];
+      }
+      break;
+    }
+    double* Xsr = B.scr;
+    double* Xrs = Xsr + (size_t)k * r;
+    double* Xrr = Xrs + (size_t)r * k;
+    double* W = Xrr + (size_t)r * r;
+    double* Pn = W + (size_t)r * r;
+    double* Rb = Pn + (size_t)r * kGJP;
+    double* Cp = Rb + (size_t)kGJP * r;
+    double* Dinv = Cp + (size_t)r * kGJP;
+    int* piv = reinterpret_cast<int*>(Dinv + kGJP * kGJP);
+    int* rowperm = piv + kGJP;
+    int* flag = rowperm + r + 1;
+    mfma_gemm(g, G, k, r, k, -1.0, Ap, n, false, T, r, false, 1.0, Ap + k, n, Xsr, r, sA, sB);
+    mfma_gemm(g, G, r, k, k, -1.0, T, r, true, Ap, n, false, 1.0, Ap + (size_t)k * n, n, Xrs, k, sA, sB);
+    mfma_gemm(g, G, r, r, k, -1.0, Ap + (size_t)k * n, n, false, T, r, false, 1.0,
+              Ap + (size_t)k * n + k, n, Xrr, r, sA, sB);
+    if (g == 0 && threadIdx.x == 0) *flag = 0;
+    box_barrier_full(B.bar, G, nbar, &s_dead, err);
+    // X_RR -= T^T X_SR
+    mfma_gemm(g, G, r, r, k, -1.0, T, r, true, Xsr, r, false, 1.0, Xrr, r, W, r, sA, sB);
+    box_barrier_full(B.bar, G, nbar, &s_dead, err);
+    double rc = 0.0;
+    // the inversion algorithm depends on r only (not on G), so a box factors
+    // identically whatever launch it is part of
+    if (r <= kLdsGJMax) {
+      if (g == 0) {
+        rc = reg_gj(W, r, B.Xinv, smem_e, red);
+        if (G > 1 && threadIdx.x == 0) st_relaxed(B.cval, rc);
+      }
+      if (G > 1) {
+        box_barrier_full(B.bar, G, nbar, &s_dead, err);
+        rc = ld_relaxed(B.cval);
+      }
+    } else {
+      const double n1 = coop_norm1(g, G, W, r, r, red, B, nbar, &s_dead, err);
+      const bool ok = coop_gj(g, G, W, r, B.Xinv, Pn, Rb, Cp, Dinv, piv, rowperm, flag, red, ired,
+                              B, nbar, &s_dead, err);
+      if (ok) {
+        const double n2 = coop_norm1(g, G, B.Xinv, r, r, red, B, nbar, &s_dead, err);
+        rc = 1.0 / (n1 * n2);
+        if (!isfinite(rc)) rc = 0.0;
+      }
+    }
+    if (!(rc >= rcond_min)) {
+      if (k < kx) {
+        ++k;
+        box_barrier_full(B.bar, G, nbar, &s_dead, err);
+        continue;
+      }
+      st = 1;
+    }
+    rc_final = rc;
+    box_barrier_full(B.bar, G, nbar, &s_dead, err);
+    mfma_gemm(g, G, k, r, r, 1.0, Xsr, r, false, B.Xinv, r, false, 0.0, nullptr, 0, B.E, r, sA, sB);
+    mfma_gemm(g, G, r, k, r, 1.0, B.Xinv, r, false, Xrs, k, false, 0.0, nullptr, 0, B.F, k, sA, sB);
+    box_barrier_full(B.bar, G, nbar, &s_dead, err);
+    mfma_gemm(g, G, k, k, r, -1.0, Xsr, r, false, B.F, k, false, 1.0, Ap, n, B.Xss, k, sA, sB);
+    break;
+  }
+  if (g == 0 && threadIdx.x == 0) {
+    k_io[B.slot] = k;
+    status[B.slot] = st;
+    rc_out[B.slot] = rc_final;
+  }
+}
+
+// ---- blocked in-place Gauss-Jordan inverse (root system) ----------------------
+// A (n x n, row-major) is overwritten by the inverse of P A, where P is the
+// row permutation chosen by partial pivoting (recorded in rowperm); a final
+// column scatter yields A^{-1}.  Per block of b pivot columns K:
+//   panel:  LU with partial pivoting of A[k0:n, K] picks the pivot rows and
+//           gives D^{-1} for the pivot block D (after the row swaps);
+//   swap:   the b row interchanges over all columns, copy of the column block;
+//   rows:   R = D^{-1} A[K, :];
+//   update: A[K,K] = D^{-1}, A[K,~K] = R, A[~K,K] = -A[~K,K] D^{-1},
+//           A[~K,~K] -= A[~K,K] R.
+// A panel without a nonzero pivot sets *status; every kernel of the sequence
+// returns at once when *status is set, so no pivot index of a failed panel is
+// ever used (the panel also leaves its unused entries as the identity).
+constexpr int kGJB = 32;
+
+__global__ __launch_bounds__(kBlock) void k_gjb_panel(const double* A, int n, int k0, int bb,
+                                                      double* W, int* piv, double* Dinv,
+                                                      int* status) {
+  constexpr int NW = kBlock / 64;
+  __shared__ double red[NW];
+  __shared__ int ired[NW];
+  __shared__ double lu[kGJB][kGJB + 1];
+  __shared__ double inv[kGJB][kGJB + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  if (*(volatile const int*)status) return;
+  const int h = n - k0;
+  for (int t = tid; t < h * bb; t += kBlock) {
+    const int i = t / bb, c = t % bb;
+    W[t] = A[(size_t)(k0 + i) * n + k0 + c];
+  }
+  __syncthreads();
+  bool singular = false;
+  for (int j = 0; j < bb; ++j) {
+    double best = -1.0;
+    int bi = h;
+    for (int i = j + tid; i < h; i += kBlock) {
+      const double v = fabs(W[(size_t)i * bb + j]);
+      if (v > best) { best = v; bi = i; }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_xor(best, o, 64);
+      const int oi = __shfl_xor(bi, o, 64);
+      if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+    }
+    if (lane == 0) { red[wid] = best; ired[wid] = bi; }
+    __syncthreads();
+    best = red[0];
+    bi = ired[0];
+    for (int w = 1; w < NW; ++w)
+      if (red[w] > best || (red[w] == best && ired[w] < bi)) { best = red[w]; bi = ired[w]; }
+    __syncthreads();
+    if (!(best > 0.0)) {
+      for (int jj = j + tid; jj < bb; jj += kBlock) piv[jj] = jj;
+      singular = true;
+      break;
+    }
+    if (tid == 0) piv[j] = bi;
+    if (bi != j)
+      for (int c = tid; c < bb; c += kBlock) {
+        const double a = W[(size_t)j * bb + c];
+        W[(size_t)j * bb + c] = W[(size_t)bi * bb + c];
+        W[(size_t)bi * bb + c] = a;
+      }
+    __syncthreads();
+    const double d = W[(size_t)j * bb + j];
+    for (int i = j + 1 + tid; i < h; i += kBlock) W[(size_t)i * bb + j] /= d;
+    __syncthreads();
+    const int rest = bb - j - 1;
+    if (rest > 0)
+      for (int t = tid; t < (h - j - 1) * rest; t += kBlock) {
+        const int i = j + 1 + t / rest, c = j + 1 + t % rest;
+        W[(size_t)i * bb + c] -= W[(size_t)i * bb + j] * W[(size_t)j * bb + c];
+      }
+    __syncthreads();
+  }
+  if (singular) {
+    if (tid == 0) *status = 1;
+    return;
+  }
+  // D = L U (first bb rows of W); D^{-1} = U^{-1} L^{-1}
+  for (int t = tid; t < bb * bb; t += kBlock) lu[t / bb][t % bb] = W[t];
+  __syncthreads();
+  // columns of L^{-1} (unit lower) then U^{-1} applied: one thread per column
+  if (tid < bb) {
+    const int c = tid;
+    double y[kGJB];
+    for (int i = 0; i < bb; ++i) {
+      double s = (i == c) ? 1.0 : 0.0;
+      for (int l = 0; l < i; ++l) s -= lu[i][l] * y[l];
+      y[i] = s;
+    }
+    for (int i = bb - 1; i >= 0; --i) {
+      double s = y[i];
+      for (int l = i + 1; l < bb; ++l) s -= lu[i][l] * y[l];
+      y[i] = s / lu[i][i];
+    }
+    for (int i = 0; i < bb; ++i) inv[i][c] = y[i];
+  }
+  __syncthreads();
+  for (int t = tid; t < bb * bb; t += kBlock) Dinv[t] = inv[t / bb][t % bb];
+}
+
+// Row interchanges of this block over all columns; copy of the column block.
+__global__ void k_gjb_swap(double* A, int n, int k0, int bb, const int* piv, int* rowperm,
+                           const int* status) {
+  if (*(volatile const int*)status) return;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < n) {
+    for (int j = 0; j < bb; ++j) {
+      const int r = k0 + piv[j];
+      if (r != k0 + j) {
+        const double a = A[(size_t)(k0 + j) * n + c];
+        A[(size_t)(k0 + j) * n + c] = A[(size_t)r * n + c];
+        A[(size_t)r * n + c] = a;
+      }
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    for (int j = 0; j < bb; ++j) {
+      const int r = k0 + piv[j];
+      const int t = rowperm[k0 + j];
+      rowperm[k0 + j] = rowperm[r];
+      rowperm[r] = t;
+    }
+  }
+}
+
+__global__ void k_gjb_copycol(const double* A, int n, int k0, int bb, double* Cpanel,
+                              const int* status) {
+  if (*(volatile const int*)status) return;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * bb) return;
+  const int i = t / bb, c = t % bb;
+  Cpanel[t] = A[(size_t)i * n + k0 + c];
+}
+
+// R = D^{-1} A[K, :]
+__global__ void k_gjb_rows(const double* A, int n, int k0, int bb, const double* Dinv, double* R,
+                           const int* status) {
+  if (*(volatile const int*)status) return;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= bb * n) return;
+  const int i = t / n, c = t % n;
+  double s = 0.0;
+  for (int l = 0; l < bb; ++l) s += Dinv[i * bb + l] * A[(size_t)(k0 + l) * n + c];
+  R[t] = s;
+}
+
+__global__ void k_gjb_update(double* A, int n, int k0, int bb, const double* Dinv,
+                             const double* R, const double* Cpanel, const int* status) {
+  if (*(volatile const int*)status) return;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)n * n) return;
+  const int i = (int)(t / n), c = (int)(t % n);
+  const bool ik = i >= k0 && i < k0 + bb;
+  const bool ck = c >= k0 && c < k0 + bb;
+  double v;
+  if (ik) {
+    v = ck ? Dinv[(i - k0) * bb + (c - k0)] : R[(size_t)(i - k0) * n + c];
+  } else if (ck) {
+    double s = 0.0;
+    for (int l = 0; l < bb; ++l) s += Cpanel[(size_t)i * bb + l] * Dinv[l * bb + (c - k0)];
+    v = -s;
+  } else {
+    double s = 0.0;
+    for (int l = 0; l < bb; ++l) s += Cpanel[(size_t)i * bb + l] * R[(size_t)l * n + c];
+    v = A[t] - s;
+  }
+  A[t] = v;
+}
+
+// out[:, rowperm[i]] = A[:, i]  (undo the row permutation of the input)
+__global__ void k_gjb_unpermute(const double* A, int n, const int* rowperm, double* out) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)n * n) return;
+  const int i = (int)(t / n), c = (int)(t % n);
+  out[(size_t)i * n + rowperm[c]] = A[t];
+}
+
+__global__ void k_iota(int* v, int n, int* zero) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) v[t] = t;
+  if (t == 0) *zero = 0;
+}
+
+// float copies of the factor blocks of every box of a level (sizes from the final ranks)
+__global__ void k_factor_to_float(const LevelBox* boxes, const int* k_final) {
+  const LevelBox& B = boxes[blockIdx.x];
+  const int n = B.n;
+  if (n == 0) return;
+  const int k = k_final[B.slot], r = n - k;
+  const int kr = k * r, rr = r * r;
+  for (int t = threadIdx.x; t < kr; t += blockDim.x) {
+    B.Tf[t] = (float)B.T[t];
+    B.Ef[t] = (float)B.E[t];
+    B.Ff[t] = (float)B.F[t];
+  }
+  for (int t = threadIdx.x; t < rr; t += blockDim.x) B.Xinvf[t] = (float)B.Xinv[t];
+}
+
+}  // namespace
+
+void launch_assemble_M(const LevelBox* boxes, int nbox, int max_m, int n_proxy, double ratio,
+                       hipStream_t s) {
+  if (nbox == 0 || max_m == 0) return;
+  dim3 grid(nbox, blocks_for(max_m, kBlock));
+  hipLaunchKernelGGL(k_assemble_M, grid, dim3(kBlock), 0, s, boxes, n_proxy, ratio);
+}
+
+void launch_assemble_abb(const LevelBox* boxes, int nbox, int max_n, double lam, bool use_perm,
+                         hipStream_t s) {
+  if (nbox == 0 || max_n == 0) return;
+  dim3 grid(nbox, blocks_for((long long)max_n * max_n, kBlock));
+  hipLaunchKernelGGL(k_assemble_abb, grid, dim3(kBlock), 0, s, boxes, lam, use_perm ? 1 : 0);
+}
+
+size_t eliminate_lds_bytes(int max_n) {
+  const int r = std::min(max_n, kLdsGJMax);
+  const size_t gj = gj_lds_doubles(r) * sizeof(double);
+  const size_t ts = std::min<size_t>((size_t)max_n * max_n / 4, kTSolveMax) * sizeof(double);
+  return std::max(gj, ts) + 64;
+}
+
+int eliminate_blocks_per_cu(int max_n) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_eliminate, kBlock,
+                                                   eliminate_lds_bytes(max_n)) != hipSuccess)
+    return 0;
+  return nb;
+}
+
+hipError_t launch_eliminate(const LevelBox* boxes, int nbox, int G, int* k_io, const int* kx,
+                            double rcond_min, int* status, double* rc_out, int* err, int max_n,
+                            hipStream_t s) {
+  if (nbox == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_bars, dim3(blocks_for(nbox, kBlock)), dim3(kBlock), 0, s, boxes, nbox, err, 1);
+  const size_t lds = eliminate_lds_bytes(max_n);
+  if (lds > 65536) {
+    hipFuncAttributes fa;
+    hipError_t e = hipFuncGetAttributes(&fa, (const void*)k_eliminate);
+    if (e != hipSuccess) return e;
+    if (fa.maxDynamicSharedSizeBytes < (int)lds) {
+      e = hipFuncSetAttribute((const void*)k_eliminate, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+      if (e != hipSuccess) return e;
+    }
+  }
+  if (G <= 1) {
+    hipLaunchKernelGGL(k_eliminate, dim3(nbox), dim3(kBlock), lds, s, boxes, 1, k_io, kx, rcond_min,
+                       status, rc_out, err);
+    return hipGetLastError();
+  }
+  void* args[] = {(void*)&boxes, (void*)&G, (void*)&k_io, (void*)&kx, (void*)&rcond_min,
+                  (void*)&status, (void*)&rc_out, (void*)&err};
+  return hipLaunchCooperativeKernel((const void*)k_eliminate, dim3(nbox * G), dim3(kBlock), args,
+                                    (unsigned)lds, s);
+}
+
+// Inverse of A (n x n) into Ainv; A is destroyed.  work: >= n*kGJB + kGJB*n +
+// n*kGJB + kGJB*kGJB doubles; iwork: >= n + kGJB ints.
+void launch_gj_blocked(double* A, int n, double* Ainv, double* work, int* iwork, int* status,
+                       hipStream_t s) {
+  double* W = work;                        // (n x kGJB)
+  double* R = W + (size_t)n * kGJB;        // (kGJB x n)
+  double* Cp = R + (size_t)kGJB * n;       // (n x kGJB)
+  double* Dinv = Cp + (size_t)n * kGJB;    // kGJB x kGJB
+  int* rowperm = iwork;
+  int* piv = iwork + n;
+  hipLaunchKernelGGL(k_iota, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, rowperm, n, status);
+  const long long nn = (long long)n * n;
+  for (int k0 = 0; k0 < n; k0 += kGJB) {
+    const int bb = std::min(kGJB, n - k0);
+    hipLaunchKernelGGL(k_gjb_panel, dim3(1), dim3(kBlock), 0, s, A, n, k0, bb, W, piv, Dinv, status);
+    hipLaunchKernelGGL(k_gjb_swap, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, A, n, k0, bb,
+                       piv, rowperm, status);
+    hipLaunchKernelGGL(k_gjb_copycol, dim3(blocks_for((long long)n * bb, kBlock)), dim3(kBlock), 0,
+                       s, A, n, k0, bb, Cp, status);
+    hipLaunchKernelGGL(k_gjb_rows, dim3(blocks_for((long long)bb * n, kBlock)), dim3(kBlock), 0, s,
+                       A, n, k0, bb, Dinv, R, status);
+    hipLaunchKernelGGL(k_gjb_update, dim3(blocks_for(nn, kBlock)), dim3(kBlock), 0, s, A, n, k0, bb,
+                       Dinv, R, Cp, status);
+  }
+  hipLaunchKernelGGL(k_gjb_unpermute, dim3(blocks_for(nn, kBlock)), dim3(kBlock), 0, s, A, n,
+                     rowperm, Ainv);
+}
+
+void launch_factor_to_float(const LevelBox* boxes, int nbox, const int* k_final, hipStream_t s) {
+  if (nbox) hipLaunchKernelGGL(k_factor_to_float, dim3(nbox), dim3(kBlock), 0, s, boxes, k_final);
+}
+
+}  // namespace rs

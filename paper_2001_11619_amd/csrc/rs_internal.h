@@ -87,7 +87,7 @@ struct SolveBox {
 constexpr int kBlock = 256;
 constexpr int kNC = 16;        // right-hand-side columns per sweep block
 
-// ---- launchers (rs_kernels.hip) -------------------------------------------
+// ---- launchers (rs_qr.hip, rs_factor.hip, rs_solve.hip, rs_apply.hip) ----
 void launch_assemble_M(const LevelBox* boxes, int nbox, int max_m, int n_proxy, double ratio,
                        hipStream_t s);
 // Register-resident pivoted QR: a 1024-thread workgroup holds RU rows per
@@ -140,8 +140,6 @@ int eliminate_blocks_per_cu(int max_n);
 hipError_t launch_eliminate(const LevelBox* boxes, int nbox, int G, int* k_io, const int* kx,
                             double rcond_min, int* status, double* rc_out, int* err, int max_n,
                             hipStream_t s);
-void launch_gj_inverse(double* A, int n, int lda, double* Ainv, double* work,
-                       double* rcond_out, int* status, hipStream_t s);
 void launch_gj_blocked(double* A, int n, double* Ainv, double* work, int* iwork, int* status,
                        hipStream_t s);
 template <typename T>
@@ -172,8 +170,6 @@ void launch_dense_apply(const double* Zinv, int nz, const double* v, int ncols, 
                         hipStream_t s);
 template <typename T>
 void launch_root_scatter(const double* sol, int ncols, const int* I0, int n0, T* c, hipStream_t s);
-void launch_to_float(const double* x, long long n, float* y, hipStream_t s);
-void launch_to_double(const float* x, long long n, double* y, hipStream_t s);
 void launch_fill(double* x, long long n, double v, hipStream_t s);
 void launch_refine_flag(const double* colsq, const double* fsq, int ncols, double tol, int max_iters,
                         int* flag, hipStream_t s);
@@ -188,9 +184,17 @@ void launch_factor_to_float(const LevelBox* boxes, int nbox, const int* k_final,
 void launch_w_to_float(const SolveBox* boxes, int nbox, int p3, hipStream_t s);
 void launch_to_rows(const double* f, int ld, int nrows, int ncols, double* c, hipStream_t s);
 void launch_from_rows(const double* c, int nrows, int ncols, double* x, int ld, hipStream_t s);
+// Exact operator apply (refinement residual).  cfg selects one of
+// apply_config_count() kernel shapes (columns per pass, targets per thread);
+// skip (nullable) holds the refinement flags: the apply is skipped once they
+// say converged or exhausted.
 size_t apply_scratch_doubles(int N, int ncols);
+int apply_config_count();
+bool apply_config_valid(int cfg, int ncols);
+int apply_default_config(int ncols);
+void apply_config_name(int cfg, char* buf, int len);
 void launch_apply_operator(Geo g, const int* curve_id, const double* hole_xy, int p,
                            double lam, const double* x, int ncols, double* y,
-                           double* part, hipStream_t s);
+                           double* part, const int* skip, int max_iters, int cfg, hipStream_t s);
 
 }  // namespace rs

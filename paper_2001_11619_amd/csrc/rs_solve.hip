@@ -1,0 +1,512 @@
+// gfx950 kernels of the solve (eq. kinv with the partition of eq. partition):
+// U, V and Psi^T V sweeps, the X_RR^{-1} blocks, the border columns H and rows
+// Psi^T, the reduced root system, and the refinement bookkeeping (residual
+// norms, convergence flag, guarded accumulation).
+#include "rs_device.h"
+
+namespace rs {
+namespace {
+
+// ---- solve kernels -----------------------------------------------------------
+
+// mode 0: U   c_R -= T^T c_S ; c_S -= E c_R
+// mode 1: Psi^T V rows (columns of Psi)   c_R -= T^T c_S ; c_S -= F^T c_R
+// mode 2: V   c_R -= F c_S ; c_S -= T c_R
+// Each box's factors are read in the precision they are stored in (float
+// copies when present, else float64); vectors and sums are float64.
+template <typename T, typename TF>
+__device__ __forceinline__ void sweep_box(const SolveBox& B, const TF* Tm, const TF* Em, const TF* Fm,
+                                          const int* sidx, const int* ridx, T* c, int ncols, int mode,
+                                          int kNC, T* smem) {
+  const int k = B.k, r = B.r;
+  const int q0 = blockIdx.y * kNC;
+  const int nq = min(kNC, ncols - q0);
+  T* cs = smem;
+  T* cr = smem + (size_t)k * kNC;
+  const int* S = sidx + B.s_off;
+  const int* R = ridx + B.r_off;
+  const int tid = threadIdx.x;
+  for (int t = tid; t < k * kNC; t += kBlock) {
+    const int s = t / kNC, q = t % kNC;
+    cs[t] = q < nq ? c[(size_t)S[s] * ncols + q0 + q] : T(0);
+  }
+  for (int t = tid; t < r * kNC; t += kBlock) {
+    const int i = t / kNC, q = t % kNC;
+    cr[t] = q < nq ? c[(size_t)R[i] * ncols + q0 + q] : T(0);
+  }
+  __syncthreads();
+  if (mode != 2) {
+    for (int t = tid; t < r * kNC; t += kBlock) {
+      const int i = t / kNC, q = t % kNC;
+      T acc = 0;
+      for (int s = 0; s < k; ++s) acc += Tm[(size_t)s * r + i] * cs[s * kNC + q];
+      cr[t] -= acc;
+    }
+    __syncthreads();
+    for (int t = tid; t < k * kNC; t += kBlock) {
+      const int s = t / kNC, q = t % kNC;
+      T acc = 0;
+      if (mode == 0)
+        for (int i = 0; i < r; ++i) acc += Em[(size_t)s * r + i] * cr[i * kNC + q];
+      else
+        for (int i = 0; i < r; ++i) acc += Fm[(size_t)i * k + s] * cr[i * kNC + q];
+      cs[t] -= acc;
+    }
+  } else {
+    for (int t = tid; t < r * kNC; t += kBlock) {
+      const int i = t / kNC, q = t % kNC;
+      T acc = 0;
+      for (int s = 0; s < k; ++s) acc += Fm[(size_t)i * k + s] * cs[s * kNC + q];
+      cr[t] -= acc;
+    }
+    __syncthreads();
+    for (int t = tid; t < k * kNC; t += kBlock) {
+      const int s = t / kNC, q = t % kNC;
+      T acc = 0;
+      for (int i = 0; i < r; ++i) acc += Tm[(size_t)s * r + i] * cr[i * kNC + q];
+      cs[t] -= acc;
+    }
+  }
+  __syncthreads();
+  for (int t = tid; t < k * kNC; t += kBlock) {
+    const int s = t / kNC, q = t % kNC;
+    if (q < nq) c[(size_t)S[s] * ncols + q0 + q] = cs[t];
+  }
+  for (int t = tid; t < r * kNC; t += kBlock) {
+    const int i = t / kNC, q = t % kNC;
+    if (q < nq) c[(size_t)R[i] * ncols + q0 + q] = cr[t];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_sweep(const SolveBox* boxes, const int* sidx,
+                                                  const int* ridx, T* c, int ncols, int mode,
+                                                  int kNC) {
+  extern __shared__ double smem_d[];
+  T* smem = reinterpret_cast<T*>(smem_d);
+  const SolveBox& B = boxes[blockIdx.x];
+  if (B.k == 0 || B.r == 0) return;
+  if (B.Tf) sweep_box<T, float>(B, B.Tf, B.Ef, B.Ff, sidx, ridx, c, ncols, mode, kNC, smem);
+  else sweep_box<T, double>(B, B.T, B.E, B.F, sidx, ridx, c, ncols, mode, kNC, smem);
+}
+
+// c_R <- X_RR^{-1} c_R
+template <typename T, typename TF>
+__device__ __forceinline__ void diag_box(const SolveBox& B, const TF* Xi, const int* ridx, T* c,
+                                         int ncols, int kNC, T* smem) {
+  const int r = B.r;
+  const int q0 = blockIdx.y * kNC;
+  const int nq = min(kNC, ncols - q0);
+  T* in = smem;
+  T* out = smem + (size_t)r * kNC;
+  const int* R = ridx + B.r_off;
+  for (int t = threadIdx.x; t < r * kNC; t += kBlock) {
+    const int i = t / kNC, q = t % kNC;
+    in[t] = q < nq ? c[(size_t)R[i] * ncols + q0 + q] : T(0);
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < r * kNC; t += kBlock) {
+    const int i = t / kNC, q = t % kNC;
+    T acc = 0;
+    for (int j = 0; j < r; ++j) acc += Xi[(size_t)i * r + j] * in[j * kNC + q];
+    out[t] = acc;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < r * kNC; t += kBlock) {
+    const int i = t / kNC, q = t % kNC;
+    if (q < nq) c[(size_t)R[i] * ncols + q0 + q] = out[t];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_diag(const SolveBox* boxes, const int* ridx, T* c,
+                                                 int ncols, int kNC) {
+  extern __shared__ double smem_d[];
+  T* smem = reinterpret_cast<T*>(smem_d);
+  const SolveBox& B = boxes[blockIdx.x];
+  if (B.r == 0) return;
+  if (B.Xinvf) diag_box<T, float>(B, B.Xinvf, ridx, c, ncols, kNC, smem);
+  else diag_box<T, double>(B, B.Xinv, ridx, c, ncols, kNC, smem);
+}
+
+// H (2N x 3p) and Psi (2N x 3p, i.e. Psi^T stored by columns), row-major.
+__global__ void k_assemble_H(Geo g, const double* hole_xy, int p, const int* curve_id,
+                             double* H, double* Psi) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= g.N) return;
+  const int p3 = 3 * p;
+  const double xj = g.x[j], yj = g.y[j];
+  for (int h = 0; h < p; ++h) {
+    const double rx = xj - hole_xy[2 * h], ry = yj - hole_xy[2 * h + 1];
+    const double r2 = rx * rx + ry * ry;
+    const double lg = -0.5 * log(r2);
+    double* h0 = H + (size_t)(2 * j) * p3 + 3 * h;
+    double* h1 = H + (size_t)(2 * j + 1) * p3 + 3 * h;
+    h0[0] = kInv4Pi * (lg + rx * rx / r2);
+    h0[1] = kInv4Pi * (rx * ry / r2);
+    h1[0] = kInv4Pi * (ry * rx / r2);
+    h1[1] = kInv4Pi * (lg + ry * ry / r2);
+    h0[2] = kInv4Pi * (-ry) / r2;
+    h1[2] = kInv4Pi * rx / r2;
+  }
+  for (int t = 0; t < p3; ++t) {
+    Psi[(size_t)(2 * j) * p3 + t] = 0.0;
+    Psi[(size_t)(2 * j + 1) * p3 + t] = 0.0;
+  }
+  const int cid = curve_id[j];
+  if (cid > 0) {
+    const int h = cid - 1;
+    const double w = g.w[j];
+    Psi[(size_t)(2 * j) * p3 + 3 * h + 0] = w;
+    Psi[(size_t)(2 * j + 1) * p3 + 3 * h + 1] = w;
+    Psi[(size_t)(2 * j) * p3 + 3 * h + 2] = -w * yj;
+    Psi[(size_t)(2 * j + 1) * p3 + 3 * h + 2] = w * xj;
+  }
+}
+
+// Per box: W = X_RR^{-1} Hh_R (r x 3p) and Gpart = Ph_R^T W (3p x 3p).
+__global__ __launch_bounds__(kBlock) void k_border_box(const SolveBox* boxes, const int* ridx,
+                                                       const double* Hh, const double* Ph,
+                                                       int p3, double* Gpart, double* scratch,
+                                                       long long scr_stride) {
+  const SolveBox& B = boxes[blockIdx.x];
+  const int r = B.r;
+  double* G = Gpart + (size_t)B.part * p3 * p3;
+  if (r == 0) {
+    for (int t = threadIdx.x; t < p3 * p3; t += kBlock) G[t] = 0.0;
+    return;
+  }
+  double* hr = scratch + (size_t)blockIdx.x * scr_stride;
+  double* pr = hr + (size_t)r * p3;
+  const int* R = ridx + B.r_off;
+  for (int t = threadIdx.x; t < r * p3; t += kBlock) {
+    const int i = t / p3, h = t % p3;
+    hr[t] = Hh[(size_t)R[i] * p3 + h];
+    pr[t] = Ph[(size_t)R[i] * p3 + h];
+  }
+  __syncthreads();
+  wg_gemm(r, p3, r, 1.0, B.Xinv, r, false, hr, p3, false, 0.0, nullptr, 0, B.W, p3);
+  wg_gemm(p3, p3, r, 1.0, pr, p3, true, B.W, p3, false, 0.0, nullptr, 0, G, p3);
+}
+
+__global__ void k_sum_parts(const double* parts, int nparts, long long stride, int len,
+                            double scale, double* out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= len) return;
+  double s = 0.0;
+  for (int p = 0; p < nparts; ++p) s += parts[(size_t)p * stride + t];
+  out[t] = scale * s;
+}
+
+// parts[box] (3p x ncols) = Ph_R^T c_R (accumulated in float64)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_border_rhs(const SolveBox* boxes, const int* ridx,
+                                                       const T* Ph, int p3, const T* c, int ncols,
+                                                       double* parts) {
+  const SolveBox& B = boxes[blockIdx.x];
+  double* out = parts + (size_t)B.part * p3 * ncols;
+  const int* R = ridx + B.r_off;
+  for (int t = threadIdx.x; t < p3 * ncols; t += kBlock) {
+    const int h = t / ncols, q = t % ncols;
+    double acc = 0.0;
+    for (int i = 0; i < B.r; ++i)
+      acc += (double)Ph[(size_t)R[i] * p3 + h] * (double)c[(size_t)R[i] * ncols + q];
+    out[t] = acc;
+  }
+}
+
+// c_R -= W lam
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_border_fix(const SolveBox* boxes, const int* ridx,
+                                                       int p3, const double* lam, T* c,
+                                                       int ncols) {
+  const SolveBox& B = boxes[blockIdx.x];
+  const int* R = ridx + B.r_off;
+  for (int t = threadIdx.x; t < B.r * ncols; t += kBlock) {
+    const int i = t / ncols, q = t % ncols;
+    double acc = 0.0;
+    if (B.Wf)
+      for (int h = 0; h < p3; ++h) acc += (double)B.Wf[(size_t)i * p3 + h] * lam[(size_t)h * ncols + q];
+    else
+      for (int h = 0; h < p3; ++h) acc += B.W[(size_t)i * p3 + h] * lam[(size_t)h * ncols + q];
+    c[(size_t)R[i] * ncols + q] -= (T)acc;
+  }
+}
+
+// Z = [[X0, Hh(I0,:)], [Ph(I0,:)^T, -I - G]]
+__global__ void k_assemble_Z(const double* X0, int n0, const double* Hh, const double* Ph,
+                             const int* I0, int p3, const double* G, double* Z) {
+  const int nz = n0 + p3;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)nz * nz) return;
+  const int i = (int)(t / nz), j = (int)(t % nz);
+  double v;
+  if (i < n0 && j < n0) v = X0[(size_t)i * n0 + j];
+  else if (i < n0) v = Hh[(size_t)I0[i] * p3 + (j - n0)];
+  else if (j < n0) v = Ph[(size_t)I0[j] * p3 + (i - n0)];
+  else v = (i == j ? -1.0 : 0.0) - G[(size_t)(i - n0) * p3 + (j - n0)];
+  Z[t] = v;
+}
+
+template <typename T>
+__global__ void k_root_gather(const T* c, int ncols, const int* I0, int n0,
+                              const double* rhs2, int p3, double* v) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (n0 + p3) * ncols) return;
+  const int i = t / ncols, q = t % ncols;
+  v[t] = i < n0 ? (double)c[(size_t)I0[i] * ncols + q] : rhs2[(size_t)(i - n0) * ncols + q];
+}
+
+__global__ void k_dense_apply(const double* Zinv, int nz, const double* v, int ncols,
+                              double* out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nz * ncols) return;
+  const int i = t / ncols, q = t % ncols;
+  double acc = 0.0;
+  for (int j = 0; j < nz; ++j) acc += Zinv[(size_t)i * nz + j] * v[(size_t)j * ncols + q];
+  out[t] = acc;
+}
+
+template <typename T>
+__global__ void k_root_scatter(const double* sol, int ncols, const int* I0, int n0, T* c) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n0 * ncols) return;
+  const int i = t / ncols, q = t % ncols;
+  c[(size_t)I0[i] * ncols + q] = (T)sol[t];
+}
+
+__global__ void k_fill(double* x, long long n, double v) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) x[t] = v;
+}
+
+// x += (double) d
+template <typename TI>
+__global__ void k_accumulate(const TI* d, long long n, double* x) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) x[t] += (double)d[t];
+}
+
+// Refinement control on the device (lets the refinement iterations run as a
+// captured graph).  flag[0] = 1 once max_q sqrt(colsq[q] / fsq[q]) <= tol
+// (fsq = 0 counts as 1); flag[1] counts the corrections applied.  Per
+// iteration: k_accumulate_unless (reads the flags), operator apply, residual,
+// then k_refine_flag (the only writer: counts the correction the iteration
+// applied, then tests the new residual).
+__global__ void k_refine_flag(const double* colsq, const double* fsq, int ncols, double tol,
+                              int max_iters, int* flag) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  if (flag[0] == 0 && flag[1] < max_iters) flag[1] += 1;
+  double worst = 0.0;
+  for (int q = 0; q < ncols; ++q) {
+    const double fq = fsq[q] > 0.0 ? fsq[q] : 1.0;
+    worst = fmax(worst, sqrt(colsq[q] / fq));
+  }
+  flag[0] = worst <= tol ? 1 : 0;
+}
+
+// x += d unless refinement has converged or used up its iterations.
+__global__ void k_accumulate_unless(const double* d, long long n, double* x, const int* flag,
+                                    int max_iters) {
+  if (flag[0] || flag[1] >= max_iters) return;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) x[t] += d[t];
+}
+
+__global__ void k_set_ints(int* p, int n, int v) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) p[t] = v;
+}
+
+// r = [f; 0] - y  (rows layout, f has nf rows); colsq[q] = ||r_q||^2 and fsq[q] = ||f_q||^2,
+// one block per column, fixed-order sums.
+__global__ __launch_bounds__(kBlock) void k_residual(const double* f, int nf, const double* y,
+                                                    int nrows, int ncols, double* r,
+                                                    double* colsq, double* fsq) {
+  constexpr int NW = kBlock / 64;
+  __shared__ double red[NW];
+  const int q = blockIdx.x;
+  double sr = 0.0, sf = 0.0;
+  for (int i = threadIdx.x; i < nrows; i += kBlock) {
+    const double fi = i < nf ? f[(size_t)i * ncols + q] : 0.0;
+    const double v = fi - y[(size_t)i * ncols + q];
+    r[(size_t)i * ncols + q] = v;
+    sr += v * v;
+    sf += fi * fi;
+  }
+  sr = block_sum(sr, red);
+  sf = block_sum(sf, red);
+  if (threadIdx.x == 0) { colsq[q] = sr; fsq[q] = sf; }
+}
+
+// float copy of W (after the border stage) for the boxes whose solve reads
+// float factors; boxes that keep float64 factors have no float W (Wf null)
+__global__ void k_w_to_float(const SolveBox* boxes, int p3) {
+  const SolveBox& B = boxes[blockIdx.x];
+  if (!B.Wf) return;
+  const int len = B.r * p3;
+  for (int t = threadIdx.x; t < len; t += blockDim.x) B.Wf[t] = (float)B.W[t];
+}
+
+__global__ void k_to_rows(const double* f, int ld, int nrows, int ncols, double* c) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)nrows * ncols) return;
+  const int i = (int)(t / ncols), q = (int)(t % ncols);
+  c[t] = f[(size_t)q * ld + i];
+}
+
+__global__ void k_from_rows(const double* c, int nrows, int ncols, double* x, int ld) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)nrows * ncols) return;
+  const int i = (int)(t / ncols), q = (int)(t % ncols);
+  x[(size_t)q * ld + i] = c[t];
+}
+
+}  // namespace
+
+// Right-hand-side columns per block so that `rows` rows fit in 64 KiB of LDS.
+inline int chunk_cols(int rows) {
+  int nc = kNC;
+  while (nc > 1 && (size_t)rows * nc * sizeof(double) > 65536) nc >>= 1;
+  return nc;
+}
+
+template <typename T>
+void launch_sweep(const SolveBox* boxes, int nbox, const int* sidx, const int* ridx, T* c,
+                  int ncols, int mode, int max_n, hipStream_t s) {
+  if (nbox == 0 || ncols == 0) return;
+  const int nc = chunk_cols(max_n);
+  dim3 grid(nbox, blocks_for(ncols, nc));
+  const size_t shm = (size_t)max_n * nc * sizeof(T);
+  hipLaunchKernelGGL(k_sweep<T>, grid, dim3(kBlock), shm, s, boxes, sidx, ridx, c, ncols, mode, nc);
+}
+template void launch_sweep<double>(const SolveBox*, int, const int*, const int*, double*, int, int,
+                                   int, hipStream_t);
+
+template <typename T>
+void launch_diag(const SolveBox* boxes, int nbox, const int* ridx, T* c, int ncols, int max_r,
+                 hipStream_t s) {
+  if (nbox == 0 || ncols == 0) return;
+  const int nc = chunk_cols(2 * max_r);
+  dim3 grid(nbox, blocks_for(ncols, nc));
+  const size_t shm = (size_t)2 * max_r * nc * sizeof(T);
+  hipLaunchKernelGGL(k_diag<T>, grid, dim3(kBlock), shm, s, boxes, ridx, c, ncols, nc);
+}
+template void launch_diag<double>(const SolveBox*, int, const int*, double*, int, int, hipStream_t);
+
+void launch_assemble_H(Geo g, const double* hole_xy, int p, const int* curve_id, double* H,
+                       double* Psi, hipStream_t s) {
+  hipLaunchKernelGGL(k_assemble_H, dim3(blocks_for(g.N, kBlock)), dim3(kBlock), 0, s, g,
+                     hole_xy, p, curve_id, H, Psi);
+}
+
+void launch_border_box(const SolveBox* boxes, int nbox, const int* ridx, const double* Hh,
+                       const double* Ph, int p3, double* Gpart, double* scratch,
+                       long long scr_stride, hipStream_t s) {
+  if (nbox == 0) return;
+  hipLaunchKernelGGL(k_border_box, dim3(nbox), dim3(kBlock), 0, s, boxes, ridx, Hh, Ph, p3,
+                     Gpart, scratch, scr_stride);
+}
+
+void launch_sum_parts(const double* parts, int nparts, long long stride, int len, double scale,
+                      double* out, hipStream_t s) {
+  if (len == 0) return;
+  hipLaunchKernelGGL(k_sum_parts, dim3(blocks_for(len, kBlock)), dim3(kBlock), 0, s, parts,
+                     nparts, stride, len, scale, out);
+}
+
+template <typename T>
+void launch_border_rhs(const SolveBox* boxes, int nbox, const int* ridx, const T* Ph, int p3,
+                       const T* c, int ncols, double* parts, hipStream_t s) {
+  if (nbox == 0) return;
+  hipLaunchKernelGGL(k_border_rhs<T>, dim3(nbox), dim3(kBlock), 0, s, boxes, ridx, Ph, p3, c, ncols,
+                     parts);
+}
+template void launch_border_rhs<double>(const SolveBox*, int, const int*, const double*, int,
+                                        const double*, int, double*, hipStream_t);
+
+template <typename T>
+void launch_border_fix(const SolveBox* boxes, int nbox, const int* ridx, int p3, const double* lam,
+                       T* c, int ncols, hipStream_t s) {
+  if (nbox == 0) return;
+  hipLaunchKernelGGL(k_border_fix<T>, dim3(nbox), dim3(kBlock), 0, s, boxes, ridx, p3, lam, c, ncols);
+}
+template void launch_border_fix<double>(const SolveBox*, int, const int*, int, const double*,
+                                        double*, int, hipStream_t);
+
+void launch_assemble_Z(const double* X0, int n0, const double* Hh, const double* Ph,
+                       const int* I0, int p3, const double* G, double* Z, hipStream_t s) {
+  const long long nz = n0 + p3;
+  hipLaunchKernelGGL(k_assemble_Z, dim3(blocks_for(nz * nz, kBlock)), dim3(kBlock), 0, s, X0,
+                     n0, Hh, Ph, I0, p3, G, Z);
+}
+
+template <typename T>
+void launch_root_gather(const T* c, int ncols, const int* I0, int n0, const double* rhs2, int p3,
+                        double* v, hipStream_t s) {
+  hipLaunchKernelGGL(k_root_gather<T>, dim3(blocks_for((long long)(n0 + p3) * ncols, kBlock)),
+                     dim3(kBlock), 0, s, c, ncols, I0, n0, rhs2, p3, v);
+}
+template void launch_root_gather<double>(const double*, int, const int*, int, const double*, int,
+                                         double*, hipStream_t);
+
+void launch_dense_apply(const double* Zinv, int nz, const double* v, int ncols, double* out,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_dense_apply, dim3(blocks_for((long long)nz * ncols, 64)), dim3(64), 0, s,
+                     Zinv, nz, v, ncols, out);
+}
+
+template <typename T>
+void launch_root_scatter(const double* sol, int ncols, const int* I0, int n0, T* c, hipStream_t s) {
+  hipLaunchKernelGGL(k_root_scatter<T>, dim3(blocks_for((long long)n0 * ncols, kBlock)),
+                     dim3(kBlock), 0, s, sol, ncols, I0, n0, c);
+}
+template void launch_root_scatter<double>(const double*, int, const int*, int, double*, hipStream_t);
+
+void launch_refine_flag(const double* colsq, const double* fsq, int ncols, double tol, int max_iters,
+                        int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_refine_flag, dim3(1), dim3(64), 0, s, colsq, fsq, ncols, tol, max_iters, flag);
+}
+
+void launch_accumulate_unless(const double* d, long long n, double* x, const int* flag, int max_iters,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_accumulate_unless, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, d, n, x,
+                     flag, max_iters);
+}
+
+void launch_set_ints(int* p, int n, int v, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_ints, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, p, n, v);
+}
+
+void launch_fill(double* x, long long n, double v, hipStream_t s) {
+  if (n) hipLaunchKernelGGL(k_fill, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, x, n, v);
+}
+
+void launch_accumulate(const double* d, long long n, double* x, hipStream_t s) {
+  if (n) hipLaunchKernelGGL(k_accumulate<double>, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, d, n, x);
+}
+
+void launch_accumulate(const float* d, long long n, double* x, hipStream_t s) {
+  if (n) hipLaunchKernelGGL(k_accumulate<float>, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, d, n, x);
+}
+
+void launch_residual(const double* f, int nf, const double* y, int nrows, int ncols, double* r,
+                     double* colsq, double* fsq, hipStream_t s) {
+  hipLaunchKernelGGL(k_residual, dim3(ncols), dim3(kBlock), 0, s, f, nf, y, nrows, ncols, r, colsq, fsq);
+}
+
+void launch_w_to_float(const SolveBox* boxes, int nbox, int p3, hipStream_t s) {
+  if (nbox) hipLaunchKernelGGL(k_w_to_float, dim3(nbox), dim3(kBlock), 0, s, boxes, p3);
+}
+
+void launch_to_rows(const double* f, int ld, int nrows, int ncols, double* c, hipStream_t s) {
+  hipLaunchKernelGGL(k_to_rows, dim3(blocks_for((long long)nrows * ncols, kBlock)), dim3(kBlock),
+                     0, s, f, ld, nrows, ncols, c);
+}
+
+void launch_from_rows(const double* c, int nrows, int ncols, double* x, int ld, hipStream_t s) {
+  hipLaunchKernelGGL(k_from_rows, dim3(blocks_for((long long)nrows * ncols, kBlock)),
+                     dim3(kBlock), 0, s, c, nrows, ncols, x, ld);
+}
+
+}  // namespace rs

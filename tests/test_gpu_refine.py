@@ -137,3 +137,21 @@ def test_mixed_boxes_float_and_double(thr):
     if thr > 1.0:
         p = _solver(g, leaf_size=32, tol=1e-7, precision=0, refine_max=30, refine_tol=1e-12).factor()
         assert np.array_equal(p.solve(f), x)
+
+
+def test_graph_skips_converged_iterations():
+    """With two refinement iterations per graph launch, an odd number of needed
+    corrections leaves a converged iteration in the last launch: it changes
+    nothing (x, the reported iterations and residual equal those of the eager
+    loop, which stops at convergence)."""
+    g = workload_small(seed=11, n_outer=256, n_holes=2, nodes_per_hole=128, radius=3.0)
+    f = boundary_data(g, exterior_forces_for_geometry(g, 2, seed=5))
+    runs = {}
+    for graph in (0, 1):
+        s = _solver(g, leaf_size=32, tol=1e-6, precision=1, refine_max=20, refine_tol=1e-10,
+                    solve_graph=graph).factor()
+        x, res = s.solve(f, residual=True)
+        runs[graph] = (x, res, s.stats()["refine_iters"])
+    assert np.array_equal(runs[0][0], runs[1][0])
+    assert runs[0][2] == runs[1][2]
+    assert np.all(runs[1][1] <= 1e-10)

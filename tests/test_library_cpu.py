@@ -34,7 +34,7 @@ def test_default_params():
     assert p.lambda_ == -0.5 and p.tol == 1e-10 and p.leaf_size == 64
     assert p.n_proxy == 64 and p.proxy_ratio == 1.5 and p.rcond_min == 1e-12
     assert p.precision == 0 and p.refine_tol == 1e-8 and p.refine_max == 0
-    assert p.has_root == 0 and p.solve_graph == 1 and p.mixed_rcond_min == 1e-4
+    assert p.has_root == 0 and p.solve_graph == 1 and p.mixed_rcond_min == 1e-4 and p.apply_shape == -1
 
 
 def _geom():
