@@ -625,9 +625,14 @@ __global__ __launch_bounds__(kBlock) void k_eliminate(const LevelBox* boxes, int
 // ever used (the panel also leaves its unused entries as the identity).
 constexpr int kGJB = 32;
 
+// The panel (h x bb) is factored in LDS when it fits (in_lds != 0, dynamic
+// LDS of h * bb doubles), else in the global work array W.
+constexpr size_t kPanelLdsBytes = 136 * 1024;
+
 __global__ __launch_bounds__(kBlock) void k_gjb_panel(const double* A, int n, int k0, int bb,
-                                                      double* W, int* piv, double* Dinv,
-                                                      int* status) {
+                                                      double* Wg, int* piv, double* Dinv,
+                                                      int* status, int in_lds) {
+  extern __shared__ double wsh[];
   constexpr int NW = kBlock / 64;
   __shared__ double red[NW];
   __shared__ int ired[NW];
@@ -635,6 +640,7 @@ __global__ __launch_bounds__(kBlock) void k_gjb_panel(const double* A, int n, in
   __shared__ double inv[kGJB][kGJB + 1];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   if (*(volatile const int*)status) return;
+  double* W = in_lds ? wsh : Wg;
   const int h = n - k0;
   for (int t = tid; t < h * bb; t += kBlock) {
     const int i = t / bb, c = t % bb;
@@ -883,7 +889,10 @@ void launch_gj_blocked(double* A, int n, double* Ainv, double* work, int* iwork,
   const long long nn = (long long)n * n;
   for (int k0 = 0; k0 < n; k0 += kGJB) {
     const int bb = std::min(kGJB, n - k0);
-    hipLaunchKernelGGL(k_gjb_panel, dim3(1), dim3(kBlock), 0, s, A, n, k0, bb, W, piv, Dinv, status);
+    const size_t pbytes = (size_t)(n - k0) * bb * sizeof(double);
+    const int in_lds = pbytes <= kPanelLdsBytes ? 1 : 0;
+    hipLaunchKernelGGL(k_gjb_panel, dim3(1), dim3(kBlock), in_lds ? pbytes : 0, s, A, n, k0, bb, W, piv,
+                       Dinv, status, in_lds);
     hipLaunchKernelGGL(k_gjb_swap, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, A, n, k0, bb,
                        piv, rowperm, status);
     hipLaunchKernelGGL(k_gjb_copycol, dim3(blocks_for((long long)n * bb, kBlock)), dim3(kBlock), 0,

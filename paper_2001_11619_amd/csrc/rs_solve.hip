@@ -189,13 +189,31 @@ __global__ __launch_bounds__(kBlock) void k_border_box(const SolveBox* boxes, co
   wg_gemm(p3, p3, r, 1.0, pr, p3, true, B.W, p3, false, 0.0, nullptr, 0, G, p3);
 }
 
-__global__ void k_sum_parts(const double* parts, int nparts, long long stride, int len,
-                            double scale, double* out) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= len) return;
-  double s = 0.0;
-  for (int p = 0; p < nparts; ++p) s += parts[(size_t)p * stride + t];
-  out[t] = scale * s;
+// out[t] = scale * sum_p parts[p * stride + t].  A block takes 64 outputs; its
+// 4 waves x 4 accumulators form 16 streams, stream s summing the parts
+// p = s, s + 16, s + 32, ... in order; the 16 stream sums are then added in
+// stream order (the result does not depend on timing).
+__global__ __launch_bounds__(256) void k_sum_parts(const double* parts, int nparts, long long stride,
+                                                   int len, double scale, double* out) {
+  __shared__ double sh[16][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int t = blockIdx.x * 64 + lane;
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  if (t < len) {
+    for (int p0 = 4 * w; p0 < nparts; p0 += 16) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (p0 + u < nparts) a[u] += parts[(size_t)(p0 + u) * stride + t];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) sh[4 * w + u][lane] = a[u];
+  __syncthreads();
+  if (w == 0 && t < len) {
+    double sum = 0.0;
+    for (int st = 0; st < 16; ++st) sum += sh[st][lane];
+    out[t] = scale * sum;
+  }
 }
 
 // parts[box] (3p x ncols) = Ph_R^T c_R (accumulated in float64)
@@ -257,14 +275,33 @@ __global__ void k_root_gather(const T* c, int ncols, const int* I0, int n0,
   v[t] = i < n0 ? (double)c[(size_t)I0[i] * ncols + q] : rhs2[(size_t)(i - n0) * ncols + q];
 }
 
-__global__ void k_dense_apply(const double* Zinv, int nz, const double* v, int ncols,
-                              double* out) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nz * ncols) return;
-  const int i = t / ncols, q = t % ncols;
-  double acc = 0.0;
-  for (int j = 0; j < nz; ++j) acc += Zinv[(size_t)i * nz + j] * v[(size_t)j * ncols + q];
-  out[t] = acc;
+// out = Zinv v (nz x ncols, rows layout): one wave per row of Zinv, lanes
+// split the row (stride 64), 8 columns at a time, fixed-order wave sums.
+__global__ __launch_bounds__(256) void k_dense_apply(const double* Zinv, int nz, const double* v,
+                                                     int ncols, double* out) {
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= nz) return;   // uniform per wave
+  const double* zr = Zinv + (size_t)i * nz;
+  for (int q0 = 0; q0 < ncols; q0 += 8) {
+    const int nq = min(8, ncols - q0);
+    double a[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] = 0.0;
+    for (int j = lane; j < nz; j += 64) {
+      const double z = zr[j];
+      const double* vj = v + (size_t)j * ncols + q0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (u < nq) a[u] += z * vj[u];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (u >= nq) break;
+      const double sum = wave_sum(a[u]);
+      if (lane == 0) out[(size_t)i * ncols + q0 + u] = sum;
+    }
+  }
 }
 
 template <typename T>
@@ -411,8 +448,8 @@ void launch_border_box(const SolveBox* boxes, int nbox, const int* ridx, const d
 void launch_sum_parts(const double* parts, int nparts, long long stride, int len, double scale,
                       double* out, hipStream_t s) {
   if (len == 0) return;
-  hipLaunchKernelGGL(k_sum_parts, dim3(blocks_for(len, kBlock)), dim3(kBlock), 0, s, parts,
-                     nparts, stride, len, scale, out);
+  hipLaunchKernelGGL(k_sum_parts, dim3(blocks_for(len, 64)), dim3(256), 0, s, parts, nparts, stride,
+                     len, scale, out);
 }
 
 template <typename T>
@@ -452,8 +489,8 @@ template void launch_root_gather<double>(const double*, int, const int*, int, co
 
 void launch_dense_apply(const double* Zinv, int nz, const double* v, int ncols, double* out,
                         hipStream_t s) {
-  hipLaunchKernelGGL(k_dense_apply, dim3(blocks_for((long long)nz * ncols, 64)), dim3(64), 0, s,
-                     Zinv, nz, v, ncols, out);
+  if (nz == 0 || ncols == 0) return;
+  hipLaunchKernelGGL(k_dense_apply, dim3(blocks_for(nz, 4)), dim3(256), 0, s, Zinv, nz, v, ncols, out);
 }
 
 template <typename T>
