@@ -35,10 +35,11 @@ HBM_PEAK_GBS = 8000.0
 
 WORKLOADS = {
     "circle10_8holes": dict(desc="outer circle R=10 (4096 nodes) + 8 random ellipses (1024 nodes each), "
-                                 "24576 unknowns + 24 border, seed 2", nrhs=4, seed=2),
-    "ellipse_2048": dict(desc="ellipse semi-axes 1.0/0.6, 2048 nodes, 4096 unknowns", nrhs=1, seed=1),
+                                 "24576 unknowns + 24 border, seed 2", nrhs=4, seed=2, tol_mixed=1e-6),
+    "ellipse_2048": dict(desc="ellipse semi-axes 1.0/0.6, 2048 nodes, 4096 unknowns", nrhs=1, seed=1,
+                         tol_mixed=1e-6),
     "circle40_64holes": dict(desc="outer circle R=40 (16384 nodes) + 64 random ellipses (1792 nodes each), "
-                                  "262144 unknowns + 192 border, seed 3", nrhs=16, seed=3),
+                                  "262144 unknowns + 192 border, seed 3", nrhs=16, seed=3, tol_mixed=1e-7),
 }
 
 
@@ -271,11 +272,12 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(workload, form):
+def measured_traffic(workload, form, tol):
     """HBM bytes per step of the pivoted-QR kernels from the committed counter
     summary (FETCH_SIZE and WRITE_SIZE runs, copy-calibrated), or None when
-    the summary is for another workload or form, or the kernels changed since."""
-    if workload != "circle10_8holes" or form != "mixed" or not os.path.exists(TRAFFIC_FILE):
+    the summary is for another workload, form or tolerance, or the kernels
+    changed since."""
+    if not os.path.exists(TRAFFIC_FILE):
         return None
     vals = {}
     with open(TRAFFIC_FILE) as fh:
@@ -283,6 +285,13 @@ def measured_traffic(workload, form):
             if ":" in line and line.startswith("- "):
                 k, v = line[2:].split(":", 1)
                 vals[k.strip()] = v.strip().strip("`")
+    if vals.get("workload") != workload or vals.get("form") != form:
+        return None
+    try:
+        if float(vals.get("tol", "nan")) != tol:
+            return None
+    except ValueError:
+        return None
     if vals.get("kernel_source_sha256") != kernel_source_hash():
         return None
     try:
@@ -291,7 +300,7 @@ def measured_traffic(workload, form):
         return None
 
 
-def roofline_of(run, steps, nrhs, n_nodes, workload, form):
+def roofline_of(run, steps, nrhs, n_nodes, workload, form, tol):
     """Roofline of the dominant kernel family (by device time).  Pivoted QR:
     the ID's algorithmic flops (row reduction 2 m n^2 - 2/3 n^3 plus 4 n^2 per
     pivoted step, or the pivoted Householder steps on M_B) over the time of
@@ -310,7 +319,7 @@ def roofline_of(run, steps, nrhs, n_nodes, workload, form):
     launches, tot_ms = ktimes[fam]
     per_step_s = tot_ms / 1e3 / steps
     achieved = work / per_step_s / 1e12
-    traffic = measured_traffic(workload, form) if fam == "cpqr" else None
+    traffic = measured_traffic(workload, form, tol) if fam == "cpqr" else None
     return {"bound": bound, "kernel": fam, "achieved": achieved, "peak": peak, "unit": unit,
             "frac": achieved / peak, "traffic": traffic, "traffic_unit": "bytes per step",
             "launches_per_step": launches // steps, "ms_per_step": tot_ms / steps,
@@ -324,7 +333,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="circle10_8holes", choices=sorted(WORKLOADS) + ["batch", "evolve"])
     ap.add_argument("--tol-plain", type=float, default=1e-10)
-    ap.add_argument("--tol-mixed", type=float, default=1e-7)
+    ap.add_argument("--tol-mixed", type=float, default=None,
+                    help="ID tolerance of the mixed form (default: per workload, the fastest that "
+                         "refines to 1e-8 in few iterations)")
     ap.add_argument("--forms", default="mixed,plain")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-size", type=int, default=32)
@@ -334,8 +345,10 @@ def main():
     ap.add_argument("--evolve-steps", type=int, default=10)
     ap.add_argument("--evolve-all", action="store_true", help="move hole 1, 2, 3, ... in turn")
     args = ap.parse_args()
+    if args.tol_mixed is None:
+        args.tol_mixed = WORKLOADS.get(args.workload, {}).get("tol_mixed", 1e-7)
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % args.gpus,
+        print("bench.py runs on one GPU; --gpus %d is not supported" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
 
@@ -394,7 +407,8 @@ def main():
         "max_rel_residual": head["max_rel_residual"],
         "setup_ms": head["setup_ms"],
         "kernel_ms_per_step": {k: v[1] / args.steps for k, v in sorted(head["ktimes"].items())},
-        "roofline": roofline_of(head, args.steps, nrhs, geom.n_nodes, args.workload, forms[0]),
+        "roofline": roofline_of(head, args.steps, nrhs, geom.n_nodes, args.workload, forms[0],
+                                args.tol_mixed if forms[0] == "mixed" else args.tol_plain),
     }
     for fm in forms[1:]:
         r = runs[fm]

@@ -234,9 +234,11 @@ struct rs_ctx {
   long long factor_epoch = 0;
   bool capturing = false;
   hipStream_t cap_stream = nullptr;
-  hipGraphExec_t refine_exec = nullptr;
+  hipGraphExec_t refine_exec = nullptr;   // one refinement iteration
   int refine_nrhs = 0;
   long long refine_epoch = -1;
+  double refine_prev = 1.0;       // largest relative residual before the last launch
+  int refine_last = 0;            // iterations in the last launch
   DevBuf d_flag;                  // [converged, corrections applied]
   PinHost h_flag;
 
@@ -1446,8 +1448,6 @@ void refine_iteration(rs_ctx* c, int nrhs) {
                      c->stream);
 }
 
-constexpr int kRefinePerGraph = 2;   // refinement iterations per graph launch
-
 // x = 0, r = [f; 0], flags cleared (f already in d_frows).
 void refine_begin(rs_ctx* c, int nrhs) {
   const int n2 = 2 * c->N;
@@ -1458,11 +1458,14 @@ void refine_begin(rs_ctx* c, int nrhs) {
   launch_residual(c->d_frows.as<double>(), n2, c->d_xs.as<double>(), ns, nrhs, c->d_r.as<double>(), colsq,
                   colsq + nrhs, c->stream);
   launch_set_ints(c->d_flag.as<int>(), 2, 0, c->stream);
+  c->refine_prev = 1.0;
+  c->refine_last = 0;
 }
 
-// Capture kRefinePerGraph refinement iterations (once per factorization and nrhs).
+// Capture one refinement iteration as a graph (once per factorization and nrhs).
 void refine_graph_capture(rs_ctx* c, int nrhs) {
   if (c->refine_exec && c->refine_nrhs == nrhs && c->refine_epoch == c->factor_epoch) return;
+  HTimer ht_(c, "host:capture");
   if (c->refine_exec) {
     HIP_CHECK(hipGraphExecDestroy(c->refine_exec));
     c->refine_exec = nullptr;
@@ -1474,7 +1477,7 @@ void refine_graph_capture(rs_ctx* c, int nrhs) {
   hipGraph_t g = nullptr;
   HIP_CHECK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
   try {
-    for (int it = 0; it < kRefinePerGraph; ++it) refine_iteration(c, nrhs);
+    refine_iteration(c, nrhs);
   } catch (...) {
     (void)hipStreamEndCapture(c->cap_stream, &g);
     if (g) (void)hipGraphDestroy(g);
@@ -1496,10 +1499,34 @@ void refine_graph_capture(rs_ctx* c, int nrhs) {
   c->refine_epoch = c->factor_epoch;
 }
 
+// Iterations for the next round of graph replays (1 or 2) before the host
+// looks at the residual again: the remaining count predicted from the
+// contraction observed so far (per iteration, geometric mean over the last
+// round); 2 before the first round.  Replays after convergence change nothing
+// (the device flag skips them), so a prediction only trades a host poll
+// against a skipped iteration.
+int refine_next_iters(rs_ctx* c) {
+  if (c->refine_last == 0 || c->last_res.empty()) return 2;
+  double cur = 0.0;
+  for (double r : c->last_res) cur = std::max(cur, r);
+  const double prev = std::max(c->refine_prev, 1e-300);
+  double rho = std::pow(std::max(cur, 1e-300) / prev, 1.0 / c->refine_last);
+  rho = std::min(std::max(rho, 1e-12), 0.99);
+  const double need = std::log(c->prm.refine_tol / std::max(cur, 1e-300)) / std::log(rho);
+  return need > 1.5 ? 2 : 1;   // an extra poll costs far less than a skipped iteration
+}
+
 void refine_graph_launch(rs_ctx* c, int nrhs) {
+  const int iters = refine_next_iters(c);
+  if (!c->last_res.empty()) {
+    double cur = 0.0;
+    for (double r : c->last_res) cur = std::max(cur, r);
+    c->refine_prev = cur;
+  }
   refine_graph_capture(c, nrhs);
+  c->refine_last = iters;
   KTimer kt_(c, "refine_graph");
-  HIP_CHECK(hipGraphLaunch(c->refine_exec, c->stream));
+  for (int it = 0; it < iters; ++it) HIP_CHECK(hipGraphLaunch(c->refine_exec, c->stream));
 }
 
 // Read the flags and norms after a graph launch; true when refinement is over
