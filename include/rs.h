@@ -197,6 +197,17 @@ rs_status rs_get_skeleton(const rs_ctx* ctx, int box, int cap, int* out, int* le
  * the residual kernel used by refinement, exposed for verification. */
 rs_status rs_apply(rs_ctx* ctx, int ncols, const double* x, double* y);
 
+/* Velocity u(t) = (D mu)(t) + (H lambda)(t) at n_targets points t off the
+ * boundary (eq. forwardeq): the double layer of the density by the boundary
+ * quadrature plus the Stokeslet and rotlet of every hole.  targets_xy: host,
+ * n_targets x 2 (x, y pairs); x: host, (2N + 3p) x ncols column-major, a
+ * solution [mu; lambda] as returned by rs_solve; u: host, (2 n_targets) x ncols
+ * column-major, rows 2t and 2t + 1 = the x and y components at target t.
+ * Plain quadrature: accurate a few node spacings away from the boundary (no
+ * near-boundary correction).  Needs only rs_build_tree (no factorization). */
+rs_status rs_evaluate(rs_ctx* ctx, int n_targets, const double* targets_xy, int ncols, const double* x,
+                      double* u);
+
 /* Inverse of a dense n x n matrix by the blocked Gauss-Jordan elimination with
  * partial pivoting that inverts the root system Z (the partitioned root solve
  * of eq. (partition)), on the context's device and stream.  a: host, row-major,

@@ -93,6 +93,7 @@ def load_library():
     lib.rs_get_skeleton.argtypes = [h, ctypes.c_int, ctypes.c_int, ip, ip]
     lib.rs_apply.argtypes = [h, ctypes.c_int, dp, dp]
     lib.rs_dense_inverse.argtypes = [h, ctypes.c_int, dp, dp]
+    lib.rs_evaluate.argtypes = [h, ctypes.c_int, dp, ctypes.c_int, dp, dp]
     lib.rs_factor_batch.argtypes = [P(h), ctypes.c_int]
     lib.rs_solve_batch.argtypes = [P(h), ctypes.c_int, ctypes.c_int, P(vp), P(vp)]
     lib.rs_set_kernel_timing.argtypes = [h, ctypes.c_int]
@@ -103,7 +104,7 @@ def load_library():
     lib.rs_last_error.restype = ctypes.c_char_p
     for name in ("rs_build_tree", "rs_factor", "rs_solve", "rs_solve_dev", "rs_update_moved_nodes",
                  "rs_set_stream", "rs_get_stats", "rs_get_boxes", "rs_get_skeleton", "rs_apply",
-                 "rs_dense_inverse", "rs_set_kernel_timing", "rs_get_kernel_times",
+                 "rs_dense_inverse", "rs_evaluate", "rs_set_kernel_timing", "rs_get_kernel_times",
                  "rs_factor_batch", "rs_solve_batch"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -116,9 +117,9 @@ def exported_symbols():
     out = []
     for name in ("rs_default_params", "rs_build_tree", "rs_factor", "rs_solve", "rs_solve_dev",
                  "rs_update_moved_nodes", "rs_set_stream", "rs_get_stats", "rs_get_boxes",
-                 "rs_get_skeleton", "rs_apply", "rs_dense_inverse", "rs_set_kernel_timing",
-                 "rs_get_kernel_times", "rs_factor_batch", "rs_solve_batch", "rs_destroy",
-                 "rs_last_error"):
+                 "rs_get_skeleton", "rs_apply", "rs_dense_inverse", "rs_evaluate",
+                 "rs_set_kernel_timing", "rs_get_kernel_times", "rs_factor_batch", "rs_solve_batch",
+                 "rs_destroy", "rs_last_error"):
         if hasattr(lib, name):
             out.append(name)
     return out
@@ -253,6 +254,17 @@ class RSSolver:
         Y = np.empty_like(Xf, order="F")
         self._check(self._lib.rs_apply(self._h, Xf.shape[1], _dptr(Xf), _dptr(Y)))
         return Y[:, 0] if one else np.ascontiguousarray(Y)
+
+    def evaluate(self, targets, x):
+        """Velocity D mu + H lambda at target points (M, 2) off the boundary from a
+        solution x ((2N + 3p) or (2N + 3p, ncols)); returns (M, 2) or (M, 2, ncols)."""
+        T = np.ascontiguousarray(targets, dtype=np.float64).reshape(-1, 2)
+        one = np.asarray(x).ndim == 1
+        X = np.asfortranarray(np.asarray(x, dtype=np.float64).reshape(self.n_system, -1))
+        U = np.empty((2 * T.shape[0], X.shape[1]), order="F")
+        self._check(self._lib.rs_evaluate(self._h, T.shape[0], _dptr(T), X.shape[1], _dptr(X), _dptr(U)))
+        U = np.ascontiguousarray(U).reshape(T.shape[0], 2, X.shape[1])
+        return U[:, :, 0] if one else U
 
     def dense_inverse(self, a):
         """Inverse of a dense square matrix by the library's blocked

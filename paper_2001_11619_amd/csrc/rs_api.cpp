@@ -10,13 +10,17 @@
 #include "rs_internal.h"
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <tuple>
 #include <unordered_map>
 #include <vector>
@@ -226,6 +230,8 @@ struct rs_ctx {
   // solve work
   DevBuf d_f, d_c, d_v, d_sol, d_parts, d_rhs2, d_xout, d_res, d_frows, d_xs, d_r, d_dx,
       d_ys, d_norms, d_apply;
+  // evaluation at target points
+  DevBuf d_evx, d_evy, d_evu, d_evpart;
   std::vector<double> last_res;   // relative residual per column of the last refined solve
 
   rs_stats stats{};
@@ -557,6 +563,85 @@ bool compress_needed(const rs_ctx* c, int b, const std::vector<int>& F) {
   return false;
 }
 
+// Process-wide pool of host threads for the per-box host work of a level
+// (near fields, unknown lists).  run(n, f) calls f(i) for every i < n, the
+// caller taking part; small n runs on the caller alone.  Calls from several
+// host threads are serialized.
+class HostPool {
+ public:
+  static HostPool& instance() {
+    static HostPool pool;
+    return pool;
+  }
+  void run(int n, const std::function<void(int)>& f) {
+    if (n < kSerialBelow || workers_.empty()) {
+      for (int i = 0; i < n; ++i) f(i);
+      return;
+    }
+    std::lock_guard<std::mutex> serial(run_mu_);
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      fn_ = &f;
+      n_ = n;
+      chunk_ = std::max(1, n / (4 * (int)(workers_.size() + 1)));
+      next_.store(0);
+      active_ = (int)workers_.size();
+      ++gen_;
+    }
+    cv_.notify_all();
+    work();
+    std::unique_lock<std::mutex> lk(mu_);
+    done_cv_.wait(lk, [&] { return active_ == 0; });
+    fn_ = nullptr;
+  }
+  ~HostPool() {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      stop_ = true;
+    }
+    cv_.notify_all();
+    for (auto& t : workers_) t.join();
+  }
+
+ private:
+  static constexpr int kSerialBelow = 32;
+  HostPool() {
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const int nthreads = (int)std::min(8u, hw);
+    for (int i = 0; i + 1 < nthreads; ++i) workers_.emplace_back([this] { loop(); });
+  }
+  void work() {
+    for (;;) {
+      const int b = next_.fetch_add(chunk_);
+      if (b >= n_) return;
+      const int e = std::min(n_, b + chunk_);
+      for (int i = b; i < e; ++i) (*fn_)(i);
+    }
+  }
+  void loop() {
+    unsigned seen = 0;
+    for (;;) {
+      {
+        std::unique_lock<std::mutex> lk(mu_);
+        cv_.wait(lk, [&] { return stop_ || gen_ != seen; });
+        if (stop_) return;
+        seen = gen_;
+      }
+      work();
+      std::lock_guard<std::mutex> lk(mu_);
+      if (--active_ == 0) done_cv_.notify_one();
+    }
+  }
+  std::vector<std::thread> workers_;
+  std::mutex run_mu_, mu_;
+  std::condition_variable cv_, done_cv_;
+  const std::function<void(int)>* fn_ = nullptr;
+  int n_ = 0, chunk_ = 1, active_ = 0;
+  unsigned gen_ = 0;
+  bool stop_ = false;
+  std::atomic<int> next_{0};
+};
+
 // Work of one context at one level: the boxes it compresses, prepared on the host.
 struct LevelPrep {
   std::vector<int> ids;          // all boxes of the level
@@ -604,35 +689,27 @@ void prepare_level(rs_ctx* c, int l, const std::vector<int>& ids, const std::vec
   geo_of(c, g);
   P = LevelPrep();
   P.ids = ids;
-  std::vector<std::vector<int>> Is(ids.size());
-  std::vector<std::vector<ChildSrc>> srcs(ids.size());
-  for (size_t t = 0; t < ids.size(); ++t) box_unknowns(c, ids[t], Is[t], &srcs[t]);
+  const int nids = (int)ids.size();
+  std::vector<std::vector<int>> Is(nids);
+  std::vector<std::vector<ChildSrc>> srcs(nids);
+  HostPool& pool = HostPool::instance();
+  pool.run(nids, [&](int t) { box_unknowns(c, ids[t], Is[t], &srcs[t]); });
   // position of each box of this level in ids (-1: other levels)
   std::vector<int>& pos_of = c->lvl_pos;
   pos_of.assign(c->boxes.size(), -1);
-  for (size_t t = 0; t < ids.size(); ++t) pos_of[ids[t]] = (int)t;
-  std::vector<int> dofs, fint;
-  std::vector<ChildSrc> src_all;
-  std::vector<int> soff;
-  size_t totM = 0, totN2 = 0, totArena = 0, totScr = 0;
-  std::vector<int> F;
-  for (size_t t = 0; t < ids.size(); ++t) {
+  for (int t = 0; t < nids; ++t) pos_of[ids[t]] = t;
+  // near field F_int of every box (active unknowns strictly inside the proxy
+  // circle, not in I_B) and whether an update can keep its factors; boxes are
+  // independent here
+  std::vector<std::vector<int>> Fs(nids);
+  std::vector<char> keep(nids, 0);
+  pool.run(nids, [&](int t) {
+    if (Is[t].empty()) return;
     const int b = ids[t];
     const Box& B = c->boxes[b];
-    BoxFac& f = c->fac[b];
-    f.level = l;
-    f.I = Is[t];
-    f.n = (int)f.I.size();
-    f.active = f.n > 0;
-    if (f.n == 0) {
-      f.k = 0;
-      f.perm.clear();
-      continue;
-    }
-    // near field F_int: active unknowns strictly inside the proxy circle, not in I_B
     const double rp = prm.proxy_ratio * B.side;
     const double rp2 = rp * rp;
-    F.clear();
+    std::vector<int>& F = Fs[t];
     auto take = [&](const std::vector<int>& cand) {
       for (int d : cand) {
         if (!active[d]) continue;
@@ -645,7 +722,27 @@ void prepare_level(rs_ctx* c, int l, const std::vector<int>& ids, const std::vec
       if (pos_of[q] >= 0) take(Is[pos_of[q]]);
     for (int q : B.near_leaf) take(c->boxes[q].dofs);
     std::sort(F.begin(), F.end());
-    if (c->old && !compress_needed(c, b, F)) {
+    if (c->old && !compress_needed(c, b, F)) keep[t] = 1;
+  });
+  std::vector<int> dofs, fint;
+  std::vector<ChildSrc> src_all;
+  std::vector<int> soff;
+  size_t totM = 0, totN2 = 0, totArena = 0, totScr = 0;
+  for (int t = 0; t < nids; ++t) {
+    const int b = ids[t];
+    const Box& B = c->boxes[b];
+    BoxFac& f = c->fac[b];
+    f.level = l;
+    f.I = std::move(Is[t]);
+    f.n = (int)f.I.size();
+    f.active = f.n > 0;
+    if (f.n == 0) {
+      f.k = 0;
+      f.perm.clear();
+      continue;
+    }
+    const std::vector<int>& F = Fs[t];
+    if (keep[t]) {
       // every input of this box's compression is unchanged: keep its factors
       const OldState& O = *c->old;
       const BoxFac& of = O.fac[O.by_key.at(BoxKey{B.level, B.ix, B.iy})];
@@ -2038,6 +2135,51 @@ rs_status rs_apply(rs_ctx* c, int ncols, const double* x, double* y) {
     launch_from_rows(c->d_res.as<double>(), (int)ns, ncols, c->d_f.as<double>(), (int)ns, c->stream);
     HIP_CHECK(hipMemcpyAsync(y, c->d_f.p, ns * ncols * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIP_CHECK(hipStreamSynchronize(c->stream));
+    resolve_timers(c);
+    return RS_OK;
+  } catch (const RsError& e) {
+    return fail(c, e);
+  }
+}
+
+rs_status rs_evaluate(rs_ctx* c, int n_targets, const double* targets_xy, int ncols, const double* x,
+                      double* u) {
+  if (!c) return RS_ERR_ARG;
+  try {
+    if (n_targets <= 0 || ncols <= 0 || !targets_xy || !x || !u)
+      throw RsError{RS_ERR_ARG, "bad n_targets or ncols, or NULL pointer"};
+    if (!finite_all(targets_xy, 2 * (size_t)n_targets)) throw RsError{RS_ERR_ARG, "non-finite target"};
+    HIP_CHECK(hipSetDevice(c->device));
+    hipStream_t s = c->stream;
+    const int ns = 2 * c->N + 3 * c->p;
+    const int nt = n_targets;
+    std::vector<double> tx(nt), ty(nt);
+    for (int t = 0; t < nt; ++t) {
+      tx[t] = targets_xy[2 * t];
+      ty[t] = targets_xy[2 * t + 1];
+    }
+    upload(c->d_evx, tx, s);
+    upload(c->d_evy, ty, s);
+    c->d_f.ensure((size_t)ns * ncols * sizeof(double));
+    c->d_c.ensure((size_t)ns * ncols * sizeof(double));
+    c->d_res.ensure((size_t)ns * ncols * sizeof(double));
+    c->d_evu.ensure((size_t)2 * nt * ncols * sizeof(double));
+    c->d_evpart.ensure(std::max<size_t>(eval_scratch_doubles(c->N, nt, ncols), 1) * sizeof(double));
+    HIP_CHECK(hipMemcpyAsync(c->d_f.p, x, (size_t)ns * ncols * sizeof(double), hipMemcpyHostToDevice, s));
+    launch_to_rows(c->d_f.as<double>(), ns, ns, ncols, c->d_c.as<double>(), s);
+    const int cfg = apply_config_for(c, ncols, c->d_c.as<double>(), c->d_res.as<double>());
+    Geo g;
+    geo_of(c, g);
+    {
+      KTimer kt_(c, "evaluate");
+      launch_evaluate(g, c->d_hole.as<double>(), c->p, c->d_evx.as<double>(), c->d_evy.as<double>(), nt,
+                      c->d_c.as<double>(), ncols, c->d_evu.as<double>(), c->d_evpart.as<double>(), cfg, s);
+    }
+    c->d_res.ensure((size_t)2 * nt * ncols * sizeof(double));
+    launch_from_rows(c->d_evu.as<double>(), 2 * nt, ncols, c->d_res.as<double>(), 2 * nt, s);
+    HIP_CHECK(hipGetLastError());
+    HIP_CHECK(hipMemcpyAsync(u, c->d_res.p, (size_t)2 * nt * ncols * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
     resolve_timers(c);
     return RS_OK;
   } catch (const RsError& e) {

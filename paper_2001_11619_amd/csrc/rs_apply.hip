@@ -37,8 +37,12 @@ __device__ __forceinline__ bool apply_skipped(const int* skip, int max_iters) {
   return skip && (skip[0] != 0 || skip[1] >= max_iters);
 }
 
+// Targets (tx, ty), nt of them: the boundary nodes themselves for the
+// operator apply, arbitrary points for the evaluation of the velocity.
 template <int NC, int T>
-__global__ __launch_bounds__(kApplyThreads) void k_apply_pairs(Geo g, const double* __restrict__ x,
+__global__ __launch_bounds__(kApplyThreads) void k_apply_pairs(Geo g, const double* __restrict__ tx,
+                                                               const double* __restrict__ ty, int nt,
+                                                               const double* __restrict__ x,
                                                                int ncols, int chunk,
                                                                double* __restrict__ part,
                                                                const int* skip, int max_iters) {
@@ -56,8 +60,8 @@ __global__ __launch_bounds__(kApplyThreads) void k_apply_pairs(Geo g, const doub
 #pragma unroll
   for (int u = 0; u < T; ++u) {
     const int i = ib + u * kApplyThreads;
-    xi[u] = i < N ? g.x[i] : 0.0;
-    yi[u] = i < N ? g.y[i] : 0.0;
+    xi[u] = i < nt ? tx[i] : 0.0;
+    yi[u] = i < nt ? ty[i] : 0.0;
 #pragma unroll
     for (int q = 0; q < NC; ++q) { ax[u][q] = 0.0; ay[u][q] = 0.0; }
   }
@@ -98,11 +102,11 @@ __global__ __launch_bounds__(kApplyThreads) void k_apply_pairs(Geo g, const doub
       }
     }
   }
-  double* out = part + (size_t)blockIdx.y * 2 * N * ncols;
+  double* out = part + (size_t)blockIdx.y * 2 * nt * ncols;
 #pragma unroll
   for (int u = 0; u < T; ++u) {
     const int i = ib + u * kApplyThreads;
-    if (i >= N) continue;
+    if (i >= nt) continue;
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
       if (q < nq) {
@@ -173,6 +177,40 @@ __global__ void k_apply_sum(Geo g, double lam, const double* hole_xy, int p, con
   y[(size_t)(2 * i + 1) * ncols + q] = ay;
 }
 
+// Velocity at targets: u[2 t + a] = sum over source chunks (fixed order) of
+// the double-layer sums + (H lambda)(target): the Stokeslet and rotlet of
+// every hole (eq. forwardeq).  x holds [mu; lambda] in the rows layout.
+__global__ void k_eval_sum(Geo g, const double* tx, const double* ty, int nt, const double* hole_xy,
+                           int p, const double* x, int ncols, const double* part, int nchunk,
+                           double* u) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)nt * ncols) return;
+  const int i = (int)(t / ncols), q = (int)(t % ncols);
+  const size_t stride = (size_t)2 * nt * ncols;
+  double ax = 0.0, ay = 0.0;
+  for (int c = 0; c < nchunk; ++c) {
+    ax += part[c * stride + (size_t)(2 * i) * ncols + q];
+    ay += part[c * stride + (size_t)(2 * i + 1) * ncols + q];
+  }
+  const double xi = tx[i], yi = ty[i];
+  const size_t base = (size_t)2 * g.N;
+  for (int h = 0; h < p; ++h) {
+    const double rx = xi - hole_xy[2 * h], ry = yi - hole_xy[2 * h + 1];
+    const double r2 = rx * rx + ry * ry;
+    const double lg = -0.5 * log(r2);
+    const double sxx = kInv4Pi * (lg + rx * rx / r2), sxy = kInv4Pi * (rx * ry / r2);
+    const double syy = kInv4Pi * (lg + ry * ry / r2);
+    const double rotx = kInv4Pi * (-ry) / r2, roty = kInv4Pi * rx / r2;
+    const double a1 = x[(base + 3 * h) * ncols + q];
+    const double a2 = x[(base + 3 * h + 1) * ncols + q];
+    const double b = x[(base + 3 * h + 2) * ncols + q];
+    ax += sxx * a1 + sxy * a2 + rotx * b;
+    ay += sxy * a1 + syy * a2 + roty * b;
+  }
+  u[(size_t)(2 * i) * ncols + q] = ax;
+  u[(size_t)(2 * i + 1) * ncols + q] = ay;
+}
+
 // Rows of Psi^T x - lambda: one block per (hole, mode), fixed-order sums.
 __global__ __launch_bounds__(kBlock) void k_apply_psi(Geo g, const int* curve_id, int p,
                                                       const double* x, int ncols, double* y,
@@ -220,6 +258,20 @@ int apply_chunk_len(int N) {
 }
 }  // namespace
 
+// The double-layer pair sums of one shape; grid = (target tiles, chunks, column chunks).
+static void launch_pairs(Geo g, const double* tx, const double* ty, int nt, const double* x, int ncols,
+                  int chunk, double* part, const int* skip, int max_iters, int cfg, dim3 grid,
+                  hipStream_t s) {
+  const ApplyShape sh = kApplyShapes[cfg];
+#define RS_APPLY(NC, T)                                                                             \
+  if (sh.nc == NC && sh.t == T)                                                                     \
+    hipLaunchKernelGGL((k_apply_pairs<NC, T>), grid, dim3(kApplyThreads), 0, s, g, tx, ty, nt, x, ncols, \
+                       chunk, part, skip, max_iters);
+  RS_APPLY(4, 2) RS_APPLY(4, 4) RS_APPLY(8, 1) RS_APPLY(8, 2) RS_APPLY(8, 4) RS_APPLY(16, 1)
+  RS_APPLY(16, 2)
+#undef RS_APPLY
+}
+
 int apply_config_count() { return kNumApplyShapes; }
 
 bool apply_config_valid(int cfg, int ncols) {
@@ -253,19 +305,32 @@ void launch_apply_operator(Geo g, const int* curve_id, const double* hole_xy, in
   const int nchunk = (g.N + chunk - 1) / chunk;
   double* nsum = part + (size_t)nchunk * 2 * g.N * ncols;
   dim3 grid(blocks_for(g.N, kApplyThreads * sh.t), nchunk, blocks_for(ncols, sh.nc));
-#define RS_APPLY(NC, T)                                                                         \
-  if (sh.nc == NC && sh.t == T)                                                                 \
-    hipLaunchKernelGGL((k_apply_pairs<NC, T>), grid, dim3(kApplyThreads), 0, s, g, x, ncols, chunk, \
-                       part, skip, max_iters);
-  RS_APPLY(4, 2) RS_APPLY(4, 4) RS_APPLY(8, 1) RS_APPLY(8, 2) RS_APPLY(8, 4) RS_APPLY(16, 1)
-  RS_APPLY(16, 2)
-#undef RS_APPLY
+  launch_pairs(g, g.x, g.y, g.N, x, ncols, chunk, part, skip, max_iters, cfg, grid, s);
   hipLaunchKernelGGL(k_apply_nsum, dim3(ncols), dim3(kBlock), 0, s, g, x, ncols, nsum, skip, max_iters);
   hipLaunchKernelGGL(k_apply_sum, dim3(blocks_for((long long)g.N * ncols, kBlock)), dim3(kBlock), 0, s,
                      g, lam, hole_xy, p, x, ncols, part, nchunk, nsum, y, skip, max_iters);
   if (p > 0)
     hipLaunchKernelGGL(k_apply_psi, dim3(3 * p), dim3(kBlock), 0, s, g, curve_id, p, x, ncols, y, skip,
                        max_iters);
+}
+
+size_t eval_scratch_doubles(int N, int nt, int ncols) {
+  const int len = apply_chunk_len(N);
+  const int nch = (N + len - 1) / len;
+  return (size_t)nch * 2 * nt * ncols;
+}
+
+void launch_evaluate(Geo g, const double* hole_xy, int p, const double* tx, const double* ty, int nt,
+                     const double* x, int ncols, double* u, double* part, int cfg, hipStream_t s) {
+  if (nt == 0 || ncols == 0) return;
+  if (!apply_config_valid(cfg, ncols)) cfg = apply_default_config(ncols);
+  const ApplyShape sh = kApplyShapes[cfg];
+  const int chunk = apply_chunk_len(g.N);
+  const int nchunk = (g.N + chunk - 1) / chunk;
+  dim3 grid(blocks_for(nt, kApplyThreads * sh.t), nchunk, blocks_for(ncols, sh.nc));
+  launch_pairs(g, tx, ty, nt, x, ncols, chunk, part, nullptr, 0, cfg, grid, s);
+  hipLaunchKernelGGL(k_eval_sum, dim3(blocks_for((long long)nt * ncols, kBlock)), dim3(kBlock), 0, s, g,
+                     tx, ty, nt, hole_xy, p, x, ncols, part, nchunk, u);
 }
 
 }  // namespace rs

@@ -11,20 +11,28 @@ namespace {
 
 // ---- factorization kernels -------------------------------------------------
 
+// Thread per row of M_B; the box's columns (source node geometry and
+// component) are staged in LDS 256 at a time, so the loop over columns reads
+// no global memory.
 __global__ __launch_bounds__(kBlock) void k_assemble_M(const LevelBox* boxes, int n_proxy,
                                                        double ratio) {
+  __shared__ double sx[kBlock], sy[kBlock], snx[kBlock], sny[kBlock], sw[kBlock];
+  __shared__ int sj[kBlock];
   const LevelBox& B = boxes[blockIdx.x];
   const int i = blockIdx.y * blockDim.x + threadIdx.x;
   const int m = B.m, n = B.n, nF = B.nF;
-  if (i >= m || n == 0) return;
+  if (n == 0 || blockIdx.y * blockDim.x >= m) return;   // uniform per block
+  const bool live = i < m;
   const int* I = B.dofs;
   const Geo& g = B.geo;
   const int np2 = 2 * n_proxy;
   const double rp = ratio * B.side;
   const double wp = 2.0 * kPi * rp / n_proxy;
-  int type, f = 0, pa = 0;
+  int type = 6, f = 0, pa = 0;
   double px = 0, py = 0, pnx = 0, pny = 0;
-  if (i < nF) {
+  if (!live) {
+    type = 6;
+  } else if (i < nF) {
     type = 0;
     f = B.fint[i];
   } else if (i < 2 * nF) {
@@ -45,20 +53,54 @@ __global__ __launch_bounds__(kBlock) void k_assemble_M(const LevelBox* boxes, in
     type = 5 + (i - 2 * nF - 3 * np2);
   }
   const int fj = f >> 1, fc = f & 1;
-  for (int c = 0; c < n; ++c) {
-    const int d = I[c];
-    const int j = d >> 1, jc = d & 1;
-    double v;
-    switch (type) {
-      case 0: v = op_entry(g, fj, fc, j, jc, 0.0); break;
-      case 1: v = op_entry(g, j, jc, fj, fc, 0.0); break;
-      case 2: v = dl_entry(px - g.x[j], py - g.y[j], g.nx[j], g.ny[j], g.w[j], pa, jc); break;
-      case 3: v = dl_entry(g.x[j] - px, g.y[j] - py, pnx, pny, wp, jc, pa); break;
-      case 4: v = sl_entry(g.x[j] - px, g.y[j] - py, wp, jc, pa); break;
-      case 5: v = g.w[j] * (jc ? g.ny[j] : g.nx[j]); break;
-      default: v = jc ? g.ny[j] : g.nx[j]; break;
+  double fx = 0, fy = 0, fnx = 0, fny = 0, fw = 0;
+  if (type <= 1) {
+    fx = g.x[fj];
+    fy = g.y[fj];
+    fnx = g.nx[fj];
+    fny = g.ny[fj];
+    fw = g.w[fj];
+  }
+  const double fn_c = fc ? fny : fnx;
+  for (int c0 = 0; c0 < n; c0 += kBlock) {
+    const int cnt = min(kBlock, n - c0);
+    __syncthreads();
+    if ((int)threadIdx.x < cnt) {
+      const int d = I[c0 + threadIdx.x];
+      const int j = d >> 1;
+      sj[threadIdx.x] = d;
+      sx[threadIdx.x] = g.x[j];
+      sy[threadIdx.x] = g.y[j];
+      snx[threadIdx.x] = g.nx[j];
+      sny[threadIdx.x] = g.ny[j];
+      sw[threadIdx.x] = g.w[j];
     }
-    B.M[(size_t)c * m + i] = v;
+    __syncthreads();
+    if (!live) continue;
+    double* col = B.M + (size_t)c0 * m + i;
+    for (int cc = 0; cc < cnt; ++cc) {
+      const int d = sj[cc];
+      const int j = d >> 1, jc = d & 1;
+      const double xj = sx[cc], yj = sy[cc], nxj = snx[cc], nyj = sny[cc], wj = sw[cc];
+      const double nj_c = jc ? nyj : nxj;
+      double v;
+      switch (type) {
+        case 0:   // target: near-field unknown f, source: column unknown (op_entry)
+          if (fj == j) v = op_entry(g, fj, fc, j, jc, 0.0);
+          else v = dl_entry(fx - xj, fy - yj, nxj, nyj, wj, fc, jc) + fn_c * (wj * nj_c);
+          break;
+        case 1:   // target: column unknown, source: near-field unknown f
+          if (fj == j) v = op_entry(g, j, jc, fj, fc, 0.0);
+          else v = dl_entry(xj - fx, yj - fy, fnx, fny, fw, jc, fc) + nj_c * (fw * fn_c);
+          break;
+        case 2: v = dl_entry(px - xj, py - yj, nxj, nyj, wj, pa, jc); break;
+        case 3: v = dl_entry(xj - px, yj - py, pnx, pny, wp, jc, pa); break;
+        case 4: v = sl_entry(xj - px, yj - py, wp, jc, pa); break;
+        case 5: v = wj * nj_c; break;
+        default: v = nj_c; break;
+      }
+      col[(size_t)cc * m] = v;
+    }
   }
 }
 

@@ -196,5 +196,10 @@ void apply_config_name(int cfg, char* buf, int len);
 void launch_apply_operator(Geo g, const int* curve_id, const double* hole_xy, int p,
                            double lam, const double* x, int ncols, double* y,
                            double* part, const int* skip, int max_iters, int cfg, hipStream_t s);
+// Velocity u = D mu + H lambda at nt target points (tx, ty); x, u rows layout
+// ((2N + 3p) x ncols and 2 nt x ncols); part: eval_scratch_doubles(N, nt, ncols).
+size_t eval_scratch_doubles(int N, int nt, int ncols);
+void launch_evaluate(Geo g, const double* hole_xy, int p, const double* tx, const double* ty, int nt,
+                     const double* x, int ncols, double* u, double* part, int cfg, hipStream_t s);
 
 }  // namespace rs

@@ -1,0 +1,88 @@
+"""Velocity at points off the boundary, u = D mu + H lambda (eq. forwardeq),
+through rs_evaluate.
+
+Parity: the GPU evaluation equals the oracle's (tests/test_oracle_dense.py pins
+that one against exact point-force flows and Couette flow) to 1e-12 relative,
+for several column counts, a ragged target count and every apply kernel shape.
+End to end: the GPU-solved (refined) density of an exterior point-force problem
+reproduces the exact interior velocity, as the dense oracle does."""
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from oracle import stokes
+from workloads import (boundary_data, exterior_forces_for_geometry, stokeslet_velocity,
+                       workload_circle10_8holes, workload_small)
+
+
+def _solver(g, **kw):
+    import torch
+
+    assert torch.cuda.is_available()
+    from paper_2001_11619_amd import RSSolver
+
+    return RSSolver.from_geometry(g, **kw)
+
+
+def _fluid_points(g, n, seed, margin):
+    """Random points of the fluid region at least `margin` (in the curves'
+    own scale) inside the outer circle and outside every hole."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    R = g.curves[0].a
+    out = []
+    while len(out) < n:
+        p = rng.uniform(-R, R, size=2)
+        if np.hypot(*p) > R - margin:
+            continue
+        ok = True
+        for c in g.curves[1:]:
+            cs, sn = np.cos(c.theta), np.sin(c.theta)
+            d = p - np.array([c.cx, c.cy])
+            lx, ly = cs * d[0] + sn * d[1], -sn * d[0] + cs * d[1]
+            if (lx / (c.a + margin)) ** 2 + (ly / (c.b + margin)) ** 2 < 1.0:
+                ok = False
+                break
+        if ok:
+            out.append(p)
+    return np.array(out)
+
+
+@pytest.mark.parametrize("ncols,shape", [(1, -1), (3, -1), (11, -1), (11, 0), (11, 6)])
+def test_evaluate_matches_oracle(ncols, shape):
+    g = workload_small(seed=13, n_outer=300, n_holes=2, nodes_per_hole=70, radius=3.0)
+    rng = np.random.Generator(np.random.PCG64(ncols))
+    X = rng.standard_normal((g.n_system, ncols))
+    tg = _fluid_points(g, 333, seed=2, margin=0.3)
+    s = _solver(g, leaf_size=32, apply_shape=shape)
+    U = s.evaluate(tg, X)
+    Uo = stokes.evaluate_interior(g, X, tg)
+    assert U.shape == Uo.shape
+    assert np.abs(U - Uo).max() <= 1e-12 * np.abs(Uo).max()
+
+
+def test_evaluate_point_force_flow_circle10_8holes():
+    """The 12288-node workload: refined GPU solve of exterior point forces, then
+    the velocity at 500 interior points equals the exact flow."""
+    g = workload_circle10_8holes()
+    cols = exterior_forces_for_geometry(g, 4, seed=2)
+    f = boundary_data(g, cols)
+    s = _solver(g, tol=1e-10, refine_max=20, refine_tol=1e-12).factor()
+    x, res = s.solve(f, residual=True)
+    assert np.all(res <= 1e-12)
+    tg = _fluid_points(g, 500, seed=4, margin=0.5)
+    U = s.evaluate(tg, x)
+    for c, forces in enumerate(cols):
+        ex = stokeslet_velocity(tg, forces)
+        assert np.abs(U[:, :, c] - ex).max() < 1e-8 * np.abs(ex).max()
+
+
+def test_evaluate_rejects_bad_input():
+    from paper_2001_11619_amd import RSError
+
+    g = workload_small(seed=13, n_outer=300, n_holes=2, nodes_per_hole=70, radius=3.0)
+    s = _solver(g, leaf_size=32)
+    with pytest.raises(RSError) as e:
+        s.evaluate(np.array([[np.nan, 0.0]]), np.zeros(g.n_system))
+    assert e.value.name == "RS_ERR_ARG"
