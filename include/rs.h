@@ -148,6 +148,21 @@ rs_status rs_update_moved_nodes(rs_ctx* ctx, int n_moved, const int* idx, const 
  * and carries the message. */
 rs_status rs_factor_batch(rs_ctx** ctxs, int n);
 
+/* rs_update_moved_nodes for n contexts together (the related geometries of one
+ * finite-difference step of a shape optimization, Section 4's Scheme A): every
+ * context's nodes are moved, then the boxes that need recompression in all
+ * contexts share one launch per kernel and level.  Entry i of each array
+ * holds context i's arguments with the meaning of rs_update_moved_nodes;
+ * hole_xy may be NULL (no context moves its hole points) or hold NULL
+ * entries.  The contexts must satisfy rs_factor_batch's conditions.  All
+ * inputs are checked before anything changes: on a bad input nothing is
+ * modified and the first bad context's status is returned (its message in
+ * that context).  Each context ends up bitwise as after its own update. */
+rs_status rs_update_moved_nodes_batch(rs_ctx** ctxs, int n, const int* n_moved, const int* const* idx,
+                                      const double* const* xy, const double* const* normal,
+                                      const double* const* weight, const double* const* curvature,
+                                      const double* const* hole_xy);
+
 /* rs_solve_dev for each of n factored contexts (f_dev[i], x_dev[i] laid out
  * as for rs_solve_dev of context i).  Refined solves with solve_graph = 1 are
  * interleaved: every context's first graph launch is queued before the first

@@ -95,6 +95,8 @@ def load_library():
     lib.rs_dense_inverse.argtypes = [h, ctypes.c_int, dp, dp]
     lib.rs_evaluate.argtypes = [h, ctypes.c_int, dp, ctypes.c_int, dp, dp]
     lib.rs_factor_batch.argtypes = [P(h), ctypes.c_int]
+    lib.rs_update_moved_nodes_batch.argtypes = [P(h), ctypes.c_int, ip, P(ip), P(dp), P(dp), P(dp), P(dp),
+                                                P(dp)]
     lib.rs_solve_batch.argtypes = [P(h), ctypes.c_int, ctypes.c_int, P(vp), P(vp)]
     lib.rs_set_kernel_timing.argtypes = [h, ctypes.c_int]
     lib.rs_get_kernel_times.argtypes = [h, ctypes.c_int, P(KernelTime), ip, ctypes.c_int]
@@ -105,7 +107,7 @@ def load_library():
     for name in ("rs_build_tree", "rs_factor", "rs_solve", "rs_solve_dev", "rs_update_moved_nodes",
                  "rs_set_stream", "rs_get_stats", "rs_get_boxes", "rs_get_skeleton", "rs_apply",
                  "rs_dense_inverse", "rs_evaluate", "rs_set_kernel_timing", "rs_get_kernel_times",
-                 "rs_factor_batch", "rs_solve_batch"):
+                 "rs_factor_batch", "rs_solve_batch", "rs_update_moved_nodes_batch"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -119,7 +121,7 @@ def exported_symbols():
                  "rs_update_moved_nodes", "rs_set_stream", "rs_get_stats", "rs_get_boxes",
                  "rs_get_skeleton", "rs_apply", "rs_dense_inverse", "rs_evaluate",
                  "rs_set_kernel_timing", "rs_get_kernel_times", "rs_factor_batch", "rs_solve_batch",
-                 "rs_destroy", "rs_last_error"):
+                 "rs_update_moved_nodes_batch", "rs_destroy", "rs_last_error"):
         if hasattr(lib, name):
             out.append(name)
     return out
@@ -147,6 +149,40 @@ def factor_batch(solvers):
     st = lib.rs_factor_batch(arr, n)
     if st != 0:
         raise RSError(st, lib.rs_last_error(solvers[0]._h).decode())
+
+
+def update_moved_nodes_batch(solvers, moves):
+    """rs_update_moved_nodes for several contexts in shared launches; moves[i] =
+    (idx, xy, normal, weight, curvature[, hole_xy]) for solvers[i]."""
+    lib = load_library()
+    n = len(solvers)
+    keep = []
+    idx_p = (ctypes.POINTER(ctypes.c_int) * n)()
+    arr = [(ctypes.POINTER(ctypes.c_double) * n)() for _ in range(5)]
+    counts = np.zeros(n, np.int32)
+    any_hole = False
+    for i, mv in enumerate(moves):
+        idx = np.ascontiguousarray(mv[0], dtype=np.int32)
+        m = idx.size
+        vals = [np.ascontiguousarray(mv[1], dtype=np.float64).reshape(m, 2),
+                np.ascontiguousarray(mv[2], dtype=np.float64).reshape(m, 2),
+                np.ascontiguousarray(mv[3], dtype=np.float64).reshape(m),
+                np.ascontiguousarray(mv[4], dtype=np.float64).reshape(m)]
+        hole = None
+        if len(mv) > 5 and mv[5] is not None:
+            hole = np.ascontiguousarray(mv[5], dtype=np.float64).reshape(-1, 2)
+            any_hole = True
+        vals.append(hole)
+        keep.append((idx, vals))
+        counts[i] = m
+        idx_p[i] = _iptr(idx)
+        for k in range(5):
+            arr[k][i] = _dptr(vals[k]) if vals[k] is not None else ctypes.POINTER(ctypes.c_double)()
+    hs = (ctypes.c_void_p * n)(*[sv._h.value for sv in solvers])
+    st = lib.rs_update_moved_nodes_batch(hs, n, _iptr(counts), idx_p, arr[0], arr[1], arr[2], arr[3],
+                                         arr[4] if any_hole else None)
+    if st != 0:
+        raise RSError(st, "; ".join(lib.rs_last_error(sv._h).decode() for sv in solvers))
 
 
 def solve_batch(solvers, f_devs, x_devs):

@@ -2217,50 +2217,71 @@ rs_status rs_dense_inverse(rs_ctx* c, int n, const double* a, double* ainv) {
   }
 }
 
+}  // extern "C"
+
+namespace {
+
+// Checks of one update's inputs (nothing is changed).
+void validate_update(const rs_ctx* c, int n_moved, const int* idx, const double* xy, const double* normal,
+                     const double* weight, const double* curvature, const double* hole_xy) {
+  if (!c->factored) throw RsError{RS_ERR_STATE, "rs_update_moved_nodes before rs_factor"};
+  if (n_moved < 0 || (n_moved > 0 && !idx)) throw RsError{RS_ERR_ARG, "bad moved-node list"};
+  if (n_moved) validate_nodes(n_moved, xy, normal, weight, curvature);
+  std::vector<char> seen(c->N, 0);
+  for (int t = 0; t < n_moved; ++t) {
+    if (idx[t] < 0 || idx[t] >= c->N) throw RsError{RS_ERR_ARG, "moved index out of range"};
+    if (seen[idx[t]]) throw RsError{RS_ERR_ARG, "duplicate moved index"};
+    seen[idx[t]] = 1;
+    if (!inside_root(c, xy[2 * t], xy[2 * t + 1]))
+      throw RsError{RS_ERR_OUT_OF_ROOT, "moved node leaves the root square"};
+  }
+  if (hole_xy && !finite_all(hole_xy, 2 * (size_t)c->p)) throw RsError{RS_ERR_ARG, "non-finite hole point"};
+}
+
+// Moves the nodes, keeps the previous factorization in O (boxes matched by
+// position) and rebuilds the tree on the same root square; the factorization
+// that follows reads O through c->old.
+void begin_update(rs_ctx* c, int n_moved, const int* idx, const double* xy, const double* normal,
+                  const double* weight, const double* curvature, const double* hole_xy, OldState& O) {
+  for (int t = 0; t < n_moved; ++t) {
+    const int i = idx[t];
+    c->x[i] = xy[2 * t];
+    c->y[i] = xy[2 * t + 1];
+    c->nx[i] = normal[2 * t];
+    c->ny[i] = normal[2 * t + 1];
+    c->w[i] = weight[t];
+    c->kap[i] = curvature[t];
+  }
+  if (hole_xy) c->hole.assign(hole_xy, hole_xy + 2 * (size_t)c->p);
+  HIP_CHECK(hipSetDevice(c->device));
+  O.boxes = std::move(c->boxes);
+  O.fac = std::move(c->fac);
+  for (size_t b = 0; b < O.boxes.size(); ++b)
+    O.by_key[BoxKey{O.boxes[b].level, O.boxes[b].ix, O.boxes[b].iy}] = (int)b;
+  O.moved.assign(c->N, 0);
+  for (int t = 0; t < n_moved; ++t) O.moved[idx[t]] = 1;
+  c->prm.has_root = 1;
+  c->prm.root[0] = c->root_cx;
+  c->prm.root[1] = c->root_cy;
+  c->prm.root[2] = c->root_side;
+  build_tree(c);
+  upload_geometry(c);
+  c->old = &O;
+}
+
+}  // namespace
+
+extern "C" {
+
 rs_status rs_update_moved_nodes(rs_ctx* c, int n_moved, const int* idx, const double* xy,
                                 const double* normal, const double* weight, const double* curvature,
                                 const double* hole_xy) {
   if (!c) return RS_ERR_ARG;
   try {
-    if (!c->factored) throw RsError{RS_ERR_STATE, "rs_update_moved_nodes before rs_factor"};
-    if (n_moved < 0 || (n_moved > 0 && !idx)) throw RsError{RS_ERR_ARG, "bad moved-node list"};
-    if (n_moved) validate_nodes(n_moved, xy, normal, weight, curvature);
-    std::vector<char> seen(c->N, 0);
-    for (int t = 0; t < n_moved; ++t) {
-      if (idx[t] < 0 || idx[t] >= c->N) throw RsError{RS_ERR_ARG, "moved index out of range"};
-      if (seen[idx[t]]) throw RsError{RS_ERR_ARG, "duplicate moved index"};
-      seen[idx[t]] = 1;
-      if (!inside_root(c, xy[2 * t], xy[2 * t + 1]))
-        throw RsError{RS_ERR_OUT_OF_ROOT, "moved node leaves the root square"};
-    }
-    if (hole_xy && !finite_all(hole_xy, 2 * (size_t)c->p)) throw RsError{RS_ERR_ARG, "non-finite hole point"};
+    validate_update(c, n_moved, idx, xy, normal, weight, curvature, hole_xy);
     auto t0 = std::chrono::steady_clock::now();
-    for (int t = 0; t < n_moved; ++t) {
-      const int i = idx[t];
-      c->x[i] = xy[2 * t];
-      c->y[i] = xy[2 * t + 1];
-      c->nx[i] = normal[2 * t];
-      c->ny[i] = normal[2 * t + 1];
-      c->w[i] = weight[t];
-      c->kap[i] = curvature[t];
-    }
-    if (hole_xy) c->hole.assign(hole_xy, hole_xy + 2 * (size_t)c->p);
-    HIP_CHECK(hipSetDevice(c->device));
-    // the tree is rebuilt on the same root square; boxes are matched by position
     OldState O;
-    O.boxes = std::move(c->boxes);
-    O.fac = std::move(c->fac);
-    for (size_t b = 0; b < O.boxes.size(); ++b)
-      O.by_key[BoxKey{O.boxes[b].level, O.boxes[b].ix, O.boxes[b].iy}] = (int)b;
-    O.moved.assign(c->N, 0);
-    for (int t = 0; t < n_moved; ++t) O.moved[idx[t]] = 1;
-    c->prm.has_root = 1;
-    c->prm.root[0] = c->root_cx;
-    c->prm.root[1] = c->root_cy;
-    c->prm.root[2] = c->root_side;
-    build_tree(c);
-    upload_geometry(c);
-    c->old = &O;
+    begin_update(c, n_moved, idx, xy, normal, weight, curvature, hole_xy, O);
     try {
       do_factor(c);
     } catch (...) {
@@ -2274,6 +2295,56 @@ rs_status rs_update_moved_nodes(rs_ctx* c, int n_moved, const int* idx, const do
     c->factored = false;
     return fail(c, e);
   }
+}
+
+rs_status rs_update_moved_nodes_batch(rs_ctx** ctxs, int n, const int* n_moved, const int* const* idx,
+                                      const double* const* xy, const double* const* normal,
+                                      const double* const* weight, const double* const* curvature,
+                                      const double* const* hole_xy) {
+  if (!ctxs || n <= 0 || !n_moved || !idx || !xy || !normal || !weight || !curvature) return RS_ERR_ARG;
+  for (int i = 0; i < n; ++i) {
+    if (!ctxs[i]) return RS_ERR_ARG;
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == ctxs[i]) return fail(ctxs[i], RsError{RS_ERR_ARG, "a context appears twice in the batch"});
+    const rs_params& a = ctxs[0]->prm;
+    const rs_params& b = ctxs[i]->prm;
+    if (ctxs[i]->device != ctxs[0]->device)
+      return fail(ctxs[i], RsError{RS_ERR_ARG, "contexts of a batch must share the device"});
+    if (a.tol != b.tol || a.n_proxy != b.n_proxy || a.proxy_ratio != b.proxy_ratio || a.lambda != b.lambda ||
+        a.rcond_min != b.rcond_min || a.precision != b.precision)
+      return fail(ctxs[i], RsError{RS_ERR_ARG, "contexts of a batch must share lambda, tol, proxy, rcond and precision"});
+  }
+  for (int i = 0; i < n; ++i) {
+    try {
+      validate_update(ctxs[i], n_moved[i], idx[i], xy[i], normal[i], weight[i], curvature[i],
+                      hole_xy ? hole_xy[i] : nullptr);
+    } catch (const RsError& e) {
+      return fail(ctxs[i], e);
+    }
+  }
+  std::vector<rs_ctx*> cs(ctxs, ctxs + n);
+  std::vector<OldState> Os(n);
+  auto t0 = std::chrono::steady_clock::now();
+  try {
+    for (int i = 0; i < n; ++i)
+      begin_update(cs[i], n_moved[i], idx[i], xy[i], normal[i], weight[i], curvature[i],
+                   hole_xy ? hole_xy[i] : nullptr, Os[i]);
+    do_factor_multi(cs);
+  } catch (const RsError& e) {
+    rs_status st = RS_OK;
+    for (rs_ctx* c : cs) {
+      c->old = nullptr;
+      c->factored = false;
+      st = fail(c, e);
+    }
+    return st;
+  }
+  const double ms = 1e3 * seconds_since(t0);
+  for (rs_ctx* c : cs) {
+    c->old = nullptr;
+    c->stats.ms_update = ms;
+  }
+  return RS_OK;
 }
 
 rs_status rs_set_stream(rs_ctx* c, void* stream) {

@@ -91,3 +91,54 @@ def test_batch_factor_equals_single():
         f = boundary_data(g, exterior_forces_for_geometry(g, 2, seed=7))
         alone = _solver(g, leaf_size=32).factor()
         assert np.array_equal(s.solve(f), alone.solve(f))
+
+
+def test_update_batch_equals_single_updates():
+    """Several related geometries updated together (rs_update_moved_nodes_batch,
+    one launch per kernel and level across them; Scheme A of the paper's
+    optimization experiments): each context is bitwise the context updated on
+    its own, and equal to a fresh factorization of its new geometry."""
+    from paper_2001_11619_amd import update_moved_nodes_batch
+
+    base = random_holes_geometry(23, 6.0, 768, [192] * 5)
+    single, batch, moves, news = [], [], [], []
+    for i in range(4):
+        rng = np.random.Generator(np.random.PCG64(100 + i))
+        g2, moved = move_hole(base, 1 + i, rng, radius=6.0)
+        a = _solver(base, leaf_size=32).factor()
+        b = _solver(base, leaf_size=32).factor()
+        mv = _moved_args(g2, moved) + (g2.hole_xy,)
+        a.update_moved_nodes(*mv[:5], hole_xy=mv[5])
+        single.append(a)
+        batch.append(b)
+        moves.append(mv)
+        news.append(g2)
+    update_moved_nodes_batch(batch, moves)
+    root = tuple(single[0].boxes()["geom"][0])
+    for i in range(4):
+        f = boundary_data(news[i], exterior_forces_for_geometry(news[i], 2, seed=i))
+        xs = single[i].solve(f)
+        xb = batch[i].solve(f)
+        assert np.array_equal(xs, xb)
+        assert batch[i].stats()["boxes_recomputed"] == single[i].stats()["boxes_recomputed"]
+        g = news[i]
+        g.root = np.array(root)
+        fresh = _solver(g, leaf_size=32, root=root).factor()
+        assert np.array_equal(fresh.solve(f), xb)
+
+
+def test_update_batch_rejects_bad_input_atomically():
+    """An invalid move in one context of the batch changes no context."""
+    from paper_2001_11619_amd import RSError, update_moved_nodes_batch
+
+    g = random_holes_geometry(22, 6.0, 512, [128] * 3)
+    ss = [_solver(g, leaf_size=32).factor() for _ in range(2)]
+    f = boundary_data(g, exterior_forces_for_geometry(g, 1, seed=1))
+    x0 = [s.solve(f) for s in ss]
+    good = (np.array([3], np.int32), g.xy[3:4] * 1.001, g.normal[3:4], g.weight[3:4], g.curvature[3:4])
+    bad = (np.array([3], np.int32), np.array([[100.0, 0.0]]), g.normal[3:4], g.weight[3:4], g.curvature[3:4])
+    with pytest.raises(RSError) as e:
+        update_moved_nodes_batch(ss, [good, bad])
+    assert e.value.name == "RS_ERR_OUT_OF_ROOT"
+    for s, x in zip(ss, x0):
+        assert np.array_equal(s.solve(f), x)
