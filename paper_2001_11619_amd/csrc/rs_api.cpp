@@ -226,6 +226,7 @@ struct rs_ctx {
   DevBuf d_sboxes, d_sidx, d_ridx;
   std::vector<size_t> sbox_off;                 // offset of each level's boxes in d_sboxes
   int n_solve_boxes = 0;
+  int n_ridx = 0;                 // length of the concatenated R lists
   int all_maxr = 0;
   // solve work
   DevBuf d_f, d_c, d_v, d_sol, d_parts, d_rhs2, d_xout, d_res, d_frows, d_xs, d_r, d_dx,
@@ -1206,6 +1207,7 @@ void build_solve_meta(rs_ctx* c) {
     c->stats.factor_bytes += (long long)(3LL * sb.k * sb.r + 1LL * sb.r * sb.r) * 8;
   }
   c->n_solve_boxes = part;
+  c->n_ridx = (int)ridx.size();
   // border W slots
   const int p3 = 3 * c->p;
   if (p3) {
@@ -1221,6 +1223,10 @@ void build_solve_meta(rs_ctx* c) {
     }
     for (auto& lv : c->sboxes)
       for (auto& sb : lv) {
+        // the W blocks follow the order of the concatenated R lists (the
+        // gathered product for G relies on it)
+        if (pw != c->d_W.as<double>() + (size_t)sb.r_off * p3)
+          throw RsError{RS_ERR_DEVICE, "border W blocks out of the R-list order"};
         sb.W = pw;
         pw += (size_t)sb.r * p3;
         if (pwf) {
@@ -1308,28 +1314,26 @@ void factor_root(rs_ctx* c) {
     }
     sweep_all(c, c->d_Hh.as<double>(), p3, 0);
     sweep_all(c, c->d_Ph.as<double>(), p3, 1);
-    const int nsb = c->n_solve_boxes;
-    c->d_Gpart.ensure(std::max<size_t>((size_t)nsb * p3 * p3, 1) * sizeof(double));
-    long long scr_stride = (long long)2 * c->all_maxr * p3;
+    // W_B of every box, then G = sum_B (Psi^T V)_R W_B as one gathered product
+    const long long scr_stride = std::max<long long>((long long)c->all_maxr * p3, 1);
     int max_nb = 1;
     for (int l = 1; l <= c->L; ++l) max_nb = std::max(max_nb, level_count(c, l));
-    c->d_bscr.ensure(std::max<size_t>((size_t)max_nb * scr_stride, 1) * sizeof(double));
-    for (int l = c->L; l >= 1; --l) {
-      const int nb = level_count(c, l);
-      if (!nb) continue;
-      {
-        KTimer kt_(c, "border_box");
-        launch_border_box(level_sboxes(c, l), nb, c->d_ridx.as<int>(), c->d_Hh.as<double>(),
-                          c->d_Ph.as<double>(), p3, c->d_Gpart.as<double>(), c->d_bscr.as<double>(),
-                          scr_stride, s);
-      }
+    c->d_bscr.ensure((size_t)max_nb * scr_stride * sizeof(double));
+    {
+      KTimer kt_(c, "border_box");
+      for (int l = c->L; l >= 1; --l)
+        launch_border_w(level_sboxes(c, l), level_count(c, l), c->d_ridx.as<int>(), c->d_Hh.as<double>(), p3,
+                        c->d_bscr.as<double>(), scr_stride, s);
+      const int nch = border_g_chunks(c->n_ridx, p3);
+      c->d_Gpart.ensure((size_t)nch * p3 * p3 * sizeof(double));
+      launch_border_g(c->d_ridx.as<int>(), c->n_ridx, c->d_Ph.as<double>(), c->d_W.as<double>(), p3, nch,
+                      c->d_Gpart.as<double>(), s);
+      c->d_G.ensure((size_t)p3 * p3 * sizeof(double));
+      launch_sum_parts(c->d_Gpart.as<double>(), nch, (long long)p3 * p3, p3 * p3, 1.0, c->d_G.as<double>(), s);
     }
     if (c->prm.precision == 1) {
       for (int l = c->L; l >= 1; --l) launch_w_to_float(level_sboxes(c, l), level_count(c, l), p3, s);
     }
-    c->d_G.ensure((size_t)p3 * p3 * sizeof(double));
-    launch_sum_parts(c->d_Gpart.as<double>(), nsb, (long long)p3 * p3, p3 * p3, 1.0,
-                     c->d_G.as<double>(), s);
     c->d_Z.ensure((size_t)nz * nz * sizeof(double));
     {
       KTimer kt_(c, "root_Z");

@@ -652,6 +652,87 @@ __global__ __launch_bounds__(kBlock) void k_eliminate(const LevelBox* boxes, int
   }
 }
 
+// ---- border of the root system (eq. partition) -----------------------------
+// W_B = X_RR^{-1} (U H)_R of every box (r x 3p) on FP64 MFMA: the rows R of
+// (U H) are gathered into the block's scratch, then one GEMM.
+__global__ __launch_bounds__(kBlock) void k_border_w(const SolveBox* boxes, const int* ridx,
+                                                     const double* Hh, int p3, double* scratch,
+                                                     long long scr_stride) {
+  __shared__ double sA[kTB * (kTK + 1)];
+  __shared__ double sB[kTK * (kTB + 1)];
+  const SolveBox& B = boxes[blockIdx.x];
+  const int r = B.r;
+  if (r == 0) return;
+  double* hr = scratch + (size_t)blockIdx.x * scr_stride;
+  const int* R = ridx + B.r_off;
+  for (int t = threadIdx.x; t < r * p3; t += kBlock) {
+    const int i = t / p3, h = t % p3;
+    hr[t] = Hh[(size_t)R[i] * p3 + h];
+  }
+  __syncthreads();
+  mfma_gemm(0, 1, r, p3, r, 1.0, B.Xinv, r, false, hr, p3, false, 0.0, nullptr, 0, B.W, p3, sA, sB);
+}
+
+// Gpart[chunk] = sum over the rows i of the chunk of Ph[R_i]^T W[i], where the
+// R lists of all boxes are concatenated (ridx) and W holds the boxes' W blocks
+// in the same order: G = sum_B (Psi^T V)_R W_B as one gathered product.  A
+// block owns a 64 x 64 tile of G and a chunk of rows; each thread a 4 x 4
+// sub-tile; rows are staged 32 at a time in LDS; the chunks are added by
+// k_sum_parts in a fixed order.
+constexpr int kBGT = 64;
+__global__ __launch_bounds__(kBlock) void k_border_g(const int* ridx, int total_r, const double* Ph,
+                                                     const double* W, int p3, int chunk,
+                                                     double* Gpart) {
+  __shared__ double sp[32][kBGT + 1];
+  __shared__ double sw[32][kBGT + 1];
+  const int tiles = (p3 + kBGT - 1) / kBGT;
+  const int a0 = (blockIdx.x / tiles) * kBGT, b0 = (blockIdx.x % tiles) * kBGT;
+  const int i0 = blockIdx.y * chunk, i1 = min(total_r, i0 + chunk);
+  const int tid = threadIdx.x;
+  const int ra = (tid >> 4) * 4, rb = (tid & 15) * 4;
+  double acc[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+  for (int r0 = i0; r0 < i1; r0 += 32) {
+    const int cnt = min(32, i1 - r0);
+    __syncthreads();
+    for (int t = tid; t < 32 * kBGT; t += kBlock) {
+      const int i = t / kBGT, cc = t % kBGT;
+      double pv = 0.0, wv = 0.0;
+      if (i < cnt) {
+        const int row = r0 + i;
+        if (a0 + cc < p3) pv = Ph[(size_t)ridx[row] * p3 + a0 + cc];
+        if (b0 + cc < p3) wv = W[(size_t)row * p3 + b0 + cc];
+      }
+      sp[i][cc] = pv;
+      sw[i][cc] = wv;
+    }
+    __syncthreads();
+    for (int i = 0; i < cnt; ++i) {
+      double pa[4], wb[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        pa[u] = sp[i][ra + u];
+        wb[u] = sw[i][rb + u];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = fma(pa[u], wb[v], acc[u][v]);
+    }
+  }
+  double* G = Gpart + (size_t)blockIdx.y * p3 * p3;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int a = a0 + ra + u, b = b0 + rb + v;
+      if (a < p3 && b < p3) G[(size_t)a * p3 + b] = acc[u][v];
+    }
+}
+
 // ---- blocked in-place Gauss-Jordan inverse (root system) ----------------------
 // A (n x n, row-major) is overwritten by the inverse of P A, where P is the
 // row permutation chosen by partial pivoting (recorded in rowperm); a final
@@ -950,6 +1031,28 @@ void launch_gj_blocked(double* A, int n, double* Ainv, double* work, int* iwork,
 
 void launch_factor_to_float(const LevelBox* boxes, int nbox, const int* k_final, hipStream_t s) {
   if (nbox) hipLaunchKernelGGL(k_factor_to_float, dim3(nbox), dim3(kBlock), 0, s, boxes, k_final);
+}
+
+void launch_border_w(const SolveBox* boxes, int nbox, const int* ridx, const double* Hh, int p3,
+                     double* scratch, long long scr_stride, hipStream_t s) {
+  if (nbox == 0 || p3 == 0) return;
+  hipLaunchKernelGGL(k_border_w, dim3(nbox), dim3(kBlock), 0, s, boxes, ridx, Hh, p3, scratch, scr_stride);
+}
+
+int border_g_chunks(int total_r, int p3) {
+  const int tiles = (p3 + kBGT - 1) / kBGT;
+  const int want = std::max(1, 2048 / std::max(1, tiles * tiles));
+  const int most = std::max(1, (total_r + 255) / 256);
+  return std::min(want, most);
+}
+
+void launch_border_g(const int* ridx, int total_r, const double* Ph, const double* W, int p3, int nchunk,
+                     double* Gpart, hipStream_t s) {
+  if (p3 == 0) return;
+  const int tiles = (p3 + kBGT - 1) / kBGT;
+  const int chunk = std::max(1, (total_r + nchunk - 1) / nchunk);
+  hipLaunchKernelGGL(k_border_g, dim3(tiles * tiles, nchunk), dim3(kBlock), 0, s, ridx, total_r, Ph, W, p3,
+                     chunk, Gpart);
 }
 
 }  // namespace rs

@@ -164,31 +164,6 @@ __global__ void k_assemble_H(Geo g, const double* hole_xy, int p, const int* cur
   }
 }
 
-// Per box: W = X_RR^{-1} Hh_R (r x 3p) and Gpart = Ph_R^T W (3p x 3p).
-__global__ __launch_bounds__(kBlock) void k_border_box(const SolveBox* boxes, const int* ridx,
-                                                       const double* Hh, const double* Ph,
-                                                       int p3, double* Gpart, double* scratch,
-                                                       long long scr_stride) {
-  const SolveBox& B = boxes[blockIdx.x];
-  const int r = B.r;
-  double* G = Gpart + (size_t)B.part * p3 * p3;
-  if (r == 0) {
-    for (int t = threadIdx.x; t < p3 * p3; t += kBlock) G[t] = 0.0;
-    return;
-  }
-  double* hr = scratch + (size_t)blockIdx.x * scr_stride;
-  double* pr = hr + (size_t)r * p3;
-  const int* R = ridx + B.r_off;
-  for (int t = threadIdx.x; t < r * p3; t += kBlock) {
-    const int i = t / p3, h = t % p3;
-    hr[t] = Hh[(size_t)R[i] * p3 + h];
-    pr[t] = Ph[(size_t)R[i] * p3 + h];
-  }
-  __syncthreads();
-  wg_gemm(r, p3, r, 1.0, B.Xinv, r, false, hr, p3, false, 0.0, nullptr, 0, B.W, p3);
-  wg_gemm(p3, p3, r, 1.0, pr, p3, true, B.W, p3, false, 0.0, nullptr, 0, G, p3);
-}
-
 // out[t] = scale * sum_p parts[p * stride + t].  A block takes 64 outputs; its
 // 4 waves x 4 accumulators form 16 streams, stream s summing the parts
 // p = s, s + 16, s + 32, ... in order; the 16 stream sums are then added in
@@ -435,14 +410,6 @@ void launch_assemble_H(Geo g, const double* hole_xy, int p, const int* curve_id,
                        double* Psi, hipStream_t s) {
   hipLaunchKernelGGL(k_assemble_H, dim3(blocks_for(g.N, kBlock)), dim3(kBlock), 0, s, g,
                      hole_xy, p, curve_id, H, Psi);
-}
-
-void launch_border_box(const SolveBox* boxes, int nbox, const int* ridx, const double* Hh,
-                       const double* Ph, int p3, double* Gpart, double* scratch,
-                       long long scr_stride, hipStream_t s) {
-  if (nbox == 0) return;
-  hipLaunchKernelGGL(k_border_box, dim3(nbox), dim3(kBlock), 0, s, boxes, ridx, Hh, Ph, p3,
-                     Gpart, scratch, scr_stride);
 }
 
 void launch_sum_parts(const double* parts, int nparts, long long stride, int len, double scale,
