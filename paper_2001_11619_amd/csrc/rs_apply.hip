@@ -3,6 +3,7 @@
 #include "rs_device.h"
 
 #include <cstdio>
+#include <type_traits>
 
 namespace rs {
 namespace {
@@ -115,6 +116,93 @@ __global__ __launch_bounds__(kApplyThreads) void k_apply_pairs(Geo g, const doub
       }
     }
   }
+}
+
+// The same pair sums with the sources read by uniform (scalar) loads instead
+// of LDS: src4 packs (x, y, w n_x, w n_y) per node; each wave walks the sources
+// of its chunk in order, every lane holding T targets.  Same arithmetic and
+// order per target as k_apply_pairs (bitwise the same result).
+template <int NC, int T>
+__global__ __launch_bounds__(kApplyThreads) void k_apply_pairs_s(const double4* __restrict__ src4,
+                                                                 const double* __restrict__ tx,
+                                                                 const double* __restrict__ ty, int nt,
+                                                                 int N, const double* __restrict__ x,
+                                                                 int ncols, int chunk,
+                                                                 double* __restrict__ part,
+                                                                 const int* __restrict__ skip,
+                                                                 int max_iters) {
+  if (apply_skipped(skip, max_iters)) return;
+  const int tid = threadIdx.x;
+  const int ib = blockIdx.x * (kApplyThreads * T) + tid;
+  const int js0 = blockIdx.y * chunk, js1 = min(N, js0 + chunk);
+  const int q0 = blockIdx.z * NC;
+  const int nq = min(NC, ncols - q0);
+  double xi[T], yi[T];
+  double ax[T][NC], ay[T][NC];
+#pragma unroll
+  for (int u = 0; u < T; ++u) {
+    const int i = ib + u * kApplyThreads;
+    xi[u] = i < nt ? tx[i] : 0.0;
+    yi[u] = i < nt ? ty[i] : 0.0;
+#pragma unroll
+    for (int q = 0; q < NC; ++q) { ax[u][q] = 0.0; ay[u][q] = 0.0; }
+  }
+  // full column chunks read without per-column checks
+  auto sweep = [&](auto full) {
+    for (int js = js0; js < js1; ++js) {
+      const double4 sp = src4[js];
+      double mv[2 * NC];
+      const double* xr0 = x + (size_t)(2 * js) * ncols + q0;
+      const double* xr1 = xr0 + ncols;
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        if (decltype(full)::value) {
+          mv[2 * q] = xr0[q];
+          mv[2 * q + 1] = xr1[q];
+        } else {
+          mv[2 * q] = q < nq ? xr0[q] : 0.0;
+          mv[2 * q + 1] = q < nq ? xr1[q] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < T; ++u) {
+        const double rx = xi[u] - sp.x, ry = yi[u] - sp.y;
+        const double r2 = fma(rx, rx, ry * ry);
+        const double rn = fma(rx, sp.z, ry * sp.w);
+        const double c = kInvPi * rn * inv_pos(r2 * r2);
+        const double crx = c * rx;
+        const double bxx = crx * rx, bxy = crx * ry, byy = c * ry * ry;
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+          ax[u][q] = fma(bxx, mv[2 * q], fma(bxy, mv[2 * q + 1], ax[u][q]));
+          ay[u][q] = fma(bxy, mv[2 * q], fma(byy, mv[2 * q + 1], ay[u][q]));
+        }
+      }
+    }
+  };
+  if (nq == NC) sweep(std::true_type{});
+  else sweep(std::false_type{});
+  double* out = part + (size_t)blockIdx.y * 2 * nt * ncols;
+#pragma unroll
+  for (int u = 0; u < T; ++u) {
+    const int i = ib + u * kApplyThreads;
+    if (i >= nt) continue;
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      if (q < nq) {
+        out[(size_t)(2 * i) * ncols + q0 + q] = ax[u][q];
+        out[(size_t)(2 * i + 1) * ncols + q0 + q] = ay[u][q];
+      }
+    }
+  }
+}
+
+// src4[j] = (x_j, y_j, w_j n_xj, w_j n_yj)
+__global__ void k_pack_sources(Geo g, double4* src4) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= g.N) return;
+  const double w = g.w[j];
+  src4[j] = make_double4(g.x[j], g.y[j], w * g.nx[j], w * g.ny[j]);
 }
 
 // nsum[q] = sum_j w_j (n_j . x_j), column q (the rank-one term's scalar);
@@ -243,8 +331,10 @@ __global__ __launch_bounds__(kBlock) void k_apply_psi(Geo g, const int* curve_id
 // Apply configurations (columns per pass NC, targets per thread T) the
 // autotuner chooses from.
 namespace {
-struct ApplyShape { int nc, t; };
-constexpr ApplyShape kApplyShapes[] = {{4, 2}, {4, 4}, {8, 1}, {8, 2}, {8, 4}, {16, 1}, {16, 2}};
+// sc = 1: sources by uniform loads (k_apply_pairs_s), 0: staged in LDS.
+struct ApplyShape { int nc, t, sc; };
+constexpr ApplyShape kApplyShapes[] = {{4, 2, 0}, {4, 4, 0}, {8, 1, 0}, {8, 2, 0}, {8, 4, 0}, {16, 1, 0},
+                                       {16, 2, 0}, {4, 4, 1}, {8, 2, 1}, {8, 4, 1}, {16, 1, 1}, {16, 2, 1}};
 constexpr int kNumApplyShapes = (int)(sizeof(kApplyShapes) / sizeof(kApplyShapes[0]));
 
 // Source chunks: about 4096 blocks of one-target threads.  The partition
@@ -258,19 +348,32 @@ int apply_chunk_len(int N) {
 }
 }  // namespace
 
-// The double-layer pair sums of one shape; grid = (target tiles, chunks, column chunks).
-static void launch_pairs(Geo g, const double* tx, const double* ty, int nt, const double* x, int ncols,
-                  int chunk, double* part, const int* skip, int max_iters, int cfg, dim3 grid,
-                  hipStream_t s) {
+// The double-layer pair sums of one shape; grid = (target tiles, chunks,
+// column chunks).  src4: scratch of 4N doubles (32-byte aligned) for the
+// packed sources of the uniform-load variants.
+static void launch_pairs(Geo g, double4* src4, const double* tx, const double* ty, int nt, const double* x,
+                         int ncols, int chunk, double* part, const int* skip, int max_iters, int cfg,
+                         dim3 grid, hipStream_t s) {
   const ApplyShape sh = kApplyShapes[cfg];
+  if (sh.sc) hipLaunchKernelGGL(k_pack_sources, dim3(blocks_for(g.N, kBlock)), dim3(kBlock), 0, s, g, src4);
 #define RS_APPLY(NC, T)                                                                             \
-  if (sh.nc == NC && sh.t == T)                                                                     \
+  if (!sh.sc && sh.nc == NC && sh.t == T)                                                           \
     hipLaunchKernelGGL((k_apply_pairs<NC, T>), grid, dim3(kApplyThreads), 0, s, g, tx, ty, nt, x, ncols, \
                        chunk, part, skip, max_iters);
+#define RS_APPLY_S(NC, T)                                                                           \
+  if (sh.sc && sh.nc == NC && sh.t == T)                                                            \
+    hipLaunchKernelGGL((k_apply_pairs_s<NC, T>), grid, dim3(kApplyThreads), 0, s, src4, tx, ty, nt, g.N, \
+                       x, ncols, chunk, part, skip, max_iters);
   RS_APPLY(4, 2) RS_APPLY(4, 4) RS_APPLY(8, 1) RS_APPLY(8, 2) RS_APPLY(8, 4) RS_APPLY(16, 1)
   RS_APPLY(16, 2)
+  RS_APPLY_S(4, 4) RS_APPLY_S(8, 2) RS_APPLY_S(8, 4) RS_APPLY_S(16, 1) RS_APPLY_S(16, 2)
 #undef RS_APPLY
+#undef RS_APPLY_S
 }
+
+// Offset (in doubles, a multiple of 4) of the packed sources in a scratch
+// whose first `used` doubles hold partial sums.
+static size_t src4_offset(size_t used) { return (used + 3) / 4 * 4; }
 
 int apply_config_count() { return kNumApplyShapes; }
 
@@ -293,7 +396,7 @@ void apply_config_name(int cfg, char* buf, int len) {
 size_t apply_scratch_doubles(int N, int ncols) {
   const int len = apply_chunk_len(N);
   const int nch = (N + len - 1) / len;
-  return (size_t)nch * 2 * N * ncols + ncols;
+  return src4_offset((size_t)nch * 2 * N * ncols + ncols) + 4 * (size_t)N;
 }
 
 void launch_apply_operator(Geo g, const int* curve_id, const double* hole_xy, int p, double lam,
@@ -304,8 +407,9 @@ void launch_apply_operator(Geo g, const int* curve_id, const double* hole_xy, in
   const int chunk = apply_chunk_len(g.N);
   const int nchunk = (g.N + chunk - 1) / chunk;
   double* nsum = part + (size_t)nchunk * 2 * g.N * ncols;
+  double4* src4 = reinterpret_cast<double4*>(part + src4_offset((size_t)nchunk * 2 * g.N * ncols + ncols));
   dim3 grid(blocks_for(g.N, kApplyThreads * sh.t), nchunk, blocks_for(ncols, sh.nc));
-  launch_pairs(g, g.x, g.y, g.N, x, ncols, chunk, part, skip, max_iters, cfg, grid, s);
+  launch_pairs(g, src4, g.x, g.y, g.N, x, ncols, chunk, part, skip, max_iters, cfg, grid, s);
   hipLaunchKernelGGL(k_apply_nsum, dim3(ncols), dim3(kBlock), 0, s, g, x, ncols, nsum, skip, max_iters);
   hipLaunchKernelGGL(k_apply_sum, dim3(blocks_for((long long)g.N * ncols, kBlock)), dim3(kBlock), 0, s,
                      g, lam, hole_xy, p, x, ncols, part, nchunk, nsum, y, skip, max_iters);
@@ -317,7 +421,7 @@ void launch_apply_operator(Geo g, const int* curve_id, const double* hole_xy, in
 size_t eval_scratch_doubles(int N, int nt, int ncols) {
   const int len = apply_chunk_len(N);
   const int nch = (N + len - 1) / len;
-  return (size_t)nch * 2 * nt * ncols;
+  return src4_offset((size_t)nch * 2 * nt * ncols) + 4 * (size_t)N;
 }
 
 void launch_evaluate(Geo g, const double* hole_xy, int p, const double* tx, const double* ty, int nt,
@@ -327,8 +431,9 @@ void launch_evaluate(Geo g, const double* hole_xy, int p, const double* tx, cons
   const ApplyShape sh = kApplyShapes[cfg];
   const int chunk = apply_chunk_len(g.N);
   const int nchunk = (g.N + chunk - 1) / chunk;
+  double4* src4 = reinterpret_cast<double4*>(part + src4_offset((size_t)nchunk * 2 * nt * ncols));
   dim3 grid(blocks_for(nt, kApplyThreads * sh.t), nchunk, blocks_for(ncols, sh.nc));
-  launch_pairs(g, tx, ty, nt, x, ncols, chunk, part, nullptr, 0, cfg, grid, s);
+  launch_pairs(g, src4, tx, ty, nt, x, ncols, chunk, part, nullptr, 0, cfg, grid, s);
   hipLaunchKernelGGL(k_eval_sum, dim3(blocks_for((long long)nt * ncols, kBlock)), dim3(kBlock), 0, s, g,
                      tx, ty, nt, hole_xy, p, x, ncols, part, nchunk, u);
 }

@@ -49,7 +49,7 @@ def _fluid_points(g, n, seed, margin):
     return np.array(out)
 
 
-@pytest.mark.parametrize("ncols,shape", [(1, -1), (3, -1), (11, -1), (11, 0), (11, 6)])
+@pytest.mark.parametrize("ncols,shape", [(1, -1), (3, -1), (11, -1), (11, 0), (11, 6), (11, 10), (16, 11)])
 def test_evaluate_matches_oracle(ncols, shape):
     g = workload_small(seed=13, n_outer=300, n_holes=2, nodes_per_hole=70, radius=3.0)
     rng = np.random.Generator(np.random.PCG64(ncols))

@@ -232,8 +232,9 @@ def test_dense_inverse_singular_panel_stops_cleanly():
 
 def test_apply_shapes_bitwise_equal():
     """Every kernel shape the operator-apply autotuner chooses from (columns
-    per pass x targets per thread) gives bitwise the same y = A x, for a ragged
-    column count and target count, and matches the oracle's operator."""
+    per pass x targets per thread, sources staged in LDS or read by uniform
+    loads; twelve shapes) gives bitwise the same y = A x, for a ragged column
+    count and target count, and matches the oracle's operator."""
     from paper_2001_11619_amd import binding
 
     g = workload_small(seed=13, n_outer=300, n_holes=2, nodes_per_hole=70, radius=3.0)
@@ -242,7 +243,7 @@ def test_apply_shapes_bitwise_equal():
     Yo = stokes.apply_system(g, X)
     lib = binding.load_library()
     ref = None
-    for shape in range(7):
+    for shape in range(12):
         s = _solver(g, leaf_size=32, apply_shape=shape)
         Y = s.apply(X)
         assert np.abs(Y - Yo).max() < 1e-12 * np.abs(Yo).max()
