@@ -764,10 +764,13 @@ __global__ __launch_bounds__(kBlock) void k_gjb_panel(const double* A, int n, in
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   if (*(volatile const int*)status) return;
   double* W = in_lds ? wsh : Wg;
+  // rows of W are ldw apart: one more than bb in LDS, so that the passes down
+  // a column (pivot search, scaling) hit distinct banks
+  const int ldw = in_lds ? bb + 1 : bb;
   const int h = n - k0;
   for (int t = tid; t < h * bb; t += kBlock) {
     const int i = t / bb, c = t % bb;
-    W[t] = A[(size_t)(k0 + i) * n + k0 + c];
+    W[(size_t)i * ldw + c] = A[(size_t)(k0 + i) * n + k0 + c];
   }
   __syncthreads();
   bool singular = false;
@@ -775,7 +778,7 @@ __global__ __launch_bounds__(kBlock) void k_gjb_panel(const double* A, int n, in
     double best = -1.0;
     int bi = h;
     for (int i = j + tid; i < h; i += kBlock) {
-      const double v = fabs(W[(size_t)i * bb + j]);
+      const double v = fabs(W[(size_t)i * ldw + j]);
       if (v > best) { best = v; bi = i; }
     }
 #pragma unroll
@@ -799,19 +802,19 @@ __global__ __launch_bounds__(kBlock) void k_gjb_panel(const double* A, int n, in
     if (tid == 0) piv[j] = bi;
     if (bi != j)
       for (int c = tid; c < bb; c += kBlock) {
-        const double a = W[(size_t)j * bb + c];
-        W[(size_t)j * bb + c] = W[(size_t)bi * bb + c];
-        W[(size_t)bi * bb + c] = a;
+        const double a = W[(size_t)j * ldw + c];
+        W[(size_t)j * ldw + c] = W[(size_t)bi * ldw + c];
+        W[(size_t)bi * ldw + c] = a;
       }
     __syncthreads();
-    const double d = W[(size_t)j * bb + j];
-    for (int i = j + 1 + tid; i < h; i += kBlock) W[(size_t)i * bb + j] /= d;
+    const double d = W[(size_t)j * ldw + j];
+    for (int i = j + 1 + tid; i < h; i += kBlock) W[(size_t)i * ldw + j] /= d;
     __syncthreads();
     const int rest = bb - j - 1;
     if (rest > 0)
       for (int t = tid; t < (h - j - 1) * rest; t += kBlock) {
         const int i = j + 1 + t / rest, c = j + 1 + t % rest;
-        W[(size_t)i * bb + c] -= W[(size_t)i * bb + j] * W[(size_t)j * bb + c];
+        W[(size_t)i * ldw + c] -= W[(size_t)i * ldw + j] * W[(size_t)j * ldw + c];
       }
     __syncthreads();
   }
@@ -820,7 +823,7 @@ __global__ __launch_bounds__(kBlock) void k_gjb_panel(const double* A, int n, in
     return;
   }
   // D = L U (first bb rows of W); D^{-1} = U^{-1} L^{-1}
-  for (int t = tid; t < bb * bb; t += kBlock) lu[t / bb][t % bb] = W[t];
+  for (int t = tid; t < bb * bb; t += kBlock) lu[t / bb][t % bb] = W[(size_t)(t / bb) * ldw + t % bb];
   __syncthreads();
   // columns of L^{-1} (unit lower) then U^{-1} applied: one thread per column
   if (tid < bb) {
@@ -1012,7 +1015,7 @@ void launch_gj_blocked(double* A, int n, double* Ainv, double* work, int* iwork,
   const long long nn = (long long)n * n;
   for (int k0 = 0; k0 < n; k0 += kGJB) {
     const int bb = std::min(kGJB, n - k0);
-    const size_t pbytes = (size_t)(n - k0) * bb * sizeof(double);
+    const size_t pbytes = (size_t)(n - k0) * (bb + 1) * sizeof(double);
     const int in_lds = pbytes <= kPanelLdsBytes ? 1 : 0;
     hipLaunchKernelGGL(k_gjb_panel, dim3(1), dim3(kBlock), in_lds ? pbytes : 0, s, A, n, k0, bb, W, piv,
                        Dinv, status, in_lds);
