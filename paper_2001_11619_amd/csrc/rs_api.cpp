@@ -587,7 +587,7 @@ class HostPool {
       chunk_ = std::max(1, n / (4 * (int)(workers_.size() + 1)));
       next_.store(0);
       active_ = (int)workers_.size();
-      ++gen_;
+      gen_.fetch_add(1, std::memory_order_release);
     }
     cv_.notify_all();
     work();
@@ -624,9 +624,9 @@ class HostPool {
     for (;;) {
       {
         std::unique_lock<std::mutex> lk(mu_);
-        cv_.wait(lk, [&] { return stop_ || gen_ != seen; });
+        cv_.wait(lk, [&] { return stop_ || gen_.load(std::memory_order_acquire) != seen; });
         if (stop_) return;
-        seen = gen_;
+        seen = gen_.load(std::memory_order_acquire);
       }
       work();
       std::lock_guard<std::mutex> lk(mu_);
@@ -638,7 +638,7 @@ class HostPool {
   std::condition_variable cv_, done_cv_;
   const std::function<void(int)>* fn_ = nullptr;
   int n_ = 0, chunk_ = 1, active_ = 0;
-  unsigned gen_ = 0;
+  std::atomic<unsigned> gen_{0};
   bool stop_ = false;
   std::atomic<int> next_{0};
 };
@@ -694,7 +694,10 @@ void prepare_level(rs_ctx* c, int l, const std::vector<int>& ids, const std::vec
   std::vector<std::vector<int>> Is(nids);
   std::vector<std::vector<ChildSrc>> srcs(nids);
   HostPool& pool = HostPool::instance();
-  pool.run(nids, [&](int t) { box_unknowns(c, ids[t], Is[t], &srcs[t]); });
+  {
+    HTimer ht2_(c, "host:prep.unknowns");
+    pool.run(nids, [&](int t) { box_unknowns(c, ids[t], Is[t], &srcs[t]); });
+  }
   // position of each box of this level in ids (-1: other levels)
   std::vector<int>& pos_of = c->lvl_pos;
   pos_of.assign(c->boxes.size(), -1);
@@ -704,6 +707,8 @@ void prepare_level(rs_ctx* c, int l, const std::vector<int>& ids, const std::vec
   // independent here
   std::vector<std::vector<int>> Fs(nids);
   std::vector<char> keep(nids, 0);
+  {
+  HTimer ht3_(c, "host:prep.near");
   pool.run(nids, [&](int t) {
     if (Is[t].empty()) return;
     const int b = ids[t];
@@ -725,6 +730,7 @@ void prepare_level(rs_ctx* c, int l, const std::vector<int>& ids, const std::vec
     std::sort(F.begin(), F.end());
     if (c->old && !compress_needed(c, b, F)) keep[t] = 1;
   });
+  }
   std::vector<int> dofs, fint;
   std::vector<ChildSrc> src_all;
   std::vector<int> soff;
@@ -781,6 +787,7 @@ void prepare_level(rs_ctx* c, int l, const std::vector<int>& ids, const std::vec
   const int nb = (int)P.lb.size();
   if (nb == 0) return;
   // workspaces and the factor arena of this level
+  HTimer ht4_(c, "host:prep.alloc");
   c->ws_M.ensure(totM * sizeof(double));
   c->ws_R.ensure(totN2 * sizeof(double));
   c->ws_A.ensure(totN2 * sizeof(double));
@@ -864,6 +871,7 @@ void prepare_level(rs_ctx* c, int l, const std::vector<int>& ids, const std::vec
 // Ranks and pivot orders read back for one context: fill its box records.
 void finish_level(rs_ctx* c, LevelPrep& P, const int* k0, const int* kk, const int* st, const double* rc,
                   std::vector<int>& boxes_done) {
+  HTimer ht_(c, "host:finish");
   for (size_t i = 0; i < P.lb.size(); ++i) {
     const int b = P.ids[P.sel[i]];
     BoxFac& f = c->fac[b];
@@ -1168,6 +1176,7 @@ void launch_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps) {
 }
 
 void build_solve_meta(rs_ctx* c) {
+  HTimer ht_(c, "host:solve_meta");
   const int L = c->L;
   c->sboxes.assign(L + 1, {});
   c->lvl_maxn.assign(L + 1, 0);
