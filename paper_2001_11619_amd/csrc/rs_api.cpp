@@ -247,6 +247,7 @@ struct rs_ctx {
   double refine_prev = 1.0;       // largest relative residual before the last launch
   int refine_last = 0;            // iterations in the last launch
   DevBuf d_flag;                  // [converged, corrections applied]
+  hipEvent_t ev_qr = nullptr;     // a level's QR ranks and pivot orders have reached the host
   PinHost h_flag;
 
   // kernel timing (HIP events around launches)
@@ -262,6 +263,7 @@ struct rs_ctx {
   ~rs_ctx() {
     if (refine_exec) (void)hipGraphExecDestroy(refine_exec);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (ev_qr) (void)hipEventDestroy(ev_qr);
     for (auto& p : pending) {
       (void)hipEventDestroy(p.a);
       (void)hipEventDestroy(p.b);
@@ -926,7 +928,12 @@ int qr_route(int m, int n, int& h, std::vector<int>& P) {
 
 // One launch per kernel over the boxes of all contexts at this level (the
 // lead context provides the stream, the descriptor array and the rank arrays).
-void launch_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps) {
+// Host work run while the level's elimination is on the device: called with
+// the pivoted QR's ranks (indexed by box slot) once they and the pivot orders
+// (in each LevelPrep::perm) have arrived.
+using LevelOverlap = std::function<void(const int* qr_rank)>;
+
+void launch_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps, const LevelOverlap& overlap) {
   rs_ctx* c = cs[0];
   const rs_params& prm = c->prm;
   hipStream_t s = c->stream;
@@ -1137,6 +1144,17 @@ void launch_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps) {
   int* st = hk + 2 * (size_t)nb;
   int* qr_err = hk + 3 * (size_t)nb;
   HIP_CHECK(hipMemcpyAsync(k0, c->ws_k.p, nb * sizeof(int), hipMemcpyDeviceToHost, s));
+  // pivot orders are final after the QR (the elimination's guard only moves k)
+  std::vector<int*> hperm(cs.size(), nullptr);
+  for (size_t i = 0; i < cs.size(); ++i) {
+    LevelPrep& P = preps[i];
+    if (P.lb.empty()) continue;
+    const size_t np = P.doff.back() + P.lb.back().n;
+    hperm[i] = cs[i]->h_perm.get<int>(np);
+    HIP_CHECK(hipMemcpyAsync(hperm[i], cs[i]->ws_perm.p, np * sizeof(int), hipMemcpyDeviceToHost, s));
+  }
+  if (!c->ev_qr) HIP_CHECK(hipEventCreateWithFlags(&c->ev_qr, hipEventDisableTiming));
+  HIP_CHECK(hipEventRecord(c->ev_qr, s));
   {
     KTimer kt_(c, "eliminate");
     HIP_CHECK(launch_eliminate(dlb, nb, Ge, c->ws_k.as<int>(), c->ws_kx.as<int>(), prm.rcond_min,
@@ -1150,13 +1168,14 @@ void launch_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps) {
   HIP_CHECK(hipMemcpyAsync(st, c->ws_status.p, nb * sizeof(int), hipMemcpyDeviceToHost, s));
   double* hrc = c->h_rc.get<double>(nb);
   HIP_CHECK(hipMemcpyAsync(hrc, c->ws_rc.p, nb * sizeof(double), hipMemcpyDeviceToHost, s));
-  std::vector<int*> hperm(cs.size(), nullptr);
-  for (size_t i = 0; i < cs.size(); ++i) {
-    LevelPrep& P = preps[i];
-    if (P.lb.empty()) continue;
-    const size_t np = P.doff.back() + P.lb.back().n;
-    hperm[i] = cs[i]->h_perm.get<int>(np);
-    HIP_CHECK(hipMemcpyAsync(hperm[i], cs[i]->ws_perm.p, np * sizeof(int), hipMemcpyDeviceToHost, s));
+  if (overlap) {
+    {
+      HTimer ht_(c, "host:level_wait");
+      HIP_CHECK(hipEventSynchronize(c->ev_qr));
+    }
+    for (size_t i = 0; i < cs.size(); ++i)
+      if (hperm[i]) preps[i].perm.assign(hperm[i], hperm[i] + preps[i].doff.back() + preps[i].lb.back().n);
+    overlap(k0);
   }
   {
     HTimer ht_(c, "host:level_wait");
@@ -1410,20 +1429,67 @@ void do_factor_multi(std::vector<rs_ctx*>& cs) {
     for (size_t b = 0; b < c->boxes.size(); ++b) by_level[i][c->boxes[b].level].push_back((int)b);
     L = std::max(L, c->L);
   }
-  for (int l = L; l >= 1; --l) {
-    std::vector<LevelPrep> preps(nc);
-    cs[0]->cur_level = l;
-    for (size_t i = 0; i < nc; ++i)
-      if (cs[i]->L >= l) prepare_level(cs[i], l, by_level[i][l], active[i], preps[i]);
-    launch_level(cs, preps);
-    // the redundant unknowns of every box of the level (recompressed or kept) leave the active set
+  // the redundant unknowns of every box of level l (recompressed or kept) leave the active set
+  auto drop_redundant = [&](int l, std::vector<std::vector<char>>& act) {
     for (size_t i = 0; i < nc; ++i) {
       if (cs[i]->L < l) continue;
       for (int b : by_level[i][l]) {
         const BoxFac& f = cs[i]->fac[b];
         if (!f.active) continue;
-        for (int t = f.k; t < f.n; ++t) active[i][f.I[f.perm[t]]] = 0;
+        for (int t = f.k; t < f.n; ++t) act[i][f.I[f.perm[t]]] = 0;
       }
+    }
+  };
+  // While level l's elimination runs, level l - 1 is prepared on the host
+  // with the ranks of level l's QR.  The elimination's guard can still raise a
+  // rank (rarely); then that preparation is discarded and done again.
+  std::vector<LevelPrep> preps(nc), next(nc);
+  bool have_next = false;
+  for (int l = L; l >= 1; --l) {
+    cs[0]->cur_level = l;
+    if (have_next) {
+      preps.swap(next);
+    } else {
+      preps.assign(nc, LevelPrep());
+      for (size_t i = 0; i < nc; ++i)
+        if (cs[i]->L >= l) prepare_level(cs[i], l, by_level[i][l], active[i], preps[i]);
+    }
+    have_next = false;
+    bool speculated = false;
+    std::vector<std::vector<int>> spec_k(nc);
+    LevelOverlap overlap;
+    if (l > 1) {
+      overlap = [&](const int* qr_rank) {
+        for (size_t i = 0; i < nc; ++i) {
+          const LevelPrep& P = preps[i];
+          for (size_t t = 0; t < P.lb.size(); ++t) {
+            BoxFac& f = cs[i]->fac[P.ids[P.sel[t]]];
+            f.k = qr_rank[P.first + t];
+            f.perm.assign(P.perm.begin() + P.doff[t], P.perm.begin() + P.doff[t] + P.lb[t].n);
+            spec_k[i].push_back(f.k);
+          }
+        }
+        std::vector<std::vector<char>> act(active);
+        drop_redundant(l, act);
+        next.assign(nc, LevelPrep());
+        for (size_t i = 0; i < nc; ++i)
+          if (cs[i]->L >= l - 1) prepare_level(cs[i], l - 1, by_level[i][l - 1], act[i], next[i]);
+        speculated = true;
+      };
+    }
+    launch_level(cs, preps, overlap);
+    drop_redundant(l, active);
+    if (speculated) {
+      bool same = true;
+      for (size_t i = 0; i < nc && same; ++i) {
+        const LevelPrep& P = preps[i];
+        for (size_t t = 0; t < P.lb.size(); ++t)
+          if (cs[i]->fac[P.ids[P.sel[t]]].k != spec_k[i][t]) {
+            same = false;
+            break;
+          }
+      }
+      have_next = same;
     }
   }
   cs[0]->cur_level = -1;
