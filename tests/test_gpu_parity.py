@@ -252,3 +252,21 @@ def test_apply_shapes_bitwise_equal():
         assert np.array_equal(Y, ref), shape
     s = _solver(g, leaf_size=32)
     assert np.array_equal(s.apply(X), ref)
+
+
+def test_guard_bumps_redo_speculative_preparation():
+    """A large rcond_min (2e-3: the oracle moves 6 pivots from R to S in two
+    boxes, at most 4 in one) makes the X_RR guard act, so the next level,
+    prepared on the host from the QR's ranks while the elimination runs, must
+    be prepared again: the result equals the dense solution after refinement
+    and is reproducible bitwise."""
+    g = workload_small(seed=11, n_outer=256, n_holes=2, nodes_per_hole=128, radius=3.0)
+    f = boundary_data(g, exterior_forces_for_geometry(g, 2, seed=5))
+    xd = stokes.dense_solve(g, f)
+    a = _solver(g, leaf_size=32, tol=1e-8, rcond_min=2e-3, refine_max=30, refine_tol=1e-12).factor()
+    assert a.stats()["guard_bumps"] > 0
+    x, res = a.solve(f, residual=True)
+    assert np.all(res <= 1e-12)
+    assert np.all(_rel(x, xd) < 1e-10)
+    b = _solver(g, leaf_size=32, tol=1e-8, rcond_min=2e-3, refine_max=30, refine_tol=1e-12).factor()
+    assert np.array_equal(b.solve(f), x)
