@@ -190,14 +190,18 @@ constexpr size_t kTSolveMax = 12288;   // T (k x r) up to this size is solved in
 // workgroup with partial pivoting by exchange steps: step j pivots on the
 // largest |W[i][j]| over the rows not used yet, and row i and column j trade
 // places; the finished tableau W holds X^{-1} with X^{-1}[j][p_c] = W[p_j][c].
-// A 16 x 16 thread grid keeps rows ty + 16 a, columns tx + 16 b of W in
-// registers for the whole sweep; per step the pivot row and column go
-// through LDS.  The pivot is compared on a 64-bit key (|W| with its low 8
-// mantissa bits replaced by 255 - i, ties within 2^-44 to the smaller row)
-// that the holders of column j + 1 fold into LDS with an atomic max during
-// step j.  The update is one FMA per element (the multipliers absorb the
-// pivot row and column).  Column 1-norms for rcond_1 are summed in a fixed
-// order.  Two barriers per step.  Returns rcond_1 (0 if singular).
+// A 16 x 16 thread grid keeps rows ty + 16 a, columns tx + 16 b (a, b < MB,
+// MB = ceil(r / 16) fixed at compile time) of W in registers for the whole
+// sweep; padding rows and columns hold zeros and stay zero.  Per step the
+// holders of the pivot row and column copy them to LDS and clear them, and
+// every element then takes one FMA (the multipliers absorb the pivot row and
+// column).  The pivot row and the column block are uniform over the
+// workgroup, so choosing the registers that hold them costs scalar branches,
+// not per-element selects.  The pivot is compared on a 64-bit key (|W| with
+// its low 8 mantissa bits replaced by 255 - i, ties within 2^-44 to the
+// smaller row) that the holders of column j + 1 fold into LDS with an atomic
+// max during step j.  Column 1-norms for rcond_1 are summed in a fixed order.
+// Two barriers per step.  Returns rcond_1 (0 if singular).
 // LDS: gj_lds_doubles(r) doubles at `sh`.
 __device__ __forceinline__ unsigned long long gj_key(double v, int i) {
   const unsigned long long b = (unsigned long long)__double_as_longlong(fabs(v));
@@ -206,11 +210,10 @@ __device__ __forceinline__ unsigned long long gj_key(double v, int i) {
 
 __host__ __device__ constexpr size_t gj_lds_doubles(int r) { return 18 * (size_t)r + 4 + (size_t)r; }
 
-__device__ double reg_gj(const double* X, int r, double* Xi, double* sh, double* red) {
+template <int MB>
+__device__ __noinline__ double reg_gj_t(const double* X, int r, double* Xi, double* sh, double* red) {
   const int tid = threadIdx.x;
   const int ty = tid >> 4, tx = tid & 15;
-  constexpr int MB = (kLdsGJMax + 15) / 16;
-  const int mb = (r + 15) >> 4;
   double* rowbuf = sh;                       // r: pivot row
   double* colbuf = rowbuf + r;               // r: pivot column
   double* part = colbuf + r;                 // 16 r: column-sum partials
@@ -219,27 +222,20 @@ __device__ double reg_gj(const double* X, int r, double* Xi, double* sh, double*
   int* ipv = pv + r;                                  // r
   double w[MB][MB];
 #pragma unroll
-  for (int a = 0; a < MB; ++a) {
-    if (a >= mb) break;
+  for (int a = 0; a < MB; ++a)
 #pragma unroll
     for (int b = 0; b < MB; ++b) {
-      if (b >= mb) break;
       const int i = ty + 16 * a, c = tx + 16 * b;
       w[a][b] = (i < r && c < r) ? X[(size_t)i * r + c] : 0.0;
     }
-  }
   if (tid < 2) keys[tid] = 0ull;
   // largest column 1-norm: per-thread partial sums, then 16 partials per column in order
   auto colnorm = [&]() {
 #pragma unroll
     for (int b = 0; b < MB; ++b) {
-      if (b >= mb) break;
       double s = 0.0;
 #pragma unroll
-      for (int a = 0; a < MB; ++a) {
-        if (a >= mb) break;
-        s += fabs(w[a][b]);
-      }
+      for (int a = 0; a < MB; ++a) s += fabs(w[a][b]);
       const int c = tx + 16 * b;
       if (c < r) part[ty * r + c] = s;
     }
@@ -256,7 +252,6 @@ __device__ double reg_gj(const double* X, int r, double* Xi, double* sh, double*
   if (tx == 0)
 #pragma unroll
     for (int a = 0; a < MB; ++a) {
-      if (a >= mb) break;
       const int i = ty + 16 * a;
       if (i < r) atomicMax(&keys[0], gj_key(w[a][0], i));
     }
@@ -264,28 +259,57 @@ __device__ double reg_gj(const double* X, int r, double* Xi, double* sh, double*
   unsigned used = 0;             // bit a: row ty + 16 a is a pivot row already
   for (int j = 0; j < r; ++j) {
     const unsigned long long key = keys[j & 1];
-    const int bi = 255 - (int)(key & 0xFF);
+    const int bi = __builtin_amdgcn_readfirstlane(255 - (int)(key & 0xFF));
     const int ab = bi >> 4, bj = j >> 4;
-    if (ty == (bi & 15))
-#pragma unroll
-      for (int a = 0; a < MB; ++a)
-        if (a == ab)
-#pragma unroll
-          for (int b = 0; b < MB; ++b) {
-            if (b >= mb) break;
-            const int c = tx + 16 * b;
-            if (c < r) rowbuf[c] = w[a][b];
-          }
-    if (tx == (j & 15))
-#pragma unroll
-      for (int b = 0; b < MB; ++b)
-        if (b == bj)
-#pragma unroll
-          for (int a = 0; a < MB; ++a) {
-            if (a >= mb) break;
-            const int i = ty + 16 * a;
-            if (i < r) colbuf[i] = w[a][b];
-          }
+    // copy the pivot column and row to LDS, then clear them in the tableau
+    // (bj, ab uniform: one scalar branch selects the register block)
+    const bool ccol = tx == (j & 15), crow = ty == (bi & 15);
+    switch (bj) {
+#define RS_GJ_COL(B)                                                   \
+      case B:                                                          \
+        if constexpr (B < MB) {                                        \
+          if (ccol) {                                                  \
+            _Pragma("unroll") for (int a = 0; a < MB; ++a) {           \
+              const int i = ty + 16 * a;                               \
+              if (i < r) colbuf[i] = w[a][B];                          \
+            }                                                          \
+          }                                                            \
+        }                                                              \
+        break;
+      RS_GJ_COL(0) RS_GJ_COL(1) RS_GJ_COL(2) RS_GJ_COL(3)
+      RS_GJ_COL(4) RS_GJ_COL(5) RS_GJ_COL(6) RS_GJ_COL(7)
+#undef RS_GJ_COL
+    }
+    switch (ab) {
+#define RS_GJ_ROW(A)                                                   \
+      case A:                                                          \
+        if constexpr (A < MB) {                                        \
+          if (crow) {                                                  \
+            _Pragma("unroll") for (int b = 0; b < MB; ++b) {           \
+              const int c = tx + 16 * b;                               \
+              if (c < r) rowbuf[c] = w[A][b];                          \
+              w[A][b] = 0.0;                                           \
+            }                                                          \
+          }                                                            \
+        }                                                              \
+        break;
+      RS_GJ_ROW(0) RS_GJ_ROW(1) RS_GJ_ROW(2) RS_GJ_ROW(3)
+      RS_GJ_ROW(4) RS_GJ_ROW(5) RS_GJ_ROW(6) RS_GJ_ROW(7)
+#undef RS_GJ_ROW
+    }
+    switch (bj) {
+#define RS_GJ_CLR(B)                                                   \
+      case B:                                                          \
+        if constexpr (B < MB) {                                        \
+          if (ccol) {                                                  \
+            _Pragma("unroll") for (int a = 0; a < MB; ++a) w[a][B] = 0.0; \
+          }                                                            \
+        }                                                              \
+        break;
+      RS_GJ_CLR(0) RS_GJ_CLR(1) RS_GJ_CLR(2) RS_GJ_CLR(3)
+      RS_GJ_CLR(4) RS_GJ_CLR(5) RS_GJ_CLR(6) RS_GJ_CLR(7)
+#undef RS_GJ_CLR
+    }
     if (tid == 0) { keys[(j + 1) & 1] = 0ull; pv[j] = bi; }
     __syncthreads();
     const double pvt = colbuf[bi];
@@ -295,34 +319,34 @@ __device__ double reg_gj(const double* X, int r, double* Xi, double* sh, double*
     double pr[MB], pc[MB];
 #pragma unroll
     for (int b = 0; b < MB; ++b) {
-      if (b >= mb) break;
       const int c = tx + 16 * b;
       pr[b] = c < r ? (c == j ? inv : rowbuf[c] * inv) : 0.0;
       const int i = ty + 16 * b;
       pc[b] = i < r ? (i == bi ? -1.0 : colbuf[i]) : 0.0;
     }
+#pragma unroll
+    for (int a = 0; a < MB; ++a)
+#pragma unroll
+      for (int b = 0; b < MB; ++b) w[a][b] = fma(-pc[a], pr[b], w[a][b]);
     const int bn = (j + 1) >> 4;
-    double cand[MB];
-#pragma unroll
-    for (int a = 0; a < MB; ++a) {
-      if (a >= mb) break;
-      const bool prow = ty + 16 * a == bi;
-      cand[a] = 0.0;
-#pragma unroll
-      for (int b = 0; b < MB; ++b) {
-        if (b >= mb) break;
-        const double w0 = (prow || tx + 16 * b == j) ? 0.0 : w[a][b];
-        w[a][b] = w0 - pc[a] * pr[b];
-        if (b == bn) cand[a] = w[a][b];
-      }
+    const bool cnext = tx == ((j + 1) & 15);
+    if (j + 1 < r) switch (bn) {
+#define RS_GJ_KEY(B)                                                   \
+      case B:                                                          \
+        if constexpr (B < MB) {                                        \
+          if (cnext) {                                                 \
+            _Pragma("unroll") for (int a = 0; a < MB; ++a) {           \
+              const int i = ty + 16 * a;                               \
+              if (i < r && !((used >> a) & 1))                         \
+                atomicMax(&keys[(j + 1) & 1], gj_key(w[a][B], i));     \
+            }                                                          \
+          }                                                            \
+        }                                                              \
+        break;
+      RS_GJ_KEY(0) RS_GJ_KEY(1) RS_GJ_KEY(2) RS_GJ_KEY(3)
+      RS_GJ_KEY(4) RS_GJ_KEY(5) RS_GJ_KEY(6) RS_GJ_KEY(7)
+#undef RS_GJ_KEY
     }
-    if (tx == ((j + 1) & 15) && j + 1 < r)
-#pragma unroll
-      for (int a = 0; a < MB; ++a) {
-        if (a >= mb) break;
-        const int i = ty + 16 * a;
-        if (i < r && !((used >> a) & 1)) atomicMax(&keys[(j + 1) & 1], gj_key(cand[a], i));
-      }
     __syncthreads();
   }
   // X^{-1}[j][p_c] = W[p_j][c]
@@ -330,13 +354,11 @@ __device__ double reg_gj(const double* X, int r, double* Xi, double* sh, double*
   __syncthreads();
 #pragma unroll
   for (int a = 0; a < MB; ++a) {
-    if (a >= mb) break;
     const int i = ty + 16 * a;
     if (i >= r) continue;
     const int row = ipv[i];
 #pragma unroll
     for (int b = 0; b < MB; ++b) {
-      if (b >= mb) break;
       const int c = tx + 16 * b;
       if (c < r) Xi[(size_t)row * r + pv[c]] = w[a][b];
     }
@@ -345,6 +367,20 @@ __device__ double reg_gj(const double* X, int r, double* Xi, double* sh, double*
   const double n2 = colnorm();
   const double rc = 1.0 / (n1 * n2);
   return isfinite(rc) ? rc : 0.0;
+}
+
+__device__ double reg_gj(const double* X, int r, double* Xi, double* sh, double* red) {
+  static_assert(kLdsGJMax == 128, "reg_gj dispatches MB = 1 .. 8");
+  switch ((r + 15) >> 4) {
+    case 1: return reg_gj_t<1>(X, r, Xi, sh, red);
+    case 2: return reg_gj_t<2>(X, r, Xi, sh, red);
+    case 3: return reg_gj_t<3>(X, r, Xi, sh, red);
+    case 4: return reg_gj_t<4>(X, r, Xi, sh, red);
+    case 5: return reg_gj_t<5>(X, r, Xi, sh, red);
+    case 6: return reg_gj_t<6>(X, r, Xi, sh, red);
+    case 7: return reg_gj_t<7>(X, r, Xi, sh, red);
+    default: return reg_gj_t<8>(X, r, Xi, sh, red);
+  }
 }
 
 // T = R11^{-1} R12 (k x r, row-major) by back substitution on all columns at
