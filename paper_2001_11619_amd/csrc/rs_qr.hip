@@ -528,25 +528,41 @@ __device__ __forceinline__ double row16_sum(double v) {
 
 // Householder vector at step j of the column x held by lane group og of the
 // calling wave: v into vsh (rows 0..16 RU-1, zero above j, one at j), (beta,
-// tau) into hh; x_j becomes R_jj = beta.
+// tau) into hh and R_jj = beta into rdg[j] (x itself is left as it is: the
+// column is not read again).  One wave runs this while the others
+// wait, so the column is first spread over all 64 lanes of the wave (through
+// vsh, in wave order): each lane then holds at most 4 rows (row lane + 64 q),
+// and the norm, the reflector and v are short per-lane loops; the squared
+// norm below row j is a full-wave sum in a fixed order.
 template <int RU>
-__device__ __forceinline__ void r16_householder(double (&x)[RU], const int j, const int og,
-                                                const int p, const int rg, double* vsh, double* hh) {
-  const int uj = j >> 4, pj = j & 15;
-  double xj = 0.0, s0 = 0.0, s1 = 0.0;
+__device__ __forceinline__ void r16_householder(const double (&x)[RU], const int j, const int og,
+                                                const int p, const int rg, double* vsh, double* hh,
+                                                double* rdg) {
+  constexpr int Q = (RU + 3) / 4;          // rows per lane after the spread
+  constexpr int M = 16 * RU;
+  const int lane = threadIdx.x & 63;
+  if (rg == og)
 #pragma unroll
-  for (int u = 0; u < RU; ++u) {
-    double& acc = (u & 1) ? s1 : s0;
-    if (u == uj) {
-      xj = x[u];
-      if (p > pj) acc += x[u] * x[u];
-    } else if (u > uj) {
-      acc += x[u] * x[u];
-    }
+    for (int u = 0; u < RU; ++u) vsh[p + 16 * u] = x[u];
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  double y[Q];
+  double acc = 0.0;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int row = lane + 64 * q;
+    y[q] = row < M ? vsh[row] : 0.0;
+    const double yv = row > j ? y[q] : 0.0;
+    acc += yv * yv;
   }
-  const double sum = row16_sum(s0 + s1);
-  const double alpha = lane_f64(xj, 16 * og + pj);
-  const double s2 = lane_f64(sum, 16 * og);
+  // x_j sits in lane j % 64 at position q = j / 64 (uniform)
+  const int qj = j >> 6;
+  double yj = y[0];
+#pragma unroll
+  for (int q = 1; q < Q; ++q) yj = (qj == q) ? y[q] : yj;
+  const double alpha = lane_f64(yj, j & 63);
+  const double s2 = wave_sum_fast(acc);
   double beta, tau, scal = 0.0;
   if (s2 == 0.0) {
     beta = alpha;
@@ -558,18 +574,13 @@ __device__ __forceinline__ void r16_householder(double (&x)[RU], const int j, co
     tau = -d * d * rcp;          // (beta - alpha) / beta
     scal = beta * rcp;           // 1 / (alpha - beta)
   }
-  if (rg == og) {
+  __builtin_amdgcn_wave_barrier();
 #pragma unroll
-    for (int u = 0; u < RU; ++u) {
-      double v;
-      if (u < uj) v = 0.0;
-      else if (u > uj) v = x[u] * scal;
-      else v = p < pj ? 0.0 : (p == pj ? 1.0 : x[u] * scal);
-      vsh[p + 16 * u] = v;
-      if (u == uj && p == pj) x[u] = beta;
-    }
+  for (int q = 0; q < Q; ++q) {
+    const int row = lane + 64 * q;
+    if (row < M) vsh[row] = row < j ? 0.0 : (row == j ? 1.0 : y[q] * scal);
   }
-  if ((threadIdx.x & 63) == 0) { hh[0] = beta; hh[1] = tau; }
+  if (lane == 0) { hh[0] = beta; hh[1] = tau; rdg[j] = beta; }
 }
 
 // ---- row reduction of tall ID matrices (unpivoted block Householder QR) ----
@@ -578,8 +589,37 @@ __device__ __forceinline__ void r16_householder(double (&x)[RU], const int j, co
 // Blocks of M_B first, then blocks of stacked factors, until the stack has at
 // most 256 rows.  One barrier per step: the Householder vector of step j + 1
 // goes to the other of two buffers.
+//
+// The reflector of step j applied to the register slots S0.. of the wave:
+// the slots before S0 hold finished columns only, whose multipliers are zero,
+// so the result is that of the full update.
+template <int RU, int NS, int S0>
+__device__ __forceinline__ void tsqr16_apply(double (&a)[NS][RU], const double* vsh, const int p,
+                                             const double tau, const int j, const int n,
+                                             const int wid, const int rg) {
+  double v[RU], t[NS];
+#pragma unroll
+  for (int sl = S0; sl < NS; ++sl) t[sl] = 0.0;
+#pragma unroll
+  for (int u = 0; u < RU; ++u) {
+    v[u] = vsh[p + 16 * u];
+#pragma unroll
+    for (int sl = S0; sl < NS; ++sl) t[sl] += v[u] * a[sl][u];
+  }
+#pragma unroll
+  for (int sl = S0; sl < NS; ++sl) {
+    const int c = 4 * (wid + kRQWaves * sl) + rg;
+    const double dot = row16_sum(t[sl]);
+    t[sl] = (c > j && c < n) ? tau * dot : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < RU; ++u)
+#pragma unroll
+    for (int sl = S0; sl < NS; ++sl) a[sl][u] -= t[sl] * v[u];
+}
+
 template <int RU, int NS>
-__device__ __forceinline__ void tsqr16_block(const QRTask& T, double* vsh2, double* hh2) {
+__device__ __forceinline__ void tsqr16_block(const QRTask& T, double* vsh2, double* hh2, double* rdg) {
   const int rows = T.rows, n = T.n;
   const int lane = threadIdx.x & 63, p = lane & 15, rg = lane >> 4;
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -603,31 +643,21 @@ __device__ __forceinline__ void tsqr16_block(const QRTask& T, double* vsh2, doub
       const int os = sj / kRQWaves;
 #pragma unroll
       for (int sl = 0; sl < NS; ++sl)
-        if (sl == os) r16_householder<RU>(a[sl], j, j & 3, p, rg, vsh, hh);
+        if (sl == os) r16_householder<RU>(a[sl], j, j & 3, p, rg, vsh, hh, rdg);
     }
     __syncthreads();
     const double tau = hh[1];
-    // the slots' dependent chains are interleaved; a column that is done or
-    // absent gets tw = 0 and is left as it is
-    double v[RU], t[NS];
-#pragma unroll
-    for (int sl = 0; sl < NS; ++sl) t[sl] = 0.0;
-#pragma unroll
-    for (int u = 0; u < RU; ++u) {
-      v[u] = vsh[p + 16 * u];
-#pragma unroll
-      for (int sl = 0; sl < NS; ++sl) t[sl] += v[u] * a[sl][u];
+    // slot sl of this wave holds columns 4 (wid + 8 sl) .. + 3: the first slot
+    // with a column right of j
+    const int d = j - 3 - 4 * wid;
+    const int s0 = d < 0 ? 0 : d / (4 * kRQWaves) + 1;
+    switch (s0) {
+      case 0: tsqr16_apply<RU, NS, 0>(a, vsh, p, tau, j, n, wid, rg); break;
+      case 1: if constexpr (NS > 1) tsqr16_apply<RU, NS, 1>(a, vsh, p, tau, j, n, wid, rg); break;
+      case 2: if constexpr (NS > 2) tsqr16_apply<RU, NS, 2>(a, vsh, p, tau, j, n, wid, rg); break;
+      case 3: if constexpr (NS > 3) tsqr16_apply<RU, NS, 3>(a, vsh, p, tau, j, n, wid, rg); break;
+      default: break;
     }
-#pragma unroll
-    for (int sl = 0; sl < NS; ++sl) {
-      const int c = 4 * (wid + kRQWaves * sl) + rg;
-      const double dot = row16_sum(t[sl]);
-      t[sl] = (c > j && c < n) ? tau * dot : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < RU; ++u)
-#pragma unroll
-      for (int sl = 0; sl < NS; ++sl) a[sl][u] -= t[sl] * v[u];
   }
 #pragma unroll
   for (int sl = 0; sl < NS; ++sl) {
@@ -637,7 +667,7 @@ __device__ __forceinline__ void tsqr16_block(const QRTask& T, double* vsh2, doub
 #pragma unroll
     for (int u = 0; u < RU; ++u) {
       const int r = p + 16 * u;
-      if (r < n) dst[r] = r <= c ? a[sl][u] : 0.0;
+      if (r < n) dst[r] = r < c ? a[sl][u] : (r == c ? (c < steps ? rdg[c] : a[sl][u]) : 0.0);
     }
   }
 }
@@ -649,7 +679,7 @@ __device__ __forceinline__ void tsqr16_block(const QRTask& T, double* vsh2, doub
 template <int RU, int NS>
 __device__ __forceinline__ void cpqr16_box(const LevelBox& B, const double tol, const int extra,
                                            int* k_out, int* kx_out, int* err, double* dyn,
-                                           double* s_hh, double* wv, int* wi) {
+                                           double* s_hh, double* wv, int* wi, double* rdg) {
   const int m = B.mq, n = B.n;
   const int tid = threadIdx.x, lane = tid & 63, p = lane & 15, rg = lane >> 4;
   const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -716,7 +746,7 @@ __device__ __forceinline__ void cpqr16_box(const LevelBox& B, const double tol, 
       const int os = sq / kRQWaves;
 #pragma unroll
       for (int sl = 0; sl < NS; ++sl)
-        if (sl == os) r16_householder<RU>(a[sl], j, q & 3, p, rg, vsh, s_hh);
+        if (sl == os) r16_householder<RU>(a[sl], j, q & 3, p, rg, vsh, s_hh, rdg);
     }
     __syncthreads();
     const double beta = s_hh[0], tau = s_hh[1];
@@ -790,7 +820,7 @@ __device__ __forceinline__ void cpqr16_box(const LevelBox& B, const double tol, 
 #pragma unroll
     for (int u = 0; u < RU; ++u) {
       const int r = p + 16 * u;
-      if (r < kx) dst[(size_t)r * n] = r <= pp ? a[sl][u] : 0.0;
+      if (r < kx) dst[(size_t)r * n] = r < pp ? a[sl][u] : (r == pp ? rdg[pp] : 0.0);
     }
   }
   for (int c = tid; c < n; c += kRQThreads) B.perm[c] = pv[c];
@@ -835,8 +865,9 @@ __device__ __forceinline__ void cpqr16_box(const LevelBox& B, const double tol, 
 __global__ __launch_bounds__(kRQThreads) void k_tsqr(const QRTask* tasks) {
   __shared__ double vsh2[2 * 16 * kR16MaxRU];
   __shared__ double hh2[4];
+  __shared__ double rdg[kR16MaxN];
   const QRTask& T = tasks[blockIdx.x];
-#define RS_TSQR(R, S) tsqr16_block<R, S>(T, vsh2, hh2)
+#define RS_TSQR(R, S) tsqr16_block<R, S>(T, vsh2, hh2, rdg)
   switch (T.ru * 8 + (T.n + 31) / 32) { RS_R16_CASES(RS_TSQR) }
 #undef RS_TSQR
 }
@@ -845,12 +876,13 @@ __global__ __launch_bounds__(kRQThreads) void k_cpqr16(const LevelBox* boxes, co
                                                        double tol, int extra, int* k_out, int* kx_out,
                                                        int* err) {
   __shared__ double dyn[16 * kR16MaxRU + kR16MaxCols];   // v, then pv / ipv as ints
+  __shared__ double rdg[kR16MaxN];                        // R_jj
   __shared__ double s_hh[2];
   __shared__ double wv[kRQWaves];
   __shared__ int wi[kRQWaves];
   const int4 w = work[blockIdx.x];
   const LevelBox& B = boxes[w.x];
-#define RS_CPQR16(R, S) cpqr16_box<R, S>(B, tol, extra, k_out, kx_out, err, dyn, s_hh, wv, wi)
+#define RS_CPQR16(R, S) cpqr16_box<R, S>(B, tol, extra, k_out, kx_out, err, dyn, s_hh, wv, wi, rdg)
   switch (w.w * 8 + (B.n + 31) / 32) { RS_R16_CASES(RS_CPQR16) }
 #undef RS_CPQR16
 }
