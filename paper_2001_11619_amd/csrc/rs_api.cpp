@@ -947,6 +947,7 @@ void launch_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps, const
   }
   const int nb = (int)all.size();
   if (nb == 0) return;
+  std::unique_ptr<HTimer> plan_timer(new HTimer(c, "host:plan"));
   for (int i = 0; i < nb; ++i) all[i].slot = i;
   // Pivoted-QR routes (depend on m and n only): most boxes are reduced by
   // blocks of rows to a stack of triangular factors (which has the same
@@ -1081,6 +1082,7 @@ void launch_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps, const
     if (cape > 0) Ge = std::min({cape / nb, std::max(1, max_n / 8), kMaxCoop});
     if (Ge < 2) Ge = 1;
   }
+  plan_timer.reset();
   upload(c->ws_boxes, all, s);
   upload(c->ws_work, work, s);
   upload(c->ws_work16, work16, s);
@@ -1478,7 +1480,10 @@ void do_factor_multi(std::vector<rs_ctx*>& cs) {
       };
     }
     launch_level(cs, preps, overlap);
-    drop_redundant(l, active);
+    {
+      HTimer ht_(cs[0], "host:drop");
+      drop_redundant(l, active);
+    }
     if (speculated) {
       bool same = true;
       for (size_t i = 0; i < nc && same; ++i) {
