@@ -129,51 +129,59 @@ __global__ __launch_bounds__(kBlock) void k_assemble_abb(const LevelBox* boxes, 
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-// C = beta*C0 + alpha*op(A) op(B) on FP64 matrix cores.  32 x 32 blocks of C
-// are dealt to the G workgroups of the box; in a block each of the 4 waves
-// owns a 16 x 16 tile and accumulates v_mfma_f64_16x16x4 products over K
-// chunks of 16 staged through LDS (zero padded at the edges).  Operand lanes:
-// A[l % 16][l / 16], B[l / 16][l % 16]; result lane l, register q holds
-// row 4 q + l / 16, column l % 16 of the tile.  C0 may alias C.
-constexpr int kTB = 32;   // block edge
-constexpr int kTK = 16;   // K chunk
-
+// C = beta*C0 + alpha*op(A) op(B) on FP64 matrix cores.  The 16 x 16 tiles
+// of C are dealt to the waves of the G workgroups of the box; a wave
+// accumulates v_mfma_f64_16x16x4 products over K in groups of 4 with its
+// operands read straight from memory (the factors were just written and sit
+// in L2): no LDS staging and no workgroup barrier, and the loads of the next
+// 8 groups are issued before the products of the current ones.  Operand
+// lanes: A[l % 16][l / 16], B[l / 16][l % 16]; result lane l, register q
+// holds row 4 q + l / 16, column l % 16 of the tile.  Every tile is summed
+// in the same order whatever G is.  C0 may alias C (each element is read
+// before it is written, by the same lane).
 __device__ void mfma_gemm(int g, int G, int M, int N, int K, double alpha, const double* A,
                           int lda, bool tA, const double* B, int ldb, bool tB, double beta,
-                          const double* C0, int ldc0, double* C, int ldc, double* sA, double* sB) {
-  const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
-  const int bm = (M + kTB - 1) / kTB, bn = (N + kTB - 1) / kTB;
-  const int wr = (wid >> 1) * 16, wc = (wid & 1) * 16;
-  for (int blk = g; blk < bm * bn; blk += G) {
-    const int i0 = (blk / bn) * kTB, j0 = (blk % bn) * kTB;
-    dbl4 acc = {0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < K; k0 += kTK) {
-      for (int t = tid; t < kTB * kTK; t += blockDim.x) {
-        const int ii = t / kTK, kk = t % kTK;
-        const int gi = i0 + ii, gk = k0 + kk;
-        sA[ii * (kTK + 1) + kk] =
-            (gi < M && gk < K) ? (tA ? A[(size_t)gk * lda + gi] : A[(size_t)gi * lda + gk]) : 0.0;
-        const int kb = t / kTB, jj = t % kTB;
-        const int gk2 = k0 + kb, gj = j0 + jj;
-        sB[kb * (kTB + 1) + jj] =
-            (gk2 < K && gj < N) ? (tB ? B[(size_t)gj * ldb + gk2] : B[(size_t)gk2 * ldb + gj]) : 0.0;
-      }
-      __syncthreads();
+                          const double* C0, int ldc0, double* C, int ldc) {
+  const int lane = threadIdx.x & 63;
+  const int NW = blockDim.x >> 6, wid = threadIdx.x >> 6;
+  const int tm = (M + 15) >> 4, tn = (N + 15) >> 4;
+  const int r16 = lane & 15, kq = lane >> 4;
+  const long long sa = tA ? lda : 1, sb = tB ? 1 : ldb;
+  const int kg = (K + 3) >> 2;                  // groups of 4 along K
+  constexpr int PF = 8;                         // groups per prefetch chunk
+  for (int t = g * NW + wid; t < tm * tn; t += G * NW) {
+    const int i0 = (t / tn) << 4, j0 = (t % tn) << 4;
+    const int gi = i0 + r16, gj = j0 + r16;
+    const double* pa = tA ? A + gi : A + (size_t)gi * lda;
+    const double* pb = tB ? B + (size_t)gj * ldb : B + gj;
+    const bool va = gi < M, vb = gj < N;
+    double an[PF], bn[PF];
+    auto load = [&](int q0) {
 #pragma unroll
-      for (int kk = 0; kk < kTK; kk += 4) {
-        const double a = sA[(wr + (lane & 15)) * (kTK + 1) + kk + (lane >> 4)];
-        const double b = sB[(kk + (lane >> 4)) * (kTB + 1) + wc + (lane & 15)];
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+      for (int u = 0; u < PF; ++u) {
+        const int k = 4 * (q0 + u) + kq;
+        an[u] = (va && k < K) ? pa[k * sa] : 0.0;
+        bn[u] = (vb && k < K) ? pb[k * sb] : 0.0;
       }
-      __syncthreads();
+    };
+    dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+    load(0);
+    for (int q0 = 0; q0 < kg; q0 += PF) {
+      double ac[PF], bc[PF];
+#pragma unroll
+      for (int u = 0; u < PF; ++u) { ac[u] = an[u]; bc[u] = bn[u]; }
+      if (q0 + PF < kg) load(q0 + PF);
+#pragma unroll
+      for (int u = 0; u < PF; ++u)
+        if (q0 + u < kg) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ac[u], bc[u], acc, 0, 0, 0);
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int gi = i0 + wr + 4 * q + (lane >> 4), gj = j0 + wc + (lane & 15);
-      if (gi < M && gj < N) {
+      const int ri = i0 + 4 * q + kq, cj = j0 + r16;
+      if (ri < M && cj < N) {
         double v = alpha * acc[q];
-        if (C0) v += beta * C0[(size_t)gi * ldc0 + gj];
-        C[(size_t)gi * ldc + gj] = v;
+        if (C0) v += beta * C0[(size_t)ri * ldc0 + cj];
+        C[(size_t)ri * ldc + cj] = v;
       }
     }
   }
@@ -199,8 +207,8 @@ constexpr size_t kTSolveMax = 12288;   // T (k x r) up to this size is solved in
 // workgroup, so choosing the registers that hold them costs scalar branches,
 // not per-element selects.  The pivot is compared on a 64-bit key (|W| with
 // its low 8 mantissa bits replaced by 255 - i, ties within 2^-44 to the
-// smaller row) that the holders of column j + 1 fold into LDS with an atomic
-// max during step j.  Column 1-norms for rcond_1 are summed in a fixed order.
+// smaller row) that the holders of column j + 1 fold into LDS with one atomic
+// max each (over their own rows first) during step j.  Column 1-norms for rcond_1 are summed in a fixed order.
 // Two barriers per step.  Returns rcond_1 (0 if singular).
 // LDS: gj_lds_doubles(r) doubles at `sh`.
 __device__ __forceinline__ unsigned long long gj_key(double v, int i) {
@@ -335,11 +343,13 @@ __device__ __noinline__ double reg_gj_t(const double* X, int r, double* Xi, doub
       case B:                                                          \
         if constexpr (B < MB) {                                        \
           if (cnext) {                                                 \
+            unsigned long long best = 0ull;                            \
             _Pragma("unroll") for (int a = 0; a < MB; ++a) {           \
               const int i = ty + 16 * a;                               \
               if (i < r && !((used >> a) & 1))                         \
-                atomicMax(&keys[(j + 1) & 1], gj_key(w[a][B], i));     \
+                best = max(best, gj_key(w[a][B], i));                  \
             }                                                          \
+            atomicMax(&keys[(j + 1) & 1], best);                       \
           }                                                            \
         }                                                              \
         break;
@@ -585,8 +595,6 @@ __global__ __launch_bounds__(kBlock) void k_eliminate(const LevelBox* boxes, int
   __shared__ double red[NW];
   __shared__ int ired[NW];
   __shared__ int s_dead;
-  __shared__ double sA[kTB * (kTK + 1)];
-  __shared__ double sB[kTK * (kTB + 1)];
   const int bidx = blockIdx.x / G, g = blockIdx.x % G;
   const LevelBox& B = boxes[bidx];
   const int n = B.n;
@@ -634,14 +642,14 @@ __global__ __launch_bounds__(kBlock) void k_eliminate(const LevelBox* boxes, int
     int* piv = reinterpret_cast<int*>(Dinv + kGJP * kGJP);
     int* rowperm = piv + kGJP;
     int* flag = rowperm + r + 1;
-    mfma_gemm(g, G, k, r, k, -1.0, Ap, n, false, T, r, false, 1.0, Ap + k, n, Xsr, r, sA, sB);
-    mfma_gemm(g, G, r, k, k, -1.0, T, r, true, Ap, n, false, 1.0, Ap + (size_t)k * n, n, Xrs, k, sA, sB);
+    mfma_gemm(g, G, k, r, k, -1.0, Ap, n, false, T, r, false, 1.0, Ap + k, n, Xsr, r);
+    mfma_gemm(g, G, r, k, k, -1.0, T, r, true, Ap, n, false, 1.0, Ap + (size_t)k * n, n, Xrs, k);
     mfma_gemm(g, G, r, r, k, -1.0, Ap + (size_t)k * n, n, false, T, r, false, 1.0,
-              Ap + (size_t)k * n + k, n, Xrr, r, sA, sB);
+              Ap + (size_t)k * n + k, n, Xrr, r);
     if (g == 0 && threadIdx.x == 0) *flag = 0;
     box_barrier_full(B.bar, G, nbar, &s_dead, err);
     // X_RR -= T^T X_SR
-    mfma_gemm(g, G, r, r, k, -1.0, T, r, true, Xsr, r, false, 1.0, Xrr, r, W, r, sA, sB);
+    mfma_gemm(g, G, r, r, k, -1.0, T, r, true, Xsr, r, false, 1.0, Xrr, r, W, r);
     box_barrier_full(B.bar, G, nbar, &s_dead, err);
     double rc = 0.0;
     // the inversion algorithm depends on r only (not on G), so a box factors
@@ -675,10 +683,10 @@ __global__ __launch_bounds__(kBlock) void k_eliminate(const LevelBox* boxes, int
     }
     rc_final = rc;
     box_barrier_full(B.bar, G, nbar, &s_dead, err);
-    mfma_gemm(g, G, k, r, r, 1.0, Xsr, r, false, B.Xinv, r, false, 0.0, nullptr, 0, B.E, r, sA, sB);
-    mfma_gemm(g, G, r, k, r, 1.0, B.Xinv, r, false, Xrs, k, false, 0.0, nullptr, 0, B.F, k, sA, sB);
+    mfma_gemm(g, G, k, r, r, 1.0, Xsr, r, false, B.Xinv, r, false, 0.0, nullptr, 0, B.E, r);
+    mfma_gemm(g, G, r, k, r, 1.0, B.Xinv, r, false, Xrs, k, false, 0.0, nullptr, 0, B.F, k);
     box_barrier_full(B.bar, G, nbar, &s_dead, err);
-    mfma_gemm(g, G, k, k, r, -1.0, Xsr, r, false, B.F, k, false, 1.0, Ap, n, B.Xss, k, sA, sB);
+    mfma_gemm(g, G, k, k, r, -1.0, Xsr, r, false, B.F, k, false, 1.0, Ap, n, B.Xss, k);
     break;
   }
   if (g == 0 && threadIdx.x == 0) {
@@ -694,8 +702,6 @@ __global__ __launch_bounds__(kBlock) void k_eliminate(const LevelBox* boxes, int
 __global__ __launch_bounds__(kBlock) void k_border_w(const SolveBox* boxes, const int* ridx,
                                                      const double* Hh, int p3, double* scratch,
                                                      long long scr_stride) {
-  __shared__ double sA[kTB * (kTK + 1)];
-  __shared__ double sB[kTK * (kTB + 1)];
   const SolveBox& B = boxes[blockIdx.x];
   const int r = B.r;
   if (r == 0) return;
@@ -706,7 +712,7 @@ __global__ __launch_bounds__(kBlock) void k_border_w(const SolveBox* boxes, cons
     hr[t] = Hh[(size_t)R[i] * p3 + h];
   }
   __syncthreads();
-  mfma_gemm(0, 1, r, p3, r, 1.0, B.Xinv, r, false, hr, p3, false, 0.0, nullptr, 0, B.W, p3, sA, sB);
+  mfma_gemm(0, 1, r, p3, r, 1.0, B.Xinv, r, false, hr, p3, false, 0.0, nullptr, 0, B.W, p3);
 }
 
 // Gpart[chunk] = sum over the rows i of the chunk of Ph[R_i]^T W[i], where the
