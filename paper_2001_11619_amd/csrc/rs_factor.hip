@@ -789,6 +789,7 @@ __global__ __launch_bounds__(kBlock) void k_border_g(const int* ridx, int total_
 // returns at once when *status is set, so no pivot index of a failed panel is
 // ever used (the panel also leaves its unused entries as the identity).
 constexpr int kGJB = 32;
+static_assert(kBlock % kGJB == 0, "the panel update deals rows to kBlock / kGJB lanes");
 
 // The panel (h x bb) is factored in LDS when it fits (in_lds != 0, dynamic
 // LDS of h * bb doubles), else in the global work array W.
@@ -823,12 +824,7 @@ __global__ __launch_bounds__(kBlock) void k_gjb_panel(const double* A, int n, in
       const double v = fabs(W[(size_t)i * ldw + j]);
       if (v > best) { best = v; bi = i; }
     }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      const double ov = __shfl_xor(best, o, 64);
-      const int oi = __shfl_xor(bi, o, 64);
-      if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
-    }
+    wave_argmax(best, bi);
     if (lane == 0) { red[wid] = best; ired[wid] = bi; }
     __syncthreads();
     best = red[0];
@@ -852,12 +848,30 @@ __global__ __launch_bounds__(kBlock) void k_gjb_panel(const double* A, int n, in
     const double d = W[(size_t)j * ldw + j];
     for (int i = j + 1 + tid; i < h; i += kBlock) W[(size_t)i * ldw + j] /= d;
     __syncthreads();
-    const int rest = bb - j - 1;
-    if (rest > 0)
-      for (int t = tid; t < (h - j - 1) * rest; t += kBlock) {
-        const int i = j + 1 + t / rest, c = j + 1 + t % rest;
-        W[(size_t)i * ldw + c] -= W[(size_t)i * ldw + j] * W[(size_t)j * ldw + c];
+    // trailing update of the panel: thread (row lane tid / 32, column j + 1 +
+    // tid % 32) takes every eighth row, with its entry of row j in a register;
+    // rows go in batches of 8 (all reads, then all writes), so the LDS round
+    // trips of a batch overlap
+    const int cc = tid & (kGJB - 1), rl = tid / kGJB;
+    if (cc < bb - j - 1) {
+      constexpr int RL = kBlock / kGJB, RB = 8;
+      const int c = j + 1 + cc;
+      const double ujc = W[(size_t)j * ldw + c];
+      for (int i0 = j + 1 + rl; i0 < h; i0 += RB * RL) {
+        double wij[RB], wic[RB];
+#pragma unroll
+        for (int u = 0; u < RB; ++u) {
+          const int i = i0 + u * RL;
+          wij[u] = i < h ? W[(size_t)i * ldw + j] : 0.0;
+          wic[u] = i < h ? W[(size_t)i * ldw + c] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < RB; ++u) {
+          const int i = i0 + u * RL;
+          if (i < h) W[(size_t)i * ldw + c] = wic[u] - wij[u] * ujc;
+        }
       }
+    }
     __syncthreads();
   }
   if (singular) {
@@ -867,21 +881,20 @@ __global__ __launch_bounds__(kBlock) void k_gjb_panel(const double* A, int n, in
   // D = L U (first bb rows of W); D^{-1} = U^{-1} L^{-1}
   for (int t = tid; t < bb * bb; t += kBlock) lu[t / bb][t % bb] = W[(size_t)(t / bb) * ldw + t % bb];
   __syncthreads();
-  // columns of L^{-1} (unit lower) then U^{-1} applied: one thread per column
+  // columns of L^{-1} (unit lower) then U^{-1} applied: one thread per
+  // column, which it builds in place in its column of inv
   if (tid < bb) {
     const int c = tid;
-    double y[kGJB];
     for (int i = 0; i < bb; ++i) {
       double s = (i == c) ? 1.0 : 0.0;
-      for (int l = 0; l < i; ++l) s -= lu[i][l] * y[l];
-      y[i] = s;
+      for (int l = 0; l < i; ++l) s -= lu[i][l] * inv[l][c];
+      inv[i][c] = s;
     }
     for (int i = bb - 1; i >= 0; --i) {
-      double s = y[i];
-      for (int l = i + 1; l < bb; ++l) s -= lu[i][l] * y[l];
-      y[i] = s / lu[i][i];
+      double s = inv[i][c];
+      for (int l = i + 1; l < bb; ++l) s -= lu[i][l] * inv[l][c];
+      inv[i][c] = s / lu[i][i];
     }
-    for (int i = 0; i < bb; ++i) inv[i][c] = y[i];
   }
   __syncthreads();
   for (int t = tid; t < bb * bb; t += kBlock) Dinv[t] = inv[t / bb][t % bb];
