@@ -191,20 +191,44 @@ __global__ __launch_bounds__(256) void k_sum_parts(const double* parts, int npar
   }
 }
 
-// parts[box] (3p x ncols) = Ph_R^T c_R (accumulated in float64)
+// parts[box] (3p x ncols) = Ph_R^T c_R (accumulated in float64).  When the
+// outputs are fewer than half the threads, the rows of R are split into
+// nseg = kBlock / (3p ncols) interleaved segments (segment g takes rows
+// g, g + nseg, ...), whose sums are added in segment order: the result
+// depends on 3p and ncols only.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_border_rhs(const SolveBox* boxes, const int* ridx,
                                                        const T* Ph, int p3, const T* c, int ncols,
                                                        double* parts) {
+  __shared__ double seg[kBlock];
   const SolveBox& B = boxes[blockIdx.x];
   double* out = parts + (size_t)B.part * p3 * ncols;
   const int* R = ridx + B.r_off;
-  for (int t = threadIdx.x; t < p3 * ncols; t += kBlock) {
-    const int h = t / ncols, q = t % ncols;
-    double acc = 0.0;
-    for (int i = 0; i < B.r; ++i)
+  const int nout = p3 * ncols;
+  const int nseg = nout <= kBlock / 2 ? kBlock / nout : 1;
+  if (nseg == 1) {
+    for (int t = threadIdx.x; t < nout; t += kBlock) {
+      const int h = t / ncols, q = t % ncols;
+      double acc = 0.0;
+      for (int i = 0; i < B.r; ++i)
+        acc += (double)Ph[(size_t)R[i] * p3 + h] * (double)c[(size_t)R[i] * ncols + q];
+      out[t] = acc;
+    }
+    return;
+  }
+  const int t = threadIdx.x, o = t % nout, g = t / nout;
+  double acc = 0.0;
+  if (g < nseg) {
+    const int h = o / ncols, q = o % ncols;
+    for (int i = g; i < B.r; i += nseg)
       acc += (double)Ph[(size_t)R[i] * p3 + h] * (double)c[(size_t)R[i] * ncols + q];
-    out[t] = acc;
+  }
+  seg[t] = acc;
+  __syncthreads();
+  if (t < nout) {
+    double sum = seg[t];
+    for (int gg = 1; gg < nseg; ++gg) sum += seg[gg * nout + t];
+    out[t] = sum;
   }
 }
 
@@ -377,17 +401,20 @@ __global__ void k_from_rows(const double* c, int nrows, int ncols, double* x, in
 }  // namespace
 
 // Right-hand-side columns per block so that `rows` rows fit in 64 KiB of LDS.
-inline int chunk_cols(int rows) {
+// Columns per block of the sweep and diagonal kernels: at most kNC, within
+// 64 KB of staged rows, and no more than the columns there are (the kernels'
+// per-column work is not spent on padding).
+inline int chunk_cols(int rows, int ncols) {
   int nc = kNC;
   while (nc > 1 && (size_t)rows * nc * sizeof(double) > 65536) nc >>= 1;
-  return nc;
+  return std::min(nc, std::max(ncols, 1));
 }
 
 template <typename T>
 void launch_sweep(const SolveBox* boxes, int nbox, const int* sidx, const int* ridx, T* c,
                   int ncols, int mode, int max_n, hipStream_t s) {
   if (nbox == 0 || ncols == 0) return;
-  const int nc = chunk_cols(max_n);
+  const int nc = chunk_cols(max_n, ncols);
   dim3 grid(nbox, blocks_for(ncols, nc));
   const size_t shm = (size_t)max_n * nc * sizeof(T);
   hipLaunchKernelGGL(k_sweep<T>, grid, dim3(kBlock), shm, s, boxes, sidx, ridx, c, ncols, mode, nc);
@@ -399,7 +426,7 @@ template <typename T>
 void launch_diag(const SolveBox* boxes, int nbox, const int* ridx, T* c, int ncols, int max_r,
                  hipStream_t s) {
   if (nbox == 0 || ncols == 0) return;
-  const int nc = chunk_cols(2 * max_r);
+  const int nc = chunk_cols(2 * max_r, ncols);
   dim3 grid(nbox, blocks_for(ncols, nc));
   const size_t shm = (size_t)2 * max_r * nc * sizeof(T);
   hipLaunchKernelGGL(k_diag<T>, grid, dim3(kBlock), shm, s, boxes, ridx, c, ncols, nc);
