@@ -186,6 +186,9 @@ inline long long key2(long long ix, long long iy) { return (ix << 32) ^ (iy & 0x
 
 struct rs_ctx {
   rs_params prm{};
+  // host clock at the end of the previous level's read-back (timing only)
+  std::chrono::steady_clock::time_point level_done{};
+  bool level_done_set = false;
   int N = 0, p = 0;
   std::vector<double> x, y, nx, ny, w, kap, hole;
   std::vector<int> curve;
@@ -1094,6 +1097,12 @@ void launch_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps, const
   c->ws_rc.ensure(nb * sizeof(double));
   c->ws_err.ensure(sizeof(int) * 4);
   const LevelBox* dlb = c->ws_boxes.as<LevelBox>();
+  if (c->timing && c->level_done_set) {
+    const int fam = family(c, "host:between_levels");
+    c->fam_ms[fam] += 1e3 * std::chrono::duration<double>(std::chrono::steady_clock::now() - c->level_done).count();
+    c->fam_launches[fam] += 1;
+    c->level_done_set = false;
+  }
   {
     KTimer kt_(c, "assemble_M");
     launch_assemble_M(dlb, nb, max_m, prm.n_proxy, prm.proxy_ratio, s);
@@ -1173,14 +1182,17 @@ void launch_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps, const
   if (overlap) {
     {
       HTimer ht_(c, "host:level_wait");
+      HTimer ht2_(c, "host:qr_wait");
       HIP_CHECK(hipEventSynchronize(c->ev_qr));
     }
     for (size_t i = 0; i < cs.size(); ++i)
       if (hperm[i]) preps[i].perm.assign(hperm[i], hperm[i] + preps[i].doff.back() + preps[i].lb.back().n);
+    HTimer ht_(c, "host:speculate");
     overlap(k0);
   }
   {
     HTimer ht_(c, "host:level_wait");
+    HTimer ht2_(c, overlap ? "host:elim_wait" : "host:last_wait");
     HIP_CHECK(hipStreamSynchronize(s));
   }
   for (size_t i = 0; i < cs.size(); ++i)
@@ -1193,6 +1205,10 @@ void launch_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps, const
     if (P.lb.empty()) continue;
     std::vector<int> done;
     finish_level(cs[i], P, k0 + P.first, kk + P.first, st + P.first, hrc + P.first, done);
+  }
+  if (c->timing) {
+    c->level_done = std::chrono::steady_clock::now();
+    c->level_done_set = true;
   }
 }
 
@@ -1413,6 +1429,7 @@ void release_all_arenas(rs_ctx* c) {
 void do_factor_multi(std::vector<rs_ctx*>& cs) {
   auto t0 = std::chrono::steady_clock::now();
   const size_t nc = cs.size();
+  for (rs_ctx* c : cs) c->level_done_set = false;
   int L = 0;
   std::vector<std::vector<char>> active(nc);
   std::vector<std::vector<std::vector<int>>> by_level(nc);
