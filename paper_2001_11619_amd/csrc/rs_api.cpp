@@ -251,6 +251,11 @@ struct rs_ctx {
   int refine_last = 0;            // iterations in the last launch
   DevBuf d_flag;                  // [converged, corrections applied]
   hipEvent_t ev_qr = nullptr;     // a level's QR ranks and pivot orders have reached the host
+  // second stream of a level's pivoted QR: the cooperative and memory-route
+  // launches run beside the row-reduced boxes (fork after assembly, join before
+  // A_BB)
+  hipStream_t side_stream = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   PinHost h_flag;
 
   // kernel timing (HIP events around launches)
@@ -267,6 +272,9 @@ struct rs_ctx {
     if (refine_exec) (void)hipGraphExecDestroy(refine_exec);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
     if (ev_qr) (void)hipEventDestroy(ev_qr);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (side_stream) (void)hipStreamDestroy(side_stream);
     for (auto& p : pending) {
       (void)hipEventDestroy(p.a);
       (void)hipEventDestroy(p.b);
@@ -313,10 +321,13 @@ int family(rs_ctx* c, const char* name) {
 // Brackets one launch (or a group of launches) with events when timing is on.
 struct KTimer {
   rs_ctx* c;
+  hipStream_t st;
   int fam = -1;
   hipEvent_t a{};
-  // detail: a sub-phase, timed only in per-level mode
-  KTimer(rs_ctx* ctx, const char* name, bool detail = false) : c(ctx) {
+  // detail: a sub-phase, timed only in per-level mode; on: the stream the
+  // phase is launched on (the context's stream when null)
+  KTimer(rs_ctx* ctx, const char* name, bool detail = false, hipStream_t on = nullptr)
+      : c(ctx), st(on ? on : ctx->stream) {
     if (!c->timing || c->capturing || (detail && c->timing != 2)) return;
     if (c->timing == 2 && c->cur_level >= 0) {
       const std::string full = std::string(name) + "@L" + std::to_string(c->cur_level);
@@ -325,7 +336,7 @@ struct KTimer {
       fam = family(c, name);
     }
     a = take_event(c);
-    HIP_CHECK(hipEventRecord(a, c->stream));
+    HIP_CHECK(hipEventRecord(a, st));
   }
   ~KTimer() {
     if (fam < 0) return;
@@ -336,7 +347,7 @@ struct KTimer {
     } else if (hipEventCreate(&b) != hipSuccess) {
       return;
     }
-    if (hipEventRecord(b, c->stream) == hipSuccess) c->pending.push_back({fam, a, b});
+    if (hipEventRecord(b, st) == hipSuccess) c->pending.push_back({fam, a, b});
   }
 };
 
@@ -1110,10 +1121,6 @@ void launch_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps, const
   {
     KTimer kt_(c, "cpqr");
     launch_zero_bars(dlb, nb, c->ws_err.as<int>(), s);
-    for (size_t r = 0; r + 1 < round_first.size(); ++r) {
-      KTimer kt2_(c, "cpqr.rows", true);
-      launch_tsqr(c->ws_tasks.as<QRTask>() + round_first[r], round_first[r + 1] - round_first[r], s);
-    }
     const int4* dw = c->ws_work.as<int4>();
     const int nA = coop.empty() ? (int)work.size() : coop.front().first;
     auto check = [&](hipError_t e, const char* what, int blocks) {
@@ -1121,6 +1128,36 @@ void launch_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps, const
         throw RsError{RS_ERR_DEVICE, std::string("pivoted-QR launch failed (") + what + ", " +
                                          hipGetErrorString(e) + ", blocks " + std::to_string(blocks) + ")"};
     };
+    // The few boxes of the cooperative and memory routes (wide or tall M_B)
+    // are factored on a second stream while the row-reduced boxes are: their
+    // boxes, rank slots and barrier words are disjoint, so the results do not
+    // depend on the overlap.
+    const bool side = !coop.empty() || nfb > 0;
+    hipStream_t s2 = s;
+    if (side) {
+      if (!c->side_stream) HIP_CHECK(hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking));
+      if (!c->ev_fork) HIP_CHECK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+      if (!c->ev_join) HIP_CHECK(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+      s2 = c->side_stream;
+      HIP_CHECK(hipEventRecord(c->ev_fork, s));
+      HIP_CHECK(hipStreamWaitEvent(s2, c->ev_fork, 0));
+      for (const auto& ch : coop) {
+        KTimer kt2_(c, "cpqr.coop", true, s2);
+        check(launch_cpqr_reg(dlb, dw + ch.first, ch.second, true, prm.tol, kGuardExtra, c->ws_k.as<int>(),
+                              c->ws_kx.as<int>(), c->ws_err.as<int>(), rq_lds, s2), "register, cooperative",
+              ch.second);
+      }
+      {
+        KTimer kt2_(c, "cpqr.mem", true, s2);
+        check(launch_cpqr(dlb, c->ws_fblist.as<int>(), nfb, G, prm.tol, kGuardExtra, c->ws_k.as<int>(),
+                          c->ws_kx.as<int>(), c->ws_err.as<int>(), fb_m, fb_n, s2), "memory", nfb * G);
+      }
+      HIP_CHECK(hipEventRecord(c->ev_join, s2));
+    }
+    for (size_t r = 0; r + 1 < round_first.size(); ++r) {
+      KTimer kt2_(c, "cpqr.rows", true);
+      launch_tsqr(c->ws_tasks.as<QRTask>() + round_first[r], round_first[r + 1] - round_first[r], s);
+    }
     {
       KTimer kt2_(c, "cpqr.r16", true);
       check(launch_cpqr16(dlb, c->ws_work16.as<int4>(), (int)work16.size(), prm.tol, kGuardExtra,
@@ -1132,17 +1169,7 @@ void launch_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps, const
       check(launch_cpqr_reg(dlb, dw, nA, false, prm.tol, kGuardExtra, c->ws_k.as<int>(), c->ws_kx.as<int>(),
                             c->ws_err.as<int>(), rq_lds, s), "register", nA);
     }
-    for (const auto& ch : coop) {
-      KTimer kt2_(c, "cpqr.coop", true);
-      check(launch_cpqr_reg(dlb, dw + ch.first, ch.second, true, prm.tol, kGuardExtra, c->ws_k.as<int>(),
-                            c->ws_kx.as<int>(), c->ws_err.as<int>(), rq_lds, s), "register, cooperative",
-            ch.second);
-    }
-    {
-      KTimer kt2_(c, "cpqr.mem", true);
-      check(launch_cpqr(dlb, c->ws_fblist.as<int>(), nfb, G, prm.tol, kGuardExtra, c->ws_k.as<int>(),
-                        c->ws_kx.as<int>(), c->ws_err.as<int>(), fb_m, fb_n, s), "memory", nfb * G);
-    }
+    if (side) HIP_CHECK(hipStreamWaitEvent(s, c->ev_join, 0));
   }
   {
     KTimer kt_(c, "assemble_abb");
