@@ -1573,10 +1573,14 @@ void solve_rows(rs_ctx* c, T* cbuf, int ncols, const double* rbot) {
   const int p3 = 3 * c->p;
   const int n0 = (int)c->I0.size();
   sweep_all<T>(c, cbuf, ncols, 0);
-  for (int l = c->L; l >= 1; --l) {
+  // The diagonal blocks, the border right-hand side and the border fix touch
+  // only each box's own R rows (disjoint over all levels) and its own partial
+  // slot: one launch over the boxes of every level (stored level after level).
+  const SolveBox* all_sb = level_sboxes(c, 1);
+  const int all_nb = c->L >= 1 ? (int)(c->sbox_off[c->L + 1] - c->sbox_off[1]) : 0;
+  {
     KTimer kt_(c, "diag");
-    launch_diag<T>(level_sboxes(c, l), level_count(c, l), c->d_ridx.as<int>(), cbuf, ncols,
-                   c->lvl_maxr[l], s);
+    launch_diag<T>(all_sb, all_nb, c->d_ridx.as<int>(), cbuf, ncols, c->all_maxr, s);
   }
   const int nz = c->nz;
   c->d_v.ensure(std::max<size_t>((size_t)nz * ncols, 1) * sizeof(double));
@@ -1585,10 +1589,10 @@ void solve_rows(rs_ctx* c, T* cbuf, int ncols, const double* rbot) {
   if (p3) {
     const int nsb = c->n_solve_boxes;
     c->d_parts.ensure(std::max<size_t>((size_t)nsb * p3 * ncols, 1) * sizeof(double));
-    for (int l = c->L; l >= 1; --l) {
+    {
       KTimer kt_(c, "border_rhs");
-      launch_border_rhs<T>(level_sboxes(c, l), level_count(c, l), c->d_ridx.as<int>(), c->d_Ph.as<double>(),
-                           p3, cbuf, ncols, c->d_parts.as<double>(), s);
+      launch_border_rhs<T>(all_sb, all_nb, c->d_ridx.as<int>(), c->d_Ph.as<double>(), p3, cbuf, ncols,
+                           c->d_parts.as<double>(), s);
     }
     c->d_rhs2.ensure((size_t)p3 * ncols * sizeof(double));
     launch_sum_parts(c->d_parts.as<double>(), nsb, (long long)p3 * ncols, p3 * ncols, -1.0,
@@ -1607,10 +1611,9 @@ void solve_rows(rs_ctx* c, T* cbuf, int ncols, const double* rbot) {
   }
   if (p3) {
     const double* lam = c->d_sol.as<double>() + (size_t)n0 * ncols;
-    for (int l = c->L; l >= 1; --l) {
+    {
       KTimer kt_(c, "border_fix");
-      launch_border_fix<T>(level_sboxes(c, l), level_count(c, l), c->d_ridx.as<int>(), p3, lam,
-                           cbuf, ncols, s);
+      launch_border_fix<T>(all_sb, all_nb, c->d_ridx.as<int>(), p3, lam, cbuf, ncols, s);
     }
     // lambda rows follow the 2N density rows
     T* dst = cbuf + (size_t)2 * c->N * ncols;
