@@ -947,6 +947,8 @@ int qr_route(int m, int n, int& h, std::vector<int>& P) {
 // (in each LevelPrep::perm) have arrived.
 using LevelOverlap = std::function<void(const int* qr_rank)>;
 
+constexpr size_t kBorderScratchMax = 64ull << 20;   // gather scratch of one border launch
+
 void launch_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps, const LevelOverlap& overlap) {
   rs_ctx* c = cs[0];
   const rs_params& prm = c->prm;
@@ -1388,15 +1390,24 @@ void factor_root(rs_ctx* c) {
     sweep_all(c, c->d_Hh.as<double>(), p3, 0);
     sweep_all(c, c->d_Ph.as<double>(), p3, 1);
     // W_B of every box, then G = sum_B (Psi^T V)_R W_B as one gathered product
+    // W_B of each box is independent of the others: one launch over the boxes
+    // of every level when their gather scratch (one slot per box) stays within
+    // kBorderScratchMax bytes, else one launch per level
     const long long scr_stride = std::max<long long>((long long)c->all_maxr * p3, 1);
+    const int all_nb = c->L >= 1 ? (int)(c->sbox_off[c->L + 1] - c->sbox_off[1]) : 0;
+    const bool one_launch = (size_t)std::max(all_nb, 1) * scr_stride * sizeof(double) <= kBorderScratchMax;
     int max_nb = 1;
     for (int l = 1; l <= c->L; ++l) max_nb = std::max(max_nb, level_count(c, l));
-    c->d_bscr.ensure((size_t)max_nb * scr_stride * sizeof(double));
+    c->d_bscr.ensure((size_t)(one_launch ? std::max(all_nb, 1) : max_nb) * scr_stride * sizeof(double));
     {
       KTimer kt_(c, "border_box");
-      for (int l = c->L; l >= 1; --l)
-        launch_border_w(level_sboxes(c, l), level_count(c, l), c->d_ridx.as<int>(), c->d_Hh.as<double>(), p3,
+      if (one_launch)
+        launch_border_w(level_sboxes(c, 1), all_nb, c->d_ridx.as<int>(), c->d_Hh.as<double>(), p3,
                         c->d_bscr.as<double>(), scr_stride, s);
+      else
+        for (int l = c->L; l >= 1; --l)
+          launch_border_w(level_sboxes(c, l), level_count(c, l), c->d_ridx.as<int>(), c->d_Hh.as<double>(), p3,
+                          c->d_bscr.as<double>(), scr_stride, s);
       const int nch = border_g_chunks(c->n_ridx, p3);
       c->d_Gpart.ensure((size_t)nch * p3 * p3 * sizeof(double));
       launch_border_g(c->d_ridx.as<int>(), c->n_ridx, c->d_Ph.as<double>(), c->d_W.as<double>(), p3, nch,
@@ -1404,9 +1415,7 @@ void factor_root(rs_ctx* c) {
       c->d_G.ensure((size_t)p3 * p3 * sizeof(double));
       launch_sum_parts(c->d_Gpart.as<double>(), nch, (long long)p3 * p3, p3 * p3, 1.0, c->d_G.as<double>(), s);
     }
-    if (c->prm.precision == 1) {
-      for (int l = c->L; l >= 1; --l) launch_w_to_float(level_sboxes(c, l), level_count(c, l), p3, s);
-    }
+    if (c->prm.precision == 1) launch_w_to_float(level_sboxes(c, 1), all_nb, p3, s);
     c->d_Z.ensure((size_t)nz * nz * sizeof(double));
     {
       KTimer kt_(c, "root_Z");
