@@ -949,6 +949,21 @@ using LevelOverlap = std::function<void(const int* qr_rank)>;
 
 constexpr size_t kBorderScratchMax = 64ull << 20;   // gather scratch of one border launch
 
+// The context's second stream, made to wait for everything enqueued so far on
+// its main stream (ev_fork); join_side makes the main stream wait for it.
+hipStream_t fork_side(rs_ctx* c) {
+  if (!c->side_stream) HIP_CHECK(hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking));
+  if (!c->ev_fork) HIP_CHECK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+  if (!c->ev_join) HIP_CHECK(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+  HIP_CHECK(hipEventRecord(c->ev_fork, c->stream));
+  HIP_CHECK(hipStreamWaitEvent(c->side_stream, c->ev_fork, 0));
+  return c->side_stream;
+}
+void join_side(rs_ctx* c) {
+  HIP_CHECK(hipEventRecord(c->ev_join, c->side_stream));
+  HIP_CHECK(hipStreamWaitEvent(c->stream, c->ev_join, 0));
+}
+
 void launch_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps, const LevelOverlap& overlap) {
   rs_ctx* c = cs[0];
   const rs_params& prm = c->prm;
@@ -1135,14 +1150,8 @@ void launch_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps, const
     // boxes, rank slots and barrier words are disjoint, so the results do not
     // depend on the overlap.
     const bool side = !coop.empty() || nfb > 0;
-    hipStream_t s2 = s;
     if (side) {
-      if (!c->side_stream) HIP_CHECK(hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking));
-      if (!c->ev_fork) HIP_CHECK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
-      if (!c->ev_join) HIP_CHECK(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
-      s2 = c->side_stream;
-      HIP_CHECK(hipEventRecord(c->ev_fork, s));
-      HIP_CHECK(hipStreamWaitEvent(s2, c->ev_fork, 0));
+      hipStream_t s2 = fork_side(c);
       for (const auto& ch : coop) {
         KTimer kt2_(c, "cpqr.coop", true, s2);
         check(launch_cpqr_reg(dlb, dw + ch.first, ch.second, true, prm.tol, kGuardExtra, c->ws_k.as<int>(),
@@ -1154,7 +1163,6 @@ void launch_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps, const
         check(launch_cpqr(dlb, c->ws_fblist.as<int>(), nfb, G, prm.tol, kGuardExtra, c->ws_k.as<int>(),
                           c->ws_kx.as<int>(), c->ws_err.as<int>(), fb_m, fb_n, s2), "memory", nfb * G);
       }
-      HIP_CHECK(hipEventRecord(c->ev_join, s2));
     }
     for (size_t r = 0; r + 1 < round_first.size(); ++r) {
       KTimer kt2_(c, "cpqr.rows", true);
@@ -1171,7 +1179,7 @@ void launch_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps, const
       check(launch_cpqr_reg(dlb, dw, nA, false, prm.tol, kGuardExtra, c->ws_k.as<int>(), c->ws_kx.as<int>(),
                             c->ws_err.as<int>(), rq_lds, s), "register", nA);
     }
-    if (side) HIP_CHECK(hipStreamWaitEvent(s, c->ev_join, 0));
+    if (side) join_side(c);
   }
   {
     KTimer kt_(c, "assemble_abb");
@@ -1328,17 +1336,18 @@ const SolveBox* level_sboxes(const rs_ctx* c, int l) {
 int level_count(const rs_ctx* c, int l) { return (int)(c->sbox_off[l + 1] - c->sbox_off[l]); }
 
 template <typename T>
-void sweep_all(rs_ctx* c, T* buf, int ncols, int mode) {
+void sweep_all(rs_ctx* c, T* buf, int ncols, int mode, hipStream_t on = nullptr) {
   const int L = c->L;
-  KTimer kt_(c, mode == 0 ? "sweep_U" : (mode == 1 ? "sweep_PsiV" : "sweep_V"));
+  hipStream_t st = on ? on : c->stream;
+  KTimer kt_(c, mode == 0 ? "sweep_U" : (mode == 1 ? "sweep_PsiV" : "sweep_V"), false, st);
   if (mode == 2) {
     for (int l = 1; l <= L; ++l)
       launch_sweep(level_sboxes(c, l), level_count(c, l), c->d_sidx.as<int>(), c->d_ridx.as<int>(),
-                   buf, ncols, mode, c->lvl_maxn[l], c->stream);
+                   buf, ncols, mode, c->lvl_maxn[l], st);
   } else {
     for (int l = L; l >= 1; --l)
       launch_sweep(level_sboxes(c, l), level_count(c, l), c->d_sidx.as<int>(), c->d_ridx.as<int>(),
-                   buf, ncols, mode, c->lvl_maxn[l], c->stream);
+                   buf, ncols, mode, c->lvl_maxn[l], st);
   }
 }
 
@@ -1387,8 +1396,11 @@ void factor_root(rs_ctx* c) {
       launch_assemble_H(g, c->d_hole.as<double>(), c->p, c->d_curve.as<int>(), c->d_Hh.as<double>(),
                         c->d_Ph.as<double>(), s);
     }
+    // the Psi^T V rows are swept on the second stream beside the U sweep of
+    // the border columns and the W blocks (which read only the latter)
+    hipStream_t s2 = fork_side(c);
+    sweep_all(c, c->d_Ph.as<double>(), p3, 1, s2);
     sweep_all(c, c->d_Hh.as<double>(), p3, 0);
-    sweep_all(c, c->d_Ph.as<double>(), p3, 1);
     // W_B of every box, then G = sum_B (Psi^T V)_R W_B as one gathered product
     // W_B of each box is independent of the others: one launch over the boxes
     // of every level when their gather scratch (one slot per box) stays within
@@ -1408,6 +1420,7 @@ void factor_root(rs_ctx* c) {
         for (int l = c->L; l >= 1; --l)
           launch_border_w(level_sboxes(c, l), level_count(c, l), c->d_ridx.as<int>(), c->d_Hh.as<double>(), p3,
                           c->d_bscr.as<double>(), scr_stride, s);
+      join_side(c);   // Psi^T V rows
       const int nch = border_g_chunks(c->n_ridx, p3);
       c->d_Gpart.ensure((size_t)nch * p3 * p3 * sizeof(double));
       launch_border_g(c->d_ridx.as<int>(), c->n_ridx, c->d_Ph.as<double>(), c->d_W.as<double>(), p3, nch,
