@@ -215,6 +215,8 @@ struct rs_ctx {
   PinHost h_rank, h_perm, h_small, h_rc;  // pinned read-back buffers
   const OldState* old = nullptr;  // set while an update runs
   // level workspaces (reused level to level)
+  DevBuf ws_boxes_b;   // descriptors of the other level parity (pre-launch beside an elimination)
+  int desc_flip = 0;
   DevBuf ws_M, ws_R, ws_A, ws_scr, ws_boxes, ws_dofs, ws_fint, ws_src, ws_perm, ws_k, ws_kx,
       ws_status, ws_coop, ws_err, ws_work, ws_fblist, ws_tasks, ws_tq, ws_work16, ws_rc;
   int n_cu = 0;                   // compute units of the device
@@ -256,6 +258,7 @@ struct rs_ctx {
   // A_BB)
   hipStream_t side_stream = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipEvent_t ev_pre = nullptr;    // the next level's assembly and row reduction are done (second stream)
   PinHost h_flag;
 
   // kernel timing (HIP events around launches)
@@ -274,6 +277,7 @@ struct rs_ctx {
     if (ev_qr) (void)hipEventDestroy(ev_qr);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
+    if (ev_pre) (void)hipEventDestroy(ev_pre);
     if (side_stream) (void)hipStreamDestroy(side_stream);
     for (auto& p : pending) {
       (void)hipEventDestroy(p.a);
@@ -369,8 +373,14 @@ struct HTimer {
 };
 
 // Resolve recorded event pairs; call after the stream has been synchronised.
+// Pairs on the second stream that have not completed yet stay pending.
 void resolve_timers(rs_ctx* c) {
+  std::vector<decltype(c->pending)::value_type> keep;
   for (auto& p : c->pending) {
+    if (hipEventQuery(p.b) == hipErrorNotReady) {
+      keep.push_back(p);
+      continue;
+    }
     float ms = 0.f;
     HIP_CHECK(hipEventElapsedTime(&ms, p.a, p.b));
     c->fam_ms[p.fam] += ms;
@@ -378,7 +388,7 @@ void resolve_timers(rs_ctx* c) {
     c->event_pool.push_back(p.a);
     c->event_pool.push_back(p.b);
   }
-  c->pending.clear();
+  c->pending.swap(keep);
 }
 
 // Leaf unknowns and the near-box lists of every box (static for a tree).  A
@@ -698,10 +708,10 @@ std::unique_ptr<DevBuf> take_arena(rs_ctx* c, size_t bytes) {
 // Host part of one level for one context: unknowns, near fields, reuse
 // decisions, workspace and arena allocation, uploads of the index lists.
 void prepare_level(rs_ctx* c, int l, const std::vector<int>& ids, const std::vector<char>& active,
-                   LevelPrep& P) {
+                   LevelPrep& P, hipStream_t up = nullptr) {
   HTimer ht_(c, "host:prepare");
   const rs_params& prm = c->prm;
-  hipStream_t s = c->stream;
+  hipStream_t s = up ? up : c->stream;     // stream of the index-list uploads
   Geo g;
   geo_of(c, g);
   P = LevelPrep();
@@ -964,10 +974,23 @@ void join_side(rs_ctx* c) {
   HIP_CHECK(hipStreamWaitEvent(c->stream, c->ev_join, 0));
 }
 
-void launch_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps, const LevelOverlap& overlap) {
+struct LevelPlan {
+  std::vector<LevelBox> all;
+  int nb = 0, max_m = 0, max_n = 0;
+  std::vector<QRTask> tasks;
+  std::vector<int> round_first;
+  std::vector<int4> work16, work;
+  std::vector<int> fb;
+  std::vector<std::pair<int, int>> coop;   // (first work item, count) of each cooperative launch
+  int fb_m = 0, fb_n = 0, G = 1, Ge = 1;
+  size_t rq_lds = 0;
+  DevBuf* desc = nullptr;                  // device copy of `all`
+};
+
+// Host plan of a level launch: descriptors, QR routes and tasks, workgroups per box.
+void plan_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps, LevelPlan& P) {
   rs_ctx* c = cs[0];
   const rs_params& prm = c->prm;
-  hipStream_t s = c->stream;
   std::vector<LevelBox> all;
   int max_m = 0, max_n = 0;
   for (size_t i = 0; i < cs.size(); ++i) {
@@ -977,6 +1000,7 @@ void launch_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps, const
     max_n = std::max(max_n, preps[i].max_n);
   }
   const int nb = (int)all.size();
+  P.nb = nb;
   if (nb == 0) return;
   std::unique_ptr<HTimer> plan_timer(new HTimer(c, "host:plan"));
   for (int i = 0; i < nb; ++i) all[i].slot = i;
@@ -1114,26 +1138,85 @@ void launch_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps, const
     if (Ge < 2) Ge = 1;
   }
   plan_timer.reset();
-  upload(c->ws_boxes, all, s);
+  P.all = std::move(all);
+  P.max_m = max_m;
+  P.max_n = max_n;
+  P.tasks = std::move(tasks);
+  P.round_first = std::move(round_first);
+  P.work16 = std::move(work16);
+  P.work = std::move(work);
+  P.fb = std::move(fb);
+  P.coop = std::move(coop);
+  P.fb_m = fb_m;
+  P.fb_n = fb_n;
+  P.rq_lds = rq_lds;
+  P.G = G;
+  P.Ge = Ge;
+  c->desc_flip ^= 1;
+  P.desc = c->desc_flip ? &c->ws_boxes_b : &c->ws_boxes;
+}
+
+// Matrix assembly and row reduction of a planned level on stream st: they read
+// the geometry, the level's index lists and M_B only, so while level l is
+// eliminated they can already run for level l - 1 (on the second stream).
+void pre_launch(std::vector<rs_ctx*>& cs, LevelPlan& P, hipStream_t st) {
+  rs_ctx* c = cs[0];
+  const rs_params& prm = c->prm;
+  upload(*P.desc, P.all, st);
+  upload(c->ws_tasks, P.tasks, st);
+  const LevelBox* dlb = P.desc->as<LevelBox>();
+  {
+    KTimer kt_(c, "assemble_M", false, st);
+    launch_assemble_M(dlb, P.nb, P.max_m, prm.n_proxy, prm.proxy_ratio, st);
+  }
+  if (P.round_first.size() > 1) {
+    KTimer kt_(c, "cpqr", false, st);
+    for (size_t r = 0; r + 1 < P.round_first.size(); ++r) {
+      KTimer kt2_(c, "cpqr.rows", true, st);
+      launch_tsqr(c->ws_tasks.as<QRTask>() + P.round_first[r], P.round_first[r + 1] - P.round_first[r], st);
+    }
+  }
+}
+
+// The rest of a level: pivoted QR, A_BB, elimination and the read-backs.  With
+// pre == null the level is planned and pre-launched here first; otherwise the
+// main stream waits for the pre-launch on the second stream (ev_pre).
+void launch_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps, LevelPlan* pre,
+                  const LevelOverlap& overlap) {
+  rs_ctx* c = cs[0];
+  const rs_params& prm = c->prm;
+  hipStream_t s = c->stream;
+  LevelPlan own;
+  if (!pre) {
+    plan_level(cs, preps, own);
+    if (own.nb == 0) return;
+    pre_launch(cs, own, s);
+    pre = &own;
+  } else {
+    HIP_CHECK(hipStreamWaitEvent(s, c->ev_pre, 0));
+    if (pre->nb == 0) return;
+  }
+  LevelPlan& P = *pre;
+  const int nb = P.nb, max_n = P.max_n, fb_m = P.fb_m, fb_n = P.fb_n, G = P.G, Ge = P.Ge;
+  const size_t rq_lds = P.rq_lds;
+  const std::vector<int4>& work = P.work;
+  const std::vector<int>& fb = P.fb;
+  const std::vector<std::pair<int, int>>& coop = P.coop;
+  const int nfb = (int)fb.size();
   upload(c->ws_work, work, s);
-  upload(c->ws_work16, work16, s);
-  upload(c->ws_tasks, tasks, s);
+  upload(c->ws_work16, P.work16, s);
   upload(c->ws_fblist, fb, s);
   c->ws_k.ensure(nb * sizeof(int));
   c->ws_kx.ensure(nb * sizeof(int));
   c->ws_status.ensure(nb * sizeof(int));
   c->ws_rc.ensure(nb * sizeof(double));
   c->ws_err.ensure(sizeof(int) * 4);
-  const LevelBox* dlb = c->ws_boxes.as<LevelBox>();
+  const LevelBox* dlb = P.desc->as<LevelBox>();
   if (c->timing && c->level_done_set) {
     const int fam = family(c, "host:between_levels");
     c->fam_ms[fam] += 1e3 * std::chrono::duration<double>(std::chrono::steady_clock::now() - c->level_done).count();
     c->fam_launches[fam] += 1;
     c->level_done_set = false;
-  }
-  {
-    KTimer kt_(c, "assemble_M");
-    launch_assemble_M(dlb, nb, max_m, prm.n_proxy, prm.proxy_ratio, s);
   }
   {
     KTimer kt_(c, "cpqr");
@@ -1164,15 +1247,11 @@ void launch_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps, const
                           c->ws_kx.as<int>(), c->ws_err.as<int>(), fb_m, fb_n, s2), "memory", nfb * G);
       }
     }
-    for (size_t r = 0; r + 1 < round_first.size(); ++r) {
-      KTimer kt2_(c, "cpqr.rows", true);
-      launch_tsqr(c->ws_tasks.as<QRTask>() + round_first[r], round_first[r + 1] - round_first[r], s);
-    }
     {
       KTimer kt2_(c, "cpqr.r16", true);
-      check(launch_cpqr16(dlb, c->ws_work16.as<int4>(), (int)work16.size(), prm.tol, kGuardExtra,
+      check(launch_cpqr16(dlb, c->ws_work16.as<int4>(), (int)P.work16.size(), prm.tol, kGuardExtra,
                           c->ws_k.as<int>(), c->ws_kx.as<int>(), c->ws_err.as<int>(), s),
-            "16-lane", (int)work16.size());
+            "16-lane", (int)P.work16.size());
     }
     {
       KTimer kt2_(c, "cpqr.reg", true);
@@ -1511,18 +1590,30 @@ void do_factor_multi(std::vector<rs_ctx*>& cs) {
   // While level l's elimination runs, level l - 1 is prepared on the host
   // with the ranks of level l's QR.  The elimination's guard can still raise a
   // rank (rarely); then that preparation is discarded and done again.
+  // The speculative preparation also plans level l - 1 and enqueues its matrix
+  // assembly and row reduction on the second stream (they read no output of
+  // level l's elimination); a discarded pre-launch is waited for before its
+  // buffers are written again.
   std::vector<LevelPrep> preps(nc), next(nc);
-  bool have_next = false;
+  LevelPlan next_plan;
+  bool have_next = false, pre_pending = false;
+  rs_ctx* c0 = cs[0];
   for (int l = L; l >= 1; --l) {
-    cs[0]->cur_level = l;
+    c0->cur_level = l;
+    LevelPlan cur_plan;
+    LevelPlan* planned = nullptr;
     if (have_next) {
       preps.swap(next);
+      std::swap(cur_plan, next_plan);
+      planned = &cur_plan;
     } else {
+      if (pre_pending) HIP_CHECK(hipStreamWaitEvent(c0->stream, c0->ev_pre, 0));
       preps.assign(nc, LevelPrep());
       for (size_t i = 0; i < nc; ++i)
         if (cs[i]->L >= l) prepare_level(cs[i], l, by_level[i][l], active[i], preps[i]);
     }
     have_next = false;
+    pre_pending = false;
     bool speculated = false;
     std::vector<std::vector<int>> spec_k(nc);
     LevelOverlap overlap;
@@ -1539,13 +1630,26 @@ void do_factor_multi(std::vector<rs_ctx*>& cs) {
         }
         std::vector<std::vector<char>> act(active);
         drop_redundant(l, act);
+        // the second stream starts after level l's QR and A_BB (ev_qr): the
+        // index lists of level l are no longer read
+        if (!c0->side_stream) HIP_CHECK(hipStreamCreateWithFlags(&c0->side_stream, hipStreamNonBlocking));
+        if (!c0->ev_pre) HIP_CHECK(hipEventCreateWithFlags(&c0->ev_pre, hipEventDisableTiming));
+        hipStream_t s2 = c0->side_stream;
+        HIP_CHECK(hipStreamWaitEvent(s2, c0->ev_qr, 0));
         next.assign(nc, LevelPrep());
         for (size_t i = 0; i < nc; ++i)
-          if (cs[i]->L >= l - 1) prepare_level(cs[i], l - 1, by_level[i][l - 1], act[i], next[i]);
+          if (cs[i]->L >= l - 1) prepare_level(cs[i], l - 1, by_level[i][l - 1], act[i], next[i], s2);
+        next_plan = LevelPlan();
+        c0->cur_level = l - 1;
+        plan_level(cs, next, next_plan);
+        if (next_plan.nb > 0) pre_launch(cs, next_plan, s2);
+        c0->cur_level = l;
+        HIP_CHECK(hipEventRecord(c0->ev_pre, s2));
+        pre_pending = true;
         speculated = true;
       };
     }
-    launch_level(cs, preps, overlap);
+    launch_level(cs, preps, planned, overlap);
     {
       HTimer ht_(cs[0], "host:drop");
       drop_redundant(l, active);
