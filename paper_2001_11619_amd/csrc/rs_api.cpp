@@ -593,7 +593,10 @@ bool compress_needed(const rs_ctx* c, int b, const std::vector<int>& F) {
 // Process-wide pool of host threads for the per-box host work of a level
 // (near fields, unknown lists).  run(n, f) calls f(i) for every i < n, the
 // caller taking part; small n runs on the caller alone.  Calls from several
-// host threads are serialized.
+// host threads are serialized.  A level's host work comes as a burst of two
+// jobs, and the next level's preparation is on the critical path of the
+// level pipeline, so workers poll for a new job for kSpinUs after finishing
+// one before they block, and the caller polls for their completion.
 class HostPool {
  public:
   static HostPool& instance() {
@@ -612,19 +615,18 @@ class HostPool {
       n_ = n;
       chunk_ = std::max(1, n / (4 * (int)(workers_.size() + 1)));
       next_.store(0);
-      active_ = (int)workers_.size();
+      active_.store((int)workers_.size());
       gen_.fetch_add(1, std::memory_order_release);
     }
     cv_.notify_all();
     work();
-    std::unique_lock<std::mutex> lk(mu_);
-    done_cv_.wait(lk, [&] { return active_ == 0; });
+    while (active_.load(std::memory_order_acquire) != 0) std::this_thread::yield();
     fn_ = nullptr;
   }
   ~HostPool() {
     {
       std::lock_guard<std::mutex> lk(mu_);
-      stop_ = true;
+      stop_.store(true);
     }
     cv_.notify_all();
     for (auto& t : workers_) t.join();
@@ -632,6 +634,7 @@ class HostPool {
 
  private:
   static constexpr int kSerialBelow = 32;
+  static constexpr int kSpinUs = 200;
   HostPool() {
     const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
     const int nthreads = (int)std::min(8u, hw);
@@ -648,24 +651,33 @@ class HostPool {
   void loop() {
     unsigned seen = 0;
     for (;;) {
-      {
-        std::unique_lock<std::mutex> lk(mu_);
-        cv_.wait(lk, [&] { return stop_ || gen_.load(std::memory_order_acquire) != seen; });
-        if (stop_) return;
-        seen = gen_.load(std::memory_order_acquire);
+      bool got = false;
+      const auto t0 = std::chrono::steady_clock::now();
+      while (!stop_.load(std::memory_order_relaxed) &&
+             std::chrono::steady_clock::now() - t0 < std::chrono::microseconds(kSpinUs)) {
+        if (gen_.load(std::memory_order_acquire) != seen) {
+          got = true;
+          break;
+        }
       }
+      if (!got) {
+        std::unique_lock<std::mutex> lk(mu_);
+        cv_.wait(lk, [&] { return stop_.load() || gen_.load(std::memory_order_acquire) != seen; });
+      }
+      if (stop_.load()) return;
+      seen = gen_.load(std::memory_order_acquire);
       work();
-      std::lock_guard<std::mutex> lk(mu_);
-      if (--active_ == 0) done_cv_.notify_one();
+      active_.fetch_sub(1, std::memory_order_acq_rel);
     }
   }
   std::vector<std::thread> workers_;
   std::mutex run_mu_, mu_;
-  std::condition_variable cv_, done_cv_;
+  std::condition_variable cv_;
   const std::function<void(int)>* fn_ = nullptr;
-  int n_ = 0, chunk_ = 1, active_ = 0;
+  int n_ = 0, chunk_ = 1;
+  std::atomic<int> active_{0};
   std::atomic<unsigned> gen_{0};
-  bool stop_ = false;
+  std::atomic<bool> stop_{false};
   std::atomic<int> next_{0};
 };
 
