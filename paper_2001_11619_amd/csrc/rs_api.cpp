@@ -967,6 +967,17 @@ int qr_route(int m, int n, int& h, std::vector<int>& P) {
 // Host work run while the level's elimination is on the device: called with
 // the pivoted QR's ranks (indexed by box slot) once they and the pivot orders
 // (in each LevelPrep::perm) have arrived.
+// Wait for an event by polling it.  Used where the host's own work is the
+// critical path (the speculative preparation of the next level starts when
+// the QR ranks arrive), so that a blocking wait's wake-up latency is not added.
+void poll_event(hipEvent_t ev) {
+  for (;;) {
+    const hipError_t e = hipEventQuery(ev);
+    if (e == hipSuccess) return;
+    if (e != hipErrorNotReady) HIP_CHECK(e);
+  }
+}
+
 using LevelOverlap = std::function<void(const int* qr_rank)>;
 
 constexpr size_t kBorderScratchMax = 64ull << 20;   // gather scratch of one border launch
@@ -1311,7 +1322,7 @@ void launch_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps, Level
     {
       HTimer ht_(c, "host:level_wait");
       HTimer ht2_(c, "host:qr_wait");
-      HIP_CHECK(hipEventSynchronize(c->ev_qr));
+      poll_event(c->ev_qr);
     }
     for (size_t i = 0; i < cs.size(); ++i)
       if (hperm[i]) preps[i].perm.assign(hperm[i], hperm[i] + preps[i].doff.back() + preps[i].lb.back().n);
