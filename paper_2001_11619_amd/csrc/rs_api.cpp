@@ -215,10 +215,12 @@ struct rs_ctx {
   PinHost h_rank, h_perm, h_small, h_rc;  // pinned read-back buffers
   const OldState* old = nullptr;  // set while an update runs
   // level workspaces (reused level to level)
-  DevBuf ws_boxes_b;   // descriptors of the other level parity (pre-launch beside an elimination)
+  // a level launch's inputs (index lists, descriptors, QR tasks and work lists)
+  // in one device buffer per level parity, filled by one copy
+  DevBuf ws_in_a, ws_in_b;
   int desc_flip = 0;
-  DevBuf ws_M, ws_R, ws_A, ws_scr, ws_boxes, ws_dofs, ws_fint, ws_src, ws_perm, ws_k, ws_kx,
-      ws_status, ws_coop, ws_err, ws_work, ws_fblist, ws_tasks, ws_tq, ws_work16, ws_rc;
+  DevBuf ws_M, ws_R, ws_A, ws_scr, ws_src, ws_perm, ws_k, ws_kx, ws_status, ws_coop, ws_err, ws_tq,
+      ws_rc;
   int n_cu = 0;                   // compute units of the device
   // root
   std::vector<int> I0;
@@ -688,6 +690,8 @@ struct LevelPrep {
   std::vector<LevelBox> lb;      // their descriptors (device pointers filled)
   std::vector<int> doff;         // offset of each compressed box's I_B in the context's list
   std::vector<int> perm;         // pivot orders read back
+  std::vector<int> dofs, fint;   // I_B and F_int of the compressed boxes, concatenated
+  std::vector<ChildSrc> src;     // where each parent unknown's child block is
   int max_m = 0, max_n = 0;
   int aid = -1;
   size_t first = 0;              // index of the first box in the batched launch
@@ -720,10 +724,9 @@ std::unique_ptr<DevBuf> take_arena(rs_ctx* c, size_t bytes) {
 // Host part of one level for one context: unknowns, near fields, reuse
 // decisions, workspace and arena allocation, uploads of the index lists.
 void prepare_level(rs_ctx* c, int l, const std::vector<int>& ids, const std::vector<char>& active,
-                   LevelPrep& P, hipStream_t up = nullptr) {
+                   LevelPrep& P) {
   HTimer ht_(c, "host:prepare");
   const rs_params& prm = c->prm;
-  hipStream_t s = up ? up : c->stream;     // stream of the index-list uploads
   Geo g;
   geo_of(c, g);
   P = LevelPrep();
@@ -836,9 +839,6 @@ void prepare_level(rs_ctx* c, int l, const std::vector<int>& ids, const std::vec
   P.aid = c->next_arena++;
   c->arenas[P.aid] = take_arena(c, totArena * sizeof(double));
   DevBuf* arena = c->arenas[P.aid].get();
-  upload(c->ws_dofs, dofs, s);
-  upload(c->ws_fint, fint, s);
-  upload(c->ws_src, src_all, s);
   c->ws_perm.ensure(std::max<size_t>(dofs.size(), 4) * sizeof(int));
   double* pM = c->ws_M.as<double>();
   double* pR = c->ws_R.as<double>();
@@ -850,9 +850,10 @@ void prepare_level(rs_ctx* c, int l, const std::vector<int>& ids, const std::vec
     LevelBox& x = P.lb[i];
     const size_t n2 = (size_t)x.n * x.n;
     const size_t kr = n2 / 4 + x.n;
-    x.dofs = c->ws_dofs.as<int>() + P.doff[i];
-    x.fint = c->ws_fint.as<int>() + (size_t)reinterpret_cast<uintptr_t>(x.fint);
-    x.src = soff[i] < 0 ? nullptr : c->ws_src.as<ChildSrc>() + soff[i];
+    // dofs, fint and src hold offsets into P's lists (src: offset + 1, 0 for a
+    // leaf) until the level plan places the lists in the launch's input buffer
+    x.dofs = reinterpret_cast<const int*>((uintptr_t)P.doff[i]);
+    x.src = reinterpret_cast<const ChildSrc*>((uintptr_t)(soff[i] + 1));
     x.perm = c->ws_perm.as<int>() + P.doff[i];
     x.M = pM;
     pM += (size_t)x.m * x.n;
@@ -904,6 +905,9 @@ void prepare_level(rs_ctx* c, int l, const std::vector<int>& ids, const std::vec
     f.Ff = x.Ff;
     f.Xinvf = x.Xinvf;
   }
+  P.dofs = std::move(dofs);
+  P.fint = std::move(fint);
+  P.src = std::move(src_all);
 }
 
 // Ranks and pivot orders read back for one context: fill its box records.
@@ -1007,7 +1011,13 @@ struct LevelPlan {
   std::vector<std::pair<int, int>> coop;   // (first work item, count) of each cooperative launch
   int fb_m = 0, fb_n = 0, G = 1, Ge = 1;
   size_t rq_lds = 0;
-  DevBuf* desc = nullptr;                  // device copy of `all`
+  DevBuf* in = nullptr;                    // the launch's input buffer (one per level parity)
+  std::vector<char> image;                 // its host image
+  const LevelBox* dboxes = nullptr;        // device addresses of the sections
+  const QRTask* dtasks = nullptr;
+  const int4* dwork = nullptr;
+  const int4* dwork16 = nullptr;
+  const int* dfb = nullptr;
 };
 
 // Host plan of a level launch: descriptors, QR routes and tasks, workgroups per box.
@@ -1176,7 +1186,55 @@ void plan_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps, LevelPl
   P.G = G;
   P.Ge = Ge;
   c->desc_flip ^= 1;
-  P.desc = c->desc_flip ? &c->ws_boxes_b : &c->ws_boxes;
+  P.in = c->desc_flip ? &c->ws_in_b : &c->ws_in_a;
+  // input buffer layout: per context its I_B, F_int and child-source lists,
+  // then descriptors, QR tasks, work lists (each section 256-byte aligned)
+  size_t off = 0;
+  auto place = [&](size_t bytes) {
+    const size_t o = off;
+    off = (off + bytes + 255) & ~(size_t)255;
+    return o;
+  };
+  std::vector<size_t> o_dofs(cs.size()), o_fint(cs.size()), o_src(cs.size());
+  for (size_t i = 0; i < cs.size(); ++i) {
+    o_dofs[i] = place(preps[i].dofs.size() * sizeof(int));
+    o_fint[i] = place(preps[i].fint.size() * sizeof(int));
+    o_src[i] = place(preps[i].src.size() * sizeof(ChildSrc));
+  }
+  const size_t o_boxes = place(P.all.size() * sizeof(LevelBox));
+  const size_t o_tasks = place(P.tasks.size() * sizeof(QRTask));
+  const size_t o_work = place(P.work.size() * sizeof(int4));
+  const size_t o_work16 = place(P.work16.size() * sizeof(int4));
+  const size_t o_fb = place(P.fb.size() * sizeof(int));
+  P.in->ensure(std::max<size_t>(off, 256));
+  char* base = static_cast<char*>(P.in->p);
+  for (size_t i = 0; i < cs.size(); ++i)
+    for (size_t t = 0; t < preps[i].lb.size(); ++t) {
+      LevelBox& x = P.all[preps[i].first + t];
+      x.dofs = reinterpret_cast<const int*>(base + o_dofs[i]) + reinterpret_cast<uintptr_t>(x.dofs);
+      x.fint = reinterpret_cast<const int*>(base + o_fint[i]) + reinterpret_cast<uintptr_t>(x.fint);
+      const uintptr_t so = reinterpret_cast<uintptr_t>(x.src);
+      x.src = so == 0 ? nullptr : reinterpret_cast<const ChildSrc*>(base + o_src[i]) + (so - 1);
+    }
+  P.image.assign(off, 0);
+  auto put = [&](size_t o, const void* src, size_t bytes) {
+    if (bytes) std::memcpy(P.image.data() + o, src, bytes);
+  };
+  for (size_t i = 0; i < cs.size(); ++i) {
+    put(o_dofs[i], preps[i].dofs.data(), preps[i].dofs.size() * sizeof(int));
+    put(o_fint[i], preps[i].fint.data(), preps[i].fint.size() * sizeof(int));
+    put(o_src[i], preps[i].src.data(), preps[i].src.size() * sizeof(ChildSrc));
+  }
+  put(o_boxes, P.all.data(), P.all.size() * sizeof(LevelBox));
+  put(o_tasks, P.tasks.data(), P.tasks.size() * sizeof(QRTask));
+  put(o_work, P.work.data(), P.work.size() * sizeof(int4));
+  put(o_work16, P.work16.data(), P.work16.size() * sizeof(int4));
+  put(o_fb, P.fb.data(), P.fb.size() * sizeof(int));
+  P.dboxes = reinterpret_cast<const LevelBox*>(base + o_boxes);
+  P.dtasks = reinterpret_cast<const QRTask*>(base + o_tasks);
+  P.dwork = reinterpret_cast<const int4*>(base + o_work);
+  P.dwork16 = reinterpret_cast<const int4*>(base + o_work16);
+  P.dfb = reinterpret_cast<const int*>(base + o_fb);
 }
 
 // Matrix assembly and row reduction of a planned level on stream st: they read
@@ -1185,9 +1243,8 @@ void plan_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps, LevelPl
 void pre_launch(std::vector<rs_ctx*>& cs, LevelPlan& P, hipStream_t st) {
   rs_ctx* c = cs[0];
   const rs_params& prm = c->prm;
-  upload(*P.desc, P.all, st);
-  upload(c->ws_tasks, P.tasks, st);
-  const LevelBox* dlb = P.desc->as<LevelBox>();
+  upload(*P.in, P.image, st);
+  const LevelBox* dlb = P.dboxes;
   {
     KTimer kt_(c, "assemble_M", false, st);
     launch_assemble_M(dlb, P.nb, P.max_m, prm.n_proxy, prm.proxy_ratio, st);
@@ -1196,7 +1253,7 @@ void pre_launch(std::vector<rs_ctx*>& cs, LevelPlan& P, hipStream_t st) {
     KTimer kt_(c, "cpqr", false, st);
     for (size_t r = 0; r + 1 < P.round_first.size(); ++r) {
       KTimer kt2_(c, "cpqr.rows", true, st);
-      launch_tsqr(c->ws_tasks.as<QRTask>() + P.round_first[r], P.round_first[r + 1] - P.round_first[r], st);
+      launch_tsqr(P.dtasks + P.round_first[r], P.round_first[r + 1] - P.round_first[r], st);
     }
   }
 }
@@ -1226,15 +1283,12 @@ void launch_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps, Level
   const std::vector<int>& fb = P.fb;
   const std::vector<std::pair<int, int>>& coop = P.coop;
   const int nfb = (int)fb.size();
-  upload(c->ws_work, work, s);
-  upload(c->ws_work16, P.work16, s);
-  upload(c->ws_fblist, fb, s);
   c->ws_k.ensure(nb * sizeof(int));
   c->ws_kx.ensure(nb * sizeof(int));
   c->ws_status.ensure(nb * sizeof(int));
   c->ws_rc.ensure(nb * sizeof(double));
   c->ws_err.ensure(sizeof(int) * 4);
-  const LevelBox* dlb = P.desc->as<LevelBox>();
+  const LevelBox* dlb = P.dboxes;
   if (c->timing && c->level_done_set) {
     const int fam = family(c, "host:between_levels");
     c->fam_ms[fam] += 1e3 * std::chrono::duration<double>(std::chrono::steady_clock::now() - c->level_done).count();
@@ -1244,7 +1298,7 @@ void launch_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps, Level
   {
     KTimer kt_(c, "cpqr");
     launch_zero_bars(dlb, nb, c->ws_err.as<int>(), s);
-    const int4* dw = c->ws_work.as<int4>();
+    const int4* dw = P.dwork;
     const int nA = coop.empty() ? (int)work.size() : coop.front().first;
     auto check = [&](hipError_t e, const char* what, int blocks) {
       if (e != hipSuccess)
@@ -1266,13 +1320,13 @@ void launch_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps, Level
       }
       {
         KTimer kt2_(c, "cpqr.mem", true, s2);
-        check(launch_cpqr(dlb, c->ws_fblist.as<int>(), nfb, G, prm.tol, kGuardExtra, c->ws_k.as<int>(),
+        check(launch_cpqr(dlb, P.dfb, nfb, G, prm.tol, kGuardExtra, c->ws_k.as<int>(),
                           c->ws_kx.as<int>(), c->ws_err.as<int>(), fb_m, fb_n, s2), "memory", nfb * G);
       }
     }
     {
       KTimer kt2_(c, "cpqr.r16", true);
-      check(launch_cpqr16(dlb, c->ws_work16.as<int4>(), (int)P.work16.size(), prm.tol, kGuardExtra,
+      check(launch_cpqr16(dlb, P.dwork16, (int)P.work16.size(), prm.tol, kGuardExtra,
                           c->ws_k.as<int>(), c->ws_kx.as<int>(), c->ws_err.as<int>(), s),
             "16-lane", (int)P.work16.size());
     }
@@ -1661,7 +1715,7 @@ void do_factor_multi(std::vector<rs_ctx*>& cs) {
         HIP_CHECK(hipStreamWaitEvent(s2, c0->ev_qr, 0));
         next.assign(nc, LevelPrep());
         for (size_t i = 0; i < nc; ++i)
-          if (cs[i]->L >= l - 1) prepare_level(cs[i], l - 1, by_level[i][l - 1], act[i], next[i], s2);
+          if (cs[i]->L >= l - 1) prepare_level(cs[i], l - 1, by_level[i][l - 1], act[i], next[i]);
         next_plan = LevelPlan();
         c0->cur_level = l - 1;
         plan_level(cs, next, next_plan);
