@@ -1512,10 +1512,21 @@ void factor_root(rs_ctx* c) {
   hipStream_t s = c->stream;
   Geo g;
   geo_of(c, g);
+  const int p3 = 3 * c->p;
+  if (p3) {
+    // the border columns H and rows Psi^T depend on the geometry only: they
+    // are assembled first, while the host builds the root and solve metadata
+    const size_t hn = (size_t)2 * c->N * p3;
+    c->d_H.ensure(hn * sizeof(double));
+    c->d_Hh.ensure(hn * sizeof(double));
+    c->d_Ph.ensure(hn * sizeof(double));
+    KTimer kt_(c, "border_H");
+    launch_assemble_H(g, c->d_hole.as<double>(), c->p, c->d_curve.as<int>(), c->d_Hh.as<double>(),
+                      c->d_Ph.as<double>(), s);
+  }
   std::vector<ChildSrc> src;
   box_unknowns(c, 0, c->I0, &src);
   const int n0 = (int)c->I0.size();
-  const int p3 = 3 * c->p;
   c->nz = n0 + p3;
   upload(c->d_I0, c->I0, s);
   c->d_X0.ensure(std::max<size_t>((size_t)n0 * n0, 1) * sizeof(double));
@@ -1543,15 +1554,6 @@ void factor_root(rs_ctx* c) {
   c->d_rstatus.ensure(sizeof(int));
   const double* Zsrc = c->d_X0.as<double>();
   if (p3) {
-    const size_t hn = (size_t)2 * c->N * p3;
-    c->d_H.ensure(hn * sizeof(double));
-    c->d_Hh.ensure(hn * sizeof(double));
-    c->d_Ph.ensure(hn * sizeof(double));
-    {
-      KTimer kt_(c, "border_H");
-      launch_assemble_H(g, c->d_hole.as<double>(), c->p, c->d_curve.as<int>(), c->d_Hh.as<double>(),
-                        c->d_Ph.as<double>(), s);
-    }
     // the Psi^T V rows are swept on the second stream beside the U sweep of
     // the border columns and the W blocks (which read only the latter)
     hipStream_t s2 = fork_side(c);
