@@ -239,7 +239,9 @@ typedef struct {
   int launches;
   double total_ms;
 } rs_kernel_time;
-/* enable: 0 off, 1 per kernel family, 2 per family and tree level ("cpqr@L7"). */
+/* enable: 0 off, 1 per kernel family, 2 per family and tree level ("cpqr@L7"),
+ * 3 the pivoted-QR family ("cpqr") only, with no host-phase timers (the least
+ * overhead, for timing a run while reporting that family's device time). */
 rs_status rs_set_kernel_timing(rs_ctx* ctx, int enable);
 /* Copies up to cap entries accumulated since the last reset; *n receives the
  * number of kernel families.  reset != 0 clears the accumulators afterwards. */

@@ -357,7 +357,8 @@ class RSSolver:
         return out[: ln.value].copy()
 
     def set_kernel_timing(self, enable=True):
-        """enable: False/0 off, True/1 per kernel family, 2 per family and tree level."""
+        """enable: False/0 off, True/1 per kernel family, 2 per family and tree
+        level, 3 the pivoted-QR family only (no host phases)."""
         self._check(self._lib.rs_set_kernel_timing(self._h, int(enable)))
 
     def kernel_times(self, reset: bool = False) -> dict:

@@ -264,7 +264,8 @@ struct rs_ctx {
   PinHost h_flag;
 
   // kernel timing (HIP events around launches)
-  int timing = 0;                 // 0 off, 1 per kernel family, 2 per family and level
+  int timing = 0;                 // 0 off, 1 per kernel family, 2 per family and level,
+                                  // 3 the pivoted-QR family only (no host phases)
   int cur_level = -1;
   struct Pending { int fam; hipEvent_t a, b; };
   std::vector<Pending> pending;
@@ -335,6 +336,7 @@ struct KTimer {
   KTimer(rs_ctx* ctx, const char* name, bool detail = false, hipStream_t on = nullptr)
       : c(ctx), st(on ? on : ctx->stream) {
     if (!c->timing || c->capturing || (detail && c->timing != 2)) return;
+    if (c->timing == 3 && std::strcmp(name, "cpqr") != 0) return;
     if (c->timing == 2 && c->cur_level >= 0) {
       const std::string full = std::string(name) + "@L" + std::to_string(c->cur_level);
       fam = family(c, full.c_str());
@@ -363,7 +365,7 @@ struct HTimer {
   int fam = -1;
   std::chrono::steady_clock::time_point t0;
   HTimer(rs_ctx* ctx, const char* name) : c(ctx) {
-    if (!c->timing) return;
+    if (!c->timing || c->timing == 3) return;
     fam = family(c, name);
     t0 = std::chrono::steady_clock::now();
   }
@@ -1289,7 +1291,7 @@ void launch_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps, Level
   c->ws_rc.ensure(nb * sizeof(double));
   c->ws_err.ensure(sizeof(int) * 4);
   const LevelBox* dlb = P.dboxes;
-  if (c->timing && c->level_done_set) {
+  if ((c->timing == 1 || c->timing == 2) && c->level_done_set) {
     const int fam = family(c, "host:between_levels");
     c->fam_ms[fam] += 1e3 * std::chrono::duration<double>(std::chrono::steady_clock::now() - c->level_done).count();
     c->fam_launches[fam] += 1;
@@ -2754,7 +2756,7 @@ rs_status rs_get_skeleton(const rs_ctx* c, int box, int cap, int* out, int* len)
 
 rs_status rs_set_kernel_timing(rs_ctx* c, int enable) {
   if (!c) return RS_ERR_ARG;
-  c->timing = enable < 0 ? 0 : (enable > 2 ? 2 : enable);
+  c->timing = enable < 0 ? 0 : (enable > 3 ? 3 : enable);
   return RS_OK;
 }
 
