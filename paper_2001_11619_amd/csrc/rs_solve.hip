@@ -165,17 +165,19 @@ __global__ void k_assemble_H(Geo g, const double* hole_xy, int p, const int* cur
 }
 
 // out[t] = scale * sum_p parts[p * stride + t].  A block takes 64 outputs; its
-// 4 waves x 4 accumulators form 16 streams, stream s summing the parts
-// p = s, s + 16, s + 32, ... in order; the 16 stream sums are then added in
+// 16 waves x 4 accumulators form 64 streams, stream s summing the parts
+// p = s, s + 64, s + 128, ... in order; the 64 stream sums are then added in
 // stream order (the result does not depend on timing).
-__global__ __launch_bounds__(256) void k_sum_parts(const double* parts, int nparts, long long stride,
-                                                   int len, double scale, double* out) {
-  __shared__ double sh[16][64];
+constexpr int kSumThreads = 1024;
+__global__ __launch_bounds__(kSumThreads) void k_sum_parts(const double* parts, int nparts, long long stride,
+                                                           int len, double scale, double* out) {
+  constexpr int NS = 4 * (kSumThreads / 64);
+  __shared__ double sh[NS][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int t = blockIdx.x * 64 + lane;
   double a[4] = {0.0, 0.0, 0.0, 0.0};
   if (t < len) {
-    for (int p0 = 4 * w; p0 < nparts; p0 += 16) {
+    for (int p0 = 4 * w; p0 < nparts; p0 += NS) {
 #pragma unroll
       for (int u = 0; u < 4; ++u)
         if (p0 + u < nparts) a[u] += parts[(size_t)(p0 + u) * stride + t];
@@ -186,7 +188,7 @@ __global__ __launch_bounds__(256) void k_sum_parts(const double* parts, int npar
   __syncthreads();
   if (w == 0 && t < len) {
     double sum = 0.0;
-    for (int st = 0; st < 16; ++st) sum += sh[st][lane];
+    for (int st = 0; st < NS; ++st) sum += sh[st][lane];
     out[t] = scale * sum;
   }
 }
@@ -356,19 +358,34 @@ __global__ void k_set_ints(int* p, int n, int v) {
 
 // r = [f; 0] - y  (rows layout, f has nf rows); colsq[q] = ||r_q||^2 and fsq[q] = ||f_q||^2,
 // one block per column, fixed-order sums.
-__global__ __launch_bounds__(kBlock) void k_residual(const double* f, int nf, const double* y,
-                                                    int nrows, int ncols, double* r,
-                                                    double* colsq, double* fsq) {
-  constexpr int NW = kBlock / 64;
+// r = [f; 0] - y for column blockIdx.x and its squared norms; one block of
+// kResThreads per column, rows taken four strides at a time (independent
+// loads in flight), sums in a fixed order.
+constexpr int kResThreads = 1024;
+__global__ __launch_bounds__(kResThreads) void k_residual(const double* f, int nf, const double* y,
+                                                         int nrows, int ncols, double* r,
+                                                         double* colsq, double* fsq) {
+  constexpr int NW = kResThreads / 64;
   __shared__ double red[NW];
   const int q = blockIdx.x;
   double sr = 0.0, sf = 0.0;
-  for (int i = threadIdx.x; i < nrows; i += kBlock) {
-    const double fi = i < nf ? f[(size_t)i * ncols + q] : 0.0;
-    const double v = fi - y[(size_t)i * ncols + q];
-    r[(size_t)i * ncols + q] = v;
-    sr += v * v;
-    sf += fi * fi;
+  for (int i0 = threadIdx.x; i0 < nrows; i0 += 4 * kResThreads) {
+    double fi[4], yi[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = i0 + u * kResThreads;
+      fi[u] = i < nf ? f[(size_t)i * ncols + q] : 0.0;
+      yi[u] = i < nrows ? y[(size_t)i * ncols + q] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = i0 + u * kResThreads;
+      if (i >= nrows) break;
+      const double v = fi[u] - yi[u];
+      r[(size_t)i * ncols + q] = v;
+      sr += v * v;
+      sf += fi[u] * fi[u];
+    }
   }
   sr = block_sum(sr, red);
   sf = block_sum(sf, red);
@@ -442,7 +459,7 @@ void launch_assemble_H(Geo g, const double* hole_xy, int p, const int* curve_id,
 void launch_sum_parts(const double* parts, int nparts, long long stride, int len, double scale,
                       double* out, hipStream_t s) {
   if (len == 0) return;
-  hipLaunchKernelGGL(k_sum_parts, dim3(blocks_for(len, 64)), dim3(256), 0, s, parts, nparts, stride,
+  hipLaunchKernelGGL(k_sum_parts, dim3(blocks_for(len, 64)), dim3(kSumThreads), 0, s, parts, nparts, stride,
                      len, scale, out);
 }
 
@@ -523,7 +540,7 @@ void launch_accumulate(const float* d, long long n, double* x, hipStream_t s) {
 
 void launch_residual(const double* f, int nf, const double* y, int nrows, int ncols, double* r,
                      double* colsq, double* fsq, hipStream_t s) {
-  hipLaunchKernelGGL(k_residual, dim3(ncols), dim3(kBlock), 0, s, f, nf, y, nrows, ncols, r, colsq, fsq);
+  hipLaunchKernelGGL(k_residual, dim3(ncols), dim3(kResThreads), 0, s, f, nf, y, nrows, ncols, r, colsq, fsq);
 }
 
 void launch_w_to_float(const SolveBox* boxes, int nbox, int p3, hipStream_t s) {
