@@ -817,27 +817,47 @@ __global__ __launch_bounds__(kBlock) void k_gjb_panel(const double* A, int n, in
   }
   __syncthreads();
   bool singular = false;
+  // The pivot of column j + 1 is found during step j's update: the threads
+  // that update column j + 1 fold a 64-bit key (|W| with its low 16 bits
+  // replaced by 65535 - row: the larger value, ties to the smaller row) into
+  // pkey with an atomic max.  Panels taller than 65535 rows search each column
+  // instead.  The update forms each multiplier as W[i][j] / d on the fly (one
+  // reciprocal per step, kept in dsc); the L columns are scaled once at the end
+  // (a per-column factor, so the later row swaps commute with it).  Two
+  // barriers per step.
+  __shared__ unsigned long long pkey[2];
+  __shared__ double dsc[kGJB];
+  const bool fused = h <= 0xFFFF;
+  const int cc = tid & (kGJB - 1), rl = tid / kGJB;
+  if (tid < 2) pkey[tid] = 0ull;
   for (int j = 0; j < bb; ++j) {
     double best = -1.0;
     int bi = h;
-    for (int i = j + tid; i < h; i += kBlock) {
-      const double v = fabs(W[(size_t)i * ldw + j]);
-      if (v > best) { best = v; bi = i; }
+    if (j == 0 || !fused) {
+      for (int i = j + tid; i < h; i += kBlock) {
+        const double v = fabs(W[(size_t)i * ldw + j]);
+        if (v > best) { best = v; bi = i; }
+      }
+      wave_argmax(best, bi);
+      if (lane == 0) { red[wid] = best; ired[wid] = bi; }
+      __syncthreads();
+      best = red[0];
+      bi = ired[0];
+      for (int w = 1; w < NW; ++w)
+        if (red[w] > best || (red[w] == best && ired[w] < bi)) { best = red[w]; bi = ired[w]; }
+      __syncthreads();
+    } else {
+      const unsigned long long key = pkey[j & 1];
+      best = (key >> 16) ? 1.0 : 0.0;        // a candidate with a nonzero value
+      bi = 0xFFFF - (int)(key & 0xFFFF);
     }
-    wave_argmax(best, bi);
-    if (lane == 0) { red[wid] = best; ired[wid] = bi; }
-    __syncthreads();
-    best = red[0];
-    bi = ired[0];
-    for (int w = 1; w < NW; ++w)
-      if (red[w] > best || (red[w] == best && ired[w] < bi)) { best = red[w]; bi = ired[w]; }
-    __syncthreads();
     if (!(best > 0.0)) {
       for (int jj = j + tid; jj < bb; jj += kBlock) piv[jj] = jj;
       singular = true;
       break;
     }
-    if (tid == 0) piv[j] = bi;
+    // pkey[(j + 1) & 1] was last read at the start of step j - 1
+    if (tid == 0) { piv[j] = bi; pkey[(j + 1) & 1] = 0ull; }
     if (bi != j)
       for (int c = tid; c < bb; c += kBlock) {
         const double a = W[(size_t)j * ldw + c];
@@ -845,18 +865,17 @@ __global__ __launch_bounds__(kBlock) void k_gjb_panel(const double* A, int n, in
         W[(size_t)bi * ldw + c] = a;
       }
     __syncthreads();
-    const double d = W[(size_t)j * ldw + j];
-    for (int i = j + 1 + tid; i < h; i += kBlock) W[(size_t)i * ldw + j] /= d;
-    __syncthreads();
+    const double rd = 1.0 / W[(size_t)j * ldw + j];
+    if (tid == 0) dsc[j] = rd;
     // trailing update of the panel: thread (row lane tid / 32, column j + 1 +
     // tid % 32) takes every eighth row, with its entry of row j in a register;
     // rows go in batches of 8 (all reads, then all writes), so the LDS round
     // trips of a batch overlap
-    const int cc = tid & (kGJB - 1), rl = tid / kGJB;
     if (cc < bb - j - 1) {
       constexpr int RL = kBlock / kGJB, RB = 8;
       const int c = j + 1 + cc;
       const double ujc = W[(size_t)j * ldw + c];
+      unsigned long long kmax = 0ull;
       for (int i0 = j + 1 + rl; i0 < h; i0 += RB * RL) {
         double wij[RB], wic[RB];
 #pragma unroll
@@ -868,10 +887,25 @@ __global__ __launch_bounds__(kBlock) void k_gjb_panel(const double* A, int n, in
 #pragma unroll
         for (int u = 0; u < RB; ++u) {
           const int i = i0 + u * RL;
-          if (i < h) W[(size_t)i * ldw + c] = wic[u] - wij[u] * ujc;
+          if (i < h) {
+            const double v = wic[u] - (wij[u] * rd) * ujc;
+            W[(size_t)i * ldw + c] = v;
+            if (cc == 0 && fused) {
+              const unsigned long long kb =
+                  ((unsigned long long)__double_as_longlong(fabs(v)) & ~0xFFFFull) | (unsigned long long)(0xFFFF - i);
+              kmax = kmax > kb ? kmax : kb;
+            }
+          }
         }
       }
+      if (cc == 0 && fused && kmax) atomicMax(&pkey[(j + 1) & 1], kmax);
     }
+    __syncthreads();
+  }
+  if (!singular) {
+    // scale the L columns by their pivots' reciprocals
+    for (int c = cc; c < bb; c += kGJB)
+      for (int i = c + 1 + rl; i < h; i += kBlock / kGJB) W[(size_t)i * ldw + c] *= dsc[c];
     __syncthreads();
   }
   if (singular) {
