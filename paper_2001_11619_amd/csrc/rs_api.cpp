@@ -1509,6 +1509,9 @@ void sweep_all(rs_ctx* c, T* buf, int ncols, int mode, hipStream_t on = nullptr)
   }
 }
 
+void ensure_solve_buffers(rs_ctx* c, int ncols);
+void refine_graph_capture(rs_ctx* c, int nrhs);
+
 void factor_root(rs_ctx* c) {
   HTimer ht_(c, "host:root");
   hipStream_t s = c->stream;
@@ -1604,6 +1607,14 @@ void factor_root(rs_ctx* c) {
                         c->d_gjiwork.as<int>(), c->d_rstatus.as<int>(), s);
     }
     HIP_CHECK(hipGetLastError());
+    // While the root inverse runs, the refinement graph for the last solve's
+    // number of right-hand sides is captured anew (capture records launches
+    // only; the factors' buffers and the solve metadata are final here).  A
+    // solve with another count captures its own graph as before.
+    if (c->refine_exec && c->refine_nrhs > 0) {
+      ensure_solve_buffers(c, c->refine_nrhs);
+      refine_graph_capture(c, c->refine_nrhs);
+    }
     int st = 0;
     HIP_CHECK(hipMemcpyAsync(&st, c->d_rstatus.p, sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_CHECK(hipStreamSynchronize(s));
