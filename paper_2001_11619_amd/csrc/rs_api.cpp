@@ -1585,11 +1585,13 @@ void factor_root(rs_ctx* c) {
                           c->d_bscr.as<double>(), scr_stride, s);
       join_side(c);   // Psi^T V rows
       const int nch = border_g_chunks(c->n_ridx, p3);
-      c->d_Gpart.ensure((size_t)nch * p3 * p3 * sizeof(double));
+      const size_t gparts = (size_t)nch * p3 * p3;
+      c->d_Gpart.ensure((gparts + sum_parts_scratch_doubles(nch, p3 * p3)) * sizeof(double));
       launch_border_g(c->d_ridx.as<int>(), c->n_ridx, c->d_Ph.as<double>(), c->d_W.as<double>(), p3, nch,
                       c->d_Gpart.as<double>(), s);
       c->d_G.ensure((size_t)p3 * p3 * sizeof(double));
-      launch_sum_parts(c->d_Gpart.as<double>(), nch, (long long)p3 * p3, p3 * p3, 1.0, c->d_G.as<double>(), s);
+      launch_sum_parts(c->d_Gpart.as<double>(), nch, (long long)p3 * p3, p3 * p3, 1.0, c->d_G.as<double>(),
+                       c->d_Gpart.as<double>() + gparts, s);
     }
     if (c->prm.precision == 1) launch_w_to_float(level_sboxes(c, 1), all_nb, p3, s);
     c->d_Z.ensure((size_t)nz * nz * sizeof(double));
@@ -1806,7 +1808,8 @@ void solve_rows(rs_ctx* c, T* cbuf, int ncols, const double* rbot) {
   const double* rhs2 = nullptr;
   if (p3) {
     const int nsb = c->n_solve_boxes;
-    c->d_parts.ensure(std::max<size_t>((size_t)nsb * p3 * ncols, 1) * sizeof(double));
+    const size_t nparts = (size_t)nsb * p3 * ncols;
+    c->d_parts.ensure((nparts + sum_parts_scratch_doubles(nsb, p3 * ncols)) * sizeof(double));
     {
       KTimer kt_(c, "border_rhs");
       launch_border_rhs<T>(all_sb, all_nb, c->d_ridx.as<int>(), c->d_Ph.as<double>(), p3, cbuf, ncols,
@@ -1814,7 +1817,7 @@ void solve_rows(rs_ctx* c, T* cbuf, int ncols, const double* rbot) {
     }
     c->d_rhs2.ensure((size_t)p3 * ncols * sizeof(double));
     launch_sum_parts(c->d_parts.as<double>(), nsb, (long long)p3 * ncols, p3 * ncols, -1.0,
-                     c->d_rhs2.as<double>(), s);
+                     c->d_rhs2.as<double>(), c->d_parts.as<double>() + nparts, s);
     if (rbot) launch_accumulate(rbot, (long long)p3 * ncols, c->d_rhs2.as<double>(), s);
     rhs2 = c->d_rhs2.as<double>();
   }
@@ -1866,11 +1869,13 @@ void ensure_solve_buffers(rs_ctx* c, int ncols) {
   c->d_r.ensure(rows * sizeof(double));
   c->d_dx.ensure(rows * sizeof(double));
   c->d_ys.ensure(rows * sizeof(double));
-  c->d_norms.ensure(2 * (size_t)ncols * sizeof(double));
+  c->d_norms.ensure((2 * (size_t)ncols + residual_scratch_doubles(ncols)) * sizeof(double));
   c->d_v.ensure(std::max<size_t>((size_t)c->nz * ncols, 1) * sizeof(double));
   c->d_sol.ensure(std::max<size_t>((size_t)c->nz * ncols, 1) * sizeof(double));
   if (p3) {
-    c->d_parts.ensure(std::max<size_t>((size_t)c->n_solve_boxes * p3 * ncols, 1) * sizeof(double));
+    c->d_parts.ensure(((size_t)c->n_solve_boxes * p3 * ncols +
+                       sum_parts_scratch_doubles(c->n_solve_boxes, p3 * ncols)) *
+                      sizeof(double));
     c->d_rhs2.ensure((size_t)p3 * ncols * sizeof(double));
   }
   c->d_apply.ensure(apply_scratch_doubles(c->N, ncols) * sizeof(double));
@@ -1889,7 +1894,7 @@ void refine_iteration(rs_ctx* c, int nrhs) {
                            c->prm.refine_max, c->stream);
   apply_device_rows(c, c->d_xs.as<double>(), nrhs, c->d_ys.as<double>(), c->d_flag.as<int>());
   launch_residual(c->d_frows.as<double>(), n2, c->d_ys.as<double>(), ns, nrhs, c->d_r.as<double>(), colsq,
-                  colsq + nrhs, c->stream);
+                  colsq + nrhs, colsq + 2 * nrhs, c->stream);
   launch_refine_flag(colsq, colsq + nrhs, nrhs, c->prm.refine_tol, c->prm.refine_max, c->d_flag.as<int>(),
                      c->stream);
 }
@@ -1902,7 +1907,7 @@ void refine_begin(rs_ctx* c, int nrhs) {
   double* colsq = c->d_norms.as<double>();
   launch_fill(c->d_xs.as<double>(), (long long)ns * nrhs, 0.0, c->stream);
   launch_residual(c->d_frows.as<double>(), n2, c->d_xs.as<double>(), ns, nrhs, c->d_r.as<double>(), colsq,
-                  colsq + nrhs, c->stream);
+                  colsq + nrhs, colsq + 2 * nrhs, c->stream);
   launch_set_ints(c->d_flag.as<int>(), 2, 0, c->stream);
   c->refine_prev = 1.0;
   c->refine_last = 0;
@@ -2448,11 +2453,11 @@ rs_status rs_solve(rs_ctx* c, int nrhs, const double* f, double* x, double* rel_
         // residual of the direct solve: x rows are in d_xs
         c->d_ys.ensure(ns * nrhs * sizeof(double));
         c->d_r.ensure(ns * nrhs * sizeof(double));
-        c->d_norms.ensure(2 * (size_t)nrhs * sizeof(double));
+        c->d_norms.ensure((2 * (size_t)nrhs + residual_scratch_doubles(nrhs)) * sizeof(double));
         apply_device_rows(c, c->d_xs.as<double>(), nrhs, c->d_ys.as<double>(), nullptr);
         double* colsq = c->d_norms.as<double>();
         launch_residual(c->d_frows.as<double>(), (int)n2, c->d_ys.as<double>(), (int)ns, nrhs,
-                        c->d_r.as<double>(), colsq, colsq + nrhs, s);
+                        c->d_r.as<double>(), colsq, colsq + nrhs, colsq + 2 * nrhs, s);
         std::vector<double> nrm(2 * nrhs);
         HIP_CHECK(hipMemcpyAsync(nrm.data(), colsq, nrm.size() * sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipStreamSynchronize(s));

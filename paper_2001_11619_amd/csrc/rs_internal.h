@@ -158,8 +158,10 @@ void launch_border_w(const SolveBox* boxes, int nbox, const int* ridx, const dou
 int border_g_chunks(int total_r, int p3);
 void launch_border_g(const int* ridx, int total_r, const double* Ph, const double* W, int p3, int nchunk,
                      double* Gpart, hipStream_t s);
+// scratch: sum_parts_scratch_doubles(nparts, len) doubles
+size_t sum_parts_scratch_doubles(int nparts, int len);
 void launch_sum_parts(const double* parts, int nparts, long long stride, int len,
-                      double scale, double* out, hipStream_t s);
+                      double scale, double* out, double* scratch, hipStream_t s);
 template <typename T>
 void launch_border_rhs(const SolveBox* boxes, int nbox, const int* ridx, const T* Ph, int p3,
                        const T* c, int ncols, double* parts, hipStream_t s);
@@ -183,8 +185,10 @@ void launch_accumulate_unless(const double* d, long long n, double* x, const int
 void launch_set_ints(int* p, int n, int v, hipStream_t s);
 void launch_accumulate(const double* d, long long n, double* x, hipStream_t s);
 void launch_accumulate(const float* d, long long n, double* x, hipStream_t s);
+// part: residual_scratch_doubles(ncols) doubles
+size_t residual_scratch_doubles(int ncols);
 void launch_residual(const double* f, int nf, const double* y, int nrows, int ncols, double* r,
-                     double* colsq, double* fsq, hipStream_t s);
+                     double* colsq, double* fsq, double* part, hipStream_t s);
 void launch_factor_to_float(const LevelBox* boxes, int nbox, const int* k_final, hipStream_t s);
 void launch_w_to_float(const SolveBox* boxes, int nbox, int p3, hipStream_t s);
 void launch_to_rows(const double* f, int ld, int nrows, int ncols, double* c, hipStream_t s);

@@ -164,33 +164,32 @@ __global__ void k_assemble_H(Geo g, const double* hole_xy, int p, const int* cur
   }
 }
 
-// out[t] = scale * sum_p parts[p * stride + t].  A block takes 64 outputs; its
-// 16 waves x 4 accumulators form 64 streams, stream s summing the parts
-// p = s, s + 64, s + 128, ... in order; the 64 stream sums are then added in
-// stream order (the result does not depend on timing).
-constexpr int kSumThreads = 1024;
-__global__ __launch_bounds__(kSumThreads) void k_sum_parts(const double* parts, int nparts, long long stride,
-                                                           int len, double scale, double* out) {
-  constexpr int NS = 4 * (kSumThreads / 64);
-  __shared__ double sh[NS][64];
+// out[t] = scale * sum_p parts[p * stride + t], in two passes whose order is
+// fixed (the result does not depend on timing).  Pass 1: block (tile, g) sums
+// the parts g kPartsPerBlock .. (g + 1) kPartsPerBlock - 1 for the 64 outputs
+// of its tile, wave w taking parts w, w + 4, ... of the range, the 4 wave sums
+// added in order; the range sums go to scratch[g][t].  Pass 2 adds the range
+// sums in order.
+constexpr int kPartsPerBlock = 32;
+__global__ __launch_bounds__(256) void k_sum_parts1(const double* parts, int nparts, long long stride,
+                                                    int len, double* scratch) {
+  __shared__ double sh[4][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int t = blockIdx.x * 64 + lane;
-  double a[4] = {0.0, 0.0, 0.0, 0.0};
-  if (t < len) {
-    for (int p0 = 4 * w; p0 < nparts; p0 += NS) {
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (p0 + u < nparts) a[u] += parts[(size_t)(p0 + u) * stride + t];
-    }
-  }
-#pragma unroll
-  for (int u = 0; u < 4; ++u) sh[4 * w + u][lane] = a[u];
+  const int p0 = blockIdx.y * kPartsPerBlock, p1 = min(nparts, p0 + kPartsPerBlock);
+  double a = 0.0;
+  if (t < len)
+    for (int p = p0 + w; p < p1; p += 4) a += parts[(size_t)p * stride + t];
+  sh[w][lane] = a;
   __syncthreads();
-  if (w == 0 && t < len) {
-    double sum = 0.0;
-    for (int st = 0; st < NS; ++st) sum += sh[st][lane];
-    out[t] = scale * sum;
-  }
+  if (w == 0 && t < len) scratch[(size_t)blockIdx.y * len + t] = ((sh[0][lane] + sh[1][lane]) + sh[2][lane]) + sh[3][lane];
+}
+__global__ void k_sum_parts2(const double* scratch, int ngroups, int len, double scale, double* out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= len) return;
+  double sum = 0.0;
+  for (int g = 0; g < ngroups; ++g) sum += scratch[(size_t)g * len + t];
+  out[t] = scale * sum;
 }
 
 // parts[box] (3p x ncols) = Ph_R^T c_R (accumulated in float64).  When the
@@ -356,40 +355,43 @@ __global__ void k_set_ints(int* p, int n, int v) {
   if (t < n) p[t] = v;
 }
 
-// r = [f; 0] - y  (rows layout, f has nf rows); colsq[q] = ||r_q||^2 and fsq[q] = ||f_q||^2,
-// one block per column, fixed-order sums.
-// r = [f; 0] - y for column blockIdx.x and its squared norms; one block of
-// kResThreads per column, rows taken four strides at a time (independent
-// loads in flight), sums in a fixed order.
-constexpr int kResThreads = 1024;
-__global__ __launch_bounds__(kResThreads) void k_residual(const double* f, int nf, const double* y,
-                                                         int nrows, int ncols, double* r,
-                                                         double* colsq, double* fsq) {
-  constexpr int NW = kResThreads / 64;
+// r = [f; 0] - y and the squared column norms of r and f, in two passes of
+// fixed order: block (c, q) takes rows c chunk .. (c + 1) chunk - 1 of column q
+// and writes its sums to part[(q kResChunks + c) 2 + {0, 1}]; the second pass
+// adds each column's chunk sums in order.
+constexpr int kResChunks = 32;
+__global__ __launch_bounds__(kBlock) void k_residual1(const double* f, int nf, const double* y, int nrows,
+                                                     int ncols, double* r, double* part) {
+  constexpr int NW = kBlock / 64;
   __shared__ double red[NW];
-  const int q = blockIdx.x;
+  const int c = blockIdx.x, q = blockIdx.y;
+  const int chunk = (nrows + kResChunks - 1) / kResChunks;
+  const int i0 = c * chunk, i1 = min(nrows, i0 + chunk);
   double sr = 0.0, sf = 0.0;
-  for (int i0 = threadIdx.x; i0 < nrows; i0 += 4 * kResThreads) {
-    double fi[4], yi[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int i = i0 + u * kResThreads;
-      fi[u] = i < nf ? f[(size_t)i * ncols + q] : 0.0;
-      yi[u] = i < nrows ? y[(size_t)i * ncols + q] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int i = i0 + u * kResThreads;
-      if (i >= nrows) break;
-      const double v = fi[u] - yi[u];
-      r[(size_t)i * ncols + q] = v;
-      sr += v * v;
-      sf += fi[u] * fi[u];
-    }
+  for (int i = i0 + threadIdx.x; i < i1; i += kBlock) {
+    const double fi = i < nf ? f[(size_t)i * ncols + q] : 0.0;
+    const double v = fi - y[(size_t)i * ncols + q];
+    r[(size_t)i * ncols + q] = v;
+    sr += v * v;
+    sf += fi * fi;
   }
   sr = block_sum(sr, red);
   sf = block_sum(sf, red);
-  if (threadIdx.x == 0) { colsq[q] = sr; fsq[q] = sf; }
+  if (threadIdx.x == 0) {
+    part[((size_t)q * kResChunks + c) * 2] = sr;
+    part[((size_t)q * kResChunks + c) * 2 + 1] = sf;
+  }
+}
+__global__ void k_residual2(const double* part, int ncols, double* colsq, double* fsq) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= ncols) return;
+  double sr = 0.0, sf = 0.0;
+  for (int c = 0; c < kResChunks; ++c) {
+    sr += part[((size_t)q * kResChunks + c) * 2];
+    sf += part[((size_t)q * kResChunks + c) * 2 + 1];
+  }
+  colsq[q] = sr;
+  fsq[q] = sf;
 }
 
 // float copy of W (after the border stage) for the boxes whose solve reads
@@ -456,11 +458,17 @@ void launch_assemble_H(Geo g, const double* hole_xy, int p, const int* curve_id,
                      hole_xy, p, curve_id, H, Psi);
 }
 
+size_t sum_parts_scratch_doubles(int nparts, int len) {
+  return (size_t)std::max(1, (nparts + kPartsPerBlock - 1) / kPartsPerBlock) * std::max(len, 1);
+}
+
 void launch_sum_parts(const double* parts, int nparts, long long stride, int len, double scale,
-                      double* out, hipStream_t s) {
+                      double* out, double* scratch, hipStream_t s) {
   if (len == 0) return;
-  hipLaunchKernelGGL(k_sum_parts, dim3(blocks_for(len, 64)), dim3(kSumThreads), 0, s, parts, nparts, stride,
-                     len, scale, out);
+  const int ng = std::max(1, (nparts + kPartsPerBlock - 1) / kPartsPerBlock);
+  hipLaunchKernelGGL(k_sum_parts1, dim3(blocks_for(len, 64), ng), dim3(256), 0, s, parts, nparts, stride, len,
+                     scratch);
+  hipLaunchKernelGGL(k_sum_parts2, dim3(blocks_for(len, 256)), dim3(256), 0, s, scratch, ng, len, scale, out);
 }
 
 template <typename T>
@@ -538,9 +546,13 @@ void launch_accumulate(const float* d, long long n, double* x, hipStream_t s) {
   if (n) hipLaunchKernelGGL(k_accumulate<float>, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, d, n, x);
 }
 
+size_t residual_scratch_doubles(int ncols) { return 2 * (size_t)kResChunks * std::max(ncols, 1); }
+
 void launch_residual(const double* f, int nf, const double* y, int nrows, int ncols, double* r,
-                     double* colsq, double* fsq, hipStream_t s) {
-  hipLaunchKernelGGL(k_residual, dim3(ncols), dim3(kResThreads), 0, s, f, nf, y, nrows, ncols, r, colsq, fsq);
+                     double* colsq, double* fsq, double* part, hipStream_t s) {
+  if (ncols == 0) return;
+  hipLaunchKernelGGL(k_residual1, dim3(kResChunks, ncols), dim3(kBlock), 0, s, f, nf, y, nrows, ncols, r, part);
+  hipLaunchKernelGGL(k_residual2, dim3(blocks_for(ncols, 64)), dim3(64), 0, s, part, ncols, colsq, fsq);
 }
 
 void launch_w_to_float(const SolveBox* boxes, int nbox, int p3, hipStream_t s) {
