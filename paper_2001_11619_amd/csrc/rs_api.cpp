@@ -219,8 +219,9 @@ struct rs_ctx {
   // in one device buffer per level parity, filled by one copy
   DevBuf ws_in_a, ws_in_b;
   int desc_flip = 0;
-  DevBuf ws_M, ws_R, ws_A, ws_scr, ws_src, ws_perm, ws_k, ws_kx, ws_status, ws_coop, ws_err, ws_tq,
-      ws_rc;
+  // ws_out: a level's per-box results read back by the host in one copy:
+  // error flags (4 ints) | k (nb ints, padded to even) | status (same) | rcond (nb doubles)
+  DevBuf ws_M, ws_R, ws_A, ws_scr, ws_src, ws_perm, ws_kx, ws_coop, ws_tq, ws_out;
   int n_cu = 0;                   // compute units of the device
   // root
   std::vector<int> I0;
@@ -1285,11 +1286,14 @@ void launch_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps, Level
   const std::vector<int>& fb = P.fb;
   const std::vector<std::pair<int, int>>& coop = P.coop;
   const int nfb = (int)fb.size();
-  c->ws_k.ensure(nb * sizeof(int));
   c->ws_kx.ensure(nb * sizeof(int));
-  c->ws_status.ensure(nb * sizeof(int));
-  c->ws_rc.ensure(nb * sizeof(double));
-  c->ws_err.ensure(sizeof(int) * 4);
+  const size_t nbp = ((size_t)nb + 1) & ~(size_t)1;   // keeps the rcond block 8-byte aligned
+  const size_t out_bytes = (4 + 2 * nbp) * sizeof(int) + (size_t)nb * sizeof(double);
+  c->ws_out.ensure(out_bytes);
+  int* d_err = c->ws_out.as<int>();
+  int* d_k = d_err + 4;
+  int* d_status = d_k + nbp;
+  double* d_rc = reinterpret_cast<double*>(d_status + nbp);
   const LevelBox* dlb = P.dboxes;
   if ((c->timing == 1 || c->timing == 2) && c->level_done_set) {
     const int fam = family(c, "host:between_levels");
@@ -1299,7 +1303,7 @@ void launch_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps, Level
   }
   {
     KTimer kt_(c, "cpqr");
-    launch_zero_bars(dlb, nb, c->ws_err.as<int>(), s);
+    launch_zero_bars(dlb, nb, d_err, s);
     const int4* dw = P.dwork;
     const int nA = coop.empty() ? (int)work.size() : coop.front().first;
     auto check = [&](hipError_t e, const char* what, int blocks) {
@@ -1316,26 +1320,26 @@ void launch_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps, Level
       hipStream_t s2 = fork_side(c);
       for (const auto& ch : coop) {
         KTimer kt2_(c, "cpqr.coop", true, s2);
-        check(launch_cpqr_reg(dlb, dw + ch.first, ch.second, true, prm.tol, kGuardExtra, c->ws_k.as<int>(),
-                              c->ws_kx.as<int>(), c->ws_err.as<int>(), rq_lds, s2), "register, cooperative",
+        check(launch_cpqr_reg(dlb, dw + ch.first, ch.second, true, prm.tol, kGuardExtra, d_k,
+                              c->ws_kx.as<int>(), d_err, rq_lds, s2), "register, cooperative",
               ch.second);
       }
       {
         KTimer kt2_(c, "cpqr.mem", true, s2);
-        check(launch_cpqr(dlb, P.dfb, nfb, G, prm.tol, kGuardExtra, c->ws_k.as<int>(),
-                          c->ws_kx.as<int>(), c->ws_err.as<int>(), fb_m, fb_n, s2), "memory", nfb * G);
+        check(launch_cpqr(dlb, P.dfb, nfb, G, prm.tol, kGuardExtra, d_k,
+                          c->ws_kx.as<int>(), d_err, fb_m, fb_n, s2), "memory", nfb * G);
       }
     }
     {
       KTimer kt2_(c, "cpqr.r16", true);
       check(launch_cpqr16(dlb, P.dwork16, (int)P.work16.size(), prm.tol, kGuardExtra,
-                          c->ws_k.as<int>(), c->ws_kx.as<int>(), c->ws_err.as<int>(), s),
+                          d_k, c->ws_kx.as<int>(), d_err, s),
             "16-lane", (int)P.work16.size());
     }
     {
       KTimer kt2_(c, "cpqr.reg", true);
-      check(launch_cpqr_reg(dlb, dw, nA, false, prm.tol, kGuardExtra, c->ws_k.as<int>(), c->ws_kx.as<int>(),
-                            c->ws_err.as<int>(), rq_lds, s), "register", nA);
+      check(launch_cpqr_reg(dlb, dw, nA, false, prm.tol, kGuardExtra, d_k, c->ws_kx.as<int>(),
+                            d_err, rq_lds, s), "register", nA);
     }
     if (side) join_side(c);
   }
@@ -1344,12 +1348,8 @@ void launch_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps, Level
     launch_assemble_abb(dlb, nb, max_n, prm.lambda, true, s);
   }
   // read-backs into pinned memory stay asynchronous: one wait per level
-  int* hk = c->h_rank.get<int>(3 * (size_t)nb + 3);
-  int* k0 = hk;
-  int* kk = hk + nb;
-  int* st = hk + 2 * (size_t)nb;
-  int* qr_err = hk + 3 * (size_t)nb;
-  HIP_CHECK(hipMemcpyAsync(k0, c->ws_k.p, nb * sizeof(int), hipMemcpyDeviceToHost, s));
+  int* k0 = c->h_rank.get<int>(nb);
+  HIP_CHECK(hipMemcpyAsync(k0, d_k, nb * sizeof(int), hipMemcpyDeviceToHost, s));
   // pivot orders are final after the QR (the elimination's guard only moves k)
   std::vector<int*> hperm(cs.size(), nullptr);
   for (size_t i = 0; i < cs.size(); ++i) {
@@ -1363,17 +1363,17 @@ void launch_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps, Level
   HIP_CHECK(hipEventRecord(c->ev_qr, s));
   {
     KTimer kt_(c, "eliminate");
-    HIP_CHECK(launch_eliminate(dlb, nb, Ge, c->ws_k.as<int>(), c->ws_kx.as<int>(), prm.rcond_min,
-                               c->ws_status.as<int>(), c->ws_rc.as<double>(), c->ws_err.as<int>() + 1,
+    HIP_CHECK(launch_eliminate(dlb, nb, Ge, d_k, c->ws_kx.as<int>(), prm.rcond_min,
+                               d_status, d_rc, d_err + 1,
                                max_n, s));
-    if (prm.precision == 1) launch_factor_to_float(dlb, nb, c->ws_k.as<int>(), s);
+    if (prm.precision == 1) launch_factor_to_float(dlb, nb, d_k, s);
   }
   HIP_CHECK(hipGetLastError());
-  HIP_CHECK(hipMemcpyAsync(qr_err, c->ws_err.p, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
-  HIP_CHECK(hipMemcpyAsync(kk, c->ws_k.p, nb * sizeof(int), hipMemcpyDeviceToHost, s));
-  HIP_CHECK(hipMemcpyAsync(st, c->ws_status.p, nb * sizeof(int), hipMemcpyDeviceToHost, s));
-  double* hrc = c->h_rc.get<double>(nb);
-  HIP_CHECK(hipMemcpyAsync(hrc, c->ws_rc.p, nb * sizeof(double), hipMemcpyDeviceToHost, s));
+  int* qr_err = reinterpret_cast<int*>(c->h_rc.get<double>(out_bytes / sizeof(double)));
+  HIP_CHECK(hipMemcpyAsync(qr_err, c->ws_out.p, out_bytes, hipMemcpyDeviceToHost, s));
+  int* kk = qr_err + 4;
+  int* st = kk + nbp;
+  double* hrc = reinterpret_cast<double*>(st + nbp);
   if (overlap) {
     {
       HTimer ht_(c, "host:level_wait");
