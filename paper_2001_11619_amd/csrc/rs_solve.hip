@@ -419,21 +419,26 @@ __global__ void k_from_rows(const double* c, int nrows, int ncols, double* x, in
 
 }  // namespace
 
-// Right-hand-side columns per block so that `rows` rows fit in 64 KiB of LDS.
 // Columns per block of the sweep and diagonal kernels: at most kNC, within
 // 64 KB of staged rows, and no more than the columns there are (the kernels'
-// per-column work is not spent on padding).
-inline int chunk_cols(int rows, int ncols) {
+// per-column work is not spent on padding).  When the boxes alone give fewer
+// than kFillBlocks blocks (the upper levels), the columns are split further:
+// a block's time is its rows x columns divided over 256 threads times the
+// inner length, so narrower blocks finish sooner and run side by side.
+constexpr int kFillBlocks = 512;
+inline int chunk_cols(int rows, int ncols, int nbox) {
   int nc = kNC;
   while (nc > 1 && (size_t)rows * nc * sizeof(double) > 65536) nc >>= 1;
-  return std::min(nc, std::max(ncols, 1));
+  nc = std::min(nc, std::max(ncols, 1));
+  while (nc > 1 && (long long)nbox * blocks_for(ncols, nc) < kFillBlocks) nc >>= 1;
+  return nc;
 }
 
 template <typename T>
 void launch_sweep(const SolveBox* boxes, int nbox, const int* sidx, const int* ridx, T* c,
                   int ncols, int mode, int max_n, hipStream_t s) {
   if (nbox == 0 || ncols == 0) return;
-  const int nc = chunk_cols(max_n, ncols);
+  const int nc = chunk_cols(max_n, ncols, nbox);
   dim3 grid(nbox, blocks_for(ncols, nc));
   const size_t shm = (size_t)max_n * nc * sizeof(T);
   hipLaunchKernelGGL(k_sweep<T>, grid, dim3(kBlock), shm, s, boxes, sidx, ridx, c, ncols, mode, nc);
@@ -445,7 +450,7 @@ template <typename T>
 void launch_diag(const SolveBox* boxes, int nbox, const int* ridx, T* c, int ncols, int max_r,
                  hipStream_t s) {
   if (nbox == 0 || ncols == 0) return;
-  const int nc = chunk_cols(2 * max_r, ncols);
+  const int nc = chunk_cols(2 * max_r, ncols, nbox);
   dim3 grid(nbox, blocks_for(ncols, nc));
   const size_t shm = (size_t)2 * max_r * nc * sizeof(T);
   hipLaunchKernelGGL(k_diag<T>, grid, dim3(kBlock), shm, s, boxes, ridx, c, ncols, nc);
