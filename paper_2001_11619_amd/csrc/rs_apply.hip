@@ -205,16 +205,22 @@ __global__ void k_pack_sources(Geo g, double4* src4) {
   src4[j] = make_double4(g.x[j], g.y[j], w * g.nx[j], w * g.ny[j]);
 }
 
+// Threads per block of the two node reductions below (k_apply_nsum,
+// k_apply_psi): they have one block per output, so a wide block keeps the
+// per-thread loop over the nodes short.
+constexpr int kNodeSumThreads = 1024;
+
 // nsum[q] = sum_j w_j (n_j . x_j), column q (the rank-one term's scalar);
 // one block per column, fixed-order sums.
-__global__ __launch_bounds__(kBlock) void k_apply_nsum(Geo g, const double* x, int ncols,
-                                                       double* nsum, const int* skip, int max_iters) {
+__global__ __launch_bounds__(kNodeSumThreads) void k_apply_nsum(Geo g, const double* x, int ncols,
+                                                                double* nsum, const int* skip,
+                                                                int max_iters) {
   if (apply_skipped(skip, max_iters)) return;
-  constexpr int NW = kBlock / 64;
+  constexpr int NW = kNodeSumThreads / 64;
   __shared__ double red[NW];
   const int q = blockIdx.x;
   double s = 0.0;
-  for (int j = threadIdx.x; j < g.N; j += kBlock)
+  for (int j = threadIdx.x; j < g.N; j += kNodeSumThreads)
     s += g.w[j] * (g.nx[j] * x[(size_t)(2 * j) * ncols + q] + g.ny[j] * x[(size_t)(2 * j + 1) * ncols + q]);
   s = block_sum(s, red);
   if (threadIdx.x == 0) nsum[q] = s;
@@ -300,29 +306,28 @@ __global__ void k_eval_sum(Geo g, const double* tx, const double* ty, int nt, co
 }
 
 // Rows of Psi^T x - lambda: one block per (hole, mode), fixed-order sums.
-__global__ __launch_bounds__(kBlock) void k_apply_psi(Geo g, const int* curve_id, int p,
-                                                      const double* x, int ncols, double* y,
-                                                      const int* skip, int max_iters) {
+__global__ __launch_bounds__(kNodeSumThreads) void k_apply_psi(Geo g, const int* curve_id, int p,
+                                                               const double* x, int ncols, double* y,
+                                                               const int* skip, int max_iters) {
   if (apply_skipped(skip, max_iters)) return;
-  constexpr int NW = kBlock / 64;
+  constexpr int NW = kNodeSumThreads / 64;
   __shared__ double red[NW];
   const int h = blockIdx.x / 3, mode = blockIdx.x % 3;
+  const int q = blockIdx.y;
   const size_t base = (size_t)2 * g.N;
-  for (int q = 0; q < ncols; ++q) {
-    double s = 0.0;
-    for (int j = threadIdx.x; j < g.N; j += kBlock) {
-      if (curve_id[j] != h + 1) continue;
-      const double w = g.w[j];
-      const double mx = x[(size_t)(2 * j) * ncols + q], my = x[(size_t)(2 * j + 1) * ncols + q];
-      if (mode == 0) s += w * mx;
-      else if (mode == 1) s += w * my;
-      else s += w * (-g.y[j] * mx + g.x[j] * my);
-    }
-    s = block_sum(s, red);
-    if (threadIdx.x == 0) {
-      const size_t row = base + 3 * h + mode;
-      y[row * ncols + q] = s - x[row * ncols + q];
-    }
+  double s = 0.0;
+  for (int j = threadIdx.x; j < g.N; j += kNodeSumThreads) {
+    if (curve_id[j] != h + 1) continue;
+    const double w = g.w[j];
+    const double mx = x[(size_t)(2 * j) * ncols + q], my = x[(size_t)(2 * j + 1) * ncols + q];
+    if (mode == 0) s += w * mx;
+    else if (mode == 1) s += w * my;
+    else s += w * (-g.y[j] * mx + g.x[j] * my);
+  }
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) {
+    const size_t row = base + 3 * h + mode;
+    y[row * ncols + q] = s - x[row * ncols + q];
   }
 }
 
@@ -402,6 +407,7 @@ size_t apply_scratch_doubles(int N, int ncols) {
 void launch_apply_operator(Geo g, const int* curve_id, const double* hole_xy, int p, double lam,
                            const double* x, int ncols, double* y, double* part, const int* skip,
                            int max_iters, int cfg, hipStream_t s) {
+  if (ncols <= 0 || g.N <= 0) return;
   if (!apply_config_valid(cfg, ncols)) cfg = apply_default_config(ncols);
   const ApplyShape sh = kApplyShapes[cfg];
   const int chunk = apply_chunk_len(g.N);
@@ -410,12 +416,13 @@ void launch_apply_operator(Geo g, const int* curve_id, const double* hole_xy, in
   double4* src4 = reinterpret_cast<double4*>(part + src4_offset((size_t)nchunk * 2 * g.N * ncols + ncols));
   dim3 grid(blocks_for(g.N, kApplyThreads * sh.t), nchunk, blocks_for(ncols, sh.nc));
   launch_pairs(g, src4, g.x, g.y, g.N, x, ncols, chunk, part, skip, max_iters, cfg, grid, s);
-  hipLaunchKernelGGL(k_apply_nsum, dim3(ncols), dim3(kBlock), 0, s, g, x, ncols, nsum, skip, max_iters);
+  hipLaunchKernelGGL(k_apply_nsum, dim3(ncols), dim3(kNodeSumThreads), 0, s, g, x, ncols, nsum, skip,
+                     max_iters);
   hipLaunchKernelGGL(k_apply_sum, dim3(blocks_for((long long)g.N * ncols, kBlock)), dim3(kBlock), 0, s,
                      g, lam, hole_xy, p, x, ncols, part, nchunk, nsum, y, skip, max_iters);
   if (p > 0)
-    hipLaunchKernelGGL(k_apply_psi, dim3(3 * p), dim3(kBlock), 0, s, g, curve_id, p, x, ncols, y, skip,
-                       max_iters);
+    hipLaunchKernelGGL(k_apply_psi, dim3(3 * p, ncols), dim3(kNodeSumThreads), 0, s, g, curve_id, p, x, ncols,
+                       y, skip, max_iters);
 }
 
 size_t eval_scratch_doubles(int N, int nt, int ncols) {
