@@ -210,20 +210,24 @@ __global__ void k_pack_sources(Geo g, double4* src4) {
 // per-thread loop over the nodes short.
 constexpr int kNodeSumThreads = 1024;
 
-// nsum[q] = sum_j w_j (n_j . x_j), column q (the rank-one term's scalar);
-// one block per column, fixed-order sums.
+// The rank-one term's scalar of column q, sum_j w_j (n_j . x_j), in
+// kNsumParts node ranges: block (q, b) sums range b into nsum[q kNsumParts + b]
+// and k_apply_sum adds the ranges in order (fixed-order sums).
+constexpr int kNsumParts = 8;
 __global__ __launch_bounds__(kNodeSumThreads) void k_apply_nsum(Geo g, const double* x, int ncols,
                                                                 double* nsum, const int* skip,
                                                                 int max_iters) {
   if (apply_skipped(skip, max_iters)) return;
   constexpr int NW = kNodeSumThreads / 64;
   __shared__ double red[NW];
-  const int q = blockIdx.x;
+  const int q = blockIdx.x, b = blockIdx.y;
+  const int len = (g.N + kNsumParts - 1) / kNsumParts;
+  const int j1 = min(g.N, (b + 1) * len);
   double s = 0.0;
-  for (int j = threadIdx.x; j < g.N; j += kNodeSumThreads)
+  for (int j = b * len + threadIdx.x; j < j1; j += kNodeSumThreads)
     s += g.w[j] * (g.nx[j] * x[(size_t)(2 * j) * ncols + q] + g.ny[j] * x[(size_t)(2 * j + 1) * ncols + q]);
   s = block_sum(s, red);
-  if (threadIdx.x == 0) nsum[q] = s;
+  if (threadIdx.x == 0) nsum[q * kNsumParts + b] = s;
 }
 
 // y[2N rows] = sum over source chunks (fixed order) + the diagonal (lam and
@@ -250,8 +254,10 @@ __global__ void k_apply_sum(Geo g, double lam, const double* hole_xy, int p, con
     ax += (cs * tx * tx + lam) * mx + cs * tx * ty * my;
     ay += cs * tx * ty * mx + (cs * ty * ty + lam) * my;
   }
-  ax += nxi * nsum[q];
-  ay += nyi * nsum[q];
+  double ns = 0.0;
+  for (int b = 0; b < kNsumParts; ++b) ns += nsum[q * kNsumParts + b];
+  ax += nxi * ns;
+  ay += nyi * ns;
   const double xi = g.x[i], yi = g.y[i];
   const size_t base = (size_t)2 * N;
   for (int h = 0; h < p; ++h) {
@@ -401,7 +407,7 @@ void apply_config_name(int cfg, char* buf, int len) {
 size_t apply_scratch_doubles(int N, int ncols) {
   const int len = apply_chunk_len(N);
   const int nch = (N + len - 1) / len;
-  return src4_offset((size_t)nch * 2 * N * ncols + ncols) + 4 * (size_t)N;
+  return src4_offset((size_t)nch * 2 * N * ncols + (size_t)kNsumParts * ncols) + 4 * (size_t)N;
 }
 
 void launch_apply_operator(Geo g, const int* curve_id, const double* hole_xy, int p, double lam,
@@ -413,10 +419,11 @@ void launch_apply_operator(Geo g, const int* curve_id, const double* hole_xy, in
   const int chunk = apply_chunk_len(g.N);
   const int nchunk = (g.N + chunk - 1) / chunk;
   double* nsum = part + (size_t)nchunk * 2 * g.N * ncols;
-  double4* src4 = reinterpret_cast<double4*>(part + src4_offset((size_t)nchunk * 2 * g.N * ncols + ncols));
+  double4* src4 =
+      reinterpret_cast<double4*>(part + src4_offset((size_t)nchunk * 2 * g.N * ncols + (size_t)kNsumParts * ncols));
   dim3 grid(blocks_for(g.N, kApplyThreads * sh.t), nchunk, blocks_for(ncols, sh.nc));
   launch_pairs(g, src4, g.x, g.y, g.N, x, ncols, chunk, part, skip, max_iters, cfg, grid, s);
-  hipLaunchKernelGGL(k_apply_nsum, dim3(ncols), dim3(kNodeSumThreads), 0, s, g, x, ncols, nsum, skip,
+  hipLaunchKernelGGL(k_apply_nsum, dim3(ncols, kNsumParts), dim3(kNodeSumThreads), 0, s, g, x, ncols, nsum, skip,
                      max_iters);
   hipLaunchKernelGGL(k_apply_sum, dim3(blocks_for((long long)g.N * ncols, kBlock)), dim3(kBlock), 0, s,
                      g, lam, hole_xy, p, x, ncols, part, nchunk, nsum, y, skip, max_iters);
