@@ -5,21 +5,25 @@ TEST INFRASTRUCTURE ONLY (see the package header).
 Section 2.2 (eq. lowrank): a column-pivoted QR of a block splits its columns
 into skeleton S and redundant R with M_R ~= M_S T, T = R11^{-1} R12, to a
 tolerance eps.  Readings taken where the paper is silent:
-  * pivot = remaining column of largest 2-norm, norms recomputed from the
-    trailing block at every step.  The paper says nothing about ties, and
-    mirror-symmetric node pairs make columns whose norms agree up to
-    rounding; so squared norms are compared on their leading 20 mantissa
-    bits (the low 32 bits of the float64 pattern cleared, a relative
-    quantum of 2^-20), and among the columns that tie at that precision the
-    one that came first in the block's original order is taken.  Any choice
-    within a factor 1 + 2^-20 of the largest norm keeps the rank-revealing
-    property of the pivoting;
+  * pivot = remaining column of largest 2-norm, the norms recomputed from
+    the trailing block at every step; an exact tie goes to the column that
+    came first in the block's original order.  This is the default rule
+    (`pivot="max"`), the plain column pivoting the paper names;
+  * an optional rule (`pivot="key20"`) compares the squared norms on their
+    leading 20 mantissa bits only (the low 32 bits of the float64 pattern
+    cleared, a relative quantum of 2^-20), the first column winning among
+    the columns tied at that precision.  Mirror-symmetric node pairs give
+    columns whose norms agree up to rounding, and two implementations that
+    sum in different orders pick different, equally valid, skeletons for
+    them; the coarser comparison makes such choices reproducible.  Any
+    choice within a factor 1 + 2^-20 of the largest norm keeps the
+    rank-revealing property of the pivoting;
   * the tolerance is relative: step j counts toward the rank k while
     |R_jj| > eps |R_11|.
 
 Pinned by tests/test_oracle_cpqr.py: same permutation and |R| as LAPACK
-dgeqp3 on matrices whose column norms are distinct at that precision, the
-tie rule, and the ID residual bound.
+dgeqp3 on random matrices (default rule), the tie rules of both options,
+exact rank on products of rank-k factors, and the ID residual bound.
 """
 
 from __future__ import annotations
@@ -35,14 +39,23 @@ def pivot_key(sq_norms: np.ndarray) -> np.ndarray:
     return (bits & np.uint64(0xFFFFFFFF00000000)).view(np.float64)
 
 
-class PivotedQR:
-    """Pivoted Householder QR of a copy of M, one step at a time."""
+PIVOT_RULES = ("max", "key20")
 
-    def __init__(self, M: np.ndarray):
+
+class PivotedQR:
+    """Pivoted Householder QR of a copy of M, one step at a time.
+
+    pivot: "max" (largest remaining norm, exact ties to the first column) or
+    "key20" (norms compared on their leading 20 mantissa bits)."""
+
+    def __init__(self, M: np.ndarray, pivot: str = "max"):
+        if pivot not in PIVOT_RULES:
+            raise ValueError("pivot rule %r not in %r" % (pivot, PIVOT_RULES))
         self.A = np.array(M, dtype=np.float64, copy=True)
         self.m, self.n = self.A.shape
         self.perm = np.arange(self.n)
         self.steps = 0
+        self.pivot = pivot
 
     @property
     def max_steps(self) -> int:
@@ -53,7 +66,9 @@ class PivotedQR:
         j = self.steps
         A = self.A
         sub = A[j:, j:]
-        norms = pivot_key(np.einsum("ij,ij->j", sub, sub))
+        norms = np.einsum("ij,ij->j", sub, sub)
+        if self.pivot == "key20":
+            norms = pivot_key(norms)
         mx = norms.max()
         cand = np.nonzero(norms == mx)[0]
         p = j + cand[np.argmin(self.perm[j + cand])]

@@ -71,6 +71,9 @@ class RSParams:
     n_proxy: int = 64
     proxy_ratio: float = 1.5
     rcond_min: float = 1e-12
+    pivot: str = "max"            # pivot rule of the ID's QR (oracle.cpqr.PIVOT_RULES)
+    level_parallel: bool = True   # False: the sequential scheme (each box sees the
+                                  # active set left by the boxes before it)
 
 
 @dataclass
@@ -87,6 +90,7 @@ class BoxFactor:
     Xss: np.ndarray               # k x k, in S order
     Fint: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int64))
     rank0: int = 0                # rank from the tolerance alone (before the guard)
+    m: int = 0                    # rows of the box's ID matrix M_B
 
     @property
     def S(self) -> np.ndarray:
@@ -190,7 +194,7 @@ class RSFactorization:
             z = np.zeros((0, 0))
             return BoxFactor(b.id, b.level, I, np.zeros(0, np.int64), 0, z, z, z, None, z, Fint)
         M = id_matrix(self.geom, b, I, Fint, prm)
-        qr = PivotedQR(M)
+        qr = PivotedQR(M, prm.pivot)
         k = qr.rank(prm.tol)
         k0 = k
         A = self.diag_block(b, I)
@@ -219,7 +223,7 @@ class RSFactorization:
             E = sla.lu_solve(lu, Xsr.T, trans=1).T
             Xss = Ass - Xsr @ Fm
             break
-        return BoxFactor(b.id, b.level, I, perm, k, T, E, Fm, lu, Xss, Fint, k0)
+        return BoxFactor(b.id, b.level, I, perm, k, T, E, Fm, lu, Xss, Fint, k0, M.shape[0])
 
     # ---- factorization ----------------------------------------------------
     def levels(self, l: int) -> List[Box]:
@@ -233,12 +237,19 @@ class RSFactorization:
         """
         N2 = self.geom.n_dofs
         active = np.ones(N2, dtype=bool)
+        seq = not self.prm.level_parallel
+        if seq and only is not None:
+            raise ValueError("updating is defined for the level-parallel scheme")
         for l in range(self.L, 0, -1):
             bl = self.levels(l)
             snap = active.copy()
             for b in bl:
                 if only is None or b.id in only or b.id not in self.fac:
-                    self.fac[b.id] = self.compress(b, snap)
+                    # sequential scheme (Section 2.2): a box's near field holds
+                    # only what the boxes compressed before it left active
+                    self.fac[b.id] = self.compress(b, active if seq else snap)
+                if seq:
+                    active[self.fac[b.id].R] = False
             for b in bl:
                 active[self.fac[b.id].R] = False
         self._factor_root()
@@ -317,13 +328,20 @@ class RSFactorization:
 
     # ---- solve ---------------------------------------------------------------
     def solve(self, f: np.ndarray) -> np.ndarray:
+        """[mu; lambda] for right-hand sides f of 2N rows (border rows zero, as
+        in eq. backwardeq) or 2N + 3p rows [f; g] (a general right-hand side of
+        the augmented system, e.g. a refinement residual): g enters the border
+        rows of the root system, Z [y_0; lambda] = [c_0; g - sum_B Ph_R z_R]."""
         assert self.factored
         f = np.asarray(f, dtype=np.float64)
         one = f.ndim == 1
         Fm = f.reshape(f.shape[0], -1)
         N2 = self.geom.n_dofs
         p = self.geom.n_holes
-        c = self.apply_U(Fm)
+        if Fm.shape[0] not in (N2, N2 + 3 * p):
+            raise ValueError("right-hand side must have 2N or 2N + 3p rows")
+        gb = Fm[N2:] if Fm.shape[0] > N2 else np.zeros((3 * p, Fm.shape[1]))
+        c = self.apply_U(Fm[:N2])
         y = np.zeros_like(c)
         z: Dict[int, np.ndarray] = {}
         for l in range(self.L, 0, -1):
@@ -338,7 +356,7 @@ class RSFactorization:
             for bid, zr in z.items():
                 y[self.fac[bid].R] = zr
         else:
-            rhs2 = np.zeros((3 * p, c.shape[1]))
+            rhs2 = gb.copy()
             for bid, zr in z.items():
                 rhs2 -= self.Ph[:, self.fac[bid].R] @ zr
             sol = sla.lu_solve(self.luZ, np.vstack([c[I0], rhs2]))
@@ -356,6 +374,8 @@ class RSFactorization:
     def update(self, new_geom, moved_nodes):
         """Refactor for new_geom (same root square) recompressing only the boxes
         whose compression inputs changed.  Returns the set of recompressed box ids."""
+        if not self.prm.level_parallel:
+            raise ValueError("updating is defined for the level-parallel scheme")
         old_boxes, old_fac = self.boxes, self.fac
         old_by_key = {b.key: b for b in old_boxes}
         moved = np.zeros(new_geom.n_nodes, dtype=bool)

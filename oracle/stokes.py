@@ -155,16 +155,58 @@ def dense_solve(geom, f, lam=-0.5):
     return x[:, 0] if one else x
 
 
-def apply_system(geom, x, lam=-0.5, block=2048):
-    """[f; 0] = A [mu; lambda] by blocked on-the-fly evaluation (no dense matrix kept)."""
+def apply_system(geom, x, lam=-0.5, block=32, threads=None):
+    """[f; 0] = A [mu; lambda] by on-the-fly evaluation (no dense matrix kept).
+
+    Written out from the definitions: for every target node i,
+      (D mu)_i = sum_{j != i} (w_j / pi) (r . n_j) / |r|^4 r (r . mu_j),  r = x_i - x_j
+                 - (w_i kappa_i / (2 pi)) t_i (t_i . mu_i)          (curvature limit)
+      (N mu)_i = n_i sum_j w_j (n_j . mu_j)                         (eq. null-spaceop)
+    plus lam mu_i, H lambda, and the rows Psi^T mu - lambda.  The pair sums are
+    taken for `block` target nodes at a time as products of the 2x2 kernel
+    components (c r_a r_b, an (Mt, N) matrix each) with the density components,
+    on `threads` host threads (NumPy releases the GIL)."""
+    from concurrent.futures import ThreadPoolExecutor
+    import os
+
     n = geom.n_dofs
+    N = geom.n_nodes
     p3 = 3 * geom.n_holes
+    xy, nr, w, kap = geom.xy, geom.normal, geom.weight, geom.curvature
     X = np.asarray(x, dtype=np.float64).reshape(n + p3, -1)
     out = np.zeros_like(X)
-    dofs = np.arange(n)
-    for s in range(0, n, block):
-        rows = dofs[s:s + block]
-        out[rows] = operator_entries(geom, rows, dofs, lam) @ X[:n]
+    mux = np.ascontiguousarray(X[0:n:2])
+    muy = np.ascontiguousarray(X[1:n:2])
+    yx = np.zeros_like(mux)
+    yy = np.zeros_like(muy)
+
+    def rows(t0):
+        t1 = min(N, t0 + block)
+        i = np.arange(t0, t1)
+        rx = xy[i, 0][:, None] - xy[None, :, 0]
+        ry = xy[i, 1][:, None] - xy[None, :, 1]
+        r2 = rx * rx + ry * ry
+        with np.errstate(divide="ignore", invalid="ignore"):
+            c = (INV_PI * w[None, :]) * (rx * nr[None, :, 0] + ry * nr[None, :, 1]) / (r2 * r2)
+        c[np.arange(i.size), i] = 0.0                  # the diagonal is the limit, below
+        kxy = c * rx * ry
+        yx[i] = (c * rx * rx) @ mux + kxy @ muy
+        yy[i] = kxy @ mux + (c * ry * ry) @ muy
+
+    nt = threads or min(8, os.cpu_count() or 1)
+    with ThreadPoolExecutor(nt) as ex:
+        list(ex.map(rows, range(0, N, block)))
+    tx, ty = -nr[:, 1], nr[:, 0]
+    cs = -(w * kap) / (2.0 * np.pi)
+    tmu = tx[:, None] * mux + ty[:, None] * muy
+    yx += cs[:, None] * tx[:, None] * tmu
+    yy += cs[:, None] * ty[:, None] * tmu
+    s = (w * nr[:, 0])[:, None] * mux + (w * nr[:, 1])[:, None] * muy
+    tot = s.sum(axis=0)[None, :]
+    yx += nr[:, 0][:, None] * tot + lam * mux
+    yy += nr[:, 1][:, None] * tot + lam * muy
+    out[0:n:2] = yx
+    out[1:n:2] = yy
     if p3:
         out[:n] += h_matrix(geom) @ X[n:]
         out[n:] = psi_t_matrix(geom) @ X[:n] - X[n:]

@@ -10,7 +10,8 @@ root is what makes an updated factorization identical to a fresh one,
 Section 2.8).  A node goes to the east child when x >= cx and to the north
 child when y >= cy; children are kept in the order SW, SE, NW, NE.
 
-Pinned by tests/test_oracle_tree.py (partition, leaf bound, containment).
+Pinned by tests/test_oracle_rs.py::test_tree_partition_and_leaf_bound
+(partition, leaf bound, containment, child levels).
 """
 
 from __future__ import annotations

@@ -2,8 +2,10 @@
 
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 from typing import Optional
 
 import numpy as np
@@ -62,6 +64,16 @@ class KernelTime(ctypes.Structure):
 
 
 _lib = None
+# every open context, closed by an exit hook that runs before the HIP runtime
+# and any profiler tool tear down (a context released later, from a finalizer
+# during interpreter shutdown, would call into a finalized runtime)
+_live = weakref.WeakSet()
+
+
+def close_all():
+    """Destroy every open context (also registered to run at interpreter exit)."""
+    for s in list(_live):
+        s.close()
 
 
 def library_path() -> str:
@@ -110,6 +122,7 @@ def load_library():
                  "rs_factor_batch", "rs_solve_batch", "rs_update_moved_nodes_batch"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
+    atexit.register(close_all)
     return lib
 
 
@@ -238,6 +251,7 @@ class RSSolver:
             raise RSError(st, lib.rs_last_error(None).decode())
         self.n_nodes = N
         self.n_holes = n_holes
+        _live.add(self)
 
     @classmethod
     def from_geometry(cls, geom, **kw):
@@ -372,6 +386,14 @@ class RSSolver:
         if self._h:
             self._lib.rs_destroy(self._h)
             self._h = ctypes.c_void_p()
+        _live.discard(self)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
 
     def __del__(self):
         try:

@@ -252,6 +252,10 @@ struct rs_ctx {
   hipGraphExec_t refine_exec = nullptr;   // one refinement iteration
   int refine_nrhs = 0;
   long long refine_epoch = -1;
+  // device addresses of every buffer the captured iteration reads or writes;
+  // a buffer that grew since the capture (rs_apply with more columns, a solve
+  // without refinement) has moved, and the graph is captured again
+  std::vector<const void*> refine_sig;
   double refine_prev = 1.0;       // largest relative residual before the last launch
   int refine_last = 0;            // iterations in the last launch
   DevBuf d_flag;                  // [converged, corrections applied]
@@ -1913,9 +1917,25 @@ void refine_begin(rs_ctx* c, int nrhs) {
   c->refine_last = 0;
 }
 
-// Capture one refinement iteration as a graph (once per factorization and nrhs).
+// Addresses of the buffers one refinement iteration touches (graph key).
+std::vector<const void*> refine_graph_sig(const rs_ctx* c) {
+  const DevBuf* bufs[] = {&c->d_r,     &c->d_dx,     &c->d_ys,   &c->d_xs,     &c->d_frows, &c->d_norms,
+                          &c->d_v,     &c->d_sol,    &c->d_parts, &c->d_rhs2,  &c->d_apply, &c->d_flag,
+                          &c->d_sboxes, &c->d_sidx,  &c->d_ridx,  &c->d_I0,    &c->d_Zinv,  &c->d_Ph,
+                          &c->d_W,     &c->d_Wf,     &c->d_x,     &c->d_y,     &c->d_nx,    &c->d_ny,
+                          &c->d_w,     &c->d_kap,    &c->d_curve, &c->d_hole};
+  std::vector<const void*> sig;
+  sig.reserve(sizeof(bufs) / sizeof(bufs[0]));
+  for (const DevBuf* b : bufs) sig.push_back(b->p);
+  return sig;
+}
+
+// Capture one refinement iteration as a graph (once per factorization, nrhs
+// and set of buffer addresses).
 void refine_graph_capture(rs_ctx* c, int nrhs) {
-  if (c->refine_exec && c->refine_nrhs == nrhs && c->refine_epoch == c->factor_epoch) return;
+  if (c->refine_exec && c->refine_nrhs == nrhs && c->refine_epoch == c->factor_epoch &&
+      c->refine_sig == refine_graph_sig(c))
+    return;
   HTimer ht_(c, "host:capture");
   if (c->refine_exec) {
     HIP_CHECK(hipGraphExecDestroy(c->refine_exec));
@@ -1948,6 +1968,7 @@ void refine_graph_capture(rs_ctx* c, int nrhs) {
   }
   c->refine_nrhs = nrhs;
   c->refine_epoch = c->factor_epoch;
+  c->refine_sig = refine_graph_sig(c);
 }
 
 // Iterations for the next round of graph replays (1 or 2) before the host

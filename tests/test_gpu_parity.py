@@ -1,13 +1,20 @@
 """GPU parity: the float64 HIP path through the C ABI against the CPU oracle.
 
-Bar (float64 path): per right-hand side, ||x_gpu - x_oracle|| / ||x_oracle||
-<= 1e-10, where the oracle is the plain level-parallel RS with the same tree,
-tolerance and pivot rule.  Ranks are compared box by box; skeletons may
-differ where two pivot candidates tie to rounding (the factorization is then
-a different but equally valid one), which is why parity is judged on the
-solution and the residual.  Sizes: a small multiply-connected case spanning
-several levels with ragged leaves, the single ellipse of 2048 nodes and the
-8-hole circle of 12288 nodes (the benchmark's workload) at full size.
+Two oracles (Section 2.2's pivoted QR read two ways):
+  * the oracle with the GPU's pivot rule ("key20": column norms compared on
+    their leading 20 mantissa bits, ties to the first column).  Same tree,
+    tolerance and rule: the factorizations are the same up to rounding, and
+    the bar is element by element, 1e-10 of the largest entry, separately for
+    the densities mu (2N rows) and the border unknowns (alpha, beta) (3p rows,
+    eq. backwardeq), per right-hand side;
+  * the oracle with the plain max-norm rule (its default).  Near-tied pivots
+    may then differ and give another, equally valid, factorization (the
+    discrete solution is unique, the factorization is not), so the bar is on
+    solutions: both reach the dense LU solution to O(eps), and the GPU
+    residual is no worse than the oracle's.
+Ranks are compared box by box.  Sizes: a small multiply-connected case
+spanning several levels with ragged leaves, the single ellipse of 2048 nodes
+and the 8-hole circle of 12288 nodes at full size.
 """
 
 import numpy as np
@@ -34,9 +41,28 @@ def _rel(a, b):
     return np.linalg.norm(a - b, axis=0) / np.linalg.norm(b, axis=0)
 
 
-def _case(g, nrhs, seed, leaf=64, tol=1e-10):
+def _elem(x, xo, n2):
+    """Element-wise error of the densities (rows < n2) and of the border
+    unknowns (rows >= n2), each relative to the largest entry of its part of
+    the reference; the worst over the right-hand sides."""
+    x = x.reshape(x.shape[0], -1)
+    xo = xo.reshape(xo.shape[0], -1)
+    em = np.max(np.abs(x[:n2] - xo[:n2]).max(axis=0) / np.abs(xo[:n2]).max(axis=0))
+    if x.shape[0] == n2:
+        return float(em), 0.0
+    eb = np.max(np.abs(x[n2:] - xo[n2:]).max(axis=0) / np.abs(xo[n2:]).max(axis=0))
+    return float(em), float(eb)
+
+
+def _residual(g, x, f):
+    rhs = np.vstack([f, np.zeros((3 * g.n_holes, f.shape[1]))])
+    r = stokes.apply_system(g, x) - rhs
+    return np.linalg.norm(r, axis=0) / np.linalg.norm(f, axis=0)
+
+
+def _case(g, nrhs, seed, leaf=64, tol=1e-10, pivot="key20"):
     f = boundary_data(g, exterior_forces_for_geometry(g, nrhs, seed=seed))
-    orc = RSFactorization(g, RSParams(tol=tol, leaf_size=leaf)).factor()
+    orc = RSFactorization(g, RSParams(tol=tol, leaf_size=leaf, pivot=pivot)).factor()
     xo = orc.solve(f)
     s = _solver(g, tol=tol, leaf_size=leaf).factor()
     x, res = s.solve(f, residual=True)
@@ -68,7 +94,8 @@ def test_tree_matches_oracle():
 def test_small_multiply_connected():
     g = workload_small(seed=11, n_outer=256, n_holes=2, nodes_per_hole=128, radius=3.0)
     f, orc, xo, s, x, res = _case(g, 3, 5, leaf=32)
-    assert np.all(_rel(x, xo) < 1e-10)
+    em, eb = _elem(x, xo, g.n_dofs)
+    assert em < 1e-10 and eb < 1e-10, (em, eb)
     same, total = _rank_agreement(orc, s)
     assert same == total
     # skeletons: equal sets except where column norms tie to rounding (this
@@ -80,23 +107,69 @@ def test_small_multiply_connected():
     assert np.all(res <= 1.5 * ro + 1e-14)
 
 
+def test_small_against_plain_pivot_oracle():
+    """Against the oracle with the plain max-norm pivot rule: both
+    factorizations solve the system to O(eps) against the dense LU, and the
+    GPU residual is no worse than the oracle's (up to rounding)."""
+    g = workload_small(seed=11, n_outer=256, n_holes=2, nodes_per_hole=128, radius=3.0)
+    f, orc, xo, s, x, res = _case(g, 3, 5, leaf=32, pivot="max")
+    xd = stokes.dense_solve(g, f)
+    ro = _residual(g, xo, f)
+    assert np.all(res <= 2.0 * ro + 1e-14), (res, ro)
+    for sol in (x, xo):
+        em, eb = _elem(sol, xd, g.n_dofs)
+        assert em < 1e-8 and eb < 1e-8, (em, eb)
+    same, total = _rank_agreement(orc, s)
+    assert same >= 0.9 * total
+
+
 def test_ellipse_2048_full_size():
     g = workload_ellipse_2048()
     f, orc, xo, s, x, res = _case(g, 1, 1)
-    assert np.all(_rel(x, xo) < 1e-10)
+    em, _ = _elem(x, xo, g.n_dofs)
+    assert em < 1e-10, em
     assert np.all(res < 1e-10)
     same, total = _rank_agreement(orc, s)
     assert same == total
+    # the plain max-norm oracle and the dense LU (C1 fits: 4096 unknowns)
+    orc2 = RSFactorization(g, RSParams(tol=1e-10, pivot="max")).factor()
+    xo2 = orc2.solve(f)
+    xd = stokes.dense_solve(g, f)
+    assert np.all(res <= 2.0 * _residual(g, xo2, f) + 1e-14)
+    assert _elem(x, xd, g.n_dofs)[0] < 1e-8
+    assert _elem(xo2, xd, g.n_dofs)[0] < 1e-8
+
+
+def _near_threshold(orc, g, b, k_gpu, tol):
+    """True when the oracle's |R_jj| / |R_11| at the pivot where the two
+    ranks part lies within 1e-3 of the tolerance (a decision on rounding)."""
+    from oracle.cpqr import PivotedQR
+    from oracle.rs import id_matrix
+
+    fb = orc.fac[b]
+    M = id_matrix(g, orc.boxes[b], fb.I, fb.Fint, orc.prm)
+    q = PivotedQR(M, orc.prm.pivot)
+    j = min(fb.rank0, k_gpu)
+    q.advance_to(j + 1)
+    ratio = abs(q.A[j, j]) / abs(q.A[0, 0])
+    return abs(ratio / tol - 1.0) < 1e-3
 
 
 def test_circle10_8holes_full_size():
     g = workload_circle10_8holes()
     f, orc, xo, s, x, res = _case(g, 4, 2)
-    assert np.all(_rel(x, xo) < 1e-10)
-    same, total = _rank_agreement(orc, s)
-    assert same >= total - 2
-    # residual of the exact operator: within the ID tolerance's reach
-    assert np.all(res < 5e-8)
+    em, eb = _elem(x, xo, g.n_dofs)
+    assert em < 1e-10 and eb < 1e-10, (em, eb)
+    bx = s.boxes()
+    for b, fb in orc.fac.items():
+        if fb.I.size == 0 or (bx["n"][b] == fb.I.size and bx["k"][b] == fb.k):
+            continue
+        # a box whose rank differs must be one whose pivot sits on the tolerance
+        assert bx["n"][b] == fb.I.size and _near_threshold(orc, g, b, int(bx["k"][b]), 1e-10), (
+            b, fb.I.size, fb.k, int(bx["n"][b]), int(bx["k"][b]))
+    # the GPU residual equals the oracle's (same factorization up to rounding)
+    ro = _residual(g, xo, f)
+    assert np.all(res <= 1.01 * ro + 1e-14), (res, ro)
 
 
 def test_single_leaf_is_dense_solve():
@@ -123,11 +196,12 @@ def test_many_rhs_ragged_chunks():
     g = workload_small(seed=12, n_outer=192, n_holes=3, nodes_per_hole=64, radius=3.0)
     nrhs = 37
     f = boundary_data(g, exterior_forces_for_geometry(g, nrhs, seed=8))
-    orc = RSFactorization(g, RSParams(leaf_size=24)).factor()
+    orc = RSFactorization(g, RSParams(leaf_size=24, pivot="key20")).factor()
     xo = orc.solve(f)
     s = _solver(g, leaf_size=24).factor()
     x = s.solve(f)
-    assert np.all(_rel(x, xo) < 1e-10)
+    em, eb = _elem(x, xo, g.n_dofs)
+    assert em < 1e-10 and eb < 1e-10, (em, eb)
 
 
 def test_apply_matches_oracle():
@@ -179,13 +253,14 @@ def test_wider_proxy_circle(ratio):
     radius is a parameter): same solution as the oracle, same ranks."""
     g = workload_small(seed=11, n_outer=256, n_holes=2, nodes_per_hole=128, radius=3.0)
     f = boundary_data(g, exterior_forces_for_geometry(g, 2, seed=5))
-    orc = RSFactorization(g, RSParams(leaf_size=24, proxy_ratio=ratio)).factor()
+    orc = RSFactorization(g, RSParams(leaf_size=24, proxy_ratio=ratio, pivot="key20")).factor()
     xo = orc.solve(f)
     s = _solver(g, leaf_size=24, proxy_ratio=ratio).factor()
     x = s.solve(f)
-    assert np.all(_rel(x, xo) < 1e-10)
+    em, eb = _elem(x, xo, g.n_dofs)
+    assert em < 1e-10 and eb < 1e-10, (em, eb)
     same, total = _rank_agreement(orc, s)
-    assert same >= total - 1
+    assert same == total
 
 
 @pytest.mark.parametrize("n", [1, 31, 33, 694, 1000])
@@ -270,3 +345,23 @@ def test_guard_bumps_redo_speculative_preparation():
     assert np.all(_rel(x, xd) < 1e-10)
     b = _solver(g, leaf_size=32, tol=1e-8, rcond_min=2e-3, refine_max=30, refine_tol=1e-12).factor()
     assert np.array_equal(b.solve(f), x)
+
+
+def test_guard_bumped_direct_solve_matches_oracle():
+    """The guard acting (rcond_min 2e-3 moves pivots from R to S in several
+    boxes): the direct float64 solve, without refinement, equals the oracle's
+    guarded factorization element by element, with the same pivots moved."""
+    g = workload_small(seed=11, n_outer=256, n_holes=2, nodes_per_hole=128, radius=3.0)
+    f = boundary_data(g, exterior_forces_for_geometry(g, 2, seed=5))
+    prm = RSParams(tol=1e-8, leaf_size=32, rcond_min=2e-3, pivot="key20")
+    orc = RSFactorization(g, prm).factor()
+    bumps = sum(fb.k - fb.rank0 for fb in orc.fac.values())
+    assert bumps >= 3
+    xo = orc.solve(f)
+    s = _solver(g, leaf_size=32, tol=1e-8, rcond_min=2e-3).factor()
+    assert s.stats()["guard_bumps"] == bumps
+    x = s.solve(f)
+    em, eb = _elem(x, xo, g.n_dofs)
+    assert em < 1e-10 and eb < 1e-10, (em, eb)
+    same, total = _rank_agreement(orc, s)
+    assert same == total

@@ -155,3 +155,27 @@ def test_graph_skips_converged_iterations():
     assert np.array_equal(runs[0][0], runs[1][0])
     assert runs[0][2] == runs[1][2]
     assert np.all(runs[1][1] <= 1e-10)
+
+
+def test_graph_recaptured_after_buffers_grow():
+    """A captured refinement graph holds device addresses.  An operator apply
+    with more columns than the captured solve grows (reallocates) the apply's
+    scratch; the next refined solve with the captured column count must
+    capture again, and equal the iterations launched one by one bitwise."""
+    g = workload_small(seed=11, n_outer=256, n_holes=2, nodes_per_hole=128, radius=3.0)
+    kw = dict(leaf_size=32, tol=1e-6, precision=1, refine_max=20, refine_tol=1e-10)
+    sg = _solver(g, solve_graph=1, **kw).factor()
+    se = _solver(g, solve_graph=0, **kw).factor()
+    f = boundary_data(g, exterior_forces_for_geometry(g, 1, seed=2))
+    xe = se.solve(f)
+    assert np.array_equal(sg.solve(f), xe)
+    rng = np.random.Generator(np.random.PCG64(3))
+    for ncols in (4, 9):
+        sg.apply(rng.standard_normal((g.n_system, ncols)))
+        assert np.array_equal(sg.solve(f), xe)
+    # a direct solve with more columns grows the solve's vectors too
+    sg2 = _solver(g, solve_graph=1, **kw).factor()
+    assert np.array_equal(sg2.solve(f), xe)
+    f7 = boundary_data(g, exterior_forces_for_geometry(g, 7, seed=4))
+    sg2.solve(f7)
+    assert np.array_equal(sg2.solve(f), xe)

@@ -24,8 +24,12 @@ def _solver(g, **kw):
     return RSSolver.from_geometry(g, **kw)
 
 
-def _rel(a, b):
-    return np.linalg.norm(a - b, axis=0) / np.linalg.norm(b, axis=0)
+def _elem(x, xo, n2):
+    """Element-wise error of the densities and of the border unknowns, each
+    relative to the largest entry of its part of the reference."""
+    em = np.max(np.abs(x[:n2] - xo[:n2]).max(axis=0) / np.abs(xo[:n2]).max(axis=0))
+    eb = np.max(np.abs(x[n2:] - xo[n2:]).max(axis=0) / np.abs(xo[n2:]).max(axis=0))
+    return float(em), float(eb)
 
 
 def _moved_args(g, moved):
@@ -37,7 +41,7 @@ def test_update_equals_fresh_factorization_bitwise():
     s = _solver(g, leaf_size=32).factor()
     root = tuple(s.boxes()["geom"][0])
     rng = np.random.Generator(np.random.PCG64(5))
-    orc = RSFactorization(g, RSParams(leaf_size=32)).factor()
+    orc = RSFactorization(g, RSParams(leaf_size=32, pivot="key20")).factor()
     for step in range(3):
         g2, moved = move_hole(g, 1 + step, rng, radius=6.0)
         s.update_moved_nodes(*_moved_args(g2, moved), hole_xy=g2.hole_xy)
@@ -50,8 +54,10 @@ def test_update_equals_fresh_factorization_bitwise():
         assert np.array_equal(xu, xf)
         nb = int(np.sum(fresh.boxes()["n"][1:] > 0))
         assert 0 < st["boxes_recomputed"] < 0.6 * nb
-        orc.update(g2, moved)
-        assert np.all(_rel(xu, orc.solve(f)) < 1e-10)
+        rec = orc.update(g2, moved)
+        assert sum(orc.fac[b].I.size > 0 for b in rec) == st["boxes_recomputed"]
+        em, eb = _elem(xu, orc.solve(f), g2.n_dofs)
+        assert em < 1e-10 and eb < 1e-10, (em, eb)
         g = g2
 
 
@@ -125,6 +131,12 @@ def test_update_batch_equals_single_updates():
         g.root = np.array(root)
         fresh = _solver(g, leaf_size=32, root=root).factor()
         assert np.array_equal(fresh.solve(f), xb)
+        # and against the oracle's own update of the same move (Section 2.8)
+        orc = RSFactorization(base, RSParams(leaf_size=32, pivot="key20")).factor()
+        rec = orc.update(g, moves[i][0])
+        assert sum(orc.fac[b].I.size > 0 for b in rec) == batch[i].stats()["boxes_recomputed"]
+        em, eb = _elem(xb, orc.solve(f), g.n_dofs)
+        assert em < 1e-10 and eb < 1e-10, (em, eb)
 
 
 def test_update_batch_rejects_bad_input_atomically():

@@ -5,6 +5,10 @@
 * ID accuracy: ||M_R - M_S T||_2 <= sqrt(k (n - k) + 1) |R_{k+1,k+1}| ... up
   to the factor of the strong rank-revealing bound, checked with margin.
 * Exact rank: a product of rank-k factors gives rank k at tolerance 1e-10.
+* Tie rules: the default rule ("max") takes the largest norm and only an
+  exact tie goes to the first column; the optional "key20" rule also ties
+  norms equal to 2^-20 relative.  Both rules give the same ranks and IDs of
+  the same accuracy on generic matrices.
 """
 
 import numpy as np
@@ -52,18 +56,47 @@ def test_tie_break_prefers_first_column():
     assert q.perm[0] == 0
 
 
-def test_near_tie_goes_to_first_column():
-    """Norms that agree to rounding count as tied: the earlier column wins
-    even when the later one is larger by a few ulps."""
+def test_plain_rule_takes_largest_norm_by_ulps():
+    """Default rule: a norm larger by a few ulps wins; only exact ties go to
+    the first column."""
     M = np.array([[1.0, 0.0, 1.0 + 4e-16], [0.0, 1.0, 0.0], [0.0, 0.0, 0.0]])
     q = PivotedQR(M)
+    q.step()
+    assert q.perm[0] == 2
+    M2 = np.array([[0.0, 1.0, 1.0], [1.0, 0.0, 0.0]])
+    q2 = PivotedQR(M2)
+    q2.step()
+    assert q2.perm[0] == 0
+
+
+def test_key20_near_tie_goes_to_first_column():
+    """key20 rule: norms that agree to 2^-20 count as tied and the earlier
+    column wins even when the later one is larger by a few ulps."""
+    M = np.array([[1.0, 0.0, 1.0 + 4e-16], [0.0, 1.0, 0.0], [0.0, 0.0, 0.0]])
+    q = PivotedQR(M, pivot="key20")
     q.step()
     assert q.perm[0] == 0
     # a genuine difference (1e-5 relative) is not a tie
     M2 = np.array([[1.0, 0.0, 1.0 + 1e-5], [0.0, 1.0, 0.0]])
-    q2 = PivotedQR(M2)
+    q2 = PivotedQR(M2, pivot="key20")
     q2.step()
     assert q2.perm[0] == 2
+
+
+def test_rules_agree_on_generic_matrices():
+    """On matrices without near-ties the two rules take the same pivots."""
+    rng = np.random.Generator(np.random.PCG64(21))
+    M = rng.standard_normal((120, 40)) * np.logspace(0, -6, 40)[None, :]
+    a, b = PivotedQR(M), PivotedQR(M, pivot="key20")
+    assert a.rank(1e-4) == b.rank(1e-4)
+    a.advance_to(40)
+    b.advance_to(40)
+    assert np.array_equal(a.perm, b.perm)
+
+
+def test_unknown_rule_rejected():
+    with pytest.raises(ValueError):
+        PivotedQR(np.eye(3), pivot="nearest")
 
 
 def test_pivot_key_is_truncation():

@@ -7,6 +7,16 @@
   U and V make U A V block diagonal (eq. ddef) and V X_D^{-1} U solves the
   system (eq. kinv).  A dropped term or a wrong sweep order in U, V or the
   row sweep for Psi^T V fails this at O(1).
+* The X_RR guard (the pivoting the paper asks for after eq. schurmat) driven
+  on purpose by a large rcond threshold: block diagonality and dense-LU
+  agreement still hold with the moved pivots.
+* P9, level-parallel vs sequential (Section 2.7): the sequential scheme's
+  zeroed rows only shrink the interpolation problem, the parallel T is an ID
+  of the smaller problem too, both schemes track the tolerance and their
+  total ranks differ by little.
+* P10, cost (Theorem 2.1 and Corollary cor:cost with d = 1): factorization
+  work and time, and solve work, grow linearly with N on a family of refined
+  ellipses, with bounded ranks and root size.
 * Tree invariants of Section 2.3.
 """
 
@@ -75,10 +85,8 @@ def _dense_U_V(rs):
     return U, V
 
 
-def test_brute_force_block_diagonal_tiny():
-    g = build_geometry([Curve(40, 1.0, 0.8, 0.2, 0.0, 0.0, False),
-                        Curve(20, 0.25, 0.2, 0.5, 0.3, 0.1, True)])
-    rs = RSFactorization(g, RSParams(tol=1e-14, leaf_size=4)).factor()
+def _blockdiag_error(rs, g):
+    """max |U A V - X_D| / max |A| with U, V formed explicitly from the sweeps."""
     n = g.n_dofs
     A = stokes.operator_entries(g, np.arange(n), np.arange(n), -0.5)
     U, V = _dense_U_V(rs)
@@ -96,14 +104,163 @@ def test_brute_force_block_diagonal_tiny():
                 Pm[[i, p]] = Pm[[p, i]]
             XD[np.ix_(R, R)] = Pm.T @ Lm @ Um
     XD[np.ix_(rs.I0, rs.I0)] = rs.X0
-    scale = np.abs(A).max()
-    assert np.abs(X - XD).max() < 1e-9 * scale
+    return np.abs(X - XD).max() / np.abs(A).max(), V
+
+
+def _tiny_geometry():
+    # 224 nodes, leaf 16: three levels with real compression at tolerance 1e-12
+    return build_geometry([Curve(160, 1.0, 0.8, 0.2, 0.0, 0.0, False),
+                           Curve(64, 0.25, 0.2, 0.5, 0.3, 0.1, True)])
+
+
+def test_brute_force_block_diagonal_tiny():
+    g = _tiny_geometry()
+    rs = RSFactorization(g, RSParams(tol=1e-12, leaf_size=16)).factor()
+    assert rs.L >= 3
+    # the transforms are not trivial: a third of the unknowns are eliminated
+    assert sum(fb.r for fb in rs.fac.values()) > 0.3 * g.n_dofs
+    err, V = _blockdiag_error(rs, g)
+    assert err < 1e-11
     # row sweep equals the explicit product Psi^T V
     Pt = stokes.psi_t_matrix(g)
     assert np.abs(rs.apply_Vt_rows(Pt) - Pt @ V).max() < 1e-12 * np.abs(Pt).max() * np.abs(V).max()
     # and the full solve equals the dense solve
     f = boundary_data(g, exterior_forces_for_geometry(g, 1, seed=3))
-    assert _rel(rs.solve(f), stokes.dense_solve(g, f)) < 1e-9
+    assert _rel(rs.solve(f), stokes.dense_solve(g, f)) < 1e-10
+
+
+def test_brute_force_detects_a_dropped_term():
+    """The pin is sensitive: with one box's E zeroed (a dropped term in the U
+    sweep) the product U A V is no longer block diagonal."""
+    g = _tiny_geometry()
+    rs = RSFactorization(g, RSParams(tol=1e-12, leaf_size=16)).factor()
+    fb = max(rs.fac.values(), key=lambda x: x.r * x.k)
+    assert fb.r > 0 and fb.k > 0
+    fb.E = np.zeros_like(fb.E)
+    err, _ = _blockdiag_error(rs, g)
+    assert err > 1e-4
+
+
+def test_guard_moves_pivots_and_stays_exact_tiny():
+    """rcond_min = 0.05 forces the X_RR guard on many boxes (pivots move from
+    R to S); the factorization is still block diagonal and solves the system."""
+    g = _tiny_geometry()
+    rs = RSFactorization(g, RSParams(tol=1e-12, leaf_size=16, rcond_min=0.05)).factor()
+    bumps = sum(fb.k - fb.rank0 for fb in rs.fac.values())
+    assert bumps >= 20
+    for fb in rs.fac.values():
+        if fb.r:
+            Xrr = fb.lu
+            lu, piv = Xrr
+            # every accepted X_RR meets the threshold
+            Xinv = sla.lu_solve(Xrr, np.eye(fb.r))
+            Lm = np.tril(lu, -1) + np.eye(fb.r)
+            Pm = np.eye(fb.r)
+            for i, p in enumerate(piv):
+                Pm[[i, p]] = Pm[[p, i]]
+            X = Pm.T @ Lm @ np.triu(lu)
+            assert 1.0 / (np.linalg.norm(X, 1) * np.linalg.norm(Xinv, 1)) >= 0.05
+    err, _ = _blockdiag_error(rs, g)
+    assert err < 1e-11
+    f = boundary_data(g, exterior_forces_for_geometry(g, 1, seed=3))
+    assert _rel(rs.solve(f), stokes.dense_solve(g, f)) < 1e-10
+
+
+def test_guard_bumps_agree_with_dense_lu():
+    """With rcond_min = 2e-3 the guard moves pivots in several boxes of the
+    two-hole case; the solution still agrees with the dense LU to O(eps), and
+    no worse than without the guard."""
+    g = workload_small(seed=11, n_outer=256, n_holes=2, nodes_per_hole=128, radius=3.0)
+    f = boundary_data(g, exterior_forces_for_geometry(g, 2, seed=5))
+    xd = stokes.dense_solve(g, f)
+    errs = {}
+    for rc in (1e-12, 2e-3):
+        rs = RSFactorization(g, RSParams(tol=1e-10, leaf_size=32, rcond_min=rc)).factor()
+        bumped = [fb for fb in rs.fac.values() if fb.k > fb.rank0]
+        if rc > 1e-12:
+            assert len(bumped) >= 3
+        errs[rc] = _rel(rs.solve(f), xd)
+    assert errs[2e-3] < 1e-9
+    assert errs[2e-3] <= errs[1e-12]
+
+
+def test_level_parallel_vs_sequential():
+    """P9 (Section 2.7).  At the leaf level both schemes compress the same
+    unknowns; the sequential near field is the parallel one minus the
+    unknowns already eliminated by earlier boxes, and the parallel T is an
+    interpolative decomposition of the smaller sequential problem as well
+    (the zero rows argument of Section 2.7).  Both schemes track the tolerance
+    and their total ranks differ by little (with a relative tolerance either
+    may be larger by a pivot on a box)."""
+    from oracle.rs import id_matrix
+
+    g = workload_small(seed=11, n_outer=256, n_holes=2, nodes_per_hole=128, radius=3.0)
+    f = boundary_data(g, exterior_forces_for_geometry(g, 2, seed=5))
+    tol = 1e-10
+    par = RSFactorization(g, RSParams(tol=tol, leaf_size=32)).factor()
+    seq = RSFactorization(g, RSParams(tol=tol, leaf_size=32, level_parallel=False)).factor()
+    rhs = np.vstack([f, np.zeros((3 * g.n_holes, f.shape[1]))])
+    for rs in (par, seq):
+        r = stokes.apply_system(g, rs.solve(f)) - rhs
+        assert np.linalg.norm(r) / np.linalg.norm(f) < 30 * tol
+    kp = sum(fb.k for fb in par.fac.values())
+    ks = sum(fb.k for fb in seq.fac.values())
+    assert abs(kp - ks) <= 0.02 * ks
+    leaves = [b for b in par.boxes if b.level == par.L]
+    assert len(leaves) >= 4
+    for b in leaves:
+        fp, fs = par.fac[b.id], seq.fac[b.id]
+        assert np.array_equal(fp.I, fs.I)
+        assert np.all(np.isin(fs.Fint, fp.Fint))
+        Mp = id_matrix(g, b, fp.I, fp.Fint, par.prm)
+        Ms = id_matrix(g, b, fs.I, fs.Fint, seq.prm)
+        S, R = fp.perm[: fp.k], fp.perm[fp.k:]
+        if R.size == 0:
+            continue
+        e = np.linalg.norm(Ms[:, R] - Ms[:, S] @ fp.T, 2)
+        assert e <= 100 * tol * np.linalg.norm(Mp, 2)
+    # the sequential scheme really saw fewer near-field rows somewhere
+    assert sum(seq.fac[b.id].Fint.size for b in leaves) < sum(par.fac[b.id].Fint.size for b in leaves)
+
+
+def _rs_work(rs, nrhs=1):
+    """Factor and solve flop models from the per-box shapes (m, n, k, r)."""
+    wf = ws = 0.0
+    for fb in rs.fac.values():
+        m, n, k = fb.m, fb.I.size, fb.k
+        r = n - k
+        wf += 4 * m * n * k - 2 * (m + n) * k * k + 4 / 3 * k ** 3 + k * k * r
+        wf += 6 * k * k * r + 10 * k * r * r + 2 / 3 * r ** 3
+        ws += nrhs * (8 * k * r + 2 * r * r)
+    n0 = rs.I0.size
+    return wf + 2 / 3 * n0 ** 3, ws + 2 * nrhs * n0 * n0
+
+
+def test_cost_linear_in_n():
+    """P10: refining one ellipse from 1024 to 4096 nodes multiplies the
+    factorization and solve work by ~4 (d = 1: per-level work 2^l O(k_l^3)
+    with bounded k_l), the ranks and the root stay bounded, and the oracle's
+    own factorization time grows no faster than ~linearly."""
+    import time
+
+    ws, ts, ks, roots = [], [], [], []
+    for n in (1024, 2048, 4096):
+        g = single_ellipse(n, 1.0, 0.6)
+        t0 = time.perf_counter()
+        rs = RSFactorization(g, RSParams(tol=1e-10)).factor()
+        ts.append(time.perf_counter() - t0)
+        ws.append(_rs_work(rs))
+        ks.append(max(fb.k for fb in rs.fac.values()))
+        roots.append(rs.I0.size)
+    wf = np.array([w[0] for w in ws])
+    wsv = np.array([w[1] for w in ws])
+    slope_f = np.polyfit(np.log([1024, 2048, 4096]), np.log(wf), 1)[0]
+    slope_s = np.polyfit(np.log([1024, 2048, 4096]), np.log(wsv), 1)[0]
+    assert 0.85 <= slope_f <= 1.15, slope_f
+    assert 0.85 <= slope_s <= 1.15, slope_s
+    assert max(ks) <= 1.2 * min(ks)
+    assert max(roots) <= 1.2 * min(roots)
+    assert ts[2] / ts[0] < 4 * 2.5
 
 
 def test_level_parallel_compresses():
@@ -111,3 +268,20 @@ def test_level_parallel_compresses():
     g = single_ellipse(1024, 1.0, 0.6)
     rs = RSFactorization(g, RSParams(tol=1e-10, leaf_size=64)).factor()
     assert rs.I0.size < 0.25 * g.n_dofs
+
+
+def test_solve_with_border_rows_matches_dense():
+    """A general right-hand side [f; g] of the augmented system (nonzero
+    border rows, as in a refinement residual) solves like the dense LU."""
+    g = workload_small(seed=11, n_outer=256, n_holes=2, nodes_per_hole=128, radius=3.0)
+    rng = np.random.Generator(np.random.PCG64(4))
+    rhs = rng.standard_normal((g.n_system, 2))
+    A = stokes.dense_system(g)
+    xd = sla.lu_solve(sla.lu_factor(A), rhs)
+    rs = RSFactorization(g, RSParams(tol=1e-12, leaf_size=32)).factor()
+    assert _rel(rs.solve(rhs), xd) < 1e-9
+    # and refinement with it converges to the dense solution
+    x = rs.solve(rhs)
+    for _ in range(3):
+        x = x + rs.solve(rhs - stokes.apply_system(g, x))
+    assert _rel(x, xd) < 1e-13
