@@ -9,9 +9,14 @@ iterative refinement with the exact float64 residual.  The quadtree and the
 geometry upload happen once before the timed region (their time is reported
 as setup_ms, never inside `value`).
 
-Forms: "mixed" (ID tolerance 1e-7, float32 factor application, float64
-pivoted QR / inverses / root / residual) and "plain" (float64 throughout, ID
-tolerance 1e-10); both refine to 1e-8.  The first form listed is `value`.
+Default workload: the 131072-node boundary (outer circle of radius 40 and 64
+ellipses, 262336 unknowns) with 16 right-hand sides.  Forms: "mixed" (float32
+factor application, float64 pivoted QR / inverses / root / residual, ID
+tolerance per workload) and "plain" (float64 throughout, ID tolerance 1e-10);
+both refine to 1e-8.  The first form listed is `value`.  A second line of
+work, the many-geometry batch (mixed, level-synchronous launches across
+geometries, against the float64 path run geometry by geometry), is reported
+beside it under "batch" (skip with --batch-size 0).
 
 value = right-hand sides solved per second including their factorization
       = nrhs * steps / (time of `steps` factor+solve steps).
@@ -34,14 +39,19 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6     # MI355X published FP64 vector / matrix peak
 BREAKDOWN_STEPS = 2                # untimed steps after the timed region, every kernel family timed
 HBM_PEAK_GBS = 8000.0
 
+# roofline: the kernel family whose launches the timed region brackets with
+# events (timing mode 3 = pivoted QR, 4 = exact operator apply)
 WORKLOADS = {
-    "circle10_8holes": dict(desc="outer circle R=10 (4096 nodes) + 8 random ellipses (1024 nodes each), "
-                                 "24576 unknowns + 24 border, seed 2", nrhs=4, seed=2, tol_mixed=1e-6),
-    "ellipse_2048": dict(desc="ellipse semi-axes 1.0/0.6, 2048 nodes, 4096 unknowns", nrhs=1, seed=1,
-                         tol_mixed=1e-6),
     "circle40_64holes": dict(desc="outer circle R=40 (16384 nodes) + 64 random ellipses (1792 nodes each), "
-                                  "262144 unknowns + 192 border, seed 3", nrhs=16, seed=3, tol_mixed=1e-7),
+                                  "262144 unknowns + 192 border, seed 3", nrhs=16, seed=3, tol_mixed=1e-7,
+                             roofline="apply_operator"),
+    "circle10_8holes": dict(desc="outer circle R=10 (4096 nodes) + 8 random ellipses (1024 nodes each), "
+                                 "24576 unknowns + 24 border, seed 2", nrhs=4, seed=2, tol_mixed=1e-6,
+                            roofline="cpqr"),
+    "ellipse_2048": dict(desc="ellipse semi-axes 1.0/0.6, 2048 nodes, 4096 unknowns", nrhs=1, seed=1,
+                         tol_mixed=1e-6, roofline="cpqr"),
 }
+TIMING_MODE = {"cpqr": 3, "apply_operator": 4}
 
 
 def batch_geometries(n):
@@ -98,6 +108,8 @@ def run_batch(args, forms):
         res = max(float(np.max(s.solve(f, residual=True)[1])) for s, f in zip(sv, fs))
         out[form] = {"value": nb * nrhs * args.steps / el, "ms_per_step": 1e3 * el / args.steps,
                      "setup_ms": setup_ms, "max_rel_residual": res}
+        for s in sv:
+            s.close()
         del sv
     unknowns = [g.n_system for g in geoms]
     head = out[forms[0]]
@@ -157,6 +169,8 @@ def run_evolve(args):
     fresh.factor()
     refactor_ms = fresh.stats()["ms_factor"]
     nbox = int(np.sum(fresh.boxes()["n"][1:] > 0))
+    fresh.close()
+    s.close()
     return {
         "metric": "RS factorization update (Section 2.8) vs full refactor, mixed precision, 16 rhs to 1e-8",
         "value": float(np.median(upd)), "unit": "ms/update", "higher_is_better": False, "n_gpus": 1,
@@ -178,11 +192,18 @@ def make_geometry(name):
             "circle40_64holes": W.workload_circle40_64holes}[name]()
 
 
-def cpu_baseline(geom, f, tol, repeats=3):
+def cpu_baseline(geom, f, tol, full, budget_s=15.0):
     """The CPU oracle (plain level-parallel RS, float64) on the host cores.
 
-    Sample: `repeats` full factorizations + solves of the same workload (about
-    10 s for the 12288-node geometry); value = nrhs / median time."""
+    full=True: the oracle factors the whole workload and solves it, three
+    times (median); value = nrhs / time.  full=False (workloads whose oracle
+    factorization takes far longer than the bench should run): a sample of the
+    workload.  The deepest level's boxes are compressed by the oracle with
+    their exact inputs (at that level every unknown is active) until
+    `budget_s` seconds are spent; the time per box, times the number of boxes
+    at that level, stands for the factorization.  Upper levels, the root and
+    the solve are left out, so value = nrhs / that time bounds the oracle's
+    throughput from above."""
     import numpy as np
     from threadpoolctl import threadpool_info
 
@@ -190,27 +211,76 @@ def cpu_baseline(geom, f, tol, repeats=3):
 
     threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
     nrhs = f.shape[1]
-    tf, ts = [], []
-    for _ in range(repeats):
-        t0 = time.perf_counter()
-        orc = RSFactorization(geom, RSParams(tol=tol)).factor()
-        t1 = time.perf_counter()
-        orc.solve(f)
-        t2 = time.perf_counter()
-        tf.append(t1 - t0)
-        ts.append(t2 - t1)
-    tot = float(np.median(np.array(tf) + np.array(ts)))
-    return {
-        "value": nrhs / tot,
-        "unit": "solves/s",
-        "cores": int(threads),
-        "kind": "oracle",
-        "sample": "%d full factorizations + solves of the same workload (%d rhs), median: factor %.2f s, "
-                  "solve %.3f s" % (repeats, nrhs, float(np.median(tf)), float(np.median(ts))),
-    }
+    if full:
+        tf, ts = [], []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            orc = RSFactorization(geom, RSParams(tol=tol)).factor()
+            t1 = time.perf_counter()
+            orc.solve(f)
+            t2 = time.perf_counter()
+            tf.append(t1 - t0)
+            ts.append(t2 - t1)
+        tot = float(np.median(np.array(tf) + np.array(ts)))
+        return {"value": nrhs / tot, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
+                "sample": "3 full factorizations + direct solves of the same workload (%d rhs), median: "
+                          "factor %.2f s, solve %.3f s" % (nrhs, float(np.median(tf)), float(np.median(ts)))}
+    # sample: the oracle's compression of a stratified random sample of boxes at
+    # every level below the top two, each with its exact inputs.  The level-start
+    # active sets and the children's skeletons come from the GPU's float64
+    # factorization of the same workload (same tree, tolerance and pivot rule as
+    # the oracle with the "key20" rule), so each sampled box is compressed from
+    # the unknowns and near field the full oracle run would give it.
+    import torch
+
+    from oracle.rs import BoxFactor
+    from paper_2001_11619_amd import RSSolver
+
+    gpu = RSSolver.from_geometry(geom, tol=tol)
+    gpu.set_stream(torch.cuda.current_stream().cuda_stream)
+    gpu.factor()
+    bx = gpu.boxes()
+    orc = RSFactorization(geom, RSParams(tol=tol, pivot="key20"))
+    nb = len(orc.boxes)
+    skel = [gpu.skeleton(b) if bx["n"][b] > 0 and b > 0 else np.zeros(0, np.int64) for b in range(nb)]
+    gpu.close()
+    active = np.ones(geom.n_dofs, dtype=bool)
+    rng = np.random.Generator(np.random.PCG64(0))
+    top = 2
+    per_level = budget_s / max(1, orc.L - top)
+    est, sampled, total = 0.0, 0, 0
+    for l in range(orc.L, 0, -1):
+        bl = orc.levels(l)
+        snap = active.copy()
+        if l > top:
+            t_level, done = 0.0, 0
+            for i in rng.permutation(len(bl)):
+                t0 = time.perf_counter()
+                orc.compress(bl[int(i)], snap)
+                t_level += time.perf_counter() - t0
+                done += 1
+                if t_level > per_level:
+                    break
+            est += t_level / done * len(bl)
+            sampled += done
+            total += len(bl)
+        for b in bl:
+            I = orc.box_dofs(b)
+            S = np.sort(skel[b.id].astype(np.int64))
+            # a stand-in whose skeleton is the GPU's (I = S, identity order); its
+            # X_SS block (values only, no effect on any box's shapes) is the identity
+            orc.fac[b.id] = BoxFactor(b.id, l, S, np.arange(S.size), S.size, None, None, None, None,
+                                      np.eye(S.size))
+            active[np.setdiff1d(I, S)] = False
+    return {"value": nrhs / est, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
+            "sample": "oracle compression of %d of the %d boxes of levels %d..%d (a random sample per level; "
+                      "each box's unknowns and near field from the GPU's float64 factorization, its children's "
+                      "X_SS blocks stood in by identities), scaled per level: %.1f s for %d rhs.  The top %d "
+                      "levels, the root and the solve are not counted, so the value is an upper bound on "
+                      "the oracle's throughput" % (sampled, total, orc.L, top + 1, est, nrhs, top)}
 
 
-def run_form(geom, f, form, steps, warmup, tol_plain, tol_mixed):
+def run_form(geom, f, form, steps, warmup, tol_plain, tol_mixed, roof_family):
     """Time `steps` factor + refined solve steps of one form ("plain" or "mixed")."""
     import numpy as np
     import torch
@@ -233,10 +303,10 @@ def run_form(geom, f, form, steps, warmup, tol_plain, tol_mixed):
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    # the timed region records HIP events around the pivoted-QR family only
-    # (the roofline kernel); the per-family breakdown comes from two more
-    # steps with every family and host phase timed, after the timed region
-    s.set_kernel_timing(3)
+    # the timed region records HIP events around the roofline family only; the
+    # per-family breakdown comes from two more steps with every family and
+    # host phase timed, after the timed region
+    s.set_kernel_timing(TIMING_MODE[roof_family])
     s.kernel_times(reset=True)
     torch.cuda.synchronize()
     fac_ms, sol_ms, iters = [], [], []
@@ -258,38 +328,44 @@ def run_form(geom, f, form, steps, warmup, tol_plain, tol_mixed):
     s.set_kernel_timing(False)
     st = s.stats()
     x, res = s.solve(f, residual=True)     # accuracy check outside the timed region
+    s.close()
     return {
-        "solver": s, "elapsed": elapsed, "setup_ms": setup_ms, "ktimes": ktimes, "kbreak": kbreak, "stats": st,
+        "elapsed": elapsed, "setup_ms": setup_ms, "ktimes": ktimes, "kbreak": kbreak, "stats": st,
         "factor_s": float(np.median(fac_ms)) / 1e3, "solve_s": float(np.median(sol_ms)) / 1e3,
-        "refine_iters": int(max(iters)), "max_rel_residual": float(np.max(res)),
-        "value": nrhs * steps / elapsed, "ms_per_step": 1e3 * elapsed / steps,
+        "refine_iters": int(max(iters)), "iters_per_step": [int(i) for i in iters],
+        "max_rel_residual": float(np.max(res)), "value": nrhs * steps / elapsed, "ms_per_step": 1e3 * elapsed / steps,
     }
 
 
-# sources of the pivoted-QR kernels (the counter summary is valid while they are unchanged)
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2001_11619_amd", "csrc", n) for n in ("rs_qr.hip", "rs_device.h")]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_cpqr_circle10_8holes.md")
+# counter summaries (copy-calibrated FETCH_SIZE + WRITE_SIZE per launch) of
+# the roofline kernels, valid while the listed sources are unchanged
+TRAFFIC = {
+    "cpqr": (os.path.join(ROOT, "profiles", "hbm_traffic_cpqr_circle10_8holes.md"), ("rs_qr.hip", "rs_device.h")),
+    "apply_operator": (os.path.join(ROOT, "profiles", "hbm_traffic_apply_circle40_64holes.md"),
+                       ("rs_apply.hip", "rs_device.h")),
+}
 
 
-def kernel_source_hash():
+def kernel_source_hash(names):
     import hashlib
 
     h = hashlib.sha256()
-    for path in KERNEL_SOURCES:
-        with open(path, "rb") as fh:
+    for n in names:
+        with open(os.path.join(ROOT, "paper_2001_11619_amd", "csrc", n), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def measured_traffic(workload, form, tol):
-    """HBM bytes per step of the pivoted-QR kernels from the committed counter
-    summary (FETCH_SIZE and WRITE_SIZE runs, copy-calibrated), or None when
-    the summary is for another workload, form or tolerance, or the kernels
-    changed since."""
-    if not os.path.exists(TRAFFIC_FILE):
+def measured_traffic(fam, workload, form, tol):
+    """HBM bytes per launch of the roofline kernel family from the committed
+    counter summary (FETCH_SIZE and WRITE_SIZE runs, copy-calibrated), or None
+    when the summary is for another workload, form or tolerance, or the
+    kernels changed since."""
+    if fam not in TRAFFIC or not os.path.exists(TRAFFIC[fam][0]):
         return None
+    path, srcs = TRAFFIC[fam]
     vals = {}
-    with open(TRAFFIC_FILE) as fh:
+    with open(path) as fh:
         for line in fh:
             if ":" in line and line.startswith("- "):
                 k, v = line[2:].split(":", 1)
@@ -301,39 +377,48 @@ def measured_traffic(workload, form, tol):
             return None
     except ValueError:
         return None
-    if vals.get("kernel_source_sha256") != kernel_source_hash():
+    if vals.get("kernel_source_sha256") != kernel_source_hash(srcs):
         return None
     try:
-        return float(vals["fetch_bytes_per_step"]) + float(vals["write_bytes_per_step"])
+        return float(vals["fetch_bytes_per_launch"]) + float(vals["write_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
 
 
-def roofline_of(run, steps, nrhs, n_nodes, workload, form, tol):
-    """Roofline of the dominant kernel family (by device time in the breakdown
-    steps).  Pivoted QR: the ID's algorithmic flops (row reduction 2 m n^2 -
-    2/3 n^3 plus 4 n^2 per pivoted step, or the pivoted Householder steps on
-    M_B) over the time of all its launches in the timed region (HIP events
-    recorded there for this family only); FP64 vector peak."""
+def roofline_of(run, steps, nrhs, n_nodes, workload, form, tol, fam):
+    """Roofline of the workload's dominant kernel family, timed live with HIP
+    events around each of its launches in the timed region.
+
+    apply_operator (the exact float64 residual, O(N^2)): per launch N (N - 1)
+    target-source node pairs, each 26 flops for the stresslet entries plus
+    8 flops per right-hand-side column for the 2 x 2 block times the density
+    (the per-pair count of the work model), over the average launch time.
+    cpqr (the IDs): per factorization sum over boxes of the pivoted QR to rank
+    k plus T, 4mnk - 2(m+n)k^2 + (4/3)k^3 + k^2 r, over the family's time per
+    step.  Both are float64 vector arithmetic: peak 78.6 TFLOP/s."""
     st, ktimes = run["stats"], run["ktimes"]
-    pairs = float(n_nodes) ** 2
-    models = {
-        "cpqr": ("alu", "TFLOP/s", st["flops_id"], FP64_VECTOR_PEAK_TFLOPS),
-        "eliminate": ("alu", "TFLOP/s", st["flops_elim"], FP64_VECTOR_PEAK_TFLOPS),
-    }
     dev = {k: v for k, v in run["kbreak"].items() if not k.startswith("host:") and "." not in k}
-    fam = max(dev, key=lambda k: dev[k][1]) if dev else None
-    if fam not in models or fam not in ktimes:
+    dominant = max(dev, key=lambda k: dev[k][1]) if dev else None
+    if fam not in ktimes:
         return None
-    bound, unit, work, peak = models[fam]
     launches, tot_ms = ktimes[fam]
-    per_step_s = tot_ms / 1e3 / steps
-    achieved = work / per_step_s / 1e12
-    traffic = measured_traffic(workload, form, tol) if fam == "cpqr" else None
-    return {"bound": bound, "kernel": fam, "achieved": achieved, "peak": peak, "unit": unit,
-            "frac": achieved / peak, "traffic": traffic, "traffic_unit": "bytes per step",
-            "launches_per_step": launches // steps, "ms_per_step": tot_ms / steps,
-            "work_per_step": work}
+    if fam == "apply_operator":
+        pairs = float(n_nodes) * (n_nodes - 1)
+        work = pairs * (26.0 + 8.0 * nrhs)
+        per_launch_s = tot_ms / 1e3 / launches
+        unit_desc = "flops per launch: N(N-1) node pairs x (26 + 8 nrhs)"
+    else:
+        work = st["flops_id"]
+        per_launch_s = tot_ms / 1e3 / steps
+        unit_desc = "flops per factorization (sum of the boxes' pivoted-QR + T counts)"
+    achieved = work / per_launch_s / 1e12
+    return {"bound": "alu", "kernel": fam, "dominant_family": dominant, "achieved": achieved,
+            "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+            "traffic": measured_traffic(fam, workload, form, tol),
+            "traffic_unit": "HBM bytes per launch" if fam == "apply_operator" else "HBM bytes per step",
+            "work": work, "work_unit": unit_desc, "launches_per_step": launches / steps,
+            "ms_per_launch": 1e3 * per_launch_s if fam == "apply_operator" else tot_ms / launches,
+            "ms_per_step": tot_ms / steps}
 
 
 def main():
@@ -341,14 +426,17 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="circle10_8holes", choices=sorted(WORKLOADS) + ["batch", "evolve"])
+    ap.add_argument("--workload", default="circle40_64holes", choices=sorted(WORKLOADS) + ["batch", "evolve"])
     ap.add_argument("--tol-plain", type=float, default=1e-10)
     ap.add_argument("--tol-mixed", type=float, default=None,
                     help="ID tolerance of the mixed form (default: per workload, the fastest that "
                          "refines to 1e-8 in few iterations)")
     ap.add_argument("--forms", default="mixed,plain")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--batch-size", type=int, default=32)
+    ap.add_argument("--batch-size", type=int, default=32,
+                    help="geometries of the many-geometry line (0: leave it out)")
+    ap.add_argument("--batch-steps", type=int, default=3)
+    ap.add_argument("--batch-tol-mixed", type=float, default=1e-7)
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="before the timed steps, one device copy of this many MiB (the reference "
                          "dispatch for calibrating HBM byte counters)")
@@ -374,6 +462,7 @@ def main():
         sys.exit(3)
     torch.cuda.set_device(0)
     if args.workload == "batch":
+        args.tol_mixed = args.batch_tol_mixed
         print(json.dumps(run_batch(args, [x for x in args.forms.split(",") if x])), flush=True)
         return
     if args.workload == "evolve":
@@ -390,11 +479,13 @@ def main():
     geom = make_geometry(args.workload)
     f = boundary_data(geom, exterior_forces_for_geometry(geom, wl["nrhs"], seed=wl["seed"]))
     nrhs = f.shape[1]
-    torch.cuda.set_device(0)
     forms = [x for x in args.forms.split(",") if x]
-    runs = {fm: run_form(geom, f, fm, args.steps, args.warmup, args.tol_plain, args.tol_mixed)
-            for fm in forms}
+    runs = {}
+    for fm in forms:
+        print("bench: %s form on %s" % (fm, args.workload), file=sys.stderr, flush=True)
+        runs[fm] = run_form(geom, f, fm, args.steps, args.warmup, args.tol_plain, args.tol_mixed, wl["roofline"])
     head = runs[forms[0]]
+    tol_head = args.tol_mixed if forms[0] == "mixed" else args.tol_plain
     out = {
         "metric": "RS factor s + solves/s at 1e-8 rel. residual, mixed-batched vs FP64 plain",
         "value": head["value"],
@@ -409,8 +500,7 @@ def main():
         "dtype": "f32+f64" if forms[0] == "mixed" else "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "desc": wl["desc"], "nrhs": nrhs, "form": forms[0],
-                   "tol": args.tol_mixed if forms[0] == "mixed" else args.tol_plain,
-                   "refine_tol": 1e-8, "leaf": 64, "n_proxy": 64},
+                   "tol": tol_head, "refine_tol": 1e-8, "leaf": 64, "n_proxy": 64},
         "factor_s": head["factor_s"],
         "solve_s": head["solve_s"],
         "refine_iters": head["refine_iters"],
@@ -418,8 +508,8 @@ def main():
         "setup_ms": head["setup_ms"],
         "kernel_ms_per_step": {k: v[1] / BREAKDOWN_STEPS for k, v in sorted(head["kbreak"].items())},
         "kernel_breakdown_steps": BREAKDOWN_STEPS,
-        "roofline": roofline_of(head, args.steps, nrhs, geom.n_nodes, args.workload, forms[0],
-                                args.tol_mixed if forms[0] == "mixed" else args.tol_plain),
+        "roofline": roofline_of(head, args.steps, nrhs, geom.n_nodes, args.workload, forms[0], tol_head,
+                                wl["roofline"]),
     }
     for fm in forms[1:]:
         r = runs[fm]
@@ -428,10 +518,28 @@ def main():
                              "refine_iters": r["refine_iters"],
                              "max_rel_residual": r["max_rel_residual"],
                              "kernel_ms_per_step": {k: v[1] / BREAKDOWN_STEPS
-                                                    for k, v in sorted(r["kbreak"].items())}}
+                                                    for k, v in sorted(r["kbreak"].items())},
+                             "roofline": roofline_of(r, args.steps, nrhs, geom.n_nodes, args.workload, fm,
+                                                     args.tol_plain if fm == "plain" else args.tol_mixed,
+                                                     wl["roofline"])}
         out["speedup_vs_" + fm] = head["value"] / r["value"]
+        out["factor_speedup_vs_" + fm] = r["factor_s"] / head["factor_s"]
+    if args.batch_size > 0:
+        print("bench: batch of %d geometries" % args.batch_size, file=sys.stderr, flush=True)
+        bargs = argparse.Namespace(**vars(args))
+        bargs.steps, bargs.warmup, bargs.tol_mixed = args.batch_steps, 1, args.batch_tol_mixed
+        b = run_batch(bargs, forms)
+        out["batch"] = {k: b[k] for k in ("value", "unit", "ms_per_step", "steps", "config", "max_rel_residual")}
+        for fm in forms[1:]:
+            out["batch"]["form_" + fm] = b["form_" + fm]
+            out["batch"]["speedup_vs_" + fm] = b["speedup_vs_" + fm]
+        out["batch"]["config"]["tol_mixed"] = args.batch_tol_mixed
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(geom, f, args.tol_plain)
+        print("bench: cpu baseline", file=sys.stderr, flush=True)
+        try:
+            out["cpu_baseline"] = cpu_baseline(geom, f, args.tol_plain, full=geom.n_nodes <= 20000)
+        except Exception as e:      # the GPU figures above stand without it
+            out["cpu_baseline"] = {"error": "%s: %s" % (type(e).__name__, e)}
     print(json.dumps(out), flush=True)
 
 

@@ -182,7 +182,8 @@ typedef struct {
   int max_rank;               /* largest skeleton                                  */
   int guard_bumps;            /* pivots moved from R to S by the X_RR guard        */
   long long factor_bytes;     /* bytes of factors read by one solve (T, E, F, X_RR^-1) */
-  double flops_id;            /* algorithmic flops of the pivoted QRs              */
+  double flops_id;            /* algorithmic flops of the IDs: per box the pivoted QR of M_B
+                                 stopped at rank k plus T, 4mnk - 2(m+n)k^2 + (4/3)k^3 + k^2 r */
   double flops_elim;          /* algorithmic flops of the eliminations             */
   double ms_factor;           /* wall time of the last rs_factor                   */
   double ms_solve;            /* wall time of the last rs_solve / rs_solve_dev     */
@@ -211,6 +212,16 @@ rs_status rs_get_skeleton(const rs_ctx* ctx, int box, int cap, int* out, int* le
  * y = A x, x host (2N+3p) x ncols column-major, y host same shape.  This is
  * the residual kernel used by refinement, exposed for verification. */
 rs_status rs_apply(rs_ctx* ctx, int ncols, const double* x, double* y);
+
+/* Apply the factored inverse to general right-hand sides of the augmented
+ * system (eq. kinv with the partitioned root solve of eq. partition): x =
+ * A_RS^{-1} b, where b may have nonzero border rows (its last 3p rows are the
+ * border right-hand side; the Krylov and refinement vectors of an outer
+ * iteration are such vectors).  b, x: host, (2N+3p) x ncols column-major.
+ * Uses the factor copies the solve uses (float32 ones for precision 1).
+ * RS_ERR_STATE before rs_factor; RS_ERR_ARG for NULL pointers, ncols <= 0 or a
+ * non-finite b. */
+rs_status rs_apply_inverse(rs_ctx* ctx, int ncols, const double* b, double* x);
 
 /* Velocity u(t) = (D mu)(t) + (H lambda)(t) at n_targets points t off the
  * boundary (eq. forwardeq): the double layer of the density by the boundary
@@ -241,7 +252,10 @@ typedef struct {
 } rs_kernel_time;
 /* enable: 0 off, 1 per kernel family, 2 per family and tree level ("cpqr@L7"),
  * 3 the pivoted-QR family ("cpqr") only, with no host-phase timers (the least
- * overhead, for timing a run while reporting that family's device time). */
+ * overhead, for timing a run while reporting that family's device time), 4
+ * the exact operator apply ("apply_operator") only; in mode 4 refinement
+ * iterations are launched one by one instead of as a captured graph, so that
+ * every apply is bracketed by events. */
 rs_status rs_set_kernel_timing(rs_ctx* ctx, int enable);
 /* Copies up to cap entries accumulated since the last reset; *n receives the
  * number of kernel families.  reset != 0 clears the accumulators afterwards. */

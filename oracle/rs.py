@@ -11,12 +11,19 @@ level-start set of active unknowns, Section 2.7):
   1. I_B: the box's active unknowns in ascending order (all unknowns of a
      leaf, else the union of its children's skeletons).
   2. Proxy circle (Section 2.5): centre of B, radius ratio * side, n_p
-     equispaced points, outward normals, weights 2 pi r_p / n_p.
+     equispaced points, outward normals.
   3. F_int: active unknowns not in I_B whose node lies strictly inside it.
   4. M_B = [A(F_int, B); A(B, F_int)^T; D(P, B); D(B, P)^T; S(B, P)^T;
-            (w_j n_j^T)_B; (n_j^T)_B]   (the stacked two-sided ID of Section
-     2.4 with the proxy rows of eq. greens; the last two rows carry the
-     global rank-one N exactly).
+            (w_j n_j^T)_B; w_B (n_j^T)_B]   (the stacked two-sided ID of
+     Section 2.4 with the proxy rows of eq. greens; the last two rows carry
+     the global rank-one N exactly).  Every row block is on the scale of one
+     boundary interaction: the proxy points act as targets of B's sources
+     with no weight of their own, and as sources for B's targets with weight
+     w_B, the largest quadrature weight of B's active nodes, which also
+     scales the target-side rank-one row.  The ID's relative tolerance is then
+     relative to the size of the operator's own entries (a unit-scale row
+     would set |R_11| and loosen the truncation of every kernel row by the
+     ratio of the two scales).
   5. Pivoted QR of M_B -> rank k, skeleton S, redundant R, T (eq. lowrank).
   6. A_BB: leaf -> lam I + D + N; otherwise children's X_SS on their own
      diagonal blocks and original kernel entries between different children
@@ -132,7 +139,9 @@ def id_matrix(geom, box: Box, I: np.ndarray, Fint: np.ndarray, prm: RSParams) ->
     """M_B of step 4 (all blocks without lam I, as I and F_int are disjoint)."""
     nodes, cpos = np.unique(I // 2, return_inverse=True)
     comp = I % 2
-    P, Pn, Pw, _ = proxy_circle(box.cx, box.cy, box.side, prm.n_proxy, prm.proxy_ratio)
+    P, Pn, _, _ = proxy_circle(box.cx, box.cy, box.side, prm.n_proxy, prm.proxy_ratio)
+    wB = geom.weight[nodes].max()
+    Pw = np.full(prm.n_proxy, wB)
     xy = geom.xy[nodes]
     blocks = []
     if Fint.size:
@@ -142,7 +151,7 @@ def id_matrix(geom, box: Box, I: np.ndarray, Fint: np.ndarray, prm: RSParams) ->
     blocks.append(_rows_t(stokes.double_layer_blocks(xy, P, Pn, Pw), cpos, comp))
     blocks.append(_rows_t(stokes.stokeslet_blocks(xy, P, Pw), cpos, comp))
     blocks.append((geom.weight[I // 2] * geom.normal[I // 2, comp])[None, :])
-    blocks.append(geom.normal[I // 2, comp][None, :])
+    blocks.append(wB * geom.normal[I // 2, comp][None, :])
     return np.vstack(blocks)
 
 

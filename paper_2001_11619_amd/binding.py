@@ -104,6 +104,7 @@ def load_library():
     lib.rs_get_boxes.argtypes = [h, ctypes.c_int, ip, ip, ip, ip, dp]
     lib.rs_get_skeleton.argtypes = [h, ctypes.c_int, ctypes.c_int, ip, ip]
     lib.rs_apply.argtypes = [h, ctypes.c_int, dp, dp]
+    lib.rs_apply_inverse.argtypes = [h, ctypes.c_int, dp, dp]
     lib.rs_dense_inverse.argtypes = [h, ctypes.c_int, dp, dp]
     lib.rs_evaluate.argtypes = [h, ctypes.c_int, dp, ctypes.c_int, dp, dp]
     lib.rs_factor_batch.argtypes = [P(h), ctypes.c_int]
@@ -118,6 +119,7 @@ def load_library():
     lib.rs_last_error.restype = ctypes.c_char_p
     for name in ("rs_build_tree", "rs_factor", "rs_solve", "rs_solve_dev", "rs_update_moved_nodes",
                  "rs_set_stream", "rs_get_stats", "rs_get_boxes", "rs_get_skeleton", "rs_apply",
+                 "rs_apply_inverse",
                  "rs_dense_inverse", "rs_evaluate", "rs_set_kernel_timing", "rs_get_kernel_times",
                  "rs_factor_batch", "rs_solve_batch", "rs_update_moved_nodes_batch"):
         getattr(lib, name).restype = ctypes.c_int
@@ -132,7 +134,7 @@ def exported_symbols():
     out = []
     for name in ("rs_default_params", "rs_build_tree", "rs_factor", "rs_solve", "rs_solve_dev",
                  "rs_update_moved_nodes", "rs_set_stream", "rs_get_stats", "rs_get_boxes",
-                 "rs_get_skeleton", "rs_apply", "rs_dense_inverse", "rs_evaluate",
+                 "rs_get_skeleton", "rs_apply", "rs_apply_inverse", "rs_dense_inverse", "rs_evaluate",
                  "rs_set_kernel_timing", "rs_get_kernel_times", "rs_factor_batch", "rs_solve_batch",
                  "rs_update_moved_nodes_batch", "rs_destroy", "rs_last_error"):
         if hasattr(lib, name):
@@ -304,6 +306,16 @@ class RSSolver:
         Y = np.empty_like(Xf, order="F")
         self._check(self._lib.rs_apply(self._h, Xf.shape[1], _dptr(Xf), _dptr(Y)))
         return Y[:, 0] if one else np.ascontiguousarray(Y)
+
+    def apply_inverse(self, b):
+        """Factored inverse applied to (2N + 3p) or (2N + 3p, ncols) right-hand
+        sides whose border rows may be nonzero."""
+        b = np.asarray(b, dtype=np.float64)
+        one = b.ndim == 1
+        Bf = np.asfortranarray(b.reshape(self.n_system, -1))
+        X = np.empty_like(Bf, order="F")
+        self._check(self._lib.rs_apply_inverse(self._h, Bf.shape[1], _dptr(Bf), _dptr(X)))
+        return X[:, 0] if one else np.ascontiguousarray(X)
 
     def evaluate(self, targets, x):
         """Velocity D mu + H lambda at target points (M, 2) off the boundary from a

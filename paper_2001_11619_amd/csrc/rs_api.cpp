@@ -342,6 +342,7 @@ struct KTimer {
       : c(ctx), st(on ? on : ctx->stream) {
     if (!c->timing || c->capturing || (detail && c->timing != 2)) return;
     if (c->timing == 3 && std::strcmp(name, "cpqr") != 0) return;
+    if (c->timing == 4 && std::strcmp(name, "apply_operator") != 0) return;
     if (c->timing == 2 && c->cur_level >= 0) {
       const std::string full = std::string(name) + "@L" + std::to_string(c->cur_level);
       fam = family(c, full.c_str());
@@ -370,7 +371,7 @@ struct HTimer {
   int fam = -1;
   std::chrono::steady_clock::time_point t0;
   HTimer(rs_ctx* ctx, const char* name) : c(ctx) {
-    if (!c->timing || c->timing == 3) return;
+    if (!c->timing || c->timing >= 3) return;
     fam = family(c, name);
     t0 = std::chrono::steady_clock::now();
   }
@@ -811,6 +812,8 @@ void prepare_level(rs_ctx* c, int l, const std::vector<int>& ids, const std::vec
     x.cx = B.cx;
     x.cy = B.cy;
     x.side = B.side;
+    x.wscale = 0.0;
+    for (int d : f.I) x.wscale = std::max(x.wscale, c->w[d >> 1]);
     x.n = f.n;
     x.nF = (int)F.size();
     x.m = 2 * x.nF + 6 * prm.n_proxy + 2;
@@ -934,19 +937,13 @@ void finish_level(rs_ctx* c, LevelPrep& P, const int* k0, const int* kk, const i
       throw RsError{RS_ERR_SINGULAR, "X_RR stayed singular after the pivot guard (box " +
                                          std::to_string(b) + ")"};
     c->stats.guard_bumps += f.k - f.rank0;
-    // algorithmic flop counts.  ID: a row-reduced box (mq < m) costs the
-    // unpivoted QR of M_B, 2 m n^2 - (2/3) n^3, plus the pivoted steps on the
-    // n x n factor, 4 n^2 per step; otherwise the pivoted Householder steps
-    // on M_B, 4 (m - j)(n - j) each.
+    // algorithmic flop counts.  ID: the pivoted QR of the m x n matrix M_B
+    // stopped after k steps plus T = R11^{-1} R12, 4mnk - 2(m+n)k^2 +
+    // (4/3)k^3 + k^2 r, whatever route computed it (the row reduction and
+    // the head-room steps for the guard are not counted)
     const double m = x.m, n = x.n, k = f.k, r = n - k;
-    double fid = 0;
-    const int steps = std::min<int>(x.m, std::min<int>(x.n, f.rank0 + 1 + kGuardExtra));
-    if (x.mq < x.m) {
-      fid = 2.0 * m * n * n - (2.0 / 3.0) * n * n * n + 4.0 * n * n * steps;
-    } else {
-      for (int j = 0; j < steps; ++j) fid += 4.0 * (m - j) * (n - j);
-    }
-    c->stats.flops_id += fid;
+    const double fid = 4.0 * m * n * k - 2.0 * (m + n) * k * k + (4.0 / 3.0) * k * k * k + k * k * r;
+    c->stats.flops_id += std::max(fid, 0.0);
     c->stats.flops_elim += k * k * r + 4 * k * k * r + 4 * k * r * r + 2 * r * r * r +
                            4 * k * r * r + 2 * k * k * r;
     c->stats.max_box_unknowns = std::max(c->stats.max_box_unknowns, x.n);
@@ -2059,7 +2056,9 @@ bool solve_device(rs_ctx* c, int nrhs, const double* f_dev, double* x_dev) {
   refine_begin(c, nrhs);
   apply_config_for(c, nrhs, c->d_xs.as<double>(), c->d_ys.as<double>());   // before any capture
   bool conv;
-  if (c->prm.solve_graph) {
+  // timing mode 4 times every launch of the exact apply: the iterations are
+  // launched one by one (events are not recorded inside a captured graph)
+  if (c->prm.solve_graph && c->timing != 4) {
     refine_graph_launch(c, nrhs);
     while (!refine_poll(c, nrhs, conv)) refine_graph_launch(c, nrhs);
   } else {
@@ -2370,7 +2369,7 @@ rs_status rs_solve_batch(rs_ctx** ctxs, int n, int nrhs, const double* const* f_
   std::vector<int> active;
   for (int i = 0; i < n; ++i) {
     rs_ctx* c = ctxs[i];
-    if (!c->factored || nrhs <= 0 || c->prm.refine_max <= 0 || !c->prm.solve_graph) {
+    if (!c->factored || nrhs <= 0 || c->prm.refine_max <= 0 || !c->prm.solve_graph || c->timing == 4) {
       const rs_status st = rs_solve_dev(c, nrhs, f_dev[i], x_dev[i]);
       if (st != RS_OK && worst == RS_OK) worst = st;
     } else {
@@ -2510,6 +2509,31 @@ rs_status rs_apply(rs_ctx* c, int ncols, const double* x, double* y) {
     launch_from_rows(c->d_res.as<double>(), (int)ns, ncols, c->d_f.as<double>(), (int)ns, c->stream);
     HIP_CHECK(hipMemcpyAsync(y, c->d_f.p, ns * ncols * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIP_CHECK(hipStreamSynchronize(c->stream));
+    resolve_timers(c);
+    return RS_OK;
+  } catch (const RsError& e) {
+    return fail(c, e);
+  }
+}
+
+rs_status rs_apply_inverse(rs_ctx* c, int ncols, const double* b, double* x) {
+  if (!c) return RS_ERR_ARG;
+  try {
+    if (!c->factored) throw RsError{RS_ERR_STATE, "rs_apply_inverse before rs_factor"};
+    if (ncols <= 0 || !b || !x) throw RsError{RS_ERR_ARG, "bad ncols or NULL pointer"};
+    const size_t ns = 2 * (size_t)c->N + 3 * (size_t)c->p;
+    if (!finite_all(b, ns * ncols)) throw RsError{RS_ERR_ARG, "non-finite right-hand side"};
+    HIP_CHECK(hipSetDevice(c->device));
+    hipStream_t s = c->stream;
+    c->d_f.ensure(ns * ncols * sizeof(double));
+    c->d_c.ensure(ns * ncols * sizeof(double));
+    c->d_res.ensure(ns * ncols * sizeof(double));
+    HIP_CHECK(hipMemcpyAsync(c->d_f.p, b, ns * ncols * sizeof(double), hipMemcpyHostToDevice, s));
+    launch_to_rows(c->d_f.as<double>(), (int)ns, (int)ns, ncols, c->d_c.as<double>(), s);
+    apply_inverse(c, c->d_c.as<double>(), ncols, c->d_res.as<double>());
+    launch_from_rows(c->d_res.as<double>(), (int)ns, ncols, c->d_f.as<double>(), (int)ns, s);
+    HIP_CHECK(hipMemcpyAsync(x, c->d_f.p, ns * ncols * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
     resolve_timers(c);
     return RS_OK;
   } catch (const RsError& e) {
@@ -2793,7 +2817,7 @@ rs_status rs_get_skeleton(const rs_ctx* c, int box, int cap, int* out, int* len)
 
 rs_status rs_set_kernel_timing(rs_ctx* c, int enable) {
   if (!c) return RS_ERR_ARG;
-  c->timing = enable < 0 ? 0 : (enable > 3 ? 3 : enable);
+  c->timing = enable < 0 ? 0 : (enable > 4 ? 4 : enable);
   return RS_OK;
 }
 

@@ -27,7 +27,9 @@ __global__ __launch_bounds__(kBlock) void k_assemble_M(const LevelBox* boxes, in
   const Geo& g = B.geo;
   const int np2 = 2 * n_proxy;
   const double rp = ratio * B.side;
-  const double wp = 2.0 * kPi * rp / n_proxy;
+  // target-side proxy rows and the target-side rank-one row carry the scale
+  // of one boundary interaction: the box's largest node weight
+  const double wp = B.wscale;
   int type = 6, f = 0, pa = 0;
   double px = 0, py = 0, pnx = 0, pny = 0;
   if (!live) {
@@ -97,7 +99,7 @@ __global__ __launch_bounds__(kBlock) void k_assemble_M(const LevelBox* boxes, in
         case 3: v = dl_entry(xj - px, yj - py, pnx, pny, wp, jc, pa); break;
         case 4: v = sl_entry(xj - px, yj - py, wp, jc, pa); break;
         case 5: v = wj * nj_c; break;
-        default: v = nj_c; break;
+        default: v = B.wscale * nj_c; break;
       }
       col[(size_t)cc * m] = v;
     }

@@ -23,6 +23,8 @@ struct ChildSrc;
 
 struct LevelBox {
   double cx, cy, side;
+  double wscale;  // largest quadrature weight of the box's active nodes: the weight of its
+                  // target-side proxy rows and the factor of its target-side rank-one row
   int n;          // active unknowns |I_B|
   int m;          // rows of the ID matrix M_B
   int nF;         // |F_int|
@@ -198,6 +200,7 @@ void launch_from_rows(const double* c, int nrows, int ncols, double* x, int ld, 
 // skip (nullable) holds the refinement flags: the apply is skipped once they
 // say converged or exhausted.
 size_t apply_scratch_doubles(int N, int ncols);
+
 int apply_config_count();
 bool apply_config_valid(int cfg, int ncols);
 int apply_default_config(int ncols);

@@ -58,7 +58,7 @@ def main():
         rs = RSFactorization(g, RSParams(tol=1e-10, pivot=rule)).factor()
         t1 = time.perf_counter()
         x = rs.solve(f)
-        _, res = rel_residual(g, x, f)
+        r, res = rel_residual(g, x, f)
         lev, nn, kk, ids = ranks_of(rs)
         say("pivot %s: factor %.1f s, levels %d, root %d, direct relative residual %.3e"
             % (rule, t1 - t0, rs.L, rs.I0.size, res))
@@ -67,12 +67,12 @@ def main():
         if rule == "key20":
             out["x_direct_key20"] = x
             xr = x.copy()
-            for it in range(8):
+            for it in range(1, 8):
+                xr = xr + rs.solve(r)
                 r, res = rel_residual(g, xr, f)
                 say("refinement %d: relative residual %.3e" % (it, res))
                 if res <= 1e-13:
                     break
-                xr = xr + rs.solve(r)
             out["x_ref"] = xr
             out["res_ref"] = np.array([res])
     out["f"] = f
