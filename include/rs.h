@@ -223,6 +223,27 @@ rs_status rs_apply(rs_ctx* ctx, int ncols, const double* x, double* y);
  * non-finite b. */
 rs_status rs_apply_inverse(rs_ctx* ctx, int ncols, const double* b, double* x);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the exact
+ * operator apply of rs_apply, y = A x, that allocates nothing.  x_dev, y_dev:
+ * device pointers, (2N+3p) x ncols column-major, owned by the caller; the
+ * work is enqueued on the context's stream and the call returns without
+ * waiting (y_dev is valid once the stream reaches that point).  Every
+ * intermediate (row-layout copies of x and y, the partial sums of the pair
+ * sums) lives in one fixed device array of 8 Mi doubles (64 MiB) that the
+ * library holds per device until the process ends; the call fails with
+ * RS_ERR_ARG, touching nothing, when what it needs exceeds that: two copies of
+ * (2N+3p) x ncols plus the partial sums, one 2N x ncols block per source
+ * chunk (48 chunks at 12288 nodes; the message states the need).  The
+ * 12288-node, 8-hole workload fits up to 6 columns.
+ * The apply shape is the one the autotuner chose for (N, ncols) earlier in
+ * the process, else the default one (every shape gives bitwise the same y).
+ * All calls on one device share that array: calls that overlap in time on
+ * one device (other streams, other contexts, other host threads) race and
+ * must be serialised by the caller.  Nothing in the array needs to start at
+ * zero. */
+rs_status rs_apply_dev_noalloc(rs_ctx* ctx, int ncols, const double* x_dev, double* y_dev);
+
 /* Velocity u(t) = (D mu)(t) + (H lambda)(t) at n_targets points t off the
  * boundary (eq. forwardeq): the double layer of the density by the boundary
  * quadrature plus the Stokeslet and rotlet of every hole.  targets_xy: host,

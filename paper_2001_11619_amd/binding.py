@@ -105,6 +105,7 @@ def load_library():
     lib.rs_get_skeleton.argtypes = [h, ctypes.c_int, ctypes.c_int, ip, ip]
     lib.rs_apply.argtypes = [h, ctypes.c_int, dp, dp]
     lib.rs_apply_inverse.argtypes = [h, ctypes.c_int, dp, dp]
+    lib.rs_apply_dev_noalloc.argtypes = [h, ctypes.c_int, vp, vp]
     lib.rs_dense_inverse.argtypes = [h, ctypes.c_int, dp, dp]
     lib.rs_evaluate.argtypes = [h, ctypes.c_int, dp, ctypes.c_int, dp, dp]
     lib.rs_factor_batch.argtypes = [P(h), ctypes.c_int]
@@ -119,7 +120,7 @@ def load_library():
     lib.rs_last_error.restype = ctypes.c_char_p
     for name in ("rs_build_tree", "rs_factor", "rs_solve", "rs_solve_dev", "rs_update_moved_nodes",
                  "rs_set_stream", "rs_get_stats", "rs_get_boxes", "rs_get_skeleton", "rs_apply",
-                 "rs_apply_inverse",
+                 "rs_apply_inverse", "rs_apply_dev_noalloc",
                  "rs_dense_inverse", "rs_evaluate", "rs_set_kernel_timing", "rs_get_kernel_times",
                  "rs_factor_batch", "rs_solve_batch", "rs_update_moved_nodes_batch"):
         getattr(lib, name).restype = ctypes.c_int
@@ -306,6 +307,14 @@ class RSSolver:
         Y = np.empty_like(Xf, order="F")
         self._check(self._lib.rs_apply(self._h, Xf.shape[1], _dptr(Xf), _dptr(Y)))
         return Y[:, 0] if one else np.ascontiguousarray(Y)
+
+    def apply_dev_noalloc(self, x_dev, y_dev):
+        """y = A x on device tensors without allocating (rs_apply_dev_noalloc):
+        x_dev, y_dev of shape (ncols, 2N + 3p), contiguous, float64 (the
+        column-major layout); enqueued on the context's stream."""
+        ncols = int(x_dev.shape[0])
+        self._check(self._lib.rs_apply_dev_noalloc(self._h, ncols, ctypes.c_void_p(x_dev.data_ptr()),
+                                                   ctypes.c_void_p(y_dev.data_ptr())))
 
     def apply_inverse(self, b):
         """Factored inverse applied to (2N + 3p) or (2N + 3p, ncols) right-hand

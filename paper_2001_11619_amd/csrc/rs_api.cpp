@@ -2141,6 +2141,18 @@ int apply_config_for(rs_ctx* c, int ncols, const double* xrows, double* yrows) {
   return best;
 }
 
+// The apply shape without running the autotuner (no launches, no memory):
+// the fixed shape, the tuned one if this problem shape was tuned before in
+// the process, else the default.
+int apply_config_cached(const rs_ctx* c, int ncols) {
+  if (c->prm.apply_shape >= 0)
+    return apply_config_valid(c->prm.apply_shape, ncols) ? c->prm.apply_shape : apply_default_config(ncols);
+  ApplyTuneCache& tc = apply_tune_cache();
+  std::lock_guard<std::mutex> lk(tc.mu);
+  auto it = tc.best.find(std::pair<int, int>{c->N, ncols});
+  return it != tc.best.end() ? it->second.first : apply_default_config(ncols);
+}
+
 // y = A x on the device (rows layout).  skip (nullable): refinement flags; the
 // apply is skipped on the device once they say converged or exhausted.
 void apply_device_rows(rs_ctx* c, const double* xrows, int ncols, double* yrows, const int* skip) {
@@ -2535,6 +2547,36 @@ rs_status rs_apply_inverse(rs_ctx* c, int ncols, const double* b, double* x) {
     HIP_CHECK(hipMemcpyAsync(x, c->d_f.p, ns * ncols * sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_CHECK(hipStreamSynchronize(s));
     resolve_timers(c);
+    return RS_OK;
+  } catch (const RsError& e) {
+    return fail(c, e);
+  }
+}
+
+rs_status rs_apply_dev_noalloc(rs_ctx* c, int ncols, const double* x_dev, double* y_dev) {
+  if (!c) return RS_ERR_ARG;
+  try {
+    if (ncols <= 0 || !x_dev || !y_dev) throw RsError{RS_ERR_ARG, "bad ncols or NULL pointer"};
+    HIP_CHECK(hipSetDevice(c->device));
+    const size_t ns = 2 * (size_t)c->N + 3 * (size_t)c->p;
+    const size_t rows = ns * (size_t)ncols;
+    const size_t off = (2 * rows + 31) / 32 * 32;         // partial sums 256-byte aligned
+    const size_t need = off + apply_scratch_doubles(c->N, ncols);
+    if (need > noalloc_scratch_doubles())
+      throw RsError{RS_ERR_ARG, "rs_apply_dev_noalloc: " + std::to_string(ncols) + " columns of " +
+                                    std::to_string(ns) + " unknowns need " + std::to_string(need) +
+                                    " doubles of scratch; the fixed per-device array holds " +
+                                    std::to_string(noalloc_scratch_doubles())};
+    double* scr = nullptr;
+    HIP_CHECK(noalloc_scratch(c->device, &scr));
+    hipStream_t s = c->stream;
+    Geo g;
+    geo_of(c, g);
+    launch_to_rows(x_dev, (int)ns, (int)ns, ncols, scr, s);
+    launch_apply_operator(g, c->d_curve.as<int>(), c->d_hole.as<double>(), c->p, c->prm.lambda, scr, ncols,
+                          scr + rows, scr + off, nullptr, 0, apply_config_cached(c, ncols), s);
+    launch_from_rows(scr + rows, (int)ns, ncols, y_dev, (int)ns, s);
+    HIP_CHECK(hipGetLastError());
     return RS_OK;
   } catch (const RsError& e) {
     return fail(c, e);

@@ -3,6 +3,7 @@
 #include "rs_device.h"
 
 #include <cstdio>
+#include <mutex>
 #include <type_traits>
 
 namespace rs {
@@ -430,6 +431,36 @@ void launch_apply_operator(Geo g, const int* curve_id, const double* hole_xy, in
   if (p > 0)
     hipLaunchKernelGGL(k_apply_psi, dim3(3 * p, ncols), dim3(kNodeSumThreads), 0, s, g, curve_id, p, x, ncols,
                        y, skip, max_iters);
+}
+
+// ---- fixed device scratch of the allocation-free apply ------------------------
+// rs_apply_dev_noalloc keeps its row-layout copies of x and y and the apply's
+// partial sums in this array instead of memory it allocates.  Each device the
+// library runs on holds its own copy for the life of the process; its device
+// address is looked up once per device (in host code the name `scratch` is a
+// host-side stand-in, never a device address) and only that address is passed
+// to kernels.
+namespace {
+constexpr size_t kNoAllocScratchDoubles = (size_t)8 << 20;   // 64 MiB per device
+__device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+size_t noalloc_scratch_doubles() { return kNoAllocScratchDoubles; }
+
+hipError_t noalloc_scratch(int device, double** out) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
 }
 
 size_t eval_scratch_doubles(int N, int nt, int ncols) {

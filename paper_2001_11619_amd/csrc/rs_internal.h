@@ -200,7 +200,11 @@ void launch_from_rows(const double* c, int nrows, int ncols, double* x, int ld, 
 // skip (nullable) holds the refinement flags: the apply is skipped once they
 // say converged or exhausted.
 size_t apply_scratch_doubles(int N, int ncols);
-
+// the fixed per-device array of the allocation-free apply: its size in
+// doubles, and its device address on `device` (which must be current;
+// looked up on the first call per device)
+size_t noalloc_scratch_doubles();
+hipError_t noalloc_scratch(int device, double** out);
 int apply_config_count();
 bool apply_config_valid(int cfg, int ncols);
 int apply_default_config(int ncols);
