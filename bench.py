@@ -359,8 +359,8 @@ def kernel_source_hash(names):
 def measured_traffic(fam, workload, form, tol):
     """HBM bytes per launch of the roofline kernel family from the committed
     counter summary (FETCH_SIZE and WRITE_SIZE runs, copy-calibrated), or None
-    when the summary is for another workload, form or tolerance, or the
-    kernels changed since."""
+    when the summary is for another workload, form or tolerance ("any" where
+    they do not change the kernel's work), or the kernels changed since."""
     if fam not in TRAFFIC or not os.path.exists(TRAFFIC[fam][0]):
         return None
     path, srcs = TRAFFIC[fam]
@@ -370,13 +370,14 @@ def measured_traffic(fam, workload, form, tol):
             if ":" in line and line.startswith("- "):
                 k, v = line[2:].split(":", 1)
                 vals[k.strip()] = v.strip().strip("`")
-    if vals.get("workload") != workload or vals.get("form") != form:
+    if vals.get("workload") != workload or vals.get("form") not in (form, "any"):
         return None
-    try:
-        if float(vals.get("tol", "nan")) != tol:
+    if vals.get("tol") != "any":
+        try:
+            if float(vals.get("tol", "nan")) != tol:
+                return None
+        except ValueError:
             return None
-    except ValueError:
-        return None
     if vals.get("kernel_source_sha256") != kernel_source_hash(srcs):
         return None
     try:
