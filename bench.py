@@ -152,6 +152,7 @@ def run_evolve(args):
     upd, sol, res, recomp = [], [], [], []
     t_all = time.perf_counter()
     for t in range(args.evolve_steps):
+        print("evolve: step %d" % t, file=sys.stderr, flush=True)
         g, moved = W.move_hole(g, 1 + t % g.n_holes if args.evolve_all else 1, rng)
         s.update_moved_nodes(moved, g.xy[moved], g.normal[moved], g.weight[moved], g.curvature[moved],
                              hole_xy=g.hole_xy)
@@ -165,10 +166,15 @@ def run_evolve(args):
     el = time.perf_counter() - t_all
     g.root = np.array(root)
     fresh = RSSolver.from_geometry(g, root=root, **kw)
+    fresh.set_stream(torch.cuda.current_stream().cuda_stream)
     fresh.factor()
     fresh.factor()
     refactor_ms = fresh.stats()["ms_factor"]
     nbox = int(np.sum(fresh.boxes()["n"][1:] > 0))
+    # Section 2.8: the updated factorization is the fresh one of the new
+    # geometry (same root): the solves agree bitwise
+    f = boundary_data(g, exterior_forces_for_geometry(g, nrhs, seed=999))
+    p8 = bool(np.array_equal(s.solve(f), fresh.solve(f)))
     fresh.close()
     s.close()
     return {
@@ -181,7 +187,8 @@ def run_evolve(args):
         "refactor_ms": refactor_ms, "speedup_update_vs_refactor": refactor_ms / float(np.median(upd)),
         "boxes_recomputed_median": float(np.median(recomp)), "boxes_total": nbox,
         "solve_ms_median": float(np.median(sol)), "max_rel_residual": float(np.max(res)),
-        "residual_per_step": res, "wall_s": el,
+        "update_equals_refactor_bitwise": p8,
+        "update_ms_per_step": upd, "residual_per_step": res, "wall_s": el,
     }
 
 
@@ -441,7 +448,7 @@ def main():
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="before the timed steps, one device copy of this many MiB (the reference "
                          "dispatch for calibrating HBM byte counters)")
-    ap.add_argument("--evolve-steps", type=int, default=10)
+    ap.add_argument("--evolve-steps", type=int, default=100)
     ap.add_argument("--evolve-all", action="store_true", help="move hole 1, 2, 3, ... in turn")
     args = ap.parse_args()
     if args.tol_mixed is None:
@@ -455,12 +462,6 @@ def main():
 
     from workloads import boundary_data, exterior_forces_for_geometry
 
-    if args.workload == "evolve":
-        # The mixed-precision factorization of the moved 64-hole geometry faulted
-        # the device twice; it stays off until it has been rerun on fixed code.
-        print("bench.py: workload %s is disabled (device-fault case not yet rerun)" % args.workload,
-              file=sys.stderr)
-        sys.exit(3)
     torch.cuda.set_device(0)
     if args.workload == "batch":
         args.tol_mixed = args.batch_tol_mixed

@@ -1477,6 +1477,18 @@ void build_solve_meta(rs_ctx* c) {
         }
       }
   }
+  // Every solve kernel reads a box's float factors together (T, E, F in the
+  // sweeps; X_RR^-1 in the diagonal step; W in the border fix) once Tf is set,
+  // and its float64 factors otherwise: the float pointers must be all set or
+  // all null, and W's float copy must exist exactly for the float boxes.
+  for (auto& lv : c->sboxes)
+    for (auto& sb : lv) {
+      const bool f = sb.Tf != nullptr;
+      const bool wf_ok = !p3 || (sb.Wf != nullptr) == (f && c->prm.precision == 1);
+      if ((sb.Ef != nullptr) != f || (sb.Ff != nullptr) != f || (sb.Xinvf != nullptr) != f || !wf_ok ||
+          (sb.r > 0 && !sb.Xinv) || (p3 && !sb.W))
+        throw RsError{RS_ERR_DEVICE, "inconsistent factor pointers in the solve metadata"};
+    }
   std::vector<SolveBox> flat;
   c->sbox_off.assign(L + 2, 0);
   for (int l = 0; l <= L; ++l) {
