@@ -64,7 +64,14 @@ typedef struct {
   int precision;       /* 0 = float64 throughout; 1 = mixed: float32 copies of T, E, F, X_RR^-1
                           (and the border W) serve the solve for every box whose rcond_1(X_RR)
                           is at least mixed_rcond_min (the others keep float64); vectors, sums,
-                          the pivoted QR, the inverses and the root stay float64                 */
+                          the pivoted QR, the inverses and the root stay float64; 2 = float32
+                          bulk: as 1, and moreover the entries of M_B and A_BB are computed in
+                          float32 from box-local offsets and the Schur-complement products
+                          (X_SR, X_RS, X_RR of eq. tmat; E, F, X_SS of eq. schurmat) run on
+                          FP32 matrix cores with float32 accumulation; the pivoted QR (rank
+                          decision), T, the X_RR inverse with its guard, the root and the
+                          refinement residual stay float64.  Its entries carry float32
+                          rounding, so its ID tolerance should stay above ~1e-6           */
   double refine_tol;   /* refinement target: max-column ||[f;0] - A x||_2 / ||f||_2             */
   int refine_max;      /* 0: direct solve; > 0: at most this many refinement iterations        */
   int has_root;        /* 1: use root[] as the fixed root square; 0: bounding square of nodes */
@@ -147,6 +154,23 @@ rs_status rs_update_moved_nodes(rs_ctx* ctx, int n_moved, const int* idx, const 
  * as after its own rs_factor.  On failure every context is left unfactored
  * and carries the message. */
 rs_status rs_factor_batch(rs_ctx** ctxs, int n);
+
+/* Update after curves were inserted or deleted (Section 2.8's updating applied
+ * to the experiment of Section 4.2, where holes are added to and removed from
+ * the domain): the context receives a whole new boundary, in the arrays and
+ * conventions of rs_build_tree (N and p may both change), and old_of_new[j],
+ * the old index of new node j or -1 for a node that did not exist.  Kept nodes
+ * keep their relative order and their data (position, normal, weight,
+ * curvature), else RS_ERR_ARG.  The context's root square is kept
+ * (RS_ERR_OUT_OF_ROOT if a node lies outside it).  Boxes whose compression
+ * inputs are unchanged keep their factors; the others, and the root with H
+ * and Psi^T for the new set of holes, are recomputed.  The result equals a
+ * fresh factorization of the new boundary with the same root.  RS_ERR_STATE
+ * before rs_factor.  Argument errors leave the context as it was; any later
+ * failure leaves it unfactored. */
+rs_status rs_update_geometry(rs_ctx* ctx, int n_nodes, const double* xy, const double* normal,
+                             const double* weight, const double* curvature, const int* curve_id,
+                             int n_holes, const double* hole_xy, const int* old_of_new);
 
 /* rs_update_moved_nodes for n contexts together (the related geometries of one
  * finite-difference step of a shape optimization, Section 4's Scheme A): every

@@ -383,12 +383,55 @@ class RSFactorization:
     def update(self, new_geom, moved_nodes):
         """Refactor for new_geom (same root square) recompressing only the boxes
         whose compression inputs changed.  Returns the set of recompressed box ids."""
-        if not self.prm.level_parallel:
-            raise ValueError("updating is defined for the level-parallel scheme")
-        old_boxes, old_fac = self.boxes, self.fac
-        old_by_key = {b.key: b for b in old_boxes}
         moved = np.zeros(new_geom.n_nodes, dtype=bool)
         moved[np.asarray(moved_nodes, dtype=np.int64)] = True
+        return self._update(new_geom, moved, np.arange(self.geom.n_nodes))
+
+    def update_geometry(self, new_geom, old_of_new):
+        """The update of Section 2.8 when curves are inserted or deleted (the
+        experiment of Section 4.2): new_geom has its own node numbering and
+        number of holes; old_of_new[j] is the old index of new node j, or -1
+        for a node that did not exist.  Kept nodes must keep their relative
+        order and their data.  A box is recompressed exactly when an input of
+        its compression changed (new or deleted nodes count as changed), and
+        the root, H and Psi^T are rebuilt for the new holes.  Returns the set
+        of recompressed box ids."""
+        old_of_new = np.asarray(old_of_new, dtype=np.int64)
+        if old_of_new.shape != (new_geom.n_nodes,):
+            raise ValueError("old_of_new must have one entry per new node")
+        kept = np.nonzero(old_of_new >= 0)[0]
+        ko = old_of_new[kept]
+        if np.any(np.diff(ko) <= 0) or (ko.size and (ko[0] < 0 or ko[-1] >= self.geom.n_nodes)):
+            raise ValueError("kept nodes must keep their relative order")
+        g0 = self.geom
+        for a in ("xy", "normal"):
+            if not np.array_equal(getattr(new_geom, a)[kept], getattr(g0, a)[ko]):
+                raise ValueError("kept nodes must keep their data")
+        for a in ("weight", "curvature"):
+            if not np.array_equal(getattr(new_geom, a)[kept], getattr(g0, a)[ko]):
+                raise ValueError("kept nodes must keep their data")
+        new_of_old = np.full(g0.n_nodes, -1, dtype=np.int64)
+        new_of_old[ko] = kept
+        moved = old_of_new < 0
+        return self._update(new_geom, moved, new_of_old)
+
+    def _update(self, new_geom, moved, new_of_old):
+        """moved: per new node, True if its data are new; new_of_old: per old
+        node, its new index or -1 (deleted).  Old index sets are carried into
+        the new numbering before they are compared or kept."""
+        if not self.prm.level_parallel:
+            raise ValueError("updating is defined for the level-parallel scheme")
+
+        def nodes_new(nodes):      # deleted nodes map below -1, so sets with them never match
+            m = new_of_old[nodes]
+            return np.where(m >= 0, m, -2 - nodes)
+
+        def dofs_new(d):
+            m = new_of_old[d // 2]
+            return np.where(m >= 0, 2 * m + d % 2, -2 - d)
+
+        old_boxes, old_fac = self.boxes, self.fac
+        old_by_key = {b.key: b for b in old_boxes}
         self.geom = new_geom
         self.boxes = build_tree(new_geom.xy, self.prm.leaf_size, self.root)
         self.L = depth(self.boxes)
@@ -403,8 +446,11 @@ class RSFactorization:
                 ofb = old_fac.get(ob.id) if ob is not None else None
                 changed = ob is None or ofb is None or ob.is_leaf != b.is_leaf
                 if not changed:
+                    kI = dofs_new(ofb.I)
+                    changed = bool(np.any(kI < 0))
+                if not changed:
                     if b.is_leaf:
-                        changed = not np.array_equal(ob.nodes, b.nodes) or bool(moved[b.nodes].any())
+                        changed = not np.array_equal(nodes_new(ob.nodes), b.nodes) or bool(moved[b.nodes].any())
                     else:
                         okeys = sorted(old_boxes[c].key for c in ob.children)
                         nkeys = sorted(self.boxes[c].key for c in b.children)
@@ -412,13 +458,13 @@ class RSFactorization:
                 if not changed:
                     I = self.box_dofs(b)
                     Fint = self.far_near(b, I, snap)
-                    changed = (not np.array_equal(Fint, ofb.Fint)) or bool(moved[Fint // 2].any())
+                    changed = (not np.array_equal(Fint, dofs_new(ofb.Fint))) or bool(moved[Fint // 2].any())
                 if changed:
                     self.fac[b.id] = self.compress(b, snap)
                     recomputed.add(b.id)
                 else:
-                    ofb.box = b.id
-                    self.fac[b.id] = ofb
+                    self.fac[b.id] = BoxFactor(b.id, ofb.level, kI, ofb.perm, ofb.k, ofb.T, ofb.E, ofb.F, ofb.lu,
+                                               ofb.Xss, dofs_new(ofb.Fint), ofb.rank0, ofb.m)
             for b in bl:
                 active[self.fac[b.id].R] = False
         self._factor_root()

@@ -99,6 +99,7 @@ def load_library():
     lib.rs_solve.argtypes = [h, ctypes.c_int, dp, dp, dp]
     lib.rs_solve_dev.argtypes = [h, ctypes.c_int, vp, vp]
     lib.rs_update_moved_nodes.argtypes = [h, ctypes.c_int, ip, dp, dp, dp, dp, dp]
+    lib.rs_update_geometry.argtypes = [h, ctypes.c_int, dp, dp, dp, dp, ip, ctypes.c_int, dp, ip]
     lib.rs_set_stream.argtypes = [h, vp]
     lib.rs_get_stats.argtypes = [h, P(Stats)]
     lib.rs_get_boxes.argtypes = [h, ctypes.c_int, ip, ip, ip, ip, dp]
@@ -119,6 +120,7 @@ def load_library():
     lib.rs_last_error.argtypes = [h]
     lib.rs_last_error.restype = ctypes.c_char_p
     for name in ("rs_build_tree", "rs_factor", "rs_solve", "rs_solve_dev", "rs_update_moved_nodes",
+                 "rs_update_geometry",
                  "rs_set_stream", "rs_get_stats", "rs_get_boxes", "rs_get_skeleton", "rs_apply",
                  "rs_apply_inverse", "rs_apply_dev_noalloc",
                  "rs_dense_inverse", "rs_evaluate", "rs_set_kernel_timing", "rs_get_kernel_times",
@@ -134,7 +136,7 @@ def exported_symbols():
     lib = load_library()
     out = []
     for name in ("rs_default_params", "rs_build_tree", "rs_factor", "rs_solve", "rs_solve_dev",
-                 "rs_update_moved_nodes", "rs_set_stream", "rs_get_stats", "rs_get_boxes",
+                 "rs_update_moved_nodes", "rs_update_geometry", "rs_set_stream", "rs_get_stats", "rs_get_boxes",
                  "rs_get_skeleton", "rs_apply", "rs_apply_inverse", "rs_dense_inverse", "rs_evaluate",
                  "rs_set_kernel_timing", "rs_get_kernel_times", "rs_factor_batch", "rs_solve_batch",
                  "rs_update_moved_nodes_batch", "rs_destroy", "rs_last_error"):
@@ -362,6 +364,27 @@ class RSSolver:
             hp = _dptr(hole_xy)
         self._check(self._lib.rs_update_moved_nodes(self._h, n, _iptr(idx), _dptr(xy), _dptr(normal),
                                                     _dptr(weight), _dptr(curvature), hp))
+        return self
+
+    def update_geometry(self, xy, normal, weight, curvature, curve_id, old_of_new, hole_xy=None):
+        """A new boundary (curves inserted or deleted); old_of_new[j] = old index
+        of new node j or -1."""
+        xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
+        N = xy.shape[0]
+        normal = np.ascontiguousarray(normal, dtype=np.float64).reshape(N, 2)
+        weight = np.ascontiguousarray(weight, dtype=np.float64).reshape(N)
+        curvature = np.ascontiguousarray(curvature, dtype=np.float64).reshape(N)
+        curve_id = np.ascontiguousarray(curve_id, dtype=np.int32).reshape(N)
+        oon = np.ascontiguousarray(old_of_new, dtype=np.int32).reshape(N)
+        n_holes = int(curve_id.max()) if N else 0
+        hp = None
+        if hole_xy is not None and n_holes:
+            hole_xy = np.ascontiguousarray(hole_xy, dtype=np.float64).reshape(n_holes, 2)
+            hp = _dptr(hole_xy)
+        self._check(self._lib.rs_update_geometry(self._h, N, _dptr(xy), _dptr(normal), _dptr(weight),
+                                                 _dptr(curvature), _iptr(curve_id), n_holes, hp, _iptr(oon)))
+        self.n_nodes = N
+        self.n_holes = n_holes
         return self
 
     def set_stream(self, stream_ptr: int):

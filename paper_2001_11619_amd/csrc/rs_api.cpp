@@ -829,7 +829,7 @@ void prepare_level(rs_ctx* c, int l, const std::vector<int>& ids, const std::vec
     totN2 += n2;
     totScr += 3 * n2 + 128 * (size_t)x.n + 2048;
     totArena += 3 * (n2 / 4 + x.n) + 2 * n2;
-    if (prm.precision == 1) totArena += (3 * (n2 / 4 + x.n) + n2 + 1) / 2 + 4;
+    if (prm.precision >= 1) totArena += (3 * (n2 / 4 + x.n) + n2 + 1) / 2 + 4;
     P.max_m = std::max(P.max_m, x.m);
     P.max_n = std::max(P.max_n, x.n);
     P.lb.push_back(x);
@@ -883,7 +883,7 @@ void prepare_level(rs_ctx* c, int l, const std::vector<int>& ids, const std::vec
     pa += n2;
     x.Xss = pa;
     pa += n2;
-    if (prm.precision == 1) {
+    if (prm.precision >= 1) {
       float* pf = reinterpret_cast<float*>(pa);
       x.Tf = pf;
       pf += kr;
@@ -1251,7 +1251,7 @@ void pre_launch(std::vector<rs_ctx*>& cs, LevelPlan& P, hipStream_t st) {
   const LevelBox* dlb = P.dboxes;
   {
     KTimer kt_(c, "assemble_M", false, st);
-    launch_assemble_M(dlb, P.nb, P.max_m, prm.n_proxy, prm.proxy_ratio, st);
+    launch_assemble_M(dlb, P.nb, P.max_m, prm.n_proxy, prm.proxy_ratio, prm.precision == 2, st);
   }
   if (P.round_first.size() > 1) {
     KTimer kt_(c, "cpqr", false, st);
@@ -1346,7 +1346,7 @@ void launch_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps, Level
   }
   {
     KTimer kt_(c, "assemble_abb");
-    launch_assemble_abb(dlb, nb, max_n, prm.lambda, true, s);
+    launch_assemble_abb(dlb, nb, max_n, prm.lambda, true, prm.precision == 2, s);
   }
   // read-backs into pinned memory stay asynchronous: one wait per level
   int* k0 = c->h_rank.get<int>(nb);
@@ -1366,8 +1366,8 @@ void launch_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps, Level
     KTimer kt_(c, "eliminate");
     HIP_CHECK(launch_eliminate(dlb, nb, Ge, d_k, c->ws_kx.as<int>(), prm.rcond_min,
                                d_status, d_rc, d_err + 1,
-                               max_n, s));
-    if (prm.precision == 1) launch_factor_to_float(dlb, nb, d_k, s);
+                               max_n, prm.precision == 2, prm.mixed_rcond_min, s));
+    if (prm.precision >= 1) launch_factor_to_float(dlb, nb, d_k, s);
   }
   HIP_CHECK(hipGetLastError());
   int* qr_err = reinterpret_cast<int*>(c->h_rc.get<double>(out_bytes / sizeof(double)));
@@ -1434,7 +1434,7 @@ void build_solve_meta(rs_ctx* c) {
     sb.W = nullptr;
     // mixed precision: the float copies serve the solve only where X_RR is
     // well conditioned; elsewhere the box's float64 factors are read
-    const bool use_f = c->prm.precision == 1 && f.rcond >= c->prm.mixed_rcond_min && f.Tf;
+    const bool use_f = c->prm.precision >= 1 && f.rcond >= c->prm.mixed_rcond_min && f.Tf;
     sb.Tf = use_f ? f.Tf : nullptr;
     sb.Ef = use_f ? f.Ef : nullptr;
     sb.Ff = use_f ? f.Ff : nullptr;
@@ -1459,7 +1459,7 @@ void build_solve_meta(rs_ctx* c) {
     c->d_W.ensure(std::max<size_t>(totW, 1) * sizeof(double));
     double* pw = c->d_W.as<double>();
     float* pwf = nullptr;
-    if (c->prm.precision == 1) {
+    if (c->prm.precision >= 1) {
       c->d_Wf.ensure(std::max<size_t>(totW, 1) * sizeof(float));
       pwf = c->d_Wf.as<float>();
     }
@@ -1484,7 +1484,7 @@ void build_solve_meta(rs_ctx* c) {
   for (auto& lv : c->sboxes)
     for (auto& sb : lv) {
       const bool f = sb.Tf != nullptr;
-      const bool wf_ok = !p3 || (sb.Wf != nullptr) == (f && c->prm.precision == 1);
+      const bool wf_ok = !p3 || (sb.Wf != nullptr) == (f && c->prm.precision >= 1);
       if ((sb.Ef != nullptr) != f || (sb.Ff != nullptr) != f || (sb.Xinvf != nullptr) != f || !wf_ok ||
           (sb.r > 0 && !sb.Xinv) || (p3 && !sb.W))
         throw RsError{RS_ERR_DEVICE, "inconsistent factor pointers in the solve metadata"};
@@ -1560,7 +1560,7 @@ void factor_root(rs_ctx* c) {
     upload(c->d_root_box, v, s);
     {
       KTimer kt_(c, "root_abb");
-      launch_assemble_abb(c->d_root_box.as<LevelBox>(), 1, n0, c->prm.lambda, false, s);
+      launch_assemble_abb(c->d_root_box.as<LevelBox>(), 1, n0, c->prm.lambda, false, false, s);
     }
   }
   build_solve_meta(c);
@@ -1606,7 +1606,7 @@ void factor_root(rs_ctx* c) {
       launch_sum_parts(c->d_Gpart.as<double>(), nch, (long long)p3 * p3, p3 * p3, 1.0, c->d_G.as<double>(),
                        c->d_Gpart.as<double>() + gparts, s);
     }
-    if (c->prm.precision == 1) launch_w_to_float(level_sboxes(c, 1), all_nb, p3, s);
+    if (c->prm.precision >= 1) launch_w_to_float(level_sboxes(c, 1), all_nb, p3, s);
     c->d_Z.ensure((size_t)nz * nz * sizeof(double));
     {
       KTimer kt_(c, "root_Z");
@@ -2261,7 +2261,7 @@ rs_status rs_build_tree(const rs_params* prm, int n_nodes, const double* xy, con
     if (!curve_id) throw RsError{RS_ERR_ARG, "NULL curve_id"};
     if (!(prm->tol > 0.0) || prm->leaf_size < 1 || prm->n_proxy < 4 || !(prm->proxy_ratio > 1.0))
       throw RsError{RS_ERR_ARG, "invalid tolerance, leaf size, proxy count or proxy ratio"};
-    if (prm->precision != 0 && prm->precision != 1) throw RsError{RS_ERR_ARG, "precision must be 0 or 1"};
+    if (prm->precision < 0 || prm->precision > 2) throw RsError{RS_ERR_ARG, "precision must be 0, 1 or 2"};
     if (!(prm->mixed_rcond_min >= 0.0) || !std::isfinite(prm->mixed_rcond_min))
       throw RsError{RS_ERR_ARG, "mixed_rcond_min must be finite and >= 0"};
     validate_nodes(n_nodes, xy, normal, weight, curvature);
@@ -2722,6 +2722,100 @@ void begin_update(rs_ctx* c, int n_moved, const int* idx, const double* xy, cons
   c->old = &O;
 }
 
+// Update after curves were inserted or deleted: validate the new boundary and
+// the node correspondence, carry the old tree's index sets into the new
+// numbering (deleted nodes map to values no new index takes, so any set that
+// held one differs), and install the new geometry.
+void begin_update_geometry(rs_ctx* c, int n_nodes, const double* xy, const double* normal,
+                           const double* weight, const double* curvature, const int* curve_id, int n_holes,
+                           const double* hole_xy, const int* old_of_new, OldState& O) {
+  if (n_nodes <= 0 || n_holes < 0 || !curve_id || !old_of_new)
+    throw RsError{RS_ERR_ARG, "bad n_nodes or n_holes, or NULL curve_id / old_of_new"};
+  validate_nodes(n_nodes, xy, normal, weight, curvature);
+  std::vector<int> count(n_holes + 1, 0);
+  for (int i = 0; i < n_nodes; ++i) {
+    if (curve_id[i] < 0 || curve_id[i] > n_holes) throw RsError{RS_ERR_ARG, "curve_id out of range"};
+    count[curve_id[i]]++;
+  }
+  for (int h = 1; h <= n_holes; ++h)
+    if (!count[h]) throw RsError{RS_ERR_ARG, "hole " + std::to_string(h) + " has no nodes"};
+  if (hole_xy && !finite_all(hole_xy, 2 * (size_t)n_holes)) throw RsError{RS_ERR_ARG, "non-finite hole point"};
+  const int n_old = c->N;
+  std::vector<int> new_of_old(n_old, -1);
+  int last = -1;
+  for (int j = 0; j < n_nodes; ++j) {
+    const int o = old_of_new[j];
+    if (o < -1 || o >= n_old) throw RsError{RS_ERR_ARG, "old_of_new entry out of range"};
+    if (o < 0) continue;
+    if (o <= last) throw RsError{RS_ERR_ARG, "kept nodes must keep their relative order"};
+    last = o;
+    if (xy[2 * j] != c->x[o] || xy[2 * j + 1] != c->y[o] || normal[2 * j] != c->nx[o] ||
+        normal[2 * j + 1] != c->ny[o] || weight[j] != c->w[o] || curvature[j] != c->kap[o])
+      throw RsError{RS_ERR_ARG, "kept node " + std::to_string(j) + " changed its data"};
+    new_of_old[o] = j;
+  }
+  for (int i = 0; i < n_nodes; ++i)
+    if (!inside_root(c, xy[2 * i], xy[2 * i + 1]))
+      throw RsError{RS_ERR_OUT_OF_ROOT, "node " + std::to_string(i) + " lies outside the fixed root"};
+  HIP_CHECK(hipSetDevice(c->device));
+  auto node_new = [&](int o) { return new_of_old[o] >= 0 ? new_of_old[o] : -2 - o; };
+  auto dof_new = [&](int d) { return new_of_old[d >> 1] >= 0 ? 2 * new_of_old[d >> 1] + (d & 1) : -2 - d; };
+  O.boxes = std::move(c->boxes);
+  O.fac = std::move(c->fac);
+  for (size_t b = 0; b < O.boxes.size(); ++b) {
+    Box& B = O.boxes[b];
+    O.by_key[BoxKey{B.level, B.ix, B.iy}] = (int)b;
+    for (int& j : B.nodes) j = node_new(j);
+    BoxFac& F = O.fac[b];
+    bool gone = false;
+    for (int& d : F.I) {
+      d = dof_new(d);
+      gone |= d < 0;
+    }
+    for (int& d : F.fint) d = dof_new(d);
+    if (gone) F.active = false;      // its unknowns changed: recompressed
+  }
+  O.moved.assign(n_nodes, 0);
+  for (int j = 0; j < n_nodes; ++j) O.moved[j] = old_of_new[j] < 0;
+  c->N = n_nodes;
+  c->p = n_holes;
+  c->x.resize(n_nodes);
+  c->y.resize(n_nodes);
+  c->nx.resize(n_nodes);
+  c->ny.resize(n_nodes);
+  for (int i = 0; i < n_nodes; ++i) {
+    c->x[i] = xy[2 * i];
+    c->y[i] = xy[2 * i + 1];
+    c->nx[i] = normal[2 * i];
+    c->ny[i] = normal[2 * i + 1];
+  }
+  c->w.assign(weight, weight + n_nodes);
+  c->kap.assign(curvature, curvature + n_nodes);
+  c->curve.assign(curve_id, curve_id + n_nodes);
+  c->hole.assign(2 * (size_t)n_holes, 0.0);
+  for (int h = 0; h < n_holes; ++h) {
+    if (hole_xy) {
+      c->hole[2 * h] = hole_xy[2 * h];
+      c->hole[2 * h + 1] = hole_xy[2 * h + 1];
+    } else {
+      double sx = 0, sy = 0;
+      for (int i = 0; i < n_nodes; ++i)
+        if (curve_id[i] == h + 1) { sx += c->x[i]; sy += c->y[i]; }
+      c->hole[2 * h] = sx / count[h + 1];
+      c->hole[2 * h + 1] = sy / count[h + 1];
+    }
+  }
+  c->prm.has_root = 1;
+  c->prm.root[0] = c->root_cx;
+  c->prm.root[1] = c->root_cy;
+  c->prm.root[2] = c->root_side;
+  build_tree(c);
+  upload_geometry(c);
+  c->stats.n_nodes = n_nodes;
+  c->stats.n_holes = n_holes;
+  c->old = &O;
+}
+
 }  // namespace
 
 extern "C" {
@@ -2746,6 +2840,34 @@ rs_status rs_update_moved_nodes(rs_ctx* c, int n_moved, const int* idx, const do
     return RS_OK;
   } catch (const RsError& e) {
     c->factored = false;
+    return fail(c, e);
+  }
+}
+
+rs_status rs_update_geometry(rs_ctx* c, int n_nodes, const double* xy, const double* normal,
+                             const double* weight, const double* curvature, const int* curve_id, int n_holes,
+                             const double* hole_xy, const int* old_of_new) {
+  if (!c) return RS_ERR_ARG;
+  try {
+    if (!c->factored) throw RsError{RS_ERR_STATE, "rs_update_geometry before rs_factor"};
+    auto t0 = std::chrono::steady_clock::now();
+    OldState O;
+    begin_update_geometry(c, n_nodes, xy, normal, weight, curvature, curve_id, n_holes, hole_xy, old_of_new, O);
+    try {
+      do_factor(c);
+    } catch (...) {
+      c->old = nullptr;
+      throw;
+    }
+    c->old = nullptr;
+    c->stats.n_levels = c->L + 1;
+    c->stats.n_boxes = (int)c->boxes.size();
+    c->stats.ms_update = 1e3 * seconds_since(t0);
+    return RS_OK;
+  } catch (const RsError& e) {
+    // argument errors leave the context untouched; a failure past them leaves
+    // it unfactored (the old factorization has been taken apart)
+    if (e.st != RS_ERR_ARG && e.st != RS_ERR_OUT_OF_ROOT) c->factored = false;
     return fail(c, e);
   }
 }

@@ -150,6 +150,44 @@ __device__ __forceinline__ double op_entry(const Geo& g, int ti, int tc, int sj,
   return v + nt * (g.w[sj] * ns);
 }
 
+// ---- the same entries in float32 (the float32 bulk form) -------------------
+// Positions enter as box-local offsets: (x - c_B) rounded to float, with c_B
+// the compressed box's centre, so that a difference of two nearby nodes keeps
+// float32's relative precision whatever the domain's size.
+__device__ __forceinline__ float dl_entry_f(float rx, float ry, float nx, float ny, float w, int a,
+                                            int b) {
+  const float r2 = rx * rx + ry * ry;
+  const float rn = rx * nx + ry * ny;
+  const float coef = (float)kInvPi * w * rn / (r2 * r2);
+  return coef * (a ? ry : rx) * (b ? ry : rx);
+}
+
+__device__ __forceinline__ float sl_entry_f(float rx, float ry, float w, int a, int b) {
+  const float r2 = rx * rx + ry * ry;
+  float v = (a ? ry : rx) * (b ? ry : rx) / r2;
+  if (a == b) v += -0.5f * logf(r2);
+  return (float)kInv4Pi * w * v;
+}
+
+// op_entry in float32; (cx, cy) = the box centre the offsets are taken from.
+__device__ __forceinline__ float op_entry_f(const Geo& g, int ti, int tc, int sj, int sc, double lam,
+                                            double cx, double cy) {
+  float v;
+  if (ti == sj) {
+    const float tx = (float)-g.ny[ti], ty = (float)g.nx[ti];
+    const float c = -((float)g.w[ti] * (float)g.kap[ti]) / (2.0f * (float)kPi);
+    v = c * (tc ? ty : tx) * (sc ? ty : tx);
+    if (tc == sc) v += (float)lam;
+  } else {
+    const float rx = (float)(g.x[ti] - cx) - (float)(g.x[sj] - cx);
+    const float ry = (float)(g.y[ti] - cy) - (float)(g.y[sj] - cy);
+    v = dl_entry_f(rx, ry, (float)g.nx[sj], (float)g.ny[sj], (float)g.w[sj], tc, sc);
+  }
+  const float nt = (float)(tc ? g.ny[ti] : g.nx[ti]);
+  const float ns = (float)(sc ? g.ny[sj] : g.nx[sj]);
+  return v + nt * ((float)g.w[sj] * ns);
+}
+
 // ---- block-level dense helpers (row-major, global memory) ----------------
 
 // C = beta*C0 + alpha*op(A) op(B); op(A) is M x K, op(B) K x N.  C0 may be C.

@@ -6,6 +6,8 @@
 // system (eq. partition) and the float copies of the factors.
 #include "rs_device.h"
 
+#include <type_traits>
+
 namespace rs {
 namespace {
 
@@ -13,10 +15,13 @@ namespace {
 
 // Thread per row of M_B; the box's columns (source node geometry and
 // component) are staged in LDS 256 at a time, so the loop over columns reads
-// no global memory.
+// no global memory.  F32: the float32 bulk form, every entry computed in
+// float32 from box-local offsets (stored as doubles, exactly).
+template <bool F32>
 __global__ __launch_bounds__(kBlock) void k_assemble_M(const LevelBox* boxes, int n_proxy,
                                                        double ratio) {
   __shared__ double sx[kBlock], sy[kBlock], snx[kBlock], sny[kBlock], sw[kBlock];
+  __shared__ float sxf[kBlock], syf[kBlock];
   __shared__ int sj[kBlock];
   const LevelBox& B = boxes[blockIdx.x];
   const int i = blockIdx.y * blockDim.x + threadIdx.x;
@@ -73,6 +78,10 @@ __global__ __launch_bounds__(kBlock) void k_assemble_M(const LevelBox* boxes, in
       sj[threadIdx.x] = d;
       sx[threadIdx.x] = g.x[j];
       sy[threadIdx.x] = g.y[j];
+      if (F32) {
+        sxf[threadIdx.x] = (float)(g.x[j] - B.cx);
+        syf[threadIdx.x] = (float)(g.y[j] - B.cy);
+      }
       snx[threadIdx.x] = g.nx[j];
       sny[threadIdx.x] = g.ny[j];
       sw[threadIdx.x] = g.w[j];
@@ -80,6 +89,37 @@ __global__ __launch_bounds__(kBlock) void k_assemble_M(const LevelBox* boxes, in
     __syncthreads();
     if (!live) continue;
     double* col = B.M + (size_t)c0 * m + i;
+    if (F32) {
+      // row point as a box-local float offset (the proxy point's is exact)
+      const float rxf = type <= 1 ? (float)(fx - B.cx) : (float)(rp * pnx);
+      const float ryf = type <= 1 ? (float)(fy - B.cy) : (float)(rp * pny);
+      const float fnxf = (float)fnx, fnyf = (float)fny, fwf = (float)fw, wpf = (float)wp;
+      const float pnxf = (float)pnx, pnyf = (float)pny, fn_cf = (float)fn_c, wsf = (float)B.wscale;
+      for (int cc = 0; cc < cnt; ++cc) {
+        const int d = sj[cc];
+        const int j = d >> 1, jc = d & 1;
+        const float xj = sxf[cc], yj = syf[cc], nxj = (float)snx[cc], nyj = (float)sny[cc], wj = (float)sw[cc];
+        const float nj_c = jc ? nyj : nxj;
+        float v;
+        switch (type) {
+          case 0:
+            if (fj == j) v = op_entry_f(g, fj, fc, j, jc, 0.0, B.cx, B.cy);
+            else v = dl_entry_f(rxf - xj, ryf - yj, nxj, nyj, wj, fc, jc) + fn_cf * (wj * nj_c);
+            break;
+          case 1:
+            if (fj == j) v = op_entry_f(g, j, jc, fj, fc, 0.0, B.cx, B.cy);
+            else v = dl_entry_f(xj - rxf, yj - ryf, fnxf, fnyf, fwf, jc, fc) + nj_c * (fwf * fn_cf);
+            break;
+          case 2: v = dl_entry_f(rxf - xj, ryf - yj, nxj, nyj, wj, pa, jc); break;
+          case 3: v = dl_entry_f(xj - rxf, yj - ryf, pnxf, pnyf, wpf, jc, pa); break;
+          case 4: v = sl_entry_f(xj - rxf, yj - ryf, wpf, jc, pa); break;
+          case 5: v = wj * nj_c; break;
+          default: v = wsf * nj_c; break;
+        }
+        col[(size_t)cc * m] = (double)v;
+      }
+      continue;
+    }
     for (int cc = 0; cc < cnt; ++cc) {
       const int d = sj[cc];
       const int j = d >> 1, jc = d & 1;
@@ -107,7 +147,7 @@ __global__ __launch_bounds__(kBlock) void k_assemble_M(const LevelBox* boxes, in
 }
 
 __global__ __launch_bounds__(kBlock) void k_assemble_abb(const LevelBox* boxes, double lam,
-                                                         int use_perm) {
+                                                         int use_perm, int f32) {
   const LevelBox& B = boxes[blockIdx.x];
   const int n = B.n;
   const int t = blockIdx.y * blockDim.x + threadIdx.x;
@@ -124,7 +164,8 @@ __global__ __launch_bounds__(kBlock) void k_assemble_abb(const LevelBox* boxes, 
     }
   }
   const int di = B.dofs[pi], dj = B.dofs[pj];
-  B.Ap[t] = op_entry(B.geo, di >> 1, di & 1, dj >> 1, dj & 1, lam);
+  B.Ap[t] = f32 ? (double)op_entry_f(B.geo, di >> 1, di & 1, dj >> 1, dj & 1, lam, B.cx, B.cy)
+                : op_entry(B.geo, di >> 1, di & 1, dj >> 1, dj & 1, lam);
 }
 
 // ---- elimination of the redundant unknowns (G workgroups per box) -----------
@@ -141,9 +182,20 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 // holds row 4 q + l / 16, column l % 16 of the tile.  Every tile is summed
 // in the same order whatever G is.  C0 may alias C (each element is read
 // before it is written, by the same lane).
-__device__ void mfma_gemm(int g, int G, int M, int N, int K, double alpha, const double* A,
-                          int lda, bool tA, const double* B, int ldb, bool tB, double beta,
-                          const double* C0, int ldc0, double* C, int ldc) {
+//
+// F32 (the float32 bulk form): the operands are rounded to float32 on load
+// and multiplied on FP32 matrix cores (v_mfma_f32_16x16x4f32) with float32
+// accumulation; beta*C0 + alpha*product is formed in float32 and stored as a
+// double (exactly).  Same operand lanes; result lane l, register q holds row
+// 4 (l / 16) + q.
+typedef float flt4 __attribute__((ext_vector_type(4)));
+
+template <bool F32>
+__device__ void mfma_gemm_t(int g, int G, int M, int N, int K, double alpha, const double* A,
+                            int lda, bool tA, const double* B, int ldb, bool tB, double beta,
+                            const double* C0, int ldc0, double* C, int ldc) {
+  using E = typename std::conditional<F32, float, double>::type;
+  using V4 = typename std::conditional<F32, flt4, dbl4>::type;
   const int lane = threadIdx.x & 63;
   const int NW = blockDim.x >> 6, wid = threadIdx.x >> 6;
   const int tm = (M + 15) >> 4, tn = (N + 15) >> 4;
@@ -157,36 +209,50 @@ __device__ void mfma_gemm(int g, int G, int M, int N, int K, double alpha, const
     const double* pa = tA ? A + gi : A + (size_t)gi * lda;
     const double* pb = tB ? B + (size_t)gj * ldb : B + gj;
     const bool va = gi < M, vb = gj < N;
-    double an[PF], bn[PF];
+    E an[PF], bn[PF];
     auto load = [&](int q0) {
 #pragma unroll
       for (int u = 0; u < PF; ++u) {
         const int k = 4 * (q0 + u) + kq;
-        an[u] = (va && k < K) ? pa[k * sa] : 0.0;
-        bn[u] = (vb && k < K) ? pb[k * sb] : 0.0;
+        an[u] = (va && k < K) ? (E)pa[k * sa] : (E)0;
+        bn[u] = (vb && k < K) ? (E)pb[k * sb] : (E)0;
       }
     };
-    dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+    V4 acc = {0, 0, 0, 0};
     load(0);
     for (int q0 = 0; q0 < kg; q0 += PF) {
-      double ac[PF], bc[PF];
+      E ac[PF], bc[PF];
 #pragma unroll
       for (int u = 0; u < PF; ++u) { ac[u] = an[u]; bc[u] = bn[u]; }
       if (q0 + PF < kg) load(q0 + PF);
 #pragma unroll
       for (int u = 0; u < PF; ++u)
-        if (q0 + u < kg) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ac[u], bc[u], acc, 0, 0, 0);
+        if (q0 + u < kg) {
+          if constexpr (F32)
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ac[u], bc[u], acc, 0, 0, 0);
+          else
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ac[u], bc[u], acc, 0, 0, 0);
+        }
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int ri = i0 + 4 * q + kq, cj = j0 + r16;
+      const int ri = F32 ? i0 + 4 * kq + q : i0 + 4 * q + kq, cj = j0 + r16;
       if (ri < M && cj < N) {
-        double v = alpha * acc[q];
-        if (C0) v += beta * C0[(size_t)ri * ldc0 + cj];
-        C[(size_t)ri * ldc + cj] = v;
+        E v = (E)alpha * acc[q];
+        if (C0) v += (E)beta * (E)C0[(size_t)ri * ldc0 + cj];
+        C[(size_t)ri * ldc + cj] = (double)v;
       }
     }
   }
+}
+
+__device__ __forceinline__ void mfma_gemm(int g, int G, int M, int N, int K, double alpha, const double* A,
+                                          int lda, bool tA, const double* B, int ldb, bool tB, double beta,
+                                          const double* C0, int ldc0, double* C, int ldc, bool f32 = false) {
+  if (f32)
+    mfma_gemm_t<true>(g, G, M, N, K, alpha, A, lda, tA, B, ldb, tB, beta, C0, ldc0, C, ldc);
+  else
+    mfma_gemm_t<false>(g, G, M, N, K, alpha, A, lda, tA, B, ldb, tB, beta, C0, ldc0, C, ldc);
 }
 
 // In-place Gauss-Jordan sweep with partial pivoting of X (r x r) held in
@@ -591,7 +657,8 @@ __device__ bool coop_gj(int g, int G, double* W, int r, double* Xi, double* Pn, 
 // rcond_1(X_RR) < rcond_min); E, F and the Schur complement X_SS (eq. schurmat).
 __global__ __launch_bounds__(kBlock) void k_eliminate(const LevelBox* boxes, int G, int* k_io,
                                                       const int* kx_in, double rcond_min,
-                                                      int* status, double* rc_out, int* err) {
+                                                      int* status, double* rc_out, int* err, int f32,
+                                                      double f32_rcond) {
   extern __shared__ double smem_e[];
   constexpr int NW = kBlock / 64;
   __shared__ double red[NW];
@@ -608,6 +675,10 @@ __global__ __launch_bounds__(kBlock) void k_eliminate(const LevelBox* boxes, int
   const int kx = kx_in[B.slot];
   int st = 0;
   double rc_final = 1.0;          // rcond_1 of the accepted X_RR (1 when r = 0)
+  // float32 bulk form: a box whose X_RR comes out with rcond_1 below
+  // f32_rcond (which would amplify float32 rounding by its inverse) is
+  // eliminated again with float64 products
+  bool fgo = f32 != 0;
   const double* Ap = B.Ap;
   const int gt = g * kBlock + threadIdx.x, GT = G * kBlock;
   while (true) {
@@ -644,14 +715,15 @@ __global__ __launch_bounds__(kBlock) void k_eliminate(const LevelBox* boxes, int
     int* piv = reinterpret_cast<int*>(Dinv + kGJP * kGJP);
     int* rowperm = piv + kGJP;
     int* flag = rowperm + r + 1;
-    mfma_gemm(g, G, k, r, k, -1.0, Ap, n, false, T, r, false, 1.0, Ap + k, n, Xsr, r);
-    mfma_gemm(g, G, r, k, k, -1.0, T, r, true, Ap, n, false, 1.0, Ap + (size_t)k * n, n, Xrs, k);
+    const bool fg = fgo;   // the Schur-complement products in float32 (float32 bulk form)
+    mfma_gemm(g, G, k, r, k, -1.0, Ap, n, false, T, r, false, 1.0, Ap + k, n, Xsr, r, fg);
+    mfma_gemm(g, G, r, k, k, -1.0, T, r, true, Ap, n, false, 1.0, Ap + (size_t)k * n, n, Xrs, k, fg);
     mfma_gemm(g, G, r, r, k, -1.0, Ap + (size_t)k * n, n, false, T, r, false, 1.0,
-              Ap + (size_t)k * n + k, n, Xrr, r);
+              Ap + (size_t)k * n + k, n, Xrr, r, fg);
     if (g == 0 && threadIdx.x == 0) *flag = 0;
     box_barrier_full(B.bar, G, nbar, &s_dead, err);
     // X_RR -= T^T X_SR
-    mfma_gemm(g, G, r, r, k, -1.0, T, r, true, Xsr, r, false, 1.0, Xrr, r, W, r);
+    mfma_gemm(g, G, r, r, k, -1.0, T, r, true, Xsr, r, false, 1.0, Xrr, r, W, r, fg);
     box_barrier_full(B.bar, G, nbar, &s_dead, err);
     double rc = 0.0;
     // the inversion algorithm depends on r only (not on G), so a box factors
@@ -683,12 +755,17 @@ __global__ __launch_bounds__(kBlock) void k_eliminate(const LevelBox* boxes, int
       }
       st = 1;
     }
+    if (fgo && !(rc >= f32_rcond)) {
+      fgo = false;
+      box_barrier_full(B.bar, G, nbar, &s_dead, err);
+      continue;
+    }
     rc_final = rc;
     box_barrier_full(B.bar, G, nbar, &s_dead, err);
-    mfma_gemm(g, G, k, r, r, 1.0, Xsr, r, false, B.Xinv, r, false, 0.0, nullptr, 0, B.E, r);
-    mfma_gemm(g, G, r, k, r, 1.0, B.Xinv, r, false, Xrs, k, false, 0.0, nullptr, 0, B.F, k);
+    mfma_gemm(g, G, k, r, r, 1.0, Xsr, r, false, B.Xinv, r, false, 0.0, nullptr, 0, B.E, r, fg);
+    mfma_gemm(g, G, r, k, r, 1.0, B.Xinv, r, false, Xrs, k, false, 0.0, nullptr, 0, B.F, k, fg);
     box_barrier_full(B.bar, G, nbar, &s_dead, err);
-    mfma_gemm(g, G, k, k, r, -1.0, Xsr, r, false, B.F, k, false, 1.0, Ap, n, B.Xss, k);
+    mfma_gemm(g, G, k, k, r, -1.0, Xsr, r, false, B.F, k, false, 1.0, Ap, n, B.Xss, k, fg);
     break;
   }
   if (g == 0 && threadIdx.x == 0) {
@@ -1036,18 +1113,21 @@ __global__ void k_factor_to_float(const LevelBox* boxes, const int* k_final) {
 
 }  // namespace
 
-void launch_assemble_M(const LevelBox* boxes, int nbox, int max_m, int n_proxy, double ratio,
+void launch_assemble_M(const LevelBox* boxes, int nbox, int max_m, int n_proxy, double ratio, bool f32,
                        hipStream_t s) {
   if (nbox == 0 || max_m == 0) return;
   dim3 grid(nbox, blocks_for(max_m, kBlock));
-  hipLaunchKernelGGL(k_assemble_M, grid, dim3(kBlock), 0, s, boxes, n_proxy, ratio);
+  if (f32)
+    hipLaunchKernelGGL(k_assemble_M<true>, grid, dim3(kBlock), 0, s, boxes, n_proxy, ratio);
+  else
+    hipLaunchKernelGGL(k_assemble_M<false>, grid, dim3(kBlock), 0, s, boxes, n_proxy, ratio);
 }
 
-void launch_assemble_abb(const LevelBox* boxes, int nbox, int max_n, double lam, bool use_perm,
+void launch_assemble_abb(const LevelBox* boxes, int nbox, int max_n, double lam, bool use_perm, bool f32,
                          hipStream_t s) {
   if (nbox == 0 || max_n == 0) return;
   dim3 grid(nbox, blocks_for((long long)max_n * max_n, kBlock));
-  hipLaunchKernelGGL(k_assemble_abb, grid, dim3(kBlock), 0, s, boxes, lam, use_perm ? 1 : 0);
+  hipLaunchKernelGGL(k_assemble_abb, grid, dim3(kBlock), 0, s, boxes, lam, use_perm ? 1 : 0, f32 ? 1 : 0);
 }
 
 size_t eliminate_lds_bytes(int max_n) {
@@ -1067,7 +1147,8 @@ int eliminate_blocks_per_cu(int max_n) {
 
 hipError_t launch_eliminate(const LevelBox* boxes, int nbox, int G, int* k_io, const int* kx,
                             double rcond_min, int* status, double* rc_out, int* err, int max_n,
-                            hipStream_t s) {
+                            bool f32, double f32_rcond, hipStream_t s) {
+  int f32i = f32 ? 1 : 0;
   if (nbox == 0) return hipSuccess;
   hipLaunchKernelGGL(k_zero_bars, dim3(blocks_for(nbox, kBlock)), dim3(kBlock), 0, s, boxes, nbox, err, 1);
   const size_t lds = eliminate_lds_bytes(max_n);
@@ -1083,11 +1164,11 @@ hipError_t launch_eliminate(const LevelBox* boxes, int nbox, int G, int* k_io, c
   }
   if (G <= 1) {
     hipLaunchKernelGGL(k_eliminate, dim3(nbox), dim3(kBlock), lds, s, boxes, 1, k_io, kx, rcond_min,
-                       status, rc_out, err);
+                       status, rc_out, err, f32i, f32_rcond);
     return hipGetLastError();
   }
-  void* args[] = {(void*)&boxes, (void*)&G, (void*)&k_io, (void*)&kx, (void*)&rcond_min,
-                  (void*)&status, (void*)&rc_out, (void*)&err};
+  void* args[] = {(void*)&boxes, (void*)&G,      (void*)&k_io, (void*)&kx, (void*)&rcond_min,
+                  (void*)&status, (void*)&rc_out, (void*)&err,  (void*)&f32i, (void*)&f32_rcond};
   return hipLaunchCooperativeKernel((const void*)k_eliminate, dim3(nbox * G), dim3(kBlock), args,
                                     (unsigned)lds, s);
 }

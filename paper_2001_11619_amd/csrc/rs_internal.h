@@ -90,7 +90,9 @@ constexpr int kBlock = 256;
 constexpr int kNC = 16;        // right-hand-side columns per sweep block
 
 // ---- launchers (rs_qr.hip, rs_factor.hip, rs_solve.hip, rs_apply.hip) ----
-void launch_assemble_M(const LevelBox* boxes, int nbox, int max_m, int n_proxy, double ratio,
+// f32: the float32 bulk form (entries computed in float32 from box-local
+// offsets; the Schur-complement products on FP32 matrix cores)
+void launch_assemble_M(const LevelBox* boxes, int nbox, int max_m, int n_proxy, double ratio, bool f32,
                        hipStream_t s);
 // Register-resident pivoted QR: a 1024-thread workgroup holds RU rows per
 // lane (RU even, 64 RU >= m) of CPW columns per wave.
@@ -136,12 +138,12 @@ size_t cpqr_lds_bytes(int max_m, int max_n);
 int cpqr_blocks_per_cu(size_t lds);
 hipError_t launch_cpqr(const LevelBox* boxes, const int* list, int nbox, int G, double tol, int extra,
                        int* k_out, int* kx_out, int* err, int max_m, int max_n, hipStream_t s);
-void launch_assemble_abb(const LevelBox* boxes, int nbox, int max_n, double lam, bool use_perm,
+void launch_assemble_abb(const LevelBox* boxes, int nbox, int max_n, double lam, bool use_perm, bool f32,
                          hipStream_t s);
 int eliminate_blocks_per_cu(int max_n);
 hipError_t launch_eliminate(const LevelBox* boxes, int nbox, int G, int* k_io, const int* kx,
                             double rcond_min, int* status, double* rc_out, int* err, int max_n,
-                            hipStream_t s);
+                            bool f32, double f32_rcond, hipStream_t s);
 void launch_gj_blocked(double* A, int n, double* Ainv, double* work, int* iwork, int* status,
                        hipStream_t s);
 template <typename T>

@@ -1,0 +1,134 @@
+"""GPU parity at the benchmark configurations' full sizes, element by element.
+
+* 131072 nodes, 64 holes (262336 unknowns), against the oracle reference
+  written by tests/golden/make_reference_c3.py (oracle calls only): the
+  float64 direct solve at ID tolerance 1e-10 against the oracle's RS with the
+  same pivot rule (1e-10 of the largest entry, densities mu and border
+  unknowns (alpha, beta) separately, eq. backwardeq), and the refined float64
+  and mixed-precision solves against the discrete solution of the system
+  (1e-8).
+* The 12288-node, 8-hole workload in mixed precision and in the float32 bulk
+  form at ID tolerance 1e-6, refined, against the oracle's discrete solution.
+* One real member of the 512-geometry batch (member 0: 13568 nodes, 4 holes):
+  float64 direct against the oracle's RS, mixed refined against the oracle's
+  discrete solution.
+The discrete solution of eq. backwardeq is unique, so the refined solves are
+compared with it whatever pivots either side took.
+"""
+
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from oracle import stokes
+from oracle.rs import RSFactorization, RSParams
+from workloads import (boundary_data, exterior_forces_for_geometry, workload_batch_member,
+                       workload_circle10_8holes, workload_circle40_64holes)
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c3_reference.npz")
+
+
+def _solver(g, **kw):
+    import torch
+
+    assert torch.cuda.is_available()
+    from paper_2001_11619_amd import RSSolver
+
+    return RSSolver.from_geometry(g, **kw)
+
+
+def _elem(x, xo, n2):
+    x = x.reshape(x.shape[0], -1)
+    xo = xo.reshape(xo.shape[0], -1)
+    em = np.max(np.abs(x[:n2] - xo[:n2]).max(axis=0) / np.abs(xo[:n2]).max(axis=0))
+    eb = np.max(np.abs(x[n2:] - xo[n2:]).max(axis=0) / np.abs(xo[n2:]).max(axis=0))
+    return float(em), float(eb)
+
+
+def _discrete_solution(g, f, tol=1e-10):
+    """The oracle's solution of eq. backwardeq to a relative residual below
+    1e-13: its RS as the inner solver of float64 refinement with the exact
+    operator."""
+    rs = RSFactorization(g, RSParams(tol=tol)).factor()
+    rhs = np.vstack([f, np.zeros((3 * g.n_holes, f.shape[1]))])
+    x = rs.solve(f)
+    for _ in range(6):
+        r = rhs - stokes.apply_system(g, x)
+        if np.max(np.linalg.norm(r, axis=0) / np.linalg.norm(f, axis=0)) <= 1e-13:
+            break
+        x = x + rs.solve(r)
+    return x
+
+
+@pytest.fixture(scope="module")
+def c3():
+    if not os.path.exists(GOLDEN):
+        pytest.fail("missing %s (python tests/golden/make_reference_c3.py writes it)" % GOLDEN)
+    ref = dict(np.load(GOLDEN))
+    return workload_circle40_64holes(), ref
+
+
+def test_c3_float64_direct_matches_oracle(c3):
+    g, ref = c3
+    f = ref["f"]
+    s = _solver(g, tol=1e-10).factor()
+    x = s.solve(f)
+    em, eb = _elem(x, ref["x_direct_key20"], g.n_dofs)
+    print("c3 float64 direct vs oracle: mu %.2e border %.2e" % (em, eb), flush=True)
+    assert em < 1e-10 and eb < 1e-10, (em, eb)
+    bx = s.boxes()
+    ids = ref["box_key20"]
+    assert np.array_equal(bx["n"][ids], ref["n_key20"])
+    same = int(np.sum(bx["k"][ids] == ref["k_key20"]))
+    print("c3 ranks equal in %d of %d boxes" % (same, ids.size), flush=True)
+    assert same >= ids.size - 2
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 1e-7), (2, 1e-6)])
+def test_c3_refined_matches_discrete_solution(c3, precision, tol):
+    g, ref = c3
+    f = ref["f"]
+    s = _solver(g, tol=tol, precision=precision, refine_max=20, refine_tol=1e-10).factor()
+    x, res = s.solve(f, residual=True)
+    em, eb = _elem(x, ref["x_ref"], g.n_dofs)
+    print("c3 precision %d refined: residual %.2e, mu %.2e border %.2e, %d iterations"
+          % (precision, float(res.max()), em, eb, s.stats()["refine_iters"]), flush=True)
+    assert np.all(res <= 1e-10)
+    assert em < 1e-8 and eb < 1e-8, (em, eb)
+
+
+@pytest.mark.parametrize("precision", [1, 2])
+def test_c2_mixed_at_bench_tolerance(precision):
+    g = workload_circle10_8holes()
+    f = boundary_data(g, exterior_forces_for_geometry(g, 4, seed=2))
+    xref = _discrete_solution(g, f)
+    s = _solver(g, tol=1e-6, precision=precision, refine_max=20, refine_tol=1e-8).factor()
+    x, res = s.solve(f, residual=True)
+    assert np.all(res <= 1e-8)
+    em, eb = _elem(x, xref, g.n_dofs)
+    print("c2 mixed 1e-6 refined to 1e-8: mu %.2e border %.2e" % (em, eb), flush=True)
+    assert em < 1e-7 and eb < 1e-7, (em, eb)
+    s2 = _solver(g, tol=1e-6, precision=precision, refine_max=20, refine_tol=1e-10).factor()
+    x2, res2 = s2.solve(f, residual=True)
+    assert np.all(res2 <= 1e-10)
+    em, eb = _elem(x2, xref, g.n_dofs)
+    assert em < 1e-8 and eb < 1e-8, (em, eb)
+
+
+def test_batch_member_against_oracle():
+    g = workload_batch_member(0)
+    f = boundary_data(g, exterior_forces_for_geometry(g, 4, seed=100))
+    orc = RSFactorization(g, RSParams(tol=1e-10, pivot="key20")).factor()
+    s = _solver(g, tol=1e-10).factor()
+    em, eb = _elem(s.solve(f), orc.solve(f), g.n_dofs)
+    print("batch member 0 float64 direct vs oracle: mu %.2e border %.2e" % (em, eb), flush=True)
+    assert em < 1e-10 and eb < 1e-10, (em, eb)
+    xref = _discrete_solution(g, f)
+    m = _solver(g, tol=1e-7, precision=1, refine_max=20, refine_tol=1e-10).factor()
+    x, res = m.solve(f, residual=True)
+    assert np.all(res <= 1e-10)
+    em, eb = _elem(x, xref, g.n_dofs)
+    assert em < 1e-8 and eb < 1e-8, (em, eb)

@@ -31,7 +31,7 @@ def _rel(a, b):
     return np.linalg.norm(a - b, axis=0) / np.linalg.norm(b, axis=0)
 
 
-@pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 1e-7), (1, 1e-5)])
+@pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 1e-7), (1, 1e-5), (2, 1e-6), (2, 1e-5)])
 def test_refined_matches_dense_small(precision, tol):
     g = workload_small(seed=11, n_outer=256, n_holes=2, nodes_per_hole=128, radius=3.0)
     f = boundary_data(g, exterior_forces_for_geometry(g, 3, seed=5))
@@ -179,3 +179,21 @@ def test_graph_recaptured_after_buffers_grow():
     f7 = boundary_data(g, exterior_forces_for_geometry(g, 7, seed=4))
     sg2.solve(f7)
     assert np.array_equal(sg2.solve(f), xe)
+
+
+def test_float32_bulk_is_float32():
+    """The float32 bulk form (precision 2) really computes its entries and
+    Schur complements in float32: its direct solution differs from the
+    float64-factorization form's at float32 level (same tolerance, same
+    tree), while both refine to the dense solution."""
+    g = workload_small(seed=11, n_outer=256, n_holes=2, nodes_per_hole=128, radius=3.0)
+    f = boundary_data(g, exterior_forces_for_geometry(g, 2, seed=5))
+    xd = stokes.dense_solve(g, f)
+    x = {}
+    for prec in (1, 2):
+        s = _solver(g, leaf_size=32, tol=1e-6, precision=prec).factor()
+        x[prec] = s.solve(f)
+    d = np.abs(x[2] - x[1]).max() / np.abs(x[1]).max()
+    assert 1e-9 < d < 1e-3, d
+    for prec in (1, 2):
+        assert np.abs(x[prec] - xd).max() / np.abs(xd).max() < 1e-3

@@ -22,6 +22,8 @@ from .geometry import (  # noqa: F401
     workload_circle40_64holes,
     workload_batch_member,
     move_hole,
+    insert_hole,
+    delete_hole,
 )
 from .rhs import (  # noqa: F401
     PointForce,

@@ -236,3 +236,42 @@ def move_hole(geom: Geometry, hole: int, rng: np.random.Generator,
     new = build_geometry(curves, root=geom.root)
     start = sum(c.n for c in curves[:ci])
     return new, np.arange(start, start + old.n, dtype=np.int64)
+
+
+def insert_hole(geom: Geometry, rng: np.random.Generator, n: int, radius: Optional[float] = None,
+                wall_gap: float = 0.5, hole_gap: float = 0.25):
+    """Add one random ellipse of n nodes (semi-axes U[0.3, 0.8], angle U[0, pi),
+    centre by rejection against the wall and the other holes), appended after
+    the existing curves.  Returns (new_geometry, old_of_new): old_of_new[j] is
+    the old index of new node j, -1 for the new hole's nodes.  The root square
+    is kept."""
+    curves = list(geom.curves)
+    R = curves[0].a if radius is None else radius
+    others = [c for c in curves if c.hole]
+    new_curve = None
+    while new_curve is None:
+        a, b = rng.uniform(0.3, 0.8), rng.uniform(0.3, 0.8)
+        th = rng.uniform(0.0, np.pi)
+        e = max(a, b)
+        for _ in range(2000):
+            c = rng.uniform(-R, R, size=2)
+            if np.hypot(c[0], c[1]) + e > R - wall_gap:
+                continue
+            if all(np.hypot(c[0] - o.cx, c[1] - o.cy) >= e + o.extent + hole_gap for o in others):
+                new_curve = Curve(int(n), a, b, th, float(c[0]), float(c[1]), True)
+                break
+    new = build_geometry(curves + [new_curve], root=geom.root)
+    old_of_new = np.concatenate([np.arange(geom.n_nodes), np.full(n, -1)]).astype(np.int64)
+    return new, old_of_new
+
+
+def delete_hole(geom: Geometry, hole: int):
+    """Remove hole `hole` (1-based).  The later curves' nodes move down in the
+    numbering, keeping their order.  Returns (new_geometry, old_of_new)."""
+    curves = list(geom.curves)
+    ci = [i for i, c in enumerate(curves) if c.hole][hole - 1]
+    start = sum(c.n for c in curves[:ci])
+    cut = curves[ci].n
+    new = build_geometry(curves[:ci] + curves[ci + 1:], root=geom.root)
+    old_of_new = np.concatenate([np.arange(start), np.arange(start + cut, geom.n_nodes)]).astype(np.int64)
+    return new, old_of_new
