@@ -488,7 +488,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="circle40_64holes", choices=sorted(WORKLOADS) + ["batch", "evolve", "holes"])
     ap.add_argument("--tol-plain", type=float, default=1e-10)
     ap.add_argument("--tol-mixed", type=float, default=None,
@@ -587,7 +587,7 @@ def main():
     if args.batch_size > 0:
         print("bench: batch of %d geometries" % args.batch_size, file=sys.stderr, flush=True)
         bargs = argparse.Namespace(**vars(args))
-        bargs.steps, bargs.warmup, bargs.tol_mixed = args.batch_steps, 1, args.batch_tol_mixed
+        bargs.steps, bargs.warmup, bargs.tol_mixed = args.batch_steps, 3, args.batch_tol_mixed
         b = run_batch(bargs, forms)
         out["batch"] = {k: b[k] for k in ("value", "unit", "ms_per_step", "steps", "config", "max_rel_residual")}
         for fm in forms[1:]:

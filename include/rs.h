@@ -216,8 +216,18 @@ typedef struct {
   int boxes_recomputed;       /* boxes recompressed by the last update             */
   int apply_config;           /* operator-apply kernel shape in use (autotuner)    */
   double apply_ms;            /* its measured time per apply (0 if not tuned)      */
+  int shape_trials;           /* launches of the last factorization that timed a
+                                 candidate workgroup count per box (cooperative QR or
+                                 elimination); the count never changes a result    */
 } rs_stats;
 rs_status rs_get_stats(const rs_ctx* ctx, rs_stats* out);
+
+/* Forget every launch shape the process has tuned: the operator-apply kernel
+ * shape per (N, columns) and the workgroups per box of the cooperative QR and
+ * elimination per level signature.  Later calls tune again from scratch (the
+ * shapes never change a result, only the speed).  Must not run while another
+ * thread factors, solves or applies with any context. */
+void rs_reset_tuning(void);
 
 /* Per-box structure of the factorization, boxes in breadth-first order
  * (root first).  For each box: level, active unknown count n and rank k

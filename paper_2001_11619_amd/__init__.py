@@ -6,4 +6,4 @@ load the library; the first `RSSolver` does, and raises if it was not built.
 """
 
 from .binding import (RSSolver, RSError, library_path, load_library, exported_symbols,  # noqa: F401
-                      factor_batch, solve_batch, update_moved_nodes_batch, close_all)
+                      factor_batch, solve_batch, update_moved_nodes_batch, close_all, reset_tuning)

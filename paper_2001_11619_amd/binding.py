@@ -55,7 +55,7 @@ class Stats(ctypes.Structure):
         ("ms_factor", ctypes.c_double), ("ms_solve", ctypes.c_double),
         ("refine_iters", ctypes.c_int), ("ms_update", ctypes.c_double),
         ("boxes_recomputed", ctypes.c_int), ("apply_config", ctypes.c_int),
-        ("apply_ms", ctypes.c_double),
+        ("apply_ms", ctypes.c_double), ("shape_trials", ctypes.c_int),
     ]
 
 
@@ -117,6 +117,8 @@ def load_library():
     lib.rs_get_kernel_times.argtypes = [h, ctypes.c_int, P(KernelTime), ip, ctypes.c_int]
     lib.rs_destroy.argtypes = [h]
     lib.rs_destroy.restype = None
+    lib.rs_reset_tuning.argtypes = []
+    lib.rs_reset_tuning.restype = None
     lib.rs_last_error.argtypes = [h]
     lib.rs_last_error.restype = ctypes.c_char_p
     for name in ("rs_build_tree", "rs_factor", "rs_solve", "rs_solve_dev", "rs_update_moved_nodes",
@@ -139,7 +141,8 @@ def exported_symbols():
                  "rs_update_moved_nodes", "rs_update_geometry", "rs_set_stream", "rs_get_stats", "rs_get_boxes",
                  "rs_get_skeleton", "rs_apply", "rs_apply_inverse", "rs_dense_inverse", "rs_evaluate",
                  "rs_set_kernel_timing", "rs_get_kernel_times", "rs_factor_batch", "rs_solve_batch",
-                 "rs_update_moved_nodes_batch", "rs_destroy", "rs_last_error"):
+                 "rs_update_moved_nodes_batch", "rs_apply_dev_noalloc", "rs_reset_tuning", "rs_destroy",
+                 "rs_last_error"):
         if hasattr(lib, name):
             out.append(name)
     return out
@@ -157,6 +160,11 @@ def default_params() -> Params:
     p = Params()
     load_library().rs_default_params(ctypes.byref(p))
     return p
+
+
+def reset_tuning():
+    """Forget every tuned launch shape in the process (rs_reset_tuning)."""
+    load_library().rs_reset_tuning()
 
 
 def factor_batch(solvers):

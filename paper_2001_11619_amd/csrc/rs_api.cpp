@@ -266,6 +266,7 @@ struct rs_ctx {
   hipStream_t side_stream = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hipEvent_t ev_pre = nullptr;    // the next level's assembly and row reduction are done (second stream)
+  hipEvent_t ev_tune[4] = {};     // launch-shape trials: memory-route QR, elimination (start, end)
   PinHost h_flag;
 
   // kernel timing (HIP events around launches)
@@ -286,6 +287,8 @@ struct rs_ctx {
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
     if (ev_pre) (void)hipEventDestroy(ev_pre);
+    for (hipEvent_t e : ev_tune)
+      if (e) (void)hipEventDestroy(e);
     if (side_stream) (void)hipStreamDestroy(side_stream);
     for (auto& p : pending) {
       (void)hipEventDestroy(p.a);
@@ -1005,6 +1008,65 @@ void join_side(rs_ctx* c) {
   HIP_CHECK(hipStreamWaitEvent(c->stream, c->ev_join, 0));
 }
 
+// Autotuner of the cooperative launch shapes (a11): the workgroups per box of
+// the memory-resident pivoted QR (G) and of the elimination (Ge).  Neither
+// changes any result (every reduction is done by one fixed workgroup in a fixed
+// order), so the choice only affects speed.  For a launch signature (kernel,
+// boxes, largest n and m rounded up) the candidates are the heuristic value,
+// half and double it (within the co-resident capacity); successive
+// factorizations in the process try them in turn, each timed with events
+// around its launch, and every later launch of that signature takes the
+// fastest.
+struct ShapeTune {
+  std::vector<int> cand;
+  std::vector<double> ms;     // < 0: not tried yet
+  int best = -1;
+  int next() const {
+    for (size_t i = 0; i < ms.size(); ++i)
+      if (ms[i] < 0) return (int)i;
+    return -1;
+  }
+};
+struct ShapeTuneCache {
+  std::mutex mu;
+  std::map<std::tuple<int, int, int, int>, ShapeTune> t;
+};
+ShapeTuneCache& shape_tune_cache() {
+  static ShapeTuneCache cache;
+  return cache;
+}
+
+// The value to launch with for a signature (and, when it is a trial, the
+// entry and candidate index to report the time to).
+int tuned_shape(int kind, int nbox, int n, int m, int g0, int cap, ShapeTune** entry, int* idx) {
+  *entry = nullptr;
+  *idx = -1;
+  if (g0 < 2) return g0;
+  ShapeTuneCache& tc = shape_tune_cache();
+  std::lock_guard<std::mutex> lk(tc.mu);
+  ShapeTune& e = tc.t[std::make_tuple(kind, nbox, (n + 31) / 32, (m + 255) / 256)];
+  if (e.cand.empty()) {
+    for (int g : {g0, g0 / 2, 2 * g0}) {
+      g = std::min(std::max(g, 2), cap);
+      if (std::find(e.cand.begin(), e.cand.end(), g) == e.cand.end()) e.cand.push_back(g);
+    }
+    e.ms.assign(e.cand.size(), -1.0);
+  }
+  const int i = e.next();
+  if (i < 0) return e.cand[e.best];
+  *entry = &e;
+  *idx = i;
+  return e.cand[i];
+}
+
+void report_shape(ShapeTune* e, int idx, double ms) {
+  if (!e || idx < 0) return;
+  ShapeTuneCache& tc = shape_tune_cache();
+  std::lock_guard<std::mutex> lk(tc.mu);
+  e->ms[idx] = ms;
+  if (e->best < 0 || ms < e->ms[e->best]) e->best = idx;
+}
+
 struct LevelPlan {
   std::vector<LevelBox> all;
   int nb = 0, max_m = 0, max_n = 0;
@@ -1014,6 +1076,11 @@ struct LevelPlan {
   std::vector<int> fb;
   std::vector<std::pair<int, int>> coop;   // (first work item, count) of each cooperative launch
   int fb_m = 0, fb_n = 0, G = 1, Ge = 1;
+  // launch-shape autotuner: the cache entries (null: not tuned) whose
+  // candidate this launch tries, and that candidate's index
+  struct ShapeTune* tq = nullptr;
+  struct ShapeTune* te = nullptr;
+  int tq_i = -1, te_i = -1;
   size_t rq_lds = 0;
   DevBuf* in = nullptr;                    // the launch's input buffer (one per level parity)
   std::vector<char> image;                 // its host image
@@ -1168,11 +1235,13 @@ void plan_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps, LevelPl
     const int capq = cpqr_blocks_per_cu(qr_lds) * c->n_cu;
     if (capq > 0) G = std::min({capq / nfb, std::max(1, fb_n / 16), kMaxCoop});
     if (G < 2) G = 1;
+    else G = tuned_shape(0, nfb, fb_n, fb_m, G, std::min(capq / nfb, kMaxCoop), &P.tq, &P.tq_i);
   }
   if (nb <= c->n_cu / 4) {
     const int cape = eliminate_blocks_per_cu(max_n) * c->n_cu;
     if (cape > 0) Ge = std::min({cape / nb, std::max(1, max_n / 8), kMaxCoop});
     if (Ge < 2) Ge = 1;
+    else Ge = tuned_shape(1, nb, max_n, max_m, Ge, std::min(cape / nb, kMaxCoop), &P.te, &P.te_i);
   }
   plan_timer.reset();
   P.all = std::move(all);
@@ -1270,6 +1339,8 @@ void launch_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps, Level
   rs_ctx* c = cs[0];
   const rs_params& prm = c->prm;
   hipStream_t s = c->stream;
+  if (!c->ev_tune[0])
+    for (hipEvent_t& e : c->ev_tune) HIP_CHECK(hipEventCreate(&e));
   LevelPlan own;
   if (!pre) {
     plan_level(cs, preps, own);
@@ -1327,8 +1398,10 @@ void launch_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps, Level
       }
       {
         KTimer kt2_(c, "cpqr.mem", true, s2);
+        if (P.tq) HIP_CHECK(hipEventRecord(c->ev_tune[0], s2));
         check(launch_cpqr(dlb, P.dfb, nfb, G, prm.tol, kGuardExtra, d_k,
                           c->ws_kx.as<int>(), d_err, fb_m, fb_n, s2), "memory", nfb * G);
+        if (P.tq) HIP_CHECK(hipEventRecord(c->ev_tune[1], s2));
       }
     }
     {
@@ -1364,9 +1437,11 @@ void launch_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps, Level
   HIP_CHECK(hipEventRecord(c->ev_qr, s));
   {
     KTimer kt_(c, "eliminate");
+    if (P.te) HIP_CHECK(hipEventRecord(c->ev_tune[2], s));
     HIP_CHECK(launch_eliminate(dlb, nb, Ge, d_k, c->ws_kx.as<int>(), prm.rcond_min,
                                d_status, d_rc, d_err + 1,
                                max_n, prm.precision == 2, prm.mixed_rcond_min, s));
+    if (P.te) HIP_CHECK(hipEventRecord(c->ev_tune[3], s));
     if (prm.precision >= 1) launch_factor_to_float(dlb, nb, d_k, s);
   }
   HIP_CHECK(hipGetLastError());
@@ -1394,6 +1469,16 @@ void launch_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps, Level
   for (size_t i = 0; i < cs.size(); ++i)
     if (hperm[i]) preps[i].perm.assign(hperm[i], hperm[i] + preps[i].doff.back() + preps[i].lb.back().n);
   resolve_timers(c);
+  // launch-shape trials (both streams are complete here)
+  for (int t = 0; t < 2; ++t) {
+    ShapeTune* e = t == 0 ? P.tq : P.te;
+    if (!e) continue;
+    ++c->stats.shape_trials;
+    float ms = 0.f;
+    HIP_CHECK(hipEventSynchronize(c->ev_tune[2 * t + 1]));
+    HIP_CHECK(hipEventElapsedTime(&ms, c->ev_tune[2 * t], c->ev_tune[2 * t + 1]));
+    report_shape(e, t == 0 ? P.tq_i : P.te_i, ms);
+  }
   if (qr_err[2]) throw RsError{RS_ERR_ARG, "non-finite entries in an ID matrix (coincident nodes?)"};
   if (qr_err[0] || qr_err[1]) throw RsError{RS_ERR_DEVICE, "box barrier timed out"};
   for (size_t i = 0; i < cs.size(); ++i) {
@@ -1674,6 +1759,7 @@ void do_factor_multi(std::vector<rs_ctx*>& cs) {
     c->fac.assign(c->boxes.size(), BoxFac());
     c->recomputed.assign(c->boxes.size(), 1);
     c->stats.guard_bumps = 0;
+    c->stats.shape_trials = 0;
     c->stats.flops_id = 0;
     c->stats.flops_elim = 0;
     c->stats.max_box_unknowns = 0;
@@ -2936,6 +3022,17 @@ rs_status rs_get_stats(const rs_ctx* c, rs_stats* out) {
   if (!c || !out) return RS_ERR_ARG;
   *out = c->stats;
   return RS_OK;
+}
+
+void rs_reset_tuning(void) {
+  {
+    ShapeTuneCache& tc = shape_tune_cache();
+    std::lock_guard<std::mutex> lk(tc.mu);
+    tc.t.clear();
+  }
+  ApplyTuneCache& ta = apply_tune_cache();
+  std::lock_guard<std::mutex> lk(ta.mu);
+  ta.best.clear();
 }
 
 rs_status rs_get_boxes(const rs_ctx* c, int cap, int* n_boxes, int* level, int* n_active, int* rank,

@@ -19,18 +19,49 @@ namespace {
 // the chunks in a fixed order (deterministic).
 //
 // A thread holds T targets and NC right-hand-side columns in registers; every
-// source staged in LDS (position, w n, its NC column values) serves the T
+// source staged in LDS (position, w n / pi, its NC column values) serves the T
 // targets, so LDS traffic per pair falls as 1 / T.  (NC, T) is chosen per
 // problem shape by the host's autotuner.
 constexpr int kApplyThreads = 256;   // threads per block = sources per LDS tile
 
-// 1 / d for d > 0 from the hardware reciprocal and one Newton step (relative
-// error about one ulp); 0 for d == 0 (coincident nodes).
-__device__ __forceinline__ double inv_pos(double d) {
+// 1 / d from the hardware reciprocal and one Newton step (relative error
+// about one ulp).
+__device__ __forceinline__ double recip(double d) {
   const double y0 = __builtin_amdgcn_rcp(d);
   const double e = fma(-d, y0, 1.0);
-  const double y1 = fma(y0, e, y0);
-  return d > 0.0 ? y1 : 0.0;
+  return fma(y0, e, y0);
+}
+
+// A floor added to |r|^4 so that a coincident pair (a target's own node,
+// r = 0) needs no branch: its |r|^4 + floor has a finite reciprocal and its
+// r . n is zero, so it contributes exactly zero.  For every other pair |r|^4
+// exceeds the floor by more than 2^53 and the sum rounds to |r|^4 itself.
+constexpr double kR4Floor = 1e-300;
+
+// Packed source weights: w n / pi (the double layer's prefactor folded in).
+__device__ __forceinline__ double2 source_wn(double w, double nx, double ny) {
+  const double wp = w * kInvPi;
+  return make_double2(wp * nx, wp * ny);
+}
+
+// Add one source's double-layer block to NC columns of a target at (xi, yi):
+// the 2 x 2 block c r r^T, c = (r . w n / pi) / |r|^4, r = target - source,
+// formed once and applied to every column as two chains of two FMAs (32
+// independent accumulators keep the FP64 pipeline full).
+template <int NC>
+__device__ __forceinline__ void pair_add(double xi, double yi, double px, double py, double wnx, double wny,
+                                         const double* mv, double* ax, double* ay) {
+  const double rx = xi - px, ry = yi - py;
+  const double r2 = fma(rx, rx, ry * ry);
+  const double rn = fma(rx, wnx, ry * wny);
+  const double c = rn * recip(fma(r2, r2, kR4Floor));
+  const double crx = c * rx;
+  const double bxx = crx * rx, bxy = crx * ry, byy = c * ry * ry;
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+    ax[q] = fma(bxx, mv[2 * q], fma(bxy, mv[2 * q + 1], ax[q]));
+    ay[q] = fma(bxy, mv[2 * q], fma(byy, mv[2 * q + 1], ay[q]));
+  }
 }
 
 // True when refinement has converged or used up its iterations (the
@@ -73,7 +104,7 @@ __global__ __launch_bounds__(kApplyThreads) void k_apply_pairs(Geo g, const doub
     if (j < js1) {
       const double w = g.w[j];
       sxy[tid] = make_double2(g.x[j], g.y[j]);
-      swn[tid] = make_double2(w * g.nx[j], w * g.ny[j]);
+      swn[tid] = source_wn(w, g.nx[j], g.ny[j]);
 #pragma unroll
       for (int q = 0; q < NC; ++q) {
         sm[tid * 2 * NC + 2 * q] = q < nq ? x[(size_t)(2 * j) * ncols + q0 + q] : 0.0;
@@ -89,19 +120,7 @@ __global__ __launch_bounds__(kApplyThreads) void k_apply_pairs(Geo g, const doub
 #pragma unroll
       for (int t = 0; t < 2 * NC; ++t) mv[t] = sm[jj * 2 * NC + t];
 #pragma unroll
-      for (int u = 0; u < T; ++u) {
-        const double rx = xi[u] - p.x, ry = yi[u] - p.y;
-        const double r2 = fma(rx, rx, ry * ry);
-        const double rn = fma(rx, wn.x, ry * wn.y);
-        const double c = kInvPi * rn * inv_pos(r2 * r2);
-        const double crx = c * rx;
-        const double bxx = crx * rx, bxy = crx * ry, byy = c * ry * ry;
-#pragma unroll
-        for (int q = 0; q < NC; ++q) {
-          ax[u][q] = fma(bxx, mv[2 * q], fma(bxy, mv[2 * q + 1], ax[u][q]));
-          ay[u][q] = fma(bxy, mv[2 * q], fma(byy, mv[2 * q + 1], ay[u][q]));
-        }
-      }
+      for (int u = 0; u < T; ++u) pair_add<NC>(xi[u], yi[u], p.x, p.y, wn.x, wn.y, mv, ax[u], ay[u]);
     }
   }
   double* out = part + (size_t)blockIdx.y * 2 * nt * ncols;
@@ -120,7 +139,7 @@ __global__ __launch_bounds__(kApplyThreads) void k_apply_pairs(Geo g, const doub
 }
 
 // The same pair sums with the sources read by uniform (scalar) loads instead
-// of LDS: src4 packs (x, y, w n_x, w n_y) per node; each wave walks the sources
+// of LDS: src4 packs (x, y, w n_x / pi, w n_y / pi) per node; each wave walks the sources
 // of its chunk in order, every lane holding T targets.  Same arithmetic and
 // order per target as k_apply_pairs (bitwise the same result).
 template <int NC, int T>
@@ -166,19 +185,7 @@ __global__ __launch_bounds__(kApplyThreads) void k_apply_pairs_s(const double4* 
         }
       }
 #pragma unroll
-      for (int u = 0; u < T; ++u) {
-        const double rx = xi[u] - sp.x, ry = yi[u] - sp.y;
-        const double r2 = fma(rx, rx, ry * ry);
-        const double rn = fma(rx, sp.z, ry * sp.w);
-        const double c = kInvPi * rn * inv_pos(r2 * r2);
-        const double crx = c * rx;
-        const double bxx = crx * rx, bxy = crx * ry, byy = c * ry * ry;
-#pragma unroll
-        for (int q = 0; q < NC; ++q) {
-          ax[u][q] = fma(bxx, mv[2 * q], fma(bxy, mv[2 * q + 1], ax[u][q]));
-          ay[u][q] = fma(bxy, mv[2 * q], fma(byy, mv[2 * q + 1], ay[u][q]));
-        }
-      }
+      for (int u = 0; u < T; ++u) pair_add<NC>(xi[u], yi[u], sp.x, sp.y, sp.z, sp.w, mv, ax[u], ay[u]);
     }
   };
   if (nq == NC) sweep(std::true_type{});
@@ -198,12 +205,12 @@ __global__ __launch_bounds__(kApplyThreads) void k_apply_pairs_s(const double4* 
   }
 }
 
-// src4[j] = (x_j, y_j, w_j n_xj, w_j n_yj)
+// src4[j] = (x_j, y_j, w_j n_xj / pi, w_j n_yj / pi)
 __global__ void k_pack_sources(Geo g, double4* src4) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= g.N) return;
-  const double w = g.w[j];
-  src4[j] = make_double4(g.x[j], g.y[j], w * g.nx[j], w * g.ny[j]);
+  const double2 wn = source_wn(g.w[j], g.nx[j], g.ny[j]);
+  src4[j] = make_double4(g.x[j], g.y[j], wn.x, wn.y);
 }
 
 // Threads per block of the two node reductions below (k_apply_nsum,

@@ -1185,9 +1185,14 @@ void launch_gj_blocked(double* A, int n, double* Ainv, double* work, int* iwork,
   int* piv = iwork + n;
   hipLaunchKernelGGL(k_iota, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, rowperm, n, status);
   const long long nn = (long long)n * n;
-  for (int k0 = 0; k0 < n; k0 += kGJB) {
-    const int bb = std::min(kGJB, n - k0);
-    const size_t pbytes = (size_t)(n - k0) * (bb + 1) * sizeof(double);
+  for (int k0 = 0; k0 < n;) {
+    // a panel is worked on in LDS: one taller than the LDS budget at kGJB
+    // columns is narrowed until it fits (down to 8 columns; taller panels
+    // stay in global memory); the blocking depends on n only
+    const int h = n - k0;
+    int bb = std::min(kGJB, h);
+    while (bb > 8 && (size_t)h * (bb + 1) * sizeof(double) > kPanelLdsBytes) --bb;
+    const size_t pbytes = (size_t)h * (bb + 1) * sizeof(double);
     const int in_lds = pbytes <= kPanelLdsBytes ? 1 : 0;
     hipLaunchKernelGGL(k_gjb_panel, dim3(1), dim3(kBlock), in_lds ? pbytes : 0, s, A, n, k0, bb, W, piv,
                        Dinv, status, in_lds);
@@ -1199,6 +1204,7 @@ void launch_gj_blocked(double* A, int n, double* Ainv, double* work, int* iwork,
                        A, n, k0, bb, Dinv, R, status);
     hipLaunchKernelGGL(k_gjb_update, dim3(blocks_for(nn, kBlock)), dim3(kBlock), 0, s, A, n, k0, bb,
                        Dinv, R, Cp, status);
+    k0 += bb;
   }
   hipLaunchKernelGGL(k_gjb_unpermute, dim3(blocks_for(nn, kBlock)), dim3(kBlock), 0, s, A, n,
                      rowperm, Ainv);

@@ -132,3 +132,25 @@ def test_batch_member_against_oracle():
     assert np.all(res <= 1e-10)
     em, eb = _elem(x, xref, g.n_dofs)
     assert em < 1e-8 and eb < 1e-8, (em, eb)
+
+
+def test_c3_launch_shape_trials_leave_results_bitwise(c3):
+    """The workgroups per box of the cooperative QR and elimination are tuned
+    online across factorizations; every candidate gives bitwise the same
+    factorization, so the solves of successive factorizations are equal while
+    the trials run and after they end."""
+    from paper_2001_11619_amd import reset_tuning
+
+    g, ref = c3
+    f = np.ascontiguousarray(ref["f"][:, :2])
+    reset_tuning()
+    s = _solver(g, tol=1e-10)
+    xs, trials = [], []
+    for _ in range(5):
+        s.factor()
+        xs.append(s.solve(f))
+        trials.append(s.stats()["shape_trials"])
+    print("c3 launch-shape trials per factorization:", trials, flush=True)
+    assert trials[0] > 0 and trials[-1] == 0, trials
+    for x in xs[1:]:
+        assert np.array_equal(x, xs[0])
