@@ -36,6 +36,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6     # MI355X published FP64 vector / matrix peak
+FP32_MFMA_PEAK_TFLOPS = 157.3    # MI355X published dense FP32 matrix peak
 BREAKDOWN_STEPS = 2                # untimed steps after the timed region, every kernel family timed
 HBM_PEAK_GBS = 8000.0
 
@@ -405,6 +406,8 @@ TRAFFIC = {
     "cpqr": (os.path.join(ROOT, "profiles", "hbm_traffic_cpqr_circle10_8holes.md"), ("rs_qr.hip", "rs_device.h")),
     "apply_operator": (os.path.join(ROOT, "profiles", "hbm_traffic_apply_circle40_64holes.md"),
                        ("rs_apply.hip", "rs_device.h")),
+    "apply_correction": (os.path.join(ROOT, "profiles", "hbm_traffic_apply_correction_circle40_64holes.md"),
+                         ("rs_apply.hip", "rs_device.h")),
 }
 
 
@@ -475,13 +478,26 @@ def roofline_of(run, steps, nrhs, n_nodes, workload, form, tol, fam):
         per_launch_s = tot_ms / 1e3 / steps
         unit_desc = "flops per factorization (sum of the boxes' pivoted-QR + T counts)"
     achieved = work / per_launch_s / 1e12
+    corr = None
+    if fam == "apply_operator" and "apply_correction" in ktimes:
+        # the float32 image of a refinement correction: the 2 x 2 blocks times
+        # the columns on FP32 matrix cores, 8 nrhs flops per node pair
+        cl, cms = ktimes["apply_correction"]
+        cwork = float(n_nodes) * (n_nodes - 1) * 8.0 * nrhs
+        cach = cwork / (cms / 1e3 / cl) / 1e12
+        corr = {"bound": "mfma", "kernel": "apply_correction", "achieved": cach,
+                "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": cach / FP32_MFMA_PEAK_TFLOPS,
+                "work": cwork, "work_unit": "FP32 matrix-core flops per launch: N(N-1) node pairs x 8 nrhs",
+                "launches_per_step": cl / steps, "ms_per_launch": cms / cl,
+                "traffic": measured_traffic("apply_correction", workload, form, tol),
+                "traffic_unit": "HBM bytes per launch"}
     return {"bound": "alu", "kernel": fam, "dominant_family": dominant, "achieved": achieved,
             "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
             "traffic": measured_traffic(fam, workload, form, tol),
             "traffic_unit": "HBM bytes per launch" if fam == "apply_operator" else "HBM bytes per step",
             "work": work, "work_unit": unit_desc, "launches_per_step": launches / steps,
             "ms_per_launch": 1e3 * per_launch_s if fam == "apply_operator" else tot_ms / launches,
-            "ms_per_step": tot_ms / steps}
+            "ms_per_step": tot_ms / steps, "correction_image": corr}
 
 
 def main():

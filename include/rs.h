@@ -86,6 +86,14 @@ typedef struct {
                           -1 = chosen per (N, ncols) by timing every candidate shape once per
                           process (the autotuner); k >= 0 = candidate k (invalid ones fall
                           back to a fixed default).  Every shape gives bitwise the same result */
+  int refine_update;   /* 1 (default): after the first exact float64 residual, the residual of a
+                          refinement iteration is updated as r - A dx, with A dx (dx the
+                          iteration's correction, small) computed on FP32 matrix cores; its
+                          rounding is bounded per node and the bound's norm, accumulated over
+                          the updates, is added to the residual norm in the convergence test,
+                          so a converged solve is certified against the exact residual; the
+                          exact float64 residual is taken again once that sum passes a quarter
+                          of refine_tol.  0: every residual is the exact float64 [f;0] - A x */
 } rs_params;
 
 /* Fill *p with the defaults: lambda -0.5, tol 1e-10, leaf 64, 64 proxy points
@@ -246,6 +254,16 @@ rs_status rs_get_skeleton(const rs_ctx* ctx, int box, int cap, int* out, int* le
  * y = A x, x host (2N+3p) x ncols column-major, y host same shape.  This is
  * the residual kernel used by refinement, exposed for verification. */
 rs_status rs_apply(rs_ctx* ctx, int ncols, const double* x, double* y);
+
+/* The float32 image of the same operator, as refinement uses it for the
+ * image A dx of a correction (rs_params.refine_update): the double-layer pair
+ * sums on FP32 matrix cores with float32 accumulation over tiles of 64 sources,
+ * the O(N) terms in float64.  x, y as for rs_apply.  bound (nullable, host,
+ * N x ncols column-major) receives per node and column a bound on |y - A x| for
+ * both of the node's rows (the Psi^T rows are exact up to float64 rounding).
+ * RS_ERR_ARG if two distinct nodes are closer than the kernel's float32 range
+ * (about 3e-8). */
+rs_status rs_apply_f32(rs_ctx* ctx, int ncols, const double* x, double* y, double* bound);
 
 /* Apply the factored inverse to general right-hand sides of the augmented
  * system (eq. kinv with the partitioned root solve of eq. partition): x =

@@ -42,6 +42,7 @@ class Params(ctypes.Structure):
         ("solve_graph", ctypes.c_int),
         ("mixed_rcond_min", ctypes.c_double),
         ("apply_shape", ctypes.c_int),
+        ("refine_update", ctypes.c_int),
     ]
 
 
@@ -106,6 +107,7 @@ def load_library():
     lib.rs_get_skeleton.argtypes = [h, ctypes.c_int, ctypes.c_int, ip, ip]
     lib.rs_apply.argtypes = [h, ctypes.c_int, dp, dp]
     lib.rs_apply_inverse.argtypes = [h, ctypes.c_int, dp, dp]
+    lib.rs_apply_f32.argtypes = [h, ctypes.c_int, dp, dp, dp]
     lib.rs_apply_dev_noalloc.argtypes = [h, ctypes.c_int, vp, vp]
     lib.rs_dense_inverse.argtypes = [h, ctypes.c_int, dp, dp]
     lib.rs_evaluate.argtypes = [h, ctypes.c_int, dp, ctypes.c_int, dp, dp]
@@ -124,7 +126,7 @@ def load_library():
     for name in ("rs_build_tree", "rs_factor", "rs_solve", "rs_solve_dev", "rs_update_moved_nodes",
                  "rs_update_geometry",
                  "rs_set_stream", "rs_get_stats", "rs_get_boxes", "rs_get_skeleton", "rs_apply",
-                 "rs_apply_inverse", "rs_apply_dev_noalloc",
+                 "rs_apply_inverse", "rs_apply_dev_noalloc", "rs_apply_f32",
                  "rs_dense_inverse", "rs_evaluate", "rs_set_kernel_timing", "rs_get_kernel_times",
                  "rs_factor_batch", "rs_solve_batch", "rs_update_moved_nodes_batch"):
         getattr(lib, name).restype = ctypes.c_int
@@ -141,7 +143,8 @@ def exported_symbols():
                  "rs_update_moved_nodes", "rs_update_geometry", "rs_set_stream", "rs_get_stats", "rs_get_boxes",
                  "rs_get_skeleton", "rs_apply", "rs_apply_inverse", "rs_dense_inverse", "rs_evaluate",
                  "rs_set_kernel_timing", "rs_get_kernel_times", "rs_factor_batch", "rs_solve_batch",
-                 "rs_update_moved_nodes_batch", "rs_apply_dev_noalloc", "rs_reset_tuning", "rs_destroy",
+                 "rs_update_moved_nodes_batch", "rs_apply_dev_noalloc", "rs_apply_f32", "rs_reset_tuning",
+                 "rs_destroy",
                  "rs_last_error"):
         if hasattr(lib, name):
             out.append(name)
@@ -230,7 +233,7 @@ class RSSolver:
     def __init__(self, xy, normal, weight, curvature, curve_id, hole_xy=None, *, tol=None,
                  leaf_size=None, n_proxy=None, proxy_ratio=None, lam=None, rcond_min=None,
                  precision=None, refine_tol=None, refine_max=None, root=None, solve_graph=None,
-                 mixed_rcond_min=None, apply_shape=None):
+                 mixed_rcond_min=None, apply_shape=None, refine_update=None):
         lib = load_library()
         self._lib = lib
         self._h = ctypes.c_void_p()
@@ -239,7 +242,8 @@ class RSSolver:
                           ("proxy_ratio", proxy_ratio), ("lambda_", lam), ("rcond_min", rcond_min),
                           ("precision", precision), ("refine_tol", refine_tol),
                           ("refine_max", refine_max), ("solve_graph", solve_graph),
-                          ("mixed_rcond_min", mixed_rcond_min), ("apply_shape", apply_shape)):
+                          ("mixed_rcond_min", mixed_rcond_min), ("apply_shape", apply_shape),
+                          ("refine_update", refine_update)):
             if val is not None:
                 setattr(p, name, val)
         if root is not None:
@@ -317,6 +321,19 @@ class RSSolver:
         Y = np.empty_like(Xf, order="F")
         self._check(self._lib.rs_apply(self._h, Xf.shape[1], _dptr(Xf), _dptr(Y)))
         return Y[:, 0] if one else np.ascontiguousarray(Y)
+
+    def apply_f32(self, x):
+        """(y, bound): the float32 matrix-core image of A x and, per node and
+        column, a bound on |y - A x| over the node's two rows (rs_apply_f32)."""
+        x = np.asarray(x, dtype=np.float64)
+        one = x.ndim == 1
+        Xf = np.asfortranarray(x.reshape(self.n_system, -1))
+        Y = np.empty_like(Xf, order="F")
+        B = np.empty((self.n_nodes, Xf.shape[1]), order="F")
+        self._check(self._lib.rs_apply_f32(self._h, Xf.shape[1], _dptr(Xf), _dptr(Y), _dptr(B)))
+        if one:
+            return Y[:, 0], B[:, 0]
+        return np.ascontiguousarray(Y), np.ascontiguousarray(B)
 
     def apply_dev_noalloc(self, x_dev, y_dev):
         """y = A x on device tensors without allocating (rs_apply_dev_noalloc):

@@ -258,7 +258,10 @@ struct rs_ctx {
   std::vector<const void*> refine_sig;
   double refine_prev = 1.0;       // largest relative residual before the last launch
   int refine_last = 0;            // iterations in the last launch
-  DevBuf d_flag;                  // [converged, corrections applied]
+  DevBuf d_flag;                  // [converged, corrections applied, next residual updated, pair dropped]
+  DevBuf d_corr;                  // scratch of the float32 correction images
+  DevBuf d_fflag;                 // flags of rs_apply_f32
+  int refine_which = 0;           // eager refinement: residual of the next iteration (0 exact, 1 updated)
   hipEvent_t ev_qr = nullptr;     // a level's QR ranks and pivot orders have reached the host
   // second stream of a level's pivoted QR: the cooperative and memory-route
   // launches run beside the row-reduced boxes (fork after assembly, join before
@@ -345,7 +348,8 @@ struct KTimer {
       : c(ctx), st(on ? on : ctx->stream) {
     if (!c->timing || c->capturing || (detail && c->timing != 2)) return;
     if (c->timing == 3 && std::strcmp(name, "cpqr") != 0) return;
-    if (c->timing == 4 && std::strcmp(name, "apply_operator") != 0) return;
+    if (c->timing == 4 && std::strcmp(name, "apply_operator") != 0 && std::strcmp(name, "apply_correction") != 0)
+      return;
     if (c->timing == 2 && c->cur_level >= 0) {
       const std::string full = std::string(name) + "@L" + std::to_string(c->cur_level);
       fam = family(c, full.c_str());
@@ -1968,7 +1972,8 @@ void ensure_solve_buffers(rs_ctx* c, int ncols) {
   c->d_r.ensure(rows * sizeof(double));
   c->d_dx.ensure(rows * sizeof(double));
   c->d_ys.ensure(rows * sizeof(double));
-  c->d_norms.ensure((2 * (size_t)ncols + residual_scratch_doubles(ncols)) * sizeof(double));
+  // colsq, fsq, bsq, acc (ncols each), then the residual's partial sums
+  c->d_norms.ensure((4 * (size_t)ncols + residual_scratch_doubles(ncols)) * sizeof(double));
   c->d_v.ensure(std::max<size_t>((size_t)c->nz * ncols, 1) * sizeof(double));
   c->d_sol.ensure(std::max<size_t>((size_t)c->nz * ncols, 1) * sizeof(double));
   if (p3) {
@@ -1978,12 +1983,31 @@ void ensure_solve_buffers(rs_ctx* c, int ncols) {
     c->d_rhs2.ensure((size_t)p3 * ncols * sizeof(double));
   }
   c->d_apply.ensure(apply_scratch_doubles(c->N, ncols) * sizeof(double));
+  if (c->prm.refine_update) c->d_corr.ensure(corr_scratch_bytes(c->N, ncols));
   c->d_flag.ensure(4 * sizeof(int));
 }
 
+// The apply of one refinement iteration (rows layout): the exact apply of x,
+// or the float32 image of the correction dx, as the device flags say; which:
+// -1 both launched (graph capture), 0 or 1 only that one (eager iterations).
+void refine_apply(rs_ctx* c, int ncols, int which) {
+  if (!c->prm.refine_update) which = 0;
+  const int cfg = apply_config_for(c, ncols, c->d_xs.as<double>(), c->d_ys.as<double>());
+  Geo g;
+  geo_of(c, g);
+  KTimer kt_(c, which == 1 ? "apply_correction" : "apply_operator");
+  launch_apply_refine(g, c->d_curve.as<int>(), c->d_hole.as<double>(), c->p, c->prm.lambda, c->d_xs.as<double>(),
+                      c->d_dx.as<double>(), ncols, c->d_ys.as<double>(), c->d_apply.as<double>(),
+                      c->prm.refine_update ? c->d_corr.p : nullptr, c->d_flag.as<int>(), c->prm.refine_max, cfg,
+                      which, c->stream);
+  HIP_CHECK(hipGetLastError());
+}
+
 // One refinement iteration on the context's buffers: dx = inverse(r),
-// x += dx (unless converged), y = A x, r = [f; 0] - y, flags.
-void refine_iteration(rs_ctx* c, int nrhs) {
+// x += dx (unless converged), then the new residual: r = [f; 0] - A x with
+// the exact apply, or r = r - A dx with the float32 image of the correction
+// (the device flags choose), and the flags.  which: as for refine_apply.
+void refine_iteration(rs_ctx* c, int nrhs, int which) {
   const int n2 = 2 * c->N;
   const int ns = n2 + 3 * c->p;
   const size_t rows = (size_t)ns * nrhs;
@@ -1991,11 +2015,13 @@ void refine_iteration(rs_ctx* c, int nrhs) {
   apply_inverse(c, c->d_r.as<double>(), nrhs, c->d_dx.as<double>());
   launch_accumulate_unless(c->d_dx.as<double>(), (long long)rows, c->d_xs.as<double>(), c->d_flag.as<int>(),
                            c->prm.refine_max, c->stream);
-  apply_device_rows(c, c->d_xs.as<double>(), nrhs, c->d_ys.as<double>(), c->d_flag.as<int>());
+  refine_apply(c, nrhs, which);
+  const double* bt = c->prm.refine_update ? corr_bound_rows(c->d_corr.p, c->N, nrhs) : nullptr;
   launch_residual(c->d_frows.as<double>(), n2, c->d_ys.as<double>(), ns, nrhs, c->d_r.as<double>(), colsq,
-                  colsq + nrhs, colsq + 2 * nrhs, c->stream);
-  launch_refine_flag(colsq, colsq + nrhs, nrhs, c->prm.refine_tol, c->prm.refine_max, c->d_flag.as<int>(),
-                     c->stream);
+                  colsq + nrhs, colsq + 2 * nrhs, colsq + 4 * nrhs, c->d_flag.as<int>(), c->prm.refine_max, bt,
+                  c->stream);
+  launch_refine_flag(colsq, colsq + nrhs, colsq + 2 * nrhs, colsq + 3 * nrhs, nrhs, c->prm.refine_tol,
+                     c->prm.refine_max, c->prm.refine_update, corr_bound_scale(), c->d_flag.as<int>(), c->stream);
 }
 
 // x = 0, r = [f; 0], flags cleared (f already in d_frows).
@@ -2006,8 +2032,9 @@ void refine_begin(rs_ctx* c, int nrhs) {
   double* colsq = c->d_norms.as<double>();
   launch_fill(c->d_xs.as<double>(), (long long)ns * nrhs, 0.0, c->stream);
   launch_residual(c->d_frows.as<double>(), n2, c->d_xs.as<double>(), ns, nrhs, c->d_r.as<double>(), colsq,
-                  colsq + nrhs, colsq + 2 * nrhs, c->stream);
-  launch_set_ints(c->d_flag.as<int>(), 2, 0, c->stream);
+                  colsq + nrhs, colsq + 2 * nrhs, colsq + 4 * nrhs, nullptr, 0, nullptr, c->stream);
+  launch_set_ints(c->d_flag.as<int>(), 4, 0, c->stream);
+  c->refine_which = 0;
   c->refine_prev = 1.0;
   c->refine_last = 0;
 }
@@ -2016,6 +2043,7 @@ void refine_begin(rs_ctx* c, int nrhs) {
 std::vector<const void*> refine_graph_sig(const rs_ctx* c) {
   const DevBuf* bufs[] = {&c->d_r,     &c->d_dx,     &c->d_ys,   &c->d_xs,     &c->d_frows, &c->d_norms,
                           &c->d_v,     &c->d_sol,    &c->d_parts, &c->d_rhs2,  &c->d_apply, &c->d_flag,
+                          &c->d_corr,
                           &c->d_sboxes, &c->d_sidx,  &c->d_ridx,  &c->d_I0,    &c->d_Zinv,  &c->d_Ph,
                           &c->d_W,     &c->d_Wf,     &c->d_x,     &c->d_y,     &c->d_nx,    &c->d_ny,
                           &c->d_w,     &c->d_kap,    &c->d_curve, &c->d_hole};
@@ -2043,7 +2071,7 @@ void refine_graph_capture(rs_ctx* c, int nrhs) {
   hipGraph_t g = nullptr;
   HIP_CHECK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
   try {
-    refine_iteration(c, nrhs);
+    refine_iteration(c, nrhs, -1);
   } catch (...) {
     (void)hipStreamEndCapture(c->cap_stream, &g);
     if (g) (void)hipGraphDestroy(g);
@@ -2099,18 +2127,21 @@ void refine_graph_launch(rs_ctx* c, int nrhs) {
 // Read the flags and norms after a graph launch; true when refinement is over
 // (conv receives whether it converged).  Fills last_res and refine_iters.
 bool refine_poll(rs_ctx* c, int nrhs, bool& conv) {
-  int* hf = c->h_flag.get<int>(4 + 4 * (size_t)nrhs);
+  int* hf = c->h_flag.get<int>(4 + 8 * (size_t)nrhs);
   double* hn = reinterpret_cast<double*>(hf + 4);
-  HIP_CHECK(hipMemcpyAsync(hf, c->d_flag.p, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
-  HIP_CHECK(hipMemcpyAsync(hn, c->d_norms.p, 2 * (size_t)nrhs * sizeof(double), hipMemcpyDeviceToHost,
+  HIP_CHECK(hipMemcpyAsync(hf, c->d_flag.p, 4 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIP_CHECK(hipMemcpyAsync(hn, c->d_norms.p, 4 * (size_t)nrhs * sizeof(double), hipMemcpyDeviceToHost,
                            c->stream));
   HIP_CHECK(hipStreamSynchronize(c->stream));
   resolve_timers(c);
   c->stats.refine_iters = hf[1];
+  c->refine_which = hf[2] == 1 ? 1 : 0;
+  // the certified relative residual: the computed norm plus the accumulated
+  // rounding bound of updated residuals
   c->last_res.assign(nrhs, 0.0);
   for (int q = 0; q < nrhs; ++q) {
     const double fq = hn[nrhs + q] > 0 ? hn[nrhs + q] : 1.0;
-    c->last_res[q] = std::sqrt(hn[q] / fq);
+    c->last_res[q] = (std::sqrt(hn[q]) + hn[3 * nrhs + q]) / std::sqrt(fq);
   }
   conv = hf[0] != 0;
   return conv || hf[1] >= c->prm.refine_max;
@@ -2119,7 +2150,7 @@ bool refine_poll(rs_ctx* c, int nrhs, bool& conv) {
 // The same iterations launched one by one, the host testing after each.
 bool refine_eager(rs_ctx* c, int nrhs) {
   for (;;) {
-    refine_iteration(c, nrhs);
+    refine_iteration(c, nrhs, c->refine_which);
     bool conv;
     if (refine_poll(c, nrhs, conv)) return conv;
   }
@@ -2334,6 +2365,7 @@ void rs_default_params(rs_params* p) {
   p->solve_graph = 1;
   p->mixed_rcond_min = 1e-4;
   p->apply_shape = -1;
+  p->refine_update = 1;
 }
 
 rs_status rs_build_tree(const rs_params* prm, int n_nodes, const double* xy, const double* normal,
@@ -2350,6 +2382,8 @@ rs_status rs_build_tree(const rs_params* prm, int n_nodes, const double* xy, con
     if (prm->precision < 0 || prm->precision > 2) throw RsError{RS_ERR_ARG, "precision must be 0, 1 or 2"};
     if (!(prm->mixed_rcond_min >= 0.0) || !std::isfinite(prm->mixed_rcond_min))
       throw RsError{RS_ERR_ARG, "mixed_rcond_min must be finite and >= 0"};
+    if (prm->refine_update != 0 && prm->refine_update != 1)
+      throw RsError{RS_ERR_ARG, "refine_update must be 0 or 1"};
     validate_nodes(n_nodes, xy, normal, weight, curvature);
     std::vector<int> count(n_holes + 1, 0);
     for (int i = 0; i < n_nodes; ++i) {
@@ -2583,11 +2617,12 @@ rs_status rs_solve(rs_ctx* c, int nrhs, const double* f, double* x, double* rel_
         // residual of the direct solve: x rows are in d_xs
         c->d_ys.ensure(ns * nrhs * sizeof(double));
         c->d_r.ensure(ns * nrhs * sizeof(double));
-        c->d_norms.ensure((2 * (size_t)nrhs + residual_scratch_doubles(nrhs)) * sizeof(double));
+        c->d_norms.ensure((4 * (size_t)nrhs + residual_scratch_doubles(nrhs)) * sizeof(double));
         apply_device_rows(c, c->d_xs.as<double>(), nrhs, c->d_ys.as<double>(), nullptr);
         double* colsq = c->d_norms.as<double>();
         launch_residual(c->d_frows.as<double>(), (int)n2, c->d_ys.as<double>(), (int)ns, nrhs,
-                        c->d_r.as<double>(), colsq, colsq + nrhs, colsq + 2 * nrhs, s);
+                        c->d_r.as<double>(), colsq, colsq + nrhs, colsq + 2 * nrhs, colsq + 4 * nrhs, nullptr, 0,
+                        nullptr, s);
         std::vector<double> nrm(2 * nrhs);
         HIP_CHECK(hipMemcpyAsync(nrm.data(), colsq, nrm.size() * sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipStreamSynchronize(s));
@@ -2620,6 +2655,53 @@ rs_status rs_apply(rs_ctx* c, int ncols, const double* x, double* y) {
     HIP_CHECK(hipMemcpyAsync(y, c->d_f.p, ns * ncols * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIP_CHECK(hipStreamSynchronize(c->stream));
     resolve_timers(c);
+    return RS_OK;
+  } catch (const RsError& e) {
+    return fail(c, e);
+  }
+}
+
+rs_status rs_apply_f32(rs_ctx* c, int ncols, const double* x, double* y, double* bound) {
+  if (!c) return RS_ERR_ARG;
+  try {
+    if (ncols <= 0 || !x || !y) throw RsError{RS_ERR_ARG, "bad ncols or NULL pointer"};
+    HIP_CHECK(hipSetDevice(c->device));
+    const size_t ns = 2 * (size_t)c->N + 3 * (size_t)c->p;
+    hipStream_t s = c->stream;
+    c->d_f.ensure(ns * ncols * sizeof(double));
+    c->d_c.ensure(ns * ncols * sizeof(double));
+    c->d_res.ensure(ns * ncols * sizeof(double));
+    c->d_apply.ensure(apply_scratch_doubles(c->N, ncols) * sizeof(double));
+    c->d_corr.ensure(corr_scratch_bytes(c->N, ncols));
+    // flags of a refinement iteration whose residual is updated: the image runs
+    c->d_fflag.ensure(4 * sizeof(int));
+    launch_set_ints(c->d_fflag.as<int>(), 4, 0, s);
+    launch_set_ints(c->d_fflag.as<int>() + 2, 1, 1, s);
+    HIP_CHECK(hipMemcpyAsync(c->d_f.p, x, ns * ncols * sizeof(double), hipMemcpyHostToDevice, s));
+    launch_to_rows(c->d_f.as<double>(), (int)ns, (int)ns, ncols, c->d_c.as<double>(), s);
+    Geo g;
+    geo_of(c, g);
+    {
+      KTimer kt_(c, "apply_correction");
+      launch_apply_refine(g, c->d_curve.as<int>(), c->d_hole.as<double>(), c->p, c->prm.lambda,
+                          c->d_c.as<double>(), c->d_c.as<double>(), ncols, c->d_res.as<double>(),
+                          c->d_apply.as<double>(), c->d_corr.p, c->d_fflag.as<int>(), 1, 0, 1, s);
+    }
+    launch_from_rows(c->d_res.as<double>(), (int)ns, ncols, c->d_f.as<double>(), (int)ns, s);
+    HIP_CHECK(hipMemcpyAsync(y, c->d_f.p, ns * ncols * sizeof(double), hipMemcpyDeviceToHost, s));
+    std::vector<double> bt((size_t)c->N * ncols);
+    int hflag[4];
+    HIP_CHECK(hipMemcpyAsync(bt.data(), corr_bound_rows(c->d_corr.p, c->N, ncols), bt.size() * sizeof(double),
+                             hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipMemcpyAsync(hflag, c->d_fflag.p, sizeof(hflag), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    resolve_timers(c);
+    if (hflag[3]) throw RsError{RS_ERR_ARG, "two distinct nodes are too close for the float32 image"};
+    if (bound) {
+      const double sc = corr_bound_scale();
+      for (int q = 0; q < ncols; ++q)
+        for (int i = 0; i < c->N; ++i) bound[(size_t)q * c->N + i] = sc * bt[(size_t)i * ncols + q];
+    }
     return RS_OK;
   } catch (const RsError& e) {
     return fail(c, e);

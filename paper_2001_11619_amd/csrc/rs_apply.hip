@@ -64,10 +64,15 @@ __device__ __forceinline__ void pair_add(double xi, double yi, double px, double
   }
 }
 
-// True when refinement has converged or used up its iterations (the
-// iteration's operator apply is then not needed).
-__device__ __forceinline__ bool apply_skipped(const int* skip, int max_iters) {
-  return skip && (skip[0] != 0 || skip[1] >= max_iters);
+// What a refinement iteration's apply does, from the refinement flags (null
+// outside refinement): flag[0] converged, flag[1] iterations done, flag[2] = 1
+// when the iteration updates the residual with a float32 image of the
+// correction.  -1: nothing (converged or out of iterations); 0: the exact
+// float64 apply of x; 1: the float32 correction image (A dx).
+__device__ __forceinline__ int apply_mode(const int* flag, int max_iters) {
+  if (!flag) return 0;
+  if (flag[0] != 0 || flag[1] >= max_iters) return -1;
+  return flag[2] == 1 ? 1 : 0;
 }
 
 // Targets (tx, ty), nt of them: the boundary nodes themselves for the
@@ -79,7 +84,7 @@ __global__ __launch_bounds__(kApplyThreads) void k_apply_pairs(Geo g, const doub
                                                                int ncols, int chunk,
                                                                double* __restrict__ part,
                                                                const int* skip, int max_iters) {
-  if (apply_skipped(skip, max_iters)) return;
+  if (apply_mode(skip, max_iters) != 0) return;
   __shared__ double2 sxy[kApplyThreads];
   __shared__ double2 swn[kApplyThreads];
   __shared__ double sm[kApplyThreads * 2 * NC];
@@ -151,7 +156,7 @@ __global__ __launch_bounds__(kApplyThreads) void k_apply_pairs_s(const double4* 
                                                                  double* __restrict__ part,
                                                                  const int* __restrict__ skip,
                                                                  int max_iters) {
-  if (apply_skipped(skip, max_iters)) return;
+  if (apply_mode(skip, max_iters) != 0) return;
   const int tid = threadIdx.x;
   const int ib = blockIdx.x * (kApplyThreads * T) + tid;
   const int js0 = blockIdx.y * chunk, js1 = min(N, js0 + chunk);
@@ -222,10 +227,14 @@ constexpr int kNodeSumThreads = 1024;
 // kNsumParts node ranges: block (q, b) sums range b into nsum[q kNsumParts + b]
 // and k_apply_sum adds the ranges in order (fixed-order sums).
 constexpr int kNsumParts = 8;
-__global__ __launch_bounds__(kNodeSumThreads) void k_apply_nsum(Geo g, const double* x, int ncols,
-                                                                double* nsum, const int* skip,
+// The O(N) kernels below take x (the exact apply) and xc (the correction, read
+// when the refinement flags ask for its image).
+__global__ __launch_bounds__(kNodeSumThreads) void k_apply_nsum(Geo g, const double* x, const double* xc,
+                                                                int ncols, double* nsum, const int* skip,
                                                                 int max_iters) {
-  if (apply_skipped(skip, max_iters)) return;
+  const int md = apply_mode(skip, max_iters);
+  if (md < 0) return;
+  if (md == 1) x = xc;
   constexpr int NW = kNodeSumThreads / 64;
   __shared__ double red[NW];
   const int q = blockIdx.x, b = blockIdx.y;
@@ -240,10 +249,14 @@ __global__ __launch_bounds__(kNodeSumThreads) void k_apply_nsum(Geo g, const dou
 
 // y[2N rows] = sum over source chunks (fixed order) + the diagonal (lam and
 // the curvature limit of D) + the rank-one term + H lambda
+// For a correction image it also adds the rounding bounds of the chunks
+// (bpart, float) into bt (per node and column).
 __global__ void k_apply_sum(Geo g, double lam, const double* hole_xy, int p, const double* x,
-                            int ncols, const double* part, int nchunk, const double* nsum,
-                            double* y, const int* skip, int max_iters) {
-  if (apply_skipped(skip, max_iters)) return;
+                            const double* xc, int ncols, const double* part, int nchunk, const double* nsum,
+                            const float* bpart, double* bt, double* y, const int* skip, int max_iters) {
+  const int md = apply_mode(skip, max_iters);
+  if (md < 0) return;
+  if (md == 1) x = xc;
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int N = g.N;
   if (t >= (long long)N * ncols) return;
@@ -253,6 +266,11 @@ __global__ void k_apply_sum(Geo g, double lam, const double* hole_xy, int p, con
   for (int c = 0; c < nchunk; ++c) {
     ax += part[c * stride + (size_t)(2 * i) * ncols + q];
     ay += part[c * stride + (size_t)(2 * i + 1) * ncols + q];
+  }
+  if (md == 1 && bpart) {
+    double b = 0.0;
+    for (int c = 0; c < nchunk; ++c) b += (double)bpart[((size_t)c * N + i) * ncols + q];
+    bt[(size_t)i * ncols + q] = b;
   }
   const double mx = x[(size_t)(2 * i) * ncols + q], my = x[(size_t)(2 * i + 1) * ncols + q];
   const double nxi = g.nx[i], nyi = g.ny[i];
@@ -321,9 +339,11 @@ __global__ void k_eval_sum(Geo g, const double* tx, const double* ty, int nt, co
 
 // Rows of Psi^T x - lambda: one block per (hole, mode), fixed-order sums.
 __global__ __launch_bounds__(kNodeSumThreads) void k_apply_psi(Geo g, const int* curve_id, int p,
-                                                               const double* x, int ncols, double* y,
-                                                               const int* skip, int max_iters) {
-  if (apply_skipped(skip, max_iters)) return;
+                                                               const double* x, const double* xc, int ncols,
+                                                               double* y, const int* skip, int max_iters) {
+  const int md = apply_mode(skip, max_iters);
+  if (md < 0) return;
+  if (md == 1) x = xc;
   constexpr int NW = kNodeSumThreads / 64;
   __shared__ double red[NW];
   const int h = blockIdx.x / 3, mode = blockIdx.x % 3;
@@ -343,6 +363,208 @@ __global__ __launch_bounds__(kNodeSumThreads) void k_apply_psi(Geo g, const int*
     const size_t row = base + 3 * h + mode;
     y[row * ncols + q] = s - x[row * ncols + q];
   }
+}
+
+// ---- float32 image of a refinement correction --------------------------------
+// Once the residual r = [f; 0] - A x is known exactly, the next one follows
+// from the correction dx alone: r' = r - A dx.  dx is small (about |r| relative
+// to x), so A dx is needed only to a relative accuracy of about
+// refine_tol / |r|, which float32 arithmetic meets.  Its double-layer pair
+// sums (the O(N^2) part) run on the FP32 matrix cores: a wave holds 16
+// targets x 16 columns, and per step of 4 sources every lane forms one pair's
+// 2 x 2 block (target lane % 16, source lane / 16) in float32, which feeds
+// four v_mfma_f32_16x16x4f32 (y_x += K_xx d_x + K_xy d_y, y_y += K_xy d_x +
+// K_yy d_y) with d as the B operand (source lane / 16, column lane % 16).  The
+// float32 accumulators are added into float64 ones every kCorrFlush sources.
+// The O(N) terms stay float64.
+//
+// Rounding bound.  The offsets r and r . (w n / pi) are formed in float64 and
+// rounded once, so every entry of the block is its exact value times
+// (1 + delta) with |delta| <= 17.25 u (u = 2^-24: the two roundings of r and
+// the one of r . wn, then r^2, r^4 with its floor (u / 4), the reciprocal
+// (2 u), and the three products of an entry, to first order), up to float64
+// rounding of the offsets.
+// Rounding d and the product cost u each, and accumulating a window of
+// kCorrFlush sources (2 kCorrFlush products per row) in float32 at most
+// 2 kCorrFlush u times the sum of the terms' magnitudes.  So per target t and
+// column q the float32 sum is off by at most (19.25 + 2 kCorrFlush) u
+// sum_s e_ts max(|dx_s,q|, |dy_s,q|), e_ts the larger row sum of |K_ts|.  The
+// kernel accumulates, per tile of kCorrTile sources, sum_s e_ts times the
+// tile's largest |d| of column q; the host scales by kCorrBoundScale u >=
+// (19.25 + 2 kCorrFlush) u, and the refinement test adds the bound's 2-norm to
+// the residual's, so a converged residual is certified.
+constexpr int kCorrThreads = 256;                      // 4 waves
+constexpr int kCorrGroups = 2;                         // 16-target groups per wave
+constexpr int kCorrTargets = 4 * 16 * kCorrGroups;     // targets per block
+constexpr int kCorrTile = 64;                          // sources per LDS tile (16 steps of 4)
+constexpr int kCorrFlush = 16;                         // sources per float32 accumulation window
+// A distinct pair with |r|^2 below 2^-50 (nodes closer than 2^-25) is out of
+// the float32 kernel's range: flag[3] is set and the refinement returns to
+// exact residuals (rs_apply_f32 reports an error).  kR4Floor32 is added to
+// every |r|^4 (the smallest normal float).
+constexpr unsigned kR2MinBits = 0x26800000u;   // bits of 2^-50
+constexpr float kR4Floor32 = 0x1p-126f;
+typedef float corr_f4 __attribute__((ext_vector_type(4)));
+
+// dx (rows layout, 2N x ncols, float64) to float32 in column blocks of 16
+// ([cb][2N][16], columns past ncols zero), and per tile of kCorrTile sources
+// the largest |d| of each column over both components ([cb][tile][16]).
+__global__ __launch_bounds__(256) void k_corr_prep(const double* x, int N, int ncols, float* d32,
+                                                   float* dmax, const int* flag, int max_iters) {
+  if (apply_mode(flag, max_iters) != 1) return;
+  __shared__ float red[16][16];
+  const int tile = blockIdx.x, cb = blockIdx.y;
+  const int j = threadIdx.x & 15, sub = threadIdx.x >> 4;
+  const int q = cb * 16 + j;
+  const int ntile = (N + kCorrTile - 1) / kCorrTile;
+  float m = 0.0f;
+  for (int u = sub; u < kCorrTile; u += 16) {
+    const int sidx = tile * kCorrTile + u;
+    if (sidx >= N) break;
+    float vx = 0.0f, vy = 0.0f;
+    if (q < ncols) {
+      vx = (float)x[(size_t)(2 * sidx) * ncols + q];
+      vy = (float)x[(size_t)(2 * sidx + 1) * ncols + q];
+    }
+    d32[((size_t)cb * 2 * N + 2 * sidx) * 16 + j] = vx;
+    d32[((size_t)cb * 2 * N + 2 * sidx + 1) * 16 + j] = vy;
+    m = fmaxf(m, fmaxf(fabsf(vx), fabsf(vy)));
+  }
+  red[sub][j] = m;
+  __syncthreads();
+  if (threadIdx.x < 16) {
+    float mm = 0.0f;
+    for (int u = 0; u < 16; ++u) mm = fmaxf(mm, red[u][threadIdx.x]);
+    dmax[((size_t)cb * ntile + tile) * 16 + threadIdx.x] = mm;
+  }
+}
+
+// Pair sums of the correction image over one source chunk: grid = (target
+// blocks of kCorrTargets, source chunks, column blocks of 16).  part: float64
+// partials in the exact apply's layout; bpart: float32 bound partials
+// [chunk][N][ncols]; flag[3] is set when a pair had to be dropped.
+__global__ __launch_bounds__(kCorrThreads) void k_apply_pairs32(const double4* __restrict__ src4, int N,
+                                                                const float* __restrict__ d32,
+                                                                const float* __restrict__ dmax, int ncols,
+                                                                int chunk, double* __restrict__ part,
+                                                                float* __restrict__ bpart, int* flag,
+                                                                int max_iters) {
+  if (apply_mode(flag, max_iters) != 1) return;
+  __shared__ double2 sxy[kCorrTile];
+  __shared__ double2 swn[kCorrTile];
+  __shared__ float sd[kCorrTile * 32];   // [source][component][16 columns]
+  __shared__ float sdm[16];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int r16 = lane & 15, kq = lane >> 4;
+  const int cb = blockIdx.z;
+  const int js0 = blockIdx.y * chunk, js1 = min(N, js0 + chunk);
+  const int ntile = (N + kCorrTile - 1) / kCorrTile;
+  const int tbase = blockIdx.x * kCorrTargets + wid * 16 * kCorrGroups;
+  double xt[kCorrGroups], yt[kCorrGroups];
+  corr_f4 cx[kCorrGroups], cy[kCorrGroups];
+  double ax[kCorrGroups][4], ay[kCorrGroups][4];
+  float bnd[kCorrGroups][4], sacc[kCorrGroups];
+#pragma unroll
+  for (int g = 0; g < kCorrGroups; ++g) {
+    const double4 tp = src4[min(tbase + 16 * g + r16, N - 1)];
+    xt[g] = tp.x;
+    yt[g] = tp.y;
+    cx[g] = corr_f4{0.0f, 0.0f, 0.0f, 0.0f};
+    cy[g] = cx[g];
+    sacc[g] = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) { ax[g][i] = 0.0; ay[g][i] = 0.0; bnd[g][i] = 0.0f; }
+  }
+  bool dropped = false;
+  const float* dblk = d32 + (size_t)cb * 2 * N * 16;
+  for (int j0 = js0; j0 < js1; j0 += kCorrTile) {
+    const int nsrc = min(kCorrTile, js1 - j0);
+    __syncthreads();
+    if (tid < kCorrTile) {
+      if (tid < nsrc) {
+        const double4 sp = src4[j0 + tid];
+        sxy[tid] = make_double2(sp.x, sp.y);
+        swn[tid] = make_double2(sp.z, sp.w);
+      } else {
+        // padding: no weight, far away (its |r|^2 overflows, its terms are 0)
+        sxy[tid] = make_double2(1e30, 1e30);
+        swn[tid] = make_double2(0.0, 0.0);
+      }
+    }
+    for (int e = tid; e < kCorrTile * 32; e += kCorrThreads)
+      sd[e] = (e >> 5) < nsrc ? dblk[(size_t)(2 * j0) * 16 + e] : 0.0f;
+    if (tid < 16) sdm[tid] = dmax[((size_t)cb * ntile + j0 / kCorrTile) * 16 + tid];
+    __syncthreads();
+#pragma unroll 1
+    for (int u0 = 0; u0 < kCorrTile / 4; u0 += kCorrFlush / 4) {
+      for (int u = u0; u < u0 + kCorrFlush / 4; ++u) {
+        const int sl = 4 * u + kq;
+        const double2 pp = sxy[sl];
+        const double2 wn = swn[sl];
+        const float bx = sd[sl * 32 + r16], by = sd[sl * 32 + 16 + r16];
+#pragma unroll
+        for (int g = 0; g < kCorrGroups; ++g) {
+          const double rxd = xt[g] - pp.x, ryd = yt[g] - pp.y;
+          const float rx = (float)rxd, ry = (float)ryd;
+          const float rn = (float)fma(rxd, wn.x, ryd * wn.y);
+          const float r2 = fmaf(rx, rx, ry * ry);
+          // 0 < r2 < 2^-50: two distinct nodes too close for float32
+          dropped |= (unsigned)__float_as_uint(r2) - 1u < kR2MinBits - 1u;
+          // the floor keeps the coincident pair (r = 0, r . wn = 0 exactly)
+          // and padding (wn = 0) finite and zero; for every other pair it
+          // changes |r|^4 by at most 2^-26 relative
+          const float inv = __builtin_amdgcn_rcpf(fmaf(r2, r2, kR4Floor32));
+          const float c = rn * inv;
+          const float crx = c * rx, cry = c * ry;
+          const float kxx = crx * rx, kxy = crx * ry, kyy = cry * ry;
+          sacc[g] += fmaxf(fabsf(kxx) + fabsf(kxy), fabsf(kxy) + fabsf(kyy));
+          cx[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(kxx, bx, cx[g], 0, 0, 0);
+          cx[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(kxy, by, cx[g], 0, 0, 0);
+          cy[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(kxy, bx, cy[g], 0, 0, 0);
+          cy[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(kyy, by, cy[g], 0, 0, 0);
+        }
+      }
+      // window end: float32 sums into float64
+#pragma unroll
+      for (int g = 0; g < kCorrGroups; ++g) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          ax[g][i] += (double)cx[g][i];
+          ay[g][i] += (double)cy[g][i];
+        }
+        cx[g] = corr_f4{0.0f, 0.0f, 0.0f, 0.0f};
+        cy[g] = cx[g];
+      }
+    }
+    // tile end: bound of the tile
+    const float dm = sdm[r16];
+#pragma unroll
+    for (int g = 0; g < kCorrGroups; ++g) {
+      float st = sacc[g];
+      st += __shfl_xor(st, 16);
+      st += __shfl_xor(st, 32);
+      sacc[g] = 0.0f;
+      // result lane l, register i holds target 4 (l / 16) + i, column l % 16
+#pragma unroll
+      for (int i = 0; i < 4; ++i) bnd[g][i] = fmaf(__shfl(st, 4 * kq + i), dm, bnd[g][i]);
+    }
+  }
+  if (dropped) flag[3] = 1;
+  const int q = cb * 16 + r16;
+  if (q >= ncols) return;
+  double* out = part + (size_t)blockIdx.y * 2 * N * ncols;
+  float* bout = bpart + (size_t)blockIdx.y * N * ncols;
+#pragma unroll
+  for (int g = 0; g < kCorrGroups; ++g)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int t = tbase + 16 * g + 4 * kq + i;
+      if (t < N) {
+        out[(size_t)(2 * t) * ncols + q] = ax[g][i];
+        out[(size_t)(2 * t + 1) * ncols + q] = ay[g][i];
+        bout[(size_t)t * ncols + q] = bnd[g][i];
+      }
+    }
 }
 
 }  // namespace
@@ -418,6 +640,47 @@ size_t apply_scratch_doubles(int N, int ncols) {
   return src4_offset((size_t)nch * 2 * N * ncols + (size_t)kNsumParts * ncols) + 4 * (size_t)N;
 }
 
+namespace {
+// Layout of the correction image's scratch (bytes): d32, dmax, bpart (float),
+// then bt (double, N x ncols).
+struct CorrLayout {
+  size_t d32, dmax, bpart, bt, total;
+};
+CorrLayout corr_layout(int N, int ncols) {
+  const int len = apply_chunk_len(N);
+  const size_t nch = (size_t)((N + len - 1) / len);
+  const size_t ncb = (size_t)((ncols + 15) / 16);
+  const size_t ntile = (size_t)((N + kCorrTile - 1) / kCorrTile);
+  CorrLayout L;
+  L.d32 = 0;
+  L.dmax = L.d32 + ncb * 2 * N * 16 * sizeof(float);
+  L.bpart = L.dmax + ncb * ntile * 16 * sizeof(float);
+  L.bt = (L.bpart + nch * N * ncols * sizeof(float) + 255) / 256 * 256;
+  L.total = L.bt + (size_t)N * ncols * sizeof(double);
+  return L;
+}
+
+// The O(N) terms and the sum of the chunk partials (both modes).
+void apply_tail(Geo g, const int* curve_id, const double* hole_xy, int p, double lam, const double* x,
+                const double* xc, int ncols, double* y, double* part, int nchunk, const float* bpart,
+                double* bt, const int* flag, int max_iters, hipStream_t s) {
+  double* nsum = part + (size_t)nchunk * 2 * g.N * ncols;
+  hipLaunchKernelGGL(k_apply_nsum, dim3(ncols, kNsumParts), dim3(kNodeSumThreads), 0, s, g, x, xc, ncols, nsum,
+                     flag, max_iters);
+  hipLaunchKernelGGL(k_apply_sum, dim3(blocks_for((long long)g.N * ncols, kBlock)), dim3(kBlock), 0, s,
+                     g, lam, hole_xy, p, x, xc, ncols, part, nchunk, nsum, bpart, bt, y, flag, max_iters);
+  if (p > 0)
+    hipLaunchKernelGGL(k_apply_psi, dim3(3 * p, ncols), dim3(kNodeSumThreads), 0, s, g, curve_id, p, x, xc,
+                       ncols, y, flag, max_iters);
+}
+
+double4* apply_src4(double* part, int N, int ncols) {
+  const int chunk = apply_chunk_len(N);
+  const int nchunk = (N + chunk - 1) / chunk;
+  return reinterpret_cast<double4*>(part + src4_offset((size_t)nchunk * 2 * N * ncols + (size_t)kNsumParts * ncols));
+}
+}  // namespace
+
 void launch_apply_operator(Geo g, const int* curve_id, const double* hole_xy, int p, double lam,
                            const double* x, int ncols, double* y, double* part, const int* skip,
                            int max_iters, int cfg, hipStream_t s) {
@@ -426,18 +689,60 @@ void launch_apply_operator(Geo g, const int* curve_id, const double* hole_xy, in
   const ApplyShape sh = kApplyShapes[cfg];
   const int chunk = apply_chunk_len(g.N);
   const int nchunk = (g.N + chunk - 1) / chunk;
-  double* nsum = part + (size_t)nchunk * 2 * g.N * ncols;
-  double4* src4 =
-      reinterpret_cast<double4*>(part + src4_offset((size_t)nchunk * 2 * g.N * ncols + (size_t)kNsumParts * ncols));
   dim3 grid(blocks_for(g.N, kApplyThreads * sh.t), nchunk, blocks_for(ncols, sh.nc));
-  launch_pairs(g, src4, g.x, g.y, g.N, x, ncols, chunk, part, skip, max_iters, cfg, grid, s);
-  hipLaunchKernelGGL(k_apply_nsum, dim3(ncols, kNsumParts), dim3(kNodeSumThreads), 0, s, g, x, ncols, nsum, skip,
-                     max_iters);
-  hipLaunchKernelGGL(k_apply_sum, dim3(blocks_for((long long)g.N * ncols, kBlock)), dim3(kBlock), 0, s,
-                     g, lam, hole_xy, p, x, ncols, part, nchunk, nsum, y, skip, max_iters);
-  if (p > 0)
-    hipLaunchKernelGGL(k_apply_psi, dim3(3 * p, ncols), dim3(kNodeSumThreads), 0, s, g, curve_id, p, x, ncols,
-                       y, skip, max_iters);
+  launch_pairs(g, apply_src4(part, g.N, ncols), g.x, g.y, g.N, x, ncols, chunk, part, skip, max_iters, cfg, grid,
+               s);
+  apply_tail(g, curve_id, hole_xy, p, lam, x, x, ncols, y, part, nchunk, nullptr, nullptr, skip, max_iters, s);
+}
+
+size_t corr_scratch_bytes(int N, int ncols) { return corr_layout(N, ncols).total; }
+
+// The bound of the correction image's pair sums: kCorrBoundScale u times the
+// per-node sums of e_ts max |d| (u = 2^-24).  (19.25 + 2 kCorrFlush) u = 51.25 u
+// is derived above; 64 leaves room.
+constexpr double kCorrBoundScale = 64.0;
+static_assert(kCorrBoundScale >= 19.25 + 2 * kCorrFlush, "bound scale below the derived constant");
+double corr_bound_scale() { return kCorrBoundScale * 0x1p-24; }
+
+double* corr_bound_rows(void* corr, int N, int ncols) {
+  return reinterpret_cast<double*>(static_cast<char*>(corr) + corr_layout(N, ncols).bt);
+}
+
+void launch_apply_refine(Geo g, const int* curve_id, const double* hole_xy, int p, double lam, const double* x,
+                         const double* dx, int ncols, double* y, double* part, void* corr, int* flag,
+                         int max_iters, int cfg, int which, hipStream_t s) {
+  if (ncols <= 0 || g.N <= 0) return;
+  if (!apply_config_valid(cfg, ncols)) cfg = apply_default_config(ncols);
+  const int chunk = apply_chunk_len(g.N);
+  const int nchunk = (g.N + chunk - 1) / chunk;
+  double4* src4 = apply_src4(part, g.N, ncols);
+  if (which != 1) {
+    const ApplyShape sh = kApplyShapes[cfg];
+    dim3 grid(blocks_for(g.N, kApplyThreads * sh.t), nchunk, blocks_for(ncols, sh.nc));
+    launch_pairs(g, src4, g.x, g.y, g.N, x, ncols, chunk, part, flag, max_iters, cfg, grid, s);
+  }
+  float *d32 = nullptr, *dmax = nullptr, *bpart = nullptr;
+  double* bt = nullptr;
+  if (corr) {
+    const CorrLayout L = corr_layout(g.N, ncols);
+    char* cb = static_cast<char*>(corr);
+    d32 = reinterpret_cast<float*>(cb + L.d32);
+    dmax = reinterpret_cast<float*>(cb + L.dmax);
+    bpart = reinterpret_cast<float*>(cb + L.bpart);
+    bt = reinterpret_cast<double*>(cb + L.bt);
+  } else {
+    which = 0;   // no scratch: the exact apply only
+  }
+  if (which != 0) {
+    const int ncb = (ncols + 15) / 16;
+    const int ntile = (g.N + kCorrTile - 1) / kCorrTile;
+    hipLaunchKernelGGL(k_pack_sources, dim3(blocks_for(g.N, kBlock)), dim3(kBlock), 0, s, g, src4);
+    hipLaunchKernelGGL(k_corr_prep, dim3(ntile, ncb), dim3(256), 0, s, dx, g.N, ncols, d32, dmax, flag,
+                       max_iters);
+    hipLaunchKernelGGL(k_apply_pairs32, dim3(blocks_for(g.N, kCorrTargets), nchunk, ncb), dim3(kCorrThreads), 0,
+                       s, src4, g.N, d32, dmax, ncols, chunk, part, bpart, flag, max_iters);
+  }
+  apply_tail(g, curve_id, hole_xy, p, lam, x, dx, ncols, y, part, nchunk, bpart, bt, flag, max_iters, s);
 }
 
 // ---- fixed device scratch of the allocation-free apply ------------------------

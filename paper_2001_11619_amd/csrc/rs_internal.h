@@ -182,17 +182,22 @@ void launch_dense_apply(const double* Zinv, int nz, const double* v, int ncols, 
 template <typename T>
 void launch_root_scatter(const double* sol, int ncols, const int* I0, int n0, T* c, hipStream_t s);
 void launch_fill(double* x, long long n, double v, hipStream_t s);
-void launch_refine_flag(const double* colsq, const double* fsq, int ncols, double tol, int max_iters,
-                        int* flag, hipStream_t s);
+// flag: 4 ints (converged, iterations, next residual updated, a pair dropped);
+// acc: per column, the accumulated rounding bound of updated residuals
+void launch_refine_flag(const double* colsq, const double* fsq, const double* bsq, double* acc, int ncols,
+                        double tol, int max_iters, int incr, double bscale, int* flag, hipStream_t s);
 void launch_accumulate_unless(const double* d, long long n, double* x, const int* flag, int max_iters,
                               hipStream_t s);
 void launch_set_ints(int* p, int n, int v, hipStream_t s);
 void launch_accumulate(const double* d, long long n, double* x, hipStream_t s);
 void launch_accumulate(const float* d, long long n, double* x, hipStream_t s);
-// part: residual_scratch_doubles(ncols) doubles
+// part: residual_scratch_doubles(ncols) doubles; flag (nullable): refinement
+// flags (an updated residual r - y when flag[2] = 1, bt its rounding bounds
+// per node); bsq receives the squared column norms of the bounds
 size_t residual_scratch_doubles(int ncols);
 void launch_residual(const double* f, int nf, const double* y, int nrows, int ncols, double* r,
-                     double* colsq, double* fsq, double* part, hipStream_t s);
+                     double* colsq, double* fsq, double* bsq, double* part, const int* flag, int max_iters,
+                     const double* bt, hipStream_t s);
 void launch_factor_to_float(const LevelBox* boxes, int nbox, const int* k_final, hipStream_t s);
 void launch_w_to_float(const SolveBox* boxes, int nbox, int p3, hipStream_t s);
 void launch_to_rows(const double* f, int ld, int nrows, int ncols, double* c, hipStream_t s);
@@ -214,6 +219,18 @@ void apply_config_name(int cfg, char* buf, int len);
 void launch_apply_operator(Geo g, const int* curve_id, const double* hole_xy, int p,
                            double lam, const double* x, int ncols, double* y,
                            double* part, const int* skip, int max_iters, int cfg, hipStream_t s);
+// The apply of one refinement iteration: the exact float64 apply of x, or the
+// float32 image of the correction dx (flag[2] = 1), chosen on the device; which
+// = -1 launches both (graph capture), 0 or 1 only that one.  corr:
+// corr_scratch_bytes(N, ncols) bytes; corr_bound_rows(corr, ...) the
+// per-node rounding bounds of the last image (N x ncols doubles), to be
+// scaled by corr_bound_scale().
+size_t corr_scratch_bytes(int N, int ncols);
+double* corr_bound_rows(void* corr, int N, int ncols);
+double corr_bound_scale();
+void launch_apply_refine(Geo g, const int* curve_id, const double* hole_xy, int p, double lam, const double* x,
+                         const double* dx, int ncols, double* y, double* part, void* corr, int* flag,
+                         int max_iters, int cfg, int which, hipStream_t s);
 // Velocity u = D mu + H lambda at nt target points (tx, ty); x, u rows layout
 // ((2N + 3p) x ncols and 2 nt x ncols); part: eval_scratch_doubles(N, nt, ncols).
 size_t eval_scratch_doubles(int N, int nt, int ncols);

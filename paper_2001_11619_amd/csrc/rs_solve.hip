@@ -325,21 +325,39 @@ __global__ void k_accumulate(const TI* d, long long n, double* x) {
 }
 
 // Refinement control on the device (lets the refinement iterations run as a
-// captured graph).  flag[0] = 1 once max_q sqrt(colsq[q] / fsq[q]) <= tol
-// (fsq = 0 counts as 1); flag[1] counts the corrections applied.  Per
+// captured graph).  flag[0] = 1 once the certified residual is small enough,
+// flag[1] counts the corrections applied, flag[2] = 1 when the next residual
+// is updated with a float32 correction image, flag[3] = 1 once a correction
+// image dropped a pair (the refinement then keeps to exact residuals).  Per
 // iteration: k_accumulate_unless (reads the flags), operator apply, residual,
-// then k_refine_flag (the only writer: counts the correction the iteration
-// applied, then tests the new residual).
-__global__ void k_refine_flag(const double* colsq, const double* fsq, int ncols, double tol,
-                              int max_iters, int* flag) {
+// then k_refine_flag (the only writer of flags 0-2: counts the correction the
+// iteration applied, then tests the new residual).
+//
+// Certificate: after an exact residual the computed norm is the residual's
+// norm (acc = 0); after an updated one the difference to the true residual is
+// at most acc, the sum of the updates' rounding bounds bscale ||bt||_2, so
+// column q passes when sqrt(colsq) + acc <= tol sqrt(fsq) (fsq = 0 counts as
+// 1).  Updates continue (incr = 1) while acc stays within a quarter of the
+// tolerance.
+__global__ void k_refine_flag(const double* colsq, const double* fsq, const double* bsq, double* acc,
+                              int ncols, double tol, int max_iters, int incr, double bscale, int* flag) {
   if (blockIdx.x != 0 || threadIdx.x != 0) return;
-  if (flag[0] == 0 && flag[1] < max_iters) flag[1] += 1;
+  if (flag[0] != 0 || flag[1] >= max_iters) return;   // the iteration was skipped
+  flag[1] += 1;
+  const bool upd = flag[2] == 1;
+  const bool dropped = flag[3] != 0;
+  bool next = incr != 0 && !dropped;
   double worst = 0.0;
   for (int q = 0; q < ncols; ++q) {
-    const double fq = fsq[q] > 0.0 ? fsq[q] : 1.0;
-    worst = fmax(worst, sqrt(colsq[q] / fq));
+    const double fq = fsq[q] > 0.0 ? sqrt(fsq[q]) : 1.0;
+    double a = 0.0;
+    if (upd) a = dropped ? INFINITY : acc[q] + bscale * sqrt(bsq[q]);
+    acc[q] = a;
+    worst = fmax(worst, (sqrt(colsq[q]) + a) / fq);
+    if (!(a <= 0.25 * tol * fq)) next = false;
   }
   flag[0] = worst <= tol ? 1 : 0;
+  flag[2] = next ? 1 : 0;
 }
 
 // x += d unless refinement has converged or used up its iterations.
@@ -355,43 +373,65 @@ __global__ void k_set_ints(int* p, int n, int v) {
   if (t < n) p[t] = v;
 }
 
-// r = [f; 0] - y and the squared column norms of r and f, in two passes of
-// fixed order: block (c, q) takes rows c chunk .. (c + 1) chunk - 1 of column q
-// and writes its sums to part[(q kResChunks + c) 2 + {0, 1}]; the second pass
-// adds each column's chunk sums in order.
+// r = [f; 0] - y (or, when the refinement flags ask for an update, r = r - y
+// with y the image of the correction) and the squared column norms of r and
+// f, and for an update of the rounding bounds bt (one per node, both rows),
+// in two passes of fixed order: block (c, q) takes rows c chunk .. (c + 1)
+// chunk - 1 of column q and writes its sums to part[(q kResChunks + c) 3 +
+// {0, 1, 2}]; the second pass adds each column's chunk sums in order.  A
+// skipped refinement iteration leaves r and the norms as they are.
 constexpr int kResChunks = 32;
+__device__ __forceinline__ int residual_mode(const int* flag, int max_iters) {
+  if (!flag) return 0;
+  if (flag[0] != 0 || flag[1] >= max_iters) return -1;
+  return flag[2] == 1 ? 1 : 0;
+}
 __global__ __launch_bounds__(kBlock) void k_residual1(const double* f, int nf, const double* y, int nrows,
-                                                     int ncols, double* r, double* part) {
+                                                     int ncols, double* r, double* part, const int* flag,
+                                                     int max_iters, const double* bt) {
+  const int md = residual_mode(flag, max_iters);
+  if (md < 0) return;
   constexpr int NW = kBlock / 64;
   __shared__ double red[NW];
   const int c = blockIdx.x, q = blockIdx.y;
   const int chunk = (nrows + kResChunks - 1) / kResChunks;
   const int i0 = c * chunk, i1 = min(nrows, i0 + chunk);
-  double sr = 0.0, sf = 0.0;
+  double sr = 0.0, sf = 0.0, sb = 0.0;
   for (int i = i0 + threadIdx.x; i < i1; i += kBlock) {
     const double fi = i < nf ? f[(size_t)i * ncols + q] : 0.0;
-    const double v = fi - y[(size_t)i * ncols + q];
-    r[(size_t)i * ncols + q] = v;
+    const size_t k = (size_t)i * ncols + q;
+    const double v = (md == 1 ? r[k] : fi) - y[k];
+    r[k] = v;
     sr += v * v;
     sf += fi * fi;
+    if (md == 1 && i < nf) {
+      const double b = bt[(size_t)(i >> 1) * ncols + q];
+      sb += b * b;
+    }
   }
   sr = block_sum(sr, red);
   sf = block_sum(sf, red);
+  sb = block_sum(sb, red);
   if (threadIdx.x == 0) {
-    part[((size_t)q * kResChunks + c) * 2] = sr;
-    part[((size_t)q * kResChunks + c) * 2 + 1] = sf;
+    part[((size_t)q * kResChunks + c) * 3] = sr;
+    part[((size_t)q * kResChunks + c) * 3 + 1] = sf;
+    part[((size_t)q * kResChunks + c) * 3 + 2] = sb;
   }
 }
-__global__ void k_residual2(const double* part, int ncols, double* colsq, double* fsq) {
+__global__ void k_residual2(const double* part, int ncols, double* colsq, double* fsq, double* bsq,
+                            const int* flag, int max_iters) {
+  if (residual_mode(flag, max_iters) < 0) return;
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= ncols) return;
-  double sr = 0.0, sf = 0.0;
+  double sr = 0.0, sf = 0.0, sb = 0.0;
   for (int c = 0; c < kResChunks; ++c) {
-    sr += part[((size_t)q * kResChunks + c) * 2];
-    sf += part[((size_t)q * kResChunks + c) * 2 + 1];
+    sr += part[((size_t)q * kResChunks + c) * 3];
+    sf += part[((size_t)q * kResChunks + c) * 3 + 1];
+    sb += part[((size_t)q * kResChunks + c) * 3 + 2];
   }
   colsq[q] = sr;
   fsq[q] = sf;
+  bsq[q] = sb;
 }
 
 // float copy of W (after the border stage) for the boxes whose solve reads
@@ -524,9 +564,10 @@ void launch_root_scatter(const double* sol, int ncols, const int* I0, int n0, T*
 }
 template void launch_root_scatter<double>(const double*, int, const int*, int, double*, hipStream_t);
 
-void launch_refine_flag(const double* colsq, const double* fsq, int ncols, double tol, int max_iters,
-                        int* flag, hipStream_t s) {
-  hipLaunchKernelGGL(k_refine_flag, dim3(1), dim3(64), 0, s, colsq, fsq, ncols, tol, max_iters, flag);
+void launch_refine_flag(const double* colsq, const double* fsq, const double* bsq, double* acc, int ncols,
+                        double tol, int max_iters, int incr, double bscale, int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_refine_flag, dim3(1), dim3(64), 0, s, colsq, fsq, bsq, acc, ncols, tol, max_iters, incr,
+                     bscale, flag);
 }
 
 void launch_accumulate_unless(const double* d, long long n, double* x, const int* flag, int max_iters,
@@ -551,13 +592,16 @@ void launch_accumulate(const float* d, long long n, double* x, hipStream_t s) {
   if (n) hipLaunchKernelGGL(k_accumulate<float>, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, d, n, x);
 }
 
-size_t residual_scratch_doubles(int ncols) { return 2 * (size_t)kResChunks * std::max(ncols, 1); }
+size_t residual_scratch_doubles(int ncols) { return 3 * (size_t)kResChunks * std::max(ncols, 1); }
 
 void launch_residual(const double* f, int nf, const double* y, int nrows, int ncols, double* r,
-                     double* colsq, double* fsq, double* part, hipStream_t s) {
+                     double* colsq, double* fsq, double* bsq, double* part, const int* flag, int max_iters,
+                     const double* bt, hipStream_t s) {
   if (ncols == 0) return;
-  hipLaunchKernelGGL(k_residual1, dim3(kResChunks, ncols), dim3(kBlock), 0, s, f, nf, y, nrows, ncols, r, part);
-  hipLaunchKernelGGL(k_residual2, dim3(blocks_for(ncols, 64)), dim3(64), 0, s, part, ncols, colsq, fsq);
+  hipLaunchKernelGGL(k_residual1, dim3(kResChunks, ncols), dim3(kBlock), 0, s, f, nf, y, nrows, ncols, r, part,
+                     flag, max_iters, bt);
+  hipLaunchKernelGGL(k_residual2, dim3(blocks_for(ncols, 64)), dim3(64), 0, s, part, ncols, colsq, fsq, bsq,
+                     flag, max_iters);
 }
 
 void launch_w_to_float(const SolveBox* boxes, int nbox, int p3, hipStream_t s) {

@@ -35,6 +35,7 @@ def test_default_params():
     assert p.n_proxy == 64 and p.proxy_ratio == 1.5 and p.rcond_min == 1e-12
     assert p.precision == 0 and p.refine_tol == 1e-8 and p.refine_max == 0
     assert p.has_root == 0 and p.solve_graph == 1 and p.mixed_rcond_min == 1e-4 and p.apply_shape == -1
+    assert p.refine_update == 1
 
 
 def _geom():
@@ -42,7 +43,7 @@ def _geom():
 
 
 @pytest.mark.parametrize("bad", ["nan_xy", "normal_len", "weight", "curve_id", "tol", "empty_hole",
-                                 "mixed_rcond"])
+                                 "mixed_rcond", "refine_update"])
 def test_invalid_input_rejected(bad):
     g = _geom()
     xy, nrm, w, kap, cid = g.xy.copy(), g.normal.copy(), g.weight.copy(), g.curvature.copy(), g.curve_id.copy()
@@ -59,6 +60,8 @@ def test_invalid_input_rejected(bad):
         kw["tol"] = -1.0
     elif bad == "mixed_rcond":
         kw["mixed_rcond_min"] = float("nan")
+    elif bad == "refine_update":
+        kw["refine_update"] = 2
     elif bad == "empty_hole":
         cid[cid == 1] = 0
         cid[0] = 2           # hole 1 has no nodes, hole 2 has one
