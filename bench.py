@@ -67,7 +67,11 @@ def run_batch(args, forms):
     """Many geometries: mixed precision, factored level-synchronously
     (rs_factor_batch) and solved interleaved (rs_solve_batch), 16 right-hand
     sides each, against the plain float64 path on the same geometries one
-    after another."""
+    after another.  The geometries go through in parts of at most
+    args.batch_chunk (device memory: about 20 KB per unknown while a part is
+    factored and solved); a step is every part's factor + solve, the timed
+    region the sum over the parts (each part's solvers are set up and warmed
+    up before its timed steps)."""
     import numpy as np
     import torch
 
@@ -75,43 +79,49 @@ def run_batch(args, forms):
     from workloads import boundary_data, exterior_forces_for_geometry
 
     nb, nrhs = args.batch_size, 16
+    chunk = max(1, min(nb, getattr(args, "batch_chunk", nb)))
     geoms = batch_geometries(nb)
     fs = [boundary_data(g, exterior_forces_for_geometry(g, nrhs, seed=100 + i)) for i, g in enumerate(geoms)]
     out = {}
     for form in forms:
         kw = dict(tol=args.tol_plain, precision=0) if form == "plain" else dict(tol=args.tol_mixed, precision=1)
-        t0 = time.perf_counter()
-        sv = [RSSolver.from_geometry(g, refine_max=20, refine_tol=1e-8, **kw) for g in geoms]
-        setup_ms = 1e3 * (time.perf_counter() - t0)
-        stream = torch.cuda.current_stream().cuda_stream
-        for s in sv:
-            s.set_stream(stream)
-        fd = [torch.tensor(np.ascontiguousarray(f.T), dtype=torch.float64, device="cuda") for f in fs]
-        xd = [torch.empty((nrhs, g.n_system), dtype=torch.float64, device="cuda") for g in geoms]
+        el, setup_ms, res = 0.0, 0.0, 0.0
+        for c0 in range(0, nb, chunk):
+            gs, fc = geoms[c0:c0 + chunk], fs[c0:c0 + chunk]
+            t0 = time.perf_counter()
+            sv = [RSSolver.from_geometry(g, refine_max=20, refine_tol=1e-8, **kw) for g in gs]
+            setup_ms += 1e3 * (time.perf_counter() - t0)
+            stream = torch.cuda.current_stream().cuda_stream
+            for s in sv:
+                s.set_stream(stream)
+            fd = [torch.tensor(np.ascontiguousarray(f.T), dtype=torch.float64, device="cuda") for f in fc]
+            xd = [torch.empty((nrhs, g.n_system), dtype=torch.float64, device="cuda") for g in gs]
 
-        def step():
-            if form == "plain":
-                for s, f_, x_ in zip(sv, fd, xd):
-                    s.factor()
-                    s.solve_dev(f_, x_)
-            else:
-                factor_batch(sv)
-                solve_batch(sv, fd, xd)
+            def step():
+                if form == "plain":
+                    for s, f_, x_ in zip(sv, fd, xd):
+                        s.factor()
+                        s.solve_dev(f_, x_)
+                else:
+                    factor_batch(sv)
+                    solve_batch(sv, fd, xd)
 
-        for _ in range(args.warmup):
-            step()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            step()
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        res = max(float(np.max(s.solve(f, residual=True)[1])) for s, f in zip(sv, fs))
+            for _ in range(args.warmup):
+                step()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                step()
+            torch.cuda.synchronize()
+            el += time.perf_counter() - t0
+            res = max([res] + [float(np.max(s.solve(f, residual=True)[1])) for s, f in zip(sv, fc)])
+            print("bench: batch %s, geometries %d..%d done (%.1f s timed so far)"
+                  % (form, c0, c0 + len(gs) - 1, el), file=sys.stderr, flush=True)
+            for s in sv:
+                s.close()
+            del sv, fd, xd
         out[form] = {"value": nb * nrhs * args.steps / el, "ms_per_step": 1e3 * el / args.steps,
-                     "setup_ms": setup_ms, "max_rel_residual": res}
-        for s in sv:
-            s.close()
-        del sv
+                     "setup_ms": setup_ms, "max_rel_residual": res, "parts": (nb + chunk - 1) // chunk}
     unknowns = [g.n_system for g in geoms]
     head = out[forms[0]]
     js = {
@@ -120,6 +130,7 @@ def run_batch(args, forms):
         "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64" if forms[0] == "mixed" else "f64", "data": "synthetic",
         "config": {"workload": "batch%d_of_512" % nb, "geometries": nb, "nrhs_each": nrhs,
+                   "geometries_per_launch": chunk,
                    "unknowns_min": min(unknowns), "unknowns_max": max(unknowns),
                    "unknowns_total": int(sum(unknowns)), "form": forms[0]},
         "max_rel_residual": head["max_rel_residual"], "setup_ms": head["setup_ms"],
@@ -515,6 +526,8 @@ def main():
     ap.add_argument("--batch-size", type=int, default=32,
                     help="geometries of the many-geometry line (0: leave it out)")
     ap.add_argument("--batch-steps", type=int, default=3)
+    ap.add_argument("--batch-chunk", type=int, default=128,
+                    help="geometries factored together in one level-synchronous batch (device memory)")
     ap.add_argument("--batch-tol-mixed", type=float, default=1e-7)
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="before the timed steps, one device copy of this many MiB (the reference "

@@ -1748,9 +1748,73 @@ void release_all_arenas(rs_ctx* c) {
   c->arenas.clear();
 }
 
+// The large level workspaces (ID matrices, R, A_BB, elimination scratch,
+// cooperation records: about 17 KB per unknown at the leaf level) are needed
+// only while a factorization runs.  They come from a per-device pool for the
+// duration of one factorization call and go back to it afterwards, so
+// factorizations that run one after another (single contexts, or batches
+// factored in parts) share one set per context of the largest call instead of
+// one per context.  The pool is never destroyed: its memory stays with the
+// process (no device frees run at exit).
+struct WorkSet {
+  DevBuf M, R, A, scr, coop;
+};
+struct WorkPool {
+  std::mutex mu;
+  std::map<int, std::vector<std::unique_ptr<WorkSet>>> free;
+};
+WorkPool& work_pool() {
+  static WorkPool* pool = new WorkPool;
+  return *pool;
+}
+void swap_buf(DevBuf& a, DevBuf& b) {
+  std::swap(a.p, b.p);
+  std::swap(a.bytes, b.bytes);
+}
+void swap_work(rs_ctx* c, WorkSet& w) {
+  swap_buf(c->ws_M, w.M);
+  swap_buf(c->ws_R, w.R);
+  swap_buf(c->ws_A, w.A);
+  swap_buf(c->ws_scr, w.scr);
+  swap_buf(c->ws_coop, w.coop);
+}
+struct WorkLease {
+  std::vector<rs_ctx*> cs;
+  std::vector<std::unique_ptr<WorkSet>> sets;
+  explicit WorkLease(const std::vector<rs_ctx*>& v) : cs(v) {
+    WorkPool& wp = work_pool();
+    std::lock_guard<std::mutex> lk(wp.mu);
+    for (rs_ctx* c : cs) {
+      auto& fl = wp.free[c->device];
+      std::unique_ptr<WorkSet> w;
+      if (!fl.empty()) {
+        w = std::move(fl.back());
+        fl.pop_back();
+      } else {
+        w = std::make_unique<WorkSet>();
+      }
+      swap_work(c, *w);
+      sets.push_back(std::move(w));
+    }
+  }
+  ~WorkLease() {
+    // the buffers go back only once the work that used them is done
+    for (rs_ctx* c : cs) (void)hipStreamSynchronize(c->stream);
+    for (rs_ctx* c : cs)
+      if (c->side_stream) (void)hipStreamSynchronize(c->side_stream);
+    WorkPool& wp = work_pool();
+    std::lock_guard<std::mutex> lk(wp.mu);
+    for (size_t i = 0; i < cs.size(); ++i) {
+      swap_work(cs[i], *sets[i]);
+      wp.free[cs[i]->device].push_back(std::move(sets[i]));
+    }
+  }
+};
+
 // Factor several contexts level-synchronously: every level is one launch per
 // kernel over the boxes of all contexts (a single context is the plain case).
 void do_factor_multi(std::vector<rs_ctx*>& cs) {
+  WorkLease lease(cs);
   auto t0 = std::chrono::steady_clock::now();
   const size_t nc = cs.size();
   for (rs_ctx* c : cs) c->level_done_set = false;
