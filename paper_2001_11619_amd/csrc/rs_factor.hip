@@ -868,21 +868,25 @@ __global__ __launch_bounds__(kBlock) void k_border_g(const int* ridx, int total_
 // returns at once when *status is set, so no pivot index of a failed panel is
 // ever used (the panel also leaves its unused entries as the identity).
 constexpr int kGJB = 32;
-static_assert(kBlock % kGJB == 0, "the panel update deals rows to kBlock / kGJB lanes");
+// threads of the panel kernel: every step of the panel is a pass over its
+// rows, so the panel's time is its column count times one pass
+constexpr int kPanelThreads = 1024;
+static_assert(kPanelThreads % kGJB == 0, "the panel update deals rows to kPanelThreads / kGJB lanes");
 
 // The panel (h x bb) is factored in LDS when it fits (in_lds != 0, dynamic
 // LDS of h * bb doubles), else in the global work array W.
 constexpr size_t kPanelLdsBytes = 136 * 1024;
 
-__global__ __launch_bounds__(kBlock) void k_gjb_panel(const double* A, int n, int k0, int bb,
-                                                      double* Wg, int* piv, double* Dinv,
-                                                      int* status, int in_lds) {
+__global__ __launch_bounds__(kPanelThreads) void k_gjb_panel(const double* A, int n, int k0, int bb,
+                                                              double* Wg, int* piv, double* Dinv,
+                                                              int* status, int in_lds) {
   extern __shared__ double wsh[];
-  constexpr int NW = kBlock / 64;
+  constexpr int NW = kPanelThreads / 64;
   __shared__ double red[NW];
   __shared__ int ired[NW];
   __shared__ double lu[kGJB][kGJB + 1];
   __shared__ double inv[kGJB][kGJB + 1];
+  __shared__ int spiv[kGJB];   // pivot rows, written out once at the end (see k_gjb_panel_reg)
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   if (*(volatile const int*)status) return;
   double* W = in_lds ? wsh : Wg;
@@ -890,7 +894,7 @@ __global__ __launch_bounds__(kBlock) void k_gjb_panel(const double* A, int n, in
   // a column (pivot search, scaling) hit distinct banks
   const int ldw = in_lds ? bb + 1 : bb;
   const int h = n - k0;
-  for (int t = tid; t < h * bb; t += kBlock) {
+  for (int t = tid; t < h * bb; t += kPanelThreads) {
     const int i = t / bb, c = t % bb;
     W[(size_t)i * ldw + c] = A[(size_t)(k0 + i) * n + k0 + c];
   }
@@ -913,7 +917,7 @@ __global__ __launch_bounds__(kBlock) void k_gjb_panel(const double* A, int n, in
     double best = -1.0;
     int bi = h;
     if (j == 0 || !fused) {
-      for (int i = j + tid; i < h; i += kBlock) {
+      for (int i = j + tid; i < h; i += kPanelThreads) {
         const double v = fabs(W[(size_t)i * ldw + j]);
         if (v > best) { best = v; bi = i; }
       }
@@ -931,14 +935,14 @@ __global__ __launch_bounds__(kBlock) void k_gjb_panel(const double* A, int n, in
       bi = 0xFFFF - (int)(key & 0xFFFF);
     }
     if (!(best > 0.0)) {
-      for (int jj = j + tid; jj < bb; jj += kBlock) piv[jj] = jj;
+      for (int jj = tid; jj < bb; jj += kPanelThreads) piv[jj] = jj < j ? spiv[jj] : jj;
       singular = true;
       break;
     }
     // pkey[(j + 1) & 1] was last read at the start of step j - 1
-    if (tid == 0) { piv[j] = bi; pkey[(j + 1) & 1] = 0ull; }
+    if (tid == 0) { spiv[j] = bi; pkey[(j + 1) & 1] = 0ull; }
     if (bi != j)
-      for (int c = tid; c < bb; c += kBlock) {
+      for (int c = tid; c < bb; c += kPanelThreads) {
         const double a = W[(size_t)j * ldw + c];
         W[(size_t)j * ldw + c] = W[(size_t)bi * ldw + c];
         W[(size_t)bi * ldw + c] = a;
@@ -947,11 +951,11 @@ __global__ __launch_bounds__(kBlock) void k_gjb_panel(const double* A, int n, in
     const double rd = 1.0 / W[(size_t)j * ldw + j];
     if (tid == 0) dsc[j] = rd;
     // trailing update of the panel: thread (row lane tid / 32, column j + 1 +
-    // tid % 32) takes every eighth row, with its entry of row j in a register;
-    // rows go in batches of 8 (all reads, then all writes), so the LDS round
-    // trips of a batch overlap
+    // tid % 32) takes every (kPanelThreads / 32)-th row, with its entry of row
+    // j in a register; rows go in batches of 8 (all reads, then all writes),
+    // so the LDS round trips of a batch overlap
     if (cc < bb - j - 1) {
-      constexpr int RL = kBlock / kGJB, RB = 8;
+      constexpr int RL = kPanelThreads / kGJB, RB = 8;
       const int c = j + 1 + cc;
       const double ujc = W[(size_t)j * ldw + c];
       unsigned long long kmax = 0ull;
@@ -984,7 +988,7 @@ __global__ __launch_bounds__(kBlock) void k_gjb_panel(const double* A, int n, in
   if (!singular) {
     // scale the L columns by their pivots' reciprocals
     for (int c = cc; c < bb; c += kGJB)
-      for (int i = c + 1 + rl; i < h; i += kBlock / kGJB) W[(size_t)i * ldw + c] *= dsc[c];
+      for (int i = c + 1 + rl; i < h; i += kPanelThreads / kGJB) W[(size_t)i * ldw + c] *= dsc[c];
     __syncthreads();
   }
   if (singular) {
@@ -992,7 +996,7 @@ __global__ __launch_bounds__(kBlock) void k_gjb_panel(const double* A, int n, in
     return;
   }
   // D = L U (first bb rows of W); D^{-1} = U^{-1} L^{-1}
-  for (int t = tid; t < bb * bb; t += kBlock) lu[t / bb][t % bb] = W[(size_t)(t / bb) * ldw + t % bb];
+  for (int t = tid; t < bb * bb; t += kPanelThreads) lu[t / bb][t % bb] = W[(size_t)(t / bb) * ldw + t % bb];
   __syncthreads();
   // columns of L^{-1} (unit lower) then U^{-1} applied: one thread per
   // column, which it builds in place in its column of inv
@@ -1010,7 +1014,122 @@ __global__ __launch_bounds__(kBlock) void k_gjb_panel(const double* A, int n, in
     }
   }
   __syncthreads();
-  for (int t = tid; t < bb * bb; t += kBlock) Dinv[t] = inv[t / bb][t % bb];
+  for (int t = tid; t < bb * bb; t += kPanelThreads) Dinv[t] = inv[t / bb][t % bb];
+  for (int t = tid; t < bb; t += kPanelThreads) piv[t] = spiv[t];
+}
+
+// The panel with its rows in registers: thread t holds row t of the h x bb
+// panel (h <= kPanelRegThreads, bb <= kGJB), so a step reads its multiplier
+// from its own registers and only the pivot row goes through LDS (a broadcast
+// read).  The row is kept rotated: after step j its registers hold columns
+// j + 1, j + 2, ... followed by its multipliers for columns 0 .. j, so the
+// column of a step is always register 0, the update of the remaining columns
+// is also the shift (one FMA per register; the pivot row goes out with zeros
+// where its multipliers sit), and a row interchange carries the multipliers
+// along.  Per step j: the largest |W[i][j]| over rows i >= j (ties to the
+// smaller row), the interchange of rows j and the pivot's row, then every
+// row below j takes W[i][c] -= l W[j][c] for c > j with l = W[i][j] / W[j][j].
+// The pivot row is final at its step and records its L and U entries in LDS.
+// Outputs as the LDS panel: the pivot rows and D^{-1} of D = L U.
+constexpr int kPanelRegThreads = 1024;
+
+__global__ __launch_bounds__(kPanelRegThreads) void k_gjb_panel_reg(const double* A, int n, int k0, int bb,
+                                                                     int* piv, double* Dinv, int* status) {
+  constexpr int NW = kPanelRegThreads / 64;
+  __shared__ double red[NW];
+  __shared__ int ired[NW];
+  __shared__ double prow[2][2 * kGJB];   // the pivot row of a step (by step parity), zero padded
+  __shared__ double srow[2][kGJB];       // the row it displaces
+  __shared__ double lu[kGJB][kGJB + 1];
+  __shared__ double inv[kGJB][kGJB + 1];
+  // pivot rows, written out once at the end: a global store inside the step
+  // loop would make every barrier wait for its completion
+  __shared__ int spiv[kGJB];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  if (*(volatile const int*)status) return;
+  const int h = n - k0;
+  double W[kGJB];
+#pragma unroll
+  for (int c = 0; c < kGJB; ++c) W[c] = (tid < h && c < bb) ? A[(size_t)(k0 + tid) * n + k0 + c] : 0.0;
+  for (int t = tid; t < 2 * 2 * kGJB; t += kPanelRegThreads) (&prow[0][0])[t] = 0.0;
+  __syncthreads();
+  for (int j = 0; j < bb; ++j) {
+    const int par = j & 1;
+    double best = -1.0;
+    int bi = h;
+    if (tid >= j && tid < h) arg_better(best, bi, fabs(W[0]), tid);
+    wave_argmax(best, bi);
+    if (lane == 0) { red[wid] = best; ired[wid] = bi; }
+    __syncthreads();
+    {
+      // all the waves' candidates loaded first, then compared without branches
+      double rv[NW];
+      int ri[NW];
+#pragma unroll
+      for (int w = 0; w < NW; ++w) { rv[w] = red[w]; ri[w] = ired[w]; }
+      best = rv[0];
+      bi = ri[0];
+#pragma unroll
+      for (int w = 1; w < NW; ++w) {
+        const bool take = rv[w] > best || (rv[w] == best && ri[w] < bi);
+        best = take ? rv[w] : best;
+        bi = take ? ri[w] : bi;
+      }
+    }
+    if (!(best > 0.0)) {
+      for (int jj = tid; jj < bb; jj += kPanelRegThreads) piv[jj] = jj < j ? spiv[jj] : jj;
+      if (tid == 0) *status = 1;
+      return;   // uniform: every thread saw the same best
+    }
+    if (tid == 0) spiv[j] = bi;
+    // interchange rows j and bi through LDS: prow is the pivot row's columns
+    // j .. 31 followed by its multipliers (L's row j)
+    if (tid == bi)
+#pragma unroll
+      for (int c = 0; c < kGJB; ++c) prow[par][c] = W[c];
+    if (tid == j)
+#pragma unroll
+      for (int c = 0; c < kGJB; ++c) srow[par][c] = W[c];
+    __syncthreads();
+    if (bi != j) {
+      if (tid == bi)
+#pragma unroll
+        for (int c = 0; c < kGJB; ++c) W[c] = srow[par][c];
+      if (tid == j)
+#pragma unroll
+        for (int c = 0; c < kGJB; ++c) W[c] = prow[par][c];
+    }
+    // the pivot row is U's row j (columns j .. bb - 1) and L's row j
+    // (multipliers for columns 0 .. j - 1)
+    if (tid < bb - j) lu[j][j + tid] = prow[par][tid];
+    if (tid < j) lu[j][tid] = prow[par][kGJB - j + tid];
+    if (tid > j && tid < h) {
+      const double l = W[0] / prow[par][0];
+      const int live = kGJB - j;   // registers 1 .. live - 1 are columns, the rest multipliers
+#pragma unroll
+      for (int c = 1; c < kGJB; ++c) W[c - 1] = fma(-l, c < live ? prow[par][c] : 0.0, W[c]);
+      W[kGJB - 1] = l;
+    }
+    // the next step writes the other parity; this one's reads are done
+    // before the next step's first barrier
+  }
+  __syncthreads();
+  if (tid < bb) {
+    const int c = tid;
+    for (int i = 0; i < bb; ++i) {
+      double sum = (i == c) ? 1.0 : 0.0;
+      for (int l = 0; l < i; ++l) sum -= lu[i][l] * inv[l][c];
+      inv[i][c] = sum;
+    }
+    for (int i = bb - 1; i >= 0; --i) {
+      double sum = inv[i][c];
+      for (int l = i + 1; l < bb; ++l) sum -= lu[i][l] * inv[l][c];
+      inv[i][c] = sum / lu[i][i];
+    }
+  }
+  __syncthreads();
+  for (int t = tid; t < bb * bb; t += kPanelRegThreads) Dinv[t] = inv[t / bb][t % bb];
+  for (int t = tid; t < bb; t += kPanelRegThreads) piv[t] = spiv[t];
 }
 
 // Row interchanges of this block over all columns; copy of the column block.
@@ -1080,6 +1199,42 @@ __global__ void k_gjb_update(double* A, int n, int k0, int bb, const double* Din
     v = A[t] - s;
   }
   A[t] = v;
+}
+
+// The same update with the rank-bb products on FP64 matrix cores: one wave
+// per 16 x 16 tile of A, acc = Cpanel[tile rows, :] (R or D^{-1})[:, tile
+// columns] in bb / 4 v_mfma_f64_16x16x4f64 (K padded with zeros), then the
+// element cases of the scalar kernel above.
+__global__ __launch_bounds__(kBlock) void k_gjb_update_mfma(double* A, int n, int k0, int bb, const double* Dinv,
+                                                           const double* R, const double* Cpanel,
+                                                           const int* status) {
+  if (*(volatile const int*)status) return;
+  const int lane = threadIdx.x & 63;
+  const int tn = (n + 15) >> 4;
+  const int t = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  if (t >= tn * tn) return;
+  const int i0 = (t / tn) << 4, j0 = (t % tn) << 4;
+  const int r16 = lane & 15, kq = lane >> 4;
+  const int ia = i0 + r16, jb = j0 + r16;
+  const bool bk = jb >= k0 && jb < k0 + bb;
+  dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int l0 = 0; l0 < bb; l0 += 4) {
+    const int l = l0 + kq;
+    const double a = (ia < n && l < bb) ? Cpanel[(size_t)ia * bb + l] : 0.0;
+    const double b = (jb < n && l < bb) ? (bk ? Dinv[l * bb + (jb - k0)] : R[(size_t)l * n + jb]) : 0.0;
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int i = i0 + 4 * q + kq, c = j0 + r16;   // result lane layout of the f64 MFMA
+    if (i >= n || c >= n) continue;
+    const bool ik = i >= k0 && i < k0 + bb, ck = c >= k0 && c < k0 + bb;
+    double v;
+    if (ik) v = ck ? Dinv[(i - k0) * bb + (c - k0)] : R[(size_t)(i - k0) * n + c];
+    else if (ck) v = -acc[q];
+    else v = A[(size_t)i * n + c] - acc[q];
+    A[(size_t)i * n + c] = v;
+  }
 }
 
 // out[:, rowperm[i]] = A[:, i]  (undo the row permutation of the input)
@@ -1191,19 +1346,26 @@ void launch_gj_blocked(double* A, int n, double* Ainv, double* work, int* iwork,
     // stay in global memory); the blocking depends on n only
     const int h = n - k0;
     int bb = std::min(kGJB, h);
-    while (bb > 8 && (size_t)h * (bb + 1) * sizeof(double) > kPanelLdsBytes) --bb;
-    const size_t pbytes = (size_t)h * (bb + 1) * sizeof(double);
-    const int in_lds = pbytes <= kPanelLdsBytes ? 1 : 0;
-    hipLaunchKernelGGL(k_gjb_panel, dim3(1), dim3(kBlock), in_lds ? pbytes : 0, s, A, n, k0, bb, W, piv,
-                       Dinv, status, in_lds);
+    if (h <= kPanelRegThreads) {
+      // rows in registers (one per thread): full-width panels
+      hipLaunchKernelGGL(k_gjb_panel_reg, dim3(1), dim3(kPanelRegThreads), 0, s, A, n, k0, bb, piv, Dinv,
+                         status);
+    } else {
+      while (bb > 8 && (size_t)h * (bb + 1) * sizeof(double) > kPanelLdsBytes) --bb;
+      const size_t pbytes = (size_t)h * (bb + 1) * sizeof(double);
+      const int in_lds = pbytes <= kPanelLdsBytes ? 1 : 0;
+      hipLaunchKernelGGL(k_gjb_panel, dim3(1), dim3(kPanelThreads), in_lds ? pbytes : 0, s, A, n, k0, bb, W,
+                         piv, Dinv, status, in_lds);
+    }
     hipLaunchKernelGGL(k_gjb_swap, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, A, n, k0, bb,
                        piv, rowperm, status);
     hipLaunchKernelGGL(k_gjb_copycol, dim3(blocks_for((long long)n * bb, kBlock)), dim3(kBlock), 0,
                        s, A, n, k0, bb, Cp, status);
     hipLaunchKernelGGL(k_gjb_rows, dim3(blocks_for((long long)bb * n, kBlock)), dim3(kBlock), 0, s,
                        A, n, k0, bb, Dinv, R, status);
-    hipLaunchKernelGGL(k_gjb_update, dim3(blocks_for(nn, kBlock)), dim3(kBlock), 0, s, A, n, k0, bb,
-                       Dinv, R, Cp, status);
+    const long long tiles = (long long)((n + 15) / 16) * ((n + 15) / 16);
+    hipLaunchKernelGGL(k_gjb_update_mfma, dim3(blocks_for(tiles, kBlock / 64)), dim3(kBlock), 0, s, A, n, k0,
+                       bb, Dinv, R, Cp, status);
     k0 += bb;
   }
   hipLaunchKernelGGL(k_gjb_unpermute, dim3(blocks_for(nn, kBlock)), dim3(kBlock), 0, s, A, n,

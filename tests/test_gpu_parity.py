@@ -263,10 +263,11 @@ def test_wider_proxy_circle(ratio):
     assert same == total
 
 
-@pytest.mark.parametrize("n", [1, 31, 33, 694, 1000])
+@pytest.mark.parametrize("n", [1, 31, 33, 694, 1000, 1300])
 def test_dense_inverse_matches_numpy(n):
     """The root system's blocked Gauss-Jordan inverse (one and several pivot
-    blocks of 32, ragged last block): equal to LAPACK's inverse to rounding on a
+    blocks of 32, ragged last block; panels of at most 1024 rows in registers,
+    taller ones (n = 1300) in LDS): equal to LAPACK's inverse to rounding on a
     well-conditioned matrix."""
     g = workload_small(seed=11, n_outer=64, n_holes=1, nodes_per_hole=32, radius=3.0)
     s = _solver(g, leaf_size=16)
@@ -278,21 +279,39 @@ def test_dense_inverse_matches_numpy(n):
     assert np.linalg.norm(a @ ai - np.eye(n)) <= 1e-12 * np.sqrt(n)
 
 
-def test_dense_inverse_singular_panel_stops_cleanly():
+@pytest.mark.parametrize("n", [100, 694, 1300])
+def test_dense_inverse_permuted_rows(n):
+    """Rows of a diagonally dominant matrix shuffled: every pivot is found far
+    from the diagonal, so rows move into each pivot block from below with the
+    multipliers of the earlier columns (register panels up to 1024 rows, LDS
+    panels above)."""
+    g = workload_small(seed=11, n_outer=64, n_holes=1, nodes_per_hole=32, radius=3.0)
+    s = _solver(g, leaf_size=16)
+    rng = np.random.default_rng(n + 1)
+    a = rng.standard_normal((n, n)) + 2.0 * np.sqrt(n) * np.eye(n)
+    a = a[rng.permutation(n)]
+    ai = s.dense_inverse(a)
+    ref = np.linalg.inv(a)
+    assert np.linalg.norm(ai - ref) <= 1e-12 * np.linalg.norm(ref)
+    assert np.linalg.norm(a @ ai - np.eye(n)) <= 1e-12 * np.sqrt(n)
+
+
+@pytest.mark.parametrize("n,zero_col", [(694, 100), (1100, 40)])
+def test_dense_inverse_singular_panel_stops_cleanly(n, zero_col):
     """A pivot column with no nonzero candidate in a middle block is reported
-    as RS_ERR_SINGULAR, and the context keeps working.  The block before it
-    takes its pivots from the last rows, so any later use of that block's
-    pivot indices would address rows past the end of the matrix."""
+    as RS_ERR_SINGULAR, and the context keeps working (in a register panel,
+    n = 694, and in an LDS panel, n = 1100).  The block before it takes its
+    pivots from the last rows, so any later use of that block's pivot indices
+    would address rows past the end of the matrix."""
     from paper_2001_11619_amd import RSError
 
     g = workload_small(seed=11, n_outer=64, n_holes=1, nodes_per_hole=32, radius=3.0)
     s = _solver(g, leaf_size=16)
-    n = 694
     rng = np.random.default_rng(3)
     a = np.eye(n) + 1e-3 * rng.standard_normal((n, n))
     for j in range(32):
-        a[n - 32 + j, 64 + j] = 10.0
-    a[:, 100] = 0.0
+        a[n - 32 + j, zero_col - 36 + j] = 10.0
+    a[:, zero_col] = 0.0
     with pytest.raises(RSError) as e:
         s.dense_inverse(a)
     assert e.value.name == "RS_ERR_SINGULAR"
