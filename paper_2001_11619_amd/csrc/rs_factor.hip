@@ -1018,100 +1018,113 @@ __global__ __launch_bounds__(kPanelThreads) void k_gjb_panel(const double* A, in
   for (int t = tid; t < bb; t += kPanelThreads) piv[t] = spiv[t];
 }
 
-// The panel with its rows in registers: thread t holds row t of the h x bb
-// panel (h <= kPanelRegThreads, bb <= kGJB), so a step reads its multiplier
-// from its own registers and only the pivot row goes through LDS (a broadcast
-// read).  The row is kept rotated: after step j its registers hold columns
-// j + 1, j + 2, ... followed by its multipliers for columns 0 .. j, so the
-// column of a step is always register 0, the update of the remaining columns
-// is also the shift (one FMA per register; the pivot row goes out with zeros
-// where its multipliers sit), and a row interchange carries the multipliers
-// along.  Per step j: the largest |W[i][j]| over rows i >= j (ties to the
-// smaller row), the interchange of rows j and the pivot's row, then every
-// row below j takes W[i][c] -= l W[j][c] for c > j with l = W[i][j] / W[j][j].
-// The pivot row is final at its step and records its L and U entries in LDS.
-// Outputs as the LDS panel: the pivot rows and D^{-1} of D = L U.
-constexpr int kPanelRegThreads = 1024;
-
-__global__ __launch_bounds__(kPanelRegThreads) void k_gjb_panel_reg(const double* A, int n, int k0, int bb,
-                                                                     int* piv, double* Dinv, int* status) {
-  constexpr int NW = kPanelRegThreads / 64;
-  __shared__ double red[NW];
-  __shared__ int ired[NW];
-  __shared__ double prow[2][2 * kGJB];   // the pivot row of a step (by step parity), zero padded
-  __shared__ double srow[2][kGJB];       // the row it displaces
+// The panel with its rows in registers: thread t holds rows t + NT u (u < RU)
+// of the h x bb panel (h <= NT RU, bb <= kGJB), so a step reads its
+// multipliers from its own registers.  A row is kept rotated: after step j its
+// registers hold columns j + 1, j + 2, ... followed by its multipliers for
+// columns 0 .. j, so the column of a step is always register 0, the update of
+// the remaining columns is also the shift (one FMA per register), and a row
+// interchange carries the multipliers along.  One barrier per step: every
+// wave publishes its best candidate row (the largest |W[i][j]| over its rows
+// i >= j, ties to the smaller row) with its value, and the row to be
+// displaced (row j) is published too; after the barrier every thread picks
+// the pivot among the candidates and reads the pivot row from LDS, rows j and
+// the pivot's trade places, and every row below j takes W[i][c] -= l W[j][c]
+// for c > j with l = W[i][j] / W[j][j].  The pivot row is final at its step
+// and records its L and U entries in LDS.  Outputs as the LDS panel: the
+// pivot rows and D^{-1} of the pivot block D = L U.
+template <int NT, int RU>
+__global__ __launch_bounds__(NT) void k_gjb_panel_reg(const double* A, int n, int k0, int bb, int* piv,
+                                                       double* Dinv, int* status) {
+  constexpr int NW = NT / 64;
+  __shared__ double cval[2][NW];
+  __shared__ int cidx[2][NW];
+  __shared__ double cand[2][NW][kGJB];   // each wave's candidate row (by step parity)
+  __shared__ double srow[2][kGJB];        // row j before the interchange
   __shared__ double lu[kGJB][kGJB + 1];
   __shared__ double inv[kGJB][kGJB + 1];
-  // pivot rows, written out once at the end: a global store inside the step
-  // loop would make every barrier wait for its completion
-  __shared__ int spiv[kGJB];
+  __shared__ int spiv[kGJB];              // pivot rows, written out at the end
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   if (*(volatile const int*)status) return;
   const int h = n - k0;
-  double W[kGJB];
+  double W[RU][kGJB];
 #pragma unroll
-  for (int c = 0; c < kGJB; ++c) W[c] = (tid < h && c < bb) ? A[(size_t)(k0 + tid) * n + k0 + c] : 0.0;
-  for (int t = tid; t < 2 * 2 * kGJB; t += kPanelRegThreads) (&prow[0][0])[t] = 0.0;
-  __syncthreads();
+  for (int u = 0; u < RU; ++u) {
+    const int i = tid + NT * u;
+#pragma unroll
+    for (int c = 0; c < kGJB; ++c) W[u][c] = (i < h && c < bb) ? A[(size_t)(k0 + i) * n + k0 + c] : 0.0;
+  }
   for (int j = 0; j < bb; ++j) {
     const int par = j & 1;
+    // this wave's candidate
     double best = -1.0;
     int bi = h;
-    if (tid >= j && tid < h) arg_better(best, bi, fabs(W[0]), tid);
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+      const int i = tid + NT * u;
+      if (i >= j && i < h) arg_better(best, bi, fabs(W[u][0]), i);
+    }
     wave_argmax(best, bi);
-    if (lane == 0) { red[wid] = best; ired[wid] = bi; }
-    __syncthreads();
-    {
-      // all the waves' candidates loaded first, then compared without branches
-      double rv[NW];
-      int ri[NW];
+    if (bi < h && tid == bi % NT) {
+      // the winner publishes its row
+      const int ub = bi / NT;
 #pragma unroll
-      for (int w = 0; w < NW; ++w) { rv[w] = red[w]; ri[w] = ired[w]; }
-      best = rv[0];
-      bi = ri[0];
+      for (int u = 0; u < RU; ++u)
+        if (u == ub)
 #pragma unroll
-      for (int w = 1; w < NW; ++w) {
-        const bool take = rv[w] > best || (rv[w] == best && ri[w] < bi);
-        best = take ? rv[w] : best;
-        bi = take ? ri[w] : bi;
-      }
+          for (int c = 0; c < kGJB; ++c) cand[par][wid][c] = W[u][c];
     }
+    if (lane == 0) { cval[par][wid] = best; cidx[par][wid] = bi; }
+    if (tid == j % NT) {
+#pragma unroll
+      for (int u = 0; u < RU; ++u)
+        if (u == j / NT)
+#pragma unroll
+          for (int c = 0; c < kGJB; ++c) srow[par][c] = W[u][c];
+    }
+    __syncthreads();
+    // the pivot among the waves' candidates: lane w of every wave takes wave
+    // w's, and the wave-wide argmax gives all threads the same pivot
+    best = lane < NW ? cval[par][lane] : -1.0;
+    bi = lane < NW ? cidx[par][lane] : h;
+    wave_argmax(best, bi);
     if (!(best > 0.0)) {
-      for (int jj = tid; jj < bb; jj += kPanelRegThreads) piv[jj] = jj < j ? spiv[jj] : jj;
+      for (int jj = tid; jj < bb; jj += NT) piv[jj] = jj < j ? spiv[jj] : jj;
       if (tid == 0) *status = 1;
-      return;   // uniform: every thread saw the same best
+      return;   // uniform: every thread saw the same candidates
     }
+    const double* prow = cand[par][(bi % NT) >> 6];   // published by the wave holding row bi
     if (tid == 0) spiv[j] = bi;
-    // interchange rows j and bi through LDS: prow is the pivot row's columns
-    // j .. 31 followed by its multipliers (L's row j)
-    if (tid == bi)
-#pragma unroll
-      for (int c = 0; c < kGJB; ++c) prow[par][c] = W[c];
-    if (tid == j)
-#pragma unroll
-      for (int c = 0; c < kGJB; ++c) srow[par][c] = W[c];
-    __syncthreads();
+    // rows j and bi trade places (the pivot row is prow, row j is srow)
     if (bi != j) {
-      if (tid == bi)
 #pragma unroll
-        for (int c = 0; c < kGJB; ++c) W[c] = srow[par][c];
-      if (tid == j)
+      for (int u = 0; u < RU; ++u) {
+        if (tid + NT * u == bi)
 #pragma unroll
-        for (int c = 0; c < kGJB; ++c) W[c] = prow[par][c];
+          for (int c = 0; c < kGJB; ++c) W[u][c] = srow[par][c];
+        if (tid + NT * u == j)
+#pragma unroll
+          for (int c = 0; c < kGJB; ++c) W[u][c] = prow[c];
+      }
     }
     // the pivot row is U's row j (columns j .. bb - 1) and L's row j
     // (multipliers for columns 0 .. j - 1)
-    if (tid < bb - j) lu[j][j + tid] = prow[par][tid];
-    if (tid < j) lu[j][tid] = prow[par][kGJB - j + tid];
-    if (tid > j && tid < h) {
-      const double l = W[0] / prow[par][0];
-      const int live = kGJB - j;   // registers 1 .. live - 1 are columns, the rest multipliers
+    if (tid < bb - j) lu[j][j + tid] = prow[tid];
+    if (tid < j) lu[j][tid] = prow[kGJB - j + tid];
+    const double rp = 1.0 / prow[0];
+    const int live = kGJB - j;   // registers 1 .. live - 1 are columns, the rest multipliers
 #pragma unroll
-      for (int c = 1; c < kGJB; ++c) W[c - 1] = fma(-l, c < live ? prow[par][c] : 0.0, W[c]);
-      W[kGJB - 1] = l;
+    for (int u = 0; u < RU; ++u) {
+      const int i = tid + NT * u;
+      if (i > j && i < h) {
+        const double l = W[u][0] * rp;
+#pragma unroll
+        for (int c = 1; c < kGJB; ++c) W[u][c - 1] = fma(-l, c < live ? prow[c] : 0.0, W[u][c]);
+        W[u][kGJB - 1] = l;
+      }
     }
-    // the next step writes the other parity; this one's reads are done
-    // before the next step's first barrier
+    // the next step publishes into the other parity; this step's reads end
+    // before the next step's barrier
   }
   __syncthreads();
   if (tid < bb) {
@@ -1128,8 +1141,8 @@ __global__ __launch_bounds__(kPanelRegThreads) void k_gjb_panel_reg(const double
     }
   }
   __syncthreads();
-  for (int t = tid; t < bb * bb; t += kPanelRegThreads) Dinv[t] = inv[t / bb][t % bb];
-  for (int t = tid; t < bb; t += kPanelRegThreads) piv[t] = spiv[t];
+  for (int t = tid; t < bb * bb; t += NT) Dinv[t] = inv[t / bb][t % bb];
+  for (int t = tid; t < bb; t += NT) piv[t] = spiv[t];
 }
 
 // Row interchanges of this block over all columns; copy of the column block.
@@ -1346,10 +1359,11 @@ void launch_gj_blocked(double* A, int n, double* Ainv, double* work, int* iwork,
     // stay in global memory); the blocking depends on n only
     const int h = n - k0;
     int bb = std::min(kGJB, h);
-    if (h <= kPanelRegThreads) {
-      // rows in registers (one per thread): full-width panels
-      hipLaunchKernelGGL(k_gjb_panel_reg, dim3(1), dim3(kPanelRegThreads), 0, s, A, n, k0, bb, piv, Dinv,
-                         status);
+    if (h <= 1024) {
+      // rows in registers: full-width panels
+      hipLaunchKernelGGL((k_gjb_panel_reg<1024, 1>), dim3(1), dim3(1024), 0, s, A, n, k0, bb, piv, Dinv, status);
+    } else if (h <= 1536) {
+      hipLaunchKernelGGL((k_gjb_panel_reg<512, 3>), dim3(1), dim3(512), 0, s, A, n, k0, bb, piv, Dinv, status);
     } else {
       while (bb > 8 && (size_t)h * (bb + 1) * sizeof(double) > kPanelLdsBytes) --bb;
       const size_t pbytes = (size_t)h * (bb + 1) * sizeof(double);
