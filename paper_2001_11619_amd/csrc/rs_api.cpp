@@ -10,6 +10,7 @@
 #include "rs_internal.h"
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -408,205 +409,6 @@ void resolve_timers(rs_ctx* c) {
   c->pending.swap(keep);
 }
 
-// Leaf unknowns and the near-box lists of every box (static for a tree).  A
-// box is listed when the distance from the compressed box's centre to its
-// square is at most the proxy radius (with a relative margin of 1e-9, so that
-// rounding in box centres never drops a box whose points may pass the strict
-// inside test).
-void build_neighbors(rs_ctx* c) {
-  std::vector<std::unordered_map<long long, int>> cells(c->L + 1);
-  for (size_t bi = 0; bi < c->boxes.size(); ++bi) {
-    const Box& B = c->boxes[bi];
-    cells[B.level][key2(B.ix, B.iy)] = (int)bi;
-  }
-  const double ratio = c->prm.proxy_ratio;
-  auto near = [](const Box& B, const Box& Q, double rp) {
-    const double h = 0.5 * Q.side;
-    const double ex = std::max(0.0, std::fabs(B.cx - Q.cx) - h);
-    const double ey = std::max(0.0, std::fabs(B.cy - Q.cy) - h);
-    return ex * ex + ey * ey <= rp * rp * (1.0 + 1e-9);
-  };
-  for (size_t bi = 0; bi < c->boxes.size(); ++bi) {
-    Box& B = c->boxes[bi];
-    B.dofs.clear();
-    B.near_same.clear();
-    B.near_leaf.clear();
-    if (B.leaf()) {
-      B.dofs.reserve(2 * B.nodes.size());
-      for (int j : B.nodes) {
-        B.dofs.push_back(2 * j);
-        B.dofs.push_back(2 * j + 1);
-      }
-      std::sort(B.dofs.begin(), B.dofs.end());
-    }
-    if (B.level == 0) continue;
-    const int l = B.level;
-    const double rp = ratio * B.side;
-    const long long D = (long long)std::floor(ratio + 0.5) + 1;
-    for (long long dx = -D; dx <= D; ++dx)
-      for (long long dy = -D; dy <= D; ++dy) {
-        if (dx == 0 && dy == 0) continue;
-        auto it = cells[l].find(key2(B.ix + dx, B.iy + dy));
-        if (it != cells[l].end() && near(B, c->boxes[it->second], rp)) B.near_same.push_back(it->second);
-      }
-    for (int lc = 0; lc < l; ++lc) {
-      const long long ax = B.ix >> (l - lc), ay = B.iy >> (l - lc);
-      const double sc = std::ldexp(B.side, l - lc);
-      const long long Dc = (long long)std::ceil(rp / sc) + 1;
-      for (long long dx = -Dc; dx <= Dc; ++dx)
-        for (long long dy = -Dc; dy <= Dc; ++dy) {
-          auto it = cells[lc].find(key2(ax + dx, ay + dy));
-          if (it == cells[lc].end()) continue;
-          const Box& Q = c->boxes[it->second];
-          if (Q.leaf() && near(B, Q, rp)) B.near_leaf.push_back(it->second);
-        }
-    }
-  }
-}
-
-void build_tree(rs_ctx* c) {
-  c->boxes.clear();
-  Box root;
-  if (c->prm.has_root) {
-    root.cx = c->prm.root[0];
-    root.cy = c->prm.root[1];
-    root.side = c->prm.root[2];
-  } else {
-    double xmin = c->x[0], xmax = c->x[0], ymin = c->y[0], ymax = c->y[0];
-    for (int i = 1; i < c->N; ++i) {
-      xmin = std::min(xmin, c->x[i]);
-      xmax = std::max(xmax, c->x[i]);
-      ymin = std::min(ymin, c->y[i]);
-      ymax = std::max(ymax, c->y[i]);
-    }
-    root.cx = 0.5 * (xmin + xmax);
-    root.cy = 0.5 * (ymin + ymax);
-    root.side = (1.0 + std::ldexp(1.0, -20)) * std::max(xmax - xmin, ymax - ymin);
-    if (root.side == 0.0) root.side = 1.0;
-  }
-  root.nodes.resize(c->N);
-  for (int i = 0; i < c->N; ++i) root.nodes[i] = i;
-  c->root_cx = root.cx;
-  c->root_cy = root.cy;
-  c->root_side = root.side;
-  c->boxes.push_back(std::move(root));
-  size_t head = 0;
-  const int leaf = c->prm.leaf_size;
-  while (head < c->boxes.size()) {
-    const size_t bi = head++;
-    if ((int)c->boxes[bi].nodes.size() <= leaf) continue;
-    if (c->boxes[bi].level >= kMaxDepth)
-      throw RsError{RS_ERR_ARG, "quadtree deeper than 48 levels (coincident nodes?)"};
-    const double cx = c->boxes[bi].cx, cy = c->boxes[bi].cy, side = c->boxes[bi].side;
-    std::vector<int> part[4];
-    for (int j : c->boxes[bi].nodes) {
-      const int q = (c->x[j] >= cx ? 1 : 0) + 2 * (c->y[j] >= cy ? 1 : 0);
-      part[q].push_back(j);
-    }
-    const double h = side / 4.0;
-    for (int q = 0; q < 4; ++q) {
-      if (part[q].empty()) continue;
-      Box ch;
-      ch.level = c->boxes[bi].level + 1;
-      ch.cx = (q % 2 == 0) ? cx - h : cx + h;
-      ch.cy = (q < 2) ? cy - h : cy + h;
-      ch.side = side / 2.0;
-      ch.ix = 2 * c->boxes[bi].ix + (q & 1);
-      ch.iy = 2 * c->boxes[bi].iy + (q >> 1);
-      ch.parent = (int)bi;
-      ch.nodes = std::move(part[q]);
-      const int id = (int)c->boxes.size();
-      c->boxes[bi].child[c->boxes[bi].nchild++] = id;
-      c->boxes.push_back(std::move(ch));
-    }
-  }
-  c->L = 0;
-  for (const Box& b : c->boxes) c->L = std::max(c->L, b.level);
-  build_neighbors(c);
-}
-
-std::vector<int> skeleton_of(const BoxFac& f) {
-  std::vector<int> s(f.k);
-  for (int i = 0; i < f.k; ++i) s[i] = f.I[f.perm[i]];
-  return s;
-}
-
-std::vector<int> redundant_of(const BoxFac& f) {
-  std::vector<int> r(f.n - f.k);
-  for (int i = f.k; i < f.n; ++i) r[i - f.k] = f.I[f.perm[i]];
-  return r;
-}
-
-// Unknowns of box b and, for a parent, where each one sits in its child's X_SS.
-void box_unknowns(const rs_ctx* c, int b, std::vector<int>& I, std::vector<ChildSrc>* src) {
-  const Box& B = c->boxes[b];
-  I.clear();
-  if (src) src->clear();
-  if (B.leaf()) {
-    I = B.dofs;
-    return;
-  }
-  struct E { int dof; int child; int idx; };
-  std::vector<E> ents;
-  for (int q = 0; q < B.nchild; ++q) {
-    const int ch = B.child[q];
-    const BoxFac& f = c->fac[ch];
-    for (int i = 0; i < f.k; ++i) ents.push_back({f.I[f.perm[i]], ch, i});
-  }
-  std::sort(ents.begin(), ents.end(), [](const E& a, const E& b2) { return a.dof < b2.dof; });
-  I.resize(ents.size());
-  if (src) src->resize(ents.size());
-  for (size_t i = 0; i < ents.size(); ++i) {
-    I[i] = ents[i].dof;
-    if (src) {
-      const BoxFac& f = c->fac[ents[i].child];
-      (*src)[i] = ChildSrc{f.Xss, ents[i].idx, f.k, ents[i].child, 0};
-    }
-  }
-}
-
-double seconds_since(std::chrono::steady_clock::time_point t0) {
-  return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-}
-
-// Updating rule (Section 2.8): a box is recompressed when an input of its
-// compression changed.  Leaf: new box, different node set, or a moved node.
-// Parent: new box, different children, or a recompressed child.  Any box: a
-// different near field F_int or a moved node in it.  Otherwise the stored
-// factors are exactly those a fresh factorization would compute.
-bool compress_needed(const rs_ctx* c, int b, const std::vector<int>& F) {
-  const OldState& O = *c->old;
-  const Box& B = c->boxes[b];
-  auto it = O.by_key.find(BoxKey{B.level, B.ix, B.iy});
-  if (it == O.by_key.end()) return true;
-  const Box& OB = O.boxes[it->second];
-  const BoxFac& OF = O.fac[it->second];
-  if (!OF.active || OB.leaf() != B.leaf()) return true;
-  if (B.leaf()) {
-    if (OB.nodes != B.nodes) return true;
-    for (int j : B.nodes)
-      if (O.moved[j]) return true;
-  } else {
-    std::vector<BoxKey> ok, nk;
-    for (int q = 0; q < OB.nchild; ++q) {
-      const Box& C = O.boxes[OB.child[q]];
-      ok.emplace_back(C.level, C.ix, C.iy);
-    }
-    for (int q = 0; q < B.nchild; ++q) {
-      const Box& C = c->boxes[B.child[q]];
-      nk.emplace_back(C.level, C.ix, C.iy);
-      if (c->recomputed[B.child[q]]) return true;
-    }
-    std::sort(ok.begin(), ok.end());
-    std::sort(nk.begin(), nk.end());
-    if (ok != nk) return true;
-  }
-  if (F != OF.fint) return true;
-  for (int d : F)
-    if (O.moved[d >> 1]) return true;
-  return false;
-}
-
 // Process-wide pool of host threads for the per-box host work of a level
 // (near fields, unknown lists).  run(n, f) calls f(i) for every i < n, the
 // caller taking part; small n runs on the caller alone.  Calls from several
@@ -697,6 +499,220 @@ class HostPool {
   std::atomic<bool> stop_{false};
   std::atomic<int> next_{0};
 };
+
+// Leaf unknowns and the near-box lists of every box (static for a tree).  A
+// box is listed when the distance from the compressed box's centre to its
+// square is at most the proxy radius (with a relative margin of 1e-9, so that
+// rounding in box centres never drops a box whose points may pass the strict
+// inside test).
+void build_neighbors(rs_ctx* c) {
+  std::vector<std::unordered_map<long long, int>> cells(c->L + 1);
+  for (size_t bi = 0; bi < c->boxes.size(); ++bi) {
+    const Box& B = c->boxes[bi];
+    cells[B.level][key2(B.ix, B.iy)] = (int)bi;
+  }
+  const double ratio = c->prm.proxy_ratio;
+  auto near = [](const Box& B, const Box& Q, double rp) {
+    const double h = 0.5 * Q.side;
+    const double ex = std::max(0.0, std::fabs(B.cx - Q.cx) - h);
+    const double ey = std::max(0.0, std::fabs(B.cy - Q.cy) - h);
+    return ex * ex + ey * ey <= rp * rp * (1.0 + 1e-9);
+  };
+  // boxes are independent here (the cell maps are only read)
+  HostPool::instance().run((int)c->boxes.size(), [&](int bi) {
+    Box& B = c->boxes[bi];
+    B.dofs.clear();
+    B.near_same.clear();
+    B.near_leaf.clear();
+    if (B.leaf()) {
+      B.dofs.reserve(2 * B.nodes.size());
+      for (int j : B.nodes) {
+        B.dofs.push_back(2 * j);
+        B.dofs.push_back(2 * j + 1);
+      }
+      std::sort(B.dofs.begin(), B.dofs.end());
+    }
+    if (B.level == 0) return;
+    const int l = B.level;
+    const double rp = ratio * B.side;
+    const long long D = (long long)std::floor(ratio + 0.5) + 1;
+    for (long long dx = -D; dx <= D; ++dx)
+      for (long long dy = -D; dy <= D; ++dy) {
+        if (dx == 0 && dy == 0) continue;
+        auto it = cells[l].find(key2(B.ix + dx, B.iy + dy));
+        if (it != cells[l].end() && near(B, c->boxes[it->second], rp)) B.near_same.push_back(it->second);
+      }
+    for (int lc = 0; lc < l; ++lc) {
+      const long long ax = B.ix >> (l - lc), ay = B.iy >> (l - lc);
+      const double sc = std::ldexp(B.side, l - lc);
+      const long long Dc = (long long)std::ceil(rp / sc) + 1;
+      for (long long dx = -Dc; dx <= Dc; ++dx)
+        for (long long dy = -Dc; dy <= Dc; ++dy) {
+          auto it = cells[lc].find(key2(ax + dx, ay + dy));
+          if (it == cells[lc].end()) continue;
+          const Box& Q = c->boxes[it->second];
+          if (Q.leaf() && near(B, Q, rp)) B.near_leaf.push_back(it->second);
+        }
+    }
+  });
+}
+
+void build_tree(rs_ctx* c) {
+  c->boxes.clear();
+  Box root;
+  if (c->prm.has_root) {
+    root.cx = c->prm.root[0];
+    root.cy = c->prm.root[1];
+    root.side = c->prm.root[2];
+  } else {
+    double xmin = c->x[0], xmax = c->x[0], ymin = c->y[0], ymax = c->y[0];
+    for (int i = 1; i < c->N; ++i) {
+      xmin = std::min(xmin, c->x[i]);
+      xmax = std::max(xmax, c->x[i]);
+      ymin = std::min(ymin, c->y[i]);
+      ymax = std::max(ymax, c->y[i]);
+    }
+    root.cx = 0.5 * (xmin + xmax);
+    root.cy = 0.5 * (ymin + ymax);
+    root.side = (1.0 + std::ldexp(1.0, -20)) * std::max(xmax - xmin, ymax - ymin);
+    if (root.side == 0.0) root.side = 1.0;
+  }
+  root.nodes.resize(c->N);
+  for (int i = 0; i < c->N; ++i) root.nodes[i] = i;
+  c->root_cx = root.cx;
+  c->root_cy = root.cy;
+  c->root_side = root.side;
+  c->boxes.push_back(std::move(root));
+  const int leaf = c->prm.leaf_size;
+  // level by level: the boxes of a level split on host threads, and their
+  // children are appended in box order (breadth-first numbering)
+  size_t lo = 0, hi = 1;
+  while (lo < hi) {
+    const int nl = (int)(hi - lo);
+    std::vector<std::array<std::vector<int>, 4>> parts(nl);
+    bool too_deep = false;
+    for (size_t bi = lo; bi < hi; ++bi)
+      if ((int)c->boxes[bi].nodes.size() > leaf && c->boxes[bi].level >= kMaxDepth) too_deep = true;
+    if (too_deep) throw RsError{RS_ERR_ARG, "quadtree deeper than 48 levels (coincident nodes?)"};
+    HostPool::instance().run(nl, [&](int t) {
+      const Box& B = c->boxes[lo + t];
+      if ((int)B.nodes.size() <= leaf) return;
+      for (int j : B.nodes) {
+        const int q = (c->x[j] >= B.cx ? 1 : 0) + 2 * (c->y[j] >= B.cy ? 1 : 0);
+        parts[t][q].push_back(j);
+      }
+    });
+    for (size_t bi = lo; bi < hi; ++bi) {
+      auto& part = parts[bi - lo];
+      const double cx = c->boxes[bi].cx, cy = c->boxes[bi].cy, side = c->boxes[bi].side;
+      const double h = side / 4.0;
+      for (int q = 0; q < 4; ++q) {
+        if (part[q].empty()) continue;
+        Box ch;
+        ch.level = c->boxes[bi].level + 1;
+        ch.cx = (q % 2 == 0) ? cx - h : cx + h;
+        ch.cy = (q < 2) ? cy - h : cy + h;
+        ch.side = side / 2.0;
+        ch.ix = 2 * c->boxes[bi].ix + (q & 1);
+        ch.iy = 2 * c->boxes[bi].iy + (q >> 1);
+        ch.parent = (int)bi;
+        ch.nodes = std::move(part[q]);
+        const int id = (int)c->boxes.size();
+        c->boxes[bi].child[c->boxes[bi].nchild++] = id;
+        c->boxes.push_back(std::move(ch));
+      }
+    }
+    lo = hi;
+    hi = c->boxes.size();
+  }
+  c->L = 0;
+  for (const Box& b : c->boxes) c->L = std::max(c->L, b.level);
+  HTimer ht_(c, "host:tree.neighbors");
+  build_neighbors(c);
+}
+
+std::vector<int> skeleton_of(const BoxFac& f) {
+  std::vector<int> s(f.k);
+  for (int i = 0; i < f.k; ++i) s[i] = f.I[f.perm[i]];
+  return s;
+}
+
+std::vector<int> redundant_of(const BoxFac& f) {
+  std::vector<int> r(f.n - f.k);
+  for (int i = f.k; i < f.n; ++i) r[i - f.k] = f.I[f.perm[i]];
+  return r;
+}
+
+// Unknowns of box b and, for a parent, where each one sits in its child's X_SS.
+void box_unknowns(const rs_ctx* c, int b, std::vector<int>& I, std::vector<ChildSrc>* src) {
+  const Box& B = c->boxes[b];
+  I.clear();
+  if (src) src->clear();
+  if (B.leaf()) {
+    I = B.dofs;
+    return;
+  }
+  struct E { int dof; int child; int idx; };
+  std::vector<E> ents;
+  for (int q = 0; q < B.nchild; ++q) {
+    const int ch = B.child[q];
+    const BoxFac& f = c->fac[ch];
+    for (int i = 0; i < f.k; ++i) ents.push_back({f.I[f.perm[i]], ch, i});
+  }
+  std::sort(ents.begin(), ents.end(), [](const E& a, const E& b2) { return a.dof < b2.dof; });
+  I.resize(ents.size());
+  if (src) src->resize(ents.size());
+  for (size_t i = 0; i < ents.size(); ++i) {
+    I[i] = ents[i].dof;
+    if (src) {
+      const BoxFac& f = c->fac[ents[i].child];
+      (*src)[i] = ChildSrc{f.Xss, ents[i].idx, f.k, ents[i].child, 0};
+    }
+  }
+}
+
+double seconds_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// Updating rule (Section 2.8): a box is recompressed when an input of its
+// compression changed.  Leaf: new box, different node set, or a moved node.
+// Parent: new box, different children, or a recompressed child.  Any box: a
+// different near field F_int or a moved node in it.  Otherwise the stored
+// factors are exactly those a fresh factorization would compute.
+bool compress_needed(const rs_ctx* c, int b, const std::vector<int>& F) {
+  const OldState& O = *c->old;
+  const Box& B = c->boxes[b];
+  auto it = O.by_key.find(BoxKey{B.level, B.ix, B.iy});
+  if (it == O.by_key.end()) return true;
+  const Box& OB = O.boxes[it->second];
+  const BoxFac& OF = O.fac[it->second];
+  if (!OF.active || OB.leaf() != B.leaf()) return true;
+  if (B.leaf()) {
+    if (OB.nodes != B.nodes) return true;
+    for (int j : B.nodes)
+      if (O.moved[j]) return true;
+  } else {
+    std::vector<BoxKey> ok, nk;
+    for (int q = 0; q < OB.nchild; ++q) {
+      const Box& C = O.boxes[OB.child[q]];
+      ok.emplace_back(C.level, C.ix, C.iy);
+    }
+    for (int q = 0; q < B.nchild; ++q) {
+      const Box& C = c->boxes[B.child[q]];
+      nk.emplace_back(C.level, C.ix, C.iy);
+      if (c->recomputed[B.child[q]]) return true;
+    }
+    std::sort(ok.begin(), ok.end());
+    std::sort(nk.begin(), nk.end());
+    if (ok != nk) return true;
+  }
+  if (F != OF.fint) return true;
+  for (int d : F)
+    if (O.moved[d >> 1]) return true;
+  return false;
+}
+
 
 // Work of one context at one level: the boxes it compresses, prepared on the host.
 struct LevelPrep {
@@ -2963,6 +2979,7 @@ void begin_update_geometry(rs_ctx* c, int n_nodes, const double* xy, const doubl
                            const double* hole_xy, const int* old_of_new, OldState& O) {
   if (n_nodes <= 0 || n_holes < 0 || !curve_id || !old_of_new)
     throw RsError{RS_ERR_ARG, "bad n_nodes or n_holes, or NULL curve_id / old_of_new"};
+  HTimer htv_(c, "host:upd.validate");
   validate_nodes(n_nodes, xy, normal, weight, curvature);
   std::vector<int> count(n_holes + 1, 0);
   for (int i = 0; i < n_nodes; ++i) {
@@ -2990,13 +3007,17 @@ void begin_update_geometry(rs_ctx* c, int n_nodes, const double* xy, const doubl
     if (!inside_root(c, xy[2 * i], xy[2 * i + 1]))
       throw RsError{RS_ERR_OUT_OF_ROOT, "node " + std::to_string(i) + " lies outside the fixed root"};
   HIP_CHECK(hipSetDevice(c->device));
+  HTimer htt_(c, "host:upd.translate");
   auto node_new = [&](int o) { return new_of_old[o] >= 0 ? new_of_old[o] : -2 - o; };
   auto dof_new = [&](int d) { return new_of_old[d >> 1] >= 0 ? 2 * new_of_old[d >> 1] + (d & 1) : -2 - d; };
   O.boxes = std::move(c->boxes);
   O.fac = std::move(c->fac);
   for (size_t b = 0; b < O.boxes.size(); ++b) {
-    Box& B = O.boxes[b];
+    const Box& B = O.boxes[b];
     O.by_key[BoxKey{B.level, B.ix, B.iy}] = (int)b;
+  }
+  HostPool::instance().run((int)O.boxes.size(), [&](int b) {
+    Box& B = O.boxes[b];
     for (int& j : B.nodes) j = node_new(j);
     BoxFac& F = O.fac[b];
     bool gone = false;
@@ -3006,7 +3027,7 @@ void begin_update_geometry(rs_ctx* c, int n_nodes, const double* xy, const doubl
     }
     for (int& d : F.fint) d = dof_new(d);
     if (gone) F.active = false;      // its unknowns changed: recompressed
-  }
+  });
   O.moved.assign(n_nodes, 0);
   for (int j = 0; j < n_nodes; ++j) O.moved[j] = old_of_new[j] < 0;
   c->N = n_nodes;
@@ -3041,8 +3062,14 @@ void begin_update_geometry(rs_ctx* c, int n_nodes, const double* xy, const doubl
   c->prm.root[0] = c->root_cx;
   c->prm.root[1] = c->root_cy;
   c->prm.root[2] = c->root_side;
-  build_tree(c);
-  upload_geometry(c);
+  {
+    HTimer ht_(c, "host:upd.tree");
+    build_tree(c);
+  }
+  {
+    HTimer ht_(c, "host:upd.upload");
+    upload_geometry(c);
+  }
   c->stats.n_nodes = n_nodes;
   c->stats.n_holes = n_holes;
   c->old = &O;
