@@ -24,6 +24,8 @@ from .geometry import (  # noqa: F401
     move_hole,
     insert_hole,
     delete_hole,
+    starfish_nodes,
+    starfish_geometry,
 )
 from .rhs import (  # noqa: F401
     PointForce,

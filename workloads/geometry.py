@@ -89,6 +89,65 @@ def ellipse_nodes(n: int, a: float, b: float, theta: float, cx: float, cy: float
     return xy, nrm, w, kap
 
 
+def starfish_nodes(n: int, radius: float, amp: float, arms: int, theta: float, cx: float, cy: float,
+                   hole: bool):
+    """Nodes, normals, weights and signed curvature of a starfish curve.
+
+    Polar radius r(t) = radius (1 + amp cos(arms t)) at parameter t_k = 2 pi k / n,
+    rotated by theta about its centre (cx, cy); trapezoid weights, analytic
+    normal and curvature (the convention of the module docstring).
+    """
+    t = 2.0 * np.pi * np.arange(n, dtype=np.float64) / n
+    r = radius * (1.0 + amp * np.cos(arms * t))
+    r1 = -radius * amp * arms * np.sin(arms * t)
+    r2 = -radius * amp * arms * arms * np.cos(arms * t)
+    ct, st = np.cos(t), np.sin(t)
+    px, py = r * ct, r * st
+    dx, dy = r1 * ct - r * st, r1 * st + r * ct
+    ddx = r2 * ct - 2.0 * r1 * st - r * ct
+    ddy = r2 * st + 2.0 * r1 * ct - r * st
+    speed = np.hypot(dx, dy)
+    c, s = np.cos(theta), np.sin(theta)
+    xy = np.stack([cx + c * px - s * py, cy + s * px + c * py], axis=1)
+    ox, oy = dy / speed, -dx / speed                 # outward for the counter-clockwise curve
+    nrm = np.stack([c * ox - s * oy, s * ox + c * oy], axis=1)
+    w = 2.0 * np.pi * speed / n
+    kap = (dx * ddy - dy * ddx) / speed ** 3
+    if hole:
+        nrm = -nrm
+        kap = -kap
+    return xy, nrm, w, kap
+
+
+def starfish_geometry(n_total: int = 16384, theta1: float = 0.0, theta2: float = np.pi,
+                      amp: float = 0.25, arms: int = 5, hole_scale: float = 0.16) -> Geometry:
+    """The Laplace Neumann workload's boundary: a starfish (radius 1) holding two
+    starfish holes 16 % of its size, with 2/3 of the nodes on the outer curve
+    and 1/6 on each hole.  Hole h sits on the outer curve scaled by 1/2 at
+    polar angle theta_h (the path the holes move along)."""
+    n_out = int(round(2 * n_total / 3))
+    n_h = (n_total - n_out) // 2
+    n_out = n_total - 2 * n_h
+    parts = [starfish_nodes(n_out, 1.0, amp, arms, 0.0, 0.0, 0.0, False)]
+    holes = []
+    for th in (theta1, theta2):
+        rr = 0.5 * (1.0 + amp * np.cos(arms * th))
+        cx, cy = rr * np.cos(th), rr * np.sin(th)
+        parts.append(starfish_nodes(n_h, hole_scale, amp, arms, th, cx, cy, True))
+        holes.append((cx, cy))
+    xy = np.concatenate([q[0] for q in parts])
+    return Geometry(
+        xy=np.ascontiguousarray(xy),
+        normal=np.ascontiguousarray(np.concatenate([q[1] for q in parts])),
+        weight=np.concatenate([q[2] for q in parts]),
+        curvature=np.concatenate([q[3] for q in parts]),
+        curve_id=np.concatenate([np.full(n_out, 0, np.int32), np.full(n_h, 1, np.int32),
+                                 np.full(n_h, 2, np.int32)]),
+        hole_xy=np.array(holes, dtype=np.float64),
+        curves=[],
+    )
+
+
 def build_geometry(curves: Sequence[Curve], root=None) -> Geometry:
     xs, ns, ws, ks, ids, holes = [], [], [], [], [], []
     h = 0
