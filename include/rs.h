@@ -94,11 +94,23 @@ typedef struct {
                           so a converged solve is certified against the exact residual; the
                           exact float64 residual is taken again once that sum passes a quarter
                           of refine_tol.  0: every residual is the exact float64 [f;0] - A x */
+  int kernel;          /* 0 (default): the Stokes double layer with its augmentation (Section 3.1).
+                          1: the Laplace Neumann formulation of Section 4.4.1: u = S mu and
+                          f = (lambda I - D + N) mu with D the adjoint double layer
+                          -(1/2pi) ((x - y) . n(x)) / |x - y|^2 (normal at the target, pointing
+                          out of the domain), N mu = the integral of mu over the boundary and no
+                          augmentation (n_holes = 0: every curve_id 0, whatever the number of
+                          curves).  The unknown layout stays two per node: unknown 2i is mu at
+                          node i, unknown 2i+1 an uncoupled one whose row is lambda x (pass 0
+                          in f there; it comes back 0).  Requires precision 0 or 1; refinement
+                          takes exact residuals (refine_update acts as 0); rs_apply_f32 is not
+                          available; rs_evaluate returns (S mu, d(S mu)/dx) per target */
 } rs_params;
 
 /* Fill *p with the defaults: lambda -0.5, tol 1e-10, leaf 64, 64 proxy points
  * at 1.5 x side, rcond_min 1e-12, float64, refine_tol 1e-8, refine_max 0
- * (direct solve), no fixed root, solve_graph 1, mixed_rcond_min 1e-4, apply_shape -1. */
+ * (direct solve), no fixed root, solve_graph 1, mixed_rcond_min 1e-4, apply_shape -1,
+ * refine_update 1, kernel 0 (Stokes). */
 void rs_default_params(rs_params* p);
 
 /* Build the adaptive quadtree (Section 2.3) for a boundary discretisation and
@@ -303,7 +315,11 @@ rs_status rs_apply_dev_noalloc(rs_ctx* ctx, int ncols, const double* x_dev, doub
  * solution [mu; lambda] as returned by rs_solve; u: host, (2 n_targets) x ncols
  * column-major, rows 2t and 2t + 1 = the x and y components at target t.
  * Plain quadrature: accurate a few node spacings away from the boundary (no
- * near-boundary correction).  Needs only rs_build_tree (no factorization). */
+ * near-boundary correction).  Needs only rs_build_tree (no factorization).
+ * With kernel 1 (Laplace Neumann, Section 4.4.1) row 2t is the potential
+ * u(t) = (S mu)(t) = -(1/2pi) sum_j log|t - y_j| w_j mu_j and row 2t + 1 its
+ * x-derivative (the quantity the section's objective measures at the
+ * domain's centre). */
 rs_status rs_evaluate(rs_ctx* ctx, int n_targets, const double* targets_xy, int ncols, const double* x,
                       double* u);
 

@@ -43,6 +43,7 @@ class Params(ctypes.Structure):
         ("mixed_rcond_min", ctypes.c_double),
         ("apply_shape", ctypes.c_int),
         ("refine_update", ctypes.c_int),
+        ("kernel", ctypes.c_int),
     ]
 
 
@@ -233,7 +234,7 @@ class RSSolver:
     def __init__(self, xy, normal, weight, curvature, curve_id, hole_xy=None, *, tol=None,
                  leaf_size=None, n_proxy=None, proxy_ratio=None, lam=None, rcond_min=None,
                  precision=None, refine_tol=None, refine_max=None, root=None, solve_graph=None,
-                 mixed_rcond_min=None, apply_shape=None, refine_update=None):
+                 mixed_rcond_min=None, apply_shape=None, refine_update=None, kernel=None):
         lib = load_library()
         self._lib = lib
         self._h = ctypes.c_void_p()
@@ -243,7 +244,7 @@ class RSSolver:
                           ("precision", precision), ("refine_tol", refine_tol),
                           ("refine_max", refine_max), ("solve_graph", solve_graph),
                           ("mixed_rcond_min", mixed_rcond_min), ("apply_shape", apply_shape),
-                          ("refine_update", refine_update)):
+                          ("refine_update", refine_update), ("kernel", kernel)):
             if val is not None:
                 setattr(p, name, val)
         if root is not None:
@@ -257,6 +258,11 @@ class RSSolver:
         weight = np.ascontiguousarray(weight, dtype=np.float64).reshape(N)
         curvature = np.ascontiguousarray(curvature, dtype=np.float64).reshape(N)
         curve_id = np.ascontiguousarray(curve_id, dtype=np.int32).reshape(N)
+        if p.kernel == 1:
+            # the Laplace Neumann formulation has no augmentation: every curve,
+            # holes included, is one boundary without border unknowns
+            curve_id = np.zeros(N, dtype=np.int32)
+            hole_xy = None
         n_holes = int(curve_id.max()) if N else 0
         hp = None
         if hole_xy is not None and n_holes:
@@ -269,6 +275,20 @@ class RSSolver:
         self.n_nodes = N
         self.n_holes = n_holes
         _live.add(self)
+
+    @staticmethod
+    def embed_scalar(f):
+        """Node values (N,) or (N, ncols) of the Laplace Neumann kernel as the
+        library's two-unknowns-per-node layout: f at unknown 2i, 0 at 2i + 1."""
+        f = np.asarray(f, dtype=np.float64)
+        out = np.zeros((2 * f.shape[0],) + f.shape[1:])
+        out[0::2] = f
+        return out
+
+    @staticmethod
+    def scalar_part(x):
+        """The density mu (unknowns 2i) of a Laplace Neumann solution."""
+        return np.ascontiguousarray(np.asarray(x)[0::2])
 
     @classmethod
     def from_geometry(cls, geom, **kw):
@@ -355,7 +375,8 @@ class RSSolver:
 
     def evaluate(self, targets, x):
         """Velocity D mu + H lambda at target points (M, 2) off the boundary from a
-        solution x ((2N + 3p) or (2N + 3p, ncols)); returns (M, 2) or (M, 2, ncols)."""
+        solution x ((2N + 3p) or (2N + 3p, ncols)); returns (M, 2) or (M, 2, ncols).
+        With kernel 1 (Laplace Neumann) the pair is (S mu, d(S mu)/dx)."""
         T = np.ascontiguousarray(targets, dtype=np.float64).reshape(-1, 2)
         one = np.asarray(x).ndim == 1
         X = np.asfortranarray(np.asarray(x, dtype=np.float64).reshape(self.n_system, -1))

@@ -314,6 +314,7 @@ void geo_of(const rs_ctx* c, Geo& g) {
   g.w = c->d_w.as<double>();
   g.kap = c->d_kap.as<double>();
   g.N = c->N;
+  g.kernel = c->prm.kernel;
 }
 
 // ---- kernel timing --------------------------------------------------------
@@ -2292,6 +2293,10 @@ ApplyTuneCache& apply_tune_cache() {
 }
 
 int apply_config_for(rs_ctx* c, int ncols, const double* xrows, double* yrows) {
+  if (c->prm.kernel == 1) {   // the Laplace apply has one shape per column count
+    c->stats.apply_config = apply_default_config(ncols);
+    return c->stats.apply_config;
+  }
   if (c->prm.apply_shape >= 0) {
     const int cfg = apply_config_valid(c->prm.apply_shape, ncols) ? c->prm.apply_shape
                                                                    : apply_default_config(ncols);
@@ -2354,6 +2359,7 @@ int apply_config_for(rs_ctx* c, int ncols, const double* xrows, double* yrows) {
 // the fixed shape, the tuned one if this problem shape was tuned before in
 // the process, else the default.
 int apply_config_cached(const rs_ctx* c, int ncols) {
+  if (c->prm.kernel == 1) return apply_default_config(ncols);
   if (c->prm.apply_shape >= 0)
     return apply_config_valid(c->prm.apply_shape, ncols) ? c->prm.apply_shape : apply_default_config(ncols);
   ApplyTuneCache& tc = apply_tune_cache();
@@ -2464,6 +2470,11 @@ rs_status rs_build_tree(const rs_params* prm, int n_nodes, const double* xy, con
       throw RsError{RS_ERR_ARG, "mixed_rcond_min must be finite and >= 0"};
     if (prm->refine_update != 0 && prm->refine_update != 1)
       throw RsError{RS_ERR_ARG, "refine_update must be 0 or 1"};
+    if (prm->kernel != 0 && prm->kernel != 1) throw RsError{RS_ERR_ARG, "kernel must be 0 or 1"};
+    if (prm->kernel == 1 && n_holes != 0)
+      throw RsError{RS_ERR_ARG, "the Laplace Neumann kernel has no augmentation: n_holes must be 0"};
+    if (prm->kernel == 1 && prm->precision > 1)
+      throw RsError{RS_ERR_ARG, "the Laplace Neumann kernel supports precision 0 and 1"};
     validate_nodes(n_nodes, xy, normal, weight, curvature);
     std::vector<int> count(n_holes + 1, 0);
     for (int i = 0; i < n_nodes; ++i) {
@@ -2475,6 +2486,7 @@ rs_status rs_build_tree(const rs_params* prm, int n_nodes, const double* xy, con
     if (hole_xy && !finite_all(hole_xy, 2 * (size_t)n_holes)) throw RsError{RS_ERR_ARG, "non-finite hole point"};
     c = new rs_ctx();
     c->prm = *prm;
+    if (c->prm.kernel == 1) c->prm.refine_update = 0;   // no float32 image of the Laplace operator
     c->N = n_nodes;
     c->p = n_holes;
     c->x.resize(n_nodes);
@@ -2745,6 +2757,7 @@ rs_status rs_apply_f32(rs_ctx* c, int ncols, const double* x, double* y, double*
   if (!c) return RS_ERR_ARG;
   try {
     if (ncols <= 0 || !x || !y) throw RsError{RS_ERR_ARG, "bad ncols or NULL pointer"};
+    if (c->prm.kernel == 1) throw RsError{RS_ERR_ARG, "no float32 image of the Laplace Neumann operator"};
     HIP_CHECK(hipSetDevice(c->device));
     const size_t ns = 2 * (size_t)c->N + 3 * (size_t)c->p;
     hipStream_t s = c->stream;
@@ -2979,6 +2992,8 @@ void begin_update_geometry(rs_ctx* c, int n_nodes, const double* xy, const doubl
                            const double* hole_xy, const int* old_of_new, OldState& O) {
   if (n_nodes <= 0 || n_holes < 0 || !curve_id || !old_of_new)
     throw RsError{RS_ERR_ARG, "bad n_nodes or n_holes, or NULL curve_id / old_of_new"};
+  if (c->prm.kernel == 1 && n_holes != 0)
+    throw RsError{RS_ERR_ARG, "the Laplace Neumann kernel has no augmentation: n_holes must be 0"};
   HTimer htv_(c, "host:upd.validate");
   validate_nodes(n_nodes, xy, normal, weight, curvature);
   std::vector<int> count(n_holes + 1, 0);

@@ -210,6 +210,80 @@ __global__ __launch_bounds__(kApplyThreads) void k_apply_pairs_s(const double4* 
   }
 }
 
+// ---- the Laplace Neumann operator (Section 4.4.1) -----------------------------
+// Pair sums of -D mu (the adjoint double layer, normal at the target) at the
+// boundary nodes, EVAL = 0, or of S mu and d(S mu)/dx at arbitrary targets,
+// EVAL = 1.  The density is component 0 of each node's pair of unknowns.  A
+// thread holds one target and NC columns; a block stages 256 sources (position,
+// w / 2pi, NC density values) in LDS.  Grid and chunking as for the Stokes
+// pairs: per source chunk the partial sums go to rows 2i (and 2i + 1 for the
+// x-derivative) of that chunk's slice of `part`, added in a fixed order by the
+// O(N) kernels.
+template <int NC, int EVAL>
+__global__ __launch_bounds__(kApplyThreads) void k_lap_pairs(Geo g, const double* __restrict__ tx,
+                                                             const double* __restrict__ ty, int nt,
+                                                             const double* __restrict__ x, int ncols,
+                                                             int chunk, double* __restrict__ part,
+                                                             const int* skip, int max_iters) {
+  if (apply_mode(skip, max_iters) != 0) return;
+  __shared__ double2 sxy[kApplyThreads];
+  __shared__ double sw[kApplyThreads];
+  __shared__ double sm[kApplyThreads * NC];
+  const int N = g.N, tid = threadIdx.x;
+  const int i = blockIdx.x * kApplyThreads + tid;
+  const int js0 = blockIdx.y * chunk, js1 = min(N, js0 + chunk);
+  const int q0 = blockIdx.z * NC;
+  const int nq = min(NC, ncols - q0);
+  const double xi = i < nt ? tx[i] : 0.0, yi = i < nt ? ty[i] : 0.0;
+  const double nxi = (!EVAL && i < nt) ? g.nx[i] : 0.0, nyi = (!EVAL && i < nt) ? g.ny[i] : 0.0;
+  double a[NC], b[NC];
+#pragma unroll
+  for (int q = 0; q < NC; ++q) { a[q] = 0.0; b[q] = 0.0; }
+  for (int j0 = js0; j0 < js1; j0 += kApplyThreads) {
+    const int j = j0 + tid;
+    __syncthreads();
+    if (j < js1) {
+      sxy[tid] = make_double2(g.x[j], g.y[j]);
+      sw[tid] = kInv2Pi * g.w[j];
+#pragma unroll
+      for (int q = 0; q < NC; ++q) sm[tid * NC + q] = q < nq ? x[(size_t)(2 * j) * ncols + q0 + q] : 0.0;
+    }
+    __syncthreads();
+    const int cnt = min(kApplyThreads, js1 - j0);
+    for (int jj = 0; jj < cnt; ++jj) {
+      const double2 p = sxy[jj];
+      const double rx = xi - p.x, ry = yi - p.y;
+      // the floor makes a target's own node (r = 0, r . n = 0) contribute
+      // exactly zero without a branch; every other pair's |r|^2 exceeds it
+      // by far more than 2^53
+      const double r2 = fma(rx, rx, fma(ry, ry, kR4Floor));
+      const double ir2 = recip(r2);
+      if (EVAL) {
+        const double cu = -0.5 * sw[jj] * log(r2);
+        const double cx = -sw[jj] * rx * ir2;
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+          a[q] = fma(cu, sm[jj * NC + q], a[q]);
+          b[q] = fma(cx, sm[jj * NC + q], b[q]);
+        }
+      } else {
+        const double c = fma(rx, nxi, ry * nyi) * ir2 * sw[jj];
+#pragma unroll
+        for (int q = 0; q < NC; ++q) a[q] = fma(c, sm[jj * NC + q], a[q]);
+      }
+    }
+  }
+  if (i >= nt) return;
+  double* out = part + (size_t)blockIdx.y * 2 * nt * ncols;
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+    if (q < nq) {
+      out[(size_t)(2 * i) * ncols + q0 + q] = a[q];
+      if (EVAL) out[(size_t)(2 * i + 1) * ncols + q0 + q] = b[q];
+    }
+  }
+}
+
 // src4[j] = (x_j, y_j, w_j n_xj / pi, w_j n_yj / pi)
 __global__ void k_pack_sources(Geo g, double4* src4) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -241,8 +315,12 @@ __global__ __launch_bounds__(kNodeSumThreads) void k_apply_nsum(Geo g, const dou
   const int len = (g.N + kNsumParts - 1) / kNsumParts;
   const int j1 = min(g.N, (b + 1) * len);
   double s = 0.0;
-  for (int j = b * len + threadIdx.x; j < j1; j += kNodeSumThreads)
-    s += g.w[j] * (g.nx[j] * x[(size_t)(2 * j) * ncols + q] + g.ny[j] * x[(size_t)(2 * j + 1) * ncols + q]);
+  if (g.kernel == 1) {   // Laplace: N mu = sum_j w_j mu_j
+    for (int j = b * len + threadIdx.x; j < j1; j += kNodeSumThreads) s += g.w[j] * x[(size_t)(2 * j) * ncols + q];
+  } else {
+    for (int j = b * len + threadIdx.x; j < j1; j += kNodeSumThreads)
+      s += g.w[j] * (g.nx[j] * x[(size_t)(2 * j) * ncols + q] + g.ny[j] * x[(size_t)(2 * j + 1) * ncols + q]);
+  }
   s = block_sum(s, red);
   if (threadIdx.x == 0) nsum[q * kNsumParts + b] = s;
 }
@@ -262,6 +340,19 @@ __global__ void k_apply_sum(Geo g, double lam, const double* hole_xy, int p, con
   if (t >= (long long)N * ncols) return;
   const int i = (int)(t / ncols), q = (int)(t % ncols);
   const size_t stride = (size_t)2 * N * ncols;
+  if (g.kernel == 1) {
+    // Laplace: chunks of -D mu, the coincident limit kappa w / 4pi, lam and
+    // N mu; the second unknown of the node has the row lam x
+    double a = 0.0;
+    for (int c = 0; c < nchunk; ++c) a += part[c * stride + (size_t)(2 * i) * ncols + q];
+    double ns = 0.0;
+    for (int b = 0; b < kNsumParts; ++b) ns += nsum[q * kNsumParts + b];
+    const double mu = x[(size_t)(2 * i) * ncols + q];
+    a += (lam + kInv4Pi * g.kap[i] * g.w[i]) * mu + ns;
+    y[(size_t)(2 * i) * ncols + q] = a;
+    y[(size_t)(2 * i + 1) * ncols + q] = lam * x[(size_t)(2 * i + 1) * ncols + q];
+    return;
+  }
   double ax = 0.0, ay = 0.0;
   for (int c = 0; c < nchunk; ++c) {
     ax += part[c * stride + (size_t)(2 * i) * ncols + q];
@@ -612,6 +703,26 @@ static void launch_pairs(Geo g, double4* src4, const double* tx, const double* t
 #undef RS_APPLY_S
 }
 
+// The Laplace pair sums (EVAL: potential and x-derivative at arbitrary
+// targets); the column block follows ncols, the partition into source chunks
+// is the Stokes one.
+static void launch_lap_pairs(Geo g, const double* tx, const double* ty, int nt, const double* x, int ncols,
+                             int chunk, double* part, const int* skip, int max_iters, bool eval, hipStream_t s) {
+  const int nc = ncols <= 1 ? 1 : (ncols <= 4 ? 4 : (ncols <= 8 ? 8 : 16));
+  dim3 grid(blocks_for(nt, kApplyThreads), (g.N + chunk - 1) / chunk, blocks_for(ncols, nc));
+#define RS_LAP(NC)                                                                                    \
+  if (nc == NC) {                                                                                     \
+    if (eval)                                                                                         \
+      hipLaunchKernelGGL((k_lap_pairs<NC, 1>), grid, dim3(kApplyThreads), 0, s, g, tx, ty, nt, x, ncols, \
+                         chunk, part, skip, max_iters);                                               \
+    else                                                                                              \
+      hipLaunchKernelGGL((k_lap_pairs<NC, 0>), grid, dim3(kApplyThreads), 0, s, g, tx, ty, nt, x, ncols, \
+                         chunk, part, skip, max_iters);                                               \
+  }
+  RS_LAP(1) RS_LAP(4) RS_LAP(8) RS_LAP(16)
+#undef RS_LAP
+}
+
 // Offset (in doubles, a multiple of 4) of the packed sources in a scratch
 // whose first `used` doubles hold partial sums.
 static size_t src4_offset(size_t used) { return (used + 3) / 4 * 4; }
@@ -690,8 +801,11 @@ void launch_apply_operator(Geo g, const int* curve_id, const double* hole_xy, in
   const int chunk = apply_chunk_len(g.N);
   const int nchunk = (g.N + chunk - 1) / chunk;
   dim3 grid(blocks_for(g.N, kApplyThreads * sh.t), nchunk, blocks_for(ncols, sh.nc));
-  launch_pairs(g, apply_src4(part, g.N, ncols), g.x, g.y, g.N, x, ncols, chunk, part, skip, max_iters, cfg, grid,
-               s);
+  if (g.kernel == 1)
+    launch_lap_pairs(g, g.x, g.y, g.N, x, ncols, chunk, part, skip, max_iters, false, s);
+  else
+    launch_pairs(g, apply_src4(part, g.N, ncols), g.x, g.y, g.N, x, ncols, chunk, part, skip, max_iters, cfg,
+                 grid, s);
   apply_tail(g, curve_id, hole_xy, p, lam, x, x, ncols, y, part, nchunk, nullptr, nullptr, skip, max_iters, s);
 }
 
@@ -716,10 +830,17 @@ void launch_apply_refine(Geo g, const int* curve_id, const double* hole_xy, int 
   const int chunk = apply_chunk_len(g.N);
   const int nchunk = (g.N + chunk - 1) / chunk;
   double4* src4 = apply_src4(part, g.N, ncols);
+  if (g.kernel == 1) {   // the Laplace path has no float32 image: exact residuals only
+    which = 0;
+    corr = nullptr;
+  }
   if (which != 1) {
     const ApplyShape sh = kApplyShapes[cfg];
     dim3 grid(blocks_for(g.N, kApplyThreads * sh.t), nchunk, blocks_for(ncols, sh.nc));
-    launch_pairs(g, src4, g.x, g.y, g.N, x, ncols, chunk, part, flag, max_iters, cfg, grid, s);
+    if (g.kernel == 1)
+      launch_lap_pairs(g, g.x, g.y, g.N, x, ncols, chunk, part, flag, max_iters, false, s);
+    else
+      launch_pairs(g, src4, g.x, g.y, g.N, x, ncols, chunk, part, flag, max_iters, cfg, grid, s);
   }
   float *d32 = nullptr, *dmax = nullptr, *bpart = nullptr;
   double* bt = nullptr;
@@ -790,7 +911,10 @@ void launch_evaluate(Geo g, const double* hole_xy, int p, const double* tx, cons
   const int nchunk = (g.N + chunk - 1) / chunk;
   double4* src4 = reinterpret_cast<double4*>(part + src4_offset((size_t)nchunk * 2 * nt * ncols));
   dim3 grid(blocks_for(nt, kApplyThreads * sh.t), nchunk, blocks_for(ncols, sh.nc));
-  launch_pairs(g, src4, tx, ty, nt, x, ncols, chunk, part, nullptr, 0, cfg, grid, s);
+  if (g.kernel == 1)
+    launch_lap_pairs(g, tx, ty, nt, x, ncols, chunk, part, nullptr, 0, true, s);
+  else
+    launch_pairs(g, src4, tx, ty, nt, x, ncols, chunk, part, nullptr, 0, cfg, grid, s);
   hipLaunchKernelGGL(k_eval_sum, dim3(blocks_for((long long)nt * ncols, kBlock)), dim3(kBlock), 0, s, g,
                      tx, ty, nt, hole_xy, p, x, ncols, part, nchunk, u);
 }

@@ -14,6 +14,7 @@ namespace {
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kInvPi = 0.31830988618379067154;
 constexpr double kInv4Pi = 0.07957747154594766788;
+constexpr double kInv2Pi = 0.15915494309189533577;
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -132,10 +133,30 @@ __device__ __forceinline__ double sl_entry(double rx, double ry, double w, int a
   return kInv4Pi * w * v;
 }
 
+// ---- the Laplace Neumann kernel (Section 4.4.1) ------------------------------
+// Operator lam I - D + N with D the adjoint double layer (normal at the
+// target) and N mu = the integral of mu.  Its density lives in component 0 of
+// each node; component 1 is an uncoupled unknown with the row lam x, so the
+// two-unknowns-per-node layout of the Stokes path carries it unchanged.
+
+// -D between distinct points: (1/2pi) ((x - y) . n_x) / |x - y|^2 w_y.
+__device__ __forceinline__ double lap_dl(double rx, double ry, double nx, double ny, double w) {
+  return kInv2Pi * w * (rx * nx + ry * ny) / (rx * rx + ry * ry);
+}
+
+// Entry of lam I - D + N; the coincident limit of -D is kappa w / (4 pi).
+__device__ __forceinline__ double lap_op_entry(const Geo& g, int ti, int tc, int sj, int sc,
+                                               double lam) {
+  if (tc | sc) return (ti == sj && tc == sc) ? lam : 0.0;
+  if (ti == sj) return lam + kInv4Pi * g.kap[ti] * g.w[ti] + g.w[ti];
+  return lap_dl(g.x[ti] - g.x[sj], g.y[ti] - g.y[sj], g.nx[ti], g.ny[ti], g.w[sj]) + g.w[sj];
+}
+
 // Entry of lam I + D + N between unknown (ti, tc) (target node, component)
 // and (sj, sc).  Coincident nodes use the curvature limit of D.
 __device__ __forceinline__ double op_entry(const Geo& g, int ti, int tc, int sj, int sc,
                                            double lam) {
+  if (g.kernel == 1) return lap_op_entry(g, ti, tc, sj, sc, lam);
   double v;
   if (ti == sj) {
     const double tx = -g.ny[ti], ty = g.nx[ti];

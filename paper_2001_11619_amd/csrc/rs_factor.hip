@@ -89,6 +89,47 @@ __global__ __launch_bounds__(kBlock) void k_assemble_M(const LevelBox* boxes, in
     __syncthreads();
     if (!live) continue;
     double* col = B.M + (size_t)c0 * m + i;
+    if (g.kernel == 1) {
+      // Laplace Neumann (Section 4.4.1): near-field rows from the operator;
+      // source side, the potential and normal flux on the proxy circle of the
+      // box's charges plus their total (the rank-one row); target side, the
+      // normal derivative at the nodes of a proxy charge and a proxy dipole,
+      // plus the constant row of N.  The second unknown of a node is
+      // uncoupled: its columns are zero.  The Stokeslet rows (type 4) are zero.
+      for (int cc = 0; cc < cnt; ++cc) {
+        const int d = sj[cc];
+        const int j = d >> 1, jc = d & 1;
+        double v = 0.0;
+        if (type == 0) {
+          v = lap_op_entry(g, fj, fc, j, jc, 0.0);
+        } else if (type == 1) {
+          v = lap_op_entry(g, j, jc, fj, fc, 0.0);
+        } else if (jc == 0) {
+          const double xj = sx[cc], yj = sy[cc], wj = sw[cc];
+          if (type == 2) {
+            const double rx = px - xj, ry = py - yj;
+            const double r2 = rx * rx + ry * ry;
+            v = pa ? kInv2Pi * wj * (rx * pnx + ry * pny) / r2 : -kInv4Pi * wj * log(r2);
+          } else if (type == 3) {
+            const double rx = xj - px, ry = yj - py;
+            const double r2 = rx * rx + ry * ry;
+            const double rnj = rx * snx[cc] + ry * sny[cc];
+            if (!pa) {
+              v = kInv2Pi * wp * rnj / r2;
+            } else {
+              const double rnp = rx * pnx + ry * pny;
+              v = kInv2Pi * wp * ((snx[cc] * pnx + sny[cc] * pny) - 2.0 * rnp * rnj / r2) / r2;
+            }
+          } else if (type == 5) {
+            v = wj;
+          } else if (type == 6) {
+            v = B.wscale;
+          }
+        }
+        col[(size_t)cc * m] = v;
+      }
+      continue;
+    }
     if (F32) {
       // row point as a box-local float offset (the proxy point's is exact)
       const float rxf = type <= 1 ? (float)(fx - B.cx) : (float)(rp * pnx);

@@ -15,6 +15,7 @@ struct Geo {
   const double* w;
   const double* kap;
   int N;
+  int kernel;   // 0: Stokes (Section 3.1), 1: Laplace Neumann (Section 4.4.1)
 };
 
 // One box compressed at a level.  Device pointers point into per-level

@@ -568,11 +568,14 @@ __device__ __forceinline__ void r16_householder(const double (&x)[RU], const int
     beta = alpha;
     tau = 0.0;
   } else {
+    // two divisions, not one reciprocal of beta (alpha - beta): in a
+    // rank-deficient block of rows the rounding residue below the diagonal
+    // shrinks from step to step, and once s2 is subnormal that product
+    // underflows and its reciprocal overflows (tau = inf, then NaN).  Each
+    // quotient here stays finite: |alpha - beta| >= |beta| >= sqrt(s2) > 0.
     beta = -copysign(sqrt(alpha * alpha + s2), alpha);
-    const double d = alpha - beta;
-    const double rcp = 1.0 / (beta * d);
-    tau = -d * d * rcp;          // (beta - alpha) / beta
-    scal = beta * rcp;           // 1 / (alpha - beta)
+    tau = (beta - alpha) / beta;
+    scal = 1.0 / (alpha - beta);
   }
   __builtin_amdgcn_wave_barrier();
 #pragma unroll

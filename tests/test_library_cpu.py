@@ -35,7 +35,7 @@ def test_default_params():
     assert p.n_proxy == 64 and p.proxy_ratio == 1.5 and p.rcond_min == 1e-12
     assert p.precision == 0 and p.refine_tol == 1e-8 and p.refine_max == 0
     assert p.has_root == 0 and p.solve_graph == 1 and p.mixed_rcond_min == 1e-4 and p.apply_shape == -1
-    assert p.refine_update == 1
+    assert p.refine_update == 1 and p.kernel == 0
 
 
 def _geom():
@@ -43,7 +43,7 @@ def _geom():
 
 
 @pytest.mark.parametrize("bad", ["nan_xy", "normal_len", "weight", "curve_id", "tol", "empty_hole",
-                                 "mixed_rcond", "refine_update"])
+                                 "mixed_rcond", "refine_update", "kernel", "laplace_precision"])
 def test_invalid_input_rejected(bad):
     g = _geom()
     xy, nrm, w, kap, cid = g.xy.copy(), g.normal.copy(), g.weight.copy(), g.curvature.copy(), g.curve_id.copy()
@@ -62,6 +62,11 @@ def test_invalid_input_rejected(bad):
         kw["mixed_rcond_min"] = float("nan")
     elif bad == "refine_update":
         kw["refine_update"] = 2
+    elif bad == "kernel":
+        kw["kernel"] = 2
+    elif bad == "laplace_precision":
+        kw["kernel"] = 1
+        kw["precision"] = 2
     elif bad == "empty_hole":
         cid[cid == 1] = 0
         cid[0] = 2           # hole 1 has no nodes, hole 2 has one
@@ -75,3 +80,22 @@ def test_fixed_root_must_contain_nodes():
     with pytest.raises(RSError) as e:
         RSSolver.from_geometry(g, root=(0.0, 0.0, 1.0))
     assert e.value.name == "RS_ERR_OUT_OF_ROOT"
+
+
+def test_laplace_kernel_rejects_holes():
+    """The Laplace Neumann kernel has no augmentation: a direct call with holes
+    is refused before anything reaches the device."""
+    import ctypes
+
+    from paper_2001_11619_amd.binding import _dptr, _iptr, load_library
+
+    g = _geom()
+    lib = load_library()
+    p = default_params()
+    p.kernel = 1
+    h = ctypes.c_void_p()
+    cid = np.ascontiguousarray(g.curve_id, dtype=np.int32)
+    st = lib.rs_build_tree(ctypes.byref(p), g.n_nodes, _dptr(np.ascontiguousarray(g.xy)),
+                           _dptr(np.ascontiguousarray(g.normal)), _dptr(g.weight), _dptr(g.curvature),
+                           _iptr(cid), int(cid.max()), None, ctypes.byref(h))
+    assert st == 1 and not h.value          # RS_ERR_ARG, no context
