@@ -259,6 +259,116 @@ def run_holes(args):
                        "inserted_nodes": 1792}, **out}
 
 
+def run_laplace(args):
+    """The heat-flux workload of Section 4.4.1 (Laplace Neumann, kernel 1):
+    16384 nodes on a starfish holding two starfish holes 16% of its size,
+    flux 0 / +1 / -1 (eq. neumanndata), holes at theta = (0.4, 3.0) on their
+    path (away from the mirror-symmetric (0, pi), where the gradient of the
+    objective vanishes by symmetry).  Timed: the
+    factorization and the refined solve of the base geometry, then one step
+    of the section's finite-difference gradient of the objective d u / d x at
+    the centre (fourth-order stencil: theta_i +- h, +- 2h, eight related
+    geometries) three ways -- eight fresh factorizations in one batch, the
+    eight updates of factored contexts in one batch (Scheme A's independent
+    updates, in shared launches), and one context updated eight times in
+    turn -- each followed by the eight refined solves and evaluations."""
+    import numpy as np
+    import torch
+
+    from paper_2001_11619_amd import RSSolver, factor_batch, update_moved_nodes_batch
+    from workloads import neumann_flux, starfish_geometry
+
+    n, theta, h = 16384, (0.4, 3.0), 0.01
+    kw = dict(kernel=1, tol=args.laplace_tol, precision=1, refine_max=20, refine_tol=1e-10,
+              root=(0.0, 0.0, 2.6))
+    stream = torch.cuda.current_stream().cuda_stream
+    centre = np.zeros((1, 2))
+
+    def make(g):
+        sv = RSSolver.from_geometry(g, **kw)
+        sv.set_stream(stream)
+        return sv
+
+    def moved(g0, g1):
+        m = np.nonzero(np.any(g0.xy != g1.xy, axis=1))[0].astype(np.int32)
+        return (m, g1.xy[m], g1.normal[m], g1.weight[m], g1.curvature[m])
+
+    def solve_obj(sv, g):
+        x = sv.solve(RSSolver.embed_scalar(neumann_flux(g.curve_id)))
+        return float(sv.evaluate(centre, x)[0, 1]), sv.stats()["refine_iters"]
+
+    base = starfish_geometry(n, *theta)
+    s = make(base)
+    for _ in range(1 + args.warmup):
+        s.factor()
+    fac_ms = []
+    for _ in range(args.steps):
+        s.factor()
+        fac_ms.append(s.stats()["ms_factor"])
+    obj0, it0 = solve_obj(s, base)
+    sol_ms = []
+    for _ in range(args.steps):
+        solve_obj(s, base)
+        sol_ms.append(s.stats()["ms_solve"])
+    shifts = [(k * h, 0.0) for k in (-2, -1, 1, 2)] + [(0.0, k * h) for k in (-2, -1, 1, 2)]
+    geoms = [starfish_geometry(n, theta[0] + a, theta[1] + b) for a, b in shifts]
+    out = {}
+    # eight fresh factorizations, one batch
+    print("laplace: fresh batch", file=sys.stderr, flush=True)
+    fresh = [make(gk) for gk in geoms]
+    factor_batch(fresh)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    factor_batch(fresh)
+    torch.cuda.synchronize()
+    out["fresh_batch_factor_ms"] = 1e3 * (time.perf_counter() - t)
+    # eight updates of factored contexts, one batch
+    print("laplace: update batch", file=sys.stderr, flush=True)
+    ctx = [make(base) for _ in geoms]
+    factor_batch(ctx)
+    update_moved_nodes_batch(ctx, [moved(base, gk) for gk in geoms])      # warm-up of the update path
+    update_moved_nodes_batch(ctx, [moved(gk, base) for gk in geoms])
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    update_moved_nodes_batch(ctx, [moved(base, gk) for gk in geoms])
+    torch.cuda.synchronize()
+    out["batch_update_ms"] = 1e3 * (time.perf_counter() - t)
+    t = time.perf_counter()
+    objs = [solve_obj(sv, gk)[0] for sv, gk in zip(ctx, geoms)]
+    out["solves_and_objective_ms"] = 1e3 * (time.perf_counter() - t)
+    xf = fresh[0].solve(RSSolver.embed_scalar(neumann_flux(geoms[0].curve_id)))
+    xu = ctx[0].solve(RSSolver.embed_scalar(neumann_flux(geoms[0].curve_id)))
+    out["update_equals_fresh_bitwise"] = bool(np.array_equal(xf, xu))
+    # one context updated eight times in turn
+    print("laplace: sequential updates", file=sys.stderr, flush=True)
+    t = time.perf_counter()
+    prev = base
+    upd = []
+    for gk in geoms:
+        s.update_moved_nodes(*moved(prev, gk))
+        upd.append(s.stats()["ms_update"])
+        solve_obj(s, gk)
+        prev = gk
+    out["sequential_update_and_solve_ms"] = 1e3 * (time.perf_counter() - t)
+    out["sequential_update_ms_median"] = float(np.median(upd))
+    o = np.array(objs)
+    grad = [float((-o[3] + 8 * o[2] - 8 * o[1] + o[0]) / (12 * h)), float((-o[7] + 8 * o[6] - 8 * o[5] + o[4]) / (12 * h))]
+    step_ms = out["batch_update_ms"] + out["solves_and_objective_ms"]
+    for sv in fresh + ctx + [s]:
+        sv.close()
+    return {
+        "metric": "Laplace Neumann (Section 4.4.1) finite-difference step: related geometries updated in one "
+                  "batch, solved to 1e-10 and the objective evaluated",
+        "value": 8 * 1e3 / step_ms, "unit": "geometries/s", "higher_is_better": True, "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "data": "synthetic", "dtype": "f32+f64",
+        "config": {"workload": "starfish16384_2holes_laplace", "n_nodes": n, "theta": list(theta), "fd_h": h,
+                   "tol": args.laplace_tol, "refine_tol": 1e-10},
+        "factor_ms_median": float(np.median(fac_ms)), "solve_ms_median": float(np.median(sol_ms)),
+        "refine_iters": int(it0), "objective_du_dx_centre": obj0, "fd_gradient": grad,
+        "fd_step_ms": step_ms, **out,
+    }
+
+
 def make_geometry(name):
     import workloads as W
 
@@ -516,7 +626,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="circle40_64holes", choices=sorted(WORKLOADS) + ["batch", "evolve", "holes"])
+    ap.add_argument("--workload", default="circle40_64holes", choices=sorted(WORKLOADS) + ["batch", "evolve", "holes", "laplace"])
     ap.add_argument("--tol-plain", type=float, default=1e-10)
     ap.add_argument("--tol-mixed", type=float, default=None,
                     help="ID tolerance of the mixed form (default: per workload, the fastest that "
@@ -532,6 +642,7 @@ def main():
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="before the timed steps, one device copy of this many MiB (the reference "
                          "dispatch for calibrating HBM byte counters)")
+    ap.add_argument("--laplace-tol", type=float, default=1e-7)
     ap.add_argument("--evolve-steps", type=int, default=100)
     ap.add_argument("--evolve-all", action="store_true", help="move hole 1, 2, 3, ... in turn")
     args = ap.parse_args()
@@ -553,6 +664,9 @@ def main():
         return
     if args.workload == "evolve":
         print(json.dumps(run_evolve(args)), flush=True)
+        return
+    if args.workload == "laplace":
+        print(json.dumps(run_laplace(args)), flush=True)
         return
     if args.workload == "holes":
         print(json.dumps(run_holes(args)), flush=True)

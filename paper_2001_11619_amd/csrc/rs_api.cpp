@@ -526,10 +526,13 @@ void build_neighbors(rs_ctx* c) {
     B.near_same.clear();
     B.near_leaf.clear();
     if (B.leaf()) {
+      // the Laplace Neumann kernel's second unknown per node is uncoupled
+      // (row lambda x): it joins no box and the solve divides it by lambda
+      const bool both = c->prm.kernel != 1;
       B.dofs.reserve(2 * B.nodes.size());
       for (int j : B.nodes) {
         B.dofs.push_back(2 * j);
-        B.dofs.push_back(2 * j + 1);
+        if (both) B.dofs.push_back(2 * j + 1);
       }
       std::sort(B.dofs.begin(), B.dofs.end());
     }
@@ -2025,6 +2028,9 @@ void solve_rows(rs_ctx* c, T* cbuf, int ncols, const double* rbot) {
     HIP_CHECK(hipMemcpyAsync(dst, lam, (size_t)p3 * ncols * sizeof(T), hipMemcpyDeviceToDevice, s));
   }
   sweep_all<T>(c, cbuf, ncols, 2);
+  // Laplace Neumann: the uncoupled second unknown of each node is in no box;
+  // its equation is lambda x = b
+  if (c->prm.kernel == 1) launch_scale_odd_rows(cbuf, c->N, ncols, 1.0 / c->prm.lambda, s);
 }
 
 // out (float64 rows, 2N+3p) = factored inverse applied to rhs (float64 rows,

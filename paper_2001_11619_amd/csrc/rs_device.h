@@ -136,8 +136,8 @@ __device__ __forceinline__ double sl_entry(double rx, double ry, double w, int a
 // ---- the Laplace Neumann kernel (Section 4.4.1) ------------------------------
 // Operator lam I - D + N with D the adjoint double layer (normal at the
 // target) and N mu = the integral of mu.  Its density lives in component 0 of
-// each node; component 1 is an uncoupled unknown with the row lam x, so the
-// two-unknowns-per-node layout of the Stokes path carries it unchanged.
+// each node; component 1 is an uncoupled unknown with the row lam x (kept so
+// that vectors have the Stokes path's two-per-node layout; it joins no box).
 
 // -D between distinct points: (1/2pi) ((x - y) . n_x) / |x - y|^2 w_y.
 __device__ __forceinline__ double lap_dl(double rx, double ry, double nx, double ny, double w) {

@@ -94,8 +94,9 @@ __global__ __launch_bounds__(kBlock) void k_assemble_M(const LevelBox* boxes, in
       // source side, the potential and normal flux on the proxy circle of the
       // box's charges plus their total (the rank-one row); target side, the
       // normal derivative at the nodes of a proxy charge and a proxy dipole,
-      // plus the constant row of N.  The second unknown of a node is
-      // uncoupled: its columns are zero.  The Stokeslet rows (type 4) are zero.
+      // plus the constant row of N.  The Stokeslet rows (type 4) are zero.
+      // (The uncoupled second unknown of a node joins no box; were one
+      // passed, its column would be zero.)
       for (int cc = 0; cc < cnt; ++cc) {
         const int d = sj[cc];
         const int j = d >> 1, jc = d & 1;

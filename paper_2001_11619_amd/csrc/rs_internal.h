@@ -183,6 +183,7 @@ void launch_dense_apply(const double* Zinv, int nz, const double* v, int ncols, 
 template <typename T>
 void launch_root_scatter(const double* sol, int ncols, const int* I0, int n0, T* c, hipStream_t s);
 void launch_fill(double* x, long long n, double v, hipStream_t s);
+void launch_scale_odd_rows(double* x, int N, int ncols, double scale, hipStream_t s);
 // flag: 4 ints (converged, iterations, next residual updated, a pair dropped);
 // acc: per column, the accumulated rounding bound of updated residuals
 void launch_refine_flag(const double* colsq, const double* fsq, const double* bsq, double* acc, int ncols,

@@ -580,6 +580,20 @@ void launch_set_ints(int* p, int n, int v, hipStream_t s) {
   hipLaunchKernelGGL(k_set_ints, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, p, n, v);
 }
 
+// Rows 2i + 1 (i < N) of a rows-layout block times `scale`: the Laplace Neumann
+// kernel's uncoupled unknowns, whose diagonal entry lambda the solve divides by.
+__global__ void k_scale_odd_rows(double* x, int N, int ncols, double scale) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)N * ncols) return;
+  const long long i = t / ncols, q = t % ncols;
+  x[(2 * i + 1) * ncols + q] *= scale;
+}
+
+void launch_scale_odd_rows(double* x, int N, int ncols, double scale, hipStream_t s) {
+  const long long n = (long long)N * ncols;
+  if (n) hipLaunchKernelGGL(k_scale_odd_rows, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, x, N, ncols, scale);
+}
+
 void launch_fill(double* x, long long n, double v, hipStream_t s) {
   if (n) hipLaunchKernelGGL(k_fill, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, s, x, n, v);
 }

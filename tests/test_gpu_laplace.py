@@ -85,6 +85,11 @@ def test_direct_solve_matches_oracle(n, leaf):
     x, res = s.solve(_embed(F), residual=True)
     mu = x[0::2]
     assert np.abs(x[1::2]).max() <= 1e-14 * np.abs(mu).max()        # the uncoupled unknowns stay 0
+    # the uncoupled unknowns: x = b / lambda there, the density unaffected
+    Fe = _embed(F)
+    Fe[1::2] = rng.standard_normal(F.shape)
+    x2 = s.solve(Fe)
+    assert np.array_equal(x2[0::2], mu) and np.array_equal(x2[1::2], Fe[1::2] / -0.5)
     mo = L.solve(g, F)
     err = np.abs(mu - mo).max(axis=0) / np.abs(mo).max(axis=0)
     print("Laplace direct solve N=%d: element-wise error %s, residual %s, ranks at the leaves %d"

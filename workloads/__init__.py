@@ -32,4 +32,5 @@ from .rhs import (  # noqa: F401
     stokeslet_velocity,
     boundary_data,
     exterior_forces_for_geometry,
+    neumann_flux,
 )

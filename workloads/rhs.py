@@ -84,3 +84,11 @@ def exterior_forces_for_geometry(geom: Geometry, ncols: int, seed: int) -> List[
                 forces.append(PointForce(z, rng.standard_normal(2), int(h) + 1))
         cols.append(forces)
     return cols
+
+
+def neumann_flux(curve_id) -> np.ndarray:
+    """The heat-flux data of the Laplace Neumann workload (eq. (neumanndata) of
+    Section 4.4.1): 0 on the outer curve, +1 on the first hole, -1 on the
+    second."""
+    c = np.asarray(curve_id)
+    return np.where(c == 1, 1.0, np.where(c == 2, -1.0, 0.0))
