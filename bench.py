@@ -543,7 +543,7 @@ def kernel_source_hash(names):
 
 
 def measured_traffic(fam, workload, form, tol):
-    """HBM bytes per launch of the roofline kernel family from the committed
+    """HBM bytes per launch (per step for the QR family) of the roofline kernel family from the committed
     counter summary (FETCH_SIZE and WRITE_SIZE runs, copy-calibrated), or None
     when the summary is for another workload, form or tolerance ("any" where
     they do not change the kernel's work), or the kernels changed since."""
@@ -566,10 +566,14 @@ def measured_traffic(fam, workload, form, tol):
             return None
     if vals.get("kernel_source_sha256") != kernel_source_hash(srcs):
         return None
-    try:
-        return float(vals["fetch_bytes_per_launch"]) + float(vals["write_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+    # the apply families are counted per launch, the QR family per step (one
+    # factorization), matching the roofline's traffic_unit
+    for unit in ("launch", "step"):
+        try:
+            return float(vals["fetch_bytes_per_" + unit]) + float(vals["write_bytes_per_" + unit])
+        except (KeyError, ValueError):
+            continue
+    return None
 
 
 def roofline_of(run, steps, nrhs, n_nodes, workload, form, tol, fam):
