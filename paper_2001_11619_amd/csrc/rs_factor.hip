@@ -919,6 +919,40 @@ static_assert(kPanelThreads % kGJB == 0, "the panel update deals rows to kPanelT
 // LDS of h * bb doubles), else in the global work array W.
 constexpr size_t kPanelLdsBytes = 136 * 1024;
 
+// D^{-1} = U^{-1} L^{-1} for the pivot block D = L U of a panel (lu holds L
+// below the diagonal, unit diagonal implied, and U on and above it; bb <=
+// kGJB).  Thread c < bb builds column c in registers: x = L^{-1} e_c by forward
+// substitution, then U^{-1} x by back substitution, with the rows of lu read
+// by broadcast from LDS.  Kept in registers, the substitutions are chains of
+// FMAs; built in LDS, every step waited for the previous step's store.
+__device__ __forceinline__ void pivot_block_inverse(const double (*lu)[kGJB + 1], const int bb, double* Dinv) {
+  const int c = threadIdx.x;
+  if (c >= bb) return;
+  double x[kGJB];
+#pragma unroll
+  for (int i = 0; i < kGJB; ++i) {
+    double s = (i == c) ? 1.0 : 0.0;
+    if (i < bb) {
+#pragma unroll
+      for (int l = 0; l < i; ++l) s -= lu[i][l] * x[l];
+    }
+    x[i] = s;
+  }
+#pragma unroll
+  for (int i = kGJB - 1; i >= 0; --i) {
+    if (i < bb) {
+      double s = x[i];
+#pragma unroll
+      for (int l = i + 1; l < kGJB; ++l)
+        if (l < bb) s -= lu[i][l] * x[l];
+      x[i] = s / lu[i][i];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < kGJB; ++i)
+    if (i < bb) Dinv[i * bb + c] = x[i];
+}
+
 __global__ __launch_bounds__(kPanelThreads) void k_gjb_panel(const double* A, int n, int k0, int bb,
                                                               double* Wg, int* piv, double* Dinv,
                                                               int* status, int in_lds) {
@@ -927,7 +961,6 @@ __global__ __launch_bounds__(kPanelThreads) void k_gjb_panel(const double* A, in
   __shared__ double red[NW];
   __shared__ int ired[NW];
   __shared__ double lu[kGJB][kGJB + 1];
-  __shared__ double inv[kGJB][kGJB + 1];
   __shared__ int spiv[kGJB];   // pivot rows, written out once at the end (see k_gjb_panel_reg)
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   if (*(volatile const int*)status) return;
@@ -1040,23 +1073,7 @@ __global__ __launch_bounds__(kPanelThreads) void k_gjb_panel(const double* A, in
   // D = L U (first bb rows of W); D^{-1} = U^{-1} L^{-1}
   for (int t = tid; t < bb * bb; t += kPanelThreads) lu[t / bb][t % bb] = W[(size_t)(t / bb) * ldw + t % bb];
   __syncthreads();
-  // columns of L^{-1} (unit lower) then U^{-1} applied: one thread per
-  // column, which it builds in place in its column of inv
-  if (tid < bb) {
-    const int c = tid;
-    for (int i = 0; i < bb; ++i) {
-      double s = (i == c) ? 1.0 : 0.0;
-      for (int l = 0; l < i; ++l) s -= lu[i][l] * inv[l][c];
-      inv[i][c] = s;
-    }
-    for (int i = bb - 1; i >= 0; --i) {
-      double s = inv[i][c];
-      for (int l = i + 1; l < bb; ++l) s -= lu[i][l] * inv[l][c];
-      inv[i][c] = s / lu[i][i];
-    }
-  }
-  __syncthreads();
-  for (int t = tid; t < bb * bb; t += kPanelThreads) Dinv[t] = inv[t / bb][t % bb];
+  pivot_block_inverse(lu, bb, Dinv);
   for (int t = tid; t < bb; t += kPanelThreads) piv[t] = spiv[t];
 }
 
@@ -1084,7 +1101,6 @@ __global__ __launch_bounds__(NT) void k_gjb_panel_reg(const double* A, int n, in
   __shared__ double cand[2][NW][kGJB];   // each wave's candidate row (by step parity)
   __shared__ double srow[2][kGJB];        // row j before the interchange
   __shared__ double lu[kGJB][kGJB + 1];
-  __shared__ double inv[kGJB][kGJB + 1];
   __shared__ int spiv[kGJB];              // pivot rows, written out at the end
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   if (*(volatile const int*)status) return;
@@ -1169,21 +1185,7 @@ __global__ __launch_bounds__(NT) void k_gjb_panel_reg(const double* A, int n, in
     // before the next step's barrier
   }
   __syncthreads();
-  if (tid < bb) {
-    const int c = tid;
-    for (int i = 0; i < bb; ++i) {
-      double sum = (i == c) ? 1.0 : 0.0;
-      for (int l = 0; l < i; ++l) sum -= lu[i][l] * inv[l][c];
-      inv[i][c] = sum;
-    }
-    for (int i = bb - 1; i >= 0; --i) {
-      double sum = inv[i][c];
-      for (int l = i + 1; l < bb; ++l) sum -= lu[i][l] * inv[l][c];
-      inv[i][c] = sum / lu[i][i];
-    }
-  }
-  __syncthreads();
-  for (int t = tid; t < bb * bb; t += NT) Dinv[t] = inv[t / bb][t % bb];
+  pivot_block_inverse(lu, bb, Dinv);
   for (int t = tid; t < bb; t += NT) piv[t] = spiv[t];
 }
 
@@ -1401,9 +1403,17 @@ void launch_gj_blocked(double* A, int n, double* Ainv, double* work, int* iwork,
     // stay in global memory); the blocking depends on n only
     const int h = n - k0;
     int bb = std::min(kGJB, h);
-    if (h <= 1024) {
-      // rows in registers: full-width panels
-      hipLaunchKernelGGL((k_gjb_panel_reg<1024, 1>), dim3(1), dim3(1024), 0, s, A, n, k0, bb, piv, Dinv, status);
+    // rows in registers: full-width panels.  The fewest waves that hold the
+    // rows: a step's barrier and candidate exchange cost less with fewer
+    // waves, and below 1024 threads the registers hold the whole step without
+    // spilling.  The pivot rule and every row's arithmetic do not depend on
+    // the thread count, so the results are bitwise the same.
+    if (h <= 256) {
+      hipLaunchKernelGGL((k_gjb_panel_reg<256, 1>), dim3(1), dim3(256), 0, s, A, n, k0, bb, piv, Dinv, status);
+    } else if (h <= 512) {
+      hipLaunchKernelGGL((k_gjb_panel_reg<512, 1>), dim3(1), dim3(512), 0, s, A, n, k0, bb, piv, Dinv, status);
+    } else if (h <= 1024) {
+      hipLaunchKernelGGL((k_gjb_panel_reg<512, 2>), dim3(1), dim3(512), 0, s, A, n, k0, bb, piv, Dinv, status);
     } else if (h <= 1536) {
       hipLaunchKernelGGL((k_gjb_panel_reg<512, 3>), dim3(1), dim3(512), 0, s, A, n, k0, bb, piv, Dinv, status);
     } else {
