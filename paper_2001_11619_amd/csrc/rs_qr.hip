@@ -70,7 +70,12 @@ __global__ __launch_bounds__(kQRThreads) void k_cpqr(const LevelBox* boxes, cons
       sum += a * a;
     }
     sum = wave_sum(sum);
-    if (lane == 0) nrm[c] = sum;
+    if (lane == 0) {
+      nrm[c] = sum;
+      // a non-finite column would never win a pivot comparison and be left
+      // out silently: flag it (the host reports non-finite entries)
+      if (!isfinite(sum)) __hip_atomic_store(err + 2, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
   }
   __syncthreads();
   const int steps = min(m, n);
@@ -389,7 +394,10 @@ __device__ __forceinline__ void cpqr_reg_box(const LevelBox& B, const int G, con
         double t = 0.0;
 #pragma unroll
         for (int u = 0; u < RU; ++u) t += a[sl][u] * a[sl][u];
-        arg_better(bv, bi, pivot_key(wave_sum_fast(t)), c);
+        const double nn = wave_sum_fast(t);
+        // a non-finite column would never win a pivot comparison: flag it
+        if (!isfinite(nn) && lane == 0) __hip_atomic_store(err + 2, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        arg_better(bv, bi, pivot_key(nn), c);
       }
     }
     if (lane == 0) { wv[wid] = bv; wi[wid] = bi; }
@@ -722,6 +730,9 @@ __device__ __forceinline__ void cpqr16_box(const LevelBox& B, const double tol, 
     for (int sl = 0; sl < NS; ++sl) {
       const int c = 4 * (wid + kRQWaves * sl) + rg;
       const double nn = row16_sum(t[sl]);
+      // a non-finite column would never win a pivot comparison: flag it
+      if (c < n && !isfinite(nn) && p == 0)
+        __hip_atomic_store(err + 2, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (c < n) arg_better(bv, bi, pivot_key(nn), c);
     }
     publish(bv, bi);
