@@ -21,6 +21,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <exception>
 #include <thread>
 #include <tuple>
 #include <unordered_map>
@@ -248,6 +249,7 @@ struct rs_ctx {
 
   // refinement iterations captured as a HIP graph (rebuilt after each factorization)
   long long factor_epoch = 0;
+  bool root_pending = false;   // the root inverse was launched and not yet joined
   bool capturing = false;
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t refine_exec = nullptr;   // one refinement iteration
@@ -423,8 +425,27 @@ class HostPool {
     static HostPool pool;
     return pool;
   }
-  void run(int n, const std::function<void(int)>& f) {
-    if (n < kSerialBelow || workers_.empty()) {
+  // f(0 .. n-1) over the pool.  Fine-grained items (n below kSerialBelow run
+  // inline); a call made from inside pool work runs inline too, so a task of
+  // run_tasks may itself call run.
+  void run(int n, const std::function<void(int)>& f) { run_impl(n, f, kSerialBelow, false); }
+  // Coarse tasks (one per context of a batch): every task may go to its own
+  // thread.  An exception of a task is rethrown here once all have ended.
+  void run_tasks(int n, const std::function<void(int)>& f) {
+    std::vector<std::exception_ptr> errs(std::max(n, 0));
+    const std::function<void(int)> g = [&](int i) {
+      try {
+        f(i);
+      } catch (...) {
+        errs[i] = std::current_exception();
+      }
+    };
+    run_impl(n, g, 2, true);
+    for (auto& e : errs)
+      if (e) std::rethrow_exception(e);
+  }
+  void run_impl(int n, const std::function<void(int)>& f, int serial_below, bool unit_chunks) {
+    if (n < serial_below || workers_.empty() || tl_in_pool) {
       for (int i = 0; i < n; ++i) f(i);
       return;
     }
@@ -433,13 +454,15 @@ class HostPool {
       std::lock_guard<std::mutex> lk(mu_);
       fn_ = &f;
       n_ = n;
-      chunk_ = std::max(1, n / (4 * (int)(workers_.size() + 1)));
+      chunk_ = unit_chunks ? 1 : std::max(1, n / (4 * (int)(workers_.size() + 1)));
       next_.store(0);
       active_.store((int)workers_.size());
       gen_.fetch_add(1, std::memory_order_release);
     }
     cv_.notify_all();
+    tl_in_pool = true;
     work();
+    tl_in_pool = false;
     while (active_.load(std::memory_order_acquire) != 0) std::this_thread::yield();
     fn_ = nullptr;
   }
@@ -458,8 +481,13 @@ class HostPool {
   HostPool() {
     const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
     const int nthreads = (int)std::min(8u, hw);
-    for (int i = 0; i + 1 < nthreads; ++i) workers_.emplace_back([this] { loop(); });
+    for (int i = 0; i + 1 < nthreads; ++i)
+      workers_.emplace_back([this] {
+        tl_in_pool = true;
+        loop();
+      });
   }
+  static thread_local bool tl_in_pool;
   void work() {
     for (;;) {
       const int b = next_.fetch_add(chunk_);
@@ -500,6 +528,7 @@ class HostPool {
   std::atomic<bool> stop_{false};
   std::atomic<int> next_{0};
 };
+thread_local bool HostPool::tl_in_pool = false;
 
 // Leaf unknowns and the near-box lists of every box (static for a tree).  A
 // box is listed when the distance from the compressed box's centre to its
@@ -1634,7 +1663,12 @@ void sweep_all(rs_ctx* c, T* buf, int ncols, int mode, hipStream_t on = nullptr)
 void ensure_solve_buffers(rs_ctx* c, int ncols);
 void refine_graph_capture(rs_ctx* c, int nrhs);
 
-void factor_root(rs_ctx* c) {
+// The root (Section 3.2's bordered system when there are holes) in two parts:
+// factor_root_launch enqueues everything and leaves the inverse running on the
+// context's side stream; factor_root_finish joins it and checks its status.
+// A batch launches every context's root before it waits for any, so the
+// root inverses (single-workgroup chains of pivot steps) run side by side.
+void factor_root_launch(rs_ctx* c) {
   HTimer ht_(c, "host:root");
   hipStream_t s = c->stream;
   Geo g;
@@ -1724,13 +1758,16 @@ void factor_root(rs_ctx* c) {
     }
     Zsrc = c->d_Z.as<double>();
   }
+  c->root_pending = false;
   if (nz > 0) {
+    hipStream_t s2 = fork_side(c);
     {
-      KTimer kt_(c, "root_inverse");
+      KTimer kt_(c, "root_inverse", false, s2);
       launch_gj_blocked(const_cast<double*>(Zsrc), nz, c->d_Zinv.as<double>(), c->d_gjwork.as<double>(),
-                        c->d_gjiwork.as<int>(), c->d_rstatus.as<int>(), s);
+                        c->d_gjiwork.as<int>(), c->d_rstatus.as<int>(), s2);
     }
     HIP_CHECK(hipGetLastError());
+    c->root_pending = true;
     // While the root inverse runs, the refinement graph for the last solve's
     // number of right-hand sides is captured anew (capture records launches
     // only; the factors' buffers and the solve metadata are final here).  A
@@ -1739,13 +1776,20 @@ void factor_root(rs_ctx* c) {
       ensure_solve_buffers(c, c->refine_nrhs);
       refine_graph_capture(c, c->refine_nrhs);
     }
-    int st = 0;
-    HIP_CHECK(hipMemcpyAsync(&st, c->d_rstatus.p, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIP_CHECK(hipStreamSynchronize(s));
-    resolve_timers(c);
-    if (st) throw RsError{RS_ERR_SINGULAR, "root system is singular"};
   }
   c->stats.root_skeleton = n0;
+}
+
+void factor_root_finish(rs_ctx* c) {
+  if (!c->root_pending) return;
+  HTimer ht_(c, "host:root_wait");
+  c->root_pending = false;
+  join_side(c);
+  int st = 0;
+  HIP_CHECK(hipMemcpyAsync(&st, c->d_rstatus.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIP_CHECK(hipStreamSynchronize(c->stream));
+  resolve_timers(c);
+  if (st) throw RsError{RS_ERR_SINGULAR, "root system is singular"};
 }
 
 // Return factor arenas no box refers to any more to the pool.
@@ -1890,8 +1934,10 @@ void do_factor_multi(std::vector<rs_ctx*>& cs) {
     } else {
       if (pre_pending) HIP_CHECK(hipStreamWaitEvent(c0->stream, c0->ev_pre, 0));
       preps.assign(nc, LevelPrep());
-      for (size_t i = 0; i < nc; ++i)
+      // the contexts of a batch are independent here: one host thread each
+      HostPool::instance().run_tasks((int)nc, [&](int i) {
         if (cs[i]->L >= l) prepare_level(cs[i], l, by_level[i][l], active[i], preps[i]);
+      });
     }
     have_next = false;
     pre_pending = false;
@@ -1918,8 +1964,9 @@ void do_factor_multi(std::vector<rs_ctx*>& cs) {
         hipStream_t s2 = c0->side_stream;
         HIP_CHECK(hipStreamWaitEvent(s2, c0->ev_qr, 0));
         next.assign(nc, LevelPrep());
-        for (size_t i = 0; i < nc; ++i)
+        HostPool::instance().run_tasks((int)nc, [&](int i) {
           if (cs[i]->L >= l - 1) prepare_level(cs[i], l - 1, by_level[i][l - 1], act[i], next[i]);
+        });
         next_plan = LevelPlan();
         c0->cur_level = l - 1;
         plan_level(cs, next, next_plan);
@@ -1950,9 +1997,12 @@ void do_factor_multi(std::vector<rs_ctx*>& cs) {
   }
   cs[0]->cur_level = -1;
   for (size_t i = 0; i < nc; ++i) {
+    cs[i]->factor_epoch++;
+    factor_root_launch(cs[i]);
+  }
+  for (size_t i = 0; i < nc; ++i) {
     rs_ctx* c = cs[i];
-    c->factor_epoch++;
-    factor_root(c);
+    factor_root_finish(c);
     collect_arenas(c);
     c->factored = true;
     c->stats.boxes_recomputed = 0;
