@@ -3231,9 +3231,12 @@ rs_status rs_update_moved_nodes_batch(rs_ctx** ctxs, int n, const int* n_moved, 
   std::vector<OldState> Os(n);
   auto t0 = std::chrono::steady_clock::now();
   try {
-    for (int i = 0; i < n; ++i)
+    // the contexts' new trees and geometry uploads are independent: one host
+    // thread each
+    HostPool::instance().run_tasks(n, [&](int i) {
       begin_update(cs[i], n_moved[i], idx[i], xy[i], normal[i], weight[i], curvature[i],
                    hole_xy ? hole_xy[i] : nullptr, Os[i]);
+    });
     do_factor_multi(cs);
   } catch (const RsError& e) {
     rs_status st = RS_OK;
