@@ -305,6 +305,22 @@ def run_laplace(args):
     for _ in range(args.steps):
         s.factor()
         fac_ms.append(s.stats()["ms_factor"])
+    # roofline of the factorization's largest kernel family, the pivoted QR
+    # (timing mode 3: events around its launches only), with the method's own
+    # flop count per factorization
+    s.set_kernel_timing(3)
+    s.kernel_times(reset=True)
+    s.factor()
+    qr_launches, qr_ms = s.kernel_times(reset=True).get("cpqr", (0, 0.0))
+    s.set_kernel_timing(0)
+    qr_work = float(s.stats()["flops_id"])
+    roof = None
+    if qr_ms > 0:
+        ach = qr_work / (qr_ms / 1e3) / 1e12
+        roof = {"bound": "alu", "kernel": "cpqr", "achieved": ach, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": ach / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                "work": qr_work, "work_unit": "flops per factorization (sum of the boxes' pivoted-QR + T counts)",
+                "launches_per_step": qr_launches, "ms_per_step": qr_ms}
     obj0, it0 = solve_obj(s, base)
     sol_ms = []
     for _ in range(args.steps):
@@ -366,6 +382,7 @@ def run_laplace(args):
         "steps": args.steps, "warmup": args.warmup, "data": "synthetic", "dtype": "f32+f64",
         "config": {"workload": "starfish16384_2holes_laplace", "n_nodes": n, "theta": list(theta), "fd_h": h,
                    "tol": args.laplace_tol, "refine_tol": 1e-10},
+        "roofline": roof,
         "factor_ms_median": float(np.median(fac_ms)), "solve_ms_median": float(np.median(sol_ms)),
         "refine_iters": int(it0), "objective_du_dx_centre": obj0, "fd_gradient": grad,
         "fd_step_ms": step_ms, **out,
