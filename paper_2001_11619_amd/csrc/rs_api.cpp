@@ -872,7 +872,9 @@ void prepare_level(rs_ctx* c, int l, const std::vector<int>& ids, const std::vec
     for (int d : f.I) x.wscale = std::max(x.wscale, c->w[d >> 1]);
     x.n = f.n;
     x.nF = (int)F.size();
-    x.m = 2 * x.nF + 6 * prm.n_proxy + 2;
+    // near field both ways, 2 rows per proxy point in each proxy block (three
+    // blocks for Stokes, two for the Laplace kernel), the two rank-one rows
+    x.m = 2 * x.nF + (prm.kernel == 1 ? 4 : 6) * prm.n_proxy + 2;
     x.geo = g;
     P.doff.push_back((int)dofs.size());
     soff.push_back(B.leaf() ? -1 : (int)src_all.size());

@@ -31,6 +31,9 @@ __global__ __launch_bounds__(kBlock) void k_assemble_M(const LevelBox* boxes, in
   const int* I = B.dofs;
   const Geo& g = B.geo;
   const int np2 = 2 * n_proxy;
+  // proxy row blocks: D(P,B), D(B,P)^T and S(B,P)^T; the Laplace kernel has no
+  // Stokeslet block
+  const int npb = g.kernel == 1 ? 2 : 3;
   const double rp = ratio * B.side;
   // target-side proxy rows and the target-side rank-one row carry the scale
   // of one boundary interaction: the box's largest node weight
@@ -45,7 +48,7 @@ __global__ __launch_bounds__(kBlock) void k_assemble_M(const LevelBox* boxes, in
   } else if (i < 2 * nF) {
     type = 1;
     f = B.fint[i - nF];
-  } else if (i < 2 * nF + 3 * np2) {
+  } else if (i < 2 * nF + npb * np2) {
     const int t = i - 2 * nF;
     type = 2 + t / np2;
     const int u = t % np2;
@@ -57,7 +60,7 @@ __global__ __launch_bounds__(kBlock) void k_assemble_M(const LevelBox* boxes, in
     px = B.cx + rp * pnx;
     py = B.cy + rp * pny;
   } else {
-    type = 5 + (i - 2 * nF - 3 * np2);
+    type = 5 + (i - 2 * nF - npb * np2);
   }
   const int fj = f >> 1, fc = f & 1;
   double fx = 0, fy = 0, fnx = 0, fny = 0, fw = 0;
@@ -94,9 +97,8 @@ __global__ __launch_bounds__(kBlock) void k_assemble_M(const LevelBox* boxes, in
       // source side, the potential and normal flux on the proxy circle of the
       // box's charges plus their total (the rank-one row); target side, the
       // normal derivative at the nodes of a proxy charge and a proxy dipole,
-      // plus the constant row of N.  The Stokeslet rows (type 4) are zero.
-      // (The uncoupled second unknown of a node joins no box; were one
-      // passed, its column would be zero.)
+      // plus the constant row of N.  (The uncoupled second unknown of a node
+      // joins no box; were one passed, its column would be zero.)
       for (int cc = 0; cc < cnt; ++cc) {
         const int d = sj[cc];
         const int j = d >> 1, jc = d & 1;
