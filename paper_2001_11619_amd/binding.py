@@ -421,6 +421,9 @@ class RSSolver:
         weight = np.ascontiguousarray(weight, dtype=np.float64).reshape(N)
         curvature = np.ascontiguousarray(curvature, dtype=np.float64).reshape(N)
         curve_id = np.ascontiguousarray(curve_id, dtype=np.int32).reshape(N)
+        if self.params.kernel == 1:
+            curve_id = np.zeros(N, dtype=np.int32)    # no augmentation (as in the constructor)
+            hole_xy = None
         oon = np.ascontiguousarray(old_of_new, dtype=np.int32).reshape(N)
         n_holes = int(curve_id.max()) if N else 0
         hp = None

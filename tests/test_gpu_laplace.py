@@ -197,3 +197,39 @@ def test_batch_of_related_geometries():
             errs.append(np.abs(x[0::2] - mo).max() / np.abs(mo).max())
     print("Laplace batch update: element-wise error against the dense solve %s" % errs, flush=True)
     assert max(errs) < 1e-8
+
+
+def test_hole_delete_and_insert_update_equals_fresh():
+    """Curves deleted and inserted (rs_update_geometry, N changes) with the
+    Laplace kernel: bitwise the fresh factorization of the new boundary, and
+    within 1e-8 of the oracle's dense solve."""
+    from workloads import Geometry, starfish_nodes
+
+    def geom(xy, nrm, w, kap, cid):
+        return Geometry(xy=np.ascontiguousarray(xy), normal=np.ascontiguousarray(nrm), weight=w, curvature=kap,
+                        curve_id=cid.astype(np.int32), hole_xy=np.zeros((0, 2)), curves=[])
+
+    g0 = starfish_geometry(3000, 0.4, 3.0)
+    s = _solver(g0, leaf_size=32).factor()
+    rng = np.random.Generator(np.random.PCG64(21))
+    # delete the second hole
+    keep = np.nonzero(g0.curve_id != 2)[0]
+    g1 = geom(g0.xy[keep], g0.normal[keep], g0.weight[keep], g0.curvature[keep], g0.curve_id[keep])
+    # insert a third hole on the holes' path at polar angle 1.8
+    th = 1.8
+    rr = 0.5 * (1.0 + 0.25 * np.cos(5 * th))
+    hx, hn, hw, hk = starfish_nodes(420, 0.16, 0.25, 5, th, rr * np.cos(th), rr * np.sin(th), True)
+    g2 = geom(np.vstack([g1.xy, hx]), np.vstack([g1.normal, hn]), np.concatenate([g1.weight, hw]),
+              np.concatenate([g1.curvature, hk]), np.concatenate([g1.curve_id, np.full(420, 2)]))
+    steps = [(g1, keep), (g2, np.concatenate([np.arange(g1.n_nodes), np.full(420, -1)]))]
+    for g, oon in steps:
+        s.update_geometry(g.xy, g.normal, g.weight, g.curvature, g.curve_id, oon)
+        fresh = _solver(g, leaf_size=32).factor()
+        f = rng.standard_normal(g.n_nodes)
+        x = s.solve(_embed(f))
+        assert np.array_equal(x, fresh.solve(_embed(f)))
+        mo = L.solve(g, f)
+        err = np.abs(x[0::2] - mo).max() / np.abs(mo).max()
+        print("Laplace curve update to %d nodes: element-wise error %.2e, recompressed %d boxes"
+              % (g.n_nodes, err, s.stats()["boxes_recomputed"]), flush=True)
+        assert err < 1e-8
