@@ -1223,7 +1223,7 @@ void plan_level(std::vector<rs_ctx*>& cs, std::vector<LevelPrep>& preps, LevelPl
     for (size_t ci = 0; ci < cs.size(); ++ci)
       for (size_t t = 0; t < preps[ci].lb.size(); ++t) preps[ci].lb[t].mq = all[preps[ci].first + t].mq;
   }
-  // Pivoted-QR plan.  Boxes whose (reduced) matrix has at most 1536 rows
+  // Pivoted-QR plan.  Boxes whose (reduced) matrix has at most 2560 rows
   // take the register-resident kernel with the fewest workgroups that hold
   // their columns (G = 1: an ordinary launch; G > 1: cooperative launches of
   // at most the resident capacity); taller ones take the memory-resident

@@ -100,7 +100,7 @@ void launch_assemble_M(const LevelBox* boxes, int nbox, int max_m, int n_proxy, 
 constexpr int kRQThreads = 512;
 constexpr int kRQWaves = kRQThreads / 64;
 constexpr int kRQBudget = 88;         // doubles per lane: CPW columns of RU rows plus v
-constexpr int kRQMaxRU = 24;           // m <= 1536
+constexpr int kRQMaxRU = 40;           // m <= 2560 (one column per wave from RU = 24 on)
 __host__ __device__ constexpr int rq_cols_per_wave(int ru) {
   return kRQBudget / ru - 1 < 20 ? kRQBudget / ru - 1 : 20;
 }

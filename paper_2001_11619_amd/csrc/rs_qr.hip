@@ -913,7 +913,15 @@ __global__ __launch_bounds__(kRQThreads) void k_cpqr16(const LevelBox* boxes, co
   case 18: CALL(18); break; \
   case 20: CALL(20); break; \
   case 22: CALL(22); break; \
-  default: CALL(24); break;
+  case 24: CALL(24); break; \
+  case 26: CALL(26); break; \
+  case 28: CALL(28); break; \
+  case 30: CALL(30); break; \
+  case 32: CALL(32); break; \
+  case 34: CALL(34); break; \
+  case 36: CALL(36); break; \
+  case 38: CALL(38); break; \
+  default: CALL(40); break;
 
 __global__ __launch_bounds__(kRQThreads) void k_cpqr_reg(const LevelBox* boxes, const int4* work,
                                                          double tol, int extra, int* k_out,
