@@ -102,8 +102,8 @@ typedef struct {
                           augmentation (n_holes = 0: every curve_id 0, whatever the number of
                           curves).  The unknown layout stays two per node: unknown 2i is mu at
                           node i, unknown 2i+1 an uncoupled one whose row is lambda x (it joins
-                          no box; the solve returns f / lambda there, 0 for 0).  Requires
-                          precision 0 or 1; refinement
+                          no box; the solve returns f / lambda there, 0 for 0).  Every
+                          precision applies; refinement
                           takes exact residuals (refine_update acts as 0); rs_apply_f32 is not
                           available; rs_evaluate returns (S mu, d(S mu)/dx) per target */
 } rs_params;

@@ -2531,8 +2531,6 @@ rs_status rs_build_tree(const rs_params* prm, int n_nodes, const double* xy, con
     if (prm->kernel != 0 && prm->kernel != 1) throw RsError{RS_ERR_ARG, "kernel must be 0 or 1"};
     if (prm->kernel == 1 && n_holes != 0)
       throw RsError{RS_ERR_ARG, "the Laplace Neumann kernel has no augmentation: n_holes must be 0"};
-    if (prm->kernel == 1 && prm->precision > 1)
-      throw RsError{RS_ERR_ARG, "the Laplace Neumann kernel supports precision 0 and 1"};
     validate_nodes(n_nodes, xy, normal, weight, curvature);
     std::vector<int> count(n_holes + 1, 0);
     for (int i = 0; i < n_nodes; ++i) {

@@ -190,9 +190,24 @@ __device__ __forceinline__ float sl_entry_f(float rx, float ry, float w, int a, 
   return (float)kInv4Pi * w * v;
 }
 
+// The Laplace Neumann entries in float32 (box-local offsets, as below).
+__device__ __forceinline__ float lap_dl_f(float rx, float ry, float nx, float ny, float w) {
+  return (float)kInv2Pi * w * (rx * nx + ry * ny) / (rx * rx + ry * ry);
+}
+
+__device__ __forceinline__ float lap_op_entry_f(const Geo& g, int ti, int tc, int sj, int sc, double lam,
+                                                double cx, double cy) {
+  if (tc | sc) return (ti == sj && tc == sc) ? (float)lam : 0.0f;
+  if (ti == sj) return (float)lam + (float)kInv4Pi * (float)g.kap[ti] * (float)g.w[ti] + (float)g.w[ti];
+  const float rx = (float)(g.x[ti] - cx) - (float)(g.x[sj] - cx);
+  const float ry = (float)(g.y[ti] - cy) - (float)(g.y[sj] - cy);
+  return lap_dl_f(rx, ry, (float)g.nx[ti], (float)g.ny[ti], (float)g.w[sj]) + (float)g.w[sj];
+}
+
 // op_entry in float32; (cx, cy) = the box centre the offsets are taken from.
 __device__ __forceinline__ float op_entry_f(const Geo& g, int ti, int tc, int sj, int sc, double lam,
                                             double cx, double cy) {
+  if (g.kernel == 1) return lap_op_entry_f(g, ti, tc, sj, sc, lam, cx, cy);
   float v;
   if (ti == sj) {
     const float tx = (float)-g.ny[ti], ty = (float)g.nx[ti];

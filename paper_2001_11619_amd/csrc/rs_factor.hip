@@ -99,6 +99,48 @@ __global__ __launch_bounds__(kBlock) void k_assemble_M(const LevelBox* boxes, in
       // normal derivative at the nodes of a proxy charge and a proxy dipole,
       // plus the constant row of N.  (The uncoupled second unknown of a node
       // joins no box; were one passed, its column would be zero.)
+      if (F32) {
+        // float32 entries from box-local offsets (the proxy point's is exact)
+        const float rxf = type <= 1 ? (float)(fx - B.cx) : (float)(rp * pnx);
+        const float ryf = type <= 1 ? (float)(fy - B.cy) : (float)(rp * pny);
+        const float fnxf = (float)fnx, fnyf = (float)fny, fwf = (float)fw, wpf = (float)wp;
+        const float pnxf = (float)pnx, pnyf = (float)pny;
+        for (int cc = 0; cc < cnt; ++cc) {
+          const int d = sj[cc];
+          const int j = d >> 1, jc = d & 1;
+          const float xj = sxf[cc], yj = syf[cc], nxj = (float)snx[cc], nyj = (float)sny[cc], wj = (float)sw[cc];
+          float v = 0.0f;
+          if (type == 0) {
+            if (fj == j) v = lap_op_entry_f(g, fj, fc, j, jc, 0.0, B.cx, B.cy);
+            else if (!(fc | jc)) v = lap_dl_f(rxf - xj, ryf - yj, fnxf, fnyf, wj) + wj;
+          } else if (type == 1) {
+            if (fj == j) v = lap_op_entry_f(g, j, jc, fj, fc, 0.0, B.cx, B.cy);
+            else if (!(fc | jc)) v = lap_dl_f(xj - rxf, yj - ryf, nxj, nyj, fwf) + fwf;
+          } else if (jc == 0) {
+            if (type == 2) {
+              const float rx = rxf - xj, ry = ryf - yj;
+              const float r2 = rx * rx + ry * ry;
+              v = pa ? (float)kInv2Pi * wj * (rx * pnxf + ry * pnyf) / r2 : -(float)kInv4Pi * wj * logf(r2);
+            } else if (type == 3) {
+              const float rx = xj - rxf, ry = yj - ryf;
+              const float r2 = rx * rx + ry * ry;
+              const float rnj = rx * nxj + ry * nyj;
+              if (!pa) {
+                v = (float)kInv2Pi * wpf * rnj / r2;
+              } else {
+                const float rnp = rx * pnxf + ry * pnyf;
+                v = (float)kInv2Pi * wpf * ((nxj * pnxf + nyj * pnyf) - 2.0f * rnp * rnj / r2) / r2;
+              }
+            } else if (type == 5) {
+              v = wj;
+            } else if (type == 6) {
+              v = (float)B.wscale;
+            }
+          }
+          col[(size_t)cc * m] = (double)v;
+        }
+        continue;
+      }
       for (int cc = 0; cc < cnt; ++cc) {
         const int d = sj[cc];
         const int j = d >> 1, jc = d & 1;

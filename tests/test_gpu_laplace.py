@@ -110,6 +110,20 @@ def test_refined_mixed_solve_matches_oracle():
     assert res[0] <= 1e-11 and err < 1e-9
 
 
+def test_refined_float32_bulk_solve_matches_oracle():
+    """The float32 bulk form (precision 2: float32 entries from box-local
+    offsets, FP32 matrix-core Schur complements) refined to 1e-11."""
+    g = starfish_geometry(2400)
+    f = L.neumann_data(g.curve_id)
+    s = _solver(g, leaf_size=32, tol=1e-6, precision=2, refine_max=12, refine_tol=1e-11).factor()
+    x, res = s.solve(_embed(f), residual=True)
+    mo = L.solve(g, f)
+    err = np.abs(x[0::2] - mo).max() / np.abs(mo).max()
+    print("Laplace refined float32 bulk solve: %d iterations, residual %.2e, element-wise error %.2e"
+          % (s.stats()["refine_iters"], res[0], err), flush=True)
+    assert res[0] <= 1e-11 and err < 1e-9
+
+
 def test_circle_rank_deficient_blocks():
     from workloads import Geometry, starfish_nodes
 

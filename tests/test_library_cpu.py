@@ -43,7 +43,7 @@ def _geom():
 
 
 @pytest.mark.parametrize("bad", ["nan_xy", "normal_len", "weight", "curve_id", "tol", "empty_hole",
-                                 "mixed_rcond", "refine_update", "kernel", "laplace_precision"])
+                                 "mixed_rcond", "refine_update", "kernel"])
 def test_invalid_input_rejected(bad):
     g = _geom()
     xy, nrm, w, kap, cid = g.xy.copy(), g.normal.copy(), g.weight.copy(), g.curvature.copy(), g.curve_id.copy()
@@ -64,9 +64,6 @@ def test_invalid_input_rejected(bad):
         kw["refine_update"] = 2
     elif bad == "kernel":
         kw["kernel"] = 2
-    elif bad == "laplace_precision":
-        kw["kernel"] = 1
-        kw["precision"] = 2
     elif bad == "empty_hole":
         cid[cid == 1] = 0
         cid[0] = 2           # hole 1 has no nodes, hole 2 has one
