@@ -192,15 +192,29 @@ __global__ void k_sum_parts2(const double* scratch, int ngroups, int len, double
   out[t] = scale * sum;
 }
 
+constexpr int kBorderOuts = 12;      // outputs per thread of the border right-hand side
+constexpr int kBorderLds = 32768;    // bytes of LDS for the staged rows of one block
+
+// Rows of a box staged in LDS per pass (at least 1): a pass loads them with
+// every thread of the block at once, so that many rows are in flight instead
+// of the one the block's threads would read together in a row-by-row loop.
+// 0 when a single row does not fit: the kernel then reads the rows from global
+// memory directly (same summation order).
+inline int border_tile(int width) { return std::min(32, kBorderLds / (8 * std::max(width, 1))); }
+
 // parts[box] (3p x ncols) = Ph_R^T c_R (accumulated in float64).  When the
 // outputs are fewer than half the threads, the rows of R are split into
 // nseg = kBlock / (3p ncols) interleaved segments (segment g takes rows
 // g, g + nseg, ...), whose sums are added in segment order: the result
-// depends on 3p and ncols only.
+// depends on 3p and ncols only.  Otherwise every thread keeps kBorderOuts
+// outputs (t, t + kBlock, ...) in registers while the box's rows go through
+// LDS in tiles (or straight from global memory when tile is 0); each output
+// sums the rows in order.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_border_rhs(const SolveBox* boxes, const int* ridx,
                                                        const T* Ph, int p3, const T* c, int ncols,
-                                                       double* parts) {
+                                                       double* parts, int tile) {
+  extern __shared__ double sh_rows[];
   __shared__ double seg[kBlock];
   const SolveBox& B = boxes[blockIdx.x];
   double* out = parts + (size_t)B.part * p3 * ncols;
@@ -208,12 +222,44 @@ __global__ __launch_bounds__(kBlock) void k_border_rhs(const SolveBox* boxes, co
   const int nout = p3 * ncols;
   const int nseg = nout <= kBlock / 2 ? kBlock / nout : 1;
   if (nseg == 1) {
-    for (int t = threadIdx.x; t < nout; t += kBlock) {
-      const int h = t / ncols, q = t % ncols;
-      double acc = 0.0;
-      for (int i = 0; i < B.r; ++i)
-        acc += (double)Ph[(size_t)R[i] * p3 + h] * (double)c[(size_t)R[i] * ncols + q];
-      out[t] = acc;
+    double* sP = sh_rows;                    // tile x 3p
+    double* sC = sh_rows + (size_t)tile * p3;  // tile x ncols
+    for (int t0 = 0; t0 < nout; t0 += kBlock * kBorderOuts) {
+      double acc[kBorderOuts];
+      int hh[kBorderOuts], qq[kBorderOuts];
+#pragma unroll
+      for (int u = 0; u < kBorderOuts; ++u) {
+        const int t = min(t0 + (int)threadIdx.x + u * kBlock, nout - 1);
+        hh[u] = t / ncols;
+        qq[u] = t % ncols;
+        acc[u] = 0.0;
+      }
+      if (tile == 0) {
+        for (int i = 0; i < B.r; ++i) {
+          const size_t r = R[i];
+#pragma unroll
+          for (int u = 0; u < kBorderOuts; ++u)
+            acc[u] += (double)Ph[r * p3 + hh[u]] * (double)c[r * ncols + qq[u]];
+        }
+      }
+      for (int i0 = 0; tile > 0 && i0 < B.r; i0 += tile) {
+        const int nt = min(tile, B.r - i0);
+        __syncthreads();
+        for (int e = threadIdx.x; e < nt * p3; e += kBlock)
+          sP[e] = (double)Ph[(size_t)R[i0 + e / p3] * p3 + e % p3];
+        for (int e = threadIdx.x; e < nt * ncols; e += kBlock)
+          sC[e] = (double)c[(size_t)R[i0 + e / ncols] * ncols + e % ncols];
+        __syncthreads();
+        for (int ii = 0; ii < nt; ++ii) {
+#pragma unroll
+          for (int u = 0; u < kBorderOuts; ++u) acc[u] += sP[ii * p3 + hh[u]] * sC[ii * ncols + qq[u]];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kBorderOuts; ++u) {
+        const int t = t0 + (int)threadIdx.x + u * kBlock;
+        if (t < nout) out[t] = acc[u];
+      }
     }
     return;
   }
@@ -233,21 +279,58 @@ __global__ __launch_bounds__(kBlock) void k_border_rhs(const SolveBox* boxes, co
   }
 }
 
-// c_R -= W lam
+// c_R -= W lam.  The block stages lam (3p x up to 16 columns) and tiles of the
+// box's rows of W in LDS; a thread computes one (row, column) of a tile, the
+// sum over h in order.  With tile 0 (3p too large for LDS) the threads take
+// the (row, column) pairs from global memory, in the same order over h.
+constexpr int kFixCols = 16;
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_border_fix(const SolveBox* boxes, const int* ridx,
                                                        int p3, const double* lam, T* c,
-                                                       int ncols) {
+                                                       int ncols, int tile) {
+  extern __shared__ double sh_rows[];
   const SolveBox& B = boxes[blockIdx.x];
+  if (B.r == 0) return;
   const int* R = ridx + B.r_off;
-  for (int t = threadIdx.x; t < B.r * ncols; t += kBlock) {
-    const int i = t / ncols, q = t % ncols;
-    double acc = 0.0;
-    if (B.Wf)
-      for (int h = 0; h < p3; ++h) acc += (double)B.Wf[(size_t)i * p3 + h] * lam[(size_t)h * ncols + q];
-    else
-      for (int h = 0; h < p3; ++h) acc += B.W[(size_t)i * p3 + h] * lam[(size_t)h * ncols + q];
-    c[(size_t)R[i] * ncols + q] -= (T)acc;
+  if (tile == 0) {
+    for (int o = threadIdx.x; o < B.r * ncols; o += kBlock) {
+      const int i = o / ncols, q = o % ncols;
+      double acc = 0.0;
+      if (B.Wf) {
+        for (int h = 0; h < p3; ++h) acc += (double)B.Wf[(size_t)i * p3 + h] * lam[(size_t)h * ncols + q];
+      } else {
+        for (int h = 0; h < p3; ++h) acc += B.W[(size_t)i * p3 + h] * lam[(size_t)h * ncols + q];
+      }
+      c[(size_t)R[i] * ncols + q] -= (T)acc;
+    }
+    return;
+  }
+  double* sL = sh_rows;                            // 3p x kFixCols
+  double* sW = sh_rows + (size_t)p3 * kFixCols;    // tile x 3p
+  for (int q0 = 0; q0 < ncols; q0 += kFixCols) {
+    const int nq = min(kFixCols, ncols - q0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < p3 * kFixCols; e += kBlock) {
+      const int h = e / kFixCols, k = e % kFixCols;
+      sL[e] = k < nq ? lam[(size_t)h * ncols + q0 + k] : 0.0;
+    }
+    for (int i0 = 0; i0 < B.r; i0 += tile) {
+      const int nt = min(tile, B.r - i0);
+      __syncthreads();
+      if (B.Wf) {
+        for (int e = threadIdx.x; e < nt * p3; e += kBlock) sW[e] = (double)B.Wf[(size_t)i0 * p3 + e];
+      } else {
+        for (int e = threadIdx.x; e < nt * p3; e += kBlock) sW[e] = B.W[(size_t)i0 * p3 + e];
+      }
+      __syncthreads();
+      for (int o = threadIdx.x; o < nt * kFixCols; o += kBlock) {
+        const int ii = o / kFixCols, k = o % kFixCols;
+        if (k >= nq) continue;
+        double acc = 0.0;
+        for (int h = 0; h < p3; ++h) acc += sW[ii * p3 + h] * sL[h * kFixCols + k];
+        c[(size_t)R[i0 + ii] * ncols + q0 + k] -= (T)acc;
+      }
+    }
   }
 }
 
@@ -520,8 +603,10 @@ template <typename T>
 void launch_border_rhs(const SolveBox* boxes, int nbox, const int* ridx, const T* Ph, int p3,
                        const T* c, int ncols, double* parts, hipStream_t s) {
   if (nbox == 0) return;
-  hipLaunchKernelGGL(k_border_rhs<T>, dim3(nbox), dim3(kBlock), 0, s, boxes, ridx, Ph, p3, c, ncols,
-                     parts);
+  const int tile = border_tile(p3 + ncols);
+  const size_t lds = (size_t)tile * (p3 + ncols) * sizeof(double);
+  hipLaunchKernelGGL(k_border_rhs<T>, dim3(nbox), dim3(kBlock), lds, s, boxes, ridx, Ph, p3, c, ncols,
+                     parts, tile);
 }
 template void launch_border_rhs<double>(const SolveBox*, int, const int*, const double*, int,
                                         const double*, int, double*, hipStream_t);
@@ -530,7 +615,10 @@ template <typename T>
 void launch_border_fix(const SolveBox* boxes, int nbox, const int* ridx, int p3, const double* lam,
                        T* c, int ncols, hipStream_t s) {
   if (nbox == 0) return;
-  hipLaunchKernelGGL(k_border_fix<T>, dim3(nbox), dim3(kBlock), 0, s, boxes, ridx, p3, lam, c, ncols);
+  // lam's column block and a tile of W rows share the LDS budget
+  const int tile = std::max(0, std::min(32, (kBorderLds - 8 * p3 * kFixCols) / (8 * std::max(p3, 1))));
+  const size_t lds = tile ? ((size_t)p3 * kFixCols + (size_t)tile * p3) * sizeof(double) : 0;
+  hipLaunchKernelGGL(k_border_fix<T>, dim3(nbox), dim3(kBlock), lds, s, boxes, ridx, p3, lam, c, ncols, tile);
 }
 template void launch_border_fix<double>(const SolveBox*, int, const int*, int, const double*,
                                         double*, int, hipStream_t);
