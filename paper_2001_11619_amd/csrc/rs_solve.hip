@@ -192,38 +192,86 @@ __global__ void k_sum_parts2(const double* scratch, int ngroups, int len, double
   out[t] = scale * sum;
 }
 
-constexpr int kBorderOuts = 12;      // outputs per thread of the border right-hand side
-constexpr int kBorderLds = 32768;    // bytes of LDS for the staged rows of one block
+constexpr int kBorderOuts = 12;      // outputs per thread of the unstaged border right-hand side
+constexpr int kBorderLds = 49152;    // bytes of LDS for the staged rows of one block
 
-// Rows of a box staged in LDS per pass (at least 1): a pass loads them with
-// every thread of the block at once, so that many rows are in flight instead
-// of the one the block's threads would read together in a row-by-row loop.
-// 0 when a single row does not fit: the kernel then reads the rows from global
-// memory directly (same summation order).
-inline int border_tile(int width) { return std::min(32, kBorderLds / (8 * std::max(width, 1))); }
+__host__ __device__ inline int round4(int v) { return (v + 3) & ~3; }
+
+// Rows of a box staged in LDS per pass (3p and ncols padded to multiples of
+// 4): a pass loads them with every thread of the block at once, so that many
+// rows are in flight.  0 when a single row does not fit: the kernel then reads
+// the rows from global memory directly (same summation order).
+inline int border_tile(int p3, int ncols) {
+  return std::min(32, kBorderLds / (8 * (round4(p3) + round4(ncols))));
+}
 
 // parts[box] (3p x ncols) = Ph_R^T c_R (accumulated in float64).  When the
 // outputs are fewer than half the threads, the rows of R are split into
 // nseg = kBlock / (3p ncols) interleaved segments (segment g takes rows
 // g, g + nseg, ...), whose sums are added in segment order: the result
-// depends on 3p and ncols only.  Otherwise every thread keeps kBorderOuts
-// outputs (t, t + kBlock, ...) in registers while the box's rows go through
-// LDS in tiles (or straight from global memory when tile is 0); each output
-// sums the rows in order.
+// depends on 3p and ncols only.  Otherwise the box's rows go through LDS in
+// tiles and every thread accumulates a 4 x 4 block of outputs (4 consecutive
+// h, 4 consecutive columns) in registers; with tile 0 every thread keeps
+// kBorderOuts outputs (t, t + kBlock, ...) and reads global memory.  Each
+// output sums the rows in order either way.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_border_rhs(const SolveBox* boxes, const int* ridx,
                                                        const T* Ph, int p3, const T* c, int ncols,
                                                        double* parts, int tile) {
-  extern __shared__ double sh_rows[];
+  extern __shared__ __align__(16) double sh_rows[];
   __shared__ double seg[kBlock];
   const SolveBox& B = boxes[blockIdx.x];
   double* out = parts + (size_t)B.part * p3 * ncols;
   const int* R = ridx + B.r_off;
   const int nout = p3 * ncols;
   const int nseg = nout <= kBlock / 2 ? kBlock / nout : 1;
+  if (nseg == 1 && tile > 0) {
+    const int p3p = round4(p3), ncp = round4(ncols), nbq = ncp / 4, nblk = (p3p / 4) * nbq;
+    double* sP = sh_rows;                        // tile x p3p
+    double* sC = sh_rows + (size_t)tile * p3p;   // tile x ncp
+    for (int b0 = 0; b0 < nblk; b0 += kBlock) {
+      const int b = b0 + (int)threadIdx.x;
+      const int h0 = 4 * (b / nbq), q0 = 4 * (b % nbq);
+      double acc[4][4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+      for (int i0 = 0; i0 < B.r; i0 += tile) {
+        const int nt = min(tile, B.r - i0);
+        __syncthreads();
+        for (int e = threadIdx.x; e < nt * p3p; e += kBlock) {
+          const int ii = e / p3p, h = e % p3p;
+          sP[e] = h < p3 ? (double)Ph[(size_t)R[i0 + ii] * p3 + h] : 0.0;
+        }
+        for (int e = threadIdx.x; e < nt * ncp; e += kBlock) {
+          const int ii = e / ncp, q = e % ncp;
+          sC[e] = q < ncols ? (double)c[(size_t)R[i0 + ii] * ncols + q] : 0.0;
+        }
+        __syncthreads();
+        if (b < nblk) {
+          for (int ii = 0; ii < nt; ++ii) {
+            const double4 pv = *reinterpret_cast<const double4*>(sP + (size_t)ii * p3p + h0);
+            const double4 cv = *reinterpret_cast<const double4*>(sC + (size_t)ii * ncp + q0);
+            const double pa[4] = {pv.x, pv.y, pv.z, pv.w}, ca[4] = {cv.x, cv.y, cv.z, cv.w};
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+              for (int v = 0; v < 4; ++v) acc[u][v] += pa[u] * ca[v];
+          }
+        }
+      }
+      if (b < nblk) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            if (h0 + u < p3 && q0 + v < ncols) out[(size_t)(h0 + u) * ncols + q0 + v] = acc[u][v];
+      }
+    }
+    return;
+  }
   if (nseg == 1) {
-    double* sP = sh_rows;                    // tile x 3p
-    double* sC = sh_rows + (size_t)tile * p3;  // tile x ncols
     for (int t0 = 0; t0 < nout; t0 += kBlock * kBorderOuts) {
       double acc[kBorderOuts];
       int hh[kBorderOuts], qq[kBorderOuts];
@@ -234,26 +282,11 @@ __global__ __launch_bounds__(kBlock) void k_border_rhs(const SolveBox* boxes, co
         qq[u] = t % ncols;
         acc[u] = 0.0;
       }
-      if (tile == 0) {
-        for (int i = 0; i < B.r; ++i) {
-          const size_t r = R[i];
+      for (int i = 0; i < B.r; ++i) {
+        const size_t r = R[i];
 #pragma unroll
-          for (int u = 0; u < kBorderOuts; ++u)
-            acc[u] += (double)Ph[r * p3 + hh[u]] * (double)c[r * ncols + qq[u]];
-        }
-      }
-      for (int i0 = 0; tile > 0 && i0 < B.r; i0 += tile) {
-        const int nt = min(tile, B.r - i0);
-        __syncthreads();
-        for (int e = threadIdx.x; e < nt * p3; e += kBlock)
-          sP[e] = (double)Ph[(size_t)R[i0 + e / p3] * p3 + e % p3];
-        for (int e = threadIdx.x; e < nt * ncols; e += kBlock)
-          sC[e] = (double)c[(size_t)R[i0 + e / ncols] * ncols + e % ncols];
-        __syncthreads();
-        for (int ii = 0; ii < nt; ++ii) {
-#pragma unroll
-          for (int u = 0; u < kBorderOuts; ++u) acc[u] += sP[ii * p3 + hh[u]] * sC[ii * ncols + qq[u]];
-        }
+        for (int u = 0; u < kBorderOuts; ++u)
+          acc[u] += (double)Ph[r * p3 + hh[u]] * (double)c[r * ncols + qq[u]];
       }
 #pragma unroll
       for (int u = 0; u < kBorderOuts; ++u) {
@@ -279,16 +312,20 @@ __global__ __launch_bounds__(kBlock) void k_border_rhs(const SolveBox* boxes, co
   }
 }
 
-// c_R -= W lam.  The block stages lam (3p x up to 16 columns) and tiles of the
-// box's rows of W in LDS; a thread computes one (row, column) of a tile, the
-// sum over h in order.  With tile 0 (3p too large for LDS) the threads take
-// the (row, column) pairs from global memory, in the same order over h.
+// c_R -= W lam.  The block stages lam (3p x 16 columns, zero-padded) in LDS
+// and takes the box's rows of W in tiles of kFixRows rows by kFixK values of
+// h (rows padded by one double against bank conflicts); the thread (row ii,
+// column group g) accumulates 4 columns of row ii in registers, the sum over h
+// in order.  With tile 0 (3p too large for LDS) the threads take the
+// (row, column) pairs from global memory, in the same order over h.
 constexpr int kFixCols = 16;
+constexpr int kFixRows = kBlock / (kFixCols / 4);  // 64
+constexpr int kFixK = 64;
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_border_fix(const SolveBox* boxes, const int* ridx,
                                                        int p3, const double* lam, T* c,
                                                        int ncols, int tile) {
-  extern __shared__ double sh_rows[];
+  extern __shared__ __align__(16) double sh_rows[];
   const SolveBox& B = boxes[blockIdx.x];
   if (B.r == 0) return;
   const int* R = ridx + B.r_off;
@@ -305,8 +342,9 @@ __global__ __launch_bounds__(kBlock) void k_border_fix(const SolveBox* boxes, co
     }
     return;
   }
-  double* sL = sh_rows;                            // 3p x kFixCols
-  double* sW = sh_rows + (size_t)p3 * kFixCols;    // tile x 3p
+  double* sL = sh_rows;                              // 3p x kFixCols
+  double* sW = sh_rows + (size_t)p3 * kFixCols;      // kFixRows x (kFixK + 1)
+  const int ii = threadIdx.x % kFixRows, g = threadIdx.x / kFixRows;
   for (int q0 = 0; q0 < ncols; q0 += kFixCols) {
     const int nq = min(kFixCols, ncols - q0);
     __syncthreads();
@@ -314,21 +352,36 @@ __global__ __launch_bounds__(kBlock) void k_border_fix(const SolveBox* boxes, co
       const int h = e / kFixCols, k = e % kFixCols;
       sL[e] = k < nq ? lam[(size_t)h * ncols + q0 + k] : 0.0;
     }
-    for (int i0 = 0; i0 < B.r; i0 += tile) {
-      const int nt = min(tile, B.r - i0);
-      __syncthreads();
-      if (B.Wf) {
-        for (int e = threadIdx.x; e < nt * p3; e += kBlock) sW[e] = (double)B.Wf[(size_t)i0 * p3 + e];
-      } else {
-        for (int e = threadIdx.x; e < nt * p3; e += kBlock) sW[e] = B.W[(size_t)i0 * p3 + e];
+    for (int i0 = 0; i0 < B.r; i0 += kFixRows) {
+      const int nt = min(kFixRows, B.r - i0);
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int k0 = 0; k0 < p3; k0 += kFixK) {
+        const int kc = min(kFixK, p3 - k0);
+        __syncthreads();
+        for (int e = threadIdx.x; e < nt * kc; e += kBlock) {
+          const int r = e / kc, kk = e % kc;
+          const size_t src = (size_t)(i0 + r) * p3 + k0 + kk;
+          sW[r * (kFixK + 1) + kk] = B.Wf ? (double)B.Wf[src] : B.W[src];
+        }
+        __syncthreads();
+        if (ii < nt && 4 * g < nq) {
+          const double* wr = sW + ii * (kFixK + 1);
+          const double* lr = sL + (size_t)k0 * kFixCols + 4 * g;
+          for (int kk = 0; kk < kc; ++kk) {
+            const double w = wr[kk];
+            const double4 lv = *reinterpret_cast<const double4*>(lr + (size_t)kk * kFixCols);
+            acc[0] += w * lv.x;
+            acc[1] += w * lv.y;
+            acc[2] += w * lv.z;
+            acc[3] += w * lv.w;
+          }
+        }
       }
-      __syncthreads();
-      for (int o = threadIdx.x; o < nt * kFixCols; o += kBlock) {
-        const int ii = o / kFixCols, k = o % kFixCols;
-        if (k >= nq) continue;
-        double acc = 0.0;
-        for (int h = 0; h < p3; ++h) acc += sW[ii * p3 + h] * sL[h * kFixCols + k];
-        c[(size_t)R[i0 + ii] * ncols + q0 + k] -= (T)acc;
+      if (ii < nt) {
+        T* crow = c + (size_t)R[i0 + ii] * ncols + q0 + 4 * g;
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          if (4 * g + v < nq) crow[v] -= (T)acc[v];
       }
     }
   }
@@ -603,8 +656,8 @@ template <typename T>
 void launch_border_rhs(const SolveBox* boxes, int nbox, const int* ridx, const T* Ph, int p3,
                        const T* c, int ncols, double* parts, hipStream_t s) {
   if (nbox == 0) return;
-  const int tile = border_tile(p3 + ncols);
-  const size_t lds = (size_t)tile * (p3 + ncols) * sizeof(double);
+  const int tile = border_tile(p3, ncols);
+  const size_t lds = (size_t)tile * (round4(p3) + round4(ncols)) * sizeof(double);
   hipLaunchKernelGGL(k_border_rhs<T>, dim3(nbox), dim3(kBlock), lds, s, boxes, ridx, Ph, p3, c, ncols,
                      parts, tile);
 }
@@ -615,10 +668,12 @@ template <typename T>
 void launch_border_fix(const SolveBox* boxes, int nbox, const int* ridx, int p3, const double* lam,
                        T* c, int ncols, hipStream_t s) {
   if (nbox == 0) return;
-  // lam's column block and a tile of W rows share the LDS budget
-  const int tile = std::max(0, std::min(32, (kBorderLds - 8 * p3 * kFixCols) / (8 * std::max(p3, 1))));
-  const size_t lds = tile ? ((size_t)p3 * kFixCols + (size_t)tile * p3) * sizeof(double) : 0;
-  hipLaunchKernelGGL(k_border_fix<T>, dim3(nbox), dim3(kBlock), lds, s, boxes, ridx, p3, lam, c, ncols, tile);
+  // lam's column block and a tile of W share 64 KiB of LDS; beyond that
+  // (3p > 251) the kernel reads global memory
+  const size_t lds = ((size_t)p3 * kFixCols + (size_t)kFixRows * (kFixK + 1)) * sizeof(double);
+  const int tile = lds <= 65536 ? 1 : 0;
+  hipLaunchKernelGGL(k_border_fix<T>, dim3(nbox), dim3(kBlock), tile ? lds : 0, s, boxes, ridx, p3, lam, c,
+                     ncols, tile);
 }
 template void launch_border_fix<double>(const SolveBox*, int, const int*, int, const double*,
                                         double*, int, hipStream_t);
