@@ -118,15 +118,84 @@ __device__ __forceinline__ void diag_box(const SolveBox& B, const TF* Xi, const 
   }
 }
 
+// The same product for boxes with r <= kDiagMaxR: the block stages c_R (16
+// columns at a time, zero-padded) in LDS and takes X_RR^{-1} in tiles of 64
+// rows by 32 columns (rows padded by one double against bank conflicts); the
+// thread (row ii, column group g) keeps 4 columns of row ii in registers.
+// Each output sums over j in order, as above.  32 KiB of LDS at most, so that
+// several blocks share a CU (most boxes have a few dozen rows).
+constexpr int kDiagTile = 64;
+constexpr int kDiagK = 32;
+constexpr int kDiagLdsTile = kDiagTile * (kDiagK + 1) * 8;        // bytes
+constexpr int kDiagMaxR = (32768 - kDiagLdsTile) / (16 * 8);      // 124
+template <typename T, typename TF>
+__device__ __forceinline__ void diag_box_tiled(const SolveBox& B, const TF* Xi, const int* ridx, T* c,
+                                               int ncols, int kNC, double* smem) {
+  const int r = B.r;
+  const int q0 = blockIdx.y * kNC;
+  const int nq = min(kNC, ncols - q0);
+  const int* R = ridx + B.r_off;
+  double* sIn = smem;                         // r x 16
+  double* sX = smem + (size_t)r * 16;         // kDiagTile x (kDiagK + 1)
+  const int ii = threadIdx.x % kDiagTile, g = threadIdx.x / kDiagTile;
+  static_assert(kBlock == 4 * kDiagTile, "4 column groups of 4 cover 16 columns");
+  for (int qa = 0; qa < nq; qa += 16) {
+    const int na = min(16, nq - qa);
+    __syncthreads();
+    for (int e = threadIdx.x; e < r * 16; e += kBlock) {
+      const int j = e / 16, k = e % 16;
+      sIn[e] = k < na ? (double)c[(size_t)R[j] * ncols + q0 + qa + k] : 0.0;
+    }
+    for (int i0 = 0; i0 < r; i0 += kDiagTile) {
+      const int nt = min(kDiagTile, r - i0);
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int k0 = 0; k0 < r; k0 += kDiagK) {
+        const int kc = min(kDiagK, r - k0);
+        __syncthreads();
+        for (int e = threadIdx.x; e < nt * kDiagK; e += kBlock) {
+          const int rr = e / kDiagK, kk = e % kDiagK;
+          if (kk < kc) sX[rr * (kDiagK + 1) + kk] = (double)Xi[(size_t)(i0 + rr) * r + k0 + kk];
+        }
+        __syncthreads();
+        if (ii < nt && 4 * g < na) {
+          const double* xr = sX + ii * (kDiagK + 1);
+          const double* vr = sIn + (size_t)k0 * 16 + 4 * g;
+          for (int kk = 0; kk < kc; ++kk) {
+            const double x = xr[kk];
+            const double4 v = *reinterpret_cast<const double4*>(vr + (size_t)kk * 16);
+            acc[0] += x * v.x;
+            acc[1] += x * v.y;
+            acc[2] += x * v.z;
+            acc[3] += x * v.w;
+          }
+        }
+      }
+      // c_R was staged whole for these columns, so the rows can be written now
+      if (ii < nt) {
+        T* crow = c + (size_t)R[i0 + ii] * ncols + q0 + qa + 4 * g;
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          if (4 * g + v < na) crow[v] = (T)acc[v];
+      }
+    }
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_diag(const SolveBox* boxes, const int* ridx, T* c,
                                                  int ncols, int kNC) {
-  extern __shared__ double smem_d[];
+  extern __shared__ __align__(16) double smem_d[];
   T* smem = reinterpret_cast<T*>(smem_d);
   const SolveBox& B = boxes[blockIdx.x];
   if (B.r == 0) return;
-  if (B.Xinvf) diag_box<T, float>(B, B.Xinvf, ridx, c, ncols, kNC, smem);
-  else diag_box<T, double>(B, B.Xinv, ridx, c, ncols, kNC, smem);
+  if (B.r <= kDiagMaxR) {
+    if (B.Xinvf) diag_box_tiled<T, float>(B, B.Xinvf, ridx, c, ncols, kNC, smem_d);
+    else diag_box_tiled<T, double>(B, B.Xinv, ridx, c, ncols, kNC, smem_d);
+  } else if (B.Xinvf) {
+    diag_box<T, float>(B, B.Xinvf, ridx, c, ncols, kNC, smem);
+  } else {
+    diag_box<T, double>(B, B.Xinv, ridx, c, ncols, kNC, smem);
+  }
 }
 
 // H (2N x 3p) and Psi (2N x 3p, i.e. Psi^T stored by columns), row-major.
@@ -193,7 +262,7 @@ __global__ void k_sum_parts2(const double* scratch, int ngroups, int len, double
 }
 
 constexpr int kBorderOuts = 12;      // outputs per thread of the unstaged border right-hand side
-constexpr int kBorderLds = 49152;    // bytes of LDS for the staged rows of one block
+constexpr int kBorderLds = 24576;    // bytes of LDS for the staged rows of one block (several blocks per CU)
 
 __host__ __device__ inline int round4(int v) { return (v + 3) & ~3; }
 
@@ -240,13 +309,13 @@ __global__ __launch_bounds__(kBlock) void k_border_rhs(const SolveBox* boxes, co
       for (int i0 = 0; i0 < B.r; i0 += tile) {
         const int nt = min(tile, B.r - i0);
         __syncthreads();
-        for (int e = threadIdx.x; e < nt * p3p; e += kBlock) {
-          const int ii = e / p3p, h = e % p3p;
-          sP[e] = h < p3 ? (double)Ph[(size_t)R[i0 + ii] * p3 + h] : 0.0;
-        }
-        for (int e = threadIdx.x; e < nt * ncp; e += kBlock) {
-          const int ii = e / ncp, q = e % ncp;
-          sC[e] = q < ncols ? (double)c[(size_t)R[i0 + ii] * ncols + q] : 0.0;
+        // one wavefront per row: coalesced, no index division
+        for (int ii = threadIdx.x / 64; ii < nt; ii += kBlock / 64) {
+          const size_t row = R[i0 + ii];
+          for (int h = threadIdx.x % 64; h < p3p; h += 64)
+            sP[ii * p3p + h] = h < p3 ? (double)Ph[row * p3 + h] : 0.0;
+          for (int q = threadIdx.x % 64; q < ncp; q += 64)
+            sC[ii * ncp + q] = q < ncols ? (double)c[row * ncols + q] : 0.0;
         }
         __syncthreads();
         if (b < nblk) {
@@ -320,7 +389,7 @@ __global__ __launch_bounds__(kBlock) void k_border_rhs(const SolveBox* boxes, co
 // (row, column) pairs from global memory, in the same order over h.
 constexpr int kFixCols = 16;
 constexpr int kFixRows = kBlock / (kFixCols / 4);  // 64
-constexpr int kFixK = 64;
+constexpr int kFixK = 32;
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_border_fix(const SolveBox* boxes, const int* ridx,
                                                        int p3, const double* lam, T* c,
@@ -628,7 +697,9 @@ void launch_diag(const SolveBox* boxes, int nbox, const int* ridx, T* c, int nco
   if (nbox == 0 || ncols == 0) return;
   const int nc = chunk_cols(2 * max_r, ncols, nbox);
   dim3 grid(nbox, blocks_for(ncols, nc));
-  const size_t shm = (size_t)2 * max_r * nc * sizeof(T);
+  // the larger of the two paths' needs (both within 64 KiB)
+  const size_t shm = std::max((size_t)2 * max_r * nc * sizeof(T),
+                              (size_t)std::min(max_r, kDiagMaxR) * 16 * sizeof(double) + kDiagLdsTile);
   hipLaunchKernelGGL(k_diag<T>, grid, dim3(kBlock), shm, s, boxes, ridx, c, ncols, nc);
 }
 template void launch_diag<double>(const SolveBox*, int, const int*, double*, int, int, hipStream_t);
@@ -669,7 +740,7 @@ void launch_border_fix(const SolveBox* boxes, int nbox, const int* ridx, int p3,
                        T* c, int ncols, hipStream_t s) {
   if (nbox == 0) return;
   // lam's column block and a tile of W share 64 KiB of LDS; beyond that
-  // (3p > 251) the kernel reads global memory
+  // (3p > 380) the kernel reads global memory
   const size_t lds = ((size_t)p3 * kFixCols + (size_t)kFixRows * (kFixK + 1)) * sizeof(double);
   const int tile = lds <= 65536 ? 1 : 0;
   hipLaunchKernelGGL(k_border_fix<T>, dim3(nbox), dim3(kBlock), tile ? lds : 0, s, boxes, ridx, p3, lam, c,
