@@ -325,11 +325,92 @@ __global__ __launch_bounds__(kNodeSumThreads) void k_apply_nsum(Geo g, const dou
   if (threadIdx.x == 0) nsum[q * kNsumParts + b] = s;
 }
 
+// The Stokes form of k_apply_sum with p > 0 holes (see there); called by the
+// whole block, so every thread reaches the barriers.
+constexpr int kSumCoefs = 320;   // (node, hole) coefficient sets per chunk
+__device__ __forceinline__ void apply_sum_stokes(const Geo& g, double lam, const double* hole_xy, int p,
+                                                 const double* x, int ncols, const double* part, int nchunk,
+                                                 const double* nsum, const float* bpart, double* bt, double* y) {
+  __shared__ double coef[kSumCoefs * 5];
+  const int N = g.N;
+  const long long t0 = (long long)blockIdx.x * kBlock;
+  const long long t = t0 + threadIdx.x;
+  const bool live = t < (long long)N * ncols;
+  const int i = live ? (int)(t / ncols) : 0, q = (int)(t % ncols);
+  // nodes of this block's (node, column) range: at most kBlock of them
+  const int i_lo = (int)(t0 / ncols);
+  const int i_hi = (int)min((long long)N - 1, (t0 + kBlock - 1) / ncols);
+  const int nn = i_hi - i_lo + 1;
+  const int hcap = max(1, kSumCoefs / nn);
+  const size_t stride = (size_t)2 * N * ncols;
+  double ax = 0.0, ay = 0.0;
+  if (live) {
+    for (int c = 0; c < nchunk; ++c) {
+      ax += part[c * stride + (size_t)(2 * i) * ncols + q];
+      ay += part[c * stride + (size_t)(2 * i + 1) * ncols + q];
+    }
+    if (bpart) {
+      double b = 0.0;
+      for (int c = 0; c < nchunk; ++c) b += (double)bpart[((size_t)c * N + i) * ncols + q];
+      bt[(size_t)i * ncols + q] = b;
+    }
+    const double mx = x[(size_t)(2 * i) * ncols + q], my = x[(size_t)(2 * i + 1) * ncols + q];
+    const double nxi = g.nx[i], nyi = g.ny[i];
+    {
+      const double tx = -nyi, ty = nxi;
+      const double cs = -(g.w[i] * g.kap[i]) / (2.0 * kPi);
+      ax += (cs * tx * tx + lam) * mx + cs * tx * ty * my;
+      ay += cs * tx * ty * mx + (cs * ty * ty + lam) * my;
+    }
+    double ns = 0.0;
+    for (int b = 0; b < kNsumParts; ++b) ns += nsum[q * kNsumParts + b];
+    ax += nxi * ns;
+    ay += nyi * ns;
+  }
+  const size_t base = (size_t)2 * N;
+  for (int h0 = 0; h0 < p; h0 += hcap) {
+    const int hn = min(hcap, p - h0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < nn * hn; e += kBlock) {
+      const int node = i_lo + e / hn, h = h0 + e % hn;
+      const double rx = g.x[node] - hole_xy[2 * h], ry = g.y[node] - hole_xy[2 * h + 1];
+      const double r2 = rx * rx + ry * ry;
+      const double lg = -0.5 * log(r2);
+      double* cf = coef + 5 * e;
+      cf[0] = kInv4Pi * (lg + rx * rx / r2);
+      cf[1] = kInv4Pi * (rx * ry / r2);
+      cf[2] = kInv4Pi * (lg + ry * ry / r2);
+      cf[3] = kInv4Pi * (-ry) / r2;
+      cf[4] = kInv4Pi * rx / r2;
+    }
+    __syncthreads();
+    if (live) {
+      const double* cfi = coef + 5 * (size_t)(i - i_lo) * hn;
+      for (int u = 0; u < hn; ++u) {
+        const int h = h0 + u;
+        const double* cf = cfi + 5 * u;
+        const double a1 = x[(base + 3 * h) * ncols + q];
+        const double a2 = x[(base + 3 * h + 1) * ncols + q];
+        const double b = x[(base + 3 * h + 2) * ncols + q];
+        ax += cf[0] * a1 + cf[1] * a2 + cf[3] * b;
+        ay += cf[1] * a1 + cf[2] * a2 + cf[4] * b;
+      }
+    }
+  }
+  if (live) {
+    y[(size_t)(2 * i) * ncols + q] = ax;
+    y[(size_t)(2 * i + 1) * ncols + q] = ay;
+  }
+}
+
 // y[2N rows] = sum over source chunks (fixed order) + the diagonal (lam and
 // the curvature limit of D) + the rank-one term + H lambda
 // For a correction image it also adds the rounding bounds of the chunks
 // (bpart, float) into bt (per node and column).
-__global__ void k_apply_sum(Geo g, double lam, const double* hole_xy, int p, const double* x,
+// With holes, the Stokeslet and rotlet coefficients of H (per node and hole,
+// the same for every column) are formed once per block in LDS, a chunk of
+// holes at a time, and every (node, column) thread adds the holes in order.
+__global__ __launch_bounds__(kBlock) void k_apply_sum(Geo g, double lam, const double* hole_xy, int p, const double* x,
                             const double* xc, int ncols, const double* part, int nchunk, const double* nsum,
                             const float* bpart, double* bt, double* y, const int* skip, int max_iters) {
   const int md = apply_mode(skip, max_iters);
@@ -337,6 +418,10 @@ __global__ void k_apply_sum(Geo g, double lam, const double* hole_xy, int p, con
   if (md == 1) x = xc;
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int N = g.N;
+  if (g.kernel == 0 && p > 0) {
+    apply_sum_stokes(g, lam, hole_xy, p, x, ncols, part, nchunk, nsum, md == 1 ? bpart : nullptr, bt, y);
+    return;
+  }
   if (t >= (long long)N * ncols) return;
   const int i = (int)(t / ncols), q = (int)(t % ncols);
   const size_t stride = (size_t)2 * N * ncols;
