@@ -293,7 +293,7 @@ __global__ void k_pack_sources(Geo g, double4* src4) {
 }
 
 // Threads per block of the two node reductions below (k_apply_nsum,
-// k_apply_psi): they have one block per output, so a wide block keeps the
+// k_apply_psi): they have few blocks, so a wide block keeps the
 // per-thread loop over the nodes short.
 constexpr int kNodeSumThreads = 1024;
 
@@ -513,7 +513,11 @@ __global__ void k_eval_sum(Geo g, const double* tx, const double* ty, int nt, co
   u[(size_t)(2 * i + 1) * ncols + q] = ay;
 }
 
-// Rows of Psi^T x - lambda: one block per (hole, mode), fixed-order sums.
+// Rows of Psi^T x - lambda.  Block (h, column chunk) scans the nodes once for
+// the three modes of hole h and kPsiCols columns; each output is the same
+// fixed-order sum as with one block per output (thread-strided over the
+// nodes, then the block sum).
+constexpr int kPsiCols = 8;
 __global__ __launch_bounds__(kNodeSumThreads) void k_apply_psi(Geo g, const int* curve_id, int p,
                                                                const double* x, const double* xc, int ncols,
                                                                double* y, const int* skip, int max_iters) {
@@ -522,22 +526,39 @@ __global__ __launch_bounds__(kNodeSumThreads) void k_apply_psi(Geo g, const int*
   if (md == 1) x = xc;
   constexpr int NW = kNodeSumThreads / 64;
   __shared__ double red[NW];
-  const int h = blockIdx.x / 3, mode = blockIdx.x % 3;
-  const int q = blockIdx.y;
+  const int h = blockIdx.x;
+  const int q0 = blockIdx.y * kPsiCols, nq = min(kPsiCols, ncols - q0);
   const size_t base = (size_t)2 * g.N;
-  double s = 0.0;
+  double s[3][kPsiCols];
+#pragma unroll
+  for (int k = 0; k < kPsiCols; ++k) s[0][k] = s[1][k] = s[2][k] = 0.0;
   for (int j = threadIdx.x; j < g.N; j += kNodeSumThreads) {
     if (curve_id[j] != h + 1) continue;
-    const double w = g.w[j];
-    const double mx = x[(size_t)(2 * j) * ncols + q], my = x[(size_t)(2 * j + 1) * ncols + q];
-    if (mode == 0) s += w * mx;
-    else if (mode == 1) s += w * my;
-    else s += w * (-g.y[j] * mx + g.x[j] * my);
+    const double w = g.w[j], xj = g.x[j], yj = g.y[j];
+    const double* x0 = x + (size_t)(2 * j) * ncols + q0;
+    const double* x1 = x + (size_t)(2 * j + 1) * ncols + q0;
+#pragma unroll
+    for (int k = 0; k < kPsiCols; ++k) {
+      if (k < nq) {
+        const double mx = x0[k], my = x1[k];
+        s[0][k] += w * mx;
+        s[1][k] += w * my;
+        s[2][k] += w * (-yj * mx + xj * my);
+      }
+    }
   }
-  s = block_sum(s, red);
-  if (threadIdx.x == 0) {
-    const size_t row = base + 3 * h + mode;
-    y[row * ncols + q] = s - x[row * ncols + q];
+#pragma unroll
+  for (int mode = 0; mode < 3; ++mode) {
+#pragma unroll
+    for (int k = 0; k < kPsiCols; ++k) {
+      if (k < nq) {   // uniform over the block
+        const double v = block_sum(s[mode][k], red);
+        if (threadIdx.x == 0) {
+          const size_t row = base + 3 * h + mode;
+          y[row * ncols + q0 + k] = v - x[row * ncols + q0 + k];
+        }
+      }
+    }
   }
 }
 
@@ -866,7 +887,7 @@ void apply_tail(Geo g, const int* curve_id, const double* hole_xy, int p, double
   hipLaunchKernelGGL(k_apply_sum, dim3(blocks_for((long long)g.N * ncols, kBlock)), dim3(kBlock), 0, s,
                      g, lam, hole_xy, p, x, xc, ncols, part, nchunk, nsum, bpart, bt, y, flag, max_iters);
   if (p > 0)
-    hipLaunchKernelGGL(k_apply_psi, dim3(3 * p, ncols), dim3(kNodeSumThreads), 0, s, g, curve_id, p, x, xc,
+    hipLaunchKernelGGL(k_apply_psi, dim3(p, blocks_for(ncols, kPsiCols)), dim3(kNodeSumThreads), 0, s, g, curve_id, p, x, xc,
                        ncols, y, flag, max_iters);
 }
 

@@ -199,38 +199,37 @@ __global__ __launch_bounds__(kBlock) void k_diag(const SolveBox* boxes, const in
 }
 
 // H (2N x 3p) and Psi (2N x 3p, i.e. Psi^T stored by columns), row-major.
+// One thread per (node j, hole h), h fastest, so that a wavefront writes
+// consecutive 3-column groups of the same rows (coalesced stores).
 __global__ void k_assemble_H(Geo g, const double* hole_xy, int p, const int* curve_id,
                              double* H, double* Psi) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= g.N) return;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)g.N * p) return;
+  const int j = (int)(t / p), h = (int)(t % p);
   const int p3 = 3 * p;
   const double xj = g.x[j], yj = g.y[j];
-  for (int h = 0; h < p; ++h) {
-    const double rx = xj - hole_xy[2 * h], ry = yj - hole_xy[2 * h + 1];
-    const double r2 = rx * rx + ry * ry;
-    const double lg = -0.5 * log(r2);
-    double* h0 = H + (size_t)(2 * j) * p3 + 3 * h;
-    double* h1 = H + (size_t)(2 * j + 1) * p3 + 3 * h;
-    h0[0] = kInv4Pi * (lg + rx * rx / r2);
-    h0[1] = kInv4Pi * (rx * ry / r2);
-    h1[0] = kInv4Pi * (ry * rx / r2);
-    h1[1] = kInv4Pi * (lg + ry * ry / r2);
-    h0[2] = kInv4Pi * (-ry) / r2;
-    h1[2] = kInv4Pi * rx / r2;
-  }
-  for (int t = 0; t < p3; ++t) {
-    Psi[(size_t)(2 * j) * p3 + t] = 0.0;
-    Psi[(size_t)(2 * j + 1) * p3 + t] = 0.0;
-  }
-  const int cid = curve_id[j];
-  if (cid > 0) {
-    const int h = cid - 1;
-    const double w = g.w[j];
-    Psi[(size_t)(2 * j) * p3 + 3 * h + 0] = w;
-    Psi[(size_t)(2 * j + 1) * p3 + 3 * h + 1] = w;
-    Psi[(size_t)(2 * j) * p3 + 3 * h + 2] = -w * yj;
-    Psi[(size_t)(2 * j + 1) * p3 + 3 * h + 2] = w * xj;
-  }
+  const double rx = xj - hole_xy[2 * h], ry = yj - hole_xy[2 * h + 1];
+  const double r2 = rx * rx + ry * ry;
+  const double lg = -0.5 * log(r2);
+  double* h0 = H + (size_t)(2 * j) * p3 + 3 * h;
+  double* h1 = H + (size_t)(2 * j + 1) * p3 + 3 * h;
+  h0[0] = kInv4Pi * (lg + rx * rx / r2);
+  h0[1] = kInv4Pi * (rx * ry / r2);
+  h1[0] = kInv4Pi * (ry * rx / r2);
+  h1[1] = kInv4Pi * (lg + ry * ry / r2);
+  h0[2] = kInv4Pi * (-ry) / r2;
+  h1[2] = kInv4Pi * rx / r2;
+  // Psi: the node's weight rows for its own hole, zero elsewhere
+  const bool own = curve_id[j] == h + 1;
+  const double w = own ? g.w[j] : 0.0;
+  double* s0 = Psi + (size_t)(2 * j) * p3 + 3 * h;
+  double* s1 = Psi + (size_t)(2 * j + 1) * p3 + 3 * h;
+  s0[0] = w;
+  s0[1] = 0.0;
+  s0[2] = own ? -w * yj : 0.0;
+  s1[0] = 0.0;
+  s1[1] = w;
+  s1[2] = own ? w * xj : 0.0;
 }
 
 // out[t] = scale * sum_p parts[p * stride + t], in two passes whose order is
@@ -706,7 +705,8 @@ template void launch_diag<double>(const SolveBox*, int, const int*, double*, int
 
 void launch_assemble_H(Geo g, const double* hole_xy, int p, const int* curve_id, double* H,
                        double* Psi, hipStream_t s) {
-  hipLaunchKernelGGL(k_assemble_H, dim3(blocks_for(g.N, kBlock)), dim3(kBlock), 0, s, g,
+  if (p == 0 || g.N == 0) return;
+  hipLaunchKernelGGL(k_assemble_H, dim3(blocks_for((long long)g.N * p, kBlock)), dim3(kBlock), 0, s, g,
                      hole_xy, p, curve_id, H, Psi);
 }
 
