@@ -204,6 +204,46 @@ def test_many_rhs_ragged_chunks():
     assert em < 1e-10 and eb < 1e-10, (em, eb)
 
 
+def test_border_rhs_wide_columns_global_path():
+    """More right-hand sides than the border right-hand side kernel stages in
+    LDS (3p + ncols beyond 3072): its rows come from global memory, and the
+    border correction runs over many 16-column chunks.  Element-wise against
+    the oracle on every column."""
+    g = workload_small(seed=12, n_outer=192, n_holes=3, nodes_per_hole=64, radius=3.0)
+    nrhs = 3100
+    f = boundary_data(g, exterior_forces_for_geometry(g, nrhs, seed=9))
+    orc = RSFactorization(g, RSParams(leaf_size=24, pivot="key20")).factor()
+    xo = orc.solve(f)
+    s = _solver(g, leaf_size=24).factor()
+    x = s.solve(f)
+    em, eb = _elem(x, xo, g.n_dofs)
+    assert em < 1e-10 and eb < 1e-10, (em, eb)
+
+
+def test_many_holes_border_fix_global_path():
+    """128 holes (3p = 384 border unknowns): the border correction's lam block
+    no longer fits LDS beside a W tile, so the kernel reads global memory.
+    The oracle's factorization takes minutes here, so the checks use the
+    oracle's exact operator (eq. backwardeq): the direct solve's residual
+    stays at the ID tolerance's scale (16-node holes make it ~1e-7), and
+    refinement with that solve as the preconditioner contracts at that rate,
+    reaching 1e-12 in at most three iterations; a wrong border correction
+    would leave an O(1) error that neither check lets through."""
+    from workloads import random_holes_geometry
+
+    g = random_holes_geometry(5, 18.0, 1024, [16] * 128)
+    assert 3 * g.n_holes > 380
+    f = boundary_data(g, exterior_forces_for_geometry(g, 3, seed=4))
+    s = _solver(g, tol=1e-10, leaf_size=64).factor()
+    res = _residual(g, s.solve(f), f)
+    assert np.all(res < 1e-6), res
+    r = _solver(g, tol=1e-10, leaf_size=64, refine_max=3, refine_tol=1e-12).factor()
+    x, _ = r.solve(f, residual=True)
+    res = _residual(g, x, f)
+    assert np.all(res < 1e-11), res
+    assert 1 <= r.stats()["refine_iters"] <= 3
+
+
 def test_apply_matches_oracle():
     g = workload_small(seed=13, n_outer=160, n_holes=2, nodes_per_hole=48, radius=3.0)
     rng = np.random.Generator(np.random.PCG64(0))
