@@ -228,7 +228,7 @@ struct rs_ctx {
   // root
   std::vector<int> I0;
   DevBuf d_I0, d_X0, d_Z, d_Zinv, d_gjwork, d_gjiwork, d_rcond, d_rstatus, d_root_box;
-  DevBuf d_H, d_Hh, d_Ph, d_Gpart, d_G, d_bscr, d_W, d_Wf;
+  DevBuf d_H, d_Hh, d_Ph, d_Gpart, d_G, d_W, d_Wf;
   int nz = 0;
   // solve metadata
   std::vector<std::vector<SolveBox>> sboxes;   // per level
@@ -1046,7 +1046,6 @@ void poll_event(hipEvent_t ev) {
 
 using LevelOverlap = std::function<void(const int* qr_rank)>;
 
-constexpr size_t kBorderScratchMax = 64ull << 20;   // gather scratch of one border launch
 
 // The context's second stream, made to wait for everything enqueued so far on
 // its main stream (ev_fork); join_side makes the main stream wait for it.
@@ -1723,24 +1722,13 @@ void factor_root_launch(rs_ctx* c) {
     sweep_all(c, c->d_Ph.as<double>(), p3, 1, s2);
     sweep_all(c, c->d_Hh.as<double>(), p3, 0);
     // W_B of every box, then G = sum_B (Psi^T V)_R W_B as one gathered product
-    // W_B of each box is independent of the others: one launch over the boxes
-    // of every level when their gather scratch (one slot per box) stays within
-    // kBorderScratchMax bytes, else one launch per level
-    const long long scr_stride = std::max<long long>((long long)c->all_maxr * p3, 1);
-    const int all_nb = c->L >= 1 ? (int)(c->sbox_off[c->L + 1] - c->sbox_off[1]) : 0;
-    const bool one_launch = (size_t)std::max(all_nb, 1) * scr_stride * sizeof(double) <= kBorderScratchMax;
-    int max_nb = 1;
-    for (int l = 1; l <= c->L; ++l) max_nb = std::max(max_nb, level_count(c, l));
-    c->d_bscr.ensure((size_t)(one_launch ? std::max(all_nb, 1) : max_nb) * scr_stride * sizeof(double));
+    // W_B of each box is independent of the others: one launch per level,
+    // its grid sized by the level's largest r
     {
       KTimer kt_(c, "border_box");
-      if (one_launch)
-        launch_border_w(level_sboxes(c, 1), all_nb, c->d_ridx.as<int>(), c->d_Hh.as<double>(), p3,
-                        c->d_bscr.as<double>(), scr_stride, s);
-      else
-        for (int l = c->L; l >= 1; --l)
-          launch_border_w(level_sboxes(c, l), level_count(c, l), c->d_ridx.as<int>(), c->d_Hh.as<double>(), p3,
-                          c->d_bscr.as<double>(), scr_stride, s);
+      for (int l = c->L; l >= 1; --l)
+        launch_border_w(level_sboxes(c, l), level_count(c, l), c->d_ridx.as<int>(), c->d_Hh.as<double>(), p3,
+                        c->lvl_maxr[l], s);
       join_side(c);   // Psi^T V rows
       const int nch = border_g_chunks(c->n_ridx, p3);
       const size_t gparts = (size_t)nch * p3 * p3;
@@ -1751,7 +1739,10 @@ void factor_root_launch(rs_ctx* c) {
       launch_sum_parts(c->d_Gpart.as<double>(), nch, (long long)p3 * p3, p3 * p3, 1.0, c->d_G.as<double>(),
                        c->d_Gpart.as<double>() + gparts, s);
     }
-    if (c->prm.precision >= 1) launch_w_to_float(level_sboxes(c, 1), all_nb, p3, s);
+    if (c->prm.precision >= 1) {
+      const int all_nb = c->L >= 1 ? (int)(c->sbox_off[c->L + 1] - c->sbox_off[1]) : 0;
+      launch_w_to_float(level_sboxes(c, 1), all_nb, p3, s);
+    }
     c->d_Z.ensure((size_t)nz * nz * sizeof(double));
     {
       KTimer kt_(c, "root_Z");

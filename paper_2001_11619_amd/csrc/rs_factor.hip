@@ -862,22 +862,63 @@ __global__ __launch_bounds__(kBlock) void k_eliminate(const LevelBox* boxes, int
 }
 
 // ---- border of the root system (eq. partition) -----------------------------
-// W_B = X_RR^{-1} (U H)_R of every box (r x 3p) on FP64 MFMA: the rows R of
-// (U H) are gathered into the block's scratch, then one GEMM.
+// W_B = X_RR^{-1} (U H)_R of every box (r x 3p) as an LDS-tiled float64 GEMM.
+// Block (box, y) owns the output tile of rows 64 ty .. and columns 64 tx ..
+// (y = ty * ntx + tx; tiles beyond the box's r exit at once); the K dimension
+// (r) goes in chunks of 32: a 64 x 32 tile of X_RR^{-1} and the 32 gathered
+// rows of (U H) over the tile's 64 columns are staged in LDS, and each thread
+// accumulates a 4 x 4 block of W in registers, the sum over k in order.
+constexpr int kBWT = 64;   // output tile edge
+constexpr int kBWK = 32;   // K chunk
 __global__ __launch_bounds__(kBlock) void k_border_w(const SolveBox* boxes, const int* ridx,
-                                                     const double* Hh, int p3, double* scratch,
-                                                     long long scr_stride) {
+                                                     const double* Hh, int p3, int ntx) {
+  __shared__ double sa[kBWT][kBWK + 1];
+  __shared__ __align__(16) double sb[kBWK][kBWT];
   const SolveBox& B = boxes[blockIdx.x];
   const int r = B.r;
-  if (r == 0) return;
-  double* hr = scratch + (size_t)blockIdx.x * scr_stride;
+  const int ty = blockIdx.y / ntx, tx = blockIdx.y % ntx;
+  const int i0 = ty * kBWT, h0 = tx * kBWT;
+  if (i0 >= r) return;   // uniform over the block
   const int* R = ridx + B.r_off;
-  for (int t = threadIdx.x; t < r * p3; t += kBlock) {
-    const int i = t / p3, h = t % p3;
-    hr[t] = Hh[(size_t)R[i] * p3 + h];
+  const double* Xi = B.Xinv;
+  const int tid = threadIdx.x;
+  const int ri = (tid >> 4) * 4, cj = (tid & 15) * 4;
+  double acc[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+  for (int k0 = 0; k0 < r; k0 += kBWK) {
+    const int kc = min(kBWK, r - k0);
+    __syncthreads();
+    for (int e = tid; e < kBWT * kBWK; e += kBlock) {
+      const int row = e / kBWK, kk = e % kBWK;
+      sa[row][kk] = (i0 + row < r && kk < kc) ? Xi[(size_t)(i0 + row) * r + k0 + kk] : 0.0;
+    }
+    for (int e = tid; e < kBWK * kBWT; e += kBlock) {
+      const int kk = e / kBWT, col = e % kBWT;
+      sb[kk][col] = (kk < kc && h0 + col < p3) ? Hh[(size_t)R[k0 + kk] * p3 + h0 + col] : 0.0;
+    }
+    __syncthreads();
+    for (int kk = 0; kk < kc; ++kk) {
+      const double4 bv = *reinterpret_cast<const double4*>(&sb[kk][cj]);
+      const double bb[4] = {bv.x, bv.y, bv.z, bv.w};
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double av = sa[ri + u][kk];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = fma(av, bb[v], acc[u][v]);
+      }
+    }
   }
-  __syncthreads();
-  mfma_gemm(0, 1, r, p3, r, 1.0, B.Xinv, r, false, hr, p3, false, 0.0, nullptr, 0, B.W, p3);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int i = i0 + ri + u;
+    if (i >= r) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      if (h0 + cj + v < p3) B.W[(size_t)i * p3 + h0 + cj + v] = acc[u][v];
+  }
 }
 
 // Gpart[chunk] = sum over the rows i of the chunk of Ph[R_i]^T W[i], where the
@@ -1486,10 +1527,11 @@ void launch_factor_to_float(const LevelBox* boxes, int nbox, const int* k_final,
   if (nbox) hipLaunchKernelGGL(k_factor_to_float, dim3(nbox), dim3(kBlock), 0, s, boxes, k_final);
 }
 
-void launch_border_w(const SolveBox* boxes, int nbox, const int* ridx, const double* Hh, int p3,
-                     double* scratch, long long scr_stride, hipStream_t s) {
-  if (nbox == 0 || p3 == 0) return;
-  hipLaunchKernelGGL(k_border_w, dim3(nbox), dim3(kBlock), 0, s, boxes, ridx, Hh, p3, scratch, scr_stride);
+void launch_border_w(const SolveBox* boxes, int nbox, const int* ridx, const double* Hh, int p3, int max_r,
+                     hipStream_t s) {
+  if (nbox == 0 || p3 == 0 || max_r <= 0) return;
+  const int ntx = (p3 + kBWT - 1) / kBWT, nty = (max_r + kBWT - 1) / kBWT;
+  hipLaunchKernelGGL(k_border_w, dim3(nbox, ntx * nty), dim3(kBlock), 0, s, boxes, ridx, Hh, p3, ntx);
 }
 
 int border_g_chunks(int total_r, int p3) {

@@ -155,11 +155,11 @@ void launch_diag(const SolveBox* boxes, int nbox, const int* ridx, T* c, int nco
                  hipStream_t s);
 void launch_assemble_H(Geo g, const double* hole_xy, int p, const int* curve_id,
                        double* H, double* Psi, hipStream_t s);
-// Border of the root system: W_B = X_RR^{-1} (U H)_R per box (scratch: nbox x
-// scr_stride >= r p3 doubles), then G parts over chunks of the concatenated R
-// lists (nchunk = border_g_chunks, Gpart: nchunk x p3 x p3).
-void launch_border_w(const SolveBox* boxes, int nbox, const int* ridx, const double* Hh, int p3,
-                     double* scratch, long long scr_stride, hipStream_t s);
+// Border of the root system: W_B = X_RR^{-1} (U H)_R per box (max_r >= every
+// box's r), then G parts over chunks of the concatenated R lists
+// (nchunk = border_g_chunks, Gpart: nchunk x p3 x p3).
+void launch_border_w(const SolveBox* boxes, int nbox, const int* ridx, const double* Hh, int p3, int max_r,
+                     hipStream_t s);
 int border_g_chunks(int total_r, int p3);
 void launch_border_g(const int* ridx, int total_r, const double* Ph, const double* W, int p3, int nchunk,
                      double* Gpart, hipStream_t s);
