@@ -480,7 +480,7 @@ class HostPool {
   static constexpr int kSpinUs = 200;
   HostPool() {
     const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
-    const int nthreads = (int)std::min(8u, hw);
+    const int nthreads = (int)std::min(16u, hw);
     for (int i = 0; i + 1 < nthreads; ++i)
       workers_.emplace_back([this] {
         tl_in_pool = true;
