@@ -931,8 +931,11 @@ constexpr int kBGT = 64;
 __global__ __launch_bounds__(kBlock) void k_border_g(const int* ridx, int total_r, const double* Ph,
                                                      const double* W, int p3, int chunk,
                                                      double* Gpart) {
-  __shared__ double sp[32][kBGT + 1];
-  __shared__ double sw[32][kBGT + 1];
+  // unpadded rows: a thread reads its 4 consecutive entries as two 16-byte
+  // loads (the 4 values of ra in a wavefront are broadcasts, the 16 of rb
+  // one contiguous span)
+  __shared__ __align__(16) double sp[32][kBGT];
+  __shared__ __align__(16) double sw[32][kBGT];
   const int tiles = (p3 + kBGT - 1) / kBGT;
   const int a0 = (blockIdx.x / tiles) * kBGT, b0 = (blockIdx.x % tiles) * kBGT;
   const int i0 = blockIdx.y * chunk, i1 = min(total_r, i0 + chunk);
@@ -959,12 +962,9 @@ __global__ __launch_bounds__(kBlock) void k_border_g(const int* ridx, int total_
     }
     __syncthreads();
     for (int i = 0; i < cnt; ++i) {
-      double pa[4], wb[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        pa[u] = sp[i][ra + u];
-        wb[u] = sw[i][rb + u];
-      }
+      const double4 pv = *reinterpret_cast<const double4*>(&sp[i][ra]);
+      const double4 wv = *reinterpret_cast<const double4*>(&sw[i][rb]);
+      const double pa[4] = {pv.x, pv.y, pv.z, pv.w}, wb[4] = {wv.x, wv.y, wv.z, wv.w};
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
