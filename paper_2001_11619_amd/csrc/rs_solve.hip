@@ -118,16 +118,18 @@ __device__ __forceinline__ void diag_box(const SolveBox& B, const TF* Xi, const 
   }
 }
 
-// The same product for boxes with r <= kDiagMaxR: the block stages c_R (16
-// columns at a time, zero-padded) in LDS and takes X_RR^{-1} in tiles of 64
-// rows by 32 columns (rows padded by one double against bank conflicts); the
-// thread (row ii, column group g) keeps 4 columns of row ii in registers.
-// Each output sums over j in order, as above.  32 KiB of LDS at most, so that
-// several blocks share a CU (most boxes have a few dozen rows).
+// The same product for boxes with r <= kDiagMaxR, through LDS: per 16
+// columns, the K dimension goes in chunks of kDiagK rows of c_R (staged) and,
+// for each 64-row tile of the box, the matching 64 x kDiagK tile of
+// X_RR^{-1} (rows padded by one double against bank conflicts).  The thread
+// (row ii of every tile, column group g) keeps 4 columns of up to
+// kDiagMaxTiles rows in registers and writes them after the last read of c_R.
+// Each output sums over j in order, as above.  21 KiB of LDS.
 constexpr int kDiagTile = 64;
 constexpr int kDiagK = 32;
-constexpr int kDiagLdsTile = kDiagTile * (kDiagK + 1) * 8;        // bytes
-constexpr int kDiagMaxR = (32768 - kDiagLdsTile) / (16 * 8);      // 124
+constexpr int kDiagMaxTiles = 8;
+constexpr int kDiagMaxR = kDiagTile * kDiagMaxTiles;                            // 512
+constexpr int kDiagLds = (kDiagK * 16 + kDiagTile * (kDiagK + 1)) * 8;          // bytes
 template <typename T, typename TF>
 __device__ __forceinline__ void diag_box_tiled(const SolveBox& B, const TF* Xi, const int* ridx, T* c,
                                                int ncols, int kNC, double* smem) {
@@ -135,47 +137,57 @@ __device__ __forceinline__ void diag_box_tiled(const SolveBox& B, const TF* Xi, 
   const int q0 = blockIdx.y * kNC;
   const int nq = min(kNC, ncols - q0);
   const int* R = ridx + B.r_off;
-  double* sIn = smem;                         // r x 16
-  double* sX = smem + (size_t)r * 16;         // kDiagTile x (kDiagK + 1)
+  const int ntile = (r + kDiagTile - 1) / kDiagTile;
+  double* sIn = smem;                      // kDiagK x 16
+  double* sX = smem + kDiagK * 16;         // kDiagTile x (kDiagK + 1)
   const int ii = threadIdx.x % kDiagTile, g = threadIdx.x / kDiagTile;
   static_assert(kBlock == 4 * kDiagTile, "4 column groups of 4 cover 16 columns");
   for (int qa = 0; qa < nq; qa += 16) {
     const int na = min(16, nq - qa);
-    __syncthreads();
-    for (int e = threadIdx.x; e < r * 16; e += kBlock) {
-      const int j = e / 16, k = e % 16;
-      sIn[e] = k < na ? (double)c[(size_t)R[j] * ncols + q0 + qa + k] : 0.0;
-    }
-    for (int i0 = 0; i0 < r; i0 += kDiagTile) {
-      const int nt = min(kDiagTile, r - i0);
-      double acc[4] = {0.0, 0.0, 0.0, 0.0};
-      for (int k0 = 0; k0 < r; k0 += kDiagK) {
-        const int kc = min(kDiagK, r - k0);
-        __syncthreads();
-        for (int e = threadIdx.x; e < nt * kDiagK; e += kBlock) {
-          const int rr = e / kDiagK, kk = e % kDiagK;
-          if (kk < kc) sX[rr * (kDiagK + 1) + kk] = (double)Xi[(size_t)(i0 + rr) * r + k0 + kk];
-        }
-        __syncthreads();
-        if (ii < nt && 4 * g < na) {
-          const double* xr = sX + ii * (kDiagK + 1);
-          const double* vr = sIn + (size_t)k0 * 16 + 4 * g;
-          for (int kk = 0; kk < kc; ++kk) {
-            const double x = xr[kk];
-            const double4 v = *reinterpret_cast<const double4*>(vr + (size_t)kk * 16);
-            acc[0] += x * v.x;
-            acc[1] += x * v.y;
-            acc[2] += x * v.z;
-            acc[3] += x * v.w;
+    double acc[kDiagMaxTiles][4];
+#pragma unroll
+    for (int t = 0; t < kDiagMaxTiles; ++t) acc[t][0] = acc[t][1] = acc[t][2] = acc[t][3] = 0.0;
+    for (int k0 = 0; k0 < r; k0 += kDiagK) {
+      const int kc = min(kDiagK, r - k0);
+      __syncthreads();
+      for (int e = threadIdx.x; e < kDiagK * 16; e += kBlock) {
+        const int j = e / 16, k = e % 16;
+        sIn[e] = (j < kc && k < na) ? (double)c[(size_t)R[k0 + j] * ncols + q0 + qa + k] : 0.0;
+      }
+#pragma unroll
+      for (int t = 0; t < kDiagMaxTiles; ++t) {
+        if (t < ntile) {   // uniform over the block
+          const int i0 = t * kDiagTile, nt = min(kDiagTile, r - i0);
+          __syncthreads();
+          for (int e = threadIdx.x; e < kDiagTile * kDiagK; e += kBlock) {
+            const int rr = e / kDiagK, kk = e % kDiagK;
+            sX[rr * (kDiagK + 1) + kk] = (rr < nt && kk < kc) ? (double)Xi[(size_t)(i0 + rr) * r + k0 + kk] : 0.0;
+          }
+          __syncthreads();
+          if (ii < nt && 4 * g < na) {
+            const double* xr = sX + ii * (kDiagK + 1);
+            const double* vr = sIn + 4 * g;
+            for (int kk = 0; kk < kc; ++kk) {
+              const double x = xr[kk];
+              const double4 v = *reinterpret_cast<const double4*>(vr + (size_t)kk * 16);
+              acc[t][0] += x * v.x;
+              acc[t][1] += x * v.y;
+              acc[t][2] += x * v.z;
+              acc[t][3] += x * v.w;
+            }
           }
         }
       }
-      // c_R was staged whole for these columns, so the rows can be written now
-      if (ii < nt) {
-        T* crow = c + (size_t)R[i0 + ii] * ncols + q0 + qa + 4 * g;
+    }
+    __syncthreads();   // every read of c_R for these columns is done
+#pragma unroll
+    for (int t = 0; t < kDiagMaxTiles; ++t) {
+      const int i = t * kDiagTile + ii;
+      if (t < ntile && i < r) {
+        T* crow = c + (size_t)R[i] * ncols + q0 + qa + 4 * g;
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-          if (4 * g + v < na) crow[v] = (T)acc[v];
+          if (4 * g + v < na) crow[v] = (T)acc[t][v];
       }
     }
   }
@@ -694,11 +706,11 @@ template <typename T>
 void launch_diag(const SolveBox* boxes, int nbox, const int* ridx, T* c, int ncols, int max_r,
                  hipStream_t s) {
   if (nbox == 0 || ncols == 0) return;
-  const int nc = chunk_cols(2 * max_r, ncols, nbox);
+  // boxes beyond kDiagMaxR rows stage 2 r x nc values (the direct loop)
+  const bool big = max_r > kDiagMaxR;
+  const int nc = chunk_cols(big ? 2 * max_r : 0, ncols, nbox);
   dim3 grid(nbox, blocks_for(ncols, nc));
-  // the larger of the two paths' needs (both within 64 KiB)
-  const size_t shm = std::max((size_t)2 * max_r * nc * sizeof(T),
-                              (size_t)std::min(max_r, kDiagMaxR) * 16 * sizeof(double) + kDiagLdsTile);
+  const size_t shm = std::max(big ? (size_t)2 * max_r * nc * sizeof(T) : (size_t)0, (size_t)kDiagLds);
   hipLaunchKernelGGL(k_diag<T>, grid, dim3(kBlock), shm, s, boxes, ridx, c, ncols, nc);
 }
 template void launch_diag<double>(const SolveBox*, int, const int*, double*, int, int, hipStream_t);
